@@ -1,0 +1,352 @@
+"""Pins for the oracle's maps epilogue, multi-plane trace (Sec. 2.2), chi^2
+(Sec. 3.1), image finder (Sec. 2.3, triangle mapping) and singularity fields (Sec. 6)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2609_08649_amd import workloads as W
+
+POINT, SIS, SIE, PJE, NFW, ENFW = 0, 1, 2, 3, 4, 5
+
+
+def row(t, x=0.0, y=0.0, b=1.0, q=1.0, pa=0.0, s=0.0, a=0.0):
+    return np.array([[t, x, y, b, q, pa, s, a]], dtype=np.float64)
+
+
+# ------------------------------------------------------------------ maps epilogue
+def test_mu_from_eigenvalues_equals_mu_from_det(orc):
+    model, _ = W.tiny_model(21, n_main=3, n_mem=6)
+    tab = orc.expand(model)
+    x, y = W.random_points(1, 200, 15.0)
+    for a in (0.3, 0.8):
+        m = orc.maps(tab, x, y, a)
+        lam = np.linalg.eigvalsh(np.stack([np.stack([m["p11"], m["p12"]], -1),
+                                           np.stack([m["p12"], m["p22"]], -1)], -2))
+        mu_eig = 1 / ((1 - a * lam[:, 1]) * (1 - a * lam[:, 0]))
+        assert np.allclose(m["mu"], mu_eig, rtol=1e-9)
+        assert np.allclose(m["e1"], lam[:, 1], rtol=1e-10, atol=1e-12)
+        assert np.allclose(m["e2"], lam[:, 0], rtol=1e-10, atol=1e-12)
+
+
+def test_distance_ratio_enters_only_through_a(orc):
+    model, _ = W.tiny_model(22, n_main=2, n_mem=4)
+    tab = orc.expand(model)
+    x, y = W.random_points(2, 50, 10.0)
+    m1, m2 = orc.maps(tab, x, y, 0.3), orc.maps(tab, x, y, 0.9)
+    for k in ("ax", "ay", "kappa", "gamma1", "gamma2", "p111"):
+        assert np.array_equal(m1[k], m2[k])
+    assert np.allclose((x - m1["beta_x"]) / 0.3, (x - m2["beta_x"]) / 0.9, rtol=1e-12)
+
+
+# ------------------------------------------------------------------ multi-plane
+def _tabs3():
+    cfg = W.config4(seed=5, grid_n=32, members=(6, 4, 3))
+    return [np.asarray(__import__("oracle.oracle", fromlist=["x"]).expand(p)) for p in cfg["planes"]], cfg
+
+
+def test_single_plane_reduces_to_lens_equation(orc):
+    model, _ = W.tiny_model(23, n_main=2, n_mem=5)
+    tab = orc.expand(model)
+    x, y = W.random_points(3, 60, 10.0)
+    zd, zs = 0.5, 2.5
+    mp = orc.multiplane([tab], [zd], [zs], x, y)
+    sp = orc.maps(tab, x, y, orc.adis(zd, zs))
+    assert np.allclose(mp["beta"][0, :, 0], sp["beta_x"], rtol=1e-13, atol=1e-13)
+    assert np.allclose(mp["mu"][0], sp["mu"], rtol=1e-11)
+
+
+def test_coincident_planes_collapse(orc):
+    model, _ = W.tiny_model(24, n_main=3, n_mem=4)
+    tab = orc.expand(model)
+    t1, t2 = tab[:3], tab[3:]
+    x, y = W.random_points(4, 60, 10.0)
+    mp = orc.multiplane([t1, t2], [0.5, 0.5], [2.0], x, y)
+    sp = orc.maps(tab, x, y, orc.adis(0.5, 2.0))
+    assert np.allclose(mp["beta"][0, :, 0], sp["beta_x"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(mp["beta"][0, :, 1], sp["beta_y"], rtol=1e-12, atol=1e-12)
+    A = mp["A"][0]
+    assert np.allclose(A[:, 1], A[:, 2], rtol=1e-10, atol=1e-12)   # symmetric when coincident
+
+
+def test_empty_plane_is_identity_and_behind_source_ignored(orc):
+    tabs, cfg = _tabs3()
+    x, y = W.random_points(5, 30, 20.0)
+    a = orc.multiplane(tabs, cfg["z_planes"], [3.0], x, y)
+    empty = np.zeros((0, 8))
+    b = orc.multiplane([tabs[0], empty, tabs[1], tabs[2]], [0.3, 0.45, 0.6, 1.2], [3.0], x, y)
+    assert np.allclose(a["beta"], b["beta"], rtol=1e-13, atol=1e-13)
+    # a source at z=0.5 sees only the first plane
+    c = orc.multiplane(tabs, cfg["z_planes"], [0.5], x, y)
+    d = orc.multiplane([tabs[0]], [0.3], [0.5], x, y)
+    assert np.allclose(c["beta"], d["beta"], rtol=1e-13, atol=1e-13)
+
+
+def test_multiplane_jacobian_matches_finite_differences(orc):
+    tabs, cfg = _tabs3()
+    x, y = W.random_points(6, 20, 20.0)
+    zs = [1.5, 6.0]
+    m = orc.multiplane(tabs, cfg["z_planes"], zs, x, y)
+    h = 1e-5
+    px = orc.multiplane(tabs, cfg["z_planes"], zs, x + h, y)["beta"]
+    mx = orc.multiplane(tabs, cfg["z_planes"], zs, x - h, y)["beta"]
+    py = orc.multiplane(tabs, cfg["z_planes"], zs, x, y + h)["beta"]
+    my = orc.multiplane(tabs, cfg["z_planes"], zs, x, y - h)["beta"]
+    A = m["A"]
+    assert np.allclose((px[..., 0] - mx[..., 0]) / (2 * h), A[..., 0], atol=1e-7)
+    assert np.allclose((py[..., 0] - my[..., 0]) / (2 * h), A[..., 1], atol=1e-7)
+    assert np.allclose((px[..., 1] - mx[..., 1]) / (2 * h), A[..., 2], atol=1e-7)
+    assert np.allclose((py[..., 1] - my[..., 1]) / (2 * h), A[..., 3], atol=1e-7)
+    # distinct planes: the Jacobian is not symmetric (Sec. 2.2)
+    assert np.max(np.abs(A[1, :, 1] - A[1, :, 2])) > 1e-6
+
+
+# ------------------------------------------------------------------ chi^2
+def _cons(theta, fam, sig, a_fam, sig2=None, phi=None):
+    n = len(fam)
+    return {"theta": np.asarray(theta, float).reshape(n, 2), "family": np.asarray(fam, np.int32),
+            "sig1": np.full(n, sig), "sig2": np.full(n, sig if sig2 is None else sig2),
+            "phi": np.zeros(n) if phi is None else np.asarray(phi, float), "a_fam": np.asarray(a_fam, float)}
+
+
+def test_chi2_without_lens_is_scatter_about_mean(orc):
+    th = np.array([[1.0, 2.0], [3.0, -1.0], [0.5, 0.5], [7.0, 7.0], [6.0, 8.0]])
+    fam = [0, 0, 0, 1, 1]
+    tabs = np.zeros((1, 0, 8))
+    r = orc.chi2_batch(tabs, _cons(th, fam, 0.5, [0.7, 0.4]))
+    exp = 0
+    for f in (0, 1):
+        t = th[np.array(fam) == f]
+        exp += np.sum((t - t.mean(0)) ** 2) / 0.25
+    assert abs(r["chi2_src"][0] - exp) < 1e-12
+    assert np.allclose(r["beta_model"][0, 0], th[:3].mean(0))
+
+
+def _images(orc, tab, beta, a, grid=None):
+    grid = grid or {"x0": -20.0, "y0": -20.0, "h": 0.25, "nx": 160, "ny": 160}
+    return orc.find_images(tab, grid, np.array([beta]), np.array([a]))
+
+
+def test_chi2_zero_on_exact_images_and_invariances(orc):
+    tab = row(SIE, 0.0, 0.0, b=8.0, q=0.7, pa=0.4, s=0.3)
+    a = 0.6
+    fi = _images(orc, tab, [0.4, -0.2], a)
+    n = fi["count"][0]
+    assert n >= 3
+    th = fi["theta"][0, :n]
+    cons = _cons(th, [0] * n, 0.5, [a])
+    r = orc.chi2_batch(tab[None], cons, img_mode=True)
+    assert r["chi2_src"][0] < 1e-16 and r["chi2_img"][0] < 1e-16
+    assert np.allclose(r["beta_model"][0, 0], [0.4, -0.2], atol=1e-9)
+    # perturbed data: translation of lens and images together leaves chi^2 unchanged
+    rng = np.random.default_rng(3)
+    thp = th + rng.normal(0, 0.05, th.shape)
+    consp = _cons(thp, [0] * n, 0.5, [a], sig2=0.3, phi=rng.uniform(0, np.pi, n))
+    r1 = orc.chi2_batch(tab[None], consp)
+    tab2 = tab.copy()
+    tab2[0, 1:3] += [3.0, -2.0]
+    consp2 = dict(consp, theta=thp + [3.0, -2.0])
+    r2 = orc.chi2_batch(tab2[None], consp2)
+    assert abs(r1["chi2_src"][0] / r2["chi2_src"][0] - 1) < 1e-9
+    # rotation of lens, images and error ellipses together leaves chi^2 unchanged
+    phi = 0.9
+    c, s = np.cos(phi), np.sin(phi)
+    tab3 = tab.copy()
+    tab3[0, 5] += phi
+    th3 = np.stack([c * thp[:, 0] - s * thp[:, 1], s * thp[:, 0] + c * thp[:, 1]], -1)
+    consp3 = dict(consp, theta=th3, phi=consp["phi"] + phi)
+    r3 = orc.chi2_batch(tab3[None], consp3)
+    assert abs(r1["chi2_src"][0] / r3["chi2_src"][0] - 1) < 1e-9
+    # sigma -> k sigma scales chi^2 by 1/k^2
+    consp4 = dict(consp, sig1=consp["sig1"] * 2, sig2=consp["sig2"] * 2)
+    assert abs(orc.chi2_batch(tab[None], consp4)["chi2_src"][0] * 4 / r1["chi2_src"][0] - 1) < 1e-12
+
+
+def test_chi2_image_over_source_plane_tends_to_one(orc):
+    """Eq. (delta): chi2_src approximates chi2_img to first order in the offsets."""
+    tab = row(SIE, 0.0, 0.0, b=8.0, q=0.75, pa=0.2, s=0.4)
+    a = 0.6
+    fi = _images(orc, tab, [0.3, 0.25], a)
+    n = fi["count"][0]
+    th = fi["theta"][0, :n]
+    rng = np.random.default_rng(5)
+    d = rng.normal(0, 1, th.shape)
+    ratios = []
+    for eps in (1e-2, 1e-3, 1e-4):
+        cons = _cons(th + eps * d, [0] * n, 0.5, [a], sig2=0.3, phi=np.full(n, 0.4))
+        r = orc.chi2_batch(tab[None], cons, img_mode=True)
+        ratios.append(r["chi2_img"][0] / r["chi2_src"][0])
+    dev = [abs(x - 1) for x in ratios]
+    assert dev[2] < 1e-3 and dev[2] < dev[1] < dev[0]
+
+
+def test_chi2_img_sis_analytic_images(orc):
+    b, a = 5.0, 0.7
+    tab = row(SIS, 0.0, 0.0, b=b)
+    th = np.array([[4.3, 0.4], [-3.1, -0.2]])
+    cons = _cons(th, [0, 0], 0.5, [a])
+    r = orc.chi2_batch(tab[None], cons, img_mode=True)
+    bm = r["beta_model"][0, 0]
+    u = bm / np.linalg.norm(bm)
+    # SIS images of beta: theta = u (|beta| + ab) and -u (ab - |beta|)
+    t1 = u * (np.linalg.norm(bm) + a * b)
+    t2 = -u * (a * b - np.linalg.norm(bm))
+    exp = (np.sum((th[0] - t1) ** 2) + np.sum((th[1] - t2) ** 2)) / 0.25
+    assert abs(r["chi2_img"][0] - exp) < 1e-9 * exp
+    assert np.allclose(r["theta_model"][0], [t1, t2], atol=1e-9)
+
+
+# ------------------------------------------------------------------ image finder
+def test_sis_two_images_analytic(orc):
+    b, a = 5.0, 0.6
+    beta = np.array([0.7, -0.5])
+    fi = _images(orc, row(SIS, b=b), beta, a)
+    assert fi["count"][0] == 2
+    nb = np.linalg.norm(beta)
+    u = beta / nb
+    exp = sorted([tuple(u * (nb + a * b)), tuple(-u * (a * b - nb))])
+    got = sorted([tuple(t) for t in fi["theta"][0, :2]])
+    assert np.allclose(exp, got, atol=1e-9)
+    for t, m in zip(fi["theta"][0, :2], fi["mu"][0, :2]):
+        assert abs(m - 1 / (1 - a * b / np.linalg.norm(t))) < 1e-8 * abs(m)
+
+
+def test_point_mass_two_images_analytic(orc):
+    thE, a = 2.0, 0.8
+    beta = np.array([0.3, 0.4])
+    fi = _images(orc, row(POINT, b=thE), beta, a, {"x0": -6.0, "y0": -6.0, "h": 0.1, "nx": 120, "ny": 120})
+    assert fi["count"][0] == 2
+    nb = 0.5
+    r = [0.5 * (nb + np.sqrt(nb * nb + 4 * a * thE ** 2)), 0.5 * (nb - np.sqrt(nb * nb + 4 * a * thE ** 2))]
+    exp = sorted([tuple(beta / nb * rr) for rr in r])
+    got = sorted([tuple(t) for t in fi["theta"][0, :2]])
+    assert np.allclose(exp, got, atol=1e-9)
+
+
+def test_nonsingular_lens_gives_odd_counts(orc):
+    tab = row(SIE, b=8.0, q=0.7, pa=0.5, s=0.5)
+    rng = np.random.default_rng(7)
+    betas = rng.uniform(-2.5, 2.5, (12, 2))
+    grid = {"x0": -15.0, "y0": -15.0, "h": 0.15, "nx": 200, "ny": 200}
+    fi = orc.find_images(tab, grid, betas, np.full(12, 0.6))
+    assert np.all(fi["count"] % 2 == 1)
+    assert set(fi["count"]) & {3, 5}
+
+
+def test_halving_h_leaves_counts_and_positions(orc):
+    tab = row(SIE, b=8.0, q=0.7, pa=0.5, s=0.5)
+    betas = np.array([[0.3, 0.2], [1.1, -0.4], [-0.2, 0.9]])
+    g1 = {"x0": -15.0, "y0": -15.0, "h": 0.2, "nx": 150, "ny": 150}
+    g2 = {"x0": -15.0, "y0": -15.0, "h": 0.1, "nx": 300, "ny": 300}
+    a = orc.find_images(tab, g1, betas, np.full(3, 0.6))
+    b = orc.find_images(tab, g2, betas, np.full(3, 0.6))
+    assert np.array_equal(a["count"], b["count"])
+    for s in range(3):
+        n = a["count"][s]
+        ta = np.array(sorted(map(tuple, a["theta"][s, :n])))
+        tb = np.array(sorted(map(tuple, b["theta"][s, :n])))
+        assert np.allclose(ta, tb, atol=1e-9)
+
+
+def _orient_frac(a, b, c):
+    A = [Fraction(v) for v in (*a, *b, *c)]
+    d = (A[2] - A[0]) * (A[5] - A[1]) - (A[3] - A[1]) * (A[4] - A[0])
+    return (d > 0) - (d < 0)
+
+
+def test_exact_orientation_against_rationals(orc):
+    rng = np.random.default_rng(9)
+    for _ in range(3000):
+        a = rng.uniform(-50, 50, 2)
+        b = rng.uniform(-50, 50, 2)
+        t = rng.uniform(-2, 3)
+        c = a + t * (b - a)                       # nearly collinear (rounded)
+        c = c + rng.integers(-3, 4, 2) * np.spacing(np.abs(c) + 1e-300)
+        assert orc.orient(a, b, c) == _orient_frac(a, b, c)
+    # exactly collinear dyadic points
+    assert orc.orient((0.5, 0.25), (1.5, 0.75), (2.5, 1.25)) == 0
+
+
+def _contains_frac(B, s):
+    sg = _orient_frac(B[0], B[1], B[2])
+    if sg == 0:
+        return False
+    for e in range(3):
+        p, q = B[e], B[(e + 1) % 3]
+        o = _orient_frac(p, q, s)
+        if o == 0:
+            d = (q[0] - p[0], q[1] - p[1]) if sg > 0 else (p[0] - q[0], p[1] - q[1])
+            if not (d[0] > 0 or (d[0] == 0 and d[1] > 0)):
+                return False
+        elif o != sg:
+            return False
+    return True
+
+
+def test_brute_force_tiny_grid_candidates(orc):
+    """Every triangle of a tiny grid tested with exact rational arithmetic."""
+    tab = np.vstack([row(SIE, 0.3, -0.2, b=6.0, q=0.7, pa=0.4, s=0.3),
+                     row(PJE, 5.0, 3.0, b=0.8, s=0.0, a=4.0), row(PJE, -4.0, 6.0, b=1.0, s=0.0, a=3.0)])
+    grid = {"x0": -12.0, "y0": -12.0, "h": 1.0, "nx": 24, "ny": 24}
+    a = 0.6
+    bx, by = orc.vertex_beta(tab, grid, a)
+    nx, ny = 24, 24
+    rng = np.random.default_rng(11)
+    srcs = rng.uniform(-1, 1, (6, 2))
+    # include a source placed exactly on a mapped vertex and one on a mapped edge midpoint
+    srcs = np.vstack([srcs, [bx[nx * 12 + 12], by[nx * 12 + 12]]])
+    fi = orc.find_images(tab, grid, srcs, np.full(len(srcs), a), max_cand=10000)
+    n_multi = 0
+    for s in range(len(srcs)):
+        exp = []
+        for j in range(ny - 1):
+            for i in range(nx - 1):
+                v00 = j * nx + i
+                vs = [(v00, v00 + 1, v00 + nx + 1), (v00, v00 + nx + 1, v00 + nx)]
+                for k in range(2):
+                    B = [(bx[v], by[v]) for v in vs[k]]
+                    if _contains_frac(B, srcs[s]):
+                        exp.append(2 * (j * (nx - 1) + i) + k)
+        got = sorted(fi["cand_tri"][fi["cand_src"] == s].tolist())
+        assert got == exp, s
+        n_multi += len(exp) >= 3
+    assert n_multi >= 3
+
+
+def test_shared_vertex_claimed_once(orc):
+    # a source exactly on a mapped grid vertex lies in exactly one triangle (no lens: identity map)
+    tab = np.zeros((0, 8))
+    grid = {"x0": 0.0, "y0": 0.0, "h": 1.0, "nx": 5, "ny": 5}
+    fi = orc.find_images(tab, grid, np.array([[2.5, 2.5], [2.0, 1.5], [1.75, 1.75]]), np.full(3, 1.0))
+    assert fi["count"].tolist() == [1, 1, 1]
+
+
+# ------------------------------------------------------------------ singularity fields
+def test_singularity_field_is_derivative_along_eigenvector(orc):
+    model, _ = W.tiny_model(26, n_main=2, n_mem=4, types=[SIE, PJE])
+    tab = orc.expand(model)
+    x, y = W.random_points(7, 40, 8.0)
+    m = orc.maps(tab, x, y, 1.0)
+    h = 1e-5
+    for k, key in ((1, "e1"), (0, "e2")):
+        H = np.stack([np.stack([m["p11"], m["p12"]], -1), np.stack([m["p12"], m["p22"]], -1)], -2)
+        w, v = np.linalg.eigh(H)
+        vec = v[:, :, k]
+        ep = orc.maps(tab, x + h * vec[:, 0], y + h * vec[:, 1], 1.0)[key]
+        em = orc.maps(tab, x - h * vec[:, 0], y - h * vec[:, 1], 1.0)[key]
+        fd = (ep - em) / (2 * h)
+        f = m["f1"] if key == "e1" else m["f2"]
+        assert np.allclose(np.abs(f), np.abs(fd), rtol=1e-5, atol=1e-7)
+
+
+def test_sie_cusp_field_vanishes_on_symmetry_axes(orc):
+    pa = 0.6
+    tab = row(SIE, 0.0, 0.0, b=6.0, q=0.7, pa=pa, s=0.0)
+    r = np.linspace(0.5, 9.0, 17)
+    c, s = np.cos(pa), np.sin(pa)
+    on_major = orc.maps(tab, r * c, r * s, 1.0)
+    on_minor = orc.maps(tab, -r * s, r * c, 1.0)
+    assert np.allclose(on_major["f1"], 0, atol=1e-10)
+    assert np.allclose(on_minor["f1"], 0, atol=1e-10)
+    off = orc.maps(tab, r * np.cos(pa + 0.4), r * np.sin(pa + 0.4), 1.0)
+    assert np.min(np.abs(off["f1"])) > 1e-6

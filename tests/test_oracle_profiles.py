@@ -1,0 +1,256 @@
+"""Pins for the oracle's halo profiles (deflection, Hessian and third derivatives).
+
+The paper prints no profile formula (Sec. 2.1 lists >20 models); each profile is
+defined here by its convergence kappa, and the oracle's closed-form deflections and
+AD derivatives are pinned to that definition through identities that a dropped
+term, a wrong sign or a transposed operand would break:
+  * div alpha = 2 kappa (Poisson equation behind alpha = grad psi),
+  * curl alpha = 0,
+  * Gauss' theorem on circles (flux of alpha = 2 x enclosed kappa),
+  * the integral definition of elliptical deflections (Schramm-type J integrals),
+  * closed forms for point mass and SIS, limits and symmetries.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+POINT, SIS, SIE, PJE, NFW, ENFW = 0, 1, 2, 3, 4, 5
+
+
+def row(t, x=0.0, y=0.0, b=1.0, q=1.0, pa=0.0, s=0.0, a=0.0):
+    return np.array([[t, x, y, b, q, pa, s, a]], dtype=np.float64)
+
+
+def prime(x, y, xc, yc, pa):
+    c, s = np.cos(pa), np.sin(pa)
+    dx, dy = x - xc, y - yc
+    return c * dx + s * dy, -s * dx + c * dy
+
+
+def nfw_kappa_X(X, ks):
+    X = np.asarray(X, dtype=np.float64)
+    out = np.empty_like(X)
+    lo, hi, one = X < 1 - 1e-6, X > 1 + 1e-6, np.abs(X - 1) <= 1e-6
+    F = np.empty_like(X)
+    F[lo] = np.arccosh(1 / X[lo]) / np.sqrt(1 - X[lo] ** 2)
+    F[hi] = np.arccos(1 / X[hi]) / np.sqrt(X[hi] ** 2 - 1)
+    out[lo | hi] = 2 * ks * (1 - F[lo | hi]) / (X[lo | hi] ** 2 - 1)
+    out[one] = 2 * ks / 3
+    return out
+
+
+def kappa_def(r, x, y):
+    """Convergence from the profile definitions (test-side, independent of the oracle)."""
+    t, xc, yc, b, q, pa, s, a = r[0]
+    t = int(t)
+    xp, yp = prime(x, y, xc, yc, pa)
+    if t == POINT:
+        return np.zeros_like(x)
+    if t == SIS:
+        return b / (2 * np.hypot(xp, yp))
+    if t == SIE:
+        return 0.5 * b / np.sqrt(s * s + xp ** 2 + yp ** 2 / q ** 2)
+    if t == PJE:
+        return 0.5 * b / np.sqrt(s * s + xp ** 2 + yp ** 2 / q ** 2) - 0.5 * b / np.sqrt(a * a + xp ** 2 + yp ** 2 / q ** 2)
+    if t in (NFW, ENFW):
+        qq = q if t == ENFW else 1.0
+        return nfw_kappa_X(np.sqrt(xp ** 2 + yp ** 2 / qq ** 2) / s, b)
+    raise ValueError
+
+
+CASES = [
+    row(SIS, 0.3, -0.4, b=2.5),
+    row(SIE, 0.5, 0.2, b=6.0, q=0.7, pa=0.6, s=0.4),
+    row(SIE, -1.0, 0.3, b=3.0, q=0.55, pa=2.2, s=0.0),
+    row(PJE, 0.1, -0.2, b=4.0, q=0.8, pa=-0.4, s=0.3, a=12.0),
+    row(PJE, 0.0, 0.0, b=1.2, q=1.0, s=0.0, a=5.0),
+    row(NFW, -0.5, 0.5, b=0.3, s=15.0),
+    row(ENFW, 0.2, 0.1, b=0.25, q=0.65, pa=1.1, s=20.0),
+]
+IDS = ["sis", "sie_cored", "sie_singular", "pje_ell", "pje_circ_trunc", "nfw", "enfw"]
+
+
+def pts(seed, n=40, half=8.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-half, half, n), rng.uniform(-half, half, n)
+
+
+def test_sis_constant_deflection(orc):
+    x, y = pts(1)
+    m = orc.maps(row(SIS, 1.0, -2.0, b=3.0), x, y, 0.7)
+    r = np.hypot(x - 1, y + 2)
+    assert np.allclose(np.hypot(m["ax"], m["ay"]), 3.0, rtol=0, atol=1e-14)
+    assert np.allclose(m["ax"] * (y + 2) - m["ay"] * (x - 1), 0, atol=1e-13)   # radial
+    # SIS: det A = 1 - a b / r (a_dis = 0.7)
+    assert np.allclose(m["detA"], 1 - 0.7 * 3.0 / r, rtol=1e-13, atol=1e-13)
+
+
+def test_point_mass_closed_form(orc):
+    x, y = pts(2)
+    m = orc.maps(row(POINT, 0.5, 0.5, b=1.7), x, y, 1.0)
+    dx, dy = x - 0.5, y - 0.5
+    r2 = dx * dx + dy * dy
+    assert np.allclose(m["ax"], 1.7 ** 2 * dx / r2, rtol=1e-14)
+    assert np.allclose(m["ay"], 1.7 ** 2 * dy / r2, rtol=1e-14)
+    assert np.allclose(m["kappa"], 0, atol=1e-13)
+    assert np.allclose(m["gamma1"], 1.7 ** 2 * (dy ** 2 - dx ** 2) / r2 ** 2, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("q,s,pa", [(0.7, 0.5, 0.0), (0.6, 0.0, 0.9), (0.9, 2.0, 2.5)])
+def test_sie_closed_form_equals_integral_definition(orc, q, s, pa):
+    b = 5.0
+    e2 = 1 - q * q
+    x, y = pts(3, 6)
+    m = orc.maps(row(SIE, 0.2, -0.1, b=b, q=q, pa=pa, s=s), x, y, 1.0)
+    for i in range(x.size):
+        xp, yp = prime(x[i], y[i], 0.2, -0.1, pa)
+
+        def J(n):
+            f = lambda u: 0.5 * b / np.sqrt(s * s + u * (xp * xp + yp * yp / (1 - e2 * u))) / (1 - e2 * u) ** (n + 0.5)
+            return integrate.quad(f, 0, 1, epsabs=1e-15, epsrel=1e-13, limit=200)[0]
+        axp, ayp = q * xp * J(0), q * yp * J(1)
+        c, sn = np.cos(pa), np.sin(pa)
+        assert abs(m["ax"][i] - (c * axp - sn * ayp)) < 1e-11
+        assert abs(m["ay"][i] - (sn * axp + c * ayp)) < 1e-11
+
+
+def test_sie_circular_limit(orc):
+    x, y = pts(4)
+    s, b = 0.8, 4.0
+    m = orc.maps(row(SIE, 0, 0, b=b, q=1 - 1e-9, pa=0.3, s=s), x, y, 1.0)
+    r2 = x * x + y * y
+    f = b * (np.sqrt(s * s + r2) - s) / r2
+    assert np.allclose(m["ax"], f * x, rtol=1e-7)
+    assert np.allclose(m["ay"], f * y, rtol=1e-7)
+
+
+def test_truncated_isothermal_closed_form_and_far_field(orc):
+    b, a = 1.3, 4.0
+    x, y = pts(5)
+    m = orc.maps(row(PJE, 0, 0, b=b, q=1.0, s=0.0, a=a), x, y, 1.0)
+    r = np.hypot(x, y)
+    ar = b * (r - np.sqrt(a * a + r * r) + a) / r
+    assert np.allclose(np.hypot(m["ax"], m["ay"]), ar, rtol=1e-13)
+    # far field: point mass with theta_E^2 = b a
+    far = orc.maps(row(PJE, 0, 0, b=b, q=1.0, s=0.0, a=a), np.array([4000.0]), np.array([3000.0]), 1.0)
+    assert abs(np.hypot(far["ax"][0], far["ay"][0]) * 5000.0 / (b * a) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("r", CASES, ids=IDS)
+def test_divergence_is_twice_kappa(orc, r):
+    x, y = pts(6)
+    m = orc.maps(r, x, y, 1.0)
+    kd = kappa_def(r, x, y)
+    assert np.allclose(m["kappa"], kd, rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("r", CASES, ids=IDS)
+def test_hessian_matches_finite_differences_and_is_curl_free(orc, r):
+    x, y = pts(7, 12)
+    m = orc.maps(r, x, y, 1.0)
+    h = 1e-5
+    axp, ayp = orc.alpha(r, x + h, y)
+    axm, aym = orc.alpha(r, x - h, y)
+    bxp, byp = orc.alpha(r, x, y + h)
+    bxm, bym = orc.alpha(r, x, y - h)
+    d11 = (axp - axm) / (2 * h)
+    d21 = (ayp - aym) / (2 * h)
+    d12 = (bxp - bxm) / (2 * h)
+    d22 = (byp - bym) / (2 * h)
+    sc = 1 + np.abs(m["p11"]) + np.abs(m["p22"])
+    assert np.all(np.abs(d11 - m["p11"]) / sc < 1e-7)
+    assert np.all(np.abs(d22 - m["p22"]) / sc < 1e-7)
+    assert np.all(np.abs(d12 - m["p12"]) / sc < 1e-7)
+    assert np.all(np.abs(d21 - d12) / sc < 1e-7)      # curl alpha = 0
+
+
+@pytest.mark.parametrize("r", CASES, ids=IDS)
+def test_third_derivatives(orc, r):
+    x, y = pts(8, 12)
+    m = orc.maps(r, x, y, 1.0)
+    h = 1e-5
+    mxp = orc.maps(r, x + h, y, 1.0)
+    mxm = orc.maps(r, x - h, y, 1.0)
+    myp = orc.maps(r, x, y + h, 1.0)
+    mym = orc.maps(r, x, y - h, 1.0)
+    d111 = (mxp["p11"] - mxm["p11"]) / (2 * h)
+    d112 = (myp["p11"] - mym["p11"]) / (2 * h)
+    d122 = (myp["p12"] - mym["p12"]) / (2 * h)
+    d222 = (myp["p22"] - mym["p22"]) / (2 * h)
+    d122b = (mxp["p22"] - mxm["p22"]) / (2 * h)
+    sc = 1 + np.abs(m["p111"]) + np.abs(m["p222"]) + np.abs(m["p112"]) + np.abs(m["p122"])
+    for a_, b_ in ((d111, m["p111"]), (d112, m["p112"]), (d122, m["p122"]), (d222, m["p222"]),
+                   (d122b, m["p122"])):
+        assert np.all(np.abs(a_ - b_) / sc < 1e-6)
+    # psi_111 + psi_122 = 2 d kappa/dx, psi_112 + psi_222 = 2 d kappa/dy (defining kappa)
+    kx = (kappa_def(r, x + h, y) - kappa_def(r, x - h, y)) / (2 * h)
+    ky = (kappa_def(r, x, y + h) - kappa_def(r, x, y - h)) / (2 * h)
+    assert np.all(np.abs(m["p111"] + m["p122"] - 2 * kx) / sc < 1e-6)
+    assert np.all(np.abs(m["p112"] + m["p222"] - 2 * ky) / sc < 1e-6)
+
+
+@pytest.mark.parametrize("r", [CASES[1], CASES[3], CASES[6]], ids=["sie", "pje", "enfw"])
+def test_gauss_theorem_on_circles(orc, r):
+    """Flux of alpha through a circle around the centre = 2 x kappa integrated over the disk."""
+    xc, yc = r[0, 1], r[0, 2]
+    for R in (0.7, 3.0, 9.0):
+        phi = np.linspace(0, 2 * np.pi, 4097)[:-1]
+        x, y = xc + R * np.cos(phi), yc + R * np.sin(phi)
+        ax, ay = orc.alpha(r, x, y)
+        flux = np.mean(ax * np.cos(phi) + ay * np.sin(phi)) * 2 * np.pi * R   # periodic trapezoid
+        mass = integrate.dblquad(lambda rr, ph: kappa_def(r, np.array([xc + rr * np.cos(ph)]),
+                                                          np.array([yc + rr * np.sin(ph)]))[0] * rr,
+                                 0, 2 * np.pi, 0, R, epsabs=1e-12, epsrel=1e-10)[0]
+        assert abs(flux / (2 * mass) - 1) < 1e-8
+
+
+def test_nfw_enclosed_mass(orc):
+    ks, rs = 0.3, 15.0
+    for R in (0.5, 5.0, 15.0, 40.0):
+        m = orc.maps(row(NFW, 0, 0, b=ks, s=rs), np.array([R]), np.array([0.0]), 1.0)
+        enc = integrate.quad(lambda r: nfw_kappa_X(np.array([r / rs]), ks)[0] * r, 0, R,
+                             epsabs=1e-14, epsrel=1e-12, points=[rs] if R > rs else None)[0]
+        assert abs(m["ax"][0] / (2 * enc / R) - 1) < 1e-9
+
+
+def test_enfw_circular_limit_equals_nfw(orc):
+    x, y = pts(9)
+    a = orc.maps(row(NFW, 0.3, 0.1, b=0.2, s=20.0), x, y, 1.0)
+    b = orc.maps(row(ENFW, 0.3, 0.1, b=0.2, q=1 - 1e-10, pa=0.7, s=20.0), x, y, 1.0)
+    for k in ("ax", "ay", "p11", "p12", "p22"):
+        assert np.allclose(a[k], b[k], rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("r", CASES[1:4] + CASES[6:], ids=["sie_cored", "sie_singular", "pje", "enfw"])
+def test_rotation_covariance(orc, r):
+    x, y = pts(10, 10)
+    phi = 0.83
+    c, s = np.cos(phi), np.sin(phi)
+    r2 = r.copy()
+    r2[0, 1], r2[0, 2] = c * r[0, 1] - s * r[0, 2], s * r[0, 1] + c * r[0, 2]
+    r2[0, 5] = r[0, 5] + phi
+    m1 = orc.maps(r, x, y, 1.0)
+    m2 = orc.maps(r2, c * x - s * y, s * x + c * y, 1.0)
+    assert np.allclose(m2["ax"], c * m1["ax"] - s * m1["ay"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(m2["ay"], s * m1["ax"] + c * m1["ay"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(m2["kappa"], m1["kappa"], rtol=1e-9, atol=1e-12)
+    gm1 = np.hypot(m1["gamma1"], m1["gamma2"])
+    gm2 = np.hypot(m2["gamma1"], m2["gamma2"])
+    assert np.allclose(gm1, gm2, rtol=1e-9, atol=1e-12)
+
+
+def test_singular_centre_flag(orc):
+    m = orc.maps(row(SIS, 1.0, 2.0, b=2.0), np.array([1.0, 1.5]), np.array([2.0, 2.0]), 1.0)
+    assert m["flags"][0] & orc.F_SINGULAR and not m["flags"][1] & orc.F_SINGULAR
+    assert m["ax"][0] == 0 and m["ay"][0] == 0
+
+
+def test_table_order_sum_is_superposition(orc):
+    from paper_2609_08649_amd import workloads as W
+    model, _ = W.tiny_model(11, n_main=4, n_mem=5)
+    tab = orc.expand(model)
+    x, y = pts(12)
+    tot = orc.maps(tab, x, y, 0.6)
+    parts = [orc.maps(tab[h:h + 1], x, y, 0.6) for h in range(tab.shape[0])]
+    for k in ("ax", "ay", "p11", "p12", "p22", "p111", "p222"):
+        assert np.allclose(tot[k], sum(p[k] for p in parts), rtol=1e-12, atol=1e-12)
