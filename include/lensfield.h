@@ -1,0 +1,258 @@
+/*
+ * lensfield — MI355X (gfx950) implementation of the lens-equation hot path of
+ * parametric strong-lens modeling (arXiv 2609.08649, "LensFactory.jl").
+ *
+ * Plain C ABI.  Every call returns an lf_status (0 = LF_OK, negative = error);
+ * lf_last_error() returns a message for the last failing call on a context.
+ * No exception crosses the boundary.
+ *
+ * Conventions (paper Sec. 2.1):
+ *   - Angles are in arcsec (the angular scale theta_0 is 1").
+ *   - The lensing potential psi, the deflection alpha = grad psi, the deformation
+ *     tensor psi_ij, kappa and gamma are defined WITHOUT the distance ratio
+ *     a_dis = D_ds / D_s; a_dis enters only the lens equation
+ *     beta = theta - a_dis alpha (Eq. lens_eq) and the Jacobian
+ *     A_ij = delta_ij - a_dis psi_ij (Eq. jac).
+ *   - Position angles are counter-clockwise from +x; PA = 0 puts the major axis
+ *     of an elliptical profile on +x.
+ *
+ * Memory and ownership:
+ *   - "device" pointers are HIP device allocations owned by the caller (for example
+ *     the data_ptr of a torch CUDA/ROCm tensor); "host" pointers are ordinary host
+ *     memory owned by the caller.  The library never frees caller memory.
+ *   - Models and constraint sets are copied into library-owned device tables at
+ *     upload and stay resident until released.
+ *   - Compute calls are asynchronous on the caller's stream (a hipStream_t passed
+ *     as void*; NULL = the default stream); outputs are valid once that stream has
+ *     synchronised.  Calls that share an lf_ctx share its scratch workspace: issue
+ *     them from one host thread on one stream, or use one context per stream.
+ *   - All per-point / per-sample outputs are structure-of-arrays in FP64, sample
+ *     major: element (s, p) of a plane lives at plane[s * P + p].
+ *
+ * Precision (lf_prec):
+ *   LF_PREC_FP64  every step in IEEE double precision.
+ *   LF_PREC_MIXED member-galaxy halo terms in FP32 accumulated in FP64; main halos,
+ *                 beta, det A, mu, chi^2, triangle containment, Newton polishing and
+ *                 the final multi-plane source positions in FP64.
+ */
+#ifndef LENSFIELD_H
+#define LENSFIELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lf_status;
+enum {
+  LF_OK = 0,
+  LF_E_INVALID_ARG = -1,   /* bad argument; nothing was launched                       */
+  LF_E_UNSUPPORTED = -2,   /* valid request the library does not implement              */
+  LF_E_OUT_OF_BUDGET = -3, /* request exceeds the context's HBM budget                   */
+  LF_E_DEVICE = -4,        /* HIP runtime error; the context should be shut down         */
+  LF_E_OVERFLOW = -5,      /* an output capacity was exceeded (see per-item flags)       */
+  LF_E_NOT_READY = -6      /* serving: ticket not complete yet                           */
+};
+
+typedef enum { LF_PREC_FP64 = 0, LF_PREC_MIXED = 1 } lf_prec;
+
+/* Halo profiles.  Field meaning per profile (all a_dis-free, arcsec):
+ *   LF_POINT  b = Einstein radius (alpha = b^2 r / |r|^2)
+ *   LF_SIS    b = isothermal strength (|alpha| = b)
+ *   LF_SIE    cored isothermal ellipsoid, kappa = (b/2) / sqrt(s^2 + x'^2 + y'^2/q^2)
+ *   LF_PJE    pseudo-Jaffe / dPIE = SIE(b, q, s) - SIE(b, q, a), 0 <= s < a (Sec. 3.4)
+ *   LF_NFW    circular NFW: b = kappa_s, s = r_s
+ *   LF_ENFW   elliptical NFW: kappa(xi), xi^2 = x'^2 + y'^2/q^2; b = kappa_s, s = r_s */
+typedef enum { LF_POINT = 0, LF_SIS = 1, LF_SIE = 2, LF_PJE = 3, LF_NFW = 4, LF_ENFW = 5 } lf_profile;
+
+/* How a raw value becomes a lensing-unit field. */
+typedef enum {
+  LF_XF_NONE = 0,       /* value already in lensing units                                  */
+  LF_XF_SIGMA_TO_B = 1, /* velocity dispersion [km/s] -> b = 4 pi (sigma/c)^2 [arcsec]      */
+  LF_XF_KPC = 2,        /* proper length at the lens redshift [kpc] -> arcsec              */
+  LF_XF_EPS_TO_Q = 3,   /* ellipticity (1-q)/(1+q) -> q (Sec. 2.1)                         */
+  LF_XF_DEG = 4,        /* degrees -> radians                                              */
+  LF_XF_M200 = 5,       /* NFW virial mass M200 [Msun] in the b slot (pairs with C200)      */
+  LF_XF_C200 = 6        /* NFW concentration c200 in the s slot                            */
+} lf_xform;
+
+typedef enum { LF_FIXED = 0, LF_FREE = 1 } lf_bind_kind;
+
+/* A model field: a fixed value, or column `index` of a parameter sample row. */
+typedef struct {
+  int32_t kind;   /* lf_bind_kind */
+  int32_t index;  /* column of the sample row when kind == LF_FREE          */
+  int32_t xform;  /* lf_xform                                               */
+  int32_t pad;
+  double value;   /* raw value when kind == LF_FIXED                       */
+} lf_binding;
+
+/* Main component (cluster halo, individually modelled galaxy).  Fields in order
+ * x, y, b, q, pa, s, a. */
+typedef struct {
+  int32_t type;   /* lf_profile */
+  int32_t pad;
+  lf_binding f[7];
+} lf_component;
+
+/* Member galaxies on the scaling relations of Sec. 3.4, Eq. (scaling):
+ * v_d = v* (L/L*)^lam, theta_core = theta*_core (L/L*)^bet, theta_cut = theta*_cut (L/L*)^alp.
+ * Per member: b = bmul * lum^(2 lam), s = smul * lum^bet, a = amul * lum^alp when lum != NULL,
+ * else b = bmul * b0, s = smul * s0, a = amul * a0.  bmul/smul/amul are bindings
+ * (bmul usually v* with LF_XF_SIGMA_TO_B).  All arrays are host pointers of length n;
+ * q and pa may be NULL (circular members). */
+typedef struct {
+  int32_t n;
+  int32_t pad;
+  const int32_t* type;
+  const double *x, *y, *q, *pa;
+  const double* lum;
+  double lam, bet, alp;
+  const double *b0, *s0, *a0;
+  lf_binding bmul, smul, amul;
+} lf_members;
+
+/* Flat LCDM (Omega_r = 0, w = -1; the paper's defaults are H0 = 70, Om = 0.3). */
+typedef struct { double H0, Om; } lf_cosmo;
+
+/* Regular grid of pixel centres: point (i, j) = (x0 + (i + 1/2) h, y0 + (j + 1/2) h),
+ * flattened p = j * nx + i. */
+typedef struct { double x0, y0, h; int32_t nx, ny; } lf_grid;
+
+/* Evaluation points: the grid when px == NULL, else explicit device arrays px, py of length n. */
+typedef struct {
+  lf_grid grid;
+  const double* px;
+  const double* py;
+  int64_t n;
+} lf_points;
+
+/* Caller-owned device output planes, each [S][P] FP64 (flags int32).  NULL = not requested.
+ * psi1xx planes are third potential derivatives (singularity maps, Sec. 6); e1 = kappa + |gamma|,
+ * e2 = kappa - |gamma|; f1, f2 = v_k . grad e_k (A3-line fields, zero where |gamma| ~ 0). */
+typedef struct {
+  double *alpha_x, *alpha_y;
+  double *psi11, *psi12, *psi22;
+  double *kappa, *gamma1, *gamma2;
+  double *detA, *mu;
+  double *beta_x, *beta_y;
+  double *psi111, *psi112, *psi122, *psi222;
+  double *e1, *e2, *f1, *f2;
+  int32_t* flags;
+} lf_maps;
+
+/* Per-item flag bits (maps: per point; chi^2: per sample; finder: per source). */
+enum {
+  LF_F_SINGULAR = 1,   /* a point sits on a singular halo centre (its term is zero) */
+  LF_F_GSING = 2,      /* singular family matrix G; pseudo-inverse used             */
+  LF_F_NOCONV = 4,     /* Newton did not converge                                   */
+  LF_F_REJECT = 8,     /* image-plane solution rejected (moved > 10 sigma / parity)  */
+  LF_F_MERGED = 16,    /* finder merged duplicate candidates                        */
+  LF_F_OVERFLOW = 32,  /* more images / candidates than the output capacity         */
+  LF_F_UMBILIC = 64,   /* |gamma| ~ 0: singularity fields not evaluated             */
+  LF_F_INVALID = 128   /* sampled parameters out of range (result is NaN)          */
+};
+
+typedef struct lf_ctx lf_ctx;
+typedef struct lf_model lf_model;
+typedef struct lf_cons lf_cons;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the library's own
+ * device allocations (0 = 90% of free memory).  Errors: LF_E_INVALID_ARG, LF_E_DEVICE. */
+lf_status lf_init(lf_ctx** out, int32_t device, size_t hbm_budget_bytes);
+lf_status lf_shutdown(lf_ctx* ctx);
+const char* lf_last_error(const lf_ctx* ctx);
+/* Library-owned device bytes currently allocated by this context. */
+size_t lf_device_bytes(const lf_ctx* ctx);
+
+/* ---------------------------------------------------------------- cosmology helpers (host) */
+/* Angular-diameter distance D(z1, z2) [Mpc] in flat LCDM (Sec. 2.1, 2.2). */
+lf_status lf_cosmo_dist(const lf_cosmo* c, double z1, double z2, double* out);
+/* Distance ratio a_dis = D(z_d, z_s) / D(0, z_s) of Eq. (lens_eq). */
+lf_status lf_cosmo_adis(const lf_cosmo* c, double z_d, double z_s, double* out);
+/* NFW (kappa_s, r_s[arcsec]) from (M200 [Msun], c200) at lens redshift z_d; kappa_s is
+ * relative to the a_dis-free critical density c^2 / (4 pi G D_d). */
+lf_status lf_nfw_params(const lf_cosmo* c, double z_d, double m200, double c200,
+                        double* kappa_s, double* r_s);
+
+/* ---------------------------------------------------------------- resident model tables */
+/* Upload a parametric model (step a1: main components with field bindings + members on
+ * the scaling relations, Sec. 3.4).  `n_free` is the width of a parameter sample row.
+ * All pointers are host pointers; the library copies them.  Errors: LF_E_INVALID_ARG
+ * (bad profile code, binding index >= n_free, a fixed field out of range). */
+lf_status lf_model_upload(lf_ctx* ctx, const lf_component* main, int32_t n_main,
+                          const lf_members* members, double z_d, const lf_cosmo* cosmo,
+                          int32_t n_free, lf_model** out);
+lf_status lf_model_release(lf_ctx* ctx, lf_model* m);
+int32_t lf_model_n_halos(const lf_model* m);
+
+/* Upload image-position constraints (Sec. 3.1): observed positions theta [n_img*2],
+ * family id [n_img] in 0..n_fam-1, error-ellipse semi-axes sig1, sig2 and angle phi
+ * [n_img] (S_i = R^T diag(sig1^2, sig2^2) R; circular errors: sig1 = sig2, phi = 0), and
+ * the distance ratio of each family a_fam [n_fam].  Host pointers, copied. */
+lf_status lf_constraints_upload(lf_ctx* ctx, const double* theta, const int32_t* family,
+                                const double* sig1, const double* sig2, const double* phi,
+                                int32_t n_img, const double* a_fam, int32_t n_fam, lf_cons** out);
+lf_status lf_constraints_release(lf_ctx* ctx, lf_cons* c);
+
+/* ---------------------------------------------------------------- hot-path calls */
+/* Steps a1-a3 (+a7): for each of S parameter samples (device params [S * n_free], or
+ * NULL with S = 1 when the model has no free field) and each point, the halo sum of
+ * alpha and psi_ij (Sec. 2.1) and, when any of psi111..f2 is requested, the third
+ * derivatives psi_ijk and the A3-line fields of Sec. 6.  a_dis > 0 sets beta, det A, mu.
+ * Errors: LF_E_INVALID_ARG (no output requested, S < 1, bad points), LF_E_UNSUPPORTED
+ * (third derivatives of an elliptical NFW). */
+lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
+                       const lf_points* pts, double a_dis, lf_prec prec, const lf_maps* out,
+                       void* stream);
+
+/* Step a4: chi^2 per parameter sample (Sec. 3.1).  mode 0 = source plane, Eq. (chi2_src)
+ * with the full magnification tensor mu_i = A^-1(theta_obs) and beta_model = G^-1 g;
+ * mode 1 = image plane, Eq. (chi2_img), with each model image found by Newton-Raphson
+ * from its observed position towards beta_model (Sec. 3.5; stop |dtheta| < 1e-9" in FP64,
+ * 1e-6" in MIXED, at most 20 steps; an image that does not converge, moves > 10 sigma or
+ * changes parity keeps its source-plane term and is flagged).
+ * params: device [S * n_free]; chi2: device [S]; flags: device [S] (or NULL).
+ * beta_model: device [S * n_fam * 2] or NULL. */
+lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
+                        const lf_cons* c, int32_t mode, lf_prec prec, double* chi2,
+                        int32_t* flags, double* beta_model, void* stream);
+
+/* Step a5: image finder by triangle mapping (replacing the marching-squares contours of
+ * Sec. 2.3).  Grid vertices are pixel centres; cell (i, j) splits along its
+ * (i,j)-(i+1,j+1) diagonal.  A source is inside a mapped triangle by exact orientation
+ * signs (ties broken by edge direction so shared edges are watertight); each candidate is
+ * polished by FP64 Newton (<= 30 steps to |d beta| < 1e-10"), accepted if it stays within
+ * 2h of its start, and merged with an earlier image closer than 1e-6".
+ * params: device row [n_free] or NULL; beta: device [n_src*2]; a_src: device [n_src].
+ * Outputs (device): theta_out [n_src*max_img*2], mu_out [n_src*max_img], count_out [n_src]
+ * (true count even when it exceeds max_img), flags [n_src] or NULL. */
+lf_status lf_find_images(lf_ctx* ctx, const lf_model* m, const double* params,
+                         const double* beta, const double* a_src, int32_t n_src,
+                         const lf_grid* grid, int32_t max_img, lf_prec prec, double* theta_out,
+                         double* mu_out, int32_t* count_out, int32_t* flags, void* stream);
+
+/* Step a6: multi-plane ray trace (Sec. 2.2).  planes sorted by z_planes (increasing),
+ * each a model without free fields.  For each point and each source redshift z_src[k]:
+ * beta [n_zs][P][2], Jacobian A [n_zs][P][4] (A11 A12 A21 A22; not symmetric), mu [n_zs][P].
+ * Planes at or behind a source do not deflect it.  Any output may be NULL. */
+lf_status lf_multiplane_trace(lf_ctx* ctx, const lf_model* const* planes, const double* z_planes,
+                              int32_t n_planes, const lf_cosmo* cosmo, const double* z_src,
+                              int32_t n_zs, const lf_points* pts, lf_prec prec, double* beta_out,
+                              double* A_out, double* mu_out, void* stream);
+
+/* Multi-plane image finder: as lf_find_images, each source at its own redshift
+ * z_src [n_src] (host pointer; device beta). */
+lf_status lf_find_images_mp(lf_ctx* ctx, const lf_model* const* planes, const double* z_planes,
+                            int32_t n_planes, const lf_cosmo* cosmo, const double* beta,
+                            const double* z_src, int32_t n_src, const lf_grid* grid,
+                            int32_t max_img, lf_prec prec, double* theta_out, double* mu_out,
+                            int32_t* count_out, int32_t* flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LENSFIELD_H */

@@ -1,0 +1,72 @@
+// Host-side internal state of the lensfield library (contexts, resident tables).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lensfield.h"
+#include "lf_internal.h"
+#include "lf_launch.h"
+
+#define LF_ENFW_NODES 24
+
+struct lf_ctx {
+  int device = 0;
+  size_t budget = 0, dev_bytes = 0;
+  int n_cu = 256;
+  std::string arch;
+  std::string last_error;
+  struct Buf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  double* quad_u = nullptr;
+  double* quad_w = nullptr;
+  void* extras = nullptr;     // autotuner / batch plans
+  lf_status fail(lf_status st, const char* fmt, ...);
+  lf_status hip(hipError_t e, const char* what);
+  void* ws(const char* name, size_t bytes, hipStream_t st, lf_status* err);
+  lf_status dmalloc(void** p, size_t bytes);
+  void dfree(void* p, size_t bytes);
+  int maps_ppl(bool mixed, bool d3);
+};
+
+struct lf_model {
+  int n_free = 0;
+  double z_d = 0;
+  lf_cosmo cosmo{70.0, 0.3};
+  lf::XfConst xc{};
+  std::vector<lf::MainDesc> main;
+  std::vector<lf::MemCat> mem;
+  lf::SegOff seg{};
+  lf::Bind mul[3];
+  lf::MainDesc* d_main = nullptr;
+  lf::MemCat* d_mem = nullptr;
+  size_t d_main_bytes = 0, d_mem_bytes = 0;
+};
+
+struct lf_cons {
+  int n_img = 0, n_fam = 0;
+  std::vector<int> order;        // host: constraint index of each sorted image
+  std::vector<int> fam_start;    // host: [n_fam + 1] offsets of families in sorted order
+  double* d_theta = nullptr;     // [n_img*2] sorted by family
+  double* d_sinv = nullptr;      // [n_img*3] S^-1 (xx, xy, yy)
+  double* d_sigmax = nullptr;    // [n_img] max(sig1, sig2)
+  int* d_fam = nullptr;          // [n_img] family of each sorted image
+  int* d_fam_start = nullptr;    // [n_fam + 1]
+  double* d_afam = nullptr;      // [n_fam]
+  size_t bytes = 0;
+};
+
+lf::XfConst lf_xf_const(const lf_cosmo* c, double zd);
+lf::DevModel lf_dev_model(const lf_model* M);
+lf::QuadTab lf_quad(const lf_ctx* ctx);
+bool lf_model_has_enfw(const lf_model* M);
+bool lf_points_spec(const lf_points* p, lf::PointsSpec& s);
+lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params, int S, bool need_mem,
+                           hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
+                           lf::MemRec64** m64, const char* tag);
+void lf_release_extras(lf_ctx* ctx);

@@ -1,0 +1,340 @@
+// Device-side lens profile mathematics for gfx950.
+//
+// Every profile returns its deflection alpha, deformation tensor psi_ij and, on request,
+// third potential derivatives psi_ijk in closed form (hand-derived, verified against
+// finite differences); all quantities are a_dis-free (Sec. 2.1).  T is float (member
+// galaxies in the mixed-precision path) or double.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lf_internal.h"
+
+namespace lf {
+
+enum { T_POINT = 0, T_SIS = 1, T_SIE = 2, T_PJE = 3, T_NFW = 4, T_ENFW = 5 };
+enum { FL_SINGULAR = 1, FL_GSING = 2, FL_NOCONV = 4, FL_REJECT = 8, FL_MERGED = 16,
+       FL_OVERFLOW = 32, FL_UMBILIC = 64, FL_INVALID = 128 };
+
+// Reciprocal and reciprocal square root: the hardware instructions (1 ulp) in FP32,
+// correctly rounded sequences in FP64.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float fatan(float x) { return atanf(x); }
+__device__ __forceinline__ double fatan(double x) { return atan(x); }
+__device__ __forceinline__ float fatanh(float x) { return atanhf(x); }
+__device__ __forceinline__ double fatanh(double x) { return atanh(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// Per-point FP64 accumulators.
+struct Acc {
+  double ax, ay, h11, h12, h22, t111, t112, t122, t222;
+  int flags;
+  __device__ void zero() { ax = ay = h11 = h12 = h22 = t111 = t112 = t122 = t222 = 0.0; flags = 0; }
+};
+
+template <class T>
+struct Term {
+  T ax, ay, h11, h12, h22, t111, t112, t122, t222;
+};
+
+template <bool D3, class T>
+__device__ __forceinline__ void add(Acc& a, const Term<T>& t) {
+  a.ax += (double)t.ax; a.ay += (double)t.ay;
+  a.h11 += (double)t.h11; a.h12 += (double)t.h12; a.h22 += (double)t.h22;
+  if (D3) { a.t111 += (double)t.t111; a.t112 += (double)t.t112; a.t122 += (double)t.t122; a.t222 += (double)t.t222; }
+}
+
+// ---------------------------------------------------------------------------------------
+// Circularly symmetric profiles: alpha = m(r^2) r_vec, psi_ij = m delta_ij + w x_i x_j with
+// w = 2 dm/d(r^2), psi_ijk = w (delta_ij x_k + delta_ik x_j + delta_jk x_i) + 2 w' x_i x_j x_k.
+// ---------------------------------------------------------------------------------------
+template <bool D3, class T>
+__device__ __forceinline__ void radial(T dx, T dy, T m, T w, T wp, Term<T>& t) {
+  t.ax = m * dx; t.ay = m * dy;
+  T wx = w * dx, wy = w * dy;
+  t.h11 = fma(wx, dx, m); t.h22 = fma(wy, dy, m); t.h12 = wx * dy;
+  if (D3) {
+    T q = (T)2 * wp;
+    T qx2 = q * dx * dx, qy2 = q * dy * dy;
+    t.t111 = dx * ((T)3 * w + qx2); t.t112 = dy * (w + qx2);
+    t.t122 = dx * (w + qy2); t.t222 = dy * ((T)3 * w + qy2);
+  }
+}
+
+// Cored isothermal term b / (R + s) with R = sqrt(s^2 + r^2): returns m, w (and w').
+template <bool D3, class T>
+__device__ __forceinline__ void cored_mw(T b, T s, T s2, T r2, T& m, T& w, T& wp) {
+  T S2 = s2 + r2;
+  T is = frsq(S2);
+  T R = S2 * is;
+  T u = frcp(R + s);
+  T uu = u * u;
+  m = b * u;
+  T wt = uu * is;
+  w = -b * wt;
+  if (D3) wp = (T)0.5 * b * wt * fma((T)2 * u, R, (T)1) * is * is;
+}
+
+// Circular pseudo-Jaffe (dPIE): cored(s) - cored(a).  Also the circular SIE when a_inf.
+template <bool D3, class T>
+__device__ __forceinline__ void cpje(T dx, T dy, T b, T s, T a, T s2, T a2, Term<T>& t) {
+  T r2 = fma(dx, dx, dy * dy);
+  T m1, w1, p1 = 0, m2, w2, p2 = 0;
+  cored_mw<D3>(b, s, s2, r2, m1, w1, p1);
+  cored_mw<D3>(b, a, a2, r2, m2, w2, p2);
+  radial<D3>(dx, dy, m1 - m2, w1 - w2, p1 - p2, t);
+}
+template <bool D3, class T>
+__device__ __forceinline__ void csie(T dx, T dy, T b, T s, T s2, Term<T>& t) {
+  T r2 = fma(dx, dx, dy * dy);
+  T m, w, p = 0;
+  cored_mw<D3>(b, s, s2, r2, m, w, p);
+  radial<D3>(dx, dy, m, w, p, t);
+}
+template <bool D3, class T>
+__device__ __forceinline__ void point_mass(T dx, T dy, T b, Term<T>& t) {
+  T r2 = fma(dx, dx, dy * dy);
+  T ir2 = frcp(r2);
+  T b2 = b * b;
+  T m = b2 * ir2;
+  T w = (T)-2 * m * ir2;
+  T wp = (T)-2 * w * ir2;
+  radial<D3>(dx, dy, m, w, wp, t);
+}
+
+// ---------------------------------------------------------------------------------------
+// Elliptical cored isothermal (SIE) in its own frame (major axis on x'):
+//   psi~ = sqrt(q^2 (s^2 + x^2) + y^2),  alpha_x = (b q/e) atan(e x / (psi~ + s)),
+//   alpha_y = (b q/e) atanh(e y / (psi~ + q^2 s)),  e = sqrt(1 - q^2);
+//   psi_ij = b q N_ij / (psi~ D), D = (1+q^2) s^2 + 2 psi~ s + x^2 + y^2,
+//   N_xx = q^2 s^2 + y^2 + s psi~, N_yy = s^2 + x^2 + s psi~, N_xy = -x y;
+//   d_k psi_ij = b q / (psi~ D) (d_k N_ij - N_ij L_k), L_k = d_k psi~/psi~ + d_k D / D.
+// ---------------------------------------------------------------------------------------
+template <bool D3, class T>
+__device__ __forceinline__ void esie_prime(T xp, T yp, T bqe, T e, T q2, T s, Term<T>& t) {
+  T xx = xp * xp, yy = yp * yp, ss = s * s;
+  T psi = fsqrt(fma(q2, ss + xx, yy));
+  T ip = frcp(psi);
+  t.ax = bqe * fatan(e * xp * frcp(psi + s));
+  t.ay = bqe * fatanh(e * yp * frcp(fma(q2, s, psi)));
+  T D = fma((T)1 + q2, ss, fma((T)2 * psi, s, xx + yy));
+  T iD = frcp(D);
+  T Tn = bqe * e * ip * iD;
+  T sp = s * psi;
+  T Nxx = fma(q2, ss, yy + sp), Nyy = ss + xx + sp, Nxy = -xp * yp;
+  t.h11 = Tn * Nxx; t.h22 = Tn * Nyy; t.h12 = Tn * Nxy;
+  if (D3) {
+    T dpx = q2 * xp * ip, dpy = yp * ip;
+    T Lx = fma(dpx, ip, (T)2 * fma(s, dpx, xp) * iD);
+    T Ly = fma(dpy, ip, (T)2 * fma(s, dpy, yp) * iD);
+    t.t111 = Tn * (s * dpx - Nxx * Lx);
+    t.t112 = Tn * ((T)2 * yp + s * dpy - Nxx * Ly);
+    t.t122 = Tn * ((T)2 * xp + s * dpx - Nyy * Lx);
+    t.t222 = Tn * (s * dpy - Nyy * Ly);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T t3eval(const Term<T>& t, T u0, T u1, T v0, T v1, T w0, T w1) {
+  return t.t111 * u0 * v0 * w0 + t.t112 * (u0 * v0 * w1 + u0 * v1 * w0 + u1 * v0 * w0) +
+         t.t122 * (u0 * v1 * w1 + u1 * v0 * w1 + u1 * v1 * w0) + t.t222 * u1 * v1 * w1;
+}
+
+// Rotate a primed-frame term back to the sky frame (x' = c dx + s dy, y' = -s dx + c dy).
+template <bool D3, class T>
+__device__ __forceinline__ void rotate_back(T c, T s, const Term<T>& p, Term<T>& t) {
+  t.ax = c * p.ax - s * p.ay;
+  t.ay = s * p.ax + c * p.ay;
+  T cc = c * c, ss = s * s, cs = c * s;
+  t.h11 = cc * p.h11 - (T)2 * cs * p.h12 + ss * p.h22;
+  t.h22 = ss * p.h11 + (T)2 * cs * p.h12 + cc * p.h22;
+  t.h12 = cs * (p.h11 - p.h22) + (cc - ss) * p.h12;
+  if (D3) {
+    // unit vectors e_x -> (c, -s), e_y -> (s, c) in the primed frame
+    t.t111 = t3eval(p, c, -s, c, -s, c, -s);
+    t.t112 = t3eval(p, c, -s, c, -s, s, c);
+    t.t122 = t3eval(p, c, -s, s, c, s, c);
+    t.t222 = t3eval(p, s, c, s, c, s, c);
+  }
+}
+
+template <bool D3, class T>
+__device__ __forceinline__ void sub_term(Term<T>& a, const Term<T>& b) {
+  a.ax -= b.ax; a.ay -= b.ay; a.h11 -= b.h11; a.h12 -= b.h12; a.h22 -= b.h22;
+  if (D3) { a.t111 -= b.t111; a.t112 -= b.t112; a.t122 -= b.t122; a.t222 -= b.t222; }
+}
+
+template <bool D3, class T>
+__device__ __forceinline__ void epje(T dx, T dy, T c, T sn, T bqe, T e, T q2, T s, T a, bool pje, Term<T>& t) {
+  T xp = c * dx + sn * dy, yp = c * dy - sn * dx;
+  Term<T> p, p2;
+  esie_prime<D3>(xp, yp, bqe, e, q2, s, p);
+  if (pje) { esie_prime<D3>(xp, yp, bqe, e, q2, a, p2); sub_term<D3>(p, p2); }
+  rotate_back<D3>(c, sn, p, t);
+}
+
+// ---------------------------------------------------------------------------------------
+// NFW.  With X^2 = xi^2 / r_s^2 and z = 1 - X^2:  F = arccosh(1/X)/sqrt(1-X^2) (X < 1),
+// arccos(1/X)/sqrt(X^2-1) (X > 1); kappa = 2 k_s G(z), G = (F - 1)/z (series near z = 0).
+// Returns G and dG/dz.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& Gp) {
+  double z = 1.0 - X2;
+  if (fabs(z) < 0.1) {
+    // F = sum z^k/(2k+1); G = sum_{k>=1} z^(k-1)/(2k+1); G' = sum_{k>=2} (k-1) z^(k-2)/(2k+1)
+    double g = 0.0, gp = 0.0;
+#pragma unroll
+    for (int k = 18; k >= 2; --k) { g = fma(g, z, 1.0 / (2 * k + 1)); gp = fma(gp, z, (double)(k - 1) / (2 * k + 1)); }
+    G = fma(g, z, 1.0 / 3.0);
+    Gp = gp;
+    F = fma(G, z, 1.0);
+  } else {
+    if (z > 0) { double w = sqrt(z); F = (log1p(w) - 0.5 * log(X2)) / w; }
+    else { double w = sqrt(-z); F = atan(w) / w; }
+    double iz = 1.0 / z;
+    G = (F - 1.0) * iz;
+    double Fp = 0.5 * (1.0 / X2 - F) * iz;
+    Gp = (Fp - G) * iz;
+  }
+}
+
+template <bool D3>
+__device__ __forceinline__ void nfw_circ(double dx, double dy, double ks, double rs, Term<double>& t) {
+  double r2 = fma(dx, dx, dy * dy);
+  double irs2 = 1.0 / (rs * rs);
+  double X2 = r2 * irs2;
+  double F, G, Gp;
+  nfw_G(X2, F, G, Gp);
+  double ir2 = 1.0 / r2;
+  double h = 0.5 * log(0.25 * X2) + F;
+  double m = 4.0 * ks * rs * rs * h * ir2;
+  double kap = 2.0 * ks * G;
+  double w = 2.0 * (kap - m) * ir2;
+  double wp = 0.0;
+  if (D3) { double kp = -2.0 * ks * Gp * irs2; wp = 2.0 * (kp - w) * ir2; }
+  radial<D3>(dx, dy, m, w, wp, t);
+}
+
+// Elliptical NFW in its own frame from the integrals
+//   J_n = int_0^1 kappa(xi^2(u)) (1 - e^2 u)^-(n+1/2) du,  K_n = int_0^1 u kappa'(xi^2(u)) (...)^-(n+1/2) du
+// with xi^2(u) = u (x^2 + y^2/(1 - e^2 u)):  alpha = q (x J0, y J1),
+// psi_xx = 2 q x^2 K0 + q J0, psi_yy = 2 q y^2 K2 + q J1, psi_xy = 2 q x y K1.
+// Fixed Gauss-Legendre nodes in t with u = t^6 (u_node, w_node carry the Jacobian).
+struct Quad {
+  int n;
+  const double* u;
+  const double* w;
+};
+__device__ __forceinline__ void enfw_prime(double xp, double yp, double ks, double rs, double q,
+                                           const Quad& qd, Term<double>& t) {
+  double e2 = 1.0 - q * q;
+  double xx = xp * xp, yy = yp * yp;
+  double irs2 = 1.0 / (rs * rs);
+  double J0 = 0, J1 = 0, K0 = 0, K1 = 0, K2 = 0;
+  for (int i = 0; i < qd.n; ++i) {
+    double u = qd.u[i], wq = qd.w[i];
+    double W = fma(-e2, u, 1.0);
+    double iW = 1.0 / W;
+    double X2 = u * fma(yy, iW, xx) * irs2;
+    double F, G, Gp;
+    nfw_G(X2, F, G, Gp);
+    double kap = 2.0 * ks * G;
+    double ukp = -2.0 * ks * Gp * irs2 * u;
+    double f0 = wq * (1.0 / sqrt(W));
+    double f1 = f0 * iW, f2 = f1 * iW;
+    J0 = fma(f0, kap, J0); J1 = fma(f1, kap, J1);
+    K0 = fma(f0, ukp, K0); K1 = fma(f1, ukp, K1); K2 = fma(f2, ukp, K2);
+  }
+  t.ax = q * xp * J0; t.ay = q * yp * J1;
+  t.h11 = 2.0 * q * xx * K0 + q * J0;
+  t.h22 = 2.0 * q * yy * K2 + q * J1;
+  t.h12 = 2.0 * q * xp * yp * K1;
+  t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
+}
+
+// ---------------------------------------------------------------------------------------
+// One main component (FP64) at one point.
+// ---------------------------------------------------------------------------------------
+template <bool D3>
+__device__ __forceinline__ void eval_main(const MainRec& r, double px, double py, const Quad& qd, Acc& acc) {
+  double dx = px - r.x, dy = py - r.y;
+  double r2 = fma(dx, dx, dy * dy);
+  Term<double> t;
+  t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
+  bool singular = (r.type == T_POINT || r.type == T_SIS || r.type == T_NFW || r.type == T_ENFW ||
+                   r.s == 0.0);
+  if (singular && r2 < 1e-24) { acc.flags |= FL_SINGULAR; return; }
+  switch (r.type) {
+    case T_POINT: point_mass<D3>(dx, dy, r.b, t); break;
+    case T_SIS: csie<D3>(dx, dy, r.b, 0.0, 0.0, t); break;
+    case T_SIE:
+      if (r.q >= 1.0) csie<D3>(dx, dy, r.b, r.s, r.s * r.s, t);
+      else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, false, t);
+      break;
+    case T_PJE:
+      if (r.q >= 1.0) cpje<D3>(dx, dy, r.b, r.s, r.a, r.s * r.s, r.a * r.a, t);
+      else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t);
+      break;
+    case T_NFW: nfw_circ<D3>(dx, dy, r.b, r.s, t); break;
+    default:
+      if (r.q >= 1.0) nfw_circ<D3>(dx, dy, r.b, r.s, t);
+      else {
+        double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
+        Term<double> p;
+        enfw_prime(xp, yp, r.b, r.s, r.q, qd, p);
+        rotate_back<false>(r.c, r.sn, p, t);
+      }
+      break;
+  }
+  add<D3>(acc, t);
+}
+
+// FP64 epilogue of a single-plane point (Sec. 2.1): kappa, gamma, det A, mu, beta,
+// eigenvalues and the A3-line fields f_k = v_k . grad e_k (Sec. 6).
+struct Epi {
+  double kappa, g1, g2, detA, mu, bx, by, e1, e2, f1, f2;
+  int flags;
+};
+template <bool D3>
+__device__ __forceinline__ void epilogue(double x, double y, double a, const Acc& h, Epi& o) {
+  o.kappa = 0.5 * (h.h11 + h.h22);
+  o.g1 = 0.5 * (h.h11 - h.h22);
+  o.g2 = h.h12;
+  double A11 = fma(-a, h.h11, 1.0), A22 = fma(-a, h.h22, 1.0), A12 = -a * h.h12;
+  o.detA = A11 * A22 - A12 * A12;
+  o.mu = 1.0 / o.detA;
+  o.bx = fma(-a, h.ax, x);
+  o.by = fma(-a, h.ay, y);
+  double gm = sqrt(o.g1 * o.g1 + o.g2 * o.g2);
+  o.e1 = o.kappa + gm;
+  o.e2 = o.kappa - gm;
+  o.flags = h.flags;
+  o.f1 = o.f2 = 0.0;
+  if (D3) {
+    if (!(gm > 1e-12 * fabs(o.kappa)) || gm == 0.0) {
+      o.flags |= FL_UMBILIC;
+    } else {
+      double gkx = 0.5 * (h.t111 + h.t122), gky = 0.5 * (h.t112 + h.t222);
+      double g1x = 0.5 * (h.t111 - h.t122), g1y = 0.5 * (h.t112 - h.t222);
+      double g2x = h.t112, g2y = h.t122;
+      double igm = 1.0 / gm;
+      double ggx = (o.g1 * g1x + o.g2 * g2x) * igm, ggy = (o.g1 * g1y + o.g2 * g2y) * igm;
+      // eigenvector of e1: the larger of (g1 + |g|, g2) and (g2, |g| - g1), x-component >= 0
+      double vax = o.g1 + gm, vay = o.g2, vbx = o.g2, vby = gm - o.g1;
+      double na = vax * vax + vay * vay, nb = vbx * vbx + vby * vby;
+      double vx, vy;
+      if (na >= nb) { double n = 1.0 / sqrt(na); vx = vax * n; vy = vay * n; }
+      else { double n = 1.0 / sqrt(nb); vx = vbx * n; vy = vby * n; }
+      if (vx < 0 || (vx == 0 && vy < 0)) { vx = -vx; vy = -vy; }
+      double wx = -vy, wy = vx;
+      if (wx < 0 || (wx == 0 && wy < 0)) { wx = -wx; wy = -wy; }
+      o.f1 = vx * (gkx + ggx) + vy * (gky + ggy);
+      o.f2 = wx * (gkx - ggx) + wy * (gky - ggy);
+    }
+  }
+}
+
+}  // namespace lf

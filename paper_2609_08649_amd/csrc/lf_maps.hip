@@ -1,0 +1,339 @@
+// Halo-table expansion (step a1) and the halo-sum maps kernel (steps a2, a3, a7).
+//
+// Layout: one lane owns PPL points (strided by the block size so stores coalesce);
+// halo records are wave-uniform, so the compiler fetches them through the scalar
+// data cache into SGPRs (s_load) and every VALU instruction of the profile maths
+// reads them as scalar operands: no LDS staging and no VGPRs spent on halo data.
+// Member galaxies are sorted by profile segment; each segment is one branch-free loop.
+#include <hip/hip_runtime.h>
+
+#include "lf_device.h"
+#include "lf_launch.h"
+
+namespace lf {
+
+static constexpr double C_KMS = 299792.458;
+static constexpr double ARCSEC = 206264.80624709636;
+static constexpr double PI_D = 3.14159265358979323846;
+
+__device__ double xf_apply(int xf, double raw, const XfConst& k) {
+  switch (xf) {
+    case 1: { double r = raw / C_KMS; return 4.0 * PI_D * r * r * ARCSEC; }    // sigma -> b
+    case 2: return raw * k.arcsec_per_kpc;                                      // kpc -> arcsec
+    case 3: return (1.0 - raw) / (1.0 + raw);                                   // eps -> q
+    case 4: return raw * (PI_D / 180.0);                                        // deg -> rad
+    default: return raw;
+  }
+}
+
+__device__ double bound_raw(const Bind& b, const double* row, int n_free, int* bad) {
+  if (b.kind == 0) return b.value;
+  if (b.index < 0 || b.index >= n_free) { *bad = 1; return 0.0; }
+  return row[b.index];
+}
+
+__global__ void k_expand(const DevModel m, const double* __restrict__ params, int S,
+                         MainRec* __restrict__ mains, MulRec* __restrict__ muls,
+                         MemRec32* __restrict__ m32, MemRec64* __restrict__ m64) {
+  const int s = blockIdx.y;
+  const double* row = params ? params + (size_t)s * m.n_free : nullptr;
+  // thread t < n_main: main component t; thread == n_main: multipliers; rest: members
+  const int per_sample = m.n_main + 1 + ((m32 || m64) ? m.n_mem : 0);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < per_sample; t += gridDim.x * blockDim.x) {
+    if (t < m.n_main) {
+      const MainDesc& d = m.main[t];
+      int bad = 0;
+      double f[7];
+      int xfs[7];
+      for (int k = 0; k < 7; ++k) {
+        double raw = bound_raw(d.f[k], row, m.n_free, &bad);
+        xfs[k] = d.f[k].xf;
+        f[k] = (xfs[k] == 5 || xfs[k] == 6) ? raw : xf_apply(xfs[k], raw, m.xc);
+      }
+      if (xfs[2] == 5 && xfs[5] == 6) {     // (M200, c200) -> (kappa_s, r_s)
+        double m200 = f[2], c = f[5];
+        double r200 = cbrt(3.0 * m200 / (4.0 * PI_D * 200.0 * m.xc.rho_c));
+        double rs = r200 / c;
+        double dc = (200.0 / 3.0) * c * c * c / (log1p(c) - c / (1.0 + c));
+        f[2] = dc * m.xc.rho_c * rs / m.xc.sigma_cr;
+        f[5] = rs / m.xc.Dd * ARCSEC;
+      }
+      MainRec r;
+      r.type = d.type;
+      r.x = f[0]; r.y = f[1]; r.b = f[2]; r.q = f[3]; r.s = f[5]; r.a = f[6];
+      double sn, c;
+      sincos(f[4], &sn, &c);
+      r.c = c; r.sn = sn;
+      r.q2 = r.q * r.q;
+      r.e = sqrt(fmax(0.0, 1.0 - r.q2));
+      r.bqe = r.e > 0 ? r.b * r.q / r.e : 0.0;
+      r.pad = 0.0;
+      bool ok = !bad;
+      for (int k = 0; k < 7; ++k) ok = ok && isfinite(f[k]);
+      ok = ok && r.q > 0.0 && r.q <= 1.0 && r.b >= 0.0 && r.s >= 0.0;
+      if (d.type == T_PJE) ok = ok && r.a > r.s;
+      if (d.type == T_NFW || d.type == T_ENFW) ok = ok && r.s > 0.0;
+      r.flags = ok ? 0 : FL_INVALID;
+      r.pad0 = r.pad1 = 0;
+      mains[(size_t)s * m.n_main + t] = r;
+    } else if (t == m.n_main) {
+      int bad = 0;
+      MulRec u;
+      u.b = xf_apply(m.mul[0].xf, bound_raw(m.mul[0], row, m.n_free, &bad), m.xc);
+      u.s = xf_apply(m.mul[1].xf, bound_raw(m.mul[1], row, m.n_free, &bad), m.xc);
+      u.a = xf_apply(m.mul[2].xf, bound_raw(m.mul[2], row, m.n_free, &bad), m.xc);
+      bool ok = !bad && isfinite(u.b) && isfinite(u.s) && isfinite(u.a) && u.b >= 0 && u.s >= 0 && u.a >= 0;
+      u.flags = ok ? 0 : FL_INVALID;
+      u.pad = 0;
+      muls[s] = u;
+    } else {
+      int i = t - m.n_main - 1;
+      // the multipliers are recomputed here (cheap) so that this thread has no dependence
+      int bad = 0;
+      double bm = xf_apply(m.mul[0].xf, bound_raw(m.mul[0], row, m.n_free, &bad), m.xc);
+      double sm = xf_apply(m.mul[1].xf, bound_raw(m.mul[1], row, m.n_free, &bad), m.xc);
+      double am = xf_apply(m.mul[2].xf, bound_raw(m.mul[2], row, m.n_free, &bad), m.xc);
+      const MemCat& c = m.mem[i];
+      double b = bm * c.fb, sc = sm * c.fs, a = am * c.fa;
+      double q2 = c.q * c.q, e = sqrt(fmax(0.0, 1.0 - q2));
+      double bqe = e > 0 ? b * c.q / e : 0.0;
+      if (m64) {
+        MemRec64 r;
+        r.x = c.x; r.y = c.y; r.b = b; r.s = sc; r.a = a; r.s2 = sc * sc; r.a2 = a * a;
+        r.c = c.c; r.sn = c.sn; r.q2 = q2; r.e = e; r.bqe = bqe;
+        m64[(size_t)s * m.n_mem + i] = r;
+      }
+      if (m32) {
+        MemRec32 r;
+        r.x = c.x; r.y = c.y;
+        r.b = (float)b; r.s = (float)sc; r.a = (float)a;
+        r.s2 = (float)(sc * sc); r.a2 = (float)(a * a);
+        r.c = (float)c.c; r.sn = (float)c.sn; r.q2 = (float)q2; r.e = (float)e; r.bqe = (float)bqe;
+        r.pad0 = r.pad1 = 0.f;
+        m32[(size_t)s * m.n_mem + i] = r;
+      }
+    }
+  }
+}
+
+hipError_t launch_expand(const DevModel& m, const double* params, int S, MainRec* mains,
+                         MulRec* muls, MemRec32* m32, MemRec64* m64, hipStream_t st) {
+  int per = m.n_main + 1 + ((m32 || m64) ? m.n_mem : 0);
+  dim3 grid((per + 255) / 256, S);
+  hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, st, m, params, S, mains, muls, m32, m64);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Member segment loops over pre-scaled records (MemRec32: FP32 maths on an offset formed
+// in FP64; MemRec64: FP64 throughout).  One loop per profile segment.
+// ---------------------------------------------------------------------------------------
+template <int SEG, bool D3, int PPL, class R>
+__device__ __forceinline__ void seg_loop(const R* __restrict__ rec, int lo, int hi,
+                                         const double (&px)[PPL], const double (&py)[PPL],
+                                         Acc (&acc)[PPL], const Quad& qd) {
+  using T = decltype(R::b);
+  constexpr bool F32 = sizeof(T) == 4;
+  for (int h = lo; h < hi; ++h) {
+    const R r = rec[h];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      T dx = (T)(px[k] - r.x), dy = (T)(py[k] - r.y);
+      Term<T> t;
+      t.t111 = t.t112 = t.t122 = t.t222 = (T)0;
+      if constexpr (SEG == SEG_CPJE || SEG == SEG_CSIE) {
+        T r2 = fma(dx, dx, dy * dy);
+        if constexpr (F32) {
+          // FP32: a point within 1e-6" of a member centre is evaluated at r = 1e-6"
+          r2 = fmaxf(r2, 1e-12f);
+        } else {
+          if (r.s == 0.0 && r2 < 1e-24) { acc[k].flags |= FL_SINGULAR; continue; }
+        }
+        T m1, w1, p1 = 0;
+        cored_mw<D3>(r.b, r.s, r.s2, r2, m1, w1, p1);
+        if constexpr (SEG == SEG_CPJE) {
+          T m2, w2, p2 = 0;
+          cored_mw<D3>(r.b, r.a, r.a2, r2, m2, w2, p2);
+          m1 -= m2; w1 -= w2; p1 -= p2;
+        }
+        radial<D3>(dx, dy, m1, w1, p1, t);
+      } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
+        if (r.s == (T)0 && dx == (T)0 && dy == (T)0) { acc[k].flags |= FL_SINGULAR; continue; }
+        epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, SEG == SEG_EPJE, t);
+      } else if constexpr (SEG == SEG_POINT) {
+        if (dx == (T)0 && dy == (T)0) { acc[k].flags |= FL_SINGULAR; continue; }
+        point_mass<D3>(dx, dy, r.b, t);
+      } else if constexpr (SEG == SEG_NFW) {
+        if (dx == (T)0 && dy == (T)0) { acc[k].flags |= FL_SINGULAR; continue; }
+        nfw_circ<D3>((double)dx, (double)dy, (double)r.b, (double)r.s, *(Term<double>*)&t);
+      } else {
+        if (dx == (T)0 && dy == (T)0) { acc[k].flags |= FL_SINGULAR; continue; }
+        double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
+        Term<double> pr;
+        enfw_prime(xp, yp, r.b, r.s, sqrt(r.q2), qd, pr);
+        rotate_back<false>((double)r.c, (double)r.sn, pr, *(Term<double>*)&t);
+      }
+      add<D3>(acc[k], t);
+    }
+  }
+}
+
+struct MapsArgs {
+  DevModel m;
+  const MainRec* mains;
+  const MemRec32* m32;
+  const MemRec64* m64;
+  int S;
+  PointsSpec pts;
+  double a;
+  MapsOut out;
+  Quad qd;
+  double* part;        // partial sums of the heavy pass: [S][NPART][P] (null = none)
+};
+static constexpr int NPART = 9;
+
+__device__ __forceinline__ void point_of(const PointsSpec& ps, long long p, double& x, double& y) {
+  if (ps.grid) {
+    long long j = p / ps.nx, i = p - j * ps.nx;
+    x = ps.x0 + ((double)i + 0.5) * ps.h;
+    y = ps.y0 + ((double)j + 0.5) * ps.h;
+  } else {
+    x = ps.px[p];
+    y = ps.py[p];
+  }
+}
+
+// Heavy pass: main components (FP64) and the rare member segments (elliptical, point,
+// NFW) whose closed forms need many registers; writes partial sums per point.
+template <bool MIXED, bool D3>
+__global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
+  const int s = blockIdx.y;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long P = A.pts.P;
+  if (p >= P) return;
+  double px[1], py[1];
+  Acc acc[1];
+  point_of(A.pts, p, px[0], py[0]);
+  acc[0].zero();
+  const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
+  for (int c = 0; c < A.m.n_main; ++c) {
+    const MainRec r = mr[c];
+    eval_main<D3>(r, px[0], py[0], A.qd, acc[0]);
+    acc[0].flags |= r.flags;
+  }
+  const SegOff& so = A.m.seg;
+  const size_t mo = (size_t)s * A.m.n_mem;
+  if (MIXED) {
+    seg_loop<SEG_EPJE, D3, 1>(A.m32 + mo, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_ESIE, D3, 1>(A.m32 + mo, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_POINT, D3, 1>(A.m32 + mo, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
+  } else {
+    seg_loop<SEG_EPJE, D3, 1>(A.m64 + mo, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_ESIE, D3, 1>(A.m64 + mo, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_POINT, D3, 1>(A.m64 + mo, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
+  }
+  seg_loop<SEG_NFW, D3, 1>(A.m64 + mo, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, acc, A.qd);
+  seg_loop<SEG_ENFW, false, 1>(A.m64 + mo, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
+  double* q = A.part + (size_t)s * NPART * P + p;
+  q[0] = acc[0].ax; q[P] = acc[0].ay; q[2 * P] = acc[0].h11; q[3 * P] = acc[0].h12; q[4 * P] = acc[0].h22;
+  if (D3) { q[5 * P] = acc[0].t111; q[6 * P] = acc[0].t112; q[7 * P] = acc[0].t122; q[8 * P] = acc[0].t222; }
+  ((int*)(A.part + (size_t)A.S * NPART * P))[(size_t)s * P + p] = acc[0].flags;
+}
+
+// Lean pass: circular cored / dPIE members (the bulk of a cluster) + fused epilogue.
+template <bool MIXED, bool D3, int PPL>
+__global__ __launch_bounds__(256) void k_maps(const MapsArgs A) {
+  const int s = blockIdx.y;
+  const long long base = (long long)blockIdx.x * (256 * PPL) + threadIdx.x;
+  const long long P = A.pts.P;
+  double px[PPL], py[PPL];
+  Acc acc[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    long long p = base + (long long)k * 256;
+    if (p >= P) p = P - 1;            // duplicate the last point; its store is masked below
+    point_of(A.pts, p, px[k], py[k]);
+    acc[k].zero();
+    if (A.part) {
+      const double* q = A.part + (size_t)s * NPART * P + p;
+      acc[k].ax = q[0]; acc[k].ay = q[P]; acc[k].h11 = q[2 * P]; acc[k].h12 = q[3 * P]; acc[k].h22 = q[4 * P];
+      if (D3) { acc[k].t111 = q[5 * P]; acc[k].t112 = q[6 * P]; acc[k].t122 = q[7 * P]; acc[k].t222 = q[8 * P]; }
+      acc[k].flags = ((const int*)(A.part + (size_t)A.S * NPART * P))[(size_t)s * P + p];
+    }
+  }
+  const SegOff& so = A.m.seg;
+  const size_t mo = (size_t)s * A.m.n_mem;
+  if (MIXED) {
+    seg_loop<SEG_CPJE, D3, PPL>(A.m32 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_CSIE, D3, PPL>(A.m32 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
+  } else {
+    seg_loop<SEG_CPJE, D3, PPL>(A.m64 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_CSIE, D3, PPL>(A.m64 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
+  }
+  const MapsOut& o = A.out;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    long long p = base + (long long)k * 256;
+    if (p >= P) break;
+    size_t idx = (size_t)s * P + p;
+    Epi e;
+    epilogue<D3>(px[k], py[k], A.a, acc[k], e);
+    if (o.ax) o.ax[idx] = acc[k].ax;
+    if (o.ay) o.ay[idx] = acc[k].ay;
+    if (o.p11) o.p11[idx] = acc[k].h11;
+    if (o.p12) o.p12[idx] = acc[k].h12;
+    if (o.p22) o.p22[idx] = acc[k].h22;
+    if (o.kappa) o.kappa[idx] = e.kappa;
+    if (o.g1) o.g1[idx] = e.g1;
+    if (o.g2) o.g2[idx] = e.g2;
+    if (o.detA) o.detA[idx] = e.detA;
+    if (o.mu) o.mu[idx] = e.mu;
+    if (o.bx) o.bx[idx] = e.bx;
+    if (o.by) o.by[idx] = e.by;
+    if (o.e1) o.e1[idx] = e.e1;
+    if (o.e2) o.e2[idx] = e.e2;
+    if (D3) {
+      if (o.t111) o.t111[idx] = acc[k].t111;
+      if (o.t112) o.t112[idx] = acc[k].t112;
+      if (o.t122) o.t122[idx] = acc[k].t122;
+      if (o.t222) o.t222[idx] = acc[k].t222;
+      if (o.f1) o.f1[idx] = e.f1;
+      if (o.f2) o.f2[idx] = e.f2;
+    }
+    if (o.flags) o.flags[idx] = e.flags;
+  }
+}
+
+template <bool MIXED, bool D3, int PPL>
+static void launch_maps_t(const MapsArgs& a, hipStream_t st) {
+  if (a.part) {
+    dim3 g1((unsigned)((a.pts.P + 255) / 256), a.S);
+    hipLaunchKernelGGL((k_heavy<MIXED, D3>), g1, dim3(256), 0, st, a);
+  }
+  long long per_block = 256LL * PPL;
+  dim3 grid((unsigned)((a.pts.P + per_block - 1) / per_block), a.S);
+  hipLaunchKernelGGL((k_maps<MIXED, D3, PPL>), grid, dim3(256), 0, st, a);
+}
+
+hipError_t launch_maps(const DevModel& m, const MainRec* mains, const MemRec32* m32,
+                       const MemRec64* m64, int S, const PointsSpec& pts, double a_dis,
+                       bool mixed, bool d3, const MapsOut& out, const QuadTab& q, int ppl,
+                       double* part, hipStream_t st) {
+  MapsArgs a;
+  a.part = part;
+  a.m = m; a.mains = mains; a.m32 = m32; a.m64 = m64; a.S = S; a.pts = pts; a.a = a_dis;
+  a.out = out; a.qd.n = q.n; a.qd.u = q.u; a.qd.w = q.w;
+#define LF_DISPATCH(MX, D, P)                 \
+  if (mixed == MX && d3 == D && ppl == P) {   \
+    launch_maps_t<MX, D, P>(a, st);           \
+    return hipGetLastError();                 \
+  }
+  LF_DISPATCH(true, false, 1) LF_DISPATCH(true, false, 2) LF_DISPATCH(true, false, 4)
+  LF_DISPATCH(false, false, 1) LF_DISPATCH(false, false, 2)
+  LF_DISPATCH(true, true, 1) LF_DISPATCH(true, true, 2)
+  LF_DISPATCH(false, true, 1)
+#undef LF_DISPATCH
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lf

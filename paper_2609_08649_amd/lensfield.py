@@ -1,0 +1,297 @@
+"""Thin ctypes binding of the lensfield C ABI (include/lensfield.h).
+
+Functions named like the C entry points marshal arguments only; every step of the
+hot path runs in the HIP library.  PyTorch provides device memory and streams.
+The library is loaded after torch so that both use the same HIP runtime; if it
+cannot be loaded the import fails loudly (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+from . import build as _build
+
+LF_OK, LF_E_INVALID_ARG, LF_E_UNSUPPORTED, LF_E_OUT_OF_BUDGET, LF_E_DEVICE, LF_E_OVERFLOW, LF_E_NOT_READY = \
+    0, -1, -2, -3, -4, -5, -6
+LF_PREC_FP64, LF_PREC_MIXED = 0, 1
+FLAG_SINGULAR, FLAG_GSING, FLAG_NOCONV, FLAG_REJECT, FLAG_MERGED, FLAG_OVERFLOW, FLAG_UMBILIC, FLAG_INVALID = \
+    1, 2, 4, 8, 16, 32, 64, 128
+FIELDS = ("x", "y", "b", "q", "pa", "s", "a")
+
+
+class LfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("lensfield error %d: %s" % (status, msg))
+        self.status = status
+
+
+class lf_binding(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("index", C.c_int32), ("xform", C.c_int32), ("pad", C.c_int32),
+                ("value", C.c_double)]
+
+
+class lf_component(C.Structure):
+    _fields_ = [("type", C.c_int32), ("pad", C.c_int32), ("f", lf_binding * 7)]
+
+
+class lf_members(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32), ("type", C.POINTER(C.c_int32)),
+                ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)), ("q", C.POINTER(C.c_double)),
+                ("pa", C.POINTER(C.c_double)), ("lum", C.POINTER(C.c_double)), ("lam", C.c_double),
+                ("bet", C.c_double), ("alp", C.c_double), ("b0", C.POINTER(C.c_double)),
+                ("s0", C.POINTER(C.c_double)), ("a0", C.POINTER(C.c_double)), ("bmul", lf_binding),
+                ("smul", lf_binding), ("amul", lf_binding)]
+
+
+class lf_cosmo(C.Structure):
+    _fields_ = [("H0", C.c_double), ("Om", C.c_double)]
+
+
+class lf_grid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("h", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+class lf_points(C.Structure):
+    _fields_ = [("grid", lf_grid), ("px", C.c_void_p), ("py", C.c_void_p), ("n", C.c_int64)]
+
+
+MAP_FIELDS = ("alpha_x", "alpha_y", "psi11", "psi12", "psi22", "kappa", "gamma1", "gamma2", "detA", "mu",
+              "beta_x", "beta_y", "psi111", "psi112", "psi122", "psi222", "e1", "e2", "f1", "f2")
+
+
+class lf_maps(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in MAP_FIELDS] + [("flags", C.c_void_p)]
+
+
+_lib = None
+P, I32, I64, D, VP = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+PP = C.POINTER(C.c_void_p)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.ensure_built()
+        L = C.CDLL(path, mode=C.RTLD_GLOBAL)
+        sig = {
+            "lf_init": (I32, [PP, I32, C.c_size_t]),
+            "lf_shutdown": (I32, [P]),
+            "lf_last_error": (C.c_char_p, [P]),
+            "lf_device_bytes": (C.c_size_t, [P]),
+            "lf_cosmo_dist": (I32, [C.POINTER(lf_cosmo), D, D, C.POINTER(D)]),
+            "lf_cosmo_adis": (I32, [C.POINTER(lf_cosmo), D, D, C.POINTER(D)]),
+            "lf_nfw_params": (I32, [C.POINTER(lf_cosmo), D, D, D, C.POINTER(D), C.POINTER(D)]),
+            "lf_model_upload": (I32, [P, C.POINTER(lf_component), I32, C.POINTER(lf_members), D,
+                                      C.POINTER(lf_cosmo), I32, PP]),
+            "lf_model_release": (I32, [P, P]),
+            "lf_model_n_halos": (I32, [P]),
+            "lf_constraints_upload": (I32, [P, P, P, P, P, P, I32, P, I32, PP]),
+            "lf_constraints_release": (I32, [P, P]),
+            "lf_lens_maps": (I32, [P, P, P, I32, C.POINTER(lf_points), D, I32, C.POINTER(lf_maps), P]),
+            "lf_chi2_batch": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
+            "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
+            "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
+                                          P, P, P, P]),
+            "lf_find_images_mp": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, P, I32, C.POINTER(lf_grid), I32,
+                                        I32, P, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names of the functions declared in include/lensfield.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lensfield.h")
+    txt = open(hdr).read()
+    decl = re.compile(r"^(?:lf_status|const char\*|size_t|int32_t|void)\s+(lf_[a-z0-9_]+)\s*\(", re.M)
+    return sorted(set(decl.findall(txt)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _bind(b):
+    kind, v, xf = b
+    if kind == "fixed":
+        return lf_binding(0, 0, int(xf), 0, float(v))
+    return lf_binding(1, int(v), int(xf), 0, 0.0)
+
+
+def _f64p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Model:
+    def __init__(self, ctx, handle, model, keep):
+        self.ctx, self.handle, self.desc, self._keep = ctx, handle, model, keep
+        self.n_free = int(model.get("n_free", 0))
+
+    @property
+    def n_halos(self):
+        return lib().lf_model_n_halos(self.handle)
+
+    def release(self):
+        if self.handle:
+            lib().lf_model_release(self.ctx.handle, self.handle)
+            self.handle = None
+
+
+class Constraints:
+    def __init__(self, ctx, handle, n_img, n_fam):
+        self.ctx, self.handle, self.n_img, self.n_fam = ctx, handle, n_img, n_fam
+
+    def release(self):
+        if self.handle:
+            lib().lf_constraints_release(self.ctx.handle, self.handle)
+            self.handle = None
+
+
+class Context:
+    """An lf_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        L = lib()
+        h = C.c_void_p()
+        st = L.lf_init(C.byref(h), int(device), C.c_size_t(hbm_budget))
+        if st != LF_OK:
+            raise LfError(st, "lf_init failed")
+        self.handle = h
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if self.handle:
+            lib().lf_shutdown(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st):
+        if st != LF_OK:
+            raise LfError(st, lib().lf_last_error(self.handle).decode())
+
+    @property
+    def device_bytes(self):
+        return lib().lf_device_bytes(self.handle)
+
+    # ---------------------------------------------------------------- helpers
+    @staticmethod
+    def cosmo(H0=70.0, Om=0.3):
+        return lf_cosmo(H0, Om)
+
+    def dist(self, z1, z2, H0=70.0, Om=0.3):
+        out = C.c_double()
+        c = lf_cosmo(H0, Om)
+        self.check(lib().lf_cosmo_dist(C.byref(c), z1, z2, C.byref(out)))
+        return out.value
+
+    def adis(self, zd, zs, H0=70.0, Om=0.3):
+        out = C.c_double()
+        c = lf_cosmo(H0, Om)
+        self.check(lib().lf_cosmo_adis(C.byref(c), zd, zs, C.byref(out)))
+        return out.value
+
+    def nfw_params(self, zd, m200, c200, H0=70.0, Om=0.3):
+        ks, rs = C.c_double(), C.c_double()
+        c = lf_cosmo(H0, Om)
+        self.check(lib().lf_nfw_params(C.byref(c), zd, m200, c200, C.byref(ks), C.byref(rs)))
+        return ks.value, rs.value
+
+    # ---------------------------------------------------------------- models
+    def upload_model(self, model) -> Model:
+        main = model["main"]
+        comps = (lf_component * max(1, len(main)))()
+        for i, c in enumerate(main):
+            comps[i].type = int(c["type"])
+            for k, f in enumerate(FIELDS):
+                comps[i].f[k] = _bind(c[f])
+        mem = model["members"]
+        n = len(mem["x"])
+        keep = []
+
+        def arr(a, dt=np.float64):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a
+
+        ms = lf_members()
+        ms.n = n
+        t = arr(mem["type"], np.int32)
+        ms.type = t.ctypes.data_as(C.POINTER(C.c_int32))
+        for k in ("x", "y", "q", "pa", "lum", "b0", "s0", "a0"):
+            a = arr(mem.get(k))
+            setattr(ms, k, _f64p(a) if a is not None else None)
+        ex = mem.get("exps", (0.0, 0.0, 0.0))
+        ms.lam, ms.bet, ms.alp = float(ex[0]), float(ex[1]), float(ex[2])
+        ms.bmul, ms.smul, ms.amul = _bind(mem["bmul"]), _bind(mem["smul"]), _bind(mem["amul"])
+        cos = lf_cosmo(model["H0"], model["Om"])
+        h = C.c_void_p()
+        self.check(lib().lf_model_upload(self.handle, comps, len(main), C.byref(ms), float(model["z_d"]),
+                                         C.byref(cos), int(model.get("n_free", 0)), C.byref(h)))
+        return Model(self, h, model, keep)
+
+    def upload_constraints(self, cons) -> Constraints:
+        th = np.ascontiguousarray(cons["theta"], np.float64).reshape(-1, 2)
+        fam = np.ascontiguousarray(cons["family"], np.int32)
+        s1 = np.ascontiguousarray(cons["sig1"], np.float64)
+        s2 = np.ascontiguousarray(cons["sig2"], np.float64)
+        ph = np.ascontiguousarray(cons["phi"], np.float64)
+        af = np.ascontiguousarray(cons["a_fam"], np.float64)
+        h = C.c_void_p()
+        self.check(lib().lf_constraints_upload(self.handle, th.ctypes.data, fam.ctypes.data, s1.ctypes.data,
+                                               s2.ctypes.data, ph.ctypes.data, fam.size, af.ctypes.data, af.size,
+                                               C.byref(h)))
+        return Constraints(self, h, fam.size, af.size)
+
+    # ---------------------------------------------------------------- hot path
+    def lens_maps(self, model: Model, params, S, points, a_dis, prec=LF_PREC_FP64,
+                  outputs=("alpha_x", "alpha_y", "psi11", "psi12", "psi22", "kappa", "gamma1", "gamma2",
+                           "detA", "mu", "beta_x", "beta_y"), flags=True, stream=None, out=None):
+        """points: grid dict (x0, y0, h, nx, ny) or (px, py) device tensors."""
+        pts = lf_points()
+        keep = []
+        if isinstance(points, dict):
+            pts.grid = lf_grid(points["x0"], points["y0"], points["h"], points["nx"], points["ny"])
+            pts.px = pts.py = None
+            P = points["nx"] * points["ny"]
+        else:
+            px, py = points
+            keep += [px, py]
+            pts.px, pts.py, pts.n = px.data_ptr(), py.data_ptr(), px.numel()
+            P = px.numel()
+        res = {} if out is None else dict(out)
+        m = lf_maps()
+        for k in outputs:
+            if k not in res:
+                res[k] = torch.empty((S, P), dtype=torch.float64, device=self.device)
+            setattr(m, k, res[k].data_ptr())
+        if flags:
+            if "flags" not in res:
+                res["flags"] = torch.empty((S, P), dtype=torch.int32, device=self.device)
+            m.flags = res["flags"].data_ptr()
+        pp = None
+        if params is not None:
+            pp = C.c_void_p(params.data_ptr())
+        self.check(lib().lf_lens_maps(self.handle, model.handle, pp, int(S), C.byref(pts), float(a_dis), int(prec),
+                                      C.byref(m), _stream(stream)))
+        return res

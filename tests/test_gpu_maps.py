@@ -1,0 +1,181 @@
+"""GPU parity of lf_lens_maps (steps a1-a3, a7) against the FP64 oracle.
+
+Bar: FP64 path within ~1e-10 relative (bug detector); MIXED path |d alpha| <= 1e-5",
+relative mu error <= 1e-4 where |mu| < 100 (tolerances of the hot-path specification).
+"""
+import numpy as np
+import pytest
+
+from paper_2609_08649_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OR2GPU = {"ax": "alpha_x", "ay": "alpha_y", "p11": "psi11", "p12": "psi12", "p22": "psi22", "kappa": "kappa",
+          "gamma1": "gamma1", "gamma2": "gamma2", "detA": "detA", "mu": "mu", "beta_x": "beta_x",
+          "beta_y": "beta_y", "e1": "e1", "e2": "e2", "p111": "psi111", "p112": "psi112", "p122": "psi122",
+          "p222": "psi222", "f1": "f1", "f2": "f2"}
+BASE = ("alpha_x", "alpha_y", "psi11", "psi12", "psi22", "kappa", "gamma1", "gamma2", "detA", "mu", "beta_x",
+        "beta_y", "e1", "e2")
+D3 = ("psi111", "psi112", "psi122", "psi222", "f1", "f2")
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2609_08649_amd import lensfield
+    return lensfield
+
+
+@pytest.fixture(scope="module")
+def ctx(lf):
+    c = lf.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def check(gpu, orc_out, prec, d3=False, sl=slice(None)):
+    """Compare GPU planes (numpy) with oracle columns at tolerances of the precision."""
+    ax, ay = gpu["alpha_x"][sl], gpu["alpha_y"][sl]
+    dal = np.hypot(ax - orc_out["ax"], ay - orc_out["ay"])
+    amag = np.hypot(orc_out["ax"], orc_out["ay"])
+    mu_o = orc_out["mu"]
+    mask = np.abs(mu_o) < 100
+    rel_mu = np.abs(gpu["mu"][sl][mask] - mu_o[mask]) / np.abs(mu_o[mask])
+    if prec == "fp64":
+        assert np.max(dal / (1 + amag)) < 1e-10, np.max(dal)
+        for k in ("p11", "p12", "p22", "kappa", "gamma1", "gamma2", "e1", "e2"):
+            g, o = gpu[OR2GPU[k]][sl], orc_out[k]
+            assert np.max(np.abs(g - o) / (1 + np.abs(o))) < 1e-9, k
+        assert np.max(rel_mu) < 1e-8
+        assert np.max(np.abs(gpu["beta_x"][sl] - orc_out["beta_x"])) < 1e-9
+        if d3:
+            for k in ("p111", "p112", "p122", "p222"):
+                g, o = gpu[OR2GPU[k]][sl], orc_out[k]
+                assert np.max(np.abs(g - o) / (1 + np.abs(o))) < 1e-7, k
+            for k in ("f1", "f2"):
+                g, o = gpu[k][sl], orc_out[k]
+                assert np.max(np.abs(np.abs(g) - np.abs(o)) / (1 + np.abs(o))) < 1e-6, k
+    else:
+        assert np.max(dal) <= 1e-5, np.max(dal)
+        assert np.max(rel_mu) <= 1e-4, np.max(rel_mu)
+        for k in ("p11", "p12", "p22", "kappa", "gamma1", "gamma2"):
+            g, o = gpu[OR2GPU[k]][sl], orc_out[k]
+            assert np.max(np.abs(g - o) / (1 + np.abs(o))) < 1e-5, k
+        if d3:
+            for k in ("p111", "p112", "p122", "p222"):
+                g, o = gpu[OR2GPU[k]][sl], orc_out[k]
+                assert np.max(np.abs(g - o) / (1 + np.abs(o))) < 1e-4, k
+
+
+def _run(ctx, lf, model, params, S, pts, a, prec, outputs=BASE):
+    m = ctx.upload_model(model)
+    pp = _dev(params) if params is not None and model.get("n_free", 0) > 0 else None
+    if not isinstance(pts, dict):
+        pts = (_dev(pts[0]), _dev(pts[1]))
+    res = ctx.lens_maps(m, pp, S, pts, a, lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED,
+                        outputs=outputs)
+    import torch
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in res.items()}
+    m.release()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed,types,ell", [(31, None, False), (32, [2, 3], True), (33, [5, 4, 0, 1], False)])
+def test_maps_mixed_profiles_explicit_points(ctx, lf, orc, prec, seed, types, ell):
+    model, _ = W.tiny_model(seed, n_main=6 if types is None else len(types), n_mem=37,
+                            elliptical_members=ell, types=types)
+    x, y = W.random_points(seed, 3001, 25.0)           # several tiles and a ragged tail
+    g = _run(ctx, lf, model, None, 1, (x, y), 0.63, prec)
+    o = orc.maps(orc.expand(model), x, y, 0.63)
+    check({k: v[0] for k, v in g.items()}, o, prec)
+    assert np.array_equal(g["flags"][0] & 1, o["flags"] & 1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_maps_third_derivatives_and_singularity_fields(ctx, lf, orc, prec):
+    model, _ = W.tiny_model(34, n_main=2, n_mem=23, types=[2, 3], elliptical_members=True)
+    model["main"].append(W._comp(W.SIS, x=W.fixed(3.0), y=W.fixed(-4.0), b=W.fixed(1.5)))
+    model["main"].append(W._comp(W.POINT, x=W.fixed(-6.0), y=W.fixed(2.0), b=W.fixed(0.7)))
+    model["main"].append(W._comp(W.NFW, x=W.fixed(1.0), y=W.fixed(1.0), b=W.fixed(0.2), s=W.fixed(12.0)))
+    x, y = W.random_points(7, 1500, 20.0)
+    g = _run(ctx, lf, model, None, 1, (x, y), 0.45, prec, outputs=BASE + D3)
+    o = orc.maps(orc.expand(model), x, y, 0.45)
+    check({k: v[0] for k, v in g.items()}, o, prec, d3=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_maps_many_samples_with_free_parameters(ctx, lf, orc, prec):
+    model, truth = W.tiny_model(35, n_main=2, n_mem=29, types=[3, 2], free_params=True)
+    rng = np.random.default_rng(1)
+    S = 5
+    params = np.repeat(truth[None], S, 0) * (1 + 0.01 * rng.normal(size=(S, truth.size)))
+    x, y = W.random_points(8, 700, 15.0)
+    g = _run(ctx, lf, model, params, S, (x, y), 0.7, prec)
+    for s in range(S):
+        o = orc.maps(orc.expand(model, params[s]), x, y, 0.7)
+        check({k: v[s] for k, v in g.items()}, o, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_maps_config1_grid(ctx, lf, orc, prec):
+    cfg = W.config1()
+    g = _run(ctx, lf, cfg["model"], None, 1, cfg["grid"], 0.6354, prec)
+    x, y = W.grid_points(cfg["grid"])
+    o = orc.maps(orc.expand(cfg["model"]), x, y, 0.6354)
+    check({k: v[0] for k, v in g.items()}, o, prec)
+
+
+def test_maps_config2_full_grid_sampled(ctx, lf, orc):
+    """Full 2048^2 cluster map in the benchmark's launch configuration; sampled outputs."""
+    cfg = W.config2(n_samples=1)
+    g = _run(ctx, lf, cfg["model"], cfg["params"][:1], 1, cfg["grid"], 0.7, "mixed")
+    x, y = W.grid_points(cfg["grid"])
+    rng = np.random.default_rng(4)
+    idx = np.concatenate([rng.choice(x.size, 3000, replace=False), [0, x.size - 1]])
+    o = orc.maps(orc.expand(cfg["model"], cfg["params"][0]), x[idx], y[idx], 0.7)
+    check({k: v[0] for k, v in g.items()}, o, "mixed", sl=idx)
+
+
+def test_maps_edge_cases(ctx, lf, orc):
+    model, _ = W.tiny_model(36, n_main=1, n_mem=3, types=[1])
+    tab = orc.expand(model)
+    # a point exactly on the SIS centre is flagged and its term is zero; a single point works
+    x = np.array([tab[0, 1]])
+    y = np.array([tab[0, 2]])
+    g = _run(ctx, lf, model, None, 1, (x, y), 0.5, "fp64")
+    o = orc.maps(tab, x, y, 0.5)
+    assert g["flags"][0, 0] & lf.FLAG_SINGULAR and o["flags"][0] & 1
+    assert abs(g["alpha_x"][0, 0] - o["ax"][0]) < 1e-12
+    # a model with members only and one with main components only
+    m2, _ = W.tiny_model(37, n_main=0, n_mem=12)
+    xx, yy = W.random_points(9, 257, 10.0)
+    check({k: v[0] for k, v in _run(ctx, lf, m2, None, 1, (xx, yy), 0.5, "fp64").items()},
+          orc.maps(orc.expand(m2), xx, yy, 0.5), "fp64")
+    m3, _ = W.tiny_model(38, n_main=3, n_mem=0, types=[2, 3, 0])
+    check({k: v[0] for k, v in _run(ctx, lf, m3, None, 1, (xx, yy), 0.5, "mixed").items()},
+          orc.maps(orc.expand(m3), xx, yy, 0.5), "mixed")
+
+
+def test_maps_errors(ctx, lf):
+    import torch
+    model, _ = W.tiny_model(39, n_main=1, n_mem=2, types=[5])
+    m = ctx.upload_model(model)
+    with pytest.raises(lf.LfError) as e:
+        ctx.lens_maps(m, None, 1, {"x0": 0, "y0": 0, "h": 1.0, "nx": 4, "ny": 4}, 0.5, outputs=(), flags=False)
+    assert e.value.status == lf.LF_E_INVALID_ARG
+    with pytest.raises(lf.LfError) as e:
+        ctx.lens_maps(m, None, 1, {"x0": 0, "y0": 0, "h": 1.0, "nx": 4, "ny": 4}, 0.5, outputs=("psi111",))
+    assert e.value.status == lf.LF_E_UNSUPPORTED
+    with pytest.raises(lf.LfError) as e:
+        ctx.lens_maps(m, None, 1, {"x0": 0, "y0": 0, "h": -1.0, "nx": 4, "ny": 4}, 0.5)
+    assert e.value.status == lf.LF_E_INVALID_ARG
+    torch.cuda.synchronize()
+    m.release()
