@@ -168,6 +168,14 @@ const char* lf_last_error(const lf_ctx* ctx);
 /* Library-owned device bytes currently allocated by this context. */
 size_t lf_device_bytes(const lf_ctx* ctx);
 
+/* Kernel timing: when enabled, every kernel the library launches is bracketed by HIP events
+ * recorded on the launching stream.  lf_profile_read synchronises those events and returns the
+ * summed duration [ms] and launch count of one kernel name ("maps_lean", "maps_heavy",
+ * "expand", "chi2_halo", ...); lf_profile_reset clears the tallies. */
+lf_status lf_profile_enable(lf_ctx* ctx, int32_t on);
+lf_status lf_profile_read(lf_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+lf_status lf_profile_reset(lf_ctx* ctx);
+
 /* ---------------------------------------------------------------- cosmology helpers (host) */
 /* Angular-diameter distance D(z1, z2) [Mpc] in flat LCDM (Sec. 2.1, 2.2). */
 lf_status lf_cosmo_dist(const lf_cosmo* c, double z1, double z2, double* out);

@@ -73,6 +73,61 @@ void lf_ctx::dfree(void* p, size_t bytes) {
   if (p) { hipFree(p); dev_bytes -= bytes; }
 }
 
+// ------------------------------------------------------------------------------ kernel timing
+hipEvent_t lf_ctx::prof_ev() {
+  if (!ev_pool.empty()) { hipEvent_t e = ev_pool.back(); ev_pool.pop_back(); return e; }
+  hipEvent_t e;
+  hipEventCreate(&e);
+  return e;
+}
+void lf_ctx::prof_begin(const char* name, hipStream_t st) {
+  if (!prof) return;
+  Rec r;
+  r.name = name; r.a = prof_ev(); r.b = nullptr;
+  hipEventRecord(r.a, st);
+  prof_pending.push_back(r);
+}
+void lf_ctx::prof_end(hipStream_t st) {
+  if (!prof || prof_pending.empty() || prof_pending.back().b) return;
+  prof_pending.back().b = prof_ev();
+  hipEventRecord(prof_pending.back().b, st);
+}
+void lf_ctx::prof_flush() {
+  for (auto& r : prof_pending) {
+    if (r.b) {
+      hipEventSynchronize(r.b);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, r.a, r.b);
+      auto& t = prof_tally[r.name];
+      t.first += ms;
+      t.second += 1;
+      ev_pool.push_back(r.b);
+    }
+    ev_pool.push_back(r.a);
+  }
+  prof_pending.clear();
+}
+extern "C" lf_status lf_profile_enable(lf_ctx* ctx, int32_t on) {
+  if (!ctx) return LF_E_INVALID_ARG;
+  ctx->prof_flush();
+  ctx->prof = on != 0;
+  return LF_OK;
+}
+extern "C" lf_status lf_profile_read(lf_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !kernel || !total_ms || !launches) return LF_E_INVALID_ARG;
+  ctx->prof_flush();
+  auto it = ctx->prof_tally.find(kernel);
+  *total_ms = it == ctx->prof_tally.end() ? 0.0 : it->second.first;
+  *launches = it == ctx->prof_tally.end() ? 0 : it->second.second;
+  return LF_OK;
+}
+extern "C" lf_status lf_profile_reset(lf_ctx* ctx) {
+  if (!ctx) return LF_E_INVALID_ARG;
+  ctx->prof_flush();
+  ctx->prof_tally.clear();
+  return LF_OK;
+}
+
 // ------------------------------------------------------------------------------ cosmology
 // Flat LCDM distances by adaptive Simpson quadrature of 1/E(z).
 namespace {
@@ -162,6 +217,8 @@ extern "C" lf_status lf_shutdown(lf_ctx* ctx) {
   if (!ctx) return LF_E_INVALID_ARG;
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
+  ctx->prof_flush();
+  for (auto e : ctx->ev_pool) hipEventDestroy(e);
   for (auto& kv : ctx->bufs) if (kv.second.ptr) hipFree(kv.second.ptr);
   if (ctx->quad_u) hipFree(ctx->quad_u);
   if (ctx->quad_w) hipFree(ctx->quad_w);
@@ -377,7 +434,10 @@ lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params,
     *m64 = (lf::MemRec64*)ctx->ws((t + ".m64").c_str(), sizeof(lf::MemRec64) * std::max<size_t>(1, (size_t)S * nb), st, &err);
     if (err) return err;
   }
-  return ctx->hip(lf::launch_expand(lf_dev_model(M), params, S, *mains, *muls, *m32, *m64, st), "expand");
+  ctx->prof_begin("expand", st);
+  hipError_t he = lf::launch_expand(lf_dev_model(M), params, S, *mains, *muls, *m32, *m64, st);
+  ctx->prof_end(st);
+  return ctx->hip(he, "expand");
 }
 
 // ------------------------------------------------------------------------------ lens maps
@@ -418,6 +478,14 @@ extern "C" lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* M, const double* 
     part = (double*)ctx->ws("maps.part", bytes, st, &e);
     if (e) return e;
   }
-  return ctx->hip(lf::launch_maps(dm, mains, m32, m64, S, ps, a_dis, mixed, d3, o, lf_quad(ctx), ppl, part, st),
-                  "maps kernel");
+  if (part) {
+    ctx->prof_begin("maps_heavy", st);
+    hipError_t he = lf::launch_maps(dm, mains, m32, m64, S, ps, a_dis, mixed, d3, o, lf_quad(ctx), ppl, part, 1, st);
+    ctx->prof_end(st);
+    if (he != hipSuccess) return ctx->hip(he, "maps heavy kernel");
+  }
+  ctx->prof_begin("maps_lean", st);
+  hipError_t he = lf::launch_maps(dm, mains, m32, m64, S, ps, a_dis, mixed, d3, o, lf_quad(ctx), ppl, part, 2, st);
+  ctx->prof_end(st);
+  return ctx->hip(he, "maps kernel");
 }

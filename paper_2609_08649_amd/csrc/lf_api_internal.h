@@ -26,6 +26,16 @@ struct lf_ctx {
   double* quad_u = nullptr;
   double* quad_w = nullptr;
   void* extras = nullptr;     // autotuner / batch plans
+  // kernel timing (HIP events on the launching stream)
+  bool prof = false;
+  struct Rec { std::string name; hipEvent_t a, b; };
+  std::vector<Rec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  std::map<std::string, std::pair<double, long long>> prof_tally;
+  hipEvent_t prof_ev();
+  void prof_begin(const char* name, hipStream_t st);
+  void prof_end(hipStream_t st);
+  void prof_flush();
   lf_status fail(lf_status st, const char* fmt, ...);
   lf_status hip(hipError_t e, const char* what);
   void* ws(const char* name, size_t bytes, hipStream_t st, lf_status* err);

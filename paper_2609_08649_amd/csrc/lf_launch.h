@@ -47,7 +47,7 @@ hipError_t launch_expand(const DevModel& m, const double* params, int S, MainRec
 hipError_t launch_maps(const DevModel& m, const MainRec* mains, const MemRec32* m32,
                        const MemRec64* m64, int S, const PointsSpec& pts, double a_dis,
                        bool mixed, bool d3, const MapsOut& out, const QuadTab& q, int ppl,
-                       double* part, hipStream_t st);
+                       double* part, int which /*1 heavy, 2 lean*/, hipStream_t st);
 
 // true when a model has components evaluated by the heavy (register-hungry) pass
 inline bool has_heavy(const DevModel& m) {

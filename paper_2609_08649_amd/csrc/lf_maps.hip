@@ -305,10 +305,11 @@ __global__ __launch_bounds__(256) void k_maps(const MapsArgs A) {
 }
 
 template <bool MIXED, bool D3, int PPL>
-static void launch_maps_t(const MapsArgs& a, hipStream_t st) {
-  if (a.part) {
+static void launch_maps_t(const MapsArgs& a, int which, hipStream_t st) {
+  if (which == 1) {
     dim3 g1((unsigned)((a.pts.P + 255) / 256), a.S);
     hipLaunchKernelGGL((k_heavy<MIXED, D3>), g1, dim3(256), 0, st, a);
+    return;
   }
   long long per_block = 256LL * PPL;
   dim3 grid((unsigned)((a.pts.P + per_block - 1) / per_block), a.S);
@@ -318,14 +319,14 @@ static void launch_maps_t(const MapsArgs& a, hipStream_t st) {
 hipError_t launch_maps(const DevModel& m, const MainRec* mains, const MemRec32* m32,
                        const MemRec64* m64, int S, const PointsSpec& pts, double a_dis,
                        bool mixed, bool d3, const MapsOut& out, const QuadTab& q, int ppl,
-                       double* part, hipStream_t st) {
+                       double* part, int which, hipStream_t st) {
   MapsArgs a;
   a.part = part;
   a.m = m; a.mains = mains; a.m32 = m32; a.m64 = m64; a.S = S; a.pts = pts; a.a = a_dis;
   a.out = out; a.qd.n = q.n; a.qd.u = q.u; a.qd.w = q.w;
 #define LF_DISPATCH(MX, D, P)                 \
   if (mixed == MX && d3 == D && ppl == P) {   \
-    launch_maps_t<MX, D, P>(a, st);           \
+    launch_maps_t<MX, D, P>(a, which, st);    \
     return hipGetLastError();                 \
   }
   LF_DISPATCH(true, false, 1) LF_DISPATCH(true, false, 2) LF_DISPATCH(true, false, 4)

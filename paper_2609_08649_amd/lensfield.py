@@ -98,6 +98,9 @@ def lib():
                                           P, P, P, P]),
             "lf_find_images_mp": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, P, I32, C.POINTER(lf_grid), I32,
                                         I32, P, P, P, P, P]),
+            "lf_profile_enable": (I32, [P, I32]),
+            "lf_profile_read": (I32, [P, C.c_char_p, C.POINTER(D), C.POINTER(I64)]),
+            "lf_profile_reset": (I32, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
