@@ -220,9 +220,10 @@ lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* m, const double* params, int
 /* Step a4: chi^2 per parameter sample (Sec. 3.1).  mode 0 = source plane, Eq. (chi2_src)
  * with the full magnification tensor mu_i = A^-1(theta_obs) and beta_model = G^-1 g;
  * mode 1 = image plane, Eq. (chi2_img), with each model image found by Newton-Raphson
- * from its observed position towards beta_model (Sec. 3.5; stop |dtheta| < 1e-9" in FP64,
- * 1e-6" in MIXED, at most 20 steps; an image that does not converge, moves > 10 sigma or
- * changes parity keeps its source-plane term and is flagged).
+ * from its observed position towards beta_model (Sec. 3.5; converged when an FP64 step is
+ * below 1e-9", at most 20 steps; MIXED takes its first steps with FP32 member terms and
+ * finishes in FP64; an image that does not converge, moves > 10 sigma or changes parity
+ * keeps its source-plane term and is flagged).
  * params: device [S * n_free]; chi2: device [S]; flags: device [S] (or NULL).
  * beta_model: device [S * n_fam * 2] or NULL. */
 lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,

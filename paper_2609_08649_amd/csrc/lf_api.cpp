@@ -358,10 +358,23 @@ extern "C" lf_status lf_model_upload(lf_ctx* ctx, const lf_component* mainc, int
   // device copies
   size_t bm = sizeof(lf::MainDesc) * std::max<size_t>(1, M->main.size());
   size_t bc = sizeof(lf::MemCat) * std::max<size_t>(1, M->mem.size());
+  size_t b32 = sizeof(lf::MemCat32) * std::max<size_t>(1, M->mem.size());
   lf_status st = ctx->dmalloc((void**)&M->d_main, bm);
-  if (st == LF_OK) st = ctx->dmalloc((void**)&M->d_mem, bc);
+  if (st == LF_OK) { M->d_main_bytes = bm; st = ctx->dmalloc((void**)&M->d_mem, bc); }
+  if (st == LF_OK) { M->d_mem_bytes = bc; st = ctx->dmalloc((void**)&M->d_cat32, b32); }
   if (st != LF_OK) { lf_model_release(ctx, M); return st; }
-  M->d_main_bytes = bm; M->d_mem_bytes = bc;
+  M->d_cat32_bytes = b32;
+  {
+    std::vector<lf::MemCat32> c32(M->mem.size());
+    for (size_t i = 0; i < M->mem.size(); ++i) {
+      const lf::MemCat& c = M->mem[i];
+      c32[i].x = c.x; c32[i].y = c.y;
+      c32[i].fb = (float)c.fb; c32[i].fs = (float)c.fs; c32[i].fa = (float)c.fa;
+      c32[i].q = (float)c.q; c32[i].c = (float)c.c; c32[i].sn = (float)c.sn;
+      c32[i].pad0 = c32[i].pad1 = 0.f;
+    }
+    if (!c32.empty()) hipMemcpy(M->d_cat32, c32.data(), sizeof(lf::MemCat32) * c32.size(), hipMemcpyHostToDevice);
+  }
   if (!M->main.empty()) hipMemcpy(M->d_main, M->main.data(), sizeof(lf::MainDesc) * M->main.size(), hipMemcpyHostToDevice);
   if (!M->mem.empty()) hipMemcpy(M->d_mem, M->mem.data(), sizeof(lf::MemCat) * M->mem.size(), hipMemcpyHostToDevice);
   // a model whose fields are all fixed is validated now (expanded on the host side of the ABI)
@@ -373,6 +386,7 @@ extern "C" lf_status lf_model_release(lf_ctx* ctx, lf_model* m) {
   if (!ctx || !m) return LF_E_INVALID_ARG;
   ctx->dfree(m->d_main, m->d_main_bytes);
   ctx->dfree(m->d_mem, m->d_mem_bytes);
+  ctx->dfree(m->d_cat32, m->d_cat32_bytes);
   delete m;
   return LF_OK;
 }

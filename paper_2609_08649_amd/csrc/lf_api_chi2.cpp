@@ -1,0 +1,133 @@
+// Constraint tables and lf_chi2_batch (step a4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "lf_api_internal.h"
+#include "lf_chi2.h"
+
+void lf_prof_mark(void* c, const char* name, int end_flag) {
+  lf_ctx* ctx = (lf_ctx*)c;
+  (void)name;
+  if (!ctx->prof) return;
+  // the stream is carried by the context while a call is in flight
+  if (end_flag) ctx->prof_end(ctx->cur_stream);
+  else ctx->prof_begin(name, ctx->cur_stream);
+}
+
+extern "C" lf_status lf_constraints_upload(lf_ctx* ctx, const double* theta, const int32_t* family,
+                                           const double* sig1, const double* sig2, const double* phi,
+                                           int32_t n_img, const double* a_fam, int32_t n_fam, lf_cons** out) {
+  if (!ctx || !out) return LF_E_INVALID_ARG;
+  *out = nullptr;
+  if (n_img < 1 || n_fam < 1 || !theta || !family || !sig1 || !sig2 || !phi || !a_fam)
+    return ctx->fail(LF_E_INVALID_ARG, "constraints: missing arrays or empty set");
+  for (int i = 0; i < n_img; ++i) {
+    if (family[i] < 0 || family[i] >= n_fam) return ctx->fail(LF_E_INVALID_ARG, "image %d: family out of range", i);
+    if (!(sig1[i] > 0) || !(sig2[i] > 0) || !std::isfinite(sig1[i]) || !std::isfinite(sig2[i]) ||
+        !std::isfinite(phi[i]) || !std::isfinite(theta[2 * i]) || !std::isfinite(theta[2 * i + 1]))
+      return ctx->fail(LF_E_INVALID_ARG, "image %d: bad position or error ellipse", i);
+  }
+  for (int f = 0; f < n_fam; ++f)
+    if (!(a_fam[f] > 0) || !std::isfinite(a_fam[f])) return ctx->fail(LF_E_INVALID_ARG, "family %d: a_dis must be > 0", f);
+  lf_cons* c = new lf_cons();
+  c->n_img = n_img;
+  c->n_fam = n_fam;
+  c->order.resize(n_img);
+  std::iota(c->order.begin(), c->order.end(), 0);
+  std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) { return family[a] < family[b]; });
+  c->fam_start.assign(n_fam + 1, 0);
+  for (int i = 0; i < n_img; ++i) c->fam_start[family[i] + 1]++;
+  for (int f = 0; f < n_fam; ++f) c->fam_start[f + 1] += c->fam_start[f];
+  std::vector<double> th(2 * n_img), si(3 * n_img), sm(n_img);
+  std::vector<int> fm(n_img);
+  for (int k = 0; k < n_img; ++k) {
+    int i = c->order[k];
+    th[2 * k] = theta[2 * i]; th[2 * k + 1] = theta[2 * i + 1];
+    fm[k] = family[i];
+    // S^-1 = R^T diag(1/sig1^2, 1/sig2^2) R, R = [[c, s], [-s, c]]  (Sec. 3.1)
+    double cs = std::cos(phi[i]), sn = std::sin(phi[i]);
+    double i1 = 1.0 / (sig1[i] * sig1[i]), i2 = 1.0 / (sig2[i] * sig2[i]);
+    si[3 * k] = cs * cs * i1 + sn * sn * i2;
+    si[3 * k + 1] = cs * sn * (i1 - i2);
+    si[3 * k + 2] = sn * sn * i1 + cs * cs * i2;
+    sm[k] = std::max(sig1[i], sig2[i]);
+  }
+  size_t bytes = sizeof(double) * (2 * n_img + 3 * n_img + n_img + n_fam) + sizeof(int) * (n_img + n_fam + 1);
+  char* base = nullptr;
+  lf_status st = ctx->dmalloc((void**)&base, bytes);
+  if (st) { delete c; return st; }
+  c->bytes = bytes;
+  c->d_theta = (double*)base;
+  c->d_sinv = c->d_theta + 2 * n_img;
+  c->d_sigmax = c->d_sinv + 3 * n_img;
+  c->d_afam = c->d_sigmax + n_img;
+  c->d_fam = (int*)(c->d_afam + n_fam);
+  c->d_fam_start = c->d_fam + n_img;
+  hipMemcpy(c->d_theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice);
+  hipMemcpy(c->d_sinv, si.data(), sizeof(double) * si.size(), hipMemcpyHostToDevice);
+  hipMemcpy(c->d_sigmax, sm.data(), sizeof(double) * sm.size(), hipMemcpyHostToDevice);
+  hipMemcpy(c->d_afam, a_fam, sizeof(double) * n_fam, hipMemcpyHostToDevice);
+  hipMemcpy(c->d_fam, fm.data(), sizeof(int) * n_img, hipMemcpyHostToDevice);
+  hipMemcpy(c->d_fam_start, c->fam_start.data(), sizeof(int) * (n_fam + 1), hipMemcpyHostToDevice);
+  *out = c;
+  return LF_OK;
+}
+
+extern "C" lf_status lf_constraints_release(lf_ctx* ctx, lf_cons* c) {
+  if (!ctx || !c) return LF_E_INVALID_ARG;
+  ctx->dfree(c->d_theta, c->bytes);
+  delete c;
+  return LF_OK;
+}
+
+lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, int S, const lf_cons* c,
+                          hipStream_t st, lf::Chi2Args& A, const char* tag) {
+  lf::MainRec* mains; lf::MulRec* muls; lf::MemRec32* m32; lf::MemRec64* m64;
+  lf_status e = lf_expand_tables(ctx, M, params, S, false, st, &mains, &muls, &m32, &m64, tag);
+  if (e) return e;
+  std::string t(tag);
+  size_t n = (size_t)S * c->n_img;
+  auto wsd = [&](const char* nm, size_t cnt) { return (double*)ctx->ws((t + nm).c_str(), sizeof(double) * std::max<size_t>(1, cnt), st, &e); };
+  auto wsi = [&](const char* nm, size_t cnt) { return (int*)ctx->ws((t + nm).c_str(), sizeof(int) * std::max<size_t>(1, cnt), st, &e); };
+  A.part = wsd(".part", n * 5); if (e) return e;
+  A.pflags = wsi(".pflags", n); if (e) return e;
+  A.wimg = wsd(".wimg", n * 6); if (e) return e;
+  A.csrc = wsd(".csrc", n); if (e) return e;
+  A.cimg = wsd(".cimg", n); if (e) return e;
+  A.iflags = wsi(".iflags", n); if (e) return e;
+  A.bm_ws = wsd(".bm", (size_t)S * c->n_fam * 2); if (e) return e;
+  A.m = lf_dev_model(M);
+  A.mains = mains; A.muls = muls; A.cat32 = M->d_cat32;
+  A.S = S; A.n_img = c->n_img; A.n_fam = c->n_fam;
+  A.th = c->d_theta; A.fam = c->d_fam; A.fam_start = c->d_fam_start; A.afam = c->d_afam;
+  A.sinv = c->d_sinv; A.sigmax = c->d_sigmax;
+  lf::QuadTab q = lf_quad(ctx);
+  A.qd.n = q.n; A.qd.u = q.u; A.qd.w = q.w;
+  A.tmod = nullptr;
+  return LF_OK;
+}
+
+extern "C" lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
+                                   const lf_cons* c, int32_t mode, lf_prec prec, double* chi2, int32_t* flags,
+                                   double* beta_model, void* stream) {
+  if (!ctx) return LF_E_INVALID_ARG;
+  if (!M || !c || !chi2) return ctx->fail(LF_E_INVALID_ARG, "null model/constraints/output");
+  if (S < 1) return ctx->fail(LF_E_INVALID_ARG, "S must be >= 1");
+  if (M->n_free > 0 && !params) return ctx->fail(LF_E_INVALID_ARG, "model has free fields: params required");
+  if (mode != 0 && mode != 1) return ctx->fail(LF_E_INVALID_ARG, "mode must be 0 (source) or 1 (image)");
+  if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  lf::Chi2Args A;
+  lf_status e = lf_chi2_prepare(ctx, M, params, S, c, st, A, "chi2");
+  if (e) return e;
+  A.chi2 = chi2; A.flags = flags; A.bmod = beta_model;
+  bool mixed = prec == LF_PREC_MIXED;
+  A.newton_tol = 1e-9;
+  ctx->cur_stream = st;
+  return ctx->hip(lf::launch_chi2(A, mixed, mode, st, lf_prof_mark, ctx), "chi2 kernels");
+}

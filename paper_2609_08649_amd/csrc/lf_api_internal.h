@@ -28,6 +28,7 @@ struct lf_ctx {
   void* extras = nullptr;     // autotuner / batch plans
   // kernel timing (HIP events on the launching stream)
   bool prof = false;
+  hipStream_t cur_stream = nullptr;
   struct Rec { std::string name; hipEvent_t a, b; };
   std::vector<Rec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
@@ -55,7 +56,8 @@ struct lf_model {
   lf::Bind mul[3];
   lf::MainDesc* d_main = nullptr;
   lf::MemCat* d_mem = nullptr;
-  size_t d_main_bytes = 0, d_mem_bytes = 0;
+  lf::MemCat32* d_cat32 = nullptr;
+  size_t d_main_bytes = 0, d_mem_bytes = 0, d_cat32_bytes = 0;
 };
 
 struct lf_cons {
@@ -80,3 +82,4 @@ lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params,
                            hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
                            lf::MemRec64** m64, const char* tag);
 void lf_release_extras(lf_ctx* ctx);
+void lf_prof_mark(void* ctx, const char* name, int end_flag);

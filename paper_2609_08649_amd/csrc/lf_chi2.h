@@ -1,0 +1,40 @@
+// Launch interface of the chi^2 kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lf_device.h"
+#include "lf_launch.h"
+
+namespace lf {
+
+struct Chi2Args {
+  DevModel m;
+  const MainRec* mains;      // [S][n_main]
+  const MulRec* muls;        // [S]
+  const MemCat32* cat32;     // FP32 member catalog (resident)
+  int S, n_img, n_fam;
+  const double* th;          // [n_img*2], images sorted by family
+  const int* fam;            // [n_img]
+  const int* fam_start;      // [n_fam+1]
+  const double* afam;        // [n_fam]
+  const double* sinv;        // [n_img*3]
+  const double* sigmax;      // [n_img]
+  double* part;              // [S*n_img*5] alpha, psi at theta_obs
+  int* pflags;               // [S*n_img]
+  double* wimg;              // [S*n_img*6] W (3), beta_obs (2), det A at theta_obs
+  double* csrc;              // [S*n_img] source-plane term of each image
+  double* cimg;              // [S*n_img] image-plane term of each image
+  int* iflags;               // [S*n_img]
+  double* bm_ws;             // [S*n_fam*2] beta_model
+  double* chi2;              // [S] out
+  int* flags;                // [S] out (may be null)
+  double* bmod;              // [S*n_fam*2] out (may be null)
+  double* tmod;              // [S*n_img*2] model image positions (may be null)
+  double newton_tol;
+  Quad qd;
+};
+
+hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st,
+                       void (*mark)(void*, const char*, int), void* ctx);
+
+}  // namespace lf

@@ -1,0 +1,310 @@
+// chi^2 per parameter sample (step a4; Sec. 3.1 Eq. chi2_src / chi2_img, Sec. 3.5 Newton).
+//
+// Lanes run over the flattened (sample, image) pairs, so a wave is fully used whatever the
+// number of images; member records stay wave-uniform (one model per launch) and each lane
+// scales them by its own sample's multipliers (b*, s*, a*).  Family and sample reductions run
+// one wave per sample: a lane per family sums its images in order, a shuffle tree sums the
+// families -- a fixed order, so results are bit-reproducible and independent of batch mates.
+#include <hip/hip_runtime.h>
+
+#include "lf_chi2.h"
+#include "lf_device.h"
+
+namespace lf {
+
+__device__ __forceinline__ void lane_point(const Chi2Args& A, long long g, int& s, int& i, double& x, double& y) {
+  s = (int)(g / A.n_img);
+  i = (int)(g - (long long)s * A.n_img);
+  x = A.th[2 * i];
+  y = A.th[2 * i + 1];
+}
+
+// Member segment loop with per-lane multipliers (T = float: FP32 catalog; double: FP64).
+template <int SEG, class T, class Cat>
+__device__ __forceinline__ void seg_ls(const Cat* __restrict__ cat, int lo, int hi, double px, double py,
+                                       T bm, T sm, T am, Acc& acc, const Quad& qd) {
+  for (int h = lo; h < hi; ++h) {
+    const Cat c = cat[h];
+    T dx = (T)(px - c.x), dy = (T)(py - c.y);
+    T b = bm * (T)c.fb, s = sm * (T)c.fs, a = am * (T)c.fa;
+    Term<T> t;
+    t.t111 = t.t112 = t.t122 = t.t222 = (T)0;
+    if constexpr (SEG == SEG_CPJE || SEG == SEG_CSIE) {
+      T r2 = fma(dx, dx, dy * dy);
+      if (s == (T)0 && r2 < (T)1e-24) { acc.flags |= FL_SINGULAR; continue; }
+      T m1, w1, p1 = 0;
+      cored_mw<false>(b, s, s * s, r2, m1, w1, p1);
+      if constexpr (SEG == SEG_CPJE) {
+        T m2, w2, p2 = 0;
+        cored_mw<false>(b, a, a * a, r2, m2, w2, p2);
+        m1 -= m2; w1 -= w2;
+      }
+      radial<false>(dx, dy, m1, w1, p1, t);
+    } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
+      if (s == (T)0 && dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
+      T q2 = (T)c.q * (T)c.q;
+      T e = sqrt((T)1 - q2);
+      epje<false>(dx, dy, (T)c.c, (T)c.sn, b * (T)c.q / e, e, q2, s, a, SEG == SEG_EPJE, t);
+    } else if constexpr (SEG == SEG_POINT) {
+      if (dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
+      point_mass<false>(dx, dy, b, t);
+    } else if constexpr (SEG == SEG_NFW) {
+      if (dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
+      nfw_circ<false>((double)dx, (double)dy, (double)b, (double)s, *(Term<double>*)&t);
+    } else {
+      if (dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
+      double xp = c.c * dx + c.sn * dy, yp = c.c * dy - c.sn * dx;
+      Term<double> pr;
+      enfw_prime(xp, yp, (double)b, (double)s, c.q, qd, pr);
+      rotate_back<false>((double)c.c, (double)c.sn, pr, *(Term<double>*)&t);
+    }
+    add<false>(acc, t);
+  }
+}
+
+// The rare member segments (elliptical, point, NFW) in FP64.
+__device__ __forceinline__ void rare_members(const Chi2Args& A, double x, double y, const MulRec& u, Acc& acc) {
+  const SegOff& so = A.m.seg;
+  seg_ls<SEG_EPJE, double>(A.m.mem, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_ESIE, double>(A.m.mem, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_POINT, double>(A.m.mem, so.off[SEG_POINT], so.off[SEG_POINT + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_NFW, double>(A.m.mem, so.off[SEG_NFW], so.off[SEG_NFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_ENFW, double>(A.m.mem, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void bulk_members(const Chi2Args& A, double x, double y, const MulRec& u, Acc& acc) {
+  const SegOff& so = A.m.seg;
+  if (MIXED) {
+    float bm = (float)u.b, sm = (float)u.s, am = (float)u.a;
+    seg_ls<SEG_CPJE, float>(A.cat32, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, bm, sm, am, acc, A.qd);
+    seg_ls<SEG_CSIE, float>(A.cat32, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, bm, sm, am, acc, A.qd);
+  } else {
+    seg_ls<SEG_CPJE, double>(A.m.mem, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+    seg_ls<SEG_CSIE, double>(A.m.mem, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  }
+}
+
+// Heavy pass: main components (FP64) + rare member segments -> partial sums.
+__global__ __launch_bounds__(256) void k_chi2_heavy(const Chi2Args A) {
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)A.S * A.n_img) return;
+  int s, i;
+  double x, y;
+  lane_point(A, g, s, i, x, y);
+  Acc acc;
+  acc.zero();
+  const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
+  for (int c = 0; c < A.m.n_main; ++c) {
+    const MainRec r = mr[c];
+    eval_main<false>(r, x, y, A.qd, acc);
+    acc.flags |= r.flags;
+  }
+  const MulRec u = A.muls[s];
+  acc.flags |= u.flags;
+  rare_members(A, x, y, u, acc);
+  double* q = A.part + (size_t)g * 5;
+  q[0] = acc.ax; q[1] = acc.ay; q[2] = acc.h11; q[3] = acc.h12; q[4] = acc.h22;
+  A.pflags[g] = acc.flags;
+}
+
+// Lean pass: circular members (the bulk), added to the partial sums.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_chi2_lean(const Chi2Args A) {
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)A.S * A.n_img) return;
+  int s, i;
+  double x, y;
+  lane_point(A, g, s, i, x, y);
+  Acc acc;
+  acc.zero();
+  double* q = A.part + (size_t)g * 5;
+  acc.ax = q[0]; acc.ay = q[1]; acc.h11 = q[2]; acc.h12 = q[3]; acc.h22 = q[4];
+  acc.flags = A.pflags[g];
+  bulk_members<MIXED>(A, x, y, A.muls[s], acc);
+  q[0] = acc.ax; q[1] = acc.ay; q[2] = acc.h11; q[3] = acc.h12; q[4] = acc.h22;
+  A.pflags[g] = acc.flags;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Source-plane chi^2: one wave per sample.  Per image: beta_obs = theta - a_f alpha,
+// mu = A^-1, W = mu^T S^-1 mu; per family: G = sum W, g = sum W beta_obs, beta_model =
+// G^-1 g; chi^2 = sum (beta_obs - beta_model)^T W (beta_obs - beta_model).
+__global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) {
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x;
+  double tot = 0.0;
+  int fl = 0;
+  for (int f = lane; f < A.n_fam; f += 64) {
+    int i0 = A.fam_start[f], i1 = A.fam_start[f + 1];
+    double a = A.afam[f];
+    double G11 = 0, G12 = 0, G22 = 0, g1 = 0, g2 = 0;
+    for (int i = i0; i < i1; ++i) {
+      size_t g = (size_t)s * A.n_img + i;
+      const double* q = A.part + g * 5;
+      fl |= A.pflags[g];
+      double bx = A.th[2 * i] - a * q[0], by = A.th[2 * i + 1] - a * q[1];
+      double A11 = 1.0 - a * q[2], A12 = -a * q[3], A22 = 1.0 - a * q[4];
+      double det = A11 * A22 - A12 * A12;
+      double m11 = A22 / det, m12 = -A12 / det, m22 = A11 / det;
+      const double* Si = A.sinv + 3 * i;
+      double t11 = Si[0] * m11 + Si[1] * m12, t12 = Si[0] * m12 + Si[1] * m22;
+      double t21 = Si[1] * m11 + Si[2] * m12, t22 = Si[1] * m12 + Si[2] * m22;
+      double W11 = m11 * t11 + m12 * t21, W12 = m11 * t12 + m12 * t22, W22 = m12 * t12 + m22 * t22;
+      double* w = A.wimg + g * 6;
+      w[0] = W11; w[1] = W12; w[2] = W22; w[3] = bx; w[4] = by; w[5] = det;
+      G11 += W11; G12 += W12; G22 += W22;
+      g1 += W11 * bx + W12 * by;
+      g2 += W12 * bx + W22 * by;
+    }
+    double bmx = 0, bmy = 0;
+    if (i1 > i0) {
+      double det = G11 * G22 - G12 * G12, tr = G11 + G22;
+      if (!(fabs(det) > 1e-12 * tr * tr)) {
+        fl |= FL_GSING;
+        double lam = 0.5 * tr + sqrt(0.25 * (G11 - G22) * (G11 - G22) + G12 * G12);
+        double vx = G12, vy = lam - G11;
+        if (fabs(vx) + fabs(vy) == 0) { vx = 1; vy = 0; }
+        double nv = sqrt(vx * vx + vy * vy);
+        vx /= nv; vy /= nv;
+        double proj = (vx * g1 + vy * g2) / (lam > 0 ? lam : 1.0);
+        bmx = proj * vx; bmy = proj * vy;
+      } else {
+        bmx = (G22 * g1 - G12 * g2) / det;
+        bmy = (-G12 * g1 + G11 * g2) / det;
+      }
+    }
+    if (A.bmod) { A.bmod[((size_t)s * A.n_fam + f) * 2] = bmx; A.bmod[((size_t)s * A.n_fam + f) * 2 + 1] = bmy; }
+    A.bm_ws[((size_t)s * A.n_fam + f) * 2] = bmx;
+    A.bm_ws[((size_t)s * A.n_fam + f) * 2 + 1] = bmy;
+    for (int i = i0; i < i1; ++i) {
+      size_t g = (size_t)s * A.n_img + i;
+      double* w = A.wimg + g * 6;
+      double dx = w[3] - bmx, dy = w[4] - bmy;
+      double c = dx * (w[0] * dx + w[1] * dy) + dy * (w[1] * dx + w[2] * dy);
+      A.csrc[g] = c;
+      tot += c;
+    }
+  }
+  tot = wave_sum(tot);
+  fl = wave_or(fl);
+  if (lane == 0) {
+    A.chi2[s] = (fl & FL_INVALID) ? __builtin_nan("") : tot;
+    if (A.flags) A.flags[s] = fl;
+  }
+}
+
+// Image-plane chi^2: Newton from theta_obs towards beta_model, full halo sum per step.
+// MIXED: a lane takes steps with FP32 member terms until its step falls below 1e-5" (or 10
+// steps have run), then FP64 steps; convergence is always an FP64 step below newton_tol, the
+// rule of the FP64 path (at most 20 steps).  The switch is decided per lane, so an image's
+// result does not depend on the other images or samples sharing its wave.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  bool active = g < (long long)A.S * A.n_img;
+  if (!active) g = (long long)A.S * A.n_img - 1;   // keep the lane in the wave's loop; no store
+  int s, i;
+  double x0, y0;
+  lane_point(A, g, s, i, x0, y0);
+  const int f = A.fam[i];
+  const double a = A.afam[f];
+  const double bmx = A.bm_ws[((size_t)s * A.n_fam + f) * 2], bmy = A.bm_ws[((size_t)s * A.n_fam + f) * 2 + 1];
+  const double det0 = A.wimg[(size_t)g * 6 + 5];
+  const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
+  const MulRec u = A.muls[s];
+  double tx = x0, ty = y0, det_last = det0;
+  bool conv = false;
+  bool fine = !MIXED;         // this lane evaluates member terms in FP64
+  for (int it = 0; it < 20; ++it) {
+    Acc acc;
+    acc.zero();
+    for (int c = 0; c < A.m.n_main; ++c) eval_main<false>(mr[c], tx, ty, A.qd, acc);
+    rare_members(A, tx, ty, u, acc);
+    if (fine) bulk_members<false>(A, tx, ty, u, acc);
+    else bulk_members<true>(A, tx, ty, u, acc);
+    if (!conv) {
+      double rx = bmx - (tx - a * acc.ax), ry = bmy - (ty - a * acc.ay);
+      double A11 = 1.0 - a * acc.h11, A12 = -a * acc.h12, A22 = 1.0 - a * acc.h22;
+      double det = A11 * A22 - A12 * A12;
+      det_last = det;
+      double dx = (A22 * rx - A12 * ry) / det, dy = (-A12 * rx + A11 * ry) / det;
+      tx += dx;
+      ty += dy;
+      double step = sqrt(dx * dx + dy * dy);
+      if (fine && step < A.newton_tol) conv = true;
+      if (!fine && (step < 1e-5 || it >= 9)) fine = true;
+    }
+    if (__all(conv)) break;
+  }
+  if (!active) return;
+  double ox = x0 - tx, oy = y0 - ty;
+  bool reject = !(sqrt(ox * ox + oy * oy) <= 10.0 * A.sigmax[i]) || ((det_last > 0) != (det0 > 0));
+  int fl = (conv ? 0 : FL_NOCONV) | (reject ? FL_REJECT : 0);
+  double c;
+  if (!conv || reject) {
+    c = A.csrc[g];
+  } else {
+    const double* Si = A.sinv + 3 * i;
+    c = ox * (Si[0] * ox + Si[1] * oy) + oy * (Si[1] * ox + Si[2] * oy);
+  }
+  A.cimg[g] = c;
+  A.iflags[g] = fl;
+  if (A.tmod) { A.tmod[(size_t)g * 2] = tx; A.tmod[(size_t)g * 2 + 1] = ty; }
+}
+
+__global__ __launch_bounds__(64) void k_chi2_img_sum(const Chi2Args A) {
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x;
+  // per lane: a fixed contiguous block of images, summed in order; then a shuffle tree
+  double tot = 0.0;
+  int fl = 0;
+  for (int i = lane; i < A.n_img; i += 64) {
+    size_t g = (size_t)s * A.n_img + i;
+    tot += A.cimg[g];
+    fl |= A.iflags[g];
+  }
+  tot = wave_sum(tot);
+  fl = wave_or(fl);
+  if (lane == 0) {
+    int f0 = A.flags ? A.flags[s] : 0;
+    A.chi2[s] = (f0 & FL_INVALID) ? __builtin_nan("") : tot;
+    if (A.flags) A.flags[s] = f0 | fl;
+  }
+}
+
+hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, void (*mark)(void*, const char*, int),
+                       void* ctx) {
+  long long n = (long long)A.S * A.n_img;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  mark(ctx, "chi2_heavy", 0);
+  hipLaunchKernelGGL(k_chi2_heavy, dim3(blocks), dim3(256), 0, st, A);
+  mark(ctx, "chi2_heavy", 1);
+  mark(ctx, "chi2_lean", 0);
+  if (mixed) hipLaunchKernelGGL(k_chi2_lean<true>, dim3(blocks), dim3(256), 0, st, A);
+  else hipLaunchKernelGGL(k_chi2_lean<false>, dim3(blocks), dim3(256), 0, st, A);
+  mark(ctx, "chi2_lean", 1);
+  mark(ctx, "chi2_src", 0);
+  hipLaunchKernelGGL(k_chi2_src, dim3(A.S), dim3(64), 0, st, A);
+  mark(ctx, "chi2_src", 1);
+  if (mode == 1) {
+    mark(ctx, "chi2_newton", 0);
+    if (mixed) hipLaunchKernelGGL(k_chi2_newton<true>, dim3(blocks), dim3(256), 0, st, A);
+    else hipLaunchKernelGGL(k_chi2_newton<false>, dim3(blocks), dim3(256), 0, st, A);
+    mark(ctx, "chi2_newton", 1);
+    hipLaunchKernelGGL(k_chi2_img_sum, dim3(A.S), dim3(64), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lf

@@ -37,6 +37,12 @@ struct MemCat {
   double x, y, fb, fs, fa, q, c, sn;
 };
 
+// FP32 copy of the member catalog (centre kept in FP64) for the per-lane scaled chi^2 path.
+struct MemCat32 {
+  double x, y;
+  float fb, fs, fa, q, c, sn, pad0, pad1;
+};
+
 // Per-sample member multipliers (b*, s*, a*) and sample validity flags.
 struct MulRec {
   double b, s, a;

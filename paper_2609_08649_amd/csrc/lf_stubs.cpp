@@ -4,14 +4,6 @@
 int lf_ctx::maps_ppl(bool mixed, bool d3) { return (mixed && !d3) ? 2 : 1; }
 void lf_release_extras(lf_ctx*) {}
 
-extern "C" lf_status lf_constraints_upload(lf_ctx* ctx, const double*, const int32_t*, const double*, const double*,
-                                           const double*, int32_t, const double*, int32_t, lf_cons** out) {
-  if (out) *out = nullptr;
-  return ctx ? ctx->fail(LF_E_UNSUPPORTED, "not implemented") : LF_E_INVALID_ARG;
-}
-extern "C" lf_status lf_constraints_release(lf_ctx*, lf_cons*) { return LF_E_UNSUPPORTED; }
-extern "C" lf_status lf_chi2_batch(lf_ctx*, const lf_model*, const double*, int32_t, const lf_cons*, int32_t, lf_prec,
-                                   double*, int32_t*, double*, void*) { return LF_E_UNSUPPORTED; }
 extern "C" lf_status lf_find_images(lf_ctx*, const lf_model*, const double*, const double*, const double*, int32_t,
                                     const lf_grid*, int32_t, lf_prec, double*, double*, int32_t*, int32_t*, void*) {
   return LF_E_UNSUPPORTED;

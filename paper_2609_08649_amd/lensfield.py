@@ -298,3 +298,20 @@ class Context:
         self.check(lib().lf_lens_maps(self.handle, model.handle, pp, int(S), C.byref(pts), float(a_dis), int(prec),
                                       C.byref(m), _stream(stream)))
         return res
+
+
+def _chi2(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC_FP64, want_beta=False,
+          stream=None, out=None):
+    """chi^2 per sample (device tensors): returns (chi2 [S] f64, flags [S] i32, beta_model or None)."""
+    dev = self.device
+    chi2 = out["chi2"] if out else torch.empty(S, dtype=torch.float64, device=dev)
+    flags = out["flags"] if out else torch.empty(S, dtype=torch.int32, device=dev)
+    bm = torch.empty((S, cons.n_fam, 2), dtype=torch.float64, device=dev) if want_beta else None
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_chi2_batch(self.handle, model.handle, pp, int(S), cons.handle, int(mode), int(prec),
+                                   C.c_void_p(chi2.data_ptr()), C.c_void_p(flags.data_ptr()),
+                                   C.c_void_p(bm.data_ptr()) if bm is not None else None, _stream(stream)))
+    return chi2, flags, bm
+
+
+Context.chi2_batch = _chi2

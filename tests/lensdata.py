@@ -1,0 +1,73 @@
+"""Test inputs derived from the seeded workloads with the oracle (never with the GPU path):
+image constraints are the oracle's images of selected sources plus seeded noise."""
+import functools
+
+import numpy as np
+
+from paper_2609_08649_amd import workloads as W
+
+
+def select_sources(orc, tab, grid, cand, zs, zd, n_src, min_img=2, max_img=7, H0=70.0, Om=0.3, mu_min=0.5):
+    """First n_src candidates (in generation order) with min_img..max_img oracle images; only
+    images with |mu| >= mu_min (observable ones) are kept as constraints."""
+    out = []
+    k = 0
+    while len(out) < n_src and k < len(cand):
+        batch = cand[k:k + 64]
+        zb = zs[k:k + 64] if np.ndim(zs) else np.full(len(batch), zs)
+        a = np.array([orc.adis(zd, z, H0, Om) for z in zb])
+        fi = orc.find_images(tab, grid, batch, a, max_img=16)
+        for j in range(len(batch)):
+            n = fi["count"][j]
+            keep = np.abs(fi["mu"][j, :n]) >= mu_min
+            if min_img <= keep.sum() <= max_img and n <= 16 and not fi["flags"][j]:
+                out.append((batch[j], zb[j], a[j], fi["theta"][j, :n][keep].copy(), fi["mu"][j, :n][keep].copy()))
+                if len(out) == n_src:
+                    break
+        k += 64
+    return out
+
+
+def constraints_from_sources(srcs, n_img_total, noise, sigma):
+    """Two images per family, then extra images in generation order up to n_img_total."""
+    th, fam = [], []
+    for f, s in enumerate(srcs):
+        for t in s[3][:2]:
+            th.append(t)
+            fam.append(f)
+    for f, s in enumerate(srcs):
+        for t in s[3][2:]:
+            if len(th) >= n_img_total:
+                break
+            th.append(t)
+            fam.append(f)
+    th = np.array(th) + noise[:len(th)]
+    n = len(th)
+    return {"theta": th, "family": np.array(fam, np.int32), "sig1": np.full(n, sigma),
+            "sig2": np.full(n, sigma), "phi": np.zeros(n), "a_fam": np.array([s[2] for s in srcs])}
+
+
+@functools.lru_cache(maxsize=None)
+def cluster_constraints(seed=2611):
+    from oracle import oracle as orc
+    cfg = W.config2(seed=seed, n_samples=1)
+    tab = orc.expand(cfg["model"], cfg["truth"])
+    grid = {"x0": -60.0, "y0": -60.0, "h": 0.25, "nx": 480, "ny": 480}
+    srcs = select_sources(orc, tab, grid, cfg["src_cand"], cfg["zs_cand"], cfg["model"]["z_d"], cfg["n_src"])
+    return constraints_from_sources(srcs, cfg["n_img"], cfg["noise"], cfg["sigma_img"])
+
+
+@functools.lru_cache(maxsize=None)
+def small_constraints(seed, n_src=4):
+    from oracle import oracle as orc
+    model, truth = W.tiny_model(seed, n_main=2, n_mem=25, types=[2, 3], free_params=True)
+    tab = orc.expand(model, truth)
+    rng = np.random.default_rng(seed)
+    cand = rng.uniform(-3, 3, (400, 2))
+    zs = rng.uniform(1.0, 6.0, 400)
+    grid = {"x0": -30.0, "y0": -30.0, "h": 0.2, "nx": 300, "ny": 300}
+    srcs = select_sources(orc, tab, grid, cand, zs, model["z_d"], n_src)
+    cons = constraints_from_sources(srcs, 10 ** 6, rng.normal(0, 0.03, (200, 2)), 0.3)
+    cons["sig2"] = cons["sig1"] * rng.uniform(0.5, 1.0, cons["sig1"].size)   # elliptical errors
+    cons["phi"] = rng.uniform(0, np.pi, cons["sig1"].size)
+    return model, truth, cons

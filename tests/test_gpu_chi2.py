@@ -1,0 +1,149 @@
+"""GPU parity of lf_chi2_batch (step a4) against the FP64 oracle.
+
+FP64 path: relative 1e-9.  MIXED path: relative 1e-3 (no chi^2 tolerance is fixed by the
+paper; 1e-3 covers the first-order propagation of |d alpha| <= 1e-5" through Eq. chi2_src
+for sigma >= 0.3" and |mu| < 100)."""
+import numpy as np
+import pytest
+
+from paper_2609_08649_amd import workloads as W
+from tests import lensdata
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2609_08649_amd import lensfield
+    return lensfield
+
+
+@pytest.fixture(scope="module")
+def ctx(lf):
+    c = lf.Context(0)
+    yield c
+    c.close()
+
+
+def _jitter(truth, S, seed, scale=0.003):
+    rng = np.random.default_rng(seed)
+    p = np.repeat(truth[None], S, 0)
+    p[1:] *= 1 + scale * rng.normal(size=(S - 1, truth.size))
+    return p
+
+
+def _gpu(ctx, lf, model, params, cons, mode, prec):
+    import torch
+    m = ctx.upload_model(model)
+    c = ctx.upload_constraints(cons)
+    pp = torch.as_tensor(params, device="cuda")
+    chi, fl, bm = ctx.chi2_batch(m, pp, params.shape[0], c, mode, prec, want_beta=True)
+    torch.cuda.synchronize()
+    out = chi.cpu().numpy(), fl.cpu().numpy(), bm.cpu().numpy()
+    c.release()
+    m.release()
+    return out
+
+
+def mu_max(orc, tabs, cons):
+    """Largest |mu| over the observed images of each sample (conditioning of W = mu^T S^-1 mu)."""
+    a = cons["a_fam"][cons["family"]]
+    out = np.zeros(len(tabs))
+    for s, t in enumerate(tabs):
+        m = orc.maps(t, cons["theta"][:, 0], cons["theta"][:, 1], 1.0)
+        det = (1 - a * m["p11"]) * (1 - a * m["p22"]) - a * a * m["p12"] ** 2
+        out[s] = np.max(np.abs(1 / det))
+    return out
+
+
+def stable_image_plane(orc, tabs, cons, ref, eps=1e-5):
+    """Samples whose image-plane chi^2 is well posed: in the oracle every image's Newton solve
+    converges and is accepted, and the result moves by less than 1e-4 (relative) when every
+    observed position is shifted by eps in three directions.  Newton basins have fractal
+    boundaries; where an image does not converge within the step budget, or a 1e-5" shift
+    changes which root it reaches, two correct implementations may legitimately disagree."""
+    base = orc.chi2_batch(tabs, cons, img_mode=True)
+    ok = (base["flags"] & 12) == 0            # every image converged and was accepted
+    for d in ((eps, 0.0), (0.0, eps), (-eps, eps)):
+        r = orc.chi2_batch(tabs, dict(cons, theta=cons["theta"] + np.array(d)), img_mode=True)
+        ok &= np.abs(r["chi2_img"] - ref) <= 1e-4 * np.abs(ref) + 1e-4
+    return ok
+
+
+def _close(g, o, prec, mu=None):
+    """FP64: 1e-9 relative, widened by 1e-15 mu_max^2 for samples whose images sit next to a
+    critical curve (W grows as mu^2, so rounding in det A is amplified); MIXED: 1e-3."""
+    mu = np.zeros_like(o) if mu is None else mu
+    tol = (1e-9 + 1e-15 * mu ** 2) if prec == "fp64" else 1e-3
+    assert np.all(np.abs(g - o) <= tol * np.abs(o) + tol), (np.max(np.abs(g - o) / np.abs(o) / tol))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed", [41, 42])
+def test_chi2_small_models(ctx, lf, orc, prec, seed):
+    model, truth, cons = lensdata.small_constraints(seed)
+    params = _jitter(truth, 37, seed)
+    P = lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED
+    tabs = orc.expand_batch(model, params)
+    o = orc.chi2_batch(tabs, cons, img_mode=True)
+    mu = mu_max(orc, tabs, cons)
+    g_src, fl_src, bm = _gpu(ctx, lf, model, params, cons, 0, P)
+    _close(g_src, o["chi2_src"], prec, mu)
+    assert np.allclose(bm, o["beta_model"], rtol=1e-8 if prec == "fp64" else 1e-4, atol=1e-9 if prec == "fp64" else 1e-5)
+    g_img, fl_img, _ = _gpu(ctx, lf, model, params, cons, 1, P)
+    st = stable_image_plane(orc, tabs, cons, o["chi2_img"])
+    assert st.sum() >= 10
+    _close(g_img[st], o["chi2_img"][st], prec, mu[st])
+    assert np.array_equal(fl_img[st] & 4, o["flags"][st] & 4)       # Newton convergence decisions agree
+
+
+def test_chi2_cluster_full_size_src(ctx, lf, orc):
+    """1024 samples x 150 images x 302 halos, MIXED and FP64, every sample compared."""
+    cfg = W.config2(n_samples=1024)
+    cons = lensdata.cluster_constraints()
+    assert cons["theta"].shape[0] == 150
+    tabs = orc.expand_batch(cfg["model"], cfg["params"])
+    o = orc.chi2_batch(tabs, cons)
+    mu = mu_max(orc, tabs, cons)
+    for prec, P in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        g, fl, bm = _gpu(ctx, lf, cfg["model"], cfg["params"], cons, 0, P)
+        _close(g, o["chi2_src"], prec, mu)
+
+
+@pytest.mark.parametrize("shrink,min_frac", [(1.0, 0.3), (0.05, 0.9)])
+def test_chi2_cluster_image_plane_subset(ctx, lf, orc, shrink, min_frac):
+    """Image-plane chi^2 at full size on 64 samples: the standard jitter around the truth and a
+    5% jitter (a converged sampler), compared on the well-posed samples."""
+    cfg = W.config2(n_samples=1024)
+    cons = lensdata.cluster_constraints()
+    params = cfg["params"][:1] + shrink * (cfg["params"][:64] - cfg["params"][:1])
+    tabs = orc.expand_batch(cfg["model"], params)
+    mu = mu_max(orc, tabs, cons)
+    o = orc.chi2_batch(tabs, cons, img_mode=True)
+    st = stable_image_plane(orc, tabs, cons, o["chi2_img"])
+    assert st.mean() >= min_frac, st.mean()
+    for prec, P in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        g, fl, _ = _gpu(ctx, lf, cfg["model"], params, cons, 1, P)
+        _close(g[st], o["chi2_img"][st], prec, mu[st])
+        assert np.array_equal(fl[st] & 4, o["flags"][st] & 4)
+
+
+def test_chi2_same_alone_and_in_batch(ctx, lf):
+    """A sample's chi^2 does not depend on its batch mates (bit-identical)."""
+    model, truth, cons = lensdata.small_constraints(41)
+    params = _jitter(truth, 40, 3)
+    full, _, _ = _gpu(ctx, lf, model, params, cons, 1, lf.LF_PREC_MIXED)
+    for s in (0, 17, 39):
+        alone, _, _ = _gpu(ctx, lf, model, params[s:s + 1], cons, 1, lf.LF_PREC_MIXED)
+        assert alone[0] == full[s]
+
+
+def test_chi2_invalid_sample_is_nan_and_flagged(ctx, lf):
+    model, truth, cons = lensdata.small_constraints(42)
+    params = _jitter(truth, 4, 5)
+    params[2, 3] = 1.7          # axis ratio q > 1 in sample 2
+    g, fl, _ = _gpu(ctx, lf, model, params, cons, 0, lf.LF_PREC_FP64)
+    assert np.isnan(g[2]) and fl[2] & lf.FLAG_INVALID
+    assert np.all(np.isfinite(g[[0, 1, 3]]))
