@@ -1,0 +1,431 @@
+// Image finder by triangle mapping (step a5) and the multi-plane passes (step a6).
+//
+// Finder pipeline (all on the device, no host synchronisation):
+//   1. vertex deflections on the grid (maps kernels, FP32 members in MIXED);
+//   2. k_find_cand: one lane per grid cell keeps its four corners in registers and loops
+//      over the sources; mapped corners beta_v = theta_v - sum_j w_j alpha_j(v); a triangle
+//      is a candidate when the source lies within eps of it (eps covers the vertex error of
+//      the precision in use), appended with one atomic per wave;
+//   3. k_find_sort: candidates sorted by (source, triangle) in LDS (bitonic, one workgroup);
+//   4. k_find_polish: per candidate, FP64 vertex deflections, exact orientation signs with
+//      the watertight tie rule, barycentric start, FP64 Newton polish and acceptance;
+//   5. k_find_final: per source, merge duplicates in candidate order, write images.
+#include <hip/hip_runtime.h>
+
+#include "lf_find.h"
+#include "lf_segs.h"
+
+namespace lf {
+
+// ---------------------------------------------------------------------------------------
+// Exact orientation: sign of (bx-ax)(cy-ay) - (by-ay)(cx-ax).  A floating-point filter with
+// the (3 + 16 eps) eps bound, and when it cannot decide, the exact sign of the sum of the
+// 16 error-free partial products (expansion arithmetic: two-sum / fma two-product).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void d_two_sum(double a, double b, double& x, double& y) {
+  x = a + b;
+  double bv = x - a, av = x - bv;
+  y = (a - av) + (b - bv);
+}
+__device__ int d_sign_of_sum(const double* t, int n) {
+  double e[40];
+  int m = 0;
+  for (int k = 0; k < n; ++k) {
+    double q = t[k];
+    int w = 0;
+    for (int i = 0; i < m; ++i) {
+      double qn, h;
+      d_two_sum(q, e[i], qn, h);
+      q = qn;
+      if (h != 0.0) e[w++] = h;
+    }
+    if (q != 0.0) e[w++] = q;
+    m = w;
+  }
+  for (int i = m - 1; i >= 0; --i)
+    if (e[i] != 0.0) return e[i] > 0 ? 1 : -1;
+  return 0;
+}
+__device__ int d_orient(double ax, double ay, double bx, double by, double cx, double cy) {
+  double l = (bx - ax) * (cy - ay), r = (by - ay) * (cx - ax);
+  double det = l - r;
+  double bound = 3.3306690738754716e-16 * (fabs(l) + fabs(r));
+  if (det > bound) return 1;
+  if (-det > bound) return -1;
+  double A[2], B[2], C[2], D[2];
+  d_two_sum(bx, -ax, A[1], A[0]);
+  d_two_sum(cy, -ay, B[1], B[0]);
+  d_two_sum(by, -ay, C[1], C[0]);
+  d_two_sum(cx, -ax, D[1], D[0]);
+  double t[16];
+  int n = 0;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double p = A[i] * B[j];
+      t[n++] = fma(A[i], B[j], -p);
+      t[n++] = p;
+      double q = -C[i] * D[j];
+      t[n++] = fma(-C[i], D[j], -q);
+      t[n++] = q;
+    }
+  return d_sign_of_sum(t, n);
+}
+// an edge whose direction, oriented so that the inside is on its left, is lexicographically
+// positive owns the points lying exactly on it
+__device__ __forceinline__ bool d_edge_closed(int sg, double px, double py, double qx, double qy) {
+  if (sg > 0) return qx > px || (qx == px && qy > py);
+  return px > qx || (px == qx && py > qy);
+}
+__device__ bool d_tri_contains(const double* B, double sx, double sy) {
+  int sg = d_orient(B[0], B[1], B[2], B[3], B[4], B[5]);
+  if (sg == 0) return false;
+  for (int e = 0; e < 3; ++e) {
+    int a = e, b = (e + 1) % 3;
+    int o = d_orient(B[2 * a], B[2 * a + 1], B[2 * b], B[2 * b + 1], sx, sy);
+    if (o == 0) {
+      if (!d_edge_closed(sg, B[2 * a], B[2 * a + 1], B[2 * b], B[2 * b + 1])) return false;
+    } else if (o != sg) {
+      return false;
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// FP64 lens evaluation: beta(theta) and the Jacobian A for one source's plane weights.
+// ---------------------------------------------------------------------------------------
+__device__ void lens_eval64(const LensDev& L, const double* w, double x, double y, double& bx, double& by,
+                            double* Aout, int& flags) {
+  if (L.n_planes == 1) {
+    Acc acc;
+    acc.zero();
+    full_sum64<false>(L.pl[0], x, y, L.qd, acc);
+    double a = w[0];
+    bx = x - a * acc.ax;
+    by = y - a * acc.ay;
+    Aout[0] = 1.0 - a * acc.h11; Aout[1] = -a * acc.h12; Aout[2] = -a * acc.h12; Aout[3] = 1.0 - a * acc.h22;
+    flags |= acc.flags;
+    return;
+  }
+  const int N = L.n_planes;
+  double al[2 * LF_MAX_PLANES], Hm[3 * LF_MAX_PLANES], Am[4 * LF_MAX_PLANES];
+  double Bx = x, By = y, F11 = 1, F12 = 0, F21 = 0, F22 = 1;
+  for (int j = 0; j < N; ++j) {
+    double tx = x, ty = y, A11 = 1, A12 = 0, A21 = 0, A22 = 1;
+    for (int i = 0; i < j; ++i) {
+      double wi = L.wij[i * LF_MAX_PLANES + j];
+      tx -= wi * al[2 * i]; ty -= wi * al[2 * i + 1];
+      const double* H = &Hm[3 * i];
+      const double* Ai = &Am[4 * i];
+      A11 -= wi * (H[0] * Ai[0] + H[1] * Ai[2]); A12 -= wi * (H[0] * Ai[1] + H[1] * Ai[3]);
+      A21 -= wi * (H[1] * Ai[0] + H[2] * Ai[2]); A22 -= wi * (H[1] * Ai[1] + H[2] * Ai[3]);
+    }
+    Acc acc;
+    acc.zero();
+    full_sum64<false>(L.pl[j], tx, ty, L.qd, acc);
+    flags |= acc.flags;
+    al[2 * j] = acc.ax; al[2 * j + 1] = acc.ay;
+    Hm[3 * j] = acc.h11; Hm[3 * j + 1] = acc.h12; Hm[3 * j + 2] = acc.h22;
+    Am[4 * j] = A11; Am[4 * j + 1] = A12; Am[4 * j + 2] = A21; Am[4 * j + 3] = A22;
+    double wj = w[j];
+    if (wj == 0.0) continue;
+    Bx -= wj * acc.ax; By -= wj * acc.ay;
+    F11 -= wj * (acc.h11 * A11 + acc.h12 * A21); F12 -= wj * (acc.h11 * A12 + acc.h12 * A22);
+    F21 -= wj * (acc.h12 * A11 + acc.h22 * A21); F22 -= wj * (acc.h12 * A12 + acc.h22 * A22);
+  }
+  bx = Bx; by = By;
+  Aout[0] = F11; Aout[1] = F12; Aout[2] = F21; Aout[3] = F22;
+}
+
+// ---------------------------------------------------------------------------------------
+// 2. candidates
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ bool near_tri(const double* B, double sx, double sy, double eps) {
+  double mnx = fmin(B[0], fmin(B[2], B[4])) - eps, mxx = fmax(B[0], fmax(B[2], B[4])) + eps;
+  double mny = fmin(B[1], fmin(B[3], B[5])) - eps, mxy = fmax(B[1], fmax(B[3], B[5])) + eps;
+  if (sx < mnx || sx > mxx || sy < mny || sy > mxy) return false;
+  double area = (B[2] - B[0]) * (B[5] - B[1]) - (B[3] - B[1]) * (B[4] - B[0]);
+  double e0 = hypot(B[2] - B[0], B[3] - B[1]), e1 = hypot(B[4] - B[2], B[5] - B[3]), e2 = hypot(B[0] - B[4], B[1] - B[5]);
+  if (fabs(area) <= eps * (e0 + e1 + e2)) return true;          // nearly degenerate: bbox decides
+  double sg = area > 0 ? 1.0 : -1.0;
+  double o0 = sg * ((B[2] - B[0]) * (sy - B[1]) - (B[3] - B[1]) * (sx - B[0]));
+  double o1 = sg * ((B[4] - B[2]) * (sy - B[3]) - (B[5] - B[3]) * (sx - B[2]));
+  double o2 = sg * ((B[0] - B[4]) * (sy - B[5]) - (B[1] - B[5]) * (sx - B[4]));
+  return o0 >= -eps * e0 && o1 >= -eps * e1 && o2 >= -eps * e2;
+}
+
+template <int NP>   // NP = 1: single plane (corners in registers); 0: up to LF_MAX_PLANES planes
+__global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
+  constexpr int MP = NP == 1 ? 1 : LF_MAX_PLANES;
+  const int np = NP == 1 ? 1 : F.n_planes;
+  const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = c < ncell;
+  const long long cc = valid ? c : 0;
+  const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
+  const long long P = (long long)F.nx * F.ny;
+  const long long v[4] = {(long long)j * F.nx + i, (long long)j * F.nx + i + 1, (long long)(j + 1) * F.nx + i,
+                          (long long)(j + 1) * F.nx + i + 1};
+  double tx[4], ty[4];
+  tx[0] = tx[2] = F.x0 + (i + 0.5) * F.h; tx[1] = tx[3] = F.x0 + (i + 1.5) * F.h;
+  ty[0] = ty[1] = F.y0 + (j + 0.5) * F.h; ty[2] = ty[3] = F.y0 + (j + 1.5) * F.h;
+  double ax[MP][4], ay[MP][4];
+  for (int p = 0; p < np; ++p)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ax[p][k] = F.va[(size_t)(F.va_pstride * p) * P + v[k]];
+      ay[p][k] = F.va[(size_t)(F.va_pstride * p + 1) * P + v[k]];
+    }
+  const int lane = threadIdx.x & 63;
+  for (int s = 0; s < F.n_src; ++s) {
+    const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
+    double bx[4], by[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { bx[k] = tx[k]; by[k] = ty[k]; }
+    for (int p = 0; p < np; ++p) {
+      double w = F.w[s * np + p];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { bx[k] = fma(-w, ax[p][k], bx[k]); by[k] = fma(-w, ay[p][k], by[k]); }
+    }
+    // corners: 0 = v(i,j), 1 = v(i+1,j), 2 = v(i,j+1), 3 = v(i+1,j+1)
+    double T0[6] = {bx[0], by[0], bx[1], by[1], bx[3], by[3]};
+    double T1[6] = {bx[0], by[0], bx[3], by[3], bx[2], by[2]};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
+      unsigned long long mask = __ballot(hit);
+      if (mask) {
+        int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
+        base = __shfl(base, leader, 64);
+        if (hit) {
+          int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+          if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(2 * cc + t);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// 3. sort by (source, triangle): bitonic in LDS, one workgroup
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_find_sort(const FindArgs F) {
+  __shared__ unsigned long long key[LF_SORT_CAP];
+  int n = min(*F.n_cand, F.cap);
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int k = threadIdx.x; k < m; k += 1024) key[k] = k < n ? F.cand[k] : ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= m; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int k = threadIdx.x; k < m; k += 1024) {
+        int l = k ^ stride;
+        if (l > k) {
+          bool up = (k & size) == 0;
+          unsigned long long a = key[k], b = key[l];
+          if ((a > b) == up) { key[k] = b; key[l] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int k = threadIdx.x; k < n; k += 1024) F.cand[k] = key[k];
+}
+
+// ---------------------------------------------------------------------------------------
+// 4. FP64 containment + Newton polish per candidate
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const LensDev L) {
+  int n = min(*F.n_cand, F.cap);
+  int k = blockIdx.x * 64 + threadIdx.x;
+  if (k >= n) return;
+  unsigned long long key = F.cand[k];
+  int s = (int)(key >> 32);
+  long long tri = (long long)(key & 0xffffffffull);
+  long long cell = tri >> 1;
+  int t = (int)(tri & 1);
+  int i = (int)(cell % (F.nx - 1)), j = (int)(cell / (F.nx - 1));
+  // vertex (i,j), then (i+1,j),(i+1,j+1) for t = 0; (i+1,j+1),(i,j+1) for t = 1
+  int vi[3] = {i, t == 0 ? i + 1 : i + 1, t == 0 ? i + 1 : i};
+  int vj[3] = {j, t == 0 ? j : j + 1, j + 1};
+  const double* w = F.w + (size_t)s * F.n_planes;
+  double B[6], T[6], A[4];
+  int fl = 0;
+  for (int q = 0; q < 3; ++q) {
+    T[2 * q] = F.x0 + (vi[q] + 0.5) * F.h;
+    T[2 * q + 1] = F.y0 + (vj[q] + 0.5) * F.h;
+    lens_eval64(L, w, T[2 * q], T[2 * q + 1], B[2 * q], B[2 * q + 1], A, fl);
+  }
+  const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
+  int status = 4;
+  double tx = 0, ty = 0, mu = 0;
+  if (d_tri_contains(B, sx, sy)) {
+    double area = (B[2] - B[0]) * (B[5] - B[1]) - (B[3] - B[1]) * (B[4] - B[0]);
+    double l1 = ((B[4] - B[2]) * (sy - B[3]) - (B[5] - B[3]) * (sx - B[2])) / area;
+    double l2 = ((B[0] - B[4]) * (sy - B[5]) - (B[1] - B[5]) * (sx - B[4])) / area;
+    double l3 = 1.0 - l1 - l2;
+    double tx0 = l1 * T[0] + l2 * T[2] + l3 * T[4], ty0 = l1 * T[1] + l2 * T[3] + l3 * T[5];
+    tx = tx0; ty = ty0;
+    bool conv = false;
+    for (int it = 0; it <= 30; ++it) {
+      double ex, ey;
+      lens_eval64(L, w, tx, ty, ex, ey, A, fl);
+      double rx = sx - ex, ry = sy - ey;
+      if (fabs(rx) < 1e-10 && fabs(ry) < 1e-10) { conv = true; break; }
+      if (it == 30) break;
+      double det = A[0] * A[3] - A[1] * A[2];
+      tx += (A[3] * rx - A[1] * ry) / det;
+      ty += (-A[2] * rx + A[0] * ry) / det;
+    }
+    mu = 1.0 / (A[0] * A[3] - A[1] * A[2]);
+    if (!conv) status = 1;
+    else if (fabs(tx - tx0) > 2.0 * F.h || fabs(ty - ty0) > 2.0 * F.h) status = 2;
+    else status = 0;
+  }
+  F.c_status[k] = status;
+  F.c_theta[2 * k] = tx;
+  F.c_theta[2 * k + 1] = ty;
+  F.c_mu[k] = mu;
+}
+
+// ---------------------------------------------------------------------------------------
+// 5. per source: merge duplicates in candidate order, write outputs
+// ---------------------------------------------------------------------------------------
+__device__ int lower_bound_key(const unsigned long long* a, int n, unsigned long long x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int m = (lo + hi) >> 1;
+    if (a[m] < x) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+__global__ __launch_bounds__(64) void k_find_final(const FindArgs F) {
+  int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= F.n_src) return;
+  int total = *F.n_cand;
+  int n = min(total, F.cap);
+  int lo = lower_bound_key(F.cand, n, (unsigned long long)s << 32);
+  int hi = lower_bound_key(F.cand, n, (unsigned long long)(s + 1) << 32);
+  int cnt = 0, fl = total > F.cap ? FL_OVERFLOW : 0;
+  for (int k = lo; k < hi; ++k) {
+    if (F.c_status[k] != 0) continue;
+    double tx = F.c_theta[2 * k], ty = F.c_theta[2 * k + 1];
+    bool dup = false;
+    for (int q = lo; q < k; ++q) {
+      if (F.c_status[q] != 0) continue;
+      double dx = tx - F.c_theta[2 * q], dy = ty - F.c_theta[2 * q + 1];
+      if (sqrt(dx * dx + dy * dy) < 1e-6) { dup = true; break; }
+    }
+    if (dup) { F.c_status[k] = 3; fl |= FL_MERGED; continue; }
+    if (cnt < F.max_img) {
+      F.theta_out[((size_t)s * F.max_img + cnt) * 2] = tx;
+      F.theta_out[((size_t)s * F.max_img + cnt) * 2 + 1] = ty;
+      if (F.mu_out) F.mu_out[(size_t)s * F.max_img + cnt] = F.c_mu[k];
+    } else {
+      fl |= FL_OVERFLOW;
+    }
+    ++cnt;
+  }
+  F.count_out[s] = cnt;
+  if (F.flags_out) F.flags_out[s] = fl;
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void (*mark)(void*, const char*, int),
+                       void* ctx) {
+  long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, F.n_cand);
+  mark(ctx, "find_cand", 0);
+  if (F.n_planes == 1) hipLaunchKernelGGL(k_find_cand<1>, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
+  else hipLaunchKernelGGL(k_find_cand<0>, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
+  mark(ctx, "find_cand", 1);
+  hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
+  mark(ctx, "find_polish", 0);
+  hipLaunchKernelGGL(k_find_polish, dim3((F.cap + 63) / 64), dim3(64), 0, st, F, L);
+  mark(ctx, "find_polish", 1);
+  hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Multi-plane passes: theta_j of every point, and the final recursion (Sec. 2.2).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mp_theta(const MPArgs M, int j) {
+  long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= M.P) return;
+  double x, y;
+  if (M.grid) {
+    long long jj = p / M.nx, ii = p - jj * M.nx;
+    x = M.x0 + ((double)ii + 0.5) * M.h;
+    y = M.y0 + ((double)jj + 0.5) * M.h;
+  } else {
+    x = M.px[p];
+    y = M.py[p];
+  }
+  for (int i = 0; i < j; ++i) {
+    double w = M.wij[i * LF_MAX_PLANES + j];
+    x -= w * M.al[(size_t)(5 * i) * M.P + p];
+    y -= w * M.al[(size_t)(5 * i + 1) * M.P + p];
+  }
+  M.tx[p] = x;
+  M.ty[p] = y;
+}
+
+__global__ __launch_bounds__(256) void k_mp_final(const MPArgs M) {
+  long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= M.P) return;
+  double x, y;
+  if (M.grid) {
+    long long jj = p / M.nx, ii = p - jj * M.nx;
+    x = M.x0 + ((double)ii + 0.5) * M.h;
+    y = M.y0 + ((double)jj + 0.5) * M.h;
+  } else {
+    x = M.px[p];
+    y = M.py[p];
+  }
+  const int N = M.n_planes;
+  double Am[4 * LF_MAX_PLANES];
+  for (int j = 0; j < N; ++j) {
+    double A11 = 1, A12 = 0, A21 = 0, A22 = 1;
+    for (int i = 0; i < j; ++i) {
+      double w = M.wij[i * LF_MAX_PLANES + j];
+      const double* q = M.al + (size_t)(5 * i) * M.P + p;
+      double h11 = q[2 * M.P], h12 = q[3 * M.P], h22 = q[4 * M.P];
+      const double* Ai = &Am[4 * i];
+      A11 -= w * (h11 * Ai[0] + h12 * Ai[2]); A12 -= w * (h11 * Ai[1] + h12 * Ai[3]);
+      A21 -= w * (h12 * Ai[0] + h22 * Ai[2]); A22 -= w * (h12 * Ai[1] + h22 * Ai[3]);
+    }
+    Am[4 * j] = A11; Am[4 * j + 1] = A12; Am[4 * j + 2] = A21; Am[4 * j + 3] = A22;
+  }
+  for (int k = 0; k < M.n_zs; ++k) {
+    double bx = x, by = y, F11 = 1, F12 = 0, F21 = 0, F22 = 1;
+    for (int j = 0; j < N; ++j) {
+      double w = M.wjs[(size_t)k * LF_MAX_PLANES + j];
+      if (w == 0.0) continue;
+      const double* q = M.al + (size_t)(5 * j) * M.P + p;
+      double ax = q[0], ay = q[M.P], h11 = q[2 * M.P], h12 = q[3 * M.P], h22 = q[4 * M.P];
+      bx -= w * ax; by -= w * ay;
+      const double* Aj = &Am[4 * j];
+      F11 -= w * (h11 * Aj[0] + h12 * Aj[2]); F12 -= w * (h11 * Aj[1] + h12 * Aj[3]);
+      F21 -= w * (h12 * Aj[0] + h22 * Aj[2]); F22 -= w * (h12 * Aj[1] + h22 * Aj[3]);
+    }
+    size_t o = (size_t)k * M.P + p;
+    if (M.beta) { M.beta[2 * o] = bx; M.beta[2 * o + 1] = by; }
+    if (M.A) { M.A[4 * o] = F11; M.A[4 * o + 1] = F12; M.A[4 * o + 2] = F21; M.A[4 * o + 3] = F22; }
+    if (M.mu) M.mu[o] = 1.0 / (F11 * F22 - F12 * F21);
+  }
+}
+
+hipError_t launch_mp_theta(const MPArgs& M, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_mp_theta, dim3((unsigned)((M.P + 255) / 256)), dim3(256), 0, st, M, j);
+  return hipGetLastError();
+}
+hipError_t launch_mp_final(const MPArgs& M, hipStream_t st) {
+  hipLaunchKernelGGL(k_mp_final, dim3((unsigned)((M.P + 255) / 256)), dim3(256), 0, st, M);
+  return hipGetLastError();
+}
+
+}  // namespace lf

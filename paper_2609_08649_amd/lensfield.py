@@ -315,3 +315,79 @@ def _chi2(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC
 
 
 Context.chi2_batch = _chi2
+
+
+def _find(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, stream=None):
+    """Images of n_src sources (beta [n,2], a_src [n] device f64 tensors) on a grid."""
+    n = beta.shape[0]
+    dev = self.device
+    th = torch.zeros((n, max_img, 2), dtype=torch.float64, device=dev)
+    mu = torch.zeros((n, max_img), dtype=torch.float64, device=dev)
+    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
+    fl = torch.zeros(n, dtype=torch.int32, device=dev)
+    g = lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_find_images(self.handle, model.handle, pp, C.c_void_p(beta.data_ptr()),
+                                    C.c_void_p(a_src.data_ptr()), int(n), C.byref(g), int(max_img), int(prec),
+                                    C.c_void_p(th.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                    C.c_void_p(cnt.data_ptr()), C.c_void_p(fl.data_ptr()), _stream(stream)))
+    return {"theta": th, "mu": mu, "count": cnt, "flags": fl}
+
+
+def _planes_arg(planes, z_planes, H0, Om):
+    arr = (C.c_void_p * len(planes))(*[p.handle.value for p in planes])
+    zp = np.ascontiguousarray(z_planes, np.float64)
+    return arr, zp, lf_cosmo(H0, Om)
+
+
+def _mp_trace(self, planes, z_planes, z_src, points, prec=LF_PREC_FP64, H0=70.0, Om=0.3, stream=None,
+              outputs=("beta", "A", "mu")):
+    arr, zp, cos = _planes_arg(planes, z_planes, H0, Om)
+    zs = np.ascontiguousarray(np.atleast_1d(z_src), np.float64)
+    pts = lf_points()
+    keep = []
+    if isinstance(points, dict):
+        pts.grid = lf_grid(points["x0"], points["y0"], points["h"], points["nx"], points["ny"])
+        P = points["nx"] * points["ny"]
+    else:
+        px, py = points
+        keep += [px, py]
+        pts.px, pts.py, pts.n = px.data_ptr(), py.data_ptr(), px.numel()
+        P = px.numel()
+    dev = self.device
+    res = {}
+    if "beta" in outputs:
+        res["beta"] = torch.empty((zs.size, P, 2), dtype=torch.float64, device=dev)
+    if "A" in outputs:
+        res["A"] = torch.empty((zs.size, P, 4), dtype=torch.float64, device=dev)
+    if "mu" in outputs:
+        res["mu"] = torch.empty((zs.size, P), dtype=torch.float64, device=dev)
+    ptr = lambda k: C.c_void_p(res[k].data_ptr()) if k in res else None
+    self.check(lib().lf_multiplane_trace(self.handle, arr, zp.ctypes.data, len(planes), C.byref(cos),
+                                         zs.ctypes.data, zs.size, C.byref(pts), int(prec), ptr("beta"), ptr("A"),
+                                         ptr("mu"), _stream(stream)))
+    return res
+
+
+def _find_mp(self, planes, z_planes, beta, z_src, grid, max_img=16, prec=LF_PREC_FP64, H0=70.0, Om=0.3,
+             stream=None):
+    arr, zp, cos = _planes_arg(planes, z_planes, H0, Om)
+    zs = np.ascontiguousarray(z_src, np.float64)
+    n = beta.shape[0]
+    dev = self.device
+    th = torch.zeros((n, max_img, 2), dtype=torch.float64, device=dev)
+    mu = torch.zeros((n, max_img), dtype=torch.float64, device=dev)
+    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
+    fl = torch.zeros(n, dtype=torch.int32, device=dev)
+    g = lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+    self.check(lib().lf_find_images_mp(self.handle, arr, zp.ctypes.data, len(planes), C.byref(cos),
+                                       C.c_void_p(beta.data_ptr()), zs.ctypes.data, int(n), C.byref(g),
+                                       int(max_img), int(prec), C.c_void_p(th.data_ptr()),
+                                       C.c_void_p(mu.data_ptr()), C.c_void_p(cnt.data_ptr()),
+                                       C.c_void_p(fl.data_ptr()), _stream(stream)))
+    return {"theta": th, "mu": mu, "count": cnt, "flags": fl}
+
+
+Context.find_images = _find
+Context.multiplane_trace = _mp_trace
+Context.find_images_mp = _find_mp

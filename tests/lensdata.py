@@ -71,3 +71,40 @@ def small_constraints(seed, n_src=4):
     cons["sig2"] = cons["sig1"] * rng.uniform(0.5, 1.0, cons["sig1"].size)   # elliptical errors
     cons["phi"] = rng.uniform(0, np.pi, cons["sig1"].size)
     return model, truth, cons
+
+
+def margin_ok(orc, tab, grid, beta, a, d=1e-4):
+    """Caustic-margin filter: the oracle's image count of a source is unchanged when the source
+    moves by d in four directions (bit-exact counts are well posed only away from caustics)."""
+    shifts = np.array([[d, 0], [-d, 0], [0, d], [0, -d]])
+    base = orc.find_images(tab, grid, beta[None], np.array([a]))["count"][0]
+    pert = orc.find_images(tab, grid, beta[None] + shifts, np.full(4, a))["count"]
+    return bool(np.all(pert == base))
+
+
+@functools.lru_cache(maxsize=None)
+def config1_sources(seed=2610):
+    """Config 1: five sources at z_s = 2 with 3-5 images each, away from caustics."""
+    from oracle import oracle as orc
+    cfg = W.config1(seed)
+    tab = orc.expand(cfg["model"])
+    a = orc.adis(cfg["model"]["z_d"], cfg["zs"])
+    out = []
+    for b in cfg["src_cand"]:
+        n = orc.find_images(tab, cfg["grid"], b[None], np.array([a]))["count"][0]
+        if 3 <= n <= 5 and margin_ok(orc, tab, cfg["grid"], b, a):
+            out.append(b)
+            if len(out) == cfg["n_src"]:
+                break
+    return np.array(out), a
+
+
+@functools.lru_cache(maxsize=None)
+def cluster_sources(seed=2611):
+    """The 60 cluster sources behind the chi^2 constraints, with their distance ratios."""
+    from oracle import oracle as orc
+    cfg = W.config2(seed=seed, n_samples=1)
+    tab = orc.expand(cfg["model"], cfg["truth"])
+    grid = {"x0": -60.0, "y0": -60.0, "h": 0.25, "nx": 480, "ny": 480}
+    srcs = select_sources(orc, tab, grid, cfg["src_cand"], cfg["zs_cand"], cfg["model"]["z_d"], cfg["n_src"])
+    return np.array([s[0] for s in srcs]), np.array([s[1] for s in srcs]), np.array([s[2] for s in srcs])

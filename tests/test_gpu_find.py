@@ -1,0 +1,106 @@
+"""GPU parity of lf_find_images (step a5) against the oracle's triangle-mapping finder.
+Counts bit-exact; image positions within 1e-4"; |d mu|/|mu| <= 1e-4 where |mu| < 100."""
+import numpy as np
+import pytest
+
+from paper_2609_08649_amd import workloads as W
+from tests import lensdata
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lf():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2609_08649_amd import lensfield
+    return lensfield
+
+
+@pytest.fixture(scope="module")
+def ctx(lf):
+    c = lf.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, lf, model, params, beta, a, grid, prec, max_img=16):
+    import torch
+    m = ctx.upload_model(model)
+    b = torch.as_tensor(np.ascontiguousarray(beta, np.float64), device="cuda")
+    aa = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(a, (beta.shape[0],)), np.float64), device="cuda")
+    pp = torch.as_tensor(params, device="cuda") if params is not None else None
+    r = ctx.find_images(m, pp, b, aa, grid, max_img, lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in r.items()}
+    m.release()
+    return out
+
+
+def compare(g, o, tol_pos):
+    assert np.array_equal(g["count"], o["count"]), (g["count"], o["count"])
+    for s in range(len(o["count"])):
+        n = min(o["count"][s], g["theta"].shape[1])
+        dt = np.abs(g["theta"][s, :n] - o["theta"][s, :n])
+        assert np.max(dt, initial=0) <= tol_pos, (s, np.max(dt))
+        mo, mg = o["mu"][s, :n], g["mu"][s, :n]
+        m = np.abs(mo) < 100
+        assert np.all(np.abs(mg[m] - mo[m]) <= 1e-4 * np.abs(mo[m]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_find_config1(ctx, lf, orc, prec):
+    cfg = W.config1()
+    beta, a = lensdata.config1_sources()
+    assert len(beta) == 5
+    o = orc.find_images(orc.expand(cfg["model"]), cfg["grid"], beta, np.full(5, a))
+    assert np.all((o["count"] >= 3) & (o["count"] <= 5))
+    g = _run(ctx, lf, cfg["model"], None, beta, a, cfg["grid"], prec)
+    compare(g, o, 1e-9 if prec == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_find_cluster_full_grid(ctx, lf, orc, prec):
+    """60 sources at their own redshifts on the 2048^2 grid over 200" (the benchmark's launch)."""
+    cfg = W.config2(n_samples=1)
+    beta, zs, a = lensdata.cluster_sources()
+    o = orc.find_images(orc.expand(cfg["model"], cfg["truth"]), cfg["grid"], beta, a)
+    g = _run(ctx, lf, cfg["model"], cfg["truth"], beta, a, cfg["grid"], prec)
+    compare(g, o, 1e-9 if prec == "fp64" else 1e-4)
+    assert o["count"].sum() >= 150
+
+
+def test_find_sis_analytic_and_vertex_sources(ctx, lf):
+    b, a = 5.0, 0.6
+    model = {"z_d": 0.5, "H0": 70.0, "Om": 0.3, "n_free": 0,
+             "main": [W._comp(W.SIS, x=W.fixed(0.0), y=W.fixed(0.0), b=W.fixed(b))],
+             "members": {"type": np.zeros(0, np.int32), "x": np.zeros(0), "y": np.zeros(0), "q": None,
+                         "pa": None, "lum": None, "b0": np.zeros(0), "s0": np.zeros(0), "a0": np.zeros(0),
+                         "bmul": W.fixed(1.0), "smul": W.fixed(1.0), "amul": W.fixed(1.0)}}
+    beta = np.array([[0.7, -0.5], [0.2, 0.1]])
+    grid = {"x0": -20.0, "y0": -20.0, "h": 0.25, "nx": 160, "ny": 160}
+    g = _run(ctx, lf, model, None, beta, a, grid, "fp64")
+    assert g["count"].tolist() == [2, 2]
+    for s in range(2):
+        nb = np.linalg.norm(beta[s])
+        u = beta[s] / nb
+        exp = sorted([tuple(u * (nb + a * b)), tuple(-u * (a * b - nb))])
+        assert np.allclose(sorted(map(tuple, g["theta"][s, :2])), exp, atol=1e-9)
+    # no lens: sources exactly on grid vertices and edges are claimed by one triangle each
+    empty = dict(model, main=[])
+    grid2 = {"x0": 0.0, "y0": 0.0, "h": 1.0, "nx": 6, "ny": 6}
+    pts = np.array([[2.5, 2.5], [2.0, 1.5], [1.75, 1.75], [3.5, 1.0], [4.5, 4.5]])
+    for prec in ("fp64", "mixed"):
+        g2 = _run(ctx, lf, empty, None, pts, 1.0, grid2, prec)
+        assert g2["count"].tolist() == [1, 1, 1, 1, 1]
+        assert np.allclose(g2["theta"][:, 0], pts, atol=1e-12)
+
+
+def test_find_overflow_reports_true_count(ctx, lf, orc):
+    cfg = W.config1()
+    beta, a = lensdata.config1_sources()
+    o = orc.find_images(orc.expand(cfg["model"]), cfg["grid"], beta, np.full(5, a))
+    g = _run(ctx, lf, cfg["model"], None, beta, a, cfg["grid"], "fp64", max_img=2)
+    assert np.array_equal(g["count"], o["count"])
+    assert np.all(g["flags"][o["count"] > 2] & lf.FLAG_OVERFLOW)
+    assert np.allclose(g["theta"][:, :2], o["theta"][:, :2], atol=1e-9)
