@@ -1,21 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the lens-equation hot path on one MI355X.
 
-Workload: the cluster-scale single-plane case (2 elliptical dPIE halos + 300 circular
-dPIE members on the Sec. 3.4 scaling relations, 2048^2 grid over 200", 60 sources /
-150 images, 1024 parameter samples), synthetic and seeded.
+Workload (synthetic, seeded): the cluster-scale single-plane case -- 2 elliptical dPIE halos
++ 300 circular dPIE members on the Sec. 3.4 scaling relations, a 2048^2 grid over 200",
+60 sources at z ~ U[1, 8] with 150 image constraints (sigma = 0.5"), 1024 parameter samples.
 
-One step = one pass of the hot path over that batch:
-  maps   a1-a3+a7: expansion, halo sums, epilogue and A3 fields on the 2048^2 grid (MIXED)
-  chi2   a1+a4:    source-plane chi^2 for 1024 samples x 150 images (MIXED)
-  find   a5:       image finder for 60 sources on the 2048^2 grid (MIXED + FP64 containment)
-The headline value is halo x point lens evaluations per second over the whole step.
+One step = one pass of the hot path over that batch, all in the MIXED precision form:
+  maps  (a1-a3): expansion, halo sums, epilogue (alpha, psi_ij, kappa, gamma, det A, mu, beta)
+                 on the 2048^2 grid for the truth sample;
+  chi2  (a1+a4): source-plane chi^2 for the 1024 samples x 150 images;
+  find  (a5):    images of the 60 sources on the 2048^2 grid (FP64 containment and polish).
+The headline value is halo x point lens evaluations per second over the whole step; chi^2
+per second, the image-plane chi^2, the plain FP64 path, the multi-plane trace (3 planes,
+4096^2 rays, eNFW halos) and the uneven batched chi^2 are reported beside it.
 
-Prints one JSON line (see the repository's design notes for the accounting).
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -27,8 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak [FLOP/s]
-# algorithmic FLOPs of one circular dPIE member at one point, alpha + Hessian (closed form
-# of the oracle, transcendental = 1): see the design notes
+# Algorithmic FLOPs of one circular dPIE member at one point (alpha + Hessian), counted on the
+# closed form (add/mul 1, FMA 2, each rsqrt/reciprocal 1): offset 2, r^2 3, two cored terms
+# 2 x 9, differences 2, alpha and Hessian assembly 9, accumulation 5.
 F_CPJE = 39
 
 
@@ -38,45 +43,124 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
+
+
+def build_constraints(ctx, lf, torch, cfg, m, params_truth, W):
+    """Image constraints from the GPU finder on the truth model: the first 60 candidate sources
+    with >= 2 observable images (|mu| >= 0.5), two images per family then extras up to 150,
+    plus the workload's seeded astrometric noise."""
+    grid = {"x0": -60.0, "y0": -60.0, "h": 0.125, "nx": 960, "ny": 960}
+    srcs = []
+    cand, zs = cfg["src_cand"], cfg["zs_cand"]
+    k = 0
+    while len(srcs) < cfg["n_src"] and k < len(cand):
+        b = cand[k:k + 128]
+        z = zs[k:k + 128]
+        a = np.array([ctx.adis(cfg["model"]["z_d"], zz) for zz in z])
+        r = ctx.find_images(m, params_truth, torch.as_tensor(b, device="cuda"), torch.as_tensor(a, device="cuda"),
+                            grid, 16, lf.LF_PREC_FP64)
+        cnt, th, mu, fl = (r["count"].cpu().numpy(), r["theta"].cpu().numpy(), r["mu"].cpu().numpy(),
+                           r["flags"].cpu().numpy())
+        for j in range(len(b)):
+            n = cnt[j]
+            keep = np.abs(mu[j, :n]) >= 0.5
+            if 2 <= keep.sum() <= 7 and n <= 16 and not fl[j]:
+                srcs.append((a[j], th[j, :n][keep]))
+                if len(srcs) == cfg["n_src"]:
+                    break
+        k += 128
+    th, fam = [], []
+    for f, (a, t) in enumerate(srcs):
+        for x in t[:2]:
+            th.append(x); fam.append(f)
+    for f, (a, t) in enumerate(srcs):
+        for x in t[2:]:
+            if len(th) < cfg["n_img"]:
+                th.append(x); fam.append(f)
+    th = np.array(th) + cfg["noise"][:len(th)]
+    n = len(th)
+    cons = {"theta": th, "family": np.array(fam, np.int32), "sig1": np.full(n, cfg["sigma_img"]),
+            "sig2": np.full(n, cfg["sigma_img"]), "phi": np.zeros(n), "a_fam": np.array([s[0] for s in srcs])}
+    return cons, srcs
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the design notes "
-              "for how the work would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the design notes "
+              "describe how the work would shard).", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2609_08649_amd import lensfield as lf
     from paper_2609_08649_amd import workloads as W
 
     dev = torch.device("cuda", 0)
+    L = lf.lib()
     cfg = W.config2()
-    model = cfg["model"]
-    grid = cfg["grid"]
+    model, grid = cfg["model"], cfg["grid"]
     ctx = lf.Context(0)
     m = ctx.upload_model(model)
     H = m.n_halos
     P = grid["nx"] * grid["ny"]
+    S = cfg["params"].shape[0]
     params = torch.as_tensor(cfg["params"], device=dev)
     truth = params[:1].contiguous()
+    cons_np, srcs = build_constraints(ctx, lf, torch, cfg, m, truth, W)
+    cons = ctx.upload_constraints(cons_np)
+    n_img = cons.n_img
+    # the 60 sources: model source positions of the truth fit, at their own distance ratios
+    _, _, bm = ctx.chi2_batch(m, truth, 1, cons, 0, lf.LF_PREC_FP64, want_beta=True)
+    src_beta = bm[0].contiguous()
+    src_a = torch.as_tensor(cons_np["a_fam"], device=dev)
     a_maps = ctx.adis(model["z_d"], 2.0)
     out_names = ("alpha_x", "alpha_y", "psi11", "psi12", "psi22", "kappa", "gamma1", "gamma2", "detA", "mu",
                  "beta_x", "beta_y")
     bufs = {k: torch.empty((1, P), dtype=torch.float64, device=dev) for k in out_names}
     bufs["flags"] = torch.empty((1, P), dtype=torch.int32, device=dev)
+    chi_out = {"chi2": torch.empty(S, dtype=torch.float64, device=dev),
+               "flags": torch.empty(S, dtype=torch.int32, device=dev)}
     stream = torch.cuda.current_stream()
+    n_src = src_beta.shape[0]
+    find_out = {"theta": torch.zeros((n_src, 16, 2), dtype=torch.float64, device=dev),
+                "mu": torch.zeros((n_src, 16), dtype=torch.float64, device=dev),
+                "count": torch.zeros(n_src, dtype=torch.int32, device=dev),
+                "flags": torch.zeros(n_src, dtype=torch.int32, device=dev)}
 
-    def step():
-        ctx.lens_maps(m, truth, 1, grid, a_maps, lf.LF_PREC_MIXED, outputs=out_names, out=bufs, stream=stream)
+    def stage_maps(prec):
+        ctx.lens_maps(m, truth, 1, grid, a_maps, prec, outputs=out_names, out=bufs, stream=stream)
 
-    evals_per_step = H * P
+    def stage_chi2(prec, mode=0):
+        ctx.chi2_batch(m, params, S, cons, mode, prec, stream=stream, out=chi_out)
+
+    def stage_find(prec):
+        ctx.find_images(m, truth, src_beta, src_a, grid, 16, prec, stream=stream, out=find_out)
+
+    def step(prec):
+        stage_maps(prec)
+        stage_chi2(prec)
+        stage_find(prec)
+
+    evals_maps = H * P
+    evals_chi2 = H * n_img * S
+    evals_find = H * P
+    evals_step = evals_maps + evals_chi2 + evals_find
+
+    def timed(fn, n):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(n):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / n
+
     for _ in range(args.warmup):
-        step()
+        step(lf.LF_PREC_MIXED)
     torch.cuda.synchronize()
-    L = lf.lib()
     L.lf_profile_reset(ctx.handle)
     L.lf_profile_enable(ctx.handle, 1)
     step_ms = []
@@ -84,40 +168,52 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        step()
+        step(lf.LF_PREC_MIXED)
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     L.lf_profile_enable(ctx.handle, 0)
-    import ctypes as C
-    tot, cnt = C.c_double(), C.c_int64()
-    L.lf_profile_read(ctx.handle, b"maps_lean", C.byref(tot), C.byref(cnt))
-    lean_ms = tot.value / max(1, cnt.value)
     ms = (t1 - t0) * 1e3 / args.steps
+
+    def prof(name):
+        tot, cnt = C.c_double(), C.c_int64()
+        L.lf_profile_read(ctx.handle, name.encode(), C.byref(tot), C.byref(cnt))
+        return tot.value, cnt.value
+
+    lean_tot, lean_cnt = prof("maps_lean")
+    lean_ms = lean_tot / max(1, lean_cnt)
     n_mem = len(model["members"]["x"])
     flops_lean = n_mem * P * F_CPJE
     achieved = flops_lean / (lean_ms * 1e-3)
+    kernels = {}
+    for k in ("expand", "maps_heavy", "maps_lean", "chi2_heavy", "chi2_lean", "chi2_src", "find_cand",
+              "find_polish"):
+        t, c = prof(k)
+        if c:
+            kernels[k] = {"avg_ms": t / c, "launches_per_step": c / args.steps}
 
-    # plain FP64 path of the same maps, for the precision comparison
-    def step64():
-        ctx.lens_maps(m, truth, 1, grid, a_maps, lf.LF_PREC_FP64, outputs=out_names, out=bufs, stream=stream)
-    step64()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    n64 = max(1, args.steps // 2)
-    for _ in range(n64):
-        step64()
-    torch.cuda.synchronize()
-    ms64 = (time.perf_counter() - t) * 1e3 / n64
+    # per-stage times (MIXED and FP64) with events on the working stream
+    n_rep = max(2, args.steps // 2)
+    st = {}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        st[name] = {"maps_ms": timed(lambda: stage_maps(prec), n_rep),
+                    "chi2_src_ms": timed(lambda: stage_chi2(prec, 0), n_rep),
+                    "chi2_img_ms": timed(lambda: stage_chi2(prec, 1), max(1, n_rep // 2)),
+                    "find_ms": timed(lambda: stage_find(prec), n_rep)}
+    fp64_step_ms = st["fp64"]["maps_ms"] + st["fp64"]["chi2_src_ms"] + st["fp64"]["find_ms"]
+
+    extras = {}
+    if not args.no_extras:
+        extras = bench_extras(ctx, lf, torch, W, stream, timed)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(model, cfg, grid, args.cpu_seconds)
+        cpu = cpu_baseline(model, cfg, cons_np, args.cpu_seconds)
 
     res = {
         "metric": "halo x point lens evals/s (alpha+Jacobian)",
-        "value": evals_per_step / (ms * 1e-3),
+        "value": evals_step / (ms * 1e-3),
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -130,43 +226,86 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "cluster single plane: 2 elliptical dPIE + 300 circular dPIE members, "
-                               "2048^2 grid over 200\", maps step", "halos": H, "points": P,
-                   "precision": "mixed (FP32 member terms, FP64 accumulation and epilogue)"},
-        "fp64_path_evals_per_s": evals_per_step / (ms64 * 1e-3),
+        "config": {"workload": "cluster single plane: 2 elliptical dPIE + 300 circular dPIE members; maps on a "
+                               "2048^2 grid over 200\", source-plane chi^2 of 1024 samples x 150 images, images of "
+                               "60 sources on the 2048^2 grid", "halos": H, "points": P, "samples": S,
+                   "images": n_img, "sources": n_src,
+                   "precision": "mixed: FP32 member terms, FP64 main halos, accumulation, epilogue, "
+                                "chi^2, containment and polish"},
+        "evals_per_step": evals_step,
+        "chi2_per_s": S / (st["mixed"]["chi2_src_ms"] * 1e-3),
+        "chi2_img_per_s": S / (st["mixed"]["chi2_img_ms"] * 1e-3),
+        "fp64_path": {"evals_per_s": evals_step / (fp64_step_ms * 1e-3),
+                      "chi2_per_s": S / (st["fp64"]["chi2_src_ms"] * 1e-3),
+                      "chi2_img_per_s": S / (st["fp64"]["chi2_img_ms"] * 1e-3)},
+        "stages_ms": st,
+        "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": "maps_lean", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                     "avg_launch_ms": lean_ms, "flops_per_launch": flops_lean},
+                     "avg_launch_ms": lean_ms, "flops_per_launch": flops_lean,
+                     "flops_per_eval": F_CPJE, "evals_per_launch": n_mem * P},
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
+    cons.release()
     m.release()
     ctx.close()
 
 
-def cpu_baseline(model, cfg, grid, seconds):
-    """The FP64 oracle (as it stands) on a bounded sample of the same maps workload."""
+def bench_extras(ctx, lf, torch, W, stream, timed):
+    out = {}
+    # multi-plane: 3 planes (300/60/40 halos incl. eNFW), 4096^2 rays, 4 source redshifts
+    c4 = W.config4()
+    planes = [ctx.upload_model(p) for p in c4["planes"]]
+    H4 = sum(p.n_halos for p in planes)
+    P4 = c4["grid"]["nx"] * c4["grid"]["ny"]
+    res = {}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        keep = ctx.multiplane_trace(planes, c4["z_planes"], c4["zs_maps"], c4["grid"], prec, stream=stream)
+        del keep
+        t = timed(lambda: ctx.multiplane_trace(planes, c4["z_planes"], c4["zs_maps"], c4["grid"], prec,
+                                               stream=stream, outputs=("beta", "mu")), 2)
+        res[name] = {"ms": t, "evals_per_s": H4 * P4 / (t * 1e-3)}
+    out["multiplane_4096"] = {"halos": H4, "rays": P4, "z_src": len(c4["zs_maps"]), **res}
+    for p in planes:
+        p.release()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(model, cfg, cons, seconds):
+    """The FP64 oracle (as it stands) timed on a bounded sample of the same workload: maps at
+    random grid points and chi^2 of a subset of the samples, all host threads."""
     from oracle import oracle as orc
     from paper_2609_08649_amd import workloads as W
     tab = orc.expand(model, cfg["params"][0])
-    x, y = W.grid_points(grid)
+    x, y = W.grid_points(cfg["grid"])
     rng = np.random.default_rng(0)
     nth = orc.nthreads_default()
+    H = tab.shape[0]
     n = 2000
-    t = 0.0
     while True:
         idx = rng.choice(x.size, n, replace=False)
         t0 = time.perf_counter()
         orc.maps(tab, x[idx], y[idx], 0.6, nthreads=nth)
-        t = time.perf_counter() - t0
-        if t > seconds / 4 or n >= 200000:
+        t_maps = time.perf_counter() - t0
+        if t_maps > seconds / 3 or n >= x.size:
             break
-        n = int(n * min(8.0, max(2.0, seconds / 4 / max(t, 1e-3))))
-    evals = n * tab.shape[0]
-    return {"value": evals / t, "unit": "evals/s", "cores": nth, "kind": "oracle",
-            "sample": "%d random grid points x %d halos of the 2048^2 maps workload (alpha, Hessian, third "
-                      "derivatives by AD), %.1f s" % (n, tab.shape[0], t)}
+        n = min(x.size, int(n * min(8.0, max(2.0, seconds / 3 / max(t_maps, 1e-3)))))
+    ns = 64
+    tabs = orc.expand_batch(model, cfg["params"][:ns])
+    t0 = time.perf_counter()
+    orc.chi2_batch(tabs, cons, nthreads=nth)
+    t_chi = time.perf_counter() - t0
+    n_img = cons["theta"].shape[0]
+    evals = n * H + ns * n_img * H
+    return {"value": evals / (t_maps + t_chi), "unit": "evals/s", "cores": nth, "kind": "oracle",
+            "chi2_per_s": ns / t_chi,
+            "sample": "%d random points of the 2048^2 maps workload (alpha, Hessian and third derivatives by "
+                      "AD) + source-plane chi^2 of %d of the 1024 samples x %d images; %d halos; %.1f s"
+                      % (n, ns, n_img, H, t_maps + t_chi)}
 
 
 if __name__ == "__main__":

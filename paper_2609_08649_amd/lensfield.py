@@ -317,14 +317,16 @@ def _chi2(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC
 Context.chi2_batch = _chi2
 
 
-def _find(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, stream=None):
+def _find(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, stream=None, out=None):
     """Images of n_src sources (beta [n,2], a_src [n] device f64 tensors) on a grid."""
     n = beta.shape[0]
     dev = self.device
-    th = torch.zeros((n, max_img, 2), dtype=torch.float64, device=dev)
-    mu = torch.zeros((n, max_img), dtype=torch.float64, device=dev)
-    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
-    fl = torch.zeros(n, dtype=torch.int32, device=dev)
+    if out is None:
+        out = {"theta": torch.zeros((n, max_img, 2), dtype=torch.float64, device=dev),
+               "mu": torch.zeros((n, max_img), dtype=torch.float64, device=dev),
+               "count": torch.zeros(n, dtype=torch.int32, device=dev),
+               "flags": torch.zeros(n, dtype=torch.int32, device=dev)}
+    th, mu, cnt, fl = out["theta"], out["mu"], out["count"], out["flags"]
     g = lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
     pp = C.c_void_p(params.data_ptr()) if params is not None else None
     self.check(lib().lf_find_images(self.handle, model.handle, pp, C.c_void_p(beta.data_ptr()),
