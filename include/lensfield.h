@@ -261,6 +261,38 @@ lf_status lf_find_images_mp(lf_ctx* ctx, const lf_model* const* planes, const do
                             int32_t max_img, lf_prec prec, double* theta_out, double* mu_out,
                             int32_t* count_out, int32_t* flags, void* stream);
 
+/* ---------------------------------------------------------------- uneven batched chi^2 (a8) */
+/* One chi^2 problem of an uneven batch: a model, its constraints and S parameter samples. */
+typedef struct {
+  const lf_model* model;
+  const lf_cons* cons;
+  const double* params;  /* device [S * n_free] (NULL when the model has no free field)  */
+  int32_t S;
+  double* chi2;          /* device [S] output                                             */
+  int32_t* flags;        /* device [S] output or NULL                                     */
+} lf_batch_item;
+
+typedef struct lf_batch lf_batch;
+
+/* Plan a batch of chi^2 problems of different sizes (models with different halo counts,
+ * constraint sets of different lengths) to run as one persistent launch: per-item expansion,
+ * the halo sums of all items from one queue of tiles ordered largest work first, then the
+ * per-sample reductions (and, mode 1, the image-plane Newton solves), all captured in a
+ * hipGraph.  autotune != 0 times candidate tile shapes (workgroup size, tile length, resident
+ * workgroups per CU) and keeps the fastest, caching the choice on disk (file named by the
+ * environment variable LF_AUTOTUNE_CACHE, else $HOME/.cache/lensfield/autotune.txt).
+ * The plan owns its workspace; the item pointers must stay valid until lf_batch_release.
+ * Results are bit-identical to lf_chi2_batch on each item.  Errors: LF_E_INVALID_ARG,
+ * LF_E_OUT_OF_BUDGET, LF_E_DEVICE. */
+lf_status lf_batch_create(lf_ctx* ctx, const lf_batch_item* items, int32_t n_items, int32_t mode,
+                          lf_prec prec, int32_t autotune, lf_batch** out);
+/* Replay the plan's graph on `stream` (reads the current contents of each item's params). */
+lf_status lf_batch_run(lf_batch* b, void* stream);
+/* Chosen tile shape: workgroup size, resident workgroups, lanes per tile, number of tiles. */
+lf_status lf_batch_info(const lf_batch* b, int32_t* block, int32_t* grid, int32_t* tile_lanes,
+                        int32_t* n_tiles);
+lf_status lf_batch_release(lf_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,25 @@ struct Chi2Args {
   Quad qd;
 };
 
+// Uneven batches: many (model, constraints, samples) items in one persistent launch.
+struct BatchTile {
+  int item, pad;
+  long long g0, g1;          // lane range [g0, g1) of the item's (sample, image) pairs
+};
+struct BatchArgs {
+  const Chi2Args* items;     // [n_items] (device)
+  int n_items;
+  const BatchTile* tiles;    // [n_tiles], largest work first
+  int n_tiles;
+  int* counter;              // [2] tile queues (halo sums, Newton)
+  const int* samp_item;      // [total_S] item of each sample of the batch
+  const int* samp_local;     // [total_S] its index inside the item
+  int total_S;
+};
+
+hipError_t launch_batch(const BatchArgs& B, bool mixed, int mode, int block, int grid_persist, hipStream_t st);
+hipError_t launch_batch_lean_only(const BatchArgs& B, bool mixed, int block, int grid_persist, hipStream_t st);
+
 hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st,
                        void (*mark)(void*, const char*, int), void* ctx);
 

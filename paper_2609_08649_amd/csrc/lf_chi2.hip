@@ -86,9 +86,7 @@ __device__ __forceinline__ void bulk_members(const Chi2Args& A, double x, double
 }
 
 // Heavy pass: main components (FP64) + rare member segments -> partial sums.
-__global__ __launch_bounds__(256) void k_chi2_heavy(const Chi2Args A) {
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (long long)A.S * A.n_img) return;
+__device__ void chi2_heavy_lane(const Chi2Args& A, long long g) {
   int s, i;
   double x, y;
   lane_point(A, g, s, i, x, y);
@@ -107,12 +105,15 @@ __global__ __launch_bounds__(256) void k_chi2_heavy(const Chi2Args A) {
   q[0] = acc.ax; q[1] = acc.ay; q[2] = acc.h11; q[3] = acc.h12; q[4] = acc.h22;
   A.pflags[g] = acc.flags;
 }
+__global__ __launch_bounds__(256) void k_chi2_heavy(const Chi2Args A) {
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)A.S * A.n_img) return;
+  chi2_heavy_lane(A, g);
+}
 
 // Lean pass: circular members (the bulk), added to the partial sums.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_chi2_lean(const Chi2Args A) {
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (long long)A.S * A.n_img) return;
+__device__ void chi2_lean_lane(const Chi2Args& A, long long g) {
   int s, i;
   double x, y;
   lane_point(A, g, s, i, x, y);
@@ -124,6 +125,12 @@ __global__ __launch_bounds__(256) void k_chi2_lean(const Chi2Args A) {
   bulk_members<MIXED>(A, x, y, A.muls[s], acc);
   q[0] = acc.ax; q[1] = acc.ay; q[2] = acc.h11; q[3] = acc.h12; q[4] = acc.h22;
   A.pflags[g] = acc.flags;
+}
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_chi2_lean(const Chi2Args A) {
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)A.S * A.n_img) return;
+  chi2_lean_lane<MIXED>(A, g);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -140,9 +147,8 @@ __device__ __forceinline__ int wave_or(int v) {
 // Source-plane chi^2: one wave per sample.  Per image: beta_obs = theta - a_f alpha,
 // mu = A^-1, W = mu^T S^-1 mu; per family: G = sum W, g = sum W beta_obs, beta_model =
 // G^-1 g; chi^2 = sum (beta_obs - beta_model)^T W (beta_obs - beta_model).
-__global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) {
-  const int s = blockIdx.x;
-  const int lane = threadIdx.x;
+__device__ void chi2_src_sample(const Chi2Args& A, int s) {
+  const int lane = threadIdx.x & 63;
   double tot = 0.0;
   int fl = 0;
   for (int f = lane; f < A.n_fam; f += 64) {
@@ -203,6 +209,7 @@ __global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) {
     if (A.flags) A.flags[s] = fl;
   }
 }
+__global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) { chi2_src_sample(A, blockIdx.x); }
 
 // Image-plane chi^2: Newton from theta_obs towards beta_model, full halo sum per step.
 // MIXED: a lane takes steps with FP32 member terms until its step falls below 1e-5" (or 10
@@ -210,9 +217,7 @@ __global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) {
 // rule of the FP64 path (at most 20 steps).  The switch is decided per lane, so an image's
 // result does not depend on the other images or samples sharing its wave.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  bool active = g < (long long)A.S * A.n_img;
+__device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
   if (!active) g = (long long)A.S * A.n_img - 1;   // keep the lane in the wave's loop; no store
   int s, i;
   double x0, y0;
@@ -262,10 +267,14 @@ __global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
   A.iflags[g] = fl;
   if (A.tmod) { A.tmod[(size_t)g * 2] = tx; A.tmod[(size_t)g * 2 + 1] = ty; }
 }
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  chi2_newton_lane<MIXED>(A, g, g < (long long)A.S * A.n_img);
+}
 
-__global__ __launch_bounds__(64) void k_chi2_img_sum(const Chi2Args A) {
-  const int s = blockIdx.x;
-  const int lane = threadIdx.x;
+__device__ void chi2_img_sample(const Chi2Args& A, int s) {
+  const int lane = threadIdx.x & 63;
   // per lane: a fixed contiguous block of images, summed in order; then a shuffle tree
   double tot = 0.0;
   int fl = 0;
@@ -282,6 +291,7 @@ __global__ __launch_bounds__(64) void k_chi2_img_sum(const Chi2Args A) {
     if (A.flags) A.flags[s] = f0 | fl;
   }
 }
+__global__ __launch_bounds__(64) void k_chi2_img_sum(const Chi2Args A) { chi2_img_sample(A, blockIdx.x); }
 
 hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, void (*mark)(void*, const char*, int),
                        void* ctx) {
@@ -303,6 +313,89 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
     else hipLaunchKernelGGL(k_chi2_newton<false>, dim3(blocks), dim3(256), 0, st, A);
     mark(ctx, "chi2_newton", 1);
     hipLaunchKernelGGL(k_chi2_img_sum, dim3(A.S), dim3(64), 0, st, A);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Uneven batches (one persistent launch over many items).  Tiles are ordered largest work
+// first and taken from an atomic queue by resident workgroups, which stop when the queue is
+// empty.  Every lane runs the same per-(sample, image) code as the single-item kernels, so a
+// sample's result is bit-identical whichever tile, workgroup or batch it lands in.
+// ---------------------------------------------------------------------------------------
+__global__ void k_batch_reset(int* counter) {
+  if (threadIdx.x < 2) counter[threadIdx.x] = 0;
+}
+
+__global__ void k_batch_heavy(const BatchArgs B) {
+  for (int t = blockIdx.x; t < B.n_tiles; t += gridDim.x) {
+    const BatchTile T = B.tiles[t];
+    const Chi2Args& A = B.items[T.item];
+    for (long long g = T.g0 + threadIdx.x; g < T.g1; g += blockDim.x) chi2_heavy_lane(A, g);
+  }
+}
+
+__device__ __forceinline__ int next_tile(int* counter) {
+  __shared__ int t_sh;
+  __syncthreads();
+  if (threadIdx.x == 0) t_sh = atomicAdd(counter, 1);
+  __syncthreads();
+  return t_sh;
+}
+
+template <bool MIXED>
+__global__ void k_batch_lean(const BatchArgs B) {
+  for (;;) {
+    int t = next_tile(&B.counter[0]);
+    if (t >= B.n_tiles) break;
+    const BatchTile T = B.tiles[t];
+    const Chi2Args& A = B.items[T.item];
+    for (long long g = T.g0 + threadIdx.x; g < T.g1; g += blockDim.x) chi2_lean_lane<MIXED>(A, g);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_batch_src(const BatchArgs B) {
+  int gs = blockIdx.x;
+  chi2_src_sample(B.items[B.samp_item[gs]], B.samp_local[gs]);
+}
+
+template <bool MIXED>
+__global__ void k_batch_newton(const BatchArgs B) {
+  for (;;) {
+    int t = next_tile(&B.counter[1]);
+    if (t >= B.n_tiles) break;
+    const BatchTile T = B.tiles[t];
+    const Chi2Args& A = B.items[T.item];
+    // uniform trip count so that whole waves take part in the convergence votes
+    for (long long base = T.g0; base < T.g1; base += blockDim.x) {
+      long long g = base + threadIdx.x;
+      chi2_newton_lane<MIXED>(A, g, g < T.g1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_batch_img(const BatchArgs B) {
+  int gs = blockIdx.x;
+  chi2_img_sample(B.items[B.samp_item[gs]], B.samp_local[gs]);
+}
+
+hipError_t launch_batch_lean_only(const BatchArgs& B, bool mixed, int block, int grid_persist, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.counter);
+  if (mixed) hipLaunchKernelGGL(k_batch_lean<true>, dim3(grid_persist), dim3(block), 0, st, B);
+  else hipLaunchKernelGGL(k_batch_lean<false>, dim3(grid_persist), dim3(block), 0, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& B, bool mixed, int mode, int block, int grid_persist, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.counter);
+  hipLaunchKernelGGL(k_batch_heavy, dim3(grid_persist), dim3(block), 0, st, B);
+  if (mixed) hipLaunchKernelGGL(k_batch_lean<true>, dim3(grid_persist), dim3(block), 0, st, B);
+  else hipLaunchKernelGGL(k_batch_lean<false>, dim3(grid_persist), dim3(block), 0, st, B);
+  hipLaunchKernelGGL(k_batch_src, dim3(B.total_S), dim3(64), 0, st, B);
+  if (mode == 1) {
+    if (mixed) hipLaunchKernelGGL(k_batch_newton<true>, dim3(grid_persist), dim3(block), 0, st, B);
+    else hipLaunchKernelGGL(k_batch_newton<false>, dim3(grid_persist), dim3(block), 0, st, B);
+    hipLaunchKernelGGL(k_batch_img, dim3(B.total_S), dim3(64), 0, st, B);
   }
   return hipGetLastError();
 }

@@ -99,6 +99,10 @@ def lib():
             "lf_find_images_mp": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, P, I32, C.POINTER(lf_grid), I32,
                                         I32, P, P, P, P, P]),
             "lf_profile_enable": (I32, [P, I32]),
+            "lf_batch_create": (I32, [P, P, I32, I32, I32, I32, PP]),
+            "lf_batch_run": (I32, [P, P]),
+            "lf_batch_info": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
+            "lf_batch_release": (I32, [P]),
             "lf_profile_read": (I32, [P, C.c_char_p, C.POINTER(D), C.POINTER(I64)]),
             "lf_profile_reset": (I32, [P]),
         }
@@ -393,3 +397,45 @@ def _find_mp(self, planes, z_planes, beta, z_src, grid, max_img=16, prec=LF_PREC
 Context.find_images = _find
 Context.multiplane_trace = _mp_trace
 Context.find_images_mp = _find_mp
+
+
+class lf_batch_item(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("cons", C.c_void_p), ("params", C.c_void_p), ("S", C.c_int32),
+                ("pad", C.c_int32), ("chi2", C.c_void_p), ("flags", C.c_void_p)]
+
+
+class Batch:
+    """A planned uneven chi^2 batch (persistent launch captured in a hipGraph)."""
+
+    def __init__(self, ctx, items, mode=0, prec=LF_PREC_MIXED, autotune=True):
+        """items: list of (Model, Constraints, params tensor [S, n_free] or None, S)."""
+        self.ctx = ctx
+        dev = ctx.device
+        self.outputs = []
+        arr = (lf_batch_item * len(items))()
+        self._keep = []
+        for k, (m, c, p, S) in enumerate(items):
+            chi = torch.empty(S, dtype=torch.float64, device=dev)
+            fl = torch.empty(S, dtype=torch.int32, device=dev)
+            self.outputs.append((chi, fl))
+            self._keep.append(p)
+            arr[k] = lf_batch_item(m.handle.value, c.handle.value, p.data_ptr() if p is not None else None,
+                                   int(S), 0, chi.data_ptr(), fl.data_ptr())
+        h = C.c_void_p()
+        ctx.check(lib().lf_batch_create(ctx.handle, C.cast(arr, C.c_void_p), len(items), int(mode), int(prec),
+                                        1 if autotune else 0, C.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        self.ctx.check(lib().lf_batch_run(self.handle, _stream(stream)))
+        return self.outputs
+
+    def info(self):
+        v = [C.c_int32() for _ in range(4)]
+        self.ctx.check(lib().lf_batch_info(self.handle, *[C.byref(x) for x in v]))
+        return {"block": v[0].value, "grid": v[1].value, "tile_lanes": v[2].value, "n_tiles": v[3].value}
+
+    def release(self):
+        if self.handle:
+            lib().lf_batch_release(self.handle)
+            self.handle = None

@@ -179,9 +179,15 @@ def config3(seed: int = 2612, n_models: int = 8, walkers_per_model: int = 512):
         n_fam = int(np.ceil(p / 2.5))
         cand = rng.uniform(-25.0, 25.0, (6 * n_fam + 400, 2))
         zs = rng.uniform(1.0, 8.0, 6 * n_fam + 400)
+        # constraint set: p positions in n_fam families (>= 2 images each), circular 0.5" errors,
+        # one source redshift per family
+        fam = np.concatenate([np.repeat(np.arange(n_fam), 2),
+                              rng.integers(0, n_fam, max(0, p - 2 * n_fam))])[:p].astype(np.int32)
+        theta = rng.uniform(-40.0, 40.0, (p, 2))
         models.append({"model": model, "params": params, "truth": truth,
                        "n_img": p, "n_fam": n_fam, "src_cand": cand, "zs_cand": zs,
-                       "sigma_img": 0.5, "noise": rng.normal(0.0, 0.05, (p + 64, 2))})
+                       "sigma_img": 0.5, "noise": rng.normal(0.0, 0.05, (p + 64, 2)),
+                       "theta": theta, "family": fam, "z_fam": rng.uniform(1.0, 8.0, n_fam)})
     return {"models": models}
 
 
