@@ -293,6 +293,56 @@ lf_status lf_batch_info(const lf_batch* b, int32_t* block, int32_t* grid, int32_
                         int32_t* n_tiles);
 lf_status lf_batch_release(lf_batch* b);
 
+/* ---------------------------------------------------------------- serving (a8) */
+typedef struct lf_server lf_server;
+
+typedef struct {
+  size_t hbm_budget;         /* device bytes the server may hold for admitted requests      */
+  int32_t n_streams;         /* >= 2: one for chi^2 batches, the rest for map chunks         */
+  int32_t max_batch_samples; /* cap on the samples of one continuous chi^2 batch (0 = 65536) */
+  int32_t map_chunk_rows;    /* grid rows per map chunk (0 = 256): preemption granularity   */
+} lf_serve_config;
+
+enum { LF_REQ_CHI2 = 0, LF_REQ_MU_MAP = 1, LF_REQ_SING_MAP = 2 };
+
+/* A request.  chi^2: model, cons, host params [S * n_free] (copied at submit), S, mode, prec;
+ * output out_host [S] (and flags_host [S] or NULL).  LF_REQ_MU_MAP: model (+ host params row or
+ * NULL), grid, a_dis, prec; out_host [P] = mu.  LF_REQ_SING_MAP: out_host [6][P] = kappa,
+ * det A, e1, e2, f1, f2 (Sec. 6).  Outputs are written by asynchronous copies: pass pinned host
+ * memory (pageable memory works but stalls the scheduler while it copies). */
+typedef struct {
+  int32_t kind;
+  int32_t S;
+  const lf_model* model;
+  const lf_cons* cons;
+  const double* params;
+  int32_t mode;
+  int32_t prec;
+  lf_grid grid;
+  double a_dis;
+  double* out_host;
+  int32_t* flags_host;
+} lf_request;
+
+/* Start a server on a context: a scheduler thread admits requests in arrival order whenever
+ * their device footprint fits the budget (a later, smaller request may pass one that does not
+ * fit yet), merges all admitted chi^2 requests of one (mode, precision) into one persistent
+ * batch launch while the previous batch runs (continuous batching), and runs maps in row
+ * chunks on the other streams so that their work overlaps with the chi^2 batches.  A request
+ * larger than the whole budget fails with LF_E_OUT_OF_BUDGET; a failing request does not
+ * affect the others.  Each result is bit-identical to the same request served alone. */
+lf_status lf_serve_start(lf_ctx* ctx, const lf_serve_config* cfg, lf_server** out);
+/* Thread-safe.  Returns a ticket (> 0) or an error for a malformed request. */
+lf_status lf_serve_submit(lf_server* s, const lf_request* req, int64_t* ticket);
+/* status: 0 pending, 1 done, < 0 the request's error; latency_ms = completion - submission. */
+lf_status lf_serve_poll(lf_server* s, int64_t ticket, int32_t* status, double* latency_ms);
+lf_status lf_serve_wait(lf_server* s, int64_t ticket, int32_t* status, double* latency_ms);
+/* Latency statistics of completed requests of one kind (-1 = all): count, p50, p99, mean [ms]. */
+lf_status lf_serve_stats(lf_server* s, int32_t kind, int64_t* count, double* p50_ms, double* p99_ms,
+                         double* mean_ms);
+/* Waits for admitted work, fails queued requests with LF_E_NOT_READY, frees the arena. */
+lf_status lf_serve_stop(lf_server* s);
+
 #ifdef __cplusplus
 }
 #endif

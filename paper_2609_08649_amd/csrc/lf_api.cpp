@@ -418,14 +418,14 @@ bool lf_points_spec(const lf_points* p, lf::PointsSpec& s) {
   if (!p) return false;
   if (p->px) {
     if (!p->py || p->n <= 0) return false;
-    s.grid = 0; s.px = p->px; s.py = p->py; s.P = p->n;
+    s.grid = 0; s.px = p->px; s.py = p->py; s.P = p->n; s.p0 = 0;
     s.x0 = s.y0 = s.h = 0; s.nx = s.ny = 0;
   } else {
     const lf_grid& g = p->grid;
     if (!(g.h > 0) || !std::isfinite(g.h) || !std::isfinite(g.x0) || !std::isfinite(g.y0) || g.nx <= 0 || g.ny <= 0)
       return false;
     s.grid = 1; s.x0 = g.x0; s.y0 = g.y0; s.h = g.h; s.nx = g.nx; s.ny = g.ny;
-    s.px = s.py = nullptr; s.P = (long long)g.nx * g.ny;
+    s.px = s.py = nullptr; s.P = (long long)g.nx * g.ny; s.p0 = 0;
   }
   return true;
 }

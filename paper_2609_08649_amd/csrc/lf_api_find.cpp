@@ -110,7 +110,7 @@ lf_status trace_planes(lf_ctx* ctx, const lf_model* const* planes, int N, const 
     hipError_t he = lf::launch_mp_theta(M, j, st);
     if (he != hipSuccess) return ctx->hip(he, "multi-plane theta_j");
     lf::PointsSpec pj;
-    pj.grid = 0; pj.px = M.tx; pj.py = M.ty; pj.P = P; pj.x0 = pj.y0 = pj.h = 0; pj.nx = pj.ny = 0;
+    pj.grid = 0; pj.px = M.tx; pj.py = M.ty; pj.P = P; pj.p0 = 0; pj.x0 = pj.y0 = pj.h = 0; pj.nx = pj.ny = 0;
     std::string tag = "mp" + std::to_string(j);
     lf::Plane64 keep;
     e = plane_sum(ctx, planes[j], nullptr, pj, mixed, alpha_psi_out(M.al + (size_t)5 * j * P, P, true), tag.c_str(),

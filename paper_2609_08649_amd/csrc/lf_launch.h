@@ -30,6 +30,7 @@ struct PointsSpec {
   const double* px;
   const double* py;
   long long P;
+  long long p0;            // grid: global index of point 0 (row chunks of a larger grid)
 };
 
 struct MapsOut {

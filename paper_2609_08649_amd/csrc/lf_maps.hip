@@ -141,7 +141,8 @@ static constexpr int NPART = 9;
 
 __device__ __forceinline__ void point_of(const PointsSpec& ps, long long p, double& x, double& y) {
   if (ps.grid) {
-    long long j = p / ps.nx, i = p - j * ps.nx;
+    long long q = p + ps.p0;
+    long long j = q / ps.nx, i = q - j * ps.nx;
     x = ps.x0 + ((double)i + 0.5) * ps.h;
     y = ps.y0 + ((double)j + 0.5) * ps.h;
   } else {

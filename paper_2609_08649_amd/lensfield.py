@@ -103,6 +103,12 @@ def lib():
             "lf_batch_run": (I32, [P, P]),
             "lf_batch_info": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
             "lf_batch_release": (I32, [P]),
+            "lf_serve_start": (I32, [P, P, PP]),
+            "lf_serve_submit": (I32, [P, P, C.POINTER(I64)]),
+            "lf_serve_poll": (I32, [P, I64, C.POINTER(I32), C.POINTER(D)]),
+            "lf_serve_wait": (I32, [P, I64, C.POINTER(I32), C.POINTER(D)]),
+            "lf_serve_stats": (I32, [P, I32, C.POINTER(I64), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
+            "lf_serve_stop": (I32, [P]),
             "lf_profile_read": (I32, [P, C.c_char_p, C.POINTER(D), C.POINTER(I64)]),
             "lf_profile_reset": (I32, [P]),
         }
@@ -438,4 +444,82 @@ class Batch:
     def release(self):
         if self.handle:
             lib().lf_batch_release(self.handle)
+            self.handle = None
+
+
+LF_REQ_CHI2, LF_REQ_MU_MAP, LF_REQ_SING_MAP = 0, 1, 2
+SING_PLANES = ("kappa", "detA", "e1", "e2", "f1", "f2")
+
+
+class lf_serve_config(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("n_streams", C.c_int32), ("max_batch_samples", C.c_int32),
+                ("map_chunk_rows", C.c_int32)]
+
+
+class lf_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("S", C.c_int32), ("model", C.c_void_p), ("cons", C.c_void_p),
+                ("params", C.c_void_p), ("mode", C.c_int32), ("prec", C.c_int32), ("grid", lf_grid),
+                ("a_dis", C.c_double), ("out_host", C.c_void_p), ("flags_host", C.c_void_p)]
+
+
+class Server:
+    """Continuous-batching server (C++ scheduler thread) on a context."""
+
+    def __init__(self, ctx, hbm_budget, n_streams=3, max_batch_samples=0, map_chunk_rows=0):
+        self.ctx = ctx
+        cfg = lf_serve_config(int(hbm_budget), int(n_streams), int(max_batch_samples), int(map_chunk_rows))
+        h = C.c_void_p()
+        ctx.check(lib().lf_serve_start(ctx.handle, C.byref(cfg), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def _submit(self, req, keep):
+        t = C.c_int64()
+        st = lib().lf_serve_submit(self.handle, C.byref(req), C.byref(t))
+        if st != LF_OK:
+            raise LfError(st, "submit rejected")
+        self._keep[t.value] = keep
+        return t.value
+
+    def submit_chi2(self, model, cons, params, mode=0, prec=LF_PREC_MIXED, out=None, flags=None):
+        """params: host float64 [S, n_free] (copied at submit).  Returns (ticket, chi2, flags) with
+        pinned host outputs that are valid once the ticket is done."""
+        p = np.ascontiguousarray(params, np.float64)
+        S = p.shape[0]
+        out = out if out is not None else torch.empty(S, dtype=torch.float64, pin_memory=True)
+        flags = flags if flags is not None else torch.empty(S, dtype=torch.int32, pin_memory=True)
+        req = lf_request(LF_REQ_CHI2, S, model.handle.value, cons.handle.value, p.ctypes.data if p.size else None,
+                         int(mode), int(prec), lf_grid(0, 0, 1, 1, 1), 1.0, out.data_ptr(), flags.data_ptr())
+        return self._submit(req, (p, out, flags)), out, flags
+
+    def submit_map(self, model, params, grid, a_dis, kind=LF_REQ_MU_MAP, prec=LF_PREC_MIXED, out=None):
+        planes = 6 if kind == LF_REQ_SING_MAP else 1
+        P = grid["nx"] * grid["ny"]
+        out = out if out is not None else torch.empty((planes, P), dtype=torch.float64, pin_memory=True)
+        p = np.ascontiguousarray(params, np.float64) if params is not None else None
+        req = lf_request(int(kind), 1, model.handle.value, None, p.ctypes.data if p is not None else None, 0, int(prec),
+                         lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"]), float(a_dis),
+                         out.data_ptr(), None)
+        return self._submit(req, (p, out)), out
+
+    def poll(self, ticket):
+        st, lat = C.c_int32(), C.c_double()
+        self.ctx.check(lib().lf_serve_poll(self.handle, int(ticket), C.byref(st), C.byref(lat)))
+        return st.value, lat.value
+
+    def wait(self, ticket):
+        st, lat = C.c_int32(), C.c_double()
+        self.ctx.check(lib().lf_serve_wait(self.handle, int(ticket), C.byref(st), C.byref(lat)))
+        self._keep.pop(ticket, None)
+        return st.value, lat.value
+
+    def stats(self, kind=-1):
+        n, p50, p99, mean = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        self.ctx.check(lib().lf_serve_stats(self.handle, int(kind), C.byref(n), C.byref(p50), C.byref(p99),
+                                            C.byref(mean)))
+        return {"count": n.value, "p50_ms": p50.value, "p99_ms": p99.value, "mean_ms": mean.value}
+
+    def stop(self):
+        if self.handle:
+            lib().lf_serve_stop(self.handle)
             self.handle = None
