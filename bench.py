@@ -272,7 +272,126 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
     for p in planes:
         p.release()
     torch.cuda.empty_cache()
+    out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
+    out["serving"] = bench_serving(ctx, lf, torch, W)
     return out
+
+
+def synthetic_cons(ctx, m):
+    a = np.array([ctx.adis(m["model"]["z_d"], z) for z in m["z_fam"]])
+    n = m["n_img"]
+    return {"theta": m["theta"], "family": m["family"], "sig1": np.full(n, 0.5), "sig2": np.full(n, 0.5),
+            "phi": np.zeros(n), "a_fam": a}
+
+
+def bench_batched(ctx, lf, torch, W, stream, timed):
+    """Uneven batch: 8 cluster models with 50-800 halos and 40-400 constraints, 512 walkers each."""
+    cfg = W.config3()
+    items, evals = [], 0
+    for mm in cfg["models"]:
+        mod = ctx.upload_model(mm["model"])
+        cons = ctx.upload_constraints(synthetic_cons(ctx, mm))
+        p = torch.as_tensor(mm["params"], device="cuda")
+        items.append((mod, cons, p, p.shape[0]))
+        evals += mod.n_halos * mm["n_img"] * p.shape[0]
+    S = sum(it[3] for it in items)
+    res = {"models": len(items), "samples": S, "halos": [it[0].n_halos for it in items],
+           "images": [it[1].n_img for it in items]}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        b = lf.Batch(ctx, items, 0, prec, autotune=True)
+        b.run(stream)
+        t = timed(lambda: b.run(stream), 10)
+        res[name] = {"graph_ms": t, "chi2_per_s": S / (t * 1e-3), "evals_per_s": evals / (t * 1e-3),
+                     "tile": b.info()}
+        b.release()
+        outs = {}
+
+        def seq():
+            for (mod, cons, p, Sm) in items:
+                ctx.chi2_batch(mod, p, Sm, cons, 0, prec, stream=stream)
+        seq()
+        t2 = timed(seq, 5)
+        res[name]["per_model_calls_ms"] = t2
+    for mod, cons, p, Sm in items:
+        cons.release()
+        mod.release()
+    return res
+
+
+def bench_serving(ctx, lf, torch, W, duration=4.0):
+    """Serving mix: Poisson arrivals, 80% chi^2 (S ~ U{1..256}) on 8 resident cluster models, 15%
+    2048^2 magnification maps, 5% 4096^2 singularity maps.  Closed-loop capacity C first, then
+    open-loop arrivals at 0.8 C; full budget and an 8 GB budget."""
+    import time as _t
+    models, conss, params = [], [], []
+    for k in range(8):
+        c2 = W.config2(seed=2620 + k, n_samples=256, grid_n=16)
+        mod = ctx.upload_model(c2["model"])
+        n = 150
+        fam = np.concatenate([np.repeat(np.arange(60), 2), np.arange(30)]).astype(np.int32)
+        rng = np.random.default_rng(k)
+        cons = {"theta": rng.uniform(-40, 40, (n, 2)), "family": fam, "sig1": np.full(n, 0.5),
+                "sig2": np.full(n, 0.5), "phi": np.zeros(n),
+                "a_fam": np.array([ctx.adis(0.5, z) for z in rng.uniform(1, 8, 60)])}
+        models.append(mod)
+        conss.append(ctx.upload_constraints(cons))
+        params.append(c2["params"])
+    g2 = {"x0": -100.0, "y0": -100.0, "h": 200.0 / 2048, "nx": 2048, "ny": 2048}
+    g4 = {"x0": -100.0, "y0": -100.0, "h": 200.0 / 4096, "nx": 4096, "ny": 4096}
+    mu_pool = [torch.empty((1, 2048 * 2048), dtype=torch.float64, pin_memory=True) for _ in range(8)]
+    sg_pool = [torch.empty((6, 4096 * 4096), dtype=torch.float64, pin_memory=True) for _ in range(3)]
+
+    def run(budget, reqs, rate_scale=None):
+        srv = lf.Server(ctx, budget, n_streams=3)
+        owner = {"mu": [None] * len(mu_pool), "sg": [None] * len(sg_pool)}
+        rr = {"mu": 0, "sg": 0}
+        tickets = []
+        n_chi2 = 0
+        t0 = _t.perf_counter()
+        for r in reqs:
+            if rate_scale is not None:
+                dt = r["t"] * rate_scale - (_t.perf_counter() - t0)
+                if dt > 0:
+                    _t.sleep(dt)
+            m = r["model"]
+            if r["kind"] == "chi2":
+                S = r["S"]
+                lo = r["seed"] % (256 - S + 1)
+                t, _, _ = srv.submit_chi2(models[m], conss[m], params[m][lo:lo + S], 0, lf.LF_PREC_MIXED)
+                n_chi2 += S
+            else:
+                key, pool, grid, kind = (("mu", mu_pool, g2, lf.LF_REQ_MU_MAP) if r["kind"] == "mu_map"
+                                         else ("sg", sg_pool, g4, lf.LF_REQ_SING_MAP))
+                i = rr[key] % len(pool)
+                rr[key] += 1
+                if owner[key][i] is not None:
+                    srv.wait(owner[key][i])          # output buffer reuse (back-pressure)
+                t, _ = srv.submit_map(models[m], params[m][0], grid, r["a_dis"], kind, lf.LF_PREC_MIXED,
+                                      out=pool[i])
+                owner[key][i] = t
+            tickets.append(t)
+        for t in tickets:
+            srv.wait(t)
+        el = _t.perf_counter() - t0
+        st = {"all": srv.stats(), "chi2": srv.stats(lf.LF_REQ_CHI2), "mu_map": srv.stats(lf.LF_REQ_MU_MAP),
+              "sing_map": srv.stats(lf.LF_REQ_SING_MAP)}
+        srv.stop()
+        return {"requests": len(reqs), "seconds": el, "req_per_s": len(reqs) / el, "chi2_per_s": n_chi2 / el,
+                "latency": st}
+
+    burst = W.config5_requests(seed=2614, rate=1e6, duration=400 / 1e6)[:150]
+    closed = run(64 << 30, burst)
+    C = closed["req_per_s"]
+    rate = 0.8 * C
+    reqs = W.config5_requests(seed=2615, rate=rate, duration=duration)
+    open_full = run(64 << 30, reqs, rate_scale=1.0)
+    open_8g = run(8 << 30, reqs, rate_scale=1.0)
+    for c in conss:
+        c.release()
+    for mm in models:
+        mm.release()
+    return {"closed_loop": closed, "open_loop_0.8C_budget64G": open_full, "open_loop_0.8C_budget8G": open_8g,
+            "offered_rate": rate}
 
 
 def cpu_baseline(model, cfg, cons, seconds):
