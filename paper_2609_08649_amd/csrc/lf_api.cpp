@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -184,6 +185,10 @@ extern "C" lf_status lf_init(lf_ctx** out, int32_t device, size_t hbm_budget_byt
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LF_E_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return LF_E_DEVICE;
   lf_ctx* c = new lf_ctx();
+  if (const char* e = getenv("LF_MAPS_PPL")) {
+    int v = atoi(e);
+    if (v == 1 || v == 2 || v == 4) c->ppl_override = v;
+  }
   c->device = device;
   size_t fr = 0, tot = 0;
   hipMemGetInfo(&fr, &tot);
@@ -222,7 +227,6 @@ extern "C" lf_status lf_shutdown(lf_ctx* ctx) {
   for (auto& kv : ctx->bufs) if (kv.second.ptr) hipFree(kv.second.ptr);
   if (ctx->quad_u) hipFree(ctx->quad_u);
   if (ctx->quad_w) hipFree(ctx->quad_w);
-  lf_release_extras(ctx);
   delete ctx;
   return LF_OK;
 }
@@ -368,10 +372,13 @@ extern "C" lf_status lf_model_upload(lf_ctx* ctx, const lf_component* mainc, int
     std::vector<lf::MemCat32> c32(M->mem.size());
     for (size_t i = 0; i < M->mem.size(); ++i) {
       const lf::MemCat& c = M->mem[i];
-      c32[i].x = c.x; c32[i].y = c.y;
+      c32[i].xh = (float)c.x; c32[i].xl = (float)(c.x - (double)c32[i].xh);
+      c32[i].yh = (float)c.y; c32[i].yl = (float)(c.y - (double)c32[i].yh);
       c32[i].fb = (float)c.fb; c32[i].fs = (float)c.fs; c32[i].fa = (float)c.fa;
       c32[i].q = (float)c.q; c32[i].c = (float)c.c; c32[i].sn = (float)c.sn;
-      c32[i].pad0 = c32[i].pad1 = 0.f;
+      const double fk = lf::NEAR_K * c.fb / c.q;
+      c32[i].fbk2 = (float)(fk * fk);
+      c32[i].pad1 = 0.f;
     }
     if (!c32.empty()) hipMemcpy(M->d_cat32, c32.data(), sizeof(lf::MemCat32) * c32.size(), hipMemcpyHostToDevice);
   }
@@ -452,6 +459,15 @@ lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params,
   hipError_t he = lf::launch_expand(lf_dev_model(M), params, S, *mains, *muls, *m32, *m64, st);
   ctx->prof_end(st);
   return ctx->hip(he, "expand");
+}
+
+// Points per lane of the lean maps kernel: one by default (measured fastest on gfx950 once the
+// FP64 near-field branch is in the member loop: it costs registers, and occupancy wins over
+// sharing a member record between points).  LF_MAPS_PPL = 2 or 4 selects the multi-point
+// variants of the FP32 path without third derivatives.
+int lf_ctx::maps_ppl(bool mixed, bool d3) {
+  if (mixed && !d3) return ppl_override ? ppl_override : 1;
+  return 1;
 }
 
 // ------------------------------------------------------------------------------ lens maps

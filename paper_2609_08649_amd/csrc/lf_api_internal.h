@@ -25,7 +25,6 @@ struct lf_ctx {
   std::map<std::string, Buf> bufs;
   double* quad_u = nullptr;
   double* quad_w = nullptr;
-  void* extras = nullptr;     // autotuner / batch plans
   // kernel timing (HIP events on the launching stream)
   bool prof = false;
   hipStream_t cur_stream = nullptr;
@@ -42,6 +41,7 @@ struct lf_ctx {
   void* ws(const char* name, size_t bytes, hipStream_t st, lf_status* err);
   lf_status dmalloc(void** p, size_t bytes);
   void dfree(void* p, size_t bytes);
+  int ppl_override = 0;        // LF_MAPS_PPL (1, 2 or 4): points per lane of the lean maps kernel
   int maps_ppl(bool mixed, bool d3);
 };
 
@@ -81,5 +81,4 @@ bool lf_points_spec(const lf_points* p, lf::PointsSpec& s);
 lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params, int S, bool need_mem,
                            hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
                            lf::MemRec64** m64, const char* tag);
-void lf_release_extras(lf_ctx* ctx);
 void lf_prof_mark(void* ctx, const char* name, int end_flag);

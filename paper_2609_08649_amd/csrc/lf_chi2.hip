@@ -19,69 +19,120 @@ __device__ __forceinline__ void lane_point(const Chi2Args& A, long long g, int& 
   y = A.th[2 * i + 1];
 }
 
-// Member segment loop with per-lane multipliers (T = float: FP32 catalog; double: FP64).
-template <int SEG, class T, class Cat>
-__device__ __forceinline__ void seg_ls(const Cat* __restrict__ cat, int lo, int hi, double px, double py,
-                                       T bm, T sm, T am, Acc& acc, const Quad& qd) {
+// One catalog member scaled by the lane's multipliers, FP64; false on a singular centre.
+template <int SEG>
+__device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, double bm, double sm, double am,
+                                         const Quad& qd, Term<double>& t) {
+  using T = double;
+  T b = bm * c.fb, s = sm * c.fs, a = am * c.fa;
+  t.t111 = t.t112 = t.t122 = t.t222 = (T)0;
+  if constexpr (SEG == SEG_CPJE || SEG == SEG_CSIE) {
+    T r2 = fma(dx, dx, dy * dy);
+    if (s == (T)0 && r2 < (T)1e-24) return false;
+    T m, w, p = 0;
+    if constexpr (SEG == SEG_CPJE) pje_mw<false>(b, s, a, s * s, a * a, a - s, (a - s) * (a + s), r2, m, w, p);
+    else cored_mw<false>(b, s, s * s, r2, m, w, p);
+    radial<false>(dx, dy, m, w, p, t);
+  } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
+    if (s == (T)0 && dx == (T)0 && dy == (T)0) return false;
+    T q2 = c.q * c.q;
+    T e = sqrt((T)1 - q2);
+    epje<false>(dx, dy, c.c, c.sn, b * c.q / e, e, q2, s, a, SEG == SEG_EPJE, t);
+  } else if constexpr (SEG == SEG_POINT) {
+    if (dx == (T)0 && dy == (T)0) return false;
+    point_mass<false>(dx, dy, b, t);
+  } else if constexpr (SEG == SEG_NFW) {
+    if (dx == (T)0 && dy == (T)0) return false;
+    nfw_circ<false>(dx, dy, b, s, t);
+  } else {
+    if (dx == (T)0 && dy == (T)0) return false;
+    double xp = c.c * dx + c.sn * dy, yp = c.c * dy - c.sn * dx;
+    Term<double> pr;
+    enfw_prime(xp, yp, b, s, c.q, qd, pr);
+    rotate_back<false>(c.c, c.sn, pr, t);
+  }
+  return true;
+}
+
+// Member segment loop with per-lane multipliers, FP64 (MemCat, every segment).
+template <int SEG>
+__device__ __forceinline__ void seg_ls(const MemCat* __restrict__ cat, int lo, int hi, double px, double py,
+                                       double bm, double sm, double am, Acc& acc, const Quad& qd) {
   for (int h = lo; h < hi; ++h) {
-    const Cat c = cat[h];
-    T dx = (T)(px - c.x), dy = (T)(py - c.y);
-    T b = bm * (T)c.fb, s = sm * (T)c.fs, a = am * (T)c.fa;
-    Term<T> t;
-    t.t111 = t.t112 = t.t122 = t.t222 = (T)0;
-    if constexpr (SEG == SEG_CPJE || SEG == SEG_CSIE) {
-      T r2 = fma(dx, dx, dy * dy);
-      if (s == (T)0 && r2 < (T)1e-24) { acc.flags |= FL_SINGULAR; continue; }
-      T m1, w1, p1 = 0;
-      cored_mw<false>(b, s, s * s, r2, m1, w1, p1);
-      if constexpr (SEG == SEG_CPJE) {
-        T m2, w2, p2 = 0;
-        cored_mw<false>(b, a, a * a, r2, m2, w2, p2);
-        m1 -= m2; w1 -= w2;
-      }
-      radial<false>(dx, dy, m1, w1, p1, t);
-    } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
-      if (s == (T)0 && dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
-      T q2 = (T)c.q * (T)c.q;
-      T e = sqrt((T)1 - q2);
-      epje<false>(dx, dy, (T)c.c, (T)c.sn, b * (T)c.q / e, e, q2, s, a, SEG == SEG_EPJE, t);
-    } else if constexpr (SEG == SEG_POINT) {
-      if (dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
-      point_mass<false>(dx, dy, b, t);
-    } else if constexpr (SEG == SEG_NFW) {
-      if (dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
-      nfw_circ<false>((double)dx, (double)dy, (double)b, (double)s, *(Term<double>*)&t);
-    } else {
-      if (dx == (T)0 && dy == (T)0) { acc.flags |= FL_SINGULAR; continue; }
-      double xp = c.c * dx + c.sn * dy, yp = c.c * dy - c.sn * dx;
-      Term<double> pr;
-      enfw_prime(xp, yp, (double)b, (double)s, c.q, qd, pr);
-      rotate_back<false>((double)c.c, (double)c.sn, pr, *(Term<double>*)&t);
-    }
-    add<false>(acc, t);
+    const MemCat c = cat[h];
+    Term<double> t;
+    if (cat_term<SEG>(c, px - c.x, py - c.y, bm, sm, am, qd, t)) add<false>(acc, t);
+    else acc.flags |= FL_SINGULAR;
   }
 }
 
-// The rare member segments (elliptical, point, NFW) in FP64.
+// The bulk circular segments in FP32 (MemCat32): offsets from FP32 pairs, terms summed in
+// FP32 over runs of 16 members and each run added to the FP64 accumulators (the same scheme
+// as the maps kernels).  A member closer than its near-field radius (NEAR_K b / q) is
+// evaluated from the FP64 catalog instead; its FP32 term is taken at r^2 = 1e30 (below 1e-14).
+template <int SEG>
+__device__ __forceinline__ void seg_ls32(const MemCat32* __restrict__ cat, const MemCat* __restrict__ cat64,
+                                         int lo, int hi, double px, double py, const MulRec& u, Acc& acc,
+                                         const Quad& qd) {
+  static_assert(SEG == SEG_CPJE || SEG == SEG_CSIE, "FP32 catalog path covers the circular segments");
+  constexpr int CHUNK = 16;
+  const float bm = (float)u.b, sm_ = (float)u.s, am = (float)u.a;
+  const float bm2 = bm * bm;
+  float xh = (float)px, xl = (float)(px - (double)xh);
+  float yh = (float)py, yl = (float)(py - (double)yh);
+  for (int h0 = lo; h0 < hi; h0 += CHUNK) {
+    const int h1 = min(h0 + CHUNK, hi);
+    float sx = 0.f, sy = 0.f, sm = 0.f, s11 = 0.f, s12 = 0.f, s22 = 0.f;
+    for (int h = h0; h < h1; ++h) {
+      const MemCat32 c = cat[h];
+      float dx = (xh - c.xh) + (xl - c.xl), dy = (yh - c.yh) + (yl - c.yl);
+      float b = bm * c.fb, s = sm_ * c.fs;
+      float r2 = fmaf(dx, dx, dy * dy);
+      const bool nr = r2 < bm2 * c.fbk2;
+      if (nr) r2 = 1e30f;
+      float m, w, p = 0.f;
+      if constexpr (SEG == SEG_CPJE) {
+        float a = am * c.fa;
+        float das = a - s;
+        pje_mw<false>(b, s, a, s * s, a * a, das, das * (a + s), r2, m, w, p);
+      } else {
+        cored_mw<false>(b, s, s * s, r2, m, w, p);
+      }
+      // psi_ij = sum(m) delta_ij + sum(w x_i x_j), alpha_i = sum(m x_i)
+      sx = fmaf(m, dx, sx); sy = fmaf(m, dy, sy); sm += m;
+      float wx = w * dx, wy = w * dy;
+      s11 = fmaf(wx, dx, s11); s12 = fmaf(wx, dy, s12); s22 = fmaf(wy, dy, s22);
+      if (nr) {
+        const MemCat q = cat64[h];
+        Term<double> t;
+        if (cat_term<SEG>(q, px - q.x, py - q.y, u.b, u.s, u.a, qd, t)) add<false>(acc, t);
+        else acc.flags |= FL_SINGULAR;
+      }
+    }
+    const double md = (double)sm;
+    acc.ax += (double)sx; acc.ay += (double)sy;
+    acc.h11 += md + (double)s11; acc.h12 += (double)s12; acc.h22 += md + (double)s22;
+  }
+}
+
 __device__ __forceinline__ void rare_members(const Chi2Args& A, double x, double y, const MulRec& u, Acc& acc) {
   const SegOff& so = A.m.seg;
-  seg_ls<SEG_EPJE, double>(A.m.mem, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
-  seg_ls<SEG_ESIE, double>(A.m.mem, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
-  seg_ls<SEG_POINT, double>(A.m.mem, so.off[SEG_POINT], so.off[SEG_POINT + 1], x, y, u.b, u.s, u.a, acc, A.qd);
-  seg_ls<SEG_NFW, double>(A.m.mem, so.off[SEG_NFW], so.off[SEG_NFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
-  seg_ls<SEG_ENFW, double>(A.m.mem, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_EPJE>(A.m.mem, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_ESIE>(A.m.mem, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_POINT>(A.m.mem, so.off[SEG_POINT], so.off[SEG_POINT + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_NFW>(A.m.mem, so.off[SEG_NFW], so.off[SEG_NFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+  seg_ls<SEG_ENFW>(A.m.mem, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
 }
 
 template <bool MIXED>
 __device__ __forceinline__ void bulk_members(const Chi2Args& A, double x, double y, const MulRec& u, Acc& acc) {
   const SegOff& so = A.m.seg;
   if (MIXED) {
-    float bm = (float)u.b, sm = (float)u.s, am = (float)u.a;
-    seg_ls<SEG_CPJE, float>(A.cat32, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, bm, sm, am, acc, A.qd);
-    seg_ls<SEG_CSIE, float>(A.cat32, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, bm, sm, am, acc, A.qd);
+    seg_ls32<SEG_CPJE>(A.cat32, A.m.mem, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, u, acc, A.qd);
+    seg_ls32<SEG_CSIE>(A.cat32, A.m.mem, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, u, acc, A.qd);
   } else {
-    seg_ls<SEG_CPJE, double>(A.m.mem, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
-    seg_ls<SEG_CSIE, double>(A.m.mem, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+    seg_ls<SEG_CPJE>(A.m.mem, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+    seg_ls<SEG_CSIE>(A.m.mem, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
   }
 }
 

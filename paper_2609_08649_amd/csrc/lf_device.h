@@ -15,12 +15,29 @@ enum { T_POINT = 0, T_SIS = 1, T_SIE = 2, T_PJE = 3, T_NFW = 4, T_ENFW = 5 };
 enum { FL_SINGULAR = 1, FL_GSING = 2, FL_NOCONV = 4, FL_REJECT = 8, FL_MERGED = 16,
        FL_OVERFLOW = 32, FL_UMBILIC = 64, FL_INVALID = 128 };
 
-// Reciprocal and reciprocal square root: the hardware instructions (1 ulp) in FP32,
-// correctly rounded sequences in FP64.
+// Reciprocal and reciprocal square root.  FP32: the hardware instructions (1 ulp).  FP64:
+// the hardware estimate refined by two Newton-Raphson steps (each doubles the number of
+// correct bits; the result is within about 1 ulp, not correctly rounded), several times
+// cheaper than the correctly rounded division and square-root sequences.  Arguments are
+// finite and positive (rsq) or finite and non-zero (rcp) wherever these are called.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double frcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double frsq(double x) {
+  // y <- y + y (1 - x y^2) / 2
+  double y = __builtin_amdgcn_rsq(x);
+  double hx = 0.5 * x;
+  double r = fma(-hx * y, y, 0.5);
+  y = fma(y, r, y);
+  r = fma(-hx * y, y, 0.5);
+  return fma(y, r, y);
+}
 __device__ __forceinline__ float fatan(float x) { return atanf(x); }
 __device__ __forceinline__ double fatan(double x) { return atan(x); }
 __device__ __forceinline__ float fatanh(float x) { return atanhf(x); }
@@ -78,14 +95,41 @@ __device__ __forceinline__ void cored_mw(T b, T s, T s2, T r2, T& m, T& w, T& wp
   if (D3) wp = (T)0.5 * b * wt * fma((T)2 * u, R, (T)1) * is * is;
 }
 
-// Circular pseudo-Jaffe (dPIE): cored(s) - cored(a).  Also the circular SIE when a_inf.
+// Circular pseudo-Jaffe (dPIE, Sec. 3.4): the cored term with core s minus the same with
+// core a > s, written without cancellation.  With R_c = sqrt(c^2 + r^2), D_c = R_c + c:
+//   dR = R_a - R_s = (a^2 - s^2) / (R_a + R_s),   dD = D_a - D_s = (a - s) + dR,
+//   m  = b/D_s - b/D_a = b dD / (D_s D_a),
+//   w  = -b/(D_s^2 R_s) + b/(D_a^2 R_a) = -b (D_a^2 dR + R_s dD (D_a + D_s)) / ((D_s D_a)^2 R_s R_a),
+// every term positive.  Subtracting two cored terms instead loses about log2(r/a) bits far
+// from the member, where both terms are ~ b/r and their difference ~ b (a - s)/r^2.
+// das = a - s and da2 = a^2 - s^2 are supplied by the caller.  w' (third derivatives only)
+// is the difference of the per-core derivatives b u^2 is^2 (u + is/2), u = 1/D, is = 1/R.
 template <bool D3, class T>
-__device__ __forceinline__ void cpje(T dx, T dy, T b, T s, T a, T s2, T a2, Term<T>& t) {
+__device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T das, T da2, T r2, T& m, T& w, T& wp) {
+  T Ss = s2 + r2, Sa = a2 + r2;
+  T is = frsq(Ss), ia = frsq(Sa);
+  T Rs = Ss * is, Ra = Sa * ia;
+  T Ds = Rs + s, Da = Ra + a;
+  T dR = da2 * frcp(Ra + Rs);
+  T dD = das + dR;
+  T iP = frcp(Ds * Da);
+  T bi = b * iP;
+  m = bi * dD;
+  T nw = fma(Da * Da, dR, Rs * dD * (Da + Ds));
+  w = -(bi * iP) * nw * (is * ia);
+  if (D3) {
+    T us = Da * iP, ua = Ds * iP;
+    T ps = us * us * is * is * fma((T)0.5, is, us);
+    T pa = ua * ua * ia * ia * fma((T)0.5, ia, ua);
+    wp = b * (ps - pa);
+  }
+}
+template <bool D3, class T>
+__device__ __forceinline__ void cpje(T dx, T dy, T b, T s, T a, T s2, T a2, T das, T da2, Term<T>& t) {
   T r2 = fma(dx, dx, dy * dy);
-  T m1, w1, p1 = 0, m2, w2, p2 = 0;
-  cored_mw<D3>(b, s, s2, r2, m1, w1, p1);
-  cored_mw<D3>(b, a, a2, r2, m2, w2, p2);
-  radial<D3>(dx, dy, m1 - m2, w1 - w2, p1 - p2, t);
+  T m, w, p = 0;
+  pje_mw<D3>(b, s, a, s2, a2, das, da2, r2, m, w, p);
+  radial<D3>(dx, dy, m, w, p, t);
 }
 template <bool D3, class T>
 __device__ __forceinline__ void csie(T dx, T dy, T b, T s, T s2, Term<T>& t) {
@@ -275,7 +319,7 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
       else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, false, t);
       break;
     case T_PJE:
-      if (r.q >= 1.0) cpje<D3>(dx, dy, r.b, r.s, r.a, r.s * r.s, r.a * r.a, t);
+      if (r.q >= 1.0) cpje<D3>(dx, dy, r.b, r.s, r.a, r.s * r.s, r.a * r.a, r.a - r.s, (r.a - r.s) * (r.a + r.s), t);
       else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t);
       break;
     case T_NFW: nfw_circ<D3>(dx, dy, r.b, r.s, t); break;

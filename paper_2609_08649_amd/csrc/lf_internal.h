@@ -37,10 +37,12 @@ struct MemCat {
   double x, y, fb, fs, fa, q, c, sn;
 };
 
-// FP32 copy of the member catalog (centre kept in FP64) for the per-lane scaled chi^2 path.
+// FP32 copy of the member catalog for the per-lane scaled chi^2 path.  The centre is kept
+// as an unevaluated FP32 pair (x = xh + xl to 48 bits) so that a point-centre offset can be
+// formed in FP32 with a relative error of a few ulp whatever the absolute coordinates.
 struct MemCat32 {
-  double x, y;
-  float fb, fs, fa, q, c, sn, pad0, pad1;
+  float xh, xl, yh, yl;
+  float fb, fs, fa, q, c, sn, fbk2, pad1;   // fbk2 = (NEAR_K fb / q)^2
 };
 
 // Per-sample member multipliers (b*, s*, a*) and sample validity flags.
@@ -49,14 +51,21 @@ struct MulRec {
   int32_t flags, pad;
 };
 
-// Pre-scaled member record for one sample.  FP32 flavour keeps the FP64 centre so that
-// the offset point - centre is formed exactly before rounding.
+// Near field of the FP32 member path: a member's term at a point closer than
+// NEAR_K * b / q (where the term's deformation exceeds about 1/NEAR_K, so FP32 rounding of the
+// term alone would exceed ~1e-7) is evaluated from the FP64 record instead.
+static constexpr double NEAR_K = 3.0;
+
+// Pre-scaled member record for one sample.  The FP32 flavour keeps the centre as an FP32
+// pair (as in MemCat32).  das = a - s and da2 = a^2 - s^2 are formed in FP64 before rounding
+// (they feed the cancellation-free dPIE form); rn2 is the squared near-field radius.
 struct MemRec32 {
-  double x, y;
-  float b, s, a, s2, a2, c, sn, q2, e, bqe, pad0, pad1;
+  float xh, xl, yh, yl;
+  float b, s, a, s2, a2, das, da2, rn2;   // the circular segments read these 12 words only
+  float c, sn, q2, e, bqe, pad0, pad1, pad2;
 };
 struct MemRec64 {
-  double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe;
+  double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, das, da2;
 };
 
 struct SegOff {          // member index range of each segment: [off[k], off[k+1])

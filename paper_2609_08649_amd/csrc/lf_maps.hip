@@ -98,19 +98,24 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
       double b = bm * c.fb, sc = sm * c.fs, a = am * c.fa;
       double q2 = c.q * c.q, e = sqrt(fmax(0.0, 1.0 - q2));
       double bqe = e > 0 ? b * c.q / e : 0.0;
+      const double das = a - sc, da2 = das * (a + sc);
       if (m64) {
         MemRec64 r;
         r.x = c.x; r.y = c.y; r.b = b; r.s = sc; r.a = a; r.s2 = sc * sc; r.a2 = a * a;
-        r.c = c.c; r.sn = c.sn; r.q2 = q2; r.e = e; r.bqe = bqe;
+        r.c = c.c; r.sn = c.sn; r.q2 = q2; r.e = e; r.bqe = bqe; r.das = das; r.da2 = da2;
         m64[(size_t)s * m.n_mem + i] = r;
       }
       if (m32) {
         MemRec32 r;
-        r.x = c.x; r.y = c.y;
+        r.xh = (float)c.x; r.xl = (float)(c.x - (double)r.xh);
+        r.yh = (float)c.y; r.yl = (float)(c.y - (double)r.yh);
         r.b = (float)b; r.s = (float)sc; r.a = (float)a;
         r.s2 = (float)(sc * sc); r.a2 = (float)(a * a);
         r.c = (float)c.c; r.sn = (float)c.sn; r.q2 = (float)q2; r.e = (float)e; r.bqe = (float)bqe;
-        r.pad0 = r.pad1 = 0.f;
+        r.das = (float)das; r.da2 = (float)da2;
+        const double rn = NEAR_K * b / c.q;
+        r.rn2 = (float)fmax(rn * rn, 1e-12);
+        r.pad0 = r.pad1 = r.pad2 = 0.f;
         m32[(size_t)s * m.n_mem + i] = r;
       }
     }
@@ -172,16 +177,16 @@ __global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
   const SegOff& so = A.m.seg;
   const size_t mo = (size_t)s * A.m.n_mem;
   if (MIXED) {
-    seg_loop<SEG_EPJE, D3, 1>(A.m32 + mo, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
-    seg_loop<SEG_ESIE, D3, 1>(A.m32 + mo, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
-    seg_loop<SEG_POINT, D3, 1>(A.m32 + mo, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
+    seg_loop<SEG_EPJE, D3, 1>(A.m32 + mo, A.m64 + mo, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_ESIE, D3, 1>(A.m32 + mo, A.m64 + mo, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_POINT, D3, 1>(A.m32 + mo, A.m64 + mo, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
   } else {
-    seg_loop<SEG_EPJE, D3, 1>(A.m64 + mo, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
-    seg_loop<SEG_ESIE, D3, 1>(A.m64 + mo, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
-    seg_loop<SEG_POINT, D3, 1>(A.m64 + mo, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
+    seg_loop<SEG_EPJE, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_ESIE, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_POINT, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
   }
-  seg_loop<SEG_NFW, D3, 1>(A.m64 + mo, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, acc, A.qd);
-  seg_loop<SEG_ENFW, false, 1>(A.m64 + mo, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
+  seg_loop<SEG_NFW, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, acc, A.qd);
+  seg_loop<SEG_ENFW, false, 1>(A.m64 + mo, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
   double* q = A.part + (size_t)s * NPART * P + p;
   q[0] = acc[0].ax; q[P] = acc[0].ay; q[2 * P] = acc[0].h11; q[3 * P] = acc[0].h12; q[4 * P] = acc[0].h22;
   if (D3) { q[5 * P] = acc[0].t111; q[6 * P] = acc[0].t112; q[7 * P] = acc[0].t122; q[8 * P] = acc[0].t222; }
@@ -212,11 +217,11 @@ __global__ __launch_bounds__(256) void k_maps(const MapsArgs A) {
   const SegOff& so = A.m.seg;
   const size_t mo = (size_t)s * A.m.n_mem;
   if (MIXED) {
-    seg_loop<SEG_CPJE, D3, PPL>(A.m32 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
-    seg_loop<SEG_CSIE, D3, PPL>(A.m32 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_CPJE, D3, PPL>(A.m32 + mo, A.m64 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_CSIE, D3, PPL>(A.m32 + mo, A.m64 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
   } else {
-    seg_loop<SEG_CPJE, D3, PPL>(A.m64 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
-    seg_loop<SEG_CSIE, D3, PPL>(A.m64 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_CPJE, D3, PPL>(A.m64 + mo, nullptr, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
+    seg_loop<SEG_CSIE, D3, PPL>(A.m64 + mo, nullptr, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
   }
   const MapsOut& o = A.out;
 #pragma unroll
