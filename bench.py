@@ -37,6 +37,78 @@ PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak [FLOP/s]
 F_CPJE = 39
 
 
+# Sources that define the lean maps kernel: a traffic measurement is reported only while
+# their hash matches the one recorded with the counters.
+MAPS_KERNEL_SOURCES = ("lf_maps.hip", "lf_segs.h", "lf_device.h", "lf_internal.h", "lf_launch.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "maps_lean_cluster2048_traffic.txt")
+COPY_PROBE_BYTES = 256 << 20
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in MAPS_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_08649_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per maps_lean launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the same counter reads for a plain copy of known size),
+    or None when the summary is missing or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def summarize_profiles(kind, dirs):
+    """Text summaries of rocprofv3 output (no GPU needed).  kind 'stats': the kernel statistics
+    CSV of --kernel-trace --stats; kind 'pmc': two --pmc runs (FETCH_SIZE dir, WRITE_SIZE dir)
+    of 'bench.py --copy-probe', calibrated on the copy of COPY_PROBE_BYTES."""
+    import csv
+    import glob
+    if kind == "stats":
+        path = glob.glob(os.path.join(dirs[0], "**", "*kernel_stats.csv"), recursive=True)[0]
+        rows = list(csv.DictReader(open(path)))
+        print("%-60s %7s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_ms", "pct"))
+        for r in rows:
+            print("%-60s %7s %12.2f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["AverageNs"]) / 1e3,
+                                                   float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+        return
+    vals = {}
+    for d, ctr in zip(dirs, ("FETCH_SIZE", "WRITE_SIZE")):
+        path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != ctr:
+                continue
+            key = (r["Kernel_Name"], r["Dispatch_Id"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        vals[ctr] = per
+    lean = "lf::k_maps<true, false, 1>"
+    out = {}
+    for ctr, per in vals.items():
+        lk = [v for (n, _), v in per.items() if lean in n]
+        # the probe's three copies are the largest copy-kernel dispatches of the run
+        cp = sorted((v for (n, _), v in per.items() if "copyBuffer" in n), reverse=True)[:3]
+        out[ctr] = (sum(lk) / len(lk), len(lk), sum(cp) / max(1, len(cp)), len(cp))
+        print("%s: maps_lean %.1f KiB per dispatch (%d dispatches); plain copy of %d MiB reads %.1f KiB "
+              "(%d dispatches)" % (ctr, out[ctr][0], out[ctr][1], COPY_PROBE_BYTES >> 20, out[ctr][2], out[ctr][3]))
+    ff = COPY_PROBE_BYTES / 1024 / out["FETCH_SIZE"][2]
+    fw = COPY_PROBE_BYTES / 1024 / out["WRITE_SIZE"][2]
+    rec = {"kernel": lean, "source_sha256": kernel_source_hash(),
+           "fetch_bytes_per_launch": out["FETCH_SIZE"][0] * 1024 * ff,
+           "write_bytes_per_launch": out["WRITE_SIZE"][0] * 1024 * fw,
+           "copy_factor_fetch": ff, "copy_factor_write": fw, "dispatches": out["FETCH_SIZE"][1]}
+    print(json.dumps(rec))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,6 +117,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the run, copy %d MiB device to device three times (counter calibration)"
+                    % (COPY_PROBE_BYTES >> 20))
+    ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
+                    help="print a summary of rocprofv3 output: 'stats DIR' or 'pmc FETCH_DIR WRITE_DIR'")
     return ap.parse_args()
 
 
@@ -89,6 +166,9 @@ def build_constraints(ctx, lf, torch, cfg, m, params_truth, W):
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize_profiles(args.summarize[0], args.summarize[1:])
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the design notes "
               "describe how the work would shard).", file=sys.stderr)
@@ -242,13 +322,19 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": "maps_lean", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR, "traffic": recorded_traffic(),
                      "avg_launch_ms": lean_ms, "flops_per_launch": flops_lean,
                      "flops_per_eval": F_CPJE, "evals_per_launch": n_mem * P},
         "extras": extras,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(res))
+    print(json.dumps(res), flush=True)
+    if args.copy_probe:
+        a = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     cons.release()
     m.release()
     ctx.close()

@@ -31,9 +31,11 @@
  *
  * Precision (lf_prec):
  *   LF_PREC_FP64  every step in IEEE double precision.
- *   LF_PREC_MIXED member-galaxy halo terms in FP32 accumulated in FP64; main halos,
- *                 beta, det A, mu, chi^2, triangle containment, Newton polishing and
- *                 the final multi-plane source positions in FP64.
+ *   LF_PREC_MIXED member-galaxy halo terms in FP32 (runs of 16 summed in FP32, then
+ *                 accumulated in FP64; a member closer than 3 b/q to the point in
+ *                 FP64); main halos, beta, det A, mu, chi^2, triangle containment,
+ *                 Newton solves and polishing and the final multi-plane source
+ *                 positions in FP64.
  */
 #ifndef LENSFIELD_H
 #define LENSFIELD_H
@@ -220,10 +222,10 @@ lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* m, const double* params, int
 /* Step a4: chi^2 per parameter sample (Sec. 3.1).  mode 0 = source plane, Eq. (chi2_src)
  * with the full magnification tensor mu_i = A^-1(theta_obs) and beta_model = G^-1 g;
  * mode 1 = image plane, Eq. (chi2_img), with each model image found by Newton-Raphson
- * from its observed position towards beta_model (Sec. 3.5; converged when an FP64 step is
- * below 1e-9", at most 20 steps; MIXED takes its first steps with FP32 member terms and
- * finishes in FP64; an image that does not converge, moves > 10 sigma or changes parity
- * keeps its source-plane term and is flagged).
+ * from its observed position towards beta_model (Sec. 3.5; FP64 steps in both precisions,
+ * MIXED affecting only the source-plane fit that sets beta_model; converged when a step is
+ * below 1e-9", at most 20 steps; an image that does not converge, moves > 10 sigma or
+ * changes parity keeps its source-plane term and is flagged).
  * params: device [S * n_free]; chi2: device [S]; flags: device [S] (or NULL).
  * beta_model: device [S * n_fam * 2] or NULL. */
 lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,

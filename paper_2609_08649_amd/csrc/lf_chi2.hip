@@ -262,12 +262,10 @@ __device__ void chi2_src_sample(const Chi2Args& A, int s) {
 }
 __global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) { chi2_src_sample(A, blockIdx.x); }
 
-// Image-plane chi^2: Newton from theta_obs towards beta_model, full halo sum per step.
-// MIXED: a lane takes steps with FP32 member terms until its step falls below 1e-5" (or 10
-// steps have run), then FP64 steps; convergence is always an FP64 step below newton_tol, the
-// rule of the FP64 path (at most 20 steps).  The switch is decided per lane, so an image's
-// result does not depend on the other images or samples sharing its wave.
-template <bool MIXED>
+// Image-plane chi^2: Newton from theta_obs towards beta_model, full halo sum per step, in
+// FP64 for both precisions (the source-plane part that sets beta_model follows the chosen
+// precision).  Converged when a step is below newton_tol, at most 20 steps.  Each lane's
+// sequence of steps depends only on its own image, so results do not depend on wave mates.
 __device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
   if (!active) g = (long long)A.S * A.n_img - 1;   // keep the lane in the wave's loop; no store
   int s, i;
@@ -281,14 +279,12 @@ __device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
   const MulRec u = A.muls[s];
   double tx = x0, ty = y0, det_last = det0;
   bool conv = false;
-  bool fine = !MIXED;         // this lane evaluates member terms in FP64
   for (int it = 0; it < 20; ++it) {
     Acc acc;
     acc.zero();
     for (int c = 0; c < A.m.n_main; ++c) eval_main<false>(mr[c], tx, ty, A.qd, acc);
     rare_members(A, tx, ty, u, acc);
-    if (fine) bulk_members<false>(A, tx, ty, u, acc);
-    else bulk_members<true>(A, tx, ty, u, acc);
+    bulk_members<false>(A, tx, ty, u, acc);
     if (!conv) {
       double rx = bmx - (tx - a * acc.ax), ry = bmy - (ty - a * acc.ay);
       double A11 = 1.0 - a * acc.h11, A12 = -a * acc.h12, A22 = 1.0 - a * acc.h22;
@@ -297,9 +293,7 @@ __device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
       double dx = (A22 * rx - A12 * ry) / det, dy = (-A12 * rx + A11 * ry) / det;
       tx += dx;
       ty += dy;
-      double step = sqrt(dx * dx + dy * dy);
-      if (fine && step < A.newton_tol) conv = true;
-      if (!fine && (step < 1e-5 || it >= 9)) fine = true;
+      if (sqrt(dx * dx + dy * dy) < A.newton_tol) conv = true;
     }
     if (__all(conv)) break;
   }
@@ -318,10 +312,9 @@ __device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
   A.iflags[g] = fl;
   if (A.tmod) { A.tmod[(size_t)g * 2] = tx; A.tmod[(size_t)g * 2 + 1] = ty; }
 }
-template <bool MIXED>
 __global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
   long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  chi2_newton_lane<MIXED>(A, g, g < (long long)A.S * A.n_img);
+  chi2_newton_lane(A, g, g < (long long)A.S * A.n_img);
 }
 
 __device__ void chi2_img_sample(const Chi2Args& A, int s) {
@@ -360,8 +353,7 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
   mark(ctx, "chi2_src", 1);
   if (mode == 1) {
     mark(ctx, "chi2_newton", 0);
-    if (mixed) hipLaunchKernelGGL(k_chi2_newton<true>, dim3(blocks), dim3(256), 0, st, A);
-    else hipLaunchKernelGGL(k_chi2_newton<false>, dim3(blocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_chi2_newton, dim3(blocks), dim3(256), 0, st, A);
     mark(ctx, "chi2_newton", 1);
     hipLaunchKernelGGL(k_chi2_img_sum, dim3(A.S), dim3(64), 0, st, A);
   }
@@ -410,7 +402,6 @@ __global__ __launch_bounds__(64) void k_batch_src(const BatchArgs B) {
   chi2_src_sample(B.items[B.samp_item[gs]], B.samp_local[gs]);
 }
 
-template <bool MIXED>
 __global__ void k_batch_newton(const BatchArgs B) {
   for (;;) {
     int t = next_tile(&B.counter[1]);
@@ -420,7 +411,7 @@ __global__ void k_batch_newton(const BatchArgs B) {
     // uniform trip count so that whole waves take part in the convergence votes
     for (long long base = T.g0; base < T.g1; base += blockDim.x) {
       long long g = base + threadIdx.x;
-      chi2_newton_lane<MIXED>(A, g, g < T.g1);
+      chi2_newton_lane(A, g, g < T.g1);
     }
   }
 }
@@ -444,8 +435,7 @@ hipError_t launch_batch(const BatchArgs& B, bool mixed, int mode, int block, int
   else hipLaunchKernelGGL(k_batch_lean<false>, dim3(grid_persist), dim3(block), 0, st, B);
   hipLaunchKernelGGL(k_batch_src, dim3(B.total_S), dim3(64), 0, st, B);
   if (mode == 1) {
-    if (mixed) hipLaunchKernelGGL(k_batch_newton<true>, dim3(grid_persist), dim3(block), 0, st, B);
-    else hipLaunchKernelGGL(k_batch_newton<false>, dim3(grid_persist), dim3(block), 0, st, B);
+    hipLaunchKernelGGL(k_batch_newton, dim3(grid_persist), dim3(block), 0, st, B);
     hipLaunchKernelGGL(k_batch_img, dim3(B.total_S), dim3(64), 0, st, B);
   }
   return hipGetLastError();
