@@ -120,6 +120,8 @@ extern "C" lf_status lf_batch_create(lf_ctx* ctx, const lf_batch_item* items, in
     const lf_batch_item& it = items[i];
     if (!it.model || !it.cons || !it.chi2 || it.S < 1 || (it.model->n_free > 0 && !it.params))
       return ctx->fail(LF_E_INVALID_ARG, "batch item %d: bad model/constraints/samples/output", i);
+    if (mode == 1 && (long long)it.S * it.cons->n_img >= (1LL << 31))
+      return ctx->fail(LF_E_INVALID_ARG, "batch item %d: image plane needs S * n_img < 2^31", i);
   }
   hipSetDevice(ctx->device);
   lf_batch* b = new lf_batch();
@@ -147,6 +149,8 @@ extern "C" lf_status lf_batch_create(lf_ctx* ctx, const lf_batch_item* items, in
     e = balloc(b, (void**)&A.cimg, sizeof(double) * n); if (e) break;
     e = balloc(b, (void**)&A.iflags, sizeof(int) * n); if (e) break;
     e = balloc(b, (void**)&A.bm_ws, sizeof(double) * S * c->n_fam * 2); if (e) break;
+    e = balloc(b, (void**)&A.strag_n, sizeof(int)); if (e) break;
+    A.n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
     A.m = lf_dev_model(M);
     A.mains = mains; A.muls = muls; A.cat32 = M->d_cat32;
     A.S = it.S; A.n_img = c->n_img; A.n_fam = c->n_fam;

@@ -100,6 +100,8 @@ lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, 
   A.cimg = wsd(".cimg", n); if (e) return e;
   A.iflags = wsi(".iflags", n); if (e) return e;
   A.bm_ws = wsd(".bm", (size_t)S * c->n_fam * 2); if (e) return e;
+  A.strag_n = wsi(".strag", 1); if (e) return e;
+  A.n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
   A.m = lf_dev_model(M);
   A.mains = mains; A.muls = muls; A.cat32 = M->d_cat32;
   A.S = S; A.n_img = c->n_img; A.n_fam = c->n_fam;
@@ -119,6 +121,8 @@ extern "C" lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* M, const double*
   if (S < 1) return ctx->fail(LF_E_INVALID_ARG, "S must be >= 1");
   if (M->n_free > 0 && !params) return ctx->fail(LF_E_INVALID_ARG, "model has free fields: params required");
   if (mode != 0 && mode != 1) return ctx->fail(LF_E_INVALID_ARG, "mode must be 0 (source) or 1 (image)");
+  if (mode == 1 && (long long)S * c->n_img >= (1LL << 31))
+    return ctx->fail(LF_E_INVALID_ARG, "image plane needs S * n_img < 2^31");
   if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
   hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;

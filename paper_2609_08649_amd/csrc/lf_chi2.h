@@ -31,6 +31,8 @@ struct Chi2Args {
   double* bmod;              // [S*n_fam*2] out (may be null)
   double* tmod;              // [S*n_img*2] model image positions (may be null)
   double newton_tol;
+  int* strag_n;              // [1] image-plane Newton: number of images left for round 2
+  int n_cu;                  // compute units (grid of the round-2 launch)
   Quad qd;
 };
 

@@ -88,7 +88,7 @@ __device__ __forceinline__ void seg_ls32(const MemCat32* __restrict__ cat, const
       float dx = (xh - c.xh) + (xl - c.xl), dy = (yh - c.yh) + (yl - c.yl);
       float b = bm * c.fb, s = sm_ * c.fs;
       float r2 = fmaf(dx, dx, dy * dy);
-      const bool nr = r2 < bm2 * c.fbk2;
+      const bool nr = r2 < fmaxf(bm2 * c.fbk2, 1e-12f);   // also catches r = 0 for b = 0
       if (nr) r2 = 1e30f;
       float m, w, p = 0.f;
       if constexpr (SEG == SEG_CPJE) {
@@ -264,58 +264,159 @@ __global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) { chi2_src_sa
 
 // Image-plane chi^2: Newton from theta_obs towards beta_model, full halo sum per step, in
 // FP64 for both precisions (the source-plane part that sets beta_model follows the chosen
-// precision).  Converged when a step is below newton_tol, at most 20 steps.  Each lane's
-// sequence of steps depends only on its own image, so results do not depend on wave mates.
-__device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
-  if (!active) g = (long long)A.S * A.n_img - 1;   // keep the lane in the wave's loop; no store
+// precision).  Converged when a step is below newton_tol, at most NEWTON_MAX steps.
+//
+// Two rounds.  Round 1 runs one lane per image for at most NEWTON_R1 steps.  An image still
+// unconverged then is appended to its item's straggler list (indices in pflags, state in
+// part: both are free once the source-plane reduction has run) and round 2 continues it with
+// one wave per image, the halo sum split over the 64 lanes -- so a few slow images no longer
+// hold whole waves for 20 steps.  Which round finishes an image depends only on that image,
+// so results do not depend on wave mates, tiles or batches.
+static constexpr int NEWTON_MAX = 20, NEWTON_R1 = 8;
+
+struct NewtonImg {
   int s, i;
-  double x0, y0;
-  lane_point(A, g, s, i, x0, y0);
-  const int f = A.fam[i];
-  const double a = A.afam[f];
-  const double bmx = A.bm_ws[((size_t)s * A.n_fam + f) * 2], bmy = A.bm_ws[((size_t)s * A.n_fam + f) * 2 + 1];
-  const double det0 = A.wimg[(size_t)g * 6 + 5];
-  const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
-  const MulRec u = A.muls[s];
-  double tx = x0, ty = y0, det_last = det0;
-  bool conv = false;
-  for (int it = 0; it < 20; ++it) {
-    Acc acc;
-    acc.zero();
-    for (int c = 0; c < A.m.n_main; ++c) eval_main<false>(mr[c], tx, ty, A.qd, acc);
-    rare_members(A, tx, ty, u, acc);
-    bulk_members<false>(A, tx, ty, u, acc);
-    if (!conv) {
-      double rx = bmx - (tx - a * acc.ax), ry = bmy - (ty - a * acc.ay);
-      double A11 = 1.0 - a * acc.h11, A12 = -a * acc.h12, A22 = 1.0 - a * acc.h22;
-      double det = A11 * A22 - A12 * A12;
-      det_last = det;
-      double dx = (A22 * rx - A12 * ry) / det, dy = (-A12 * rx + A11 * ry) / det;
-      tx += dx;
-      ty += dy;
-      if (sqrt(dx * dx + dy * dy) < A.newton_tol) conv = true;
-    }
-    if (__all(conv)) break;
-  }
-  if (!active) return;
-  double ox = x0 - tx, oy = y0 - ty;
-  bool reject = !(sqrt(ox * ox + oy * oy) <= 10.0 * A.sigmax[i]) || ((det_last > 0) != (det0 > 0));
+  double x0, y0, a, bmx, bmy, det0;
+};
+__device__ __forceinline__ void newton_img(const Chi2Args& A, long long g, NewtonImg& N) {
+  lane_point(A, g, N.s, N.i, N.x0, N.y0);
+  const int f = A.fam[N.i];
+  N.a = A.afam[f];
+  N.bmx = A.bm_ws[((size_t)N.s * A.n_fam + f) * 2];
+  N.bmy = A.bm_ws[((size_t)N.s * A.n_fam + f) * 2 + 1];
+  N.det0 = A.wimg[(size_t)g * 6 + 5];
+}
+// One Newton update from the halo sums at (tx, ty); true once a step is below newton_tol.
+__device__ __forceinline__ bool newton_update(const Chi2Args& A, const NewtonImg& N, const Acc& acc, double& tx,
+                                              double& ty, double& det_last) {
+  const double a = N.a;
+  double rx = N.bmx - (tx - a * acc.ax), ry = N.bmy - (ty - a * acc.ay);
+  double A11 = 1.0 - a * acc.h11, A12 = -a * acc.h12, A22 = 1.0 - a * acc.h22;
+  double det = A11 * A22 - A12 * A12;
+  det_last = det;
+  double dx = (A22 * rx - A12 * ry) / det, dy = (-A12 * rx + A11 * ry) / det;
+  tx += dx;
+  ty += dy;
+  return sqrt(dx * dx + dy * dy) < A.newton_tol;
+}
+__device__ __forceinline__ void newton_finish(const Chi2Args& A, long long g, const NewtonImg& N, bool conv,
+                                              double tx, double ty, double det_last) {
+  double ox = N.x0 - tx, oy = N.y0 - ty;
+  bool reject = !(sqrt(ox * ox + oy * oy) <= 10.0 * A.sigmax[N.i]) || ((det_last > 0) != (N.det0 > 0));
   int fl = (conv ? 0 : FL_NOCONV) | (reject ? FL_REJECT : 0);
   double c;
   if (!conv || reject) {
     c = A.csrc[g];
   } else {
-    const double* Si = A.sinv + 3 * i;
+    const double* Si = A.sinv + 3 * N.i;
     c = ox * (Si[0] * ox + Si[1] * oy) + oy * (Si[1] * ox + Si[2] * oy);
   }
   A.cimg[g] = c;
   A.iflags[g] = fl;
   if (A.tmod) { A.tmod[(size_t)g * 2] = tx; A.tmod[(size_t)g * 2 + 1] = ty; }
 }
+
+// Round 1 (every lane of the wave calls it; inactive lanes only take part in the votes).
+__device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
+  if (!active) g = (long long)A.S * A.n_img - 1;
+  NewtonImg N;
+  newton_img(A, g, N);
+  const MainRec* mr = A.mains + (size_t)N.s * A.m.n_main;
+  const MulRec u = A.muls[N.s];
+  double tx = N.x0, ty = N.y0, det_last = N.det0;
+  bool conv = false;
+  for (int it = 0; it < NEWTON_R1; ++it) {
+    Acc acc;
+    acc.zero();
+    for (int c = 0; c < A.m.n_main; ++c) eval_main<false>(mr[c], tx, ty, A.qd, acc);
+    rare_members(A, tx, ty, u, acc);
+    bulk_members<false>(A, tx, ty, u, acc);
+    if (!conv) conv = newton_update(A, N, acc, tx, ty, det_last);
+    if (__all(conv)) break;
+  }
+  const bool strag = active && !conv;
+  const unsigned long long mask = __ballot(strag);
+  if (mask) {
+    const int lane = threadIdx.x & 63, first = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == first) base = atomicAdd(A.strag_n, __popcll(mask));
+    base = __shfl(base, first, 64);
+    if (strag) {
+      A.pflags[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int)g;
+      double* st = A.part + (size_t)g * 5;
+      st[0] = tx; st[1] = ty; st[2] = det_last;
+    }
+  }
+  if (active && conv) newton_finish(A, g, N, true, tx, ty, det_last);
+}
 __global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
   long long g = (long long)blockIdx.x * 256 + threadIdx.x;
   chi2_newton_lane(A, g, g < (long long)A.S * A.n_img);
 }
+
+// Full FP64 halo sum of sample s at (x, y) by one wave: lane l takes halos l, l+64, ...; the
+// partial sums are combined by a butterfly of shuffles, after which every lane holds the same
+// bits.
+__device__ void chi2_sum_wave(const Chi2Args& A, int s, double x, double y, Acc& acc) {
+  const int lane = threadIdx.x & 63;
+  acc.zero();
+  const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
+  const MulRec u = A.muls[s];
+  const int nm = A.m.n_main, H = nm + A.m.n_mem;
+  for (int h = lane; h < H; h += 64) {
+    if (h < nm) {
+      eval_main<false>(mr[h], x, y, A.qd, acc);
+      continue;
+    }
+    const int m = h - nm;
+    int sg = 0;
+    while (sg + 1 < NSEG && m >= A.m.seg.off[sg + 1]) ++sg;
+    const MemCat c = A.m.mem[m];
+    const double dx = x - c.x, dy = y - c.y;
+    Term<double> t;
+    bool ok;
+    switch (sg) {
+      case SEG_CPJE: ok = cat_term<SEG_CPJE>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+      case SEG_EPJE: ok = cat_term<SEG_EPJE>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+      case SEG_CSIE: ok = cat_term<SEG_CSIE>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+      case SEG_ESIE: ok = cat_term<SEG_ESIE>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+      case SEG_POINT: ok = cat_term<SEG_POINT>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+      case SEG_NFW: ok = cat_term<SEG_NFW>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+      default: ok = cat_term<SEG_ENFW>(c, dx, dy, u.b, u.s, u.a, A.qd, t); break;
+    }
+    if (ok) add<false>(acc, t);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    acc.ax += __shfl_xor(acc.ax, o, 64);
+    acc.ay += __shfl_xor(acc.ay, o, 64);
+    acc.h11 += __shfl_xor(acc.h11, o, 64);
+    acc.h12 += __shfl_xor(acc.h12, o, 64);
+    acc.h22 += __shfl_xor(acc.h22, o, 64);
+  }
+}
+
+// Round 2: one wave per straggler image (g read from the item's list).
+__device__ void chi2_newton_wave(const Chi2Args& A, long long g) {
+  NewtonImg N;
+  newton_img(A, g, N);
+  const double* st = A.part + (size_t)g * 5;
+  double tx = st[0], ty = st[1], det_last = st[2];
+  bool conv = false;
+  for (int it = NEWTON_R1; it < NEWTON_MAX && !conv; ++it) {
+    Acc acc;
+    chi2_sum_wave(A, N.s, tx, ty, acc);
+    conv = newton_update(A, N, acc, tx, ty, det_last);
+  }
+  if ((threadIdx.x & 63) == 0) newton_finish(A, g, N, conv, tx, ty, det_last);
+}
+__device__ __forceinline__ void newton_round2(const Chi2Args& A) {
+  const int n = *A.strag_n;
+  const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nw = (int)((gridDim.x * blockDim.x) >> 6);
+  for (int j = w; j < n; j += nw) chi2_newton_wave(A, A.pflags[j]);
+}
+__global__ __launch_bounds__(256) void k_chi2_newton2(const Chi2Args A) { newton_round2(A); }
+__global__ void k_chi2_reset(int* p) { *p = 0; }
 
 __device__ void chi2_img_sample(const Chi2Args& A, int s) {
   const int lane = threadIdx.x & 63;
@@ -353,7 +454,9 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
   mark(ctx, "chi2_src", 1);
   if (mode == 1) {
     mark(ctx, "chi2_newton", 0);
+    hipLaunchKernelGGL(k_chi2_reset, dim3(1), dim3(1), 0, st, A.strag_n);
     hipLaunchKernelGGL(k_chi2_newton, dim3(blocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_chi2_newton2, dim3(A.n_cu * 4), dim3(256), 0, st, A);
     mark(ctx, "chi2_newton", 1);
     hipLaunchKernelGGL(k_chi2_img_sum, dim3(A.S), dim3(64), 0, st, A);
   }
@@ -366,11 +469,12 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
 // empty.  Every lane runs the same per-(sample, image) code as the single-item kernels, so a
 // sample's result is bit-identical whichever tile, workgroup or batch it lands in.
 // ---------------------------------------------------------------------------------------
-__global__ void k_batch_reset(int* counter) {
+__global__ void k_batch_reset(int* counter, const Chi2Args* items, int n_items) {
   if (threadIdx.x < 2) counter[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < n_items; i += blockDim.x) *items[i].strag_n = 0;
 }
 
-__global__ void k_batch_heavy(const BatchArgs B) {
+__global__ __launch_bounds__(256) void k_batch_heavy(const BatchArgs B) {
   for (int t = blockIdx.x; t < B.n_tiles; t += gridDim.x) {
     const BatchTile T = B.tiles[t];
     const Chi2Args& A = B.items[T.item];
@@ -387,7 +491,7 @@ __device__ __forceinline__ int next_tile(int* counter) {
 }
 
 template <bool MIXED>
-__global__ void k_batch_lean(const BatchArgs B) {
+__global__ __launch_bounds__(256) void k_batch_lean(const BatchArgs B) {
   for (;;) {
     int t = next_tile(&B.counter[0]);
     if (t >= B.n_tiles) break;
@@ -402,7 +506,7 @@ __global__ __launch_bounds__(64) void k_batch_src(const BatchArgs B) {
   chi2_src_sample(B.items[B.samp_item[gs]], B.samp_local[gs]);
 }
 
-__global__ void k_batch_newton(const BatchArgs B) {
+__global__ __launch_bounds__(256) void k_batch_newton(const BatchArgs B) {
   for (;;) {
     int t = next_tile(&B.counter[1]);
     if (t >= B.n_tiles) break;
@@ -416,26 +520,31 @@ __global__ void k_batch_newton(const BatchArgs B) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_batch_newton2(const BatchArgs B) {
+  for (int i = 0; i < B.n_items; ++i) newton_round2(B.items[i]);
+}
+
 __global__ __launch_bounds__(64) void k_batch_img(const BatchArgs B) {
   int gs = blockIdx.x;
   chi2_img_sample(B.items[B.samp_item[gs]], B.samp_local[gs]);
 }
 
 hipError_t launch_batch_lean_only(const BatchArgs& B, bool mixed, int block, int grid_persist, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.counter);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.counter, B.items, B.n_items);
   if (mixed) hipLaunchKernelGGL(k_batch_lean<true>, dim3(grid_persist), dim3(block), 0, st, B);
   else hipLaunchKernelGGL(k_batch_lean<false>, dim3(grid_persist), dim3(block), 0, st, B);
   return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs& B, bool mixed, int mode, int block, int grid_persist, hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.counter);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, B.counter, B.items, B.n_items);
   hipLaunchKernelGGL(k_batch_heavy, dim3(grid_persist), dim3(block), 0, st, B);
   if (mixed) hipLaunchKernelGGL(k_batch_lean<true>, dim3(grid_persist), dim3(block), 0, st, B);
   else hipLaunchKernelGGL(k_batch_lean<false>, dim3(grid_persist), dim3(block), 0, st, B);
   hipLaunchKernelGGL(k_batch_src, dim3(B.total_S), dim3(64), 0, st, B);
   if (mode == 1) {
     hipLaunchKernelGGL(k_batch_newton, dim3(grid_persist), dim3(block), 0, st, B);
+    hipLaunchKernelGGL(k_batch_newton2, dim3(grid_persist), dim3(256), 0, st, B);
     hipLaunchKernelGGL(k_batch_img, dim3(B.total_S), dim3(64), 0, st, B);
   }
   return hipGetLastError();

@@ -136,7 +136,7 @@ namespace {
 
 size_t chi2_footprint(const lf_request& r) {
   size_t S = r.S, n = S * r.cons->n_img;
-  return 256 * 12 + sizeof(double) * S * r.model->n_free + sizeof(double) * S + sizeof(int) * S +
+  return 256 * 13 + sizeof(int) + sizeof(double) * S * r.model->n_free + sizeof(double) * S + sizeof(int) * S +
          sizeof(lf::MainRec) * std::max<size_t>(1, S * r.model->main.size()) + sizeof(lf::MulRec) * S +
          sizeof(double) * n * (5 + 6 + 1 + 1) + sizeof(int) * n * 2 + sizeof(double) * S * r.cons->n_fam * 2;
 }
@@ -180,7 +180,9 @@ bool admit_chi2(lf_server* s, Req& q) {
   A.cimg = (double*)get(sizeof(double) * n);
   A.iflags = (int*)get(sizeof(int) * n);
   A.bm_ws = (double*)get(sizeof(double) * S * r.cons->n_fam * 2);
+  A.strag_n = (int*)get(sizeof(int));
   if (!ok) { give_back(s, q); return false; }
+  A.n_cu = s->ctx->n_cu > 0 ? s->ctx->n_cu : 256;
   A.m = lf_dev_model(r.model);
   A.cat32 = r.model->d_cat32;
   A.S = r.S; A.n_img = r.cons->n_img; A.n_fam = r.cons->n_fam;
@@ -466,6 +468,7 @@ extern "C" lf_status lf_serve_submit(lf_server* s, const lf_request* req, int64_
   q->r = r;
   if (r.kind == LF_REQ_CHI2) {
     if (!r.cons || r.S < 1 || (r.mode != 0 && r.mode != 1) || (r.model->n_free > 0 && !r.params)) return LF_E_INVALID_ARG;
+    if (r.mode == 1 && (long long)r.S * r.cons->n_img >= (1LL << 31)) return LF_E_INVALID_ARG;
     size_t tiles = ((size_t)r.S * r.cons->n_img + 255) / 256;
     if (sizeof(lf::Chi2Args) + sizeof(lf::BatchTile) * tiles + sizeof(int) * 2 * (size_t)r.S + 1024 > TABLE_BYTES)
       return LF_E_OUT_OF_BUDGET;
