@@ -39,7 +39,7 @@ struct Chi2Args {
 // Uneven batches: many (model, constraints, samples) items in one persistent launch.
 struct BatchTile {
   int item, pad;
-  long long g0, g1;          // lane range [g0, g1) of the item's (sample, image) pairs
+  long long g0, g1;          // thread range [g0, g1) of the item's (image, sample) pairs
 };
 struct BatchArgs {
   const Chi2Args* items;     // [n_items] (device)

@@ -1,8 +1,9 @@
 // chi^2 per parameter sample (step a4; Sec. 3.1 Eq. chi2_src / chi2_img, Sec. 3.5 Newton).
 //
-// Lanes run over the flattened (sample, image) pairs, so a wave is fully used whatever the
-// number of images; member records stay wave-uniform (one model per launch) and each lane
-// scales them by its own sample's multipliers (b*, s*, a*).  Family and sample reductions run
+// Lanes run over the flattened (image, sample) pairs, sample fastest, so a wave is fully used
+// whatever the number of images and mostly holds one image under many samples; member records
+// stay wave-uniform (one model per launch) and each lane scales them by its own sample's
+// multipliers (b*, s*, a*).  Family and sample reductions run
 // one wave per sample: a lane per family sums its images in order, a shuffle tree sums the
 // families -- a fixed order, so results are bit-reproducible and independent of batch mates.
 #include <hip/hip_runtime.h>
@@ -12,11 +13,19 @@
 
 namespace lf {
 
+// g indexes the per-(sample, image) buffers sample-major: g = s * n_img + i.
 __device__ __forceinline__ void lane_point(const Chi2Args& A, long long g, int& s, int& i, double& x, double& y) {
   s = (int)(g / A.n_img);
   i = (int)(g - (long long)s * A.n_img);
   x = A.th[2 * i];
   y = A.th[2 * i + 1];
+}
+// Threads run over (image, sample) pairs with the sample fastest: the lanes of a wave hold
+// the same observed image under up to 64 parameter samples, so they share the point, the
+// member offsets and the near-field decisions (no divergence), and converge alike in Newton.
+__device__ __forceinline__ long long lane_slot(const Chi2Args& A, long long t) {
+  const long long i = t / A.S, s = t - i * A.S;
+  return s * A.n_img + i;
 }
 
 // One catalog member scaled by the lane's multipliers, FP64; false on a singular centre.
@@ -124,15 +133,25 @@ __device__ __forceinline__ void rare_members(const Chi2Args& A, double x, double
   seg_ls<SEG_ENFW>(A.m.mem, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], x, y, u.b, u.s, u.a, acc, A.qd);
 }
 
+// The circular (bulk) segments, or the k-th of K equal member sub-ranges of each of them.
 template <bool MIXED>
-__device__ __forceinline__ void bulk_members(const Chi2Args& A, double x, double y, const MulRec& u, Acc& acc) {
+__device__ __forceinline__ void bulk_members(const Chi2Args& A, double x, double y, const MulRec& u, Acc& acc,
+                                             int k = 0, int K = 1) {
   const SegOff& so = A.m.seg;
+  auto part = [&](int sg, int& a, int& b) {
+    const int lo = so.off[sg], n = so.off[sg + 1] - lo;
+    a = lo + (int)((long long)n * k / K);
+    b = lo + (int)((long long)n * (k + 1) / K);
+  };
+  int a0, b0, a1, b1;
+  part(SEG_CPJE, a0, b0);
+  part(SEG_CSIE, a1, b1);
   if (MIXED) {
-    seg_ls32<SEG_CPJE>(A.cat32, A.m.mem, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, u, acc, A.qd);
-    seg_ls32<SEG_CSIE>(A.cat32, A.m.mem, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, u, acc, A.qd);
+    seg_ls32<SEG_CPJE>(A.cat32, A.m.mem, a0, b0, x, y, u, acc, A.qd);
+    seg_ls32<SEG_CSIE>(A.cat32, A.m.mem, a1, b1, x, y, u, acc, A.qd);
   } else {
-    seg_ls<SEG_CPJE>(A.m.mem, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
-    seg_ls<SEG_CSIE>(A.m.mem, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], x, y, u.b, u.s, u.a, acc, A.qd);
+    seg_ls<SEG_CPJE>(A.m.mem, a0, b0, x, y, u.b, u.s, u.a, acc, A.qd);
+    seg_ls<SEG_CSIE>(A.m.mem, a1, b1, x, y, u.b, u.s, u.a, acc, A.qd);
   }
 }
 
@@ -157,31 +176,62 @@ __device__ void chi2_heavy_lane(const Chi2Args& A, long long g) {
   A.pflags[g] = acc.flags;
 }
 __global__ __launch_bounds__(256) void k_chi2_heavy(const Chi2Args A) {
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (long long)A.S * A.n_img) return;
-  chi2_heavy_lane(A, g);
+  long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)A.S * A.n_img) return;
+  chi2_heavy_lane(A, lane_slot(A, t));
 }
 
-// Lean pass: circular members (the bulk), added to the partial sums.
+// Lean pass: circular members (the bulk), added to the partial sums.  One workgroup takes 64
+// (image, sample) threads; each image's members are split into CHI2_SPLIT equal sub-ranges
+// per segment and its W waves take sub-ranges k = wave, wave + W, ... (a wave's loop bounds
+// stay uniform, so member records remain scalar loads).  At one lane per image the pass is
+// latency-bound (a 1024 x 150 batch fills only ~2 waves per SIMD); the split multiplies the
+// waves by CHI2_SPLIT.  Sub-range sums meet in LDS and are added to the partial sums in the
+// order k = 0, 1, 2, 3 whatever W is, so an image's result never depends on the launch shape,
+// tile or batch.
+static constexpr int CHI2_SPLIT = 4;
+
 template <bool MIXED>
-__device__ void chi2_lean_lane(const Chi2Args& A, long long g) {
+__device__ void chi2_lean_group(const Chi2Args& A, long long u0, long long u_end) {
+  __shared__ double red[CHI2_SPLIT][5][64];
+  __shared__ int redf[CHI2_SPLIT][64];
+  // wave index made explicitly uniform, so that the member loops' bounds are scalar
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int W = blockDim.x >> 6;
+  const long long u = u0 + lane;
+  const bool active = u < u_end;
+  const long long g = lane_slot(A, active ? u : u_end - 1);
   int s, i;
   double x, y;
   lane_point(A, g, s, i, x, y);
-  Acc acc;
-  acc.zero();
-  double* q = A.part + (size_t)g * 5;
-  acc.ax = q[0]; acc.ay = q[1]; acc.h11 = q[2]; acc.h12 = q[3]; acc.h22 = q[4];
-  acc.flags = A.pflags[g];
-  bulk_members<MIXED>(A, x, y, A.muls[s], acc);
-  q[0] = acc.ax; q[1] = acc.ay; q[2] = acc.h11; q[3] = acc.h12; q[4] = acc.h22;
-  A.pflags[g] = acc.flags;
+  const MulRec mr = A.muls[s];
+  for (int k = wave; k < CHI2_SPLIT; k += W) {
+    Acc acc;
+    acc.zero();
+    bulk_members<MIXED>(A, x, y, mr, acc, k, CHI2_SPLIT);
+    red[k][0][lane] = acc.ax; red[k][1][lane] = acc.ay; red[k][2][lane] = acc.h11;
+    red[k][3][lane] = acc.h12; red[k][4][lane] = acc.h22; redf[k][lane] = acc.flags;
+  }
+  __syncthreads();
+  if (wave == 0 && active) {
+    double* q = A.part + (size_t)g * 5;
+    int fl = 0;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double t = red[0][c][lane];
+#pragma unroll
+      for (int k = 1; k < CHI2_SPLIT; ++k) t += red[k][c][lane];
+      q[c] += t;
+    }
+#pragma unroll
+    for (int k = 0; k < CHI2_SPLIT; ++k) fl |= redf[k][lane];
+    A.pflags[g] |= fl;
+  }
+  __syncthreads();
 }
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_chi2_lean(const Chi2Args A) {
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (long long)A.S * A.n_img) return;
-  chi2_lean_lane<MIXED>(A, g);
+  chi2_lean_group<MIXED>(A, (long long)blockIdx.x * 64, (long long)A.S * A.n_img);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -350,8 +400,9 @@ __device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
   if (active && conv) newton_finish(A, g, N, true, tx, ty, det_last);
 }
 __global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  chi2_newton_lane(A, g, g < (long long)A.S * A.n_img);
+  long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool active = t < (long long)A.S * A.n_img;
+  chi2_newton_lane(A, active ? lane_slot(A, t) : 0, active);
 }
 
 // Full FP64 halo sum of sample s at (x, y) by one wave: lane l takes halos l, l+64, ...; the
@@ -446,8 +497,9 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
   hipLaunchKernelGGL(k_chi2_heavy, dim3(blocks), dim3(256), 0, st, A);
   mark(ctx, "chi2_heavy", 1);
   mark(ctx, "chi2_lean", 0);
-  if (mixed) hipLaunchKernelGGL(k_chi2_lean<true>, dim3(blocks), dim3(256), 0, st, A);
-  else hipLaunchKernelGGL(k_chi2_lean<false>, dim3(blocks), dim3(256), 0, st, A);
+  const unsigned lean_blocks = (unsigned)((n + 63) / 64);
+  if (mixed) hipLaunchKernelGGL(k_chi2_lean<true>, dim3(lean_blocks), dim3(256), 0, st, A);
+  else hipLaunchKernelGGL(k_chi2_lean<false>, dim3(lean_blocks), dim3(256), 0, st, A);
   mark(ctx, "chi2_lean", 1);
   mark(ctx, "chi2_src", 0);
   hipLaunchKernelGGL(k_chi2_src, dim3(A.S), dim3(64), 0, st, A);
@@ -478,7 +530,7 @@ __global__ __launch_bounds__(256) void k_batch_heavy(const BatchArgs B) {
   for (int t = blockIdx.x; t < B.n_tiles; t += gridDim.x) {
     const BatchTile T = B.tiles[t];
     const Chi2Args& A = B.items[T.item];
-    for (long long g = T.g0 + threadIdx.x; g < T.g1; g += blockDim.x) chi2_heavy_lane(A, g);
+    for (long long t = T.g0 + threadIdx.x; t < T.g1; t += blockDim.x) chi2_heavy_lane(A, lane_slot(A, t));
   }
 }
 
@@ -497,7 +549,7 @@ __global__ __launch_bounds__(256) void k_batch_lean(const BatchArgs B) {
     if (t >= B.n_tiles) break;
     const BatchTile T = B.tiles[t];
     const Chi2Args& A = B.items[T.item];
-    for (long long g = T.g0 + threadIdx.x; g < T.g1; g += blockDim.x) chi2_lean_lane<MIXED>(A, g);
+    for (long long u0 = T.g0; u0 < T.g1; u0 += 64) chi2_lean_group<MIXED>(A, u0, T.g1);
   }
 }
 
@@ -514,8 +566,8 @@ __global__ __launch_bounds__(256) void k_batch_newton(const BatchArgs B) {
     const Chi2Args& A = B.items[T.item];
     // uniform trip count so that whole waves take part in the convergence votes
     for (long long base = T.g0; base < T.g1; base += blockDim.x) {
-      long long g = base + threadIdx.x;
-      chi2_newton_lane(A, g, g < T.g1);
+      const long long t = base + threadIdx.x;
+      chi2_newton_lane(A, t < T.g1 ? lane_slot(A, t) : 0, t < T.g1);
     }
   }
 }

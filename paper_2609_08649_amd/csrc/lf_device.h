@@ -43,7 +43,14 @@ __device__ __forceinline__ double fatan(double x) { return atan(x); }
 __device__ __forceinline__ float fatanh(float x) { return atanhf(x); }
 __device__ __forceinline__ double fatanh(double x) { return atanh(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+// FP64 square root from the refined reciprocal square root y: s = x y, corrected once by
+// s + (y/2)(x - s^2) (the residual taken with an FMA); x >= 0, finite.
+__device__ __forceinline__ double fsqrt(double x) {
+  const double y = frsq(x);
+  const double s = x * y;
+  const double r = fma(-s, s, x);
+  return x > 0.0 ? fma(0.5 * y, r, s) : 0.0;
+}
 
 // Per-point FP64 accumulators.
 struct Acc {
