@@ -289,7 +289,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(model, cfg, cons_np, args.cpu_seconds)
+        cpu = cpu_baseline(model, cfg, n_img, cons_np["family"], a_maps, args.cpu_seconds)
 
     res = {
         "metric": "halo x point lens evals/s (alpha+Jacobian)",
@@ -480,9 +480,13 @@ def bench_serving(ctx, lf, torch, W, duration=4.0):
             "offered_rate": rate}
 
 
-def cpu_baseline(model, cfg, cons, seconds):
-    """The FP64 oracle (as it stands) timed on a bounded sample of the same workload: maps at
-    random grid points and chi^2 of a subset of the samples, all host threads."""
+def cpu_baseline(model, cfg, n_img, family, a_maps, seconds):
+    """The FP64 oracle (as it stands, all host threads) timed on one whole step of the same
+    workload: maps at every point of the 2048^2 grid (fewer if that alone exceeds the time
+    budget), source-plane chi^2 of all 1024 samples, images of 60 sources on the 2048^2 grid.
+    Inputs come from the workload generator and the oracle only: constraint positions of the
+    same shape (chi^2 time does not depend on their values) and the generator's first 60
+    candidate sources at their own redshifts."""
     from oracle import oracle as orc
     from paper_2609_08649_amd import workloads as W
     tab = orc.expand(model, cfg["params"][0])
@@ -490,27 +494,37 @@ def cpu_baseline(model, cfg, cons, seconds):
     rng = np.random.default_rng(0)
     nth = orc.nthreads_default()
     H = tab.shape[0]
-    n = 2000
+    n = 20000
     while True:
         idx = rng.choice(x.size, n, replace=False)
         t0 = time.perf_counter()
-        orc.maps(tab, x[idx], y[idx], 0.6, nthreads=nth)
+        orc.maps(tab, x[idx], y[idx], a_maps, nthreads=nth)
         t_maps = time.perf_counter() - t0
-        if t_maps > seconds / 3 or n >= x.size:
+        if t_maps > seconds / 2 or n >= x.size:
             break
-        n = min(x.size, int(n * min(8.0, max(2.0, seconds / 3 / max(t_maps, 1e-3)))))
-    ns = 64
-    tabs = orc.expand_batch(model, cfg["params"][:ns])
+        n = min(x.size, int(n * min(8.0, max(2.0, seconds / 2 / max(t_maps, 1e-3)))))
+    S = cfg["params"].shape[0]
+    n_fam = int(family.max()) + 1
+    cons = {"theta": rng.uniform(-40.0, 40.0, (n_img, 2)), "family": family, "sig1": np.full(n_img, 0.5),
+            "sig2": np.full(n_img, 0.5), "phi": np.zeros(n_img),
+            "a_fam": np.array([orc.adis(model["z_d"], z) for z in cfg["zs_cand"][:n_fam]])}
+    tabs = orc.expand_batch(model, cfg["params"])
     t0 = time.perf_counter()
     orc.chi2_batch(tabs, cons, nthreads=nth)
     t_chi = time.perf_counter() - t0
-    n_img = cons["theta"].shape[0]
-    evals = n * H + ns * n_img * H
-    return {"value": evals / (t_maps + t_chi), "unit": "evals/s", "cores": nth, "kind": "oracle",
-            "chi2_per_s": ns / t_chi,
-            "sample": "%d random points of the 2048^2 maps workload (alpha, Hessian and third derivatives by "
-                      "AD) + source-plane chi^2 of %d of the 1024 samples x %d images; %d halos; %.1f s"
-                      % (n, ns, n_img, H, t_maps + t_chi)}
+    n_src = 60
+    a_src = np.array([orc.adis(model["z_d"], z) for z in cfg["zs_cand"][:n_src]])
+    t0 = time.perf_counter()
+    orc.find_images(tab, cfg["grid"], cfg["src_cand"][:n_src].copy(), a_src, nthreads=nth)
+    t_find = time.perf_counter() - t0
+    P = x.size
+    evals = n * H + S * n_img * H + P * H
+    t = t_maps + t_chi + t_find
+    return {"value": evals / t, "unit": "evals/s", "cores": nth, "kind": "oracle",
+            "chi2_per_s": S / t_chi, "seconds": {"maps": t_maps, "chi2": t_chi, "find": t_find},
+            "sample": "one step: maps at %d of the %d grid points (alpha, Hessian, third derivatives by AD), "
+                      "source-plane chi^2 of %d samples x %d images, images of %d sources on the 2048^2 grid; "
+                      "%d halos; %.1f s" % (n, P, S, n_img, n_src, H, t)}
 
 
 if __name__ == "__main__":

@@ -234,9 +234,48 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
       ax[p][k] = F.va[(size_t)(F.va_pstride * p) * P + v[k]];
       ay[p][k] = F.va[(size_t)(F.va_pstride * p + 1) * P + v[k]];
     }
+  // FP32 copies for the prefilter: a cell is tested in FP64 only when the source lies in the
+  // FP32 bounding box of its four mapped corners widened by eps plus a bound on the FP32
+  // rounding (inputs and FMAs, each <= 2^-24 of a magnitude <= R = |theta| + sum w |alpha| +
+  // |beta_s|, at most np + 3 of them per coordinate, taken with a factor 4).
+  float txf[4], tyf[4], axf[MP][4], ayf[MP][4], amax[MP];
+  float tmax = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    txf[k] = (float)tx[k]; tyf[k] = (float)ty[k];
+    tmax = fmaxf(tmax, fmaxf(fabsf(txf[k]), fabsf(tyf[k])));
+  }
+  for (int p = 0; p < np; ++p) {
+    amax[p] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      axf[p][k] = (float)ax[p][k]; ayf[p][k] = (float)ay[p][k];
+      amax[p] = fmaxf(amax[p], fmaxf(fabsf(axf[p][k]), fabsf(ayf[p][k])));
+    }
+  }
+  const float rel = 4.f * (float)(np + 3) * 5.9604645e-8f;   // 4 (np + 3) 2^-24
   const int lane = threadIdx.x & 63;
   for (int s = 0; s < F.n_src; ++s) {
     const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
+    {
+      const float sxf = (float)sx, syf = (float)sy;
+      float bxf[4], byf[4];
+      float R = tmax + fmaxf(fabsf(sxf), fabsf(syf));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { bxf[k] = txf[k]; byf[k] = tyf[k]; }
+      for (int p = 0; p < np; ++p) {
+        const float wf = (float)F.w[s * np + p];
+        R = fmaf(fabsf(wf), amax[p], R);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { bxf[k] = fmaf(-wf, axf[p][k], bxf[k]); byf[k] = fmaf(-wf, ayf[p][k], byf[k]); }
+      }
+      const float m = (float)F.eps + rel * R;
+      const bool in = valid && sxf >= fminf(fminf(bxf[0], bxf[1]), fminf(bxf[2], bxf[3])) - m &&
+                      sxf <= fmaxf(fmaxf(bxf[0], bxf[1]), fmaxf(bxf[2], bxf[3])) + m &&
+                      syf >= fminf(fminf(byf[0], byf[1]), fminf(byf[2], byf[3])) - m &&
+                      syf <= fmaxf(fmaxf(byf[0], byf[1]), fmaxf(byf[2], byf[3])) + m;
+      if (!__any(in)) continue;
+    }
     double bx[4], by[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) { bx[k] = tx[k]; by[k] = ty[k]; }
