@@ -5,7 +5,12 @@
 // budget is a hard bound.  chi^2 requests admitted while a batch is on the device form the
 // next batch (one persistent launch per (mode, precision)); map requests are cut into row
 // chunks that run on the other streams, so small chi^2 requests are not queued behind large
-// maps.  Completion is detected with events; latencies use the host steady clock.
+// maps.  Each chunk's rows are copied to the host right after they are computed.  A map is
+// bound to one map stream when its first chunk starts (its chunks stay in order there); a
+// free map stream runs the next chunk of the map with the least remaining work among its own
+// maps and the unbound ones (shortest remaining first at chunk granularity), so a small
+// magnification map overtakes a large singularity map between two of its chunks.
+// Completion is detected with events; latencies use the host steady clock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -86,8 +91,10 @@ struct Req {
   int n_planes = 0;
   long long P = 0;
   int next_row = 0;
+  int stream = -1;                         // map stream the map is bound to (-1: not started)
   bool expanded = false;
   size_t footprint = 0;
+  long long remaining() const { return (long long)(r.grid.ny - next_row) * r.grid.nx * n_planes; }
 };
 
 struct Unit {                               // work on the device, awaiting its event
@@ -97,7 +104,7 @@ struct Unit {                               // work on the device, awaiting its 
   std::vector<lf::Chi2Args> args;           // host sources of the batch tables, kept alive
   std::vector<lf::BatchTile> tiles;
   std::vector<int> samp;
-  bool map_chunk = false;
+  std::shared_ptr<Req> map;                 // map chunk: its request
   bool last_chunk = false;
 };
 
@@ -119,7 +126,7 @@ struct lf_server {
   int64_t next_id = 1;
   std::deque<std::shared_ptr<Req>> incoming, pending;
   std::vector<std::shared_ptr<Req>> admitted_chi2, maps_queue;
-  std::vector<std::shared_ptr<Req>> map_active;   // per map stream (index s - 1)
+  std::vector<std::shared_ptr<Req>> map_bound;    // started maps, each bound to one map stream
   std::vector<Unit> inflight;
   std::map<int64_t, std::shared_ptr<Req>> all;
   std::vector<hipEvent_t> ev_pool;
@@ -314,7 +321,8 @@ void launch_chi2_batch(lf_server* s) {
   s->inflight.push_back(u);
 }
 
-void launch_map_chunk(lf_server* s, int si, Req& q) {
+void launch_map_chunk(lf_server* s, int si, const std::shared_ptr<Req>& qp) {
+  Req& q = *qp;
   hipStream_t st = s->streams[si];
   const lf_request& r = q.r;
   if (!q.expanded) {
@@ -346,14 +354,16 @@ void launch_map_chunk(lf_server* s, int si, Req& q) {
   if (part) lf::launch_maps(dm, q.mains, q.m32, q.m64, 1, ps, r.a_dis, mixed, d3, o, lf_quad(s->ctx), ppl, part, 1, st);
   lf::launch_maps(dm, q.mains, q.m32, q.m64, 1, ps, r.a_dis, mixed, d3, o, lf_quad(s->ctx), ppl, part, 2, st);
   q.next_row += rows;
+  const size_t n = (size_t)rows * r.grid.nx;
+  for (int p = 0; p < q.n_planes; ++p)
+    hipMemcpyAsync((double*)r.out_host + p * q.P + off, q.d_out + p * q.P + off, sizeof(double) * n,
+                   hipMemcpyDeviceToHost, st);
+  if (r.flags_host)
+    hipMemcpyAsync((int*)r.flags_host + off, q.d_flags + off, sizeof(int) * n, hipMemcpyDeviceToHost, st);
   Unit u;
   u.stream = si;
-  u.map_chunk = true;
   u.last_chunk = q.next_row >= r.grid.ny;
-  if (u.last_chunk) {
-    hipMemcpyAsync(r.out_host, q.d_out, sizeof(double) * q.n_planes * q.P, hipMemcpyDeviceToHost, st);
-    if (r.flags_host) hipMemcpyAsync(r.flags_host, q.d_flags, sizeof(int) * q.P, hipMemcpyDeviceToHost, st);
-  }
+  u.map = qp;
   u.ev = s->ev();
   hipEventRecord(u.ev, st);
   s->busy[si] = true;
@@ -369,9 +379,7 @@ void lf_server::loop() {
       std::unique_lock<std::mutex> lk(mu);
       bool idle = inflight.empty() && incoming.empty() && pending.empty() && admitted_chi2.empty() &&
                   maps_queue.empty();
-      bool any_active = false;
-      for (auto& a : map_active) any_active = any_active || a;
-      if (idle && !any_active) {
+      if (idle && map_bound.empty()) {
         if (stop) break;
         cv.wait_for(lk, std::chrono::milliseconds(2));
       }
@@ -390,15 +398,14 @@ void lf_server::loop() {
         ev_pool.push_back(u.ev);
         busy[u.stream] = false;
         std::lock_guard<std::mutex> lk(mu);
-        if (!u.map_chunk) {
+        if (!u.map) {
           for (auto& q : u.reqs) {
             finish(this, *q, 1);
             admitted_chi2.erase(std::find(admitted_chi2.begin(), admitted_chi2.end(), q));
           }
         } else if (u.last_chunk) {
-          auto& q = map_active[u.stream - 1];
-          finish(this, *q, 1);
-          q.reset();
+          finish(this, *u.map, 1);
+          map_bound.erase(std::find(map_bound.begin(), map_bound.end(), u.map));
         }
         done_cv.notify_all();
         inflight.erase(inflight.begin() + k);
@@ -424,9 +431,20 @@ void lf_server::loop() {
     if (!busy[0]) launch_chi2_batch(this);
     for (int si = 1; si < (int)streams.size(); ++si) {
       if (busy[si]) continue;
-      auto& act = map_active[si - 1];
-      if (!act && !maps_queue.empty()) { act = maps_queue.front(); maps_queue.erase(maps_queue.begin()); }
-      if (act && act->next_row < act->r.grid.ny) { launch_map_chunk(this, si, *act); progressed = true; }
+      // shortest remaining work among this stream's unfinished maps and the unbound ones
+      std::shared_ptr<Req> best;
+      for (auto& q : map_bound)
+        if (q->stream == si && q->next_row < q->r.grid.ny && (!best || q->remaining() < best->remaining())) best = q;
+      for (auto& q : maps_queue)
+        if (!best || q->remaining() < best->remaining()) best = q;
+      if (!best) continue;
+      if (best->stream < 0) {
+        best->stream = si;
+        maps_queue.erase(std::find(maps_queue.begin(), maps_queue.end(), best));
+        map_bound.push_back(best);
+      }
+      launch_map_chunk(this, si, best);
+      progressed = true;
     }
     if (!progressed && !inflight.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
@@ -453,7 +471,6 @@ extern "C" lf_status lf_serve_start(lf_ctx* ctx, const lf_serve_config* cfg, lf_
   s->streams.resize(cfg->n_streams);
   for (auto& st : s->streams) hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   s->busy.assign(cfg->n_streams, false);
-  s->map_active.resize(cfg->n_streams - 1);
   s->th = std::thread([s]() { s->loop(); });
   *out = s;
   return LF_OK;
