@@ -230,7 +230,8 @@ __device__ __forceinline__ void epje(T dx, T dy, T c, T sn, T bqe, T e, T q2, T 
 // ---------------------------------------------------------------------------------------
 // NFW.  With X^2 = xi^2 / r_s^2 and z = 1 - X^2:  F = arccosh(1/X)/sqrt(1-X^2) (X < 1),
 // arccos(1/X)/sqrt(X^2-1) (X > 1); kappa = 2 k_s G(z), G = (F - 1)/z (series near z = 0).
-// Returns G and dG/dz.
+// Returns G and dG/dz.  For X < 1, arccosh(1/X) = log((1 + w)/X) = log((1 + w)^2 / X^2) / 2
+// with w = sqrt(z) >= 0.3 outside the series range: one logarithm, no cancellation.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& Gp) {
   double z = 1.0 - X2;
@@ -243,11 +244,17 @@ __device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& G
     Gp = gp;
     F = fma(G, z, 1.0);
   } else {
-    if (z > 0) { double w = sqrt(z); F = (log1p(w) - 0.5 * log(X2)) / w; }
-    else { double w = sqrt(-z); F = atan(w) / w; }
-    double iz = 1.0 / z;
+    const double iX2 = frcp(X2);
+    if (z > 0) {
+      const double w = fsqrt(z), w1 = 1.0 + w;
+      F = 0.5 * log(w1 * w1 * iX2) * frcp(w);
+    } else {
+      const double w = fsqrt(-z);
+      F = atan(w) * frcp(w);
+    }
+    const double iz = frcp(z);
     G = (F - 1.0) * iz;
-    double Fp = 0.5 * (1.0 / X2 - F) * iz;
+    const double Fp = 0.5 * (iX2 - F) * iz;
     Gp = (Fp - G) * iz;
   }
 }
@@ -259,7 +266,7 @@ __device__ __forceinline__ void nfw_circ(double dx, double dy, double ks, double
   double X2 = r2 * irs2;
   double F, G, Gp;
   nfw_G(X2, F, G, Gp);
-  double ir2 = 1.0 / r2;
+  double ir2 = frcp(r2);
   double h = 0.5 * log(0.25 * X2) + F;
   double m = 4.0 * ks * rs * rs * h * ir2;
   double kap = 2.0 * ks * G;
@@ -288,13 +295,13 @@ __device__ __forceinline__ void enfw_prime(double xp, double yp, double ks, doub
   for (int i = 0; i < qd.n; ++i) {
     double u = qd.u[i], wq = qd.w[i];
     double W = fma(-e2, u, 1.0);
-    double iW = 1.0 / W;
+    double iW = frcp(W);
     double X2 = u * fma(yy, iW, xx) * irs2;
     double F, G, Gp;
     nfw_G(X2, F, G, Gp);
     double kap = 2.0 * ks * G;
     double ukp = -2.0 * ks * Gp * irs2 * u;
-    double f0 = wq * (1.0 / sqrt(W));
+    double f0 = wq * frsq(W);
     double f1 = f0 * iW, f2 = f1 * iW;
     J0 = fma(f0, kap, J0); J1 = fma(f1, kap, J1);
     K0 = fma(f0, ukp, K0); K1 = fma(f1, ukp, K1); K2 = fma(f2, ukp, K2);
