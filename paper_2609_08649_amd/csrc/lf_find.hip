@@ -473,6 +473,11 @@ __global__ __launch_bounds__(256) void k_mp_theta(const MPArgs M, int j) {
   M.ty[p] = y;
 }
 
+// Final pass of the multi-plane trace: per ray, the plane Jacobians A_j (recursion of Sec. 2.2)
+// and, per source redshift, beta and A.  NP > 0: the ray's 5 NP plane values are loaded into
+// registers once (independent loads, issued together) and reused for every source redshift;
+// NP = 0: any number of planes, values read where used.
+template <int NP>
 __global__ __launch_bounds__(256) void k_mp_final(const MPArgs M) {
   long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   if (p >= M.P) return;
@@ -485,14 +490,30 @@ __global__ __launch_bounds__(256) void k_mp_final(const MPArgs M) {
     x = M.px[p];
     y = M.py[p];
   }
-  const int N = M.n_planes;
-  double Am[4 * LF_MAX_PLANES];
-  for (int j = 0; j < N; ++j) {
+  constexpr int MP = NP > 0 ? NP : LF_MAX_PLANES;
+  const int N = NP > 0 ? NP : M.n_planes;
+  const double* __restrict__ al = M.al;
+  double v[NP > 0 ? 5 * NP : 1];
+  if constexpr (NP > 0) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) v[5 * j + c] = al[(size_t)(5 * j + c) * M.P + p];
+  }
+  auto val = [&](int j, int c) -> double {
+    if constexpr (NP > 0) return v[5 * j + c];
+    else return al[(size_t)(5 * j + c) * M.P + p];
+  };
+  double Am[4 * MP];
+#pragma unroll
+  for (int j = 0; j < MP; ++j) {
+    if (j >= N) break;
     double A11 = 1, A12 = 0, A21 = 0, A22 = 1;
-    for (int i = 0; i < j; ++i) {
-      double w = M.wij[i * LF_MAX_PLANES + j];
-      const double* q = M.al + (size_t)(5 * i) * M.P + p;
-      double h11 = q[2 * M.P], h12 = q[3 * M.P], h22 = q[4 * M.P];
+#pragma unroll
+    for (int i = 0; i < MP; ++i) {
+      if (i >= j) break;
+      const double w = M.wij[i * LF_MAX_PLANES + j];
+      const double h11 = val(i, 2), h12 = val(i, 3), h22 = val(i, 4);
       const double* Ai = &Am[4 * i];
       A11 -= w * (h11 * Ai[0] + h12 * Ai[2]); A12 -= w * (h11 * Ai[1] + h12 * Ai[3]);
       A21 -= w * (h12 * Ai[0] + h22 * Ai[2]); A22 -= w * (h12 * Ai[1] + h22 * Ai[3]);
@@ -501,11 +522,12 @@ __global__ __launch_bounds__(256) void k_mp_final(const MPArgs M) {
   }
   for (int k = 0; k < M.n_zs; ++k) {
     double bx = x, by = y, F11 = 1, F12 = 0, F21 = 0, F22 = 1;
-    for (int j = 0; j < N; ++j) {
-      double w = M.wjs[(size_t)k * LF_MAX_PLANES + j];
+#pragma unroll
+    for (int j = 0; j < MP; ++j) {
+      if (j >= N) break;
+      const double w = M.wjs[(size_t)k * LF_MAX_PLANES + j];
       if (w == 0.0) continue;
-      const double* q = M.al + (size_t)(5 * j) * M.P + p;
-      double ax = q[0], ay = q[M.P], h11 = q[2 * M.P], h12 = q[3 * M.P], h22 = q[4 * M.P];
+      const double ax = val(j, 0), ay = val(j, 1), h11 = val(j, 2), h12 = val(j, 3), h22 = val(j, 4);
       bx -= w * ax; by -= w * ay;
       const double* Aj = &Am[4 * j];
       F11 -= w * (h11 * Aj[0] + h12 * Aj[2]); F12 -= w * (h11 * Aj[1] + h12 * Aj[3]);
@@ -523,7 +545,14 @@ hipError_t launch_mp_theta(const MPArgs& M, int j, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_mp_final(const MPArgs& M, hipStream_t st) {
-  hipLaunchKernelGGL(k_mp_final, dim3((unsigned)((M.P + 255) / 256)), dim3(256), 0, st, M);
+  const dim3 g((unsigned)((M.P + 255) / 256)), b(256);
+  switch (M.n_planes) {
+    case 1: hipLaunchKernelGGL(k_mp_final<1>, g, b, 0, st, M); break;
+    case 2: hipLaunchKernelGGL(k_mp_final<2>, g, b, 0, st, M); break;
+    case 3: hipLaunchKernelGGL(k_mp_final<3>, g, b, 0, st, M); break;
+    case 4: hipLaunchKernelGGL(k_mp_final<4>, g, b, 0, st, M); break;
+    default: hipLaunchKernelGGL(k_mp_final<0>, g, b, 0, st, M); break;
+  }
   return hipGetLastError();
 }
 
