@@ -407,6 +407,10 @@ lf::DevModel lf_dev_model(const lf_model* M) {
   for (int k = 0; k < 3; ++k) d.mul[k] = M->mul[k];
   d.xc = M->xc;
   d.n_free = M->n_free;
+  d.has_enfw = lf_model_has_enfw(M) ? 1 : 0;
+  d.has_rare = 0;
+  for (int k : {lf::SEG_EPJE, lf::SEG_ESIE, lf::SEG_POINT, lf::SEG_NFW, lf::SEG_ENFW})
+    if (M->seg.off[k + 1] > M->seg.off[k]) d.has_rare = 1;
   return d;
 }
 

@@ -316,7 +316,10 @@ __device__ __forceinline__ void enfw_prime(double xp, double yp, double ks, doub
 // ---------------------------------------------------------------------------------------
 // One main component (FP64) at one point.
 // ---------------------------------------------------------------------------------------
-template <bool D3>
+// ENFW = false compiles the elliptical NFW quadrature out (a kernel variant for models without
+// elliptical NFW halos, which then needs far fewer registers); such a halo reaching it is
+// flagged invalid.
+template <bool D3, bool ENFW = true>
 __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py, const Quad& qd, Acc& acc) {
   double dx = px - r.x, dy = py - r.y;
   double r2 = fma(dx, dx, dy * dy);
@@ -339,11 +342,14 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
     case T_NFW: nfw_circ<D3>(dx, dy, r.b, r.s, t); break;
     default:
       if (r.q >= 1.0) nfw_circ<D3>(dx, dy, r.b, r.s, t);
-      else {
+      else if constexpr (ENFW) {
         double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
         Term<double> p;
         enfw_prime(xp, yp, r.b, r.s, r.q, qd, p);
         rotate_back<false>(r.c, r.sn, p, t);
+      } else {
+        acc.flags |= FL_INVALID;
+        return;
       }
       break;
   }

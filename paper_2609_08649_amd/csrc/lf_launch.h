@@ -15,6 +15,8 @@ struct DevModel {          // device view of a resident model
   Bind mul[3];             // bmul, smul, amul
   XfConst xc;
   int n_free;
+  int has_enfw;            // an elliptical NFW main component or member (selects kernel variants)
+  int has_rare;            // members outside the circular segments
 };
 
 struct QuadTab {           // eNFW quadrature nodes (device)

@@ -158,8 +158,12 @@ __device__ __forceinline__ void point_of(const PointsSpec& ps, long long p, doub
 
 // Heavy pass: main components (FP64) and the rare member segments (elliptical, point,
 // NFW) whose closed forms need many registers; writes partial sums per point.
-template <bool MIXED, bool D3>
+// KIND: 0 = any model; 1 = no elliptical NFW; 2 = main components only (no rare member
+// segments) and no elliptical NFW -- variants for the common cluster model, which then needs
+// fewer registers (more waves per SIMD hide the FP64 latency).
+template <bool MIXED, bool D3, int KIND>
 __global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
+  constexpr bool ENFW = KIND == 0, RARE = KIND < 2;
   const int s = blockIdx.y;
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long P = A.pts.P;
@@ -171,12 +175,13 @@ __global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
   const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
   for (int c = 0; c < A.m.n_main; ++c) {
     const MainRec r = mr[c];
-    eval_main<D3>(r, px[0], py[0], A.qd, acc[0]);
+    eval_main<D3, ENFW>(r, px[0], py[0], A.qd, acc[0]);
     acc[0].flags |= r.flags;
   }
   const SegOff& so = A.m.seg;
   const size_t mo = (size_t)s * A.m.n_mem;
-  if (MIXED) {
+  if (!RARE) {
+  } else if (MIXED) {
     seg_loop<SEG_EPJE, D3, 1>(A.m32 + mo, A.m64 + mo, so.off[SEG_EPJE], so.off[SEG_EPJE + 1], px, py, acc, A.qd);
     seg_loop<SEG_ESIE, D3, 1>(A.m32 + mo, A.m64 + mo, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
     seg_loop<SEG_POINT, D3, 1>(A.m32 + mo, A.m64 + mo, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
@@ -185,8 +190,10 @@ __global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
     seg_loop<SEG_ESIE, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, acc, A.qd);
     seg_loop<SEG_POINT, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, acc, A.qd);
   }
-  seg_loop<SEG_NFW, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, acc, A.qd);
-  seg_loop<SEG_ENFW, false, 1>(A.m64 + mo, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
+  if constexpr (RARE)
+    seg_loop<SEG_NFW, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, acc, A.qd);
+  if constexpr (ENFW)
+    seg_loop<SEG_ENFW, false, 1>(A.m64 + mo, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
   double* q = A.part + (size_t)s * NPART * P + p;
   q[0] = acc[0].ax; q[P] = acc[0].ay; q[2 * P] = acc[0].h11; q[3 * P] = acc[0].h12; q[4 * P] = acc[0].h22;
   if (D3) { q[5 * P] = acc[0].t111; q[6 * P] = acc[0].t112; q[7 * P] = acc[0].t122; q[8 * P] = acc[0].t222; }
@@ -261,7 +268,9 @@ template <bool MIXED, bool D3, int PPL>
 static void launch_maps_t(const MapsArgs& a, int which, hipStream_t st) {
   if (which == 1) {
     dim3 g1((unsigned)((a.pts.P + 255) / 256), a.S);
-    hipLaunchKernelGGL((k_heavy<MIXED, D3>), g1, dim3(256), 0, st, a);
+    if (a.m.has_enfw) hipLaunchKernelGGL((k_heavy<MIXED, D3, 0>), g1, dim3(256), 0, st, a);
+    else if (a.m.has_rare) hipLaunchKernelGGL((k_heavy<MIXED, D3, 1>), g1, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_heavy<MIXED, D3, 2>), g1, dim3(256), 0, st, a);
     return;
   }
   long long per_block = 256LL * PPL;
