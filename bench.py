@@ -112,7 +112,7 @@ def summarize_profiles(kind, dirs):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -126,9 +126,10 @@ def parse():
 
 
 def build_constraints(ctx, lf, torch, cfg, m, params_truth, W):
-    """Image constraints from the GPU finder on the truth model: the first 60 candidate sources
-    with >= 2 observable images (|mu| >= 0.5), two images per family then extras up to 150,
-    plus the workload's seeded astrometric noise."""
+    """Image constraints from the GPU finder on the truth model: the first n_src candidate sources
+    with >= 2 observable images (|mu| >= 0.5), two images per family then extras up to n_img,
+    plus the workload's seeded astrometric noise (timing inputs only; parity tests build their
+    constraints with the oracle)."""
     grid = {"x0": -60.0, "y0": -60.0, "h": 0.125, "nx": 960, "ny": 960}
     srcs = []
     cand, zs = cfg["src_cand"], cfg["zs_cand"]
@@ -287,9 +288,10 @@ def main():
     if not args.no_extras:
         extras = bench_extras(ctx, lf, torch, W, stream, timed)
 
-    cpu = None
+    cpu, prec_rep = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(model, cfg, n_img, cons_np["family"], a_maps, args.cpu_seconds)
+        cpu, ref = cpu_baseline(model, cfg, n_img, cons_np["family"], a_maps, args.cpu_seconds)
+        prec_rep = precision_report(ctx, lf, torch, m, params, grid, a_maps, ref)
 
     res = {
         "metric": "halo x point lens evals/s (alpha+Jacobian)",
@@ -326,6 +328,7 @@ def main():
                      "avg_launch_ms": lean_ms, "flops_per_launch": flops_lean,
                      "flops_per_eval": F_CPJE, "evals_per_launch": n_mem * P},
         "extras": extras,
+        "precision_vs_oracle": prec_rep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
@@ -354,50 +357,100 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
         t = timed(lambda: ctx.multiplane_trace(planes, c4["z_planes"], c4["zs_maps"], c4["grid"], prec,
                                                stream=stream, outputs=("beta", "mu")), 2)
         res[name] = {"ms": t, "evals_per_s": H4 * P4 / (t * 1e-3)}
-    out["multiplane_4096"] = {"halos": H4, "rays": P4, "z_src": len(c4["zs_maps"]), **res}
+    n4 = c4["n_src"]
+    b4 = torch.as_tensor(c4["src_cand"][:n4], device="cuda")
+    z4 = np.asarray(c4["zs_cand"][:n4])
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        r = ctx.find_images_mp(planes, c4["z_planes"], b4, z4, c4["grid"], 16, prec, stream=stream)
+        t = timed(lambda: ctx.find_images_mp(planes, c4["z_planes"], b4, z4, c4["grid"], 16, prec, stream=stream), 2)
+        res[name]["find_ms"] = t
+        res[name]["find_images"] = int(r["count"].sum().item())
+    out["multiplane_4096"] = {"halos": H4, "rays": P4, "z_src": len(c4["zs_maps"]), "find_sources": n4, **res}
     for p in planes:
         p.release()
     torch.cuda.empty_cache()
+    out["config1_latency"] = bench_config1(ctx, lf, torch, W, stream)
     out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
     out["serving"] = bench_serving(ctx, lf, torch, W)
     return out
 
 
-def synthetic_cons(ctx, m):
-    a = np.array([ctx.adis(m["model"]["z_d"], z) for z in m["z_fam"]])
-    n = m["n_img"]
-    return {"theta": m["theta"], "family": m["family"], "sig1": np.full(n, 0.5), "sig2": np.full(n, 0.5),
-            "phi": np.zeros(n), "a_fam": a}
+def bench_config1(ctx, lf, torch, W, stream, n_calls=30):
+    """Small single plane (cored SIE + 10 truncated isothermals, 256^2 grid over 60", 5 sources at
+    z_s = 2): per-call latency (host launch to completion; median and p99 over n_calls) of the maps
+    (12 outputs), the finder and the image-plane chi^2 of one sample -- latency-bound sizes."""
+    import time as _t
+    cfg = W.config1()
+    m = ctx.upload_model(cfg["model"])
+    a = ctx.adis(cfg["model"]["z_d"], cfg["zs"])
+    n = cfg["n_src"]
+    beta = torch.as_tensor(cfg["src_cand"][:n], device="cuda")
+    asrc = torch.full((n,), a, dtype=torch.float64, device="cuda")
+    r = ctx.find_images(m, None, beta, asrc, cfg["grid"], 16, lf.LF_PREC_FP64)
+    cnt, th = r["count"].cpu().numpy(), r["theta"].cpu().numpy()
+    theta, fam = [], []
+    for k in range(n):
+        for t in th[k, :cnt[k]]:
+            theta.append(t); fam.append(k)
+    ni = len(theta)
+    theta = np.array(theta) + cfg["noise"][:ni]
+    cons = ctx.upload_constraints({"theta": theta, "family": np.array(fam, np.int32),
+                                   "sig1": np.full(ni, cfg["sigma_img"]), "sig2": np.full(ni, cfg["sigma_img"]),
+                                   "phi": np.zeros(ni), "a_fam": np.full(n, a)})
+
+    def lat(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n_calls):
+            t0 = _t.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((_t.perf_counter() - t0) * 1e3)
+        return {"p50_ms": float(np.percentile(ts, 50)), "p99_ms": float(np.percentile(ts, 99))}
+
+    out = {"halos": m.n_halos, "points": cfg["grid"]["nx"] * cfg["grid"]["ny"], "sources": n, "images": ni}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        out[name] = {"maps": lat(lambda: ctx.lens_maps(m, None, 1, cfg["grid"], a, prec, stream=stream)),
+                     "find": lat(lambda: ctx.find_images(m, None, beta, asrc, cfg["grid"], 16, prec, stream=stream)),
+                     "chi2_img": lat(lambda: ctx.chi2_batch(m, None, 1, cons, 1, prec, stream=stream))}
+    cons.release()
+    m.release()
+    return out
 
 
 def bench_batched(ctx, lf, torch, W, stream, timed):
-    """Uneven batch: 8 cluster models with 50-800 halos and 40-400 constraints, 512 walkers each."""
+    """Uneven batch: 8 cluster models with 50-800 halos and up to 40-400 image constraints (images
+    of each model's candidate sources found on the truth model, as for the cluster workload),
+    512 walkers each."""
     cfg = W.config3()
     items, evals = [], 0
     for mm in cfg["models"]:
         mod = ctx.upload_model(mm["model"])
-        cons = ctx.upload_constraints(synthetic_cons(ctx, mm))
+        truth = torch.as_tensor(mm["truth"][None], device="cuda")
+        cons_np, _ = build_constraints(ctx, lf, torch, dict(mm, n_src=mm["n_fam"]), mod, truth, W)
+        cons = ctx.upload_constraints(cons_np)
         p = torch.as_tensor(mm["params"], device="cuda")
         items.append((mod, cons, p, p.shape[0]))
-        evals += mod.n_halos * mm["n_img"] * p.shape[0]
+        evals += mod.n_halos * cons.n_img * p.shape[0]
     S = sum(it[3] for it in items)
     res = {"models": len(items), "samples": S, "halos": [it[0].n_halos for it in items],
            "images": [it[1].n_img for it in items]}
     for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
-        b = lf.Batch(ctx, items, 0, prec, autotune=True)
-        b.run(stream)
-        t = timed(lambda: b.run(stream), 10)
-        res[name] = {"graph_ms": t, "chi2_per_s": S / (t * 1e-3), "evals_per_s": evals / (t * 1e-3),
-                     "tile": b.info()}
-        b.release()
-        outs = {}
+        for mode, tag in ((0, ""), (1, "_img")):
+            b = lf.Batch(ctx, items, mode, prec, autotune=True)
+            b.run(stream)
+            t = timed(lambda: b.run(stream), 10 if mode == 0 else 3)
+            res[name + tag] = {"graph_ms": t, "chi2_per_s": S / (t * 1e-3), "tile": b.info()}
+            if mode == 0:
+                res[name]["evals_per_s"] = evals / (t * 1e-3)
+            b.release()
 
-        def seq():
-            for (mod, cons, p, Sm) in items:
-                ctx.chi2_batch(mod, p, Sm, cons, 0, prec, stream=stream)
-        seq()
-        t2 = timed(seq, 5)
-        res[name]["per_model_calls_ms"] = t2
+            def seq():
+                for (mod, cons, p, Sm) in items:
+                    ctx.chi2_batch(mod, p, Sm, cons, mode, prec, stream=stream)
+            seq()
+            res[name + tag]["per_model_calls_ms"] = timed(seq, 5 if mode == 0 else 2)
     for mod, cons, p, Sm in items:
         cons.release()
         mod.release()
@@ -406,8 +459,9 @@ def bench_batched(ctx, lf, torch, W, stream, timed):
 
 def bench_serving(ctx, lf, torch, W, duration=4.0):
     """Serving mix: Poisson arrivals, 80% chi^2 (S ~ U{1..256}) on 8 resident cluster models, 15%
-    2048^2 magnification maps, 5% 4096^2 singularity maps.  Closed-loop capacity C first, then
-    open-loop arrivals at 0.8 C; full budget and an 8 GB budget."""
+    2048^2 magnification maps, 5% 4096^2 singularity maps.  Closed-loop capacity C first (a burst
+    of 150 requests), then open-loop arrivals at 0.5 C, 0.8 C and 0.95 C for `duration` seconds
+    each with the full budget, and 0.8 C with an 8 GB budget."""
     import time as _t
     models, conss, params = [], [], []
     for k in range(8):
@@ -468,16 +522,17 @@ def bench_serving(ctx, lf, torch, W, duration=4.0):
     burst = W.config5_requests(seed=2614, rate=1e6, duration=400 / 1e6)[:150]
     closed = run(64 << 30, burst)
     C = closed["req_per_s"]
-    rate = 0.8 * C
-    reqs = W.config5_requests(seed=2615, rate=rate, duration=duration)
-    open_full = run(64 << 30, reqs, rate_scale=1.0)
-    open_8g = run(8 << 30, reqs, rate_scale=1.0)
+    out = {"closed_loop": closed, "capacity_req_per_s": C}
+    for frac in (0.5, 0.8, 0.95):
+        reqs = W.config5_requests(seed=2615, rate=frac * C, duration=duration)
+        out["open_loop_%gC_budget64G" % frac] = dict(run(64 << 30, reqs, rate_scale=1.0), offered_rate=frac * C)
+        if frac == 0.8:
+            out["open_loop_0.8C_budget8G"] = dict(run(8 << 30, reqs, rate_scale=1.0), offered_rate=frac * C)
     for c in conss:
         c.release()
     for mm in models:
         mm.release()
-    return {"closed_loop": closed, "open_loop_0.8C_budget64G": open_full, "open_loop_0.8C_budget8G": open_8g,
-            "offered_rate": rate}
+    return out
 
 
 def cpu_baseline(model, cfg, n_img, family, a_maps, seconds):
@@ -485,8 +540,8 @@ def cpu_baseline(model, cfg, n_img, family, a_maps, seconds):
     workload: maps at every point of the 2048^2 grid (fewer if that alone exceeds the time
     budget), source-plane chi^2 of all 1024 samples, images of 60 sources on the 2048^2 grid.
     Inputs come from the workload generator and the oracle only: constraint positions of the
-    same shape (chi^2 time does not depend on their values) and the generator's first 60
-    candidate sources at their own redshifts."""
+    same shape (random points with |mu| < 20 in the truth model; chi^2 time does not depend on
+    their values) and the generator's first 60 candidate sources at their own redshifts."""
     from oracle import oracle as orc
     from paper_2609_08649_amd import workloads as W
     tab = orc.expand(model, cfg["params"][0])
@@ -496,35 +551,104 @@ def cpu_baseline(model, cfg, n_img, family, a_maps, seconds):
     H = tab.shape[0]
     n = 20000
     while True:
-        idx = rng.choice(x.size, n, replace=False)
+        idx = np.sort(rng.choice(x.size, n, replace=False))
         t0 = time.perf_counter()
-        orc.maps(tab, x[idx], y[idx], a_maps, nthreads=nth)
+        o_maps = orc.maps(tab, x[idx], y[idx], a_maps, nthreads=nth)
         t_maps = time.perf_counter() - t0
         if t_maps > seconds / 2 or n >= x.size:
             break
         n = min(x.size, int(n * min(8.0, max(2.0, seconds / 2 / max(t_maps, 1e-3)))))
     S = cfg["params"].shape[0]
     n_fam = int(family.max()) + 1
-    cons = {"theta": rng.uniform(-40.0, 40.0, (n_img, 2)), "family": family, "sig1": np.full(n_img, 0.5),
-            "sig2": np.full(n_img, 0.5), "phi": np.zeros(n_img),
-            "a_fam": np.array([orc.adis(model["z_d"], z) for z in cfg["zs_cand"][:n_fam]])}
+    a_fam = np.array([orc.adis(model["z_d"], z) for z in cfg["zs_cand"][:n_fam]])
+    # constraint positions: random points where the truth model's |mu| < 20 at the family's
+    # distance ratio (away from critical curves, like observed images), taken in order
+    cand = rng.uniform(-40.0, 40.0, (20 * n_img, 2))
+    oc = orc.maps(tab, cand[:, 0], cand[:, 1], 1.0, nthreads=nth)
+    theta = []
+    for k in range(cand.shape[0]):
+        if len(theta) == n_img:
+            break
+        a = a_fam[family[len(theta)]]
+        det = (1 - a * oc["p11"][k]) * (1 - a * oc["p22"][k]) - (a * oc["p12"][k]) ** 2
+        if abs(det) > 0.05:
+            theta.append(cand[k])
+    cons = {"theta": np.array(theta), "family": family, "sig1": np.full(n_img, 0.5),
+            "sig2": np.full(n_img, 0.5), "phi": np.zeros(n_img), "a_fam": a_fam}
     tabs = orc.expand_batch(model, cfg["params"])
     t0 = time.perf_counter()
-    orc.chi2_batch(tabs, cons, nthreads=nth)
+    o_chi = orc.chi2_batch(tabs, cons, nthreads=nth)
     t_chi = time.perf_counter() - t0
     n_src = 60
     a_src = np.array([orc.adis(model["z_d"], z) for z in cfg["zs_cand"][:n_src]])
     t0 = time.perf_counter()
-    orc.find_images(tab, cfg["grid"], cfg["src_cand"][:n_src].copy(), a_src, nthreads=nth)
+    o_find = orc.find_images(tab, cfg["grid"], cfg["src_cand"][:n_src].copy(), a_src, nthreads=nth)
     t_find = time.perf_counter() - t0
     P = x.size
     evals = n * H + S * n_img * H + P * H
     t = t_maps + t_chi + t_find
-    return {"value": evals / t, "unit": "evals/s", "cores": nth, "kind": "oracle",
-            "chi2_per_s": S / t_chi, "seconds": {"maps": t_maps, "chi2": t_chi, "find": t_find},
-            "sample": "one step: maps at %d of the %d grid points (alpha, Hessian, third derivatives by AD), "
-                      "source-plane chi^2 of %d samples x %d images, images of %d sources on the 2048^2 grid; "
-                      "%d halos; %.1f s" % (n, P, S, n_img, n_src, H, t)}
+    res = {"value": evals / t, "unit": "evals/s", "cores": nth, "kind": "oracle",
+           "chi2_per_s": S / t_chi, "seconds": {"maps": t_maps, "chi2": t_chi, "find": t_find},
+           "sample": "one step: maps at %d of the %d grid points (alpha, Hessian, third derivatives by AD), "
+                     "source-plane chi^2 of %d samples x %d images, images of %d sources on the 2048^2 grid; "
+                     "%d halos; %.1f s" % (n, P, S, n_img, n_src, H, t)}
+    # conditioning of each sample's chi^2: the largest |mu| at its constraint positions (outside
+    # the timed region; W = mu^T S^-1 mu makes chi^2 as sensitive to det A as mu^2)
+    af = cons["a_fam"][family]
+    mu_max = np.zeros(S)
+    for k in range(S):
+        o = orc.maps(tabs[k], cons["theta"][:, 0], cons["theta"][:, 1], 1.0, nthreads=nth)
+        det = (1 - af * o["p11"]) * (1 - af * o["p22"]) - (af * o["p12"]) ** 2
+        mu_max[k] = np.max(1.0 / np.abs(det))
+    ref = {"idx": idx, "maps": o_maps, "cons": cons, "chi2": o_chi, "mu_max": mu_max, "find": o_find,
+           "src": cfg["src_cand"][:n_src], "a_src": a_src}
+    return res, ref
+
+
+def precision_report(ctx, lf, torch, m, params, grid, a_maps, ref):
+    """The MIXED path against the oracle outputs of the CPU-baseline run (same inputs): maps at
+    the sampled grid points, source-plane chi^2 of every sample, images of the 60 sources."""
+    dev = torch.device("cuda", 0)
+    g = ctx.lens_maps(m, params[:1].contiguous(), 1, grid, a_maps, lf.LF_PREC_MIXED,
+                      outputs=("alpha_x", "alpha_y", "mu"))
+    idx = torch.as_tensor(ref["idx"], device=dev)
+    ax, ay, mu = (g[k][0][idx].cpu().numpy() for k in ("alpha_x", "alpha_y", "mu"))
+    o = ref["maps"]
+    da = np.hypot(ax - o["ax"], ay - o["ay"])
+    sel = np.abs(o["mu"]) < 100
+    rmu = np.abs(mu[sel] - o["mu"][sel]) / np.abs(o["mu"][sel])
+    out = {"maps": {"points": int(idx.numel()), "max_dalpha": float(da.max()),
+                    "p999_dalpha": float(np.quantile(da, 0.999)), "max_rel_mu": float(rmu.max()),
+                    "p999_rel_mu": float(np.quantile(rmu, 0.999)), "limits": {"dalpha": 1e-5, "rel_mu": 1e-4}}}
+    cons = ctx.upload_constraints(ref["cons"])
+    c, fl, _ = ctx.chi2_batch(m, params, params.shape[0], cons, 0, lf.LF_PREC_MIXED)
+    c = c.cpu().numpy()
+    oc = ref["chi2"]["chi2_src"]
+    rel = np.abs(c - oc) / np.abs(oc)
+    well = ref["mu_max"] < 100
+    # jittered samples can still move a critical curve onto a constraint position
+    out["chi2_src"] = {"samples": int(c.size), "median_rel": float(np.median(rel)),
+                       "samples_all_mu_lt_100": int(well.sum()),
+                       "max_rel_all_mu_lt_100": float(rel[well].max()) if well.any() else None,
+                       "max_rel_any": float(rel.max()), "mu_max_at_worst": float(ref["mu_max"][np.argmax(rel)]),
+                       "limit": 1e-3}
+    cons.release()
+    n = ref["src"].shape[0]
+    r = ctx.find_images(m, params[:1].contiguous(), torch.as_tensor(ref["src"], device=dev),
+                        torch.as_tensor(ref["a_src"], device=dev), grid, 16, lf.LF_PREC_MIXED)
+    cnt, th = r["count"].cpu().numpy(), r["theta"].cpu().numpy()
+    of = ref["find"]
+    dth = 0.0
+    for k in range(n):
+        if cnt[k] == of["count"][k]:
+            for t in th[k, :cnt[k]]:
+                dth = max(dth, float(np.min(np.hypot(*(of["theta"][k, :cnt[k]] - t).T))))
+    # the generator's sources are not filtered for caustic margins here, so a count may differ
+    # where a source lies within the MIXED vertex error of a caustic
+    out["find"] = {"sources": n, "images": int(of["count"].sum()),
+                   "count_mismatches": int(np.sum(cnt != of["count"])), "max_dtheta": dth,
+                   "limits": {"dtheta": 1e-4}}
+    return out
 
 
 if __name__ == "__main__":

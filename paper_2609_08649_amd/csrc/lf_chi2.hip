@@ -319,10 +319,11 @@ __global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) { chi2_src_sa
 // Two rounds.  Round 1 runs one lane per image for at most NEWTON_R1 steps.  An image still
 // unconverged then is appended to its item's straggler list (indices in pflags, state in
 // part: both are free once the source-plane reduction has run) and round 2 continues it with
-// one wave per image, the halo sum split over the 64 lanes -- so a few slow images no longer
-// hold whole waves for 20 steps.  Which round finishes an image depends only on that image,
-// so results do not depend on wave mates, tiles or batches.
-static constexpr int NEWTON_MAX = 20, NEWTON_R1 = 8;
+// a group of NEWTON_G lanes per image, the halo sum split over the group -- so a few slow
+// images no longer hold whole waves for 20 steps, and many slow ones still fill the waves
+// (64 / NEWTON_G images per wave).  Which round finishes an image, and the group's summation
+// order, depend only on that image, so results do not depend on wave mates, tiles or batches.
+static constexpr int NEWTON_MAX = 20, NEWTON_R1 = 8, NEWTON_G = 8;
 
 struct NewtonImg {
   int s, i;
@@ -405,16 +406,16 @@ __global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
   chi2_newton_lane(A, active ? lane_slot(A, t) : 0, active);
 }
 
-// Full FP64 halo sum of sample s at (x, y) by one wave: lane l takes halos l, l+64, ...; the
-// partial sums are combined by a butterfly of shuffles, after which every lane holds the same
-// bits.
-__device__ void chi2_sum_wave(const Chi2Args& A, int s, double x, double y, Acc& acc) {
-  const int lane = threadIdx.x & 63;
+// Full FP64 halo sum of sample s at (x, y) by a group of NEWTON_G adjacent lanes: lane k of the
+// group takes halos k, k + G, ...; the partial sums are combined by a butterfly of shuffles
+// within the group, after which every lane of the group holds the same bits.
+__device__ void chi2_sum_group(const Chi2Args& A, int s, double x, double y, Acc& acc) {
+  const int k = threadIdx.x & (NEWTON_G - 1);
   acc.zero();
   const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
   const MulRec u = A.muls[s];
   const int nm = A.m.n_main, H = nm + A.m.n_mem;
-  for (int h = lane; h < H; h += 64) {
+  for (int h = k; h < H; h += NEWTON_G) {
     if (h < nm) {
       eval_main<false>(mr[h], x, y, A.qd, acc);
       continue;
@@ -438,7 +439,7 @@ __device__ void chi2_sum_wave(const Chi2Args& A, int s, double x, double y, Acc&
     if (ok) add<false>(acc, t);
   }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
+  for (int o = 1; o < NEWTON_G; o <<= 1) {
     acc.ax += __shfl_xor(acc.ax, o, 64);
     acc.ay += __shfl_xor(acc.ay, o, 64);
     acc.h11 += __shfl_xor(acc.h11, o, 64);
@@ -447,8 +448,10 @@ __device__ void chi2_sum_wave(const Chi2Args& A, int s, double x, double y, Acc&
   }
 }
 
-// Round 2: one wave per straggler image (g read from the item's list).
-__device__ void chi2_newton_wave(const Chi2Args& A, long long g) {
+// Round 2: one group of NEWTON_G lanes per straggler image (g read from the item's list).  The
+// lanes of a group always agree (same sums), so a group runs its loop as one; groups of a wave
+// may stop at different steps, and their shuffles never leave the group.
+__device__ void chi2_newton_group(const Chi2Args& A, long long g) {
   NewtonImg N;
   newton_img(A, g, N);
   const double* st = A.part + (size_t)g * 5;
@@ -456,15 +459,16 @@ __device__ void chi2_newton_wave(const Chi2Args& A, long long g) {
   bool conv = false;
   for (int it = NEWTON_R1; it < NEWTON_MAX && !conv; ++it) {
     Acc acc;
-    chi2_sum_wave(A, N.s, tx, ty, acc);
+    chi2_sum_group(A, N.s, tx, ty, acc);
     conv = newton_update(A, N, acc, tx, ty, det_last);
   }
-  if ((threadIdx.x & 63) == 0) newton_finish(A, g, N, conv, tx, ty, det_last);
+  if ((threadIdx.x & (NEWTON_G - 1)) == 0) newton_finish(A, g, N, conv, tx, ty, det_last);
 }
 __device__ __forceinline__ void newton_round2(const Chi2Args& A) {
   const int n = *A.strag_n;
-  const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), nw = (int)((gridDim.x * blockDim.x) >> 6);
-  for (int j = w; j < n; j += nw) chi2_newton_wave(A, A.pflags[j]);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int grp = (int)(t / NEWTON_G), ngrp = (int)((long long)gridDim.x * blockDim.x / NEWTON_G);
+  for (int j = grp; j < n; j += ngrp) chi2_newton_group(A, A.pflags[j]);
 }
 __global__ __launch_bounds__(256) void k_chi2_newton2(const Chi2Args A) { newton_round2(A); }
 __global__ void k_chi2_reset(int* p) { *p = 0; }
