@@ -18,6 +18,9 @@
 //   * Sec. 2.3 lens-equation solving (replaced here by triangle mapping with exact
 //     orientation predicates; accuracy O(h^2) before polishing).
 //   * Sec. 3.1 Eq. (chi2_img), Eq. (chi2_src), Eq. (delta), beta_model = G^-1 g.
+//   * Sec. 2.1 Eq. (time_delay) (Fermat potential, lensing potential psi without a_dis);
+//     Sec. 3.2 Eq. (chi2_flux), Eq. (msrc) and the linear magnification expansion;
+//     Sec. 3.3 Eq. (chi2_td), Eq. (dt0), Eq. (td_approx).
 //   * Sec. 3.4 Eq. (scaling) for member galaxies.
 //   * Sec. 3.5 Newton-Raphson image-plane solve started at the observed images.
 //   * Sec. 6 singularity maps (A3-line fields from third derivatives).
@@ -335,6 +338,91 @@ static int halo_sum_alpha(const double* tab, int H, double x, double y, double* 
 }
 
 // ----------------------------------------------------------------------------
+// Lensing potential psi (Sec. 2.1, defined without a_dis), one halo, FP64, each profile
+// up to its own additive constant (time delays only use differences within a family,
+// whose common offset is the fitted zero point).  Closed forms, textbook derivations:
+//   point mass  b^2 ln r;  SIS  b r;  circular cored  b (R - s ln(R + s)), R = sqrt(s^2 + r^2);
+//   elliptical cored SIE  x alpha_x + y alpha_y - b q s ln sqrt((psi~ + s)^2 + e^2 x^2)
+//     (halo frame, psi~ = sqrt(q^2 (s^2 + x^2) + y^2), e^2 = 1 - q^2);
+//   PJE = SIE(s) - SIE(a);  NFW  2 kappa_s r_s^2 h(X), h = ln^2(X/2) - arccosh^2(1/X) (X < 1),
+//     ln^2(X/2) + arccos^2(1/X) (X > 1);
+//   elliptical NFW  (q/2) int_0^1 xi(u) alpha_c(xi(u)) / (u sqrt(1 - e^2 u)) du with
+//     xi alpha_c(xi) = 4 kappa_s r_s^2 (ln(X/2) + F(X)), X = xi / r_s (the deflection of the
+//     circular profile with the same kappa), u = t^2.
+// Pinned in the tests by grad psi = alpha (central differences) for every profile.
+// ----------------------------------------------------------------------------
+static double sie_potential(double x, double y, double b, double q, double s) {
+  if (q >= 1.0) {
+    double R = std::sqrt(s * s + x * x + y * y);
+    return b * (R - (s > 0 ? s * std::log(R + s) : 0.0));
+  }
+  double e2 = 1 - q * q;
+  double psi = std::sqrt(q * q * (s * s + x * x) + y * y);
+  double ax, ay;
+  sie_alpha<double>(x, y, b, q, s, ax, ay);
+  double v = x * ax + y * ay;
+  if (s > 0) v -= b * q * s * 0.5 * std::log((psi + s) * (psi + s) + e2 * x * x);
+  return v;
+}
+// ln(X/2) + F(X) (the bracket of the circular NFW deflection)
+static double nfw_g(double X2) {
+  double F, G;
+  nfw_F<double>(1.0 - X2, F, G, X2);
+  return 0.5 * std::log(X2 / 4.0) + F;
+}
+static double nfw_potential(double r2, double ks, double rs) {
+  double X2 = r2 / (rs * rs);
+  double X = std::sqrt(X2);
+  double l = std::log(X / 2);
+  double h;
+  if (X < 1) { double ac = std::log((1 + std::sqrt(1 - X2)) / X); h = l * l - ac * ac; }
+  else { double ac = std::acos(1 / X); h = l * l + ac * ac; }
+  return 2 * ks * rs * rs * h;
+}
+static double enfw_potential(double x, double y, double ks, double rs, double q) {
+  double e2 = 1 - q * q;
+  std::function<void(double, double*)> f = [&](double t, double* o) {
+    if (t <= 0) { o[0] = 0; return; }
+    double u = t * t, w = 1 - e2 * u;
+    double xi2 = u * (x * x + y * y / w);
+    double xa = 4 * ks * rs * rs * nfw_g(xi2 / (rs * rs));
+    o[0] = xa * 2 * t / (u * std::sqrt(w));
+  };
+  double I[1];
+  integrate<double, 1>(f, 0.0, 1.0, 1e-13, I);
+  return 0.5 * q * I[0];
+}
+static double halo_potential(const double* row, double X, double Y, bool* singular) {
+  int type = (int)row[0];
+  double xc = row[1], yc = row[2], b = row[3], q = row[4], pa = row[5], s = row[6], a = row[7];
+  double dx = X - xc, dy = Y - yc;
+  double r2 = dx * dx + dy * dy;
+  bool singular_type = (type == POINT || type == SIS || type == NFW || type == ENFW ||
+                        ((type == SIE || type == PJE) && s == 0.0));
+  *singular = singular_type && r2 < 1e-24;
+  if (*singular) return 0.0;
+  if (type == POINT) return b * b * 0.5 * std::log(r2);
+  if (type == SIS) return b * std::sqrt(r2);
+  if (type == NFW) return nfw_potential(r2, b, s);
+  double c = std::cos(pa), sn = std::sin(pa);
+  double xp = c * dx + sn * dy, yp = -sn * dx + c * dy;
+  if (type == SIE) return sie_potential(xp, yp, b, q, s);
+  if (type == PJE) return sie_potential(xp, yp, b, q, s) - sie_potential(xp, yp, b, q, a);
+  if (q >= 1.0) return nfw_potential(r2, b, s);
+  return enfw_potential(xp, yp, b, s, q);
+}
+static int potential_sum(const double* tab, int H, double x, double y, double* pot) {
+  double acc = 0; int flags = 0;
+  for (int h = 0; h < H; ++h) {
+    bool sg;
+    acc += halo_potential(tab + 8 * h, x, y, &sg);
+    if (sg) flags |= F_SINGULAR;
+  }
+  *pot = acc;
+  return flags;
+}
+
+// ----------------------------------------------------------------------------
 // Halo-table expansion (Sec. 3.4 Eq. scaling; unit conversions).
 // ----------------------------------------------------------------------------
 enum { XF_NONE = 0, XF_SIGMA_TO_B = 1, XF_KPC = 2, XF_EPS_TO_Q = 3, XF_DEG = 4, XF_M200 = 5, XF_C200 = 6 };
@@ -620,15 +708,23 @@ static void sinv(double s1, double s2, double phi, double* S) {
   S[2] = s * s * i1 + c * c * i2;          // (1,1)
 }
 
+// Per-image quantities kept for the flux and time-delay terms.
+struct ImgInfo {
+  std::vector<double> h;    // [n][9] halo sums at theta_obs (alpha, psi_ij, psi_ijk)
+  std::vector<int> ok;      // image-plane solution converged and accepted
+};
+
 static int chi2_one(const double* tab, int H, const double* th, const int* fam, const double* s1,
                     const double* s2, const double* phi, int n, const double* afam, int n_fam,
                     int img_mode, double newton_tol, double* chi_src, double* chi_img,
-                    double* bmod, double* tmod) {
+                    double* bmod, double* tmod, ImgInfo* info = nullptr) {
   int flags = 0;
   std::vector<double> bo(2 * n), W(3 * n), detA0(n), csrc_i(n);
+  if (info) { info->h.assign(9 * n, 0.0); info->ok.assign(n, 0); }
   for (int i = 0; i < n; ++i) {
     double h[9];
     flags |= halo_sum(tab, H, th[2 * i], th[2 * i + 1], h);
+    if (info) std::copy(h, h + 9, info->h.begin() + 9 * i);
     double a = afam[fam[i]];
     bo[2 * i] = th[2 * i] - a * h[0]; bo[2 * i + 1] = th[2 * i + 1] - a * h[1];
     double A11 = 1 - a * h[2], A12 = -a * h[3], A22 = 1 - a * h[4];
@@ -715,10 +811,127 @@ static int chi2_one(const double* tab, int H, const double* th, const int* fam, 
       double S[3];
       sinv(s1[i], s2[i], phi[i], S);
       tot_img += ox * (S[0] * ox + S[1] * oy) + oy * (S[1] * ox + S[2] * oy);    // Eq. (chi2_img)
+      if (info) info->ok[i] = 1;
     }
   }
   *chi_img = tot_img;
   return flags;
+}
+
+// Flux and time-delay terms (Sec. 3.2, 3.3) of one halo table, after the position fit.
+// Per image i of family f (distance ratio a, time scale T = (1+z_d)/c D_d D_s/D_ds theta_0^2):
+//   mu = 1/det A(theta_obs); grad mu = -mu^2 grad det A (third derivatives);
+//   source plane (and images the image-plane solve did not accept):
+//     mu_model = mu + (A^-1 (beta_model - beta_obs)) . grad mu          (linear expansion),
+//     dt_model = T [|theta_obs - beta_obs|^2 / 2 - a psi(theta_obs)]
+//                + T (beta_model - beta_obs) . (beta_obs - theta_obs)   Eq. (td_approx);
+//   image plane (accepted images): mu_model = mu(theta_model),
+//     dt_model = T [|theta_model - beta_model|^2 / 2 - a psi(theta_model)]   Eq. (time_delay);
+//   per family: m_src by Eq. (msrc), chi2_f by Eq. (chi2_flux) (magnitudes: 2.5 log10 |mu|);
+//   dt_0 by Eq. (dt0), chi2_dt by Eq. (chi2_td).
+// An image enters a term only where its error (sig_mag, sig_dt) is positive.
+static int obs_terms(const double* tab, int H, const double* th, const int* fam, int n, const double* afam,
+                     int n_fam, const double* bmod, const double* tmod, const ImgInfo& I, int img_mode,
+                     const double* mag, const double* smag, const double* dt, const double* sdt,
+                     const double* tsc, double* chi_f, double* chi_t) {
+  int flags = 0;
+  std::vector<double> mval(n, 0.0), tval(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    bool want_f = mag && smag[i] > 0, want_t = dt && sdt[i] > 0;
+    if (!want_f && !want_t) continue;
+    int f = fam[i];
+    double a = afam[f];
+    const double* h = &I.h[9 * i];
+    double tx = th[2 * i], ty = th[2 * i + 1];
+    double bx = tx - a * h[0], by = ty - a * h[1];
+    double A11 = 1 - a * h[2], A12 = -a * h[3], A22 = 1 - a * h[4];
+    double det = A11 * A22 - A12 * A12, mu = 1 / det;
+    double dbx = bmod[2 * f] - bx, dby = bmod[2 * f + 1] - by;
+    double mu_m, t_m;
+    bool img = img_mode && I.ok[i];
+    if (img) {
+      double mx = tmod[2 * i], my = tmod[2 * i + 1];
+      double g[9], pot;
+      flags |= halo_sum(tab, H, mx, my, g);
+      flags |= potential_sum(tab, H, mx, my, &pot);
+      double B11 = 1 - a * g[2], B12 = -a * g[3], B22 = 1 - a * g[4];
+      mu_m = 1 / (B11 * B22 - B12 * B12);
+      double ex = mx - bmod[2 * f], ey = my - bmod[2 * f + 1];
+      t_m = want_t ? tsc[f] * (0.5 * (ex * ex + ey * ey) - a * pot) : 0.0;
+    } else {
+      double gdx = -a * (h[5] * A22 + A11 * h[7] - 2 * A12 * h[6]);
+      double gdy = -a * (h[6] * A22 + A11 * h[8] - 2 * A12 * h[7]);
+      double dthx = (A22 * dbx - A12 * dby) / det, dthy = (-A12 * dbx + A11 * dby) / det;
+      mu_m = mu - mu * mu * (dthx * gdx + dthy * gdy);
+      t_m = 0.0;
+      if (want_t) {
+        double pot;
+        flags |= potential_sum(tab, H, tx, ty, &pot);
+        double ex = tx - bx, ey = ty - by;
+        t_m = tsc[f] * (0.5 * (ex * ex + ey * ey) - a * pot) + tsc[f] * (dbx * (bx - tx) + dby * (by - ty));
+      }
+    }
+    if (want_f) mval[i] = mag[i] + 2.5 * std::log10(std::fabs(mu_m));
+    if (want_t) tval[i] = dt[i] - t_m;
+  }
+  double cf = 0, ct = 0;
+  for (int f = 0; f < n_fam; ++f) {
+    double wf = 0, sf = 0, wt = 0, st = 0;
+    for (int i = 0; i < n; ++i) {
+      if (fam[i] != f) continue;
+      if (mag && smag[i] > 0) { double w = 1 / (smag[i] * smag[i]); wf += w; sf += w * mval[i]; }
+      if (dt && sdt[i] > 0) { double w = 1 / (sdt[i] * sdt[i]); wt += w; st += w * tval[i]; }
+    }
+    double msrc = wf > 0 ? sf / wf : 0, dt0 = wt > 0 ? st / wt : 0;      // Eq. (msrc), Eq. (dt0)
+    for (int i = 0; i < n; ++i) {
+      if (fam[i] != f) continue;
+      if (mag && smag[i] > 0) { double d = mval[i] - msrc; cf += d * d / (smag[i] * smag[i]); }
+      if (dt && sdt[i] > 0) { double d = tval[i] - dt0; ct += d * d / (sdt[i] * sdt[i]); }
+    }
+  }
+  *chi_f = cf; *chi_t = ct;
+  return flags;
+}
+
+// Position, flux and time-delay chi^2 terms of S halo tables (Sec. 3.1-3.3): chi_pos is
+// the source-plane or image-plane position term; mag/smag and dt/sdt/tsc may be null.
+int orc_chi2_obs(const double* tabs, int S, int H, const double* th, const int* fam,
+                 const double* s1, const double* s2, const double* phi, int n,
+                 const double* afam, int n_fam, int img_mode, double newton_tol,
+                 const double* mag, const double* smag, const double* dt, const double* sdt,
+                 const double* tsc, double* chi_pos, double* chi_f, double* chi_t, int* flags, int nthreads) {
+  parallel_for(S, nthreads, [&](int lo, int hi) {
+    std::vector<double> bm(2 * n_fam), tm(2 * n);
+    ImgInfo I;
+    for (int s = lo; s < hi; ++s) {
+      const double* tab = tabs + (size_t)s * H * 8;
+      double cs = 0, ci = 0;
+      int fl = chi2_one(tab, H, th, fam, s1, s2, phi, n, afam, n_fam, img_mode, newton_tol, &cs, &ci,
+                        bm.data(), tm.data(), &I);
+      chi_pos[s] = img_mode ? ci : cs;
+      fl |= obs_terms(tab, H, th, fam, n, afam, n_fam, bm.data(), tm.data(), I, img_mode, mag, smag, dt, sdt,
+                      tsc, chi_f + s, chi_t + s);
+      flags[s] = fl;
+    }
+  });
+  return 0;
+}
+
+// Lensing potential sum at P points.
+int orc_potential(const double* tab, int H, const double* px, const double* py, int P, double* pot, int* flags,
+                  int nthreads) {
+  parallel_for(P, nthreads, [&](int lo, int hi) {
+    for (int p = lo; p < hi; ++p) flags[p] = potential_sum(tab, H, px[p], py[p], pot + p);
+  });
+  return 0;
+}
+
+// Time-delay scale (1 + z_d)/c D_d D_s / D_ds theta_0^2 with theta_0 = 1", in days per arcsec^2.
+double orc_tdscale(double zd, double zs, double H0, double Om) {
+  const double MPC_M = 3.0856775814913673e22, C_MS = 299792458.0, DAY = 86400.0;
+  double Dd = dist(0, zd, H0, Om), Ds = dist(0, zs, H0, Om), Dds = dist(zd, zs, H0, Om);
+  double th0 = 1.0 / ARCSEC;
+  return (1 + zd) / C_MS * (Dd * Ds / Dds) * MPC_M * th0 * th0 / DAY;
 }
 
 // Batched over S halo tables (each [H x 8]).

@@ -48,6 +48,8 @@ def lib():
         L.orc_sigma_to_b.argtypes = [d]
         L.orc_orient.restype = i
         L.orc_orient.argtypes = [d] * 6
+        L.orc_tdscale.restype = d
+        L.orc_tdscale.argtypes = [d, d, d, d]
         _lib = L
     return _lib
 
@@ -219,6 +221,47 @@ def chi2_batch(tabs, cons, img_mode=False, newton_tol=1e-9, nthreads=None):
                          C.c_int(nthreads or nthreads_default()))
     return {"chi2_src": cs, "chi2_img": ci if img_mode else None, "flags": fl,
             "beta_model": bm, "theta_model": tm}
+
+
+def potential(tab, px, py, nthreads=None):
+    """Lensing potential psi (a_dis-free; each profile up to its own constant) at points."""
+    tab = _f64(tab)
+    px, py = _f64(px), _f64(py)
+    P = px.size
+    pot = np.zeros(P)
+    fl = np.zeros(P, np.int32)
+    lib().orc_potential(_p(tab), C.c_int(tab.shape[0]), _p(px), _p(py), C.c_int(P), _p(pot), _p(fl, C.c_int),
+                        C.c_int(nthreads or nthreads_default()))
+    return pot, fl
+
+
+def tdscale(zd, zs, H0=70.0, Om=0.3):
+    """(1+z_d)/c D_d D_s/D_ds (1 arcsec)^2 in days per arcsec^2."""
+    return lib().orc_tdscale(C.c_double(zd), C.c_double(zs), C.c_double(H0), C.c_double(Om))
+
+
+def chi2_obs(tabs, cons, img_mode=False, newton_tol=1e-9, nthreads=None):
+    """Position, flux and time-delay chi^2 terms: cons may carry mag, sig_mag (per image),
+    dt, sig_dt (per image) and tscale (per family); an image enters a term where its error is
+    positive."""
+    tabs = _f64(tabs)
+    S, H = tabs.shape[0], tabs.shape[1]
+    th = _f64(cons["theta"])
+    fam = _i32(cons["family"])
+    s1, s2, phi = _f64(cons["sig1"]), _f64(cons["sig2"]), _f64(cons["phi"])
+    afam = _f64(cons["a_fam"])
+    n, nf = fam.size, afam.size
+    opt = lambda k: _f64(cons[k]) if cons.get(k) is not None else None
+    mag, smag, dt, sdt, tsc = opt("mag"), opt("sig_mag"), opt("dt"), opt("sig_dt"), opt("tscale")
+    cp, cf, ct = np.zeros(S), np.zeros(S), np.zeros(S)
+    fl = np.zeros(S, np.int32)
+    lib().orc_chi2_obs(_p(tabs), C.c_int(S), C.c_int(H), _p(th), _p(fam, C.c_int), _p(s1), _p(s2), _p(phi),
+                       C.c_int(n), _p(afam), C.c_int(nf), C.c_int(1 if img_mode else 0), C.c_double(newton_tol),
+                       _p(mag) if mag is not None else None, _p(smag) if smag is not None else None,
+                       _p(dt) if dt is not None else None, _p(sdt) if sdt is not None else None,
+                       _p(tsc) if tsc is not None else None, _p(cp), _p(cf), _p(ct), _p(fl, C.c_int),
+                       C.c_int(nthreads or nthreads_default()))
+    return {"pos": cp, "flux": cf, "td": ct, "total": cp + cf + ct, "flags": fl}
 
 
 # --------------------------------------------------------------------------- image finder
