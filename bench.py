@@ -6,10 +6,10 @@ Workload (synthetic, seeded): the cluster-scale single-plane case -- 2 elliptica
 60 sources at z ~ U[1, 8] with 150 image constraints (sigma = 0.5"), 1024 parameter samples.
 
 One step = one pass of the hot path over that batch, all in the MIXED precision form:
-  maps  (a1-a3): expansion, halo sums, epilogue (alpha, psi_ij, kappa, gamma, det A, mu, beta)
+  maps:         expansion, halo sums, epilogue (alpha, psi_ij, kappa, gamma, det A, mu, beta)
                  on the 2048^2 grid for the truth sample;
-  chi2  (a1+a4): source-plane chi^2 for the 1024 samples x 150 images;
-  find  (a5):    images of the 60 sources on the 2048^2 grid (FP64 containment and polish).
+  chi2:         source-plane chi^2 for the 1024 samples x 150 images;
+  find:         images of the 60 sources on the 2048^2 grid (FP64 containment and polish).
 The headline value is halo x point lens evaluations per second over the whole step; chi^2
 per second, the image-plane chi^2, the plain FP64 path, the multi-plane trace (3 planes,
 4096^2 rays, eNFW halos) and the uneven batched chi^2 are reported beside it.

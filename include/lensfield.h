@@ -187,9 +187,12 @@ lf_status lf_cosmo_adis(const lf_cosmo* c, double z_d, double z_s, double* out);
  * relative to the a_dis-free critical density c^2 / (4 pi G D_d). */
 lf_status lf_nfw_params(const lf_cosmo* c, double z_d, double m200, double c200,
                         double* kappa_s, double* r_s);
+/* Time-delay scale (1 + z_d)/c D_d D_s / D_ds theta_0^2 of Eq. (time_delay) with
+ * theta_0 = 1", in days per arcsec^2 (multiplies the Fermat potential in arcsec^2). */
+lf_status lf_cosmo_tdscale(const lf_cosmo* c, double z_d, double z_s, double* out);
 
 /* ---------------------------------------------------------------- resident model tables */
-/* Upload a parametric model (step a1: main components with field bindings + members on
+/* Upload a parametric model (main components with field bindings + members on
  * the scaling relations, Sec. 3.4).  `n_free` is the width of a parameter sample row.
  * All pointers are host pointers; the library copies them.  Errors: LF_E_INVALID_ARG
  * (bad profile code, binding index >= n_free, a fixed field out of range). */
@@ -207,9 +210,17 @@ lf_status lf_constraints_upload(lf_ctx* ctx, const double* theta, const int32_t*
                                 const double* sig1, const double* sig2, const double* phi,
                                 int32_t n_img, const double* a_fam, int32_t n_fam, lf_cons** out);
 lf_status lf_constraints_release(lf_ctx* ctx, lf_cons* c);
+/* Attach flux (Sec. 3.2) and/or time-delay (Sec. 3.3) measurements to a constraint set, in
+ * the image order of lf_constraints_upload: magnitudes mag and errors sig_mag [n_img]
+ * (both NULL: no flux data), delays dt [days] and errors sig_dt [n_img] with the time-delay
+ * scale of each family tscale [n_fam] (lf_cosmo_tdscale; all three NULL: no delays).  An
+ * image enters a term only where its error is > 0.  Host pointers, copied; at most once per
+ * set.  Errors: LF_E_INVALID_ARG (incomplete or non-finite data, tscale <= 0). */
+lf_status lf_constraints_observables(lf_ctx* ctx, lf_cons* c, const double* mag, const double* sig_mag,
+                                     const double* dt, const double* sig_dt, const double* tscale);
 
 /* ---------------------------------------------------------------- hot-path calls */
-/* Steps a1-a3 (+a7): for each of S parameter samples (device params [S * n_free], or
+/* Halo-sum maps: for each of S parameter samples (device params [S * n_free], or
  * NULL with S = 1 when the model has no free field) and each point, the halo sum of
  * alpha and psi_ij (Sec. 2.1) and, when any of psi111..f2 is requested, the third
  * derivatives psi_ijk and the A3-line fields of Sec. 6.  a_dis > 0 sets beta, det A, mu.
@@ -219,7 +230,7 @@ lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* m, const double* params, int
                        const lf_points* pts, double a_dis, lf_prec prec, const lf_maps* out,
                        void* stream);
 
-/* Step a4: chi^2 per parameter sample (Sec. 3.1).  mode 0 = source plane, Eq. (chi2_src)
+/* chi^2 per parameter sample (Sec. 3.1).  mode 0 = source plane, Eq. (chi2_src)
  * with the full magnification tensor mu_i = A^-1(theta_obs) and beta_model = G^-1 g;
  * mode 1 = image plane, Eq. (chi2_img), with each model image found by Newton-Raphson
  * from its observed position towards beta_model (Sec. 3.5; FP64 steps in both precisions,
@@ -232,7 +243,22 @@ lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* m, const double* params, in
                         const lf_cons* c, int32_t mode, lf_prec prec, double* chi2,
                         int32_t* flags, double* beta_model, void* stream);
 
-/* Step a5: image finder by triangle mapping (replacing the marching-squares contours of
+/* chi^2 with flux and time-delay terms: the total chi^2 = chi2_pos + chi2_f + chi2_dt of Sec. 3.2
+ * and 3.3 when the constraint set carries flux or delay data (lf_constraints_observables),
+ * with the per-term values in terms [S * 3] (position, flux, delay; device, or NULL).  Per
+ * family, the source magnitude (Eq. msrc) and the delay zero point (Eq. dt0) are the
+ * weighted means; magnitudes use 2.5 log10 |mu|.  mode 0: mu_model and dt_model from the
+ * linear expansions about theta_obs (mu + A^-1 (beta_model - beta_obs) . grad mu, with
+ * grad mu from the third derivatives; Eq. td_approx); mode 1: mu and the Fermat potential at
+ * the accepted model image (Eq. time_delay), the expansions for images the Newton solve did
+ * not accept.  These terms are evaluated in FP64 in both precisions.  Without such data the
+ * call equals lf_chi2_batch.  Errors: those of lf_chi2_batch; LF_E_UNSUPPORTED for flux data
+ * with an elliptical NFW component (its third derivatives are not provided). */
+lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
+                        const lf_cons* c, int32_t mode, lf_prec prec, double* chi2,
+                        int32_t* flags, double* beta_model, double* terms, void* stream);
+
+/* Image finder by triangle mapping (replacing the marching-squares contours of
  * Sec. 2.3).  Grid vertices are pixel centres; cell (i, j) splits along its
  * (i,j)-(i+1,j+1) diagonal.  A source is inside a mapped triangle by exact orientation
  * signs (ties broken by edge direction so shared edges are watertight); each candidate is
@@ -246,7 +272,7 @@ lf_status lf_find_images(lf_ctx* ctx, const lf_model* m, const double* params,
                          const lf_grid* grid, int32_t max_img, lf_prec prec, double* theta_out,
                          double* mu_out, int32_t* count_out, int32_t* flags, void* stream);
 
-/* Step a6: multi-plane ray trace (Sec. 2.2).  planes sorted by z_planes (increasing),
+/* Multi-plane ray trace (Sec. 2.2).  planes sorted by z_planes (increasing),
  * each a model without free fields.  For each point and each source redshift z_src[k]:
  * beta [n_zs][P][2], Jacobian A [n_zs][P][4] (A11 A12 A21 A22; not symmetric), mu [n_zs][P].
  * Planes at or behind a source do not deflect it.  Any output may be NULL. */
@@ -263,7 +289,7 @@ lf_status lf_find_images_mp(lf_ctx* ctx, const lf_model* const* planes, const do
                             int32_t max_img, lf_prec prec, double* theta_out, double* mu_out,
                             int32_t* count_out, int32_t* flags, void* stream);
 
-/* ---------------------------------------------------------------- uneven batched chi^2 (a8) */
+/* ---------------------------------------------------------------- uneven batched chi^2 */
 /* One chi^2 problem of an uneven batch: a model, its constraints and S parameter samples. */
 typedef struct {
   const lf_model* model;
@@ -295,7 +321,7 @@ lf_status lf_batch_info(const lf_batch* b, int32_t* block, int32_t* grid, int32_
                         int32_t* n_tiles);
 lf_status lf_batch_release(lf_batch* b);
 
-/* ---------------------------------------------------------------- serving (a8) */
+/* ---------------------------------------------------------------- serving */
 typedef struct lf_server lf_server;
 
 typedef struct {

@@ -245,6 +245,14 @@ extern "C" lf_status lf_cosmo_adis(const lf_cosmo* c, double zd, double zs, doub
   *out = dist_mpc(zd, zs, c->H0, c->Om) / dist_mpc(0, zs, c->H0, c->Om);
   return LF_OK;
 }
+extern "C" lf_status lf_cosmo_tdscale(const lf_cosmo* c, double zd, double zs, double* out) {
+  if (!cosmo_ok(c) || !out || !(zd > 0) || !(zs > zd) || !std::isfinite(zs)) return LF_E_INVALID_ARG;
+  const double MPC_M = 3.0856775814913673e22, C_MS = C_KMS * 1e3, DAY = 86400.0, th0 = 1.0 / ARCSEC;
+  const double Dd = dist_mpc(0, zd, c->H0, c->Om), Ds = dist_mpc(0, zs, c->H0, c->Om);
+  const double Dds = dist_mpc(zd, zs, c->H0, c->Om);
+  *out = (1.0 + zd) / C_MS * (Dd * Ds / Dds) * MPC_M * th0 * th0 / DAY;
+  return LF_OK;
+}
 extern "C" lf_status lf_nfw_params(const lf_cosmo* c, double zd, double m200, double c200, double* ks,
                                    double* rs_arcsec) {
   if (!cosmo_ok(c) || !(zd > 0) || !(m200 > 0) || !(c200 > 0) || !ks || !rs_arcsec) return LF_E_INVALID_ARG;

@@ -1,4 +1,4 @@
-// Uneven batched chi^2 (step a8): plans, hipGraph capture, tile autotuner.
+// Uneven batched chi^2: plans, hipGraph capture, tile autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -120,6 +120,8 @@ extern "C" lf_status lf_batch_create(lf_ctx* ctx, const lf_batch_item* items, in
     const lf_batch_item& it = items[i];
     if (!it.model || !it.cons || !it.chi2 || it.S < 1 || (it.model->n_free > 0 && !it.params))
       return ctx->fail(LF_E_INVALID_ARG, "batch item %d: bad model/constraints/samples/output", i);
+    if (it.cons->has_obs())
+      return ctx->fail(LF_E_UNSUPPORTED, "batch item %d: flux / time-delay constraints are served by lf_chi2_terms", i);
     if (mode == 1 && (long long)it.S * it.cons->n_img >= (1LL << 31))
       return ctx->fail(LF_E_INVALID_ARG, "batch item %d: image plane needs S * n_img < 2^31", i);
   }

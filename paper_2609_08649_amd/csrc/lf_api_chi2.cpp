@@ -1,4 +1,4 @@
-// Constraint tables and lf_chi2_batch (step a4).
+// Constraint tables (positions, fluxes, delays), lf_chi2_batch and lf_chi2_terms.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -77,9 +77,47 @@ extern "C" lf_status lf_constraints_upload(lf_ctx* ctx, const double* theta, con
   return LF_OK;
 }
 
+extern "C" lf_status lf_constraints_observables(lf_ctx* ctx, lf_cons* c, const double* mag, const double* sig_mag,
+                                                const double* dt, const double* sig_dt, const double* tscale) {
+  if (!ctx || !c) return LF_E_INVALID_ARG;
+  if (c->has_obs()) return ctx->fail(LF_E_INVALID_ARG, "constraints: observables already set");
+  const bool hf = mag || sig_mag, ht = dt || sig_dt || tscale;
+  if (!hf && !ht) return ctx->fail(LF_E_INVALID_ARG, "constraints: no flux or time-delay data");
+  if (hf && (!mag || !sig_mag)) return ctx->fail(LF_E_INVALID_ARG, "flux data needs mag and sig_mag");
+  if (ht && (!dt || !sig_dt || !tscale)) return ctx->fail(LF_E_INVALID_ARG, "time-delay data needs dt, sig_dt and tscale");
+  const int n = c->n_img, nf = c->n_fam;
+  for (int i = 0; i < n; ++i) {
+    if (hf && (!std::isfinite(sig_mag[i]) || (sig_mag[i] > 0 && !std::isfinite(mag[i]))))
+      return ctx->fail(LF_E_INVALID_ARG, "image %d: bad magnitude or error", i);
+    if (ht && (!std::isfinite(sig_dt[i]) || (sig_dt[i] > 0 && !std::isfinite(dt[i]))))
+      return ctx->fail(LF_E_INVALID_ARG, "image %d: bad delay or error", i);
+  }
+  if (ht)
+    for (int f = 0; f < nf; ++f)
+      if (!(tscale[f] > 0) || !std::isfinite(tscale[f])) return ctx->fail(LF_E_INVALID_ARG, "family %d: tscale must be > 0", f);
+  std::vector<double> h;
+  if (hf) { h.resize(2 * n); for (int k = 0; k < n; ++k) { h[k] = mag[c->order[k]]; h[n + k] = sig_mag[c->order[k]]; } }
+  if (ht) {
+    size_t o = h.size();
+    h.resize(o + 2 * n + nf);
+    for (int k = 0; k < n; ++k) { h[o + k] = dt[c->order[k]]; h[o + n + k] = sig_dt[c->order[k]]; }
+    for (int f = 0; f < nf; ++f) h[o + 2 * n + f] = tscale[f];
+  }
+  size_t bytes = sizeof(double) * h.size();
+  lf_status st = ctx->dmalloc((void**)&c->d_obs, bytes);
+  if (st) return st;
+  c->obs_bytes = bytes;
+  hipMemcpy(c->d_obs, h.data(), bytes, hipMemcpyHostToDevice);
+  double* p = (double*)c->d_obs;
+  if (hf) { c->d_mag = p; p += 2 * n; }
+  if (ht) { c->d_dt = p; c->d_tsc = p + 2 * n; }
+  return LF_OK;
+}
+
 extern "C" lf_status lf_constraints_release(lf_ctx* ctx, lf_cons* c) {
   if (!ctx || !c) return LF_E_INVALID_ARG;
   ctx->dfree(c->d_theta, c->bytes);
+  if (c->d_obs) ctx->dfree(c->d_obs, c->obs_bytes);
   delete c;
   return LF_OK;
 }
@@ -102,6 +140,14 @@ lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, 
   A.bm_ws = wsd(".bm", (size_t)S * c->n_fam * 2); if (e) return e;
   A.strag_n = wsi(".strag", 1); if (e) return e;
   A.n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+  A.mag = A.smag = A.dt = A.sdt = A.tsc = nullptr;
+  A.ext = A.extm = A.terms = nullptr;
+  if (c->has_obs()) {
+    if (c->d_mag) { A.mag = c->d_mag; A.smag = c->d_mag + c->n_img; }
+    if (c->d_dt) { A.dt = c->d_dt; A.sdt = c->d_dt + c->n_img; A.tsc = c->d_tsc; }
+    A.ext = wsd(".ext", n * 8); if (e) return e;
+    A.extm = wsd(".extm", n * 4); if (e) return e;
+  }
   A.m = lf_dev_model(M);
   A.mains = mains; A.muls = muls; A.cat32 = M->d_cat32;
   A.S = S; A.n_img = c->n_img; A.n_fam = c->n_fam;
@@ -110,12 +156,19 @@ lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, 
   lf::QuadTab q = lf_quad(ctx);
   A.qd.n = q.n; A.qd.u = q.u; A.qd.w = q.w;
   A.tmod = nullptr;
+  if (c->has_obs()) { A.tmod = wsd(".tmod", n * 2); if (e) return e; }
   return LF_OK;
 }
 
 extern "C" lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
                                    const lf_cons* c, int32_t mode, lf_prec prec, double* chi2, int32_t* flags,
                                    double* beta_model, void* stream) {
+  return lf_chi2_terms(ctx, M, params, S, c, mode, prec, chi2, flags, beta_model, nullptr, stream);
+}
+
+extern "C" lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
+                                   const lf_cons* c, int32_t mode, lf_prec prec, double* chi2, int32_t* flags,
+                                   double* beta_model, double* terms, void* stream) {
   if (!ctx) return LF_E_INVALID_ARG;
   if (!M || !c || !chi2) return ctx->fail(LF_E_INVALID_ARG, "null model/constraints/output");
   if (S < 1) return ctx->fail(LF_E_INVALID_ARG, "S must be >= 1");
@@ -124,12 +177,14 @@ extern "C" lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* M, const double*
   if (mode == 1 && (long long)S * c->n_img >= (1LL << 31))
     return ctx->fail(LF_E_INVALID_ARG, "image plane needs S * n_img < 2^31");
   if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
+  if (c->d_mag && lf_model_has_enfw(M))
+    return ctx->fail(LF_E_UNSUPPORTED, "flux terms need third derivatives, not available for elliptical NFW");
   hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;
   lf::Chi2Args A;
   lf_status e = lf_chi2_prepare(ctx, M, params, S, c, st, A, "chi2");
   if (e) return e;
-  A.chi2 = chi2; A.flags = flags; A.bmod = beta_model;
+  A.chi2 = chi2; A.flags = flags; A.bmod = beta_model; A.terms = terms;
   bool mixed = prec == LF_PREC_MIXED;
   A.newton_tol = 1e-9;
   ctx->cur_stream = st;

@@ -1,4 +1,5 @@
-// lf_find_images (step a5), lf_multiplane_trace (step a6), lf_find_images_mp.
+// lf_find_images (triangle-mapping finder), lf_multiplane_trace (multi-plane recursion),
+// lf_find_images_mp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -71,6 +71,13 @@ struct lf_cons {
   int* d_fam_start = nullptr;    // [n_fam + 1]
   double* d_afam = nullptr;      // [n_fam]
   size_t bytes = 0;
+  // flux and time-delay data (Sec. 3.2, 3.3), sorted like the images; null when absent
+  double* d_mag = nullptr;       // [n_img] magnitudes and [n_img] errors (d_mag + n_img)
+  double* d_dt = nullptr;        // [n_img] delays and [n_img] errors (d_dt + n_img)
+  double* d_tsc = nullptr;       // [n_fam] time-delay scales [days / arcsec^2]
+  size_t obs_bytes = 0;
+  char* d_obs = nullptr;
+  bool has_obs() const { return d_mag || d_dt; }
 };
 
 lf::XfConst lf_xf_const(const lf_cosmo* c, double zd);

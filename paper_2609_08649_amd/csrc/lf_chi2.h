@@ -31,6 +31,15 @@ struct Chi2Args {
   double* bmod;              // [S*n_fam*2] out (may be null)
   double* tmod;              // [S*n_img*2] model image positions (may be null)
   double newton_tol;
+  // flux and time-delay terms (Sec. 3.2, 3.3); the pointers are null without such data
+  const double* mag;         // [n_img] observed magnitudes (sorted order)
+  const double* smag;        // [n_img] their errors; <= 0: no measurement
+  const double* dt;          // [n_img] observed delays [days]
+  const double* sdt;         // [n_img] their errors; <= 0: no measurement
+  const double* tsc;         // [n_fam] (1+z_d)/c D_d D_s/D_ds theta_0^2 [days / arcsec^2]
+  double* ext;               // [S*n_img*8] FP64 at theta_obs: psi, psi_111..psi_222, psi_11, psi_12, psi_22
+  double* extm;              // [S*n_img*4] FP64 at accepted model images: psi, psi_11, psi_12, psi_22
+  double* terms;             // [S*3] out: position, flux, delay chi^2 terms (may be null)
   int* strag_n;              // [1] image-plane Newton: number of images left for round 2
   int n_cu;                  // compute units (grid of the round-2 launch)
   Quad qd;

@@ -1,4 +1,4 @@
-// chi^2 per parameter sample (step a4; Sec. 3.1 Eq. chi2_src / chi2_img, Sec. 3.5 Newton).
+// chi^2 per parameter sample (Sec. 3.1 Eq. chi2_src / chi2_img, Sec. 3.5 Newton).
 //
 // Lanes run over the flattened (image, sample) pairs, sample fastest, so a wave is fully used
 // whatever the number of images and mostly holds one image under many samples; member records
@@ -7,6 +7,8 @@
 // one wave per sample: a lane per family sums its images in order, a shuffle tree sums the
 // families -- a fixed order, so results are bit-reproducible and independent of batch mates.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lf_chi2.h"
 #include "lf_device.h"
@@ -29,7 +31,8 @@ __device__ __forceinline__ long long lane_slot(const Chi2Args& A, long long t) {
 }
 
 // One catalog member scaled by the lane's multipliers, FP64; false on a singular centre.
-template <int SEG>
+// D3: third derivatives too (not for elliptical NFW members, which the callers exclude).
+template <int SEG, bool D3 = false>
 __device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, double bm, double sm, double am,
                                          const Quad& qd, Term<double>& t) {
   using T = double;
@@ -39,20 +42,20 @@ __device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, 
     T r2 = fma(dx, dx, dy * dy);
     if (s == (T)0 && r2 < (T)1e-24) return false;
     T m, w, p = 0;
-    if constexpr (SEG == SEG_CPJE) pje_mw<false>(b, s, a, s * s, a * a, a - s, (a - s) * (a + s), r2, m, w, p);
-    else cored_mw<false>(b, s, s * s, r2, m, w, p);
-    radial<false>(dx, dy, m, w, p, t);
+    if constexpr (SEG == SEG_CPJE) pje_mw<D3>(b, s, a, s * s, a * a, a - s, (a - s) * (a + s), r2, m, w, p);
+    else cored_mw<D3>(b, s, s * s, r2, m, w, p);
+    radial<D3>(dx, dy, m, w, p, t);
   } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
     if (s == (T)0 && dx == (T)0 && dy == (T)0) return false;
     T q2 = c.q * c.q;
     T e = sqrt((T)1 - q2);
-    epje<false>(dx, dy, c.c, c.sn, b * c.q / e, e, q2, s, a, SEG == SEG_EPJE, t);
+    epje<D3>(dx, dy, c.c, c.sn, b * c.q / e, e, q2, s, a, SEG == SEG_EPJE, t);
   } else if constexpr (SEG == SEG_POINT) {
     if (dx == (T)0 && dy == (T)0) return false;
-    point_mass<false>(dx, dy, b, t);
+    point_mass<D3>(dx, dy, b, t);
   } else if constexpr (SEG == SEG_NFW) {
     if (dx == (T)0 && dy == (T)0) return false;
-    nfw_circ<false>(dx, dy, b, s, t);
+    nfw_circ<D3>(dx, dy, b, s, t);
   } else {
     if (dx == (T)0 && dy == (T)0) return false;
     double xp = c.c * dx + c.sn * dy, yp = c.c * dy - c.sn * dx;
@@ -61,6 +64,31 @@ __device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, 
     rotate_back<false>(c.c, c.sn, pr, t);
   }
   return true;
+}
+
+// Potential of one catalog member scaled by the lane's multipliers, FP64 (0 on a singular
+// centre).
+template <int SEG>
+__device__ __forceinline__ double cat_pot(const MemCat& c, double dx, double dy, double bm, double sm, double am,
+                                          const Quad& qd) {
+  const double b = bm * c.fb, s = sm * c.fs, a = am * c.fa, r2 = fma(dx, dx, dy * dy);
+  if constexpr (SEG == SEG_CPJE || SEG == SEG_CSIE || SEG == SEG_EPJE || SEG == SEG_ESIE) {
+    if (s == 0.0 && r2 < 1e-24) return 0.0;
+  } else {
+    if (r2 < 1e-24) return 0.0;
+  }
+  if constexpr (SEG == SEG_CPJE) return pot_cpje(b, s, a, r2);
+  else if constexpr (SEG == SEG_CSIE) return pot_cored(b, s, r2);
+  else if constexpr (SEG == SEG_POINT) return b * b * 0.5 * log(r2);
+  else if constexpr (SEG == SEG_NFW) return pot_nfw(r2, b, s);
+  else {
+    const double xp = c.c * dx + c.sn * dy, yp = c.c * dy - c.sn * dx;
+    if constexpr (SEG == SEG_ENFW) return pot_enfw(xp, yp, b, s, c.q, qd);
+    const double q2 = c.q * c.q, e = sqrt(1.0 - q2), bqe = b * c.q / e;
+    double v = pot_esie(xp, yp, bqe, e, q2, s);
+    if constexpr (SEG == SEG_EPJE) v -= pot_esie(xp, yp, bqe, e, q2, a);
+    return v;
+  }
 }
 
 // Member segment loop with per-lane multipliers, FP64 (MemCat, every segment).
@@ -248,9 +276,126 @@ __device__ __forceinline__ int wave_or(int v) {
 // Source-plane chi^2: one wave per sample.  Per image: beta_obs = theta - a_f alpha,
 // mu = A^-1, W = mu^T S^-1 mu; per family: G = sum W, g = sum W beta_obs, beta_model =
 // G^-1 g; chi^2 = sum (beta_obs - beta_model)^T W (beta_obs - beta_model).
-__device__ void chi2_src_sample(const Chi2Args& A, int s) {
+// ---------------------------------------------------------------------------------------
+// Flux and time-delay terms (Sec. 3.2 Eq. chi2_flux, msrc; Sec. 3.3 Eq. chi2_td, dt0,
+// td_approx), FP64 in both precisions.  The observables pass evaluates, per (image, sample),
+// the potential, psi_ij and the third derivatives at theta_obs (WHICH = 0) or the potential
+// and psi_ij at the accepted image-plane model image (WHICH = 1).
+// ---------------------------------------------------------------------------------------
+template <bool D3>
+__device__ void obs_sums(const Chi2Args& A, int s, double x, double y, bool want_pot, Acc& acc, double& pot) {
+  acc.zero();
+  pot = 0.0;
+  const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
+  for (int c = 0; c < A.m.n_main; ++c) {
+    const MainRec r = mr[c];
+    eval_main<D3>(r, x, y, A.qd, acc);
+    if (want_pot) pot += pot_main(r, x, y, A.qd);
+  }
+  const MulRec u = A.muls[s];
+  const SegOff& so = A.m.seg;
+  auto seg = [&](auto tag) {
+    constexpr int SEG = decltype(tag)::value;
+    for (int h = so.off[SEG]; h < so.off[SEG + 1]; ++h) {
+      const MemCat c = A.m.mem[h];
+      const double dx = x - c.x, dy = y - c.y;
+      Term<double> t;
+      if (cat_term<SEG, D3 && SEG != SEG_ENFW>(c, dx, dy, u.b, u.s, u.a, A.qd, t)) add<D3>(acc, t);
+      if (want_pot) pot += cat_pot<SEG>(c, dx, dy, u.b, u.s, u.a, A.qd);
+    }
+  };
+  seg(std::integral_constant<int, SEG_CPJE>());
+  seg(std::integral_constant<int, SEG_EPJE>());
+  seg(std::integral_constant<int, SEG_CSIE>());
+  seg(std::integral_constant<int, SEG_ESIE>());
+  seg(std::integral_constant<int, SEG_POINT>());
+  seg(std::integral_constant<int, SEG_NFW>());
+  seg(std::integral_constant<int, SEG_ENFW>());
+}
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_chi2_obs(const Chi2Args A) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)A.S * A.n_img) return;
+  const long long g = lane_slot(A, t);
+  int s, i;
+  double x, y;
+  lane_point(A, g, s, i, x, y);
+  const bool want_pot = A.dt != nullptr;
+  Acc acc;
+  double pot;
+  if (WHICH == 0) {
+    obs_sums<true>(A, s, x, y, want_pot, acc, pot);
+    double* e = A.ext + (size_t)g * 8;
+    e[0] = pot; e[1] = acc.t111; e[2] = acc.t112; e[3] = acc.t122; e[4] = acc.t222;
+    e[5] = acc.h11; e[6] = acc.h12; e[7] = acc.h22;
+  } else {
+    if (A.iflags[g] != 0) return;              // not accepted: the source-plane expansion is used
+    obs_sums<false>(A, s, A.tmod[2 * g], A.tmod[2 * g + 1], want_pot, acc, pot);
+    double* e = A.extm + (size_t)g * 4;
+    e[0] = pot; e[1] = acc.h11; e[2] = acc.h12; e[3] = acc.h22;
+  }
+}
+
+// Model magnitude term m_i + 2.5 log10 |mu_model| and delay residual dt_obs - dt_model of image
+// g (sorted index i, family f).  img: the image-plane solution was accepted (mu and psi at the
+// model image); otherwise the source-plane expansions about theta_obs.
+__device__ void obs_image(const Chi2Args& A, size_t g, int i, int f, bool img, double& mval, double& tval) {
+  const double a = A.afam[f];
+  const double bmx = A.bm_ws[(g / A.n_img * A.n_fam + f) * 2], bmy = A.bm_ws[(g / A.n_img * A.n_fam + f) * 2 + 1];
+  const double T = A.dt ? A.tsc[f] : 0.0;
+  double mu_m, t_m;
+  if (img) {
+    const double* e = A.extm + g * 4;
+    const double B11 = 1.0 - a * e[1], B12 = -a * e[2], B22 = 1.0 - a * e[3];
+    mu_m = 1.0 / (B11 * B22 - B12 * B12);
+    const double ex = A.tmod[2 * g] - bmx, ey = A.tmod[2 * g + 1] - bmy;
+    t_m = T * (0.5 * (ex * ex + ey * ey) - a * e[0]);
+  } else {
+    const double* e = A.ext + g * 8;
+    const double* w = A.wimg + g * 6;
+    const double tx = A.th[2 * i], ty = A.th[2 * i + 1], bx = w[3], by = w[4];
+    const double A11 = 1.0 - a * e[5], A12 = -a * e[6], A22 = 1.0 - a * e[7];
+    const double det = A11 * A22 - A12 * A12, mu = 1.0 / det;
+    const double gdx = -a * (e[1] * A22 + A11 * e[3] - 2.0 * A12 * e[2]);
+    const double gdy = -a * (e[2] * A22 + A11 * e[4] - 2.0 * A12 * e[3]);
+    const double dbx = bmx - bx, dby = bmy - by;
+    const double dthx = (A22 * dbx - A12 * dby) / det, dthy = (-A12 * dbx + A11 * dby) / det;
+    mu_m = mu - mu * mu * (dthx * gdx + dthy * gdy);
+    const double ex = tx - bx, ey = ty - by;
+    t_m = T * (0.5 * (ex * ex + ey * ey) - a * e[0]) + T * (dbx * (bx - tx) + dby * (by - ty));
+  }
+  mval = A.mag ? A.mag[i] + 2.5 * log10(fabs(mu_m)) : 0.0;
+  tval = A.dt ? A.dt[i] - t_m : 0.0;
+}
+// chi^2_f and chi^2_dt of family f of sample s; the nuisance zero points m_src and dt_0 are the
+// weighted means of Eq. (msrc) and Eq. (dt0).  img: image-plane mode (accepted images use
+// their model image).
+__device__ void obs_family(const Chi2Args& A, int s, int f, bool img, double& cf, double& ct) {
+  const int i0 = A.fam_start[f], i1 = A.fam_start[f + 1];
+  double wf = 0, sf = 0, wt = 0, st = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const double msrc = wf > 0 ? sf / wf : 0.0, dt0 = wt > 0 ? st / wt : 0.0;
+    for (int i = i0; i < i1; ++i) {
+      const bool hf = A.mag && A.smag[i] > 0, ht = A.dt && A.sdt[i] > 0;
+      if (!hf && !ht) continue;
+      const size_t g = (size_t)s * A.n_img + i;
+      double mv, tv;
+      obs_image(A, g, i, f, img && A.iflags[g] == 0, mv, tv);
+      if (pass == 0) {
+        if (hf) { const double w = 1.0 / (A.smag[i] * A.smag[i]); wf += w; sf += w * mv; }
+        if (ht) { const double w = 1.0 / (A.sdt[i] * A.sdt[i]); wt += w; st += w * tv; }
+      } else {
+        if (hf) { const double d = mv - msrc; cf += d * d / (A.smag[i] * A.smag[i]); }
+        if (ht) { const double d = tv - dt0; ct += d * d / (A.sdt[i] * A.sdt[i]); }
+      }
+    }
+  }
+}
+
+// obs: add the flux and time-delay terms (source-plane mode with such constraints).
+__device__ void chi2_src_sample(const Chi2Args& A, int s, bool obs) {
   const int lane = threadIdx.x & 63;
-  double tot = 0.0;
+  double tot = 0.0, cf = 0.0, ct = 0.0;
   int fl = 0;
   for (int f = lane; f < A.n_fam; f += 64) {
     int i0 = A.fam_start[f], i1 = A.fam_start[f + 1];
@@ -302,15 +447,18 @@ __device__ void chi2_src_sample(const Chi2Args& A, int s) {
       A.csrc[g] = c;
       tot += c;
     }
+    if (obs) obs_family(A, s, f, false, cf, ct);
   }
   tot = wave_sum(tot);
   fl = wave_or(fl);
+  if (obs) { cf = wave_sum(cf); ct = wave_sum(ct); }
   if (lane == 0) {
-    A.chi2[s] = (fl & FL_INVALID) ? __builtin_nan("") : tot;
+    A.chi2[s] = (fl & FL_INVALID) ? __builtin_nan("") : tot + cf + ct;
     if (A.flags) A.flags[s] = fl;
+    if (A.terms) { A.terms[3 * (size_t)s] = tot; A.terms[3 * (size_t)s + 1] = cf; A.terms[3 * (size_t)s + 2] = ct; }
   }
 }
-__global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A) { chi2_src_sample(A, blockIdx.x); }
+__global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A, int obs) { chi2_src_sample(A, blockIdx.x, obs != 0); }
 
 // Image-plane chi^2: Newton from theta_obs towards beta_model, full halo sum per step, in
 // FP64 for both precisions (the source-plane part that sets beta_model follows the chosen
@@ -476,19 +624,24 @@ __global__ void k_chi2_reset(int* p) { *p = 0; }
 __device__ void chi2_img_sample(const Chi2Args& A, int s) {
   const int lane = threadIdx.x & 63;
   // per lane: a fixed contiguous block of images, summed in order; then a shuffle tree
-  double tot = 0.0;
+  double tot = 0.0, cf = 0.0, ct = 0.0;
   int fl = 0;
   for (int i = lane; i < A.n_img; i += 64) {
     size_t g = (size_t)s * A.n_img + i;
     tot += A.cimg[g];
     fl |= A.iflags[g];
   }
+  const bool obs = A.mag || A.dt;
+  if (obs)
+    for (int f = lane; f < A.n_fam; f += 64) obs_family(A, s, f, true, cf, ct);
   tot = wave_sum(tot);
   fl = wave_or(fl);
+  if (obs) { cf = wave_sum(cf); ct = wave_sum(ct); }
   if (lane == 0) {
     int f0 = A.flags ? A.flags[s] : 0;
-    A.chi2[s] = (f0 & FL_INVALID) ? __builtin_nan("") : tot;
+    A.chi2[s] = (f0 & FL_INVALID) ? __builtin_nan("") : tot + cf + ct;
     if (A.flags) A.flags[s] = f0 | fl;
+    if (A.terms) { A.terms[3 * (size_t)s] = tot; A.terms[3 * (size_t)s + 1] = cf; A.terms[3 * (size_t)s + 2] = ct; }
   }
 }
 __global__ __launch_bounds__(64) void k_chi2_img_sum(const Chi2Args A) { chi2_img_sample(A, blockIdx.x); }
@@ -505,8 +658,14 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
   if (mixed) hipLaunchKernelGGL(k_chi2_lean<true>, dim3(lean_blocks), dim3(256), 0, st, A);
   else hipLaunchKernelGGL(k_chi2_lean<false>, dim3(lean_blocks), dim3(256), 0, st, A);
   mark(ctx, "chi2_lean", 1);
+  const bool obs = A.mag || A.dt;
+  if (obs) {
+    mark(ctx, "chi2_obs", 0);
+    hipLaunchKernelGGL(k_chi2_obs<0>, dim3(blocks), dim3(256), 0, st, A);
+    mark(ctx, "chi2_obs", 1);
+  }
   mark(ctx, "chi2_src", 0);
-  hipLaunchKernelGGL(k_chi2_src, dim3(A.S), dim3(64), 0, st, A);
+  hipLaunchKernelGGL(k_chi2_src, dim3(A.S), dim3(64), 0, st, A, (obs && mode == 0) ? 1 : 0);
   mark(ctx, "chi2_src", 1);
   if (mode == 1) {
     mark(ctx, "chi2_newton", 0);
@@ -514,6 +673,7 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
     hipLaunchKernelGGL(k_chi2_newton, dim3(blocks), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_chi2_newton2, dim3(A.n_cu * 4), dim3(256), 0, st, A);
     mark(ctx, "chi2_newton", 1);
+    if (obs) hipLaunchKernelGGL(k_chi2_obs<1>, dim3(blocks), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_chi2_img_sum, dim3(A.S), dim3(64), 0, st, A);
   }
   return hipGetLastError();
@@ -559,7 +719,7 @@ __global__ __launch_bounds__(256) void k_batch_lean(const BatchArgs B) {
 
 __global__ __launch_bounds__(64) void k_batch_src(const BatchArgs B) {
   int gs = blockIdx.x;
-  chi2_src_sample(B.items[B.samp_item[gs]], B.samp_local[gs]);
+  chi2_src_sample(B.items[B.samp_item[gs]], B.samp_local[gs], false);
 }
 
 __global__ __launch_bounds__(256) void k_batch_newton(const BatchArgs B) {

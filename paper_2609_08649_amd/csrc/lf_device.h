@@ -314,6 +314,79 @@ __device__ __forceinline__ void enfw_prime(double xp, double yp, double ks, doub
 }
 
 // ---------------------------------------------------------------------------------------
+// Lensing potential psi (Sec. 2.1, defined without a_dis), FP64, for the time-delay terms;
+// each profile up to its own additive constant (delays use differences within a family):
+//   circular cored  b (R - s ln(R + s));  circular dPIE  b (-(R_a - R_s) - s ln D_s + a ln D_a)
+//   (R_a - R_s as in pje_mw);  elliptical SIE  x alpha_x + y alpha_y - b q s ln sqrt((psi~ + s)^2
+//   + e^2 x^2) in the halo frame;  point mass  b^2 ln r;  NFW  2 k_s r_s^2 h(X) with
+//   h = ln^2(X/2) - arccosh^2(1/X) (X < 1), ln^2(X/2) + arccos^2(1/X) (X > 1);  elliptical NFW
+//   (q/2) int_0^1 xi alpha_c(xi) / (u sqrt(1 - e^2 u)) du, xi alpha_c = 4 k_s r_s^2 (ln(X/2) + F).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double pot_cored(double b, double s, double r2) {
+  const double R = sqrt(fma(s, s, r2));
+  return s > 0.0 ? b * (R - s * log(R + s)) : b * R;
+}
+__device__ __forceinline__ double pot_cpje(double b, double s, double a, double r2) {
+  const double Rs = sqrt(fma(s, s, r2)), Ra = sqrt(fma(a, a, r2));
+  const double dR = (a - s) * (a + s) / (Ra + Rs);
+  double v = a * log(Ra + a) - dR;
+  if (s > 0.0) v -= s * log(Rs + s);
+  return b * v;
+}
+__device__ __forceinline__ double pot_esie(double xp, double yp, double bqe, double e, double q2, double s) {
+  const double psi = sqrt(fma(q2, fma(s, s, xp * xp), yp * yp));
+  const double ax = bqe * atan(e * xp / (psi + s)), ay = bqe * atanh(e * yp / fma(q2, s, psi));
+  double v = xp * ax + yp * ay;
+  if (s > 0.0) {
+    const double ps = psi + s;
+    v -= bqe * e * s * 0.5 * log(fma(ps, ps, e * e * xp * xp));   // b q s = bqe e s
+  }
+  return v;
+}
+__device__ __forceinline__ double pot_nfw(double r2, double ks, double rs) {
+  const double X2 = r2 / (rs * rs), X = sqrt(X2);
+  const double l = log(0.5 * X);
+  double h;
+  if (X < 1.0) { const double ac = log((1.0 + sqrt(1.0 - X2)) / X); h = l * l - ac * ac; }
+  else { const double ac = acos(1.0 / X); h = l * l + ac * ac; }
+  return 2.0 * ks * rs * rs * h;
+}
+__device__ __forceinline__ double pot_enfw(double xp, double yp, double ks, double rs, double q, const Quad& qd) {
+  const double e2 = 1.0 - q * q, xx = xp * xp, yy = yp * yp, irs2 = 1.0 / (rs * rs);
+  double I = 0.0;
+  for (int i = 0; i < qd.n; ++i) {
+    const double u = qd.u[i], W = fma(-e2, u, 1.0);
+    const double X2 = u * (xx + yy / W) * irs2;
+    double F, G, Gp;
+    nfw_G(X2, F, G, Gp);
+    const double xa = 4.0 * ks * rs * rs * (0.5 * log(0.25 * X2) + F);
+    I = fma(qd.w[i], xa / (u * sqrt(W)), I);
+  }
+  return 0.5 * q * I;
+}
+// Potential of one main component (0 on a singular centre, where its deflection is 0 too).
+__device__ __forceinline__ double pot_main(const MainRec& r, double px, double py, const Quad& qd) {
+  const double dx = px - r.x, dy = py - r.y, r2 = fma(dx, dx, dy * dy);
+  const bool singular = (r.type == T_POINT || r.type == T_SIS || r.type == T_NFW || r.type == T_ENFW || r.s == 0.0);
+  if (singular && r2 < 1e-24) return 0.0;
+  switch (r.type) {
+    case T_POINT: return r.b * r.b * 0.5 * log(r2);
+    case T_SIS: return r.b * sqrt(r2);
+    case T_NFW: return pot_nfw(r2, r.b, r.s);
+    default: break;
+  }
+  if (r.q >= 1.0) {
+    if (r.type == T_SIE) return pot_cored(r.b, r.s, r2);
+    if (r.type == T_PJE) return pot_cpje(r.b, r.s, r.a, r2);
+    return pot_nfw(r2, r.b, r.s);
+  }
+  const double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
+  if (r.type == T_SIE) return pot_esie(xp, yp, r.bqe, r.e, r.q2, r.s);
+  if (r.type == T_PJE) return pot_esie(xp, yp, r.bqe, r.e, r.q2, r.s) - pot_esie(xp, yp, r.bqe, r.e, r.q2, r.a);
+  return pot_enfw(xp, yp, r.b, r.s, r.q, qd);
+}
+
+// ---------------------------------------------------------------------------------------
 // One main component (FP64) at one point.
 // ---------------------------------------------------------------------------------------
 // ENFW = false compiles the elliptical NFW quadrature out (a kernel variant for models without

@@ -1,4 +1,4 @@
-// Image finder by triangle mapping (step a5) and the multi-plane passes (step a6).
+// Image finder by triangle mapping and the multi-plane passes.
 //
 // Finder pipeline (all on the device, no host synchronisation):
 //   1. vertex deflections on the grid (maps kernels, FP32 members in MIXED);

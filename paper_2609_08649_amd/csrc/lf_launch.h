@@ -46,7 +46,7 @@ struct MapsOut {
 hipError_t launch_expand(const DevModel& m, const double* params, int S, MainRec* mains,
                          MulRec* muls, MemRec32* m32, MemRec64* m64, hipStream_t st);
 
-// a2+a3(+a7): halo sums and fused epilogue over points for S samples.
+// Halo sums and fused epilogue over points for S samples.
 hipError_t launch_maps(const DevModel& m, const MainRec* mains, const MemRec32* m32,
                        const MemRec64* m64, int S, const PointsSpec& pts, double a_dis,
                        bool mixed, bool d3, const MapsOut& out, const QuadTab& q, int ppl,

@@ -1,4 +1,5 @@
-// Halo-table expansion (step a1) and the halo-sum maps kernel (steps a2, a3, a7).
+// Halo-table expansion (parametric model -> per-sample halo records) and the halo-sum maps
+// kernel (deflection, Hessian, third derivatives and their epilogue fields).
 //
 // Layout: one lane owns PPL points (strided by the block size so stores coalesce);
 // halo records are wave-uniform, so the compiler fetches them through the scalar

@@ -1,4 +1,4 @@
-// Serving runtime (step a8): HBM-budget admission, continuous chi^2 batching, chunked maps.
+// Serving runtime: HBM-budget admission, continuous chi^2 batching, chunked maps.
 //
 // One scheduler thread owns all HIP work of the server.  Device memory comes from one arena
 // allocated at start (first-fit with coalescing), so admission never calls hipMalloc and the
@@ -486,6 +486,7 @@ extern "C" lf_status lf_serve_submit(lf_server* s, const lf_request* req, int64_
   if (r.kind == LF_REQ_CHI2) {
     if (!r.cons || r.S < 1 || (r.mode != 0 && r.mode != 1) || (r.model->n_free > 0 && !r.params)) return LF_E_INVALID_ARG;
     if (r.mode == 1 && (long long)r.S * r.cons->n_img >= (1LL << 31)) return LF_E_INVALID_ARG;
+    if (r.cons->has_obs()) return LF_E_UNSUPPORTED;      // flux / delay terms: lf_chi2_terms
     size_t tiles = ((size_t)r.S * r.cons->n_img + 255) / 256;
     if (sizeof(lf::Chi2Args) + sizeof(lf::BatchTile) * tiles + sizeof(int) * 2 * (size_t)r.S + 1024 > TABLE_BYTES)
       return LF_E_OUT_OF_BUDGET;

@@ -84,6 +84,7 @@ def lib():
             "lf_device_bytes": (C.c_size_t, [P]),
             "lf_cosmo_dist": (I32, [C.POINTER(lf_cosmo), D, D, C.POINTER(D)]),
             "lf_cosmo_adis": (I32, [C.POINTER(lf_cosmo), D, D, C.POINTER(D)]),
+            "lf_cosmo_tdscale": (I32, [C.POINTER(lf_cosmo), D, D, C.POINTER(D)]),
             "lf_nfw_params": (I32, [C.POINTER(lf_cosmo), D, D, D, C.POINTER(D), C.POINTER(D)]),
             "lf_model_upload": (I32, [P, C.POINTER(lf_component), I32, C.POINTER(lf_members), D,
                                       C.POINTER(lf_cosmo), I32, PP]),
@@ -91,8 +92,10 @@ def lib():
             "lf_model_n_halos": (I32, [P]),
             "lf_constraints_upload": (I32, [P, P, P, P, P, P, I32, P, I32, PP]),
             "lf_constraints_release": (I32, [P, P]),
+            "lf_constraints_observables": (I32, [P, P, P, P, P, P, P]),
             "lf_lens_maps": (I32, [P, P, P, I32, C.POINTER(lf_points), D, I32, C.POINTER(lf_maps), P]),
             "lf_chi2_batch": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
+            "lf_chi2_terms": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P, P]),
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
                                           P, P, P, P]),
@@ -222,6 +225,13 @@ class Context:
         self.check(lib().lf_cosmo_adis(C.byref(c), zd, zs, C.byref(out)))
         return out.value
 
+    def tdscale(self, zd, zs, H0=70.0, Om=0.3):
+        """(1+z_d)/c D_d D_s/D_ds theta_0^2 in days per arcsec^2."""
+        out = C.c_double()
+        c = lf_cosmo(H0, Om)
+        self.check(lib().lf_cosmo_tdscale(C.byref(c), zd, zs, C.byref(out)))
+        return out.value
+
     def nfw_params(self, zd, m200, c200, H0=70.0, Om=0.3):
         ks, rs = C.c_double(), C.c_double()
         c = lf_cosmo(H0, Om)
@@ -274,7 +284,21 @@ class Context:
         self.check(lib().lf_constraints_upload(self.handle, th.ctypes.data, fam.ctypes.data, s1.ctypes.data,
                                                s2.ctypes.data, ph.ctypes.data, fam.size, af.ctypes.data, af.size,
                                                C.byref(h)))
-        return Constraints(self, h, fam.size, af.size)
+        c = Constraints(self, h, fam.size, af.size)
+        has_mag, has_dt = cons.get("mag") is not None, cons.get("dt") is not None
+        if has_mag or has_dt:
+            def f64(k):
+                return np.ascontiguousarray(cons[k], np.float64) if cons.get(k) is not None else None
+            arrs = [f64("mag") if has_mag else None, f64("sig_mag") if has_mag else None,
+                    f64("dt") if has_dt else None, f64("sig_dt") if has_dt else None,
+                    f64("tscale") if has_dt else None]
+            ptrs = [None if a is None else a.ctypes.data for a in arrs]
+            try:
+                self.check(lib().lf_constraints_observables(self.handle, h, *ptrs))
+            except Exception:
+                c.release()
+                raise
+        return c
 
     # ---------------------------------------------------------------- hot path
     def lens_maps(self, model: Model, params, S, points, a_dis, prec=LF_PREC_FP64,
@@ -325,6 +349,25 @@ def _chi2(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC
 
 
 Context.chi2_batch = _chi2
+
+
+def _chi2_terms(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC_FP64, want_beta=False,
+                stream=None):
+    """Total chi^2 with the flux and delay terms: (chi2 [S], flags [S], terms [S,3], beta_model or None)."""
+    dev = self.device
+    chi2 = torch.empty(S, dtype=torch.float64, device=dev)
+    flags = torch.empty(S, dtype=torch.int32, device=dev)
+    terms = torch.empty((S, 3), dtype=torch.float64, device=dev)
+    bm = torch.empty((S, cons.n_fam, 2), dtype=torch.float64, device=dev) if want_beta else None
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_chi2_terms(self.handle, model.handle, pp, int(S), cons.handle, int(mode), int(prec),
+                                   C.c_void_p(chi2.data_ptr()), C.c_void_p(flags.data_ptr()),
+                                   C.c_void_p(bm.data_ptr()) if bm is not None else None,
+                                   C.c_void_p(terms.data_ptr()), _stream(stream)))
+    return chi2, flags, terms, bm
+
+
+Context.chi2_terms = _chi2_terms
 
 
 def _find(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, stream=None, out=None):

@@ -41,10 +41,42 @@ def constraints_from_sources(srcs, n_img_total, noise, sigma):
                 break
             th.append(t)
             fam.append(f)
+    src_img = []
+    for f, s in enumerate(srcs):
+        src_img += [(f, k) for k in range(min(2, len(s[3])))]
+    for f, s in enumerate(srcs):
+        for k in range(2, len(s[3])):
+            if len(src_img) >= n_img_total:
+                break
+            src_img.append((f, k))
     th = np.array(th) + noise[:len(th)]
     n = len(th)
     return {"theta": th, "family": np.array(fam, np.int32), "sig1": np.full(n, sigma),
-            "sig2": np.full(n, sigma), "phi": np.zeros(n), "a_fam": np.array([s[2] for s in srcs])}
+            "sig2": np.full(n, sigma), "phi": np.zeros(n), "a_fam": np.array([s[2] for s in srcs]),
+            "src_img": np.array(src_img, np.int32)}
+
+
+def observables(orc, tab, srcs, cons, zd, seed, sig_mag=0.15, sig_dt=1.0, H0=70.0, Om=0.3):
+    """Flux and delay data for a constraint set: magnitudes m0_f - 2.5 log10|mu| and delays
+    T_f (|theta - beta|^2 / 2 - a psi) + t0_f at each image's true (noise-free) position, plus
+    seeded Gaussian noise; about one image in six has no magnitude and one in three no delay."""
+    rng = np.random.default_rng(seed)
+    nf = len(srcs)
+    m0 = rng.uniform(22.0, 26.0, nf)
+    t0 = rng.uniform(-500.0, 500.0, nf)
+    T = np.array([orc.tdscale(zd, s[1], H0, Om) for s in srcs])
+    n = cons["theta"].shape[0]
+    mag, dt = np.zeros(n), np.zeros(n)
+    for i, (f, k) in enumerate(cons["src_img"]):
+        th, mu = srcs[f][3][k], srcs[f][4][k]
+        psi = orc.potential(tab, th[:1], th[1:])[0][0]
+        d = th - srcs[f][0]
+        mag[i] = m0[f] - 2.5 * np.log10(abs(mu))
+        dt[i] = T[f] * (0.5 * d @ d - srcs[f][2] * psi) + t0[f]
+    smag = np.where(rng.uniform(size=n) < 1 / 6, 0.0, sig_mag)
+    sdt = np.where(rng.uniform(size=n) < 1 / 3, -1.0, sig_dt)
+    return dict(cons, mag=mag + rng.normal(0, sig_mag, n), sig_mag=smag, dt=dt + rng.normal(0, sig_dt, n),
+                sig_dt=sdt, tscale=T)
 
 
 @functools.lru_cache(maxsize=None)
@@ -58,7 +90,19 @@ def cluster_constraints(seed=2611):
 
 
 @functools.lru_cache(maxsize=None)
-def small_constraints(seed, n_src=4):
+def cluster_observables(seed=2611):
+    """The cluster constraints with flux and delay data of their sources."""
+    from oracle import oracle as orc
+    cfg = W.config2(seed=seed, n_samples=1)
+    tab = orc.expand(cfg["model"], cfg["truth"])
+    grid = {"x0": -60.0, "y0": -60.0, "h": 0.25, "nx": 480, "ny": 480}
+    srcs = select_sources(orc, tab, grid, cfg["src_cand"], cfg["zs_cand"], cfg["model"]["z_d"], cfg["n_src"])
+    cons = constraints_from_sources(srcs, cfg["n_img"], cfg["noise"], cfg["sigma_img"])
+    return observables(orc, tab, srcs, cons, cfg["model"]["z_d"], seed + 1)
+
+
+@functools.lru_cache(maxsize=None)
+def _small(seed, n_src):
     from oracle import oracle as orc
     model, truth = W.tiny_model(seed, n_main=2, n_mem=25, types=[2, 3], free_params=True)
     tab = orc.expand(model, truth)
@@ -70,7 +114,20 @@ def small_constraints(seed, n_src=4):
     cons = constraints_from_sources(srcs, 10 ** 6, rng.normal(0, 0.03, (200, 2)), 0.3)
     cons["sig2"] = cons["sig1"] * rng.uniform(0.5, 1.0, cons["sig1"].size)   # elliptical errors
     cons["phi"] = rng.uniform(0, np.pi, cons["sig1"].size)
+    return model, truth, cons, tab, srcs
+
+
+def small_constraints(seed, n_src=4):
+    model, truth, cons, _, _ = _small(seed, n_src)
     return model, truth, cons
+
+
+@functools.lru_cache(maxsize=None)
+def small_observables(seed, n_src=4):
+    """small_constraints(seed) with flux and delay data."""
+    from oracle import oracle as orc
+    model, truth, cons, tab, srcs = _small(seed, n_src)
+    return model, truth, observables(orc, tab, srcs, cons, model["z_d"], seed + 7)
 
 
 def margin_ok(orc, tab, grid, beta, a, d=1e-4):

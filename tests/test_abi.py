@@ -54,3 +54,8 @@ def test_host_cosmology_helpers_match_oracle_without_gpu(orc):
     oks, ors = orc.nfw_params(70.0, 0.3, 0.3, 8e14, 5.0)
     assert abs(ks.value / oks - 1) < 1e-10 and abs(rs.value / ors - 1) < 1e-10
     assert L.lf_cosmo_adis(C.byref(c), 2.0, 1.0, C.byref(out)) == lf.LF_E_INVALID_ARG
+    for zd, zs, H0 in ((0.5, 2.0, 70.0), (0.3, 1.2, 67.0), (0.6, 9.0, 73.0)):
+        c = lf.lf_cosmo(H0, 0.3)
+        assert L.lf_cosmo_tdscale(C.byref(c), zd, zs, C.byref(out)) == 0
+        assert abs(out.value / orc.tdscale(zd, zs, H0=H0) - 1) < 1e-11
+    assert L.lf_cosmo_tdscale(C.byref(c), 2.0, 1.0, C.byref(out)) == lf.LF_E_INVALID_ARG

@@ -1,4 +1,4 @@
-"""GPU parity of lf_chi2_batch (step a4) against the FP64 oracle.
+"""GPU parity of lf_chi2_batch against the FP64 oracle.
 
 FP64 path: relative 1e-9.  MIXED path: relative 1e-3 (no chi^2 tolerance is fixed by the
 paper; 1e-3 covers the first-order propagation of |d alpha| <= 1e-5" through Eq. chi2_src

@@ -1,4 +1,4 @@
-"""GPU parity of lf_find_images (step a5) against the oracle's triangle-mapping finder.
+"""GPU parity of lf_find_images against the oracle's triangle-mapping finder.
 Counts bit-exact; image positions within 1e-4"; |d mu|/|mu| <= 1e-4 where |mu| < 100."""
 import numpy as np
 import pytest

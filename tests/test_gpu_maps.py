@@ -1,4 +1,4 @@
-"""GPU parity of lf_lens_maps (steps a1-a3, a7) against the FP64 oracle.
+"""GPU parity of lf_lens_maps against the FP64 oracle.
 
 Bar: FP64 path within ~1e-10 relative (bug detector); MIXED path |d alpha| <= 1e-5",
 relative mu error <= 1e-4 where |mu| < 100 (tolerances of the hot-path specification).

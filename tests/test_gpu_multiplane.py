@@ -1,4 +1,4 @@
-"""GPU parity of lf_multiplane_trace and lf_find_images_mp (step a6) against the oracle.
+"""GPU parity of lf_multiplane_trace and lf_find_images_mp against the oracle.
 FP64 path: ~1e-10; MIXED: |d beta| <= 1e-5" (|d alpha| <= 1e-5" times distance ratios < 1),
 relative mu <= 1e-4 where |mu| < 100; image finding as for a single plane."""
 import numpy as np
