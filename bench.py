@@ -146,15 +146,15 @@ def build_constraints(ctx, lf, torch, cfg, m, params_truth, W):
             n = cnt[j]
             keep = np.abs(mu[j, :n]) >= 0.5
             if 2 <= keep.sum() <= 7 and n <= 16 and not fl[j]:
-                srcs.append((a[j], th[j, :n][keep]))
+                srcs.append((a[j], th[j, :n][keep], z[j]))
                 if len(srcs) == cfg["n_src"]:
                     break
         k += 128
     th, fam = [], []
-    for f, (a, t) in enumerate(srcs):
+    for f, (a, t, _) in enumerate(srcs):
         for x in t[:2]:
             th.append(x); fam.append(f)
-    for f, (a, t) in enumerate(srcs):
+    for f, (a, t, _) in enumerate(srcs):
         for x in t[2:]:
             if len(th) < cfg["n_img"]:
                 th.append(x); fam.append(f)
@@ -283,6 +283,7 @@ def main():
                     "chi2_img_ms": timed(lambda: stage_chi2(prec, 1), max(1, n_rep // 2)),
                     "find_ms": timed(lambda: stage_find(prec), n_rep)}
     fp64_step_ms = st["fp64"]["maps_ms"] + st["fp64"]["chi2_src_ms"] + st["fp64"]["find_ms"]
+    obs = bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, n_rep)
 
     extras = {}
     if not args.no_extras:
@@ -321,6 +322,7 @@ def main():
                       "chi2_per_s": S / (st["fp64"]["chi2_src_ms"] * 1e-3),
                       "chi2_img_per_s": S / (st["fp64"]["chi2_img_ms"] * 1e-3)},
         "stages_ms": st,
+        "chi2_flux_td": obs,
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": "maps_lean", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
@@ -341,6 +343,32 @@ def main():
     cons.release()
     m.release()
     ctx.close()
+
+
+def bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, n_rep):
+    """chi^2 with flux and time-delay terms (lf_chi2_terms) on the 150 cluster constraints, every
+    image with a magnitude (sigma 0.15 mag) and a delay (sigma 1 day); the values are seeded
+    timing inputs: magnitudes U[22, 26], delays U[-500, 500] days."""
+    rng = np.random.default_rng(2627)
+    n = cons_np["theta"].shape[0]
+    tsc = np.array([ctx.tdscale(cfg["model"]["z_d"], s[2]) for s in srcs])
+    c = ctx.upload_constraints(dict(cons_np, mag=rng.uniform(22, 26, n), sig_mag=np.full(n, 0.15),
+                                    dt=rng.uniform(-500, 500, n), sig_dt=np.full(n, 1.0), tscale=tsc))
+    S = params.shape[0]
+    dev = params.device
+    out = {"chi2": torch.empty(S, dtype=torch.float64, device=dev),
+           "flags": torch.empty(S, dtype=torch.int32, device=dev),
+           "terms": torch.empty((S, 3), dtype=torch.float64, device=dev)}
+    res = {"samples": S, "images": n}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        for mode, tag in ((0, "src"), (1, "img")):
+            fn = lambda: ctx.chi2_terms(m, params, S, c, mode, prec, stream=stream, out=out)
+            fn()
+            t = timed(fn, n_rep if mode == 0 else max(1, n_rep // 2))
+            res["%s_%s_ms" % (name, tag)] = t
+            res["%s_%s_per_s" % (name, tag)] = S / (t * 1e-3)
+    c.release()
+    return res
 
 
 def bench_extras(ctx, lf, torch, W, stream, timed):

@@ -352,12 +352,12 @@ Context.chi2_batch = _chi2
 
 
 def _chi2_terms(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC_FP64, want_beta=False,
-                stream=None):
+                stream=None, out=None):
     """Total chi^2 with the flux and delay terms: (chi2 [S], flags [S], terms [S,3], beta_model or None)."""
     dev = self.device
-    chi2 = torch.empty(S, dtype=torch.float64, device=dev)
-    flags = torch.empty(S, dtype=torch.int32, device=dev)
-    terms = torch.empty((S, 3), dtype=torch.float64, device=dev)
+    chi2 = out["chi2"] if out else torch.empty(S, dtype=torch.float64, device=dev)
+    flags = out["flags"] if out else torch.empty(S, dtype=torch.int32, device=dev)
+    terms = out["terms"] if out else torch.empty((S, 3), dtype=torch.float64, device=dev)
     bm = torch.empty((S, cons.n_fam, 2), dtype=torch.float64, device=dev) if want_beta else None
     pp = C.c_void_p(params.data_ptr()) if params is not None else None
     self.check(lib().lf_chi2_terms(self.handle, model.handle, pp, int(S), cons.handle, int(mode), int(prec),
