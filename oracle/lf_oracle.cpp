@@ -23,7 +23,9 @@
 //     Sec. 3.3 Eq. (chi2_td), Eq. (dt0), Eq. (td_approx).
 //   * Sec. 3.4 Eq. (scaling) for member galaxies.
 //   * Sec. 3.5 Newton-Raphson image-plane solve started at the observed images.
-//   * Sec. 6 singularity maps (A3-line fields from third derivatives).
+//   * Sec. 6 singularity maps: A3-line fields from third derivatives, and the
+//     extraction of A3 lines, umbilics (D4) and swallowtails (A4) from a vertex grid
+//     with refinement of every crossing and point (the refinement the paper plans).
 // Readings where the paper is silent (profile formulas, sigma->b, eNFW, tie rules,
 // Newton stopping rules) are listed in the design notes of the repository.
 //
@@ -1249,4 +1251,352 @@ int orc_vertex_beta(const double* tab, int H, double x0, double y0, double h, in
   return 0;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Singularity maps (Sec. 6): A3 lines, umbilics (D4) and swallowtails (A4) of a
+// single-plane lens, extracted from the fields on a grid of vertices x0 + (i+1/2)h.
+//
+// Definitions (the cited formalism is not available; these follow from the cusp
+// condition): e_1,2 = kappa +- |gamma| are the eigenvalues of the deformation tensor psi_ij
+// and v_1,2 their unit eigenvectors.  A critical curve at distance ratio a is 1 - a e_k = 0,
+// and it has a cusp where v_k is tangent to it, i.e. f_k = v_k . grad e_k = 0: the A3 line of
+// e_k is the zero set of f_k (independent of a; the cusp there forms for a = 1/e_k).  v_k is
+// a line field (defined up to sign), so f_k is compared between two points only after the
+// second point's eigenvector has been aligned with the first's.  Around a point where
+// gamma = 0 (an umbilic, D4: e_1 = e_2, the two A3 lines meet) the line field turns by a half
+// turn, so the orientation product around a grid cell is -1 exactly for cells holding such a
+// point.  A swallowtail (A4) lies on an A3 line where v_k is tangent to the line: there
+// g_k = v_k . grad f_k (orientation independent) changes sign along the line.
+// ---------------------------------------------------------------------------------------
+struct SingVal {
+  double kap, g1, g2, e[2], f[2], v[2][2];
+  bool umb;
+  int flags;
+};
+
+// Fields at one point.  Eigenvector of e_1: angle phi = atan2(gamma_2, gamma_1) / 2, the
+// sign chosen with a positive x component (then y); v_2 is v_1 turned by +90 degrees with
+// the same sign rule.  f_k = v_k . grad e_k with grad e_1,2 = grad kappa +- grad |gamma|.
+static SingVal sing_at(const double* tab, int H, double x, double y) {
+  double d[9];
+  SingVal o;
+  o.flags = halo_sum(tab, H, x, y, d);
+  double p11 = d[2], p12 = d[3], p22 = d[4], p111 = d[5], p112 = d[6], p122 = d[7], p222 = d[8];
+  o.kap = 0.5 * (p11 + p22);
+  o.g1 = 0.5 * (p11 - p22);
+  o.g2 = p12;
+  double gm = std::hypot(o.g1, o.g2);
+  o.e[0] = o.kap + gm;
+  o.e[1] = o.kap - gm;
+  o.umb = gm == 0.0 || gm <= 1e-12 * std::fabs(o.kap);
+  if (o.umb) {
+    o.f[0] = o.f[1] = 0.0;
+    o.v[0][0] = 1; o.v[0][1] = 0; o.v[1][0] = 0; o.v[1][1] = 1;
+    return o;
+  }
+  double phi = 0.5 * std::atan2(o.g2, o.g1);
+  double vx = std::cos(phi), vy = std::sin(phi);
+  if (vx < 0 || (vx == 0 && vy < 0)) { vx = -vx; vy = -vy; }
+  double wx = -vy, wy = vx;
+  if (wx < 0 || (wx == 0 && wy < 0)) { wx = -wx; wy = -wy; }
+  o.v[0][0] = vx; o.v[0][1] = vy; o.v[1][0] = wx; o.v[1][1] = wy;
+  double dkx = 0.5 * (p111 + p122), dky = 0.5 * (p112 + p222);       // grad kappa
+  double d1x = 0.5 * (p111 - p122), d1y = 0.5 * (p112 - p222);       // grad gamma_1
+  double d2x = p112, d2y = p122;                                     // grad gamma_2
+  double dgx = (o.g1 * d1x + o.g2 * d2x) / gm, dgy = (o.g1 * d1y + o.g2 * d2y) / gm;
+  o.f[0] = vx * (dkx + dgx) + vy * (dky + dgy);
+  o.f[1] = wx * (dkx - dgx) + wy * (dky - dgy);
+  return o;
+}
+
+static inline double vdot(const SingVal& a, const SingVal& b, int k) {
+  return a.v[k][0] * b.v[k][0] + a.v[k][1] * b.v[k][1];
+}
+// +1 when b's eigenvector k points the same way as a's (dot >= 0), else -1
+static inline double align(const SingVal& a, const SingVal& b, int k) { return vdot(a, b, k) >= 0 ? 1.0 : -1.0; }
+// sign classes: zero counts as positive
+static inline bool neg(double v) { return v < 0; }
+
+struct SingGrid {
+  const double* tab; int H;
+  double x0, y0, h; int nx, ny;
+  std::vector<SingVal> V;
+  double X(int i) const { return x0 + (i + 0.5) * h; }
+  double Y(int j) const { return y0 + (j + 0.5) * h; }
+  const SingVal& at(int i, int j) const { return V[(size_t)j * nx + i]; }
+};
+
+// Edge test: does f_k change sign (after alignment) between vertices a and b?
+static bool edge_cross(const SingVal& a, const SingVal& b, int k) {
+  if (a.umb || b.umb) return false;
+  return neg(a.f[k]) != neg(align(a, b, k) * b.f[k]);
+}
+
+// f_k at q aligned with reference eigenvector r
+static double f_aligned(const double* tab, int H, double qx, double qy, const SingVal& r, int k, bool* umb) {
+  SingVal q = sing_at(tab, H, qx, qy);
+  if (q.umb) *umb = true;
+  return align(r, q, k) * q.f[k];
+}
+
+struct Crossing { double x, y, e, g; int k, flags; int64_t key; };
+
+// Crossing on the edge from vertex a = (ax, ay) to b = a + h (dir): linear interpolation, then
+// (refine) the Illinois variant of regula falsi on t in [0, 1] until the bracket is below
+// tol arcsec.  Then e_k and g_k = v_k . grad f_k (central differences, step 1e-3 h, f aligned
+// with v_k at the crossing) at the crossing.  Flags: 1 an evaluation met an umbilic-flagged
+// point, 2 no convergence in 100 steps, 4 (refine) |f_k| at the result above 1e-3 of its
+// larger end value: a jump, not a root.
+static Crossing refine_crossing(const SingGrid& G, double ax, double ay, double dxh, double dyh,
+                                const SingVal& A, const SingVal& B, int k, bool refine, double tol) {
+  Crossing c; c.k = k; c.flags = 0;
+  double F0 = A.f[k], F1 = align(A, B, k) * B.f[k];
+  const double Fend = std::max(std::fabs(F0), std::fabs(F1));
+  double t0 = 0.0, t1 = 1.0;
+  double t = F0 / (F0 - F1);
+  if (refine) {
+    int side = 0;
+    bool done = false;
+    for (int it = 0; it < 100 && !done; ++it) {
+      double tn = (t0 * F1 - t1 * F0) / (F1 - F0);
+      if (!(tn > t0 && tn < t1)) tn = 0.5 * (t0 + t1);
+      bool u = false;
+      double F = f_aligned(G.tab, G.H, ax + tn * dxh, ay + tn * dyh, A, k, &u);
+      if (u) c.flags |= 1;
+      t = tn;
+      if (F == 0.0) { done = true; break; }
+      if (neg(F) == neg(F0)) { t0 = tn; F0 = F; if (side == -1) F1 *= 0.5; side = -1; }
+      else { t1 = tn; F1 = F; if (side == 1) F0 *= 0.5; side = 1; }
+      if ((t1 - t0) * G.h < tol) { t = 0.5 * (t0 + t1); done = true; }
+    }
+    if (!done) c.flags |= 2;
+  }
+  c.x = ax + t * dxh;
+  c.y = ay + t * dyh;
+  SingVal P = sing_at(G.tab, G.H, c.x, c.y);
+  if (P.umb) { c.flags |= 1; c.e = P.e[k]; c.g = 0.0; return c; }
+  c.e = P.e[k];
+  // a sign change that is not a root: f (aligned) jumps where the eigenvector turns by more
+  // than a quarter turn along the edge (next to an umbilic) or across a singular centre
+  if (refine && std::fabs(P.f[k]) > 1e-3 * Fend) c.flags |= 4;
+  double d = 1e-3 * G.h;
+  bool u = false;
+  double fxp = f_aligned(G.tab, G.H, c.x + d, c.y, P, k, &u), fxm = f_aligned(G.tab, G.H, c.x - d, c.y, P, k, &u);
+  double fyp = f_aligned(G.tab, G.H, c.x, c.y + d, P, k, &u), fym = f_aligned(G.tab, G.H, c.x, c.y - d, P, k, &u);
+  if (u) c.flags |= 1;
+  c.g = P.v[k][0] * (fxp - fxm) / (2 * d) + P.v[k][1] * (fyp - fym) / (2 * d);
+  return c;
+}
+
+// g_k = v_k . grad f_k at q: f aligned with v_k(q), central differences with step d
+static double g_at(const double* tab, int H, double x, double y, int k, double d, bool* umb, double* f,
+                   double* fx, double* fy) {
+  SingVal P = sing_at(tab, H, x, y);
+  if (P.umb) *umb = true;
+  double fxp = f_aligned(tab, H, x + d, y, P, k, umb), fxm = f_aligned(tab, H, x - d, y, P, k, umb);
+  double fyp = f_aligned(tab, H, x, y + d, P, k, umb), fym = f_aligned(tab, H, x, y - d, P, k, umb);
+  *f = P.f[k];
+  *fx = (fxp - fxm) / (2 * d);
+  *fy = (fyp - fym) / (2 * d);
+  return P.v[k][0] * *fx + P.v[k][1] * *fy;
+}
+
+// Swallowtail refinement: Newton on (f_k, g_k) = 0 from the interpolated point; grad f from
+// the differences inside g (step 1e-3 h), grad g from central differences of g (step
+// 1e-2 h).  Status 0 converged (step < 1e-10") within h of the start, 1 no convergence in
+// 20 steps, 2 moved farther than h.
+static int swallowtail_newton(const SingGrid& G, int k, double* px, double* py) {
+  double x = *px, y = *py, d = 1e-3 * G.h, dg = 1e-2 * G.h;
+  bool conv = false, umb = false;
+  for (int it = 0; it < 20; ++it) {
+    double f, fx, fy, t0, t1, t2;
+    double g = g_at(G.tab, G.H, x, y, k, d, &umb, &f, &fx, &fy);
+    double gxp = g_at(G.tab, G.H, x + dg, y, k, d, &umb, &t0, &t1, &t2);
+    double gxm = g_at(G.tab, G.H, x - dg, y, k, d, &umb, &t0, &t1, &t2);
+    double gyp = g_at(G.tab, G.H, x, y + dg, k, d, &umb, &t0, &t1, &t2);
+    double gym = g_at(G.tab, G.H, x, y - dg, k, d, &umb, &t0, &t1, &t2);
+    double gx = (gxp - gxm) / (2 * dg), gy = (gyp - gym) / (2 * dg);
+    double det = fx * gy - fy * gx;
+    double sx = -(gy * f - fy * g) / det, sy = -(-gx * f + fx * g) / det;
+    x += sx; y += sy;
+    if (!std::isfinite(x) || !std::isfinite(y)) break;
+    if (std::sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
+  }
+  int st = conv ? 0 : 1;
+  if (conv && std::hypot(x - *px, y - *py) > G.h) st = 2;
+  if (umb) st |= 8;
+  if (st == 0) { *px = x; *py = y; }
+  return st;
+}
+
+// Umbilic of a cell: Newton on (gamma_1, gamma_2) = 0 from the cell centre with the Jacobian
+// from the third derivatives; status 0 accepted (converged inside the closed cell), 1 no
+// convergence in 30 steps, 2 converged outside the cell.
+static int umbilic_newton(const SingGrid& G, int i, int j, double* ux, double* uy, double* kap) {
+  double x = G.X(i) + 0.5 * G.h, y = G.Y(j) + 0.5 * G.h;
+  bool conv = false;
+  for (int it = 0; it < 30; ++it) {
+    double d[9];
+    halo_sum(G.tab, G.H, x, y, d);
+    double g1 = 0.5 * (d[2] - d[4]), g2 = d[3];
+    double J11 = 0.5 * (d[5] - d[7]), J12 = 0.5 * (d[6] - d[8]), J21 = d[6], J22 = d[7];
+    double det = J11 * J22 - J12 * J21;
+    double sx = -(J22 * g1 - J12 * g2) / det, sy = -(-J21 * g1 + J11 * g2) / det;
+    x += sx; y += sy;
+    if (std::sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
+    if (!std::isfinite(x) || !std::isfinite(y)) break;
+  }
+  double d[9];
+  halo_sum(G.tab, G.H, x, y, d);
+  *ux = x; *uy = y; *kap = 0.5 * (d[2] + d[4]);
+  if (!conv) return 1;
+  bool inside = x >= G.X(i) && x <= G.X(i + 1) && y >= G.Y(j) && y <= G.Y(j + 1);
+  return inside ? 0 : 2;
+}
+
+extern "C" {
+// Singularity map of one single-plane lens on an nx x ny vertex grid.
+// Crossings (ordered by row j; in a row the horizontal edges (i,j)-(i+1,j) by i, then the
+// vertical edges (i,j)-(i,j+1) by i; per edge k = 1 then 2): cx [2n], ck, ce (e_k), cg (g_k),
+// cfl.  Segments (cells in row-major order, k = 1 then 2): ends sa, sb (crossing index, or
+// -(umbilic index) - 1), sk.  Umbilics (cells with orientation product -1, row-major): ux
+// [2n], ukap, ustat (0 ok, 1 no convergence, 2 outside the cell; +4 a family's crossings
+// could not be joined to it).  Swallowtails (segments in order): wx [2n], wk, we, wseg, wstat
+// (refine: the interpolated point polished by Newton on (f_k, g_k); 0 ok, 1 no convergence,
+// 2 moved > h (the interpolated point is kept), +8 an umbilic-flagged evaluation).
+// counts[0..3] = crossings, segments, umbilics, swallowtails (true counts; arrays hold at most
+// cap of each); counts[4] = cells skipped next to umbilic-flagged vertices; counts[5] = cells
+// whose crossings could not be paired.
+int orc_sing_map(const double* tab, int H, double x0, double y0, double h, int nx, int ny, int refine,
+                 double tol, int cap, double* cx, int* ck, double* ce, double* cg, int* cfl, int* sa, int* sb,
+                 int* sk, double* ux, double* ukap, int* ustat, double* wx, int* wk, double* we, int* wseg,
+                 int* wstat, int* counts, int nthreads) {
+  SingGrid G;
+  G.tab = tab; G.H = H; G.x0 = x0; G.y0 = y0; G.h = h; G.nx = nx; G.ny = ny;
+  G.V.resize((size_t)nx * ny);
+  parallel_for(ny, nthreads, [&](int lo, int hi) {
+    for (int j = lo; j < hi; ++j)
+      for (int i = 0; i < nx; ++i) G.V[(size_t)j * nx + i] = sing_at(tab, H, G.X(i), G.Y(j));
+  });
+  // 1. crossings in canonical order, then their refinement
+  struct Raw { int i, j, dir, k; };
+  std::vector<Raw> raw;
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i + 1 < nx; ++i)
+      for (int k = 0; k < 2; ++k)
+        if (edge_cross(G.at(i, j), G.at(i + 1, j), k)) raw.push_back({i, j, 0, k});
+    if (j + 1 < ny)
+      for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < 2; ++k)
+          if (edge_cross(G.at(i, j), G.at(i, j + 1), k)) raw.push_back({i, j, 1, k});
+  }
+  std::vector<Crossing> X(raw.size());
+  parallel_for((int)raw.size(), nthreads, [&](int lo, int hi) {
+    for (int n = lo; n < hi; ++n) {
+      const Raw& r = raw[n];
+      const SingVal& A = G.at(r.i, r.j);
+      const SingVal& B = r.dir == 0 ? G.at(r.i + 1, r.j) : G.at(r.i, r.j + 1);
+      X[n] = refine_crossing(G, G.X(r.i), G.Y(r.j), r.dir == 0 ? h : 0.0, r.dir == 0 ? 0.0 : h, A, B, r.k,
+                             refine != 0, tol);
+      X[n].key = ((((int64_t)r.j * 2 + r.dir) * nx + r.i) * 2 + r.k);
+    }
+  });
+  auto find_x = [&](int i, int j, int dir, int k) -> int {
+    int64_t key = ((((int64_t)j * 2 + dir) * nx + i) * 2 + k);
+    int lo = 0, hi = (int)X.size();
+    while (lo < hi) { int m = (lo + hi) / 2; if (X[m].key < key) lo = m + 1; else hi = m; }
+    return (lo < (int)X.size() && X[lo].key == key) ? lo : -1;
+  };
+  // 2. cells: segments and umbilic cells
+  struct Seg { int a, b, k; };
+  std::vector<Seg> S;
+  struct Umb { int i, j, stat; double x, y, kap; };
+  std::vector<Umb> U;
+  int skipped = 0, unpaired = 0;
+  for (int j = 0; j + 1 < ny; ++j)
+    for (int i = 0; i + 1 < nx; ++i) {
+      const SingVal* c[4] = {&G.at(i, j), &G.at(i + 1, j), &G.at(i + 1, j + 1), &G.at(i, j + 1)};
+      if (c[0]->umb || c[1]->umb || c[2]->umb || c[3]->umb) { ++skipped; continue; }
+      // loop edges: bottom, right, top, left (crossing lookups by their stored edge)
+      const int ei[4] = {i, i + 1, i, i}, ej[4] = {j, j, j + 1, j}, ed[4] = {0, 1, 0, 1};
+      double P = align(*c[0], *c[1], 0) * align(*c[1], *c[2], 0) * align(*c[2], *c[3], 0) * align(*c[3], *c[0], 0);
+      int uidx = -1;
+      if (P < 0) { uidx = (int)U.size(); U.push_back({i, j, 0, 0, 0, 0}); }
+      for (int k = 0; k < 2; ++k) {
+        int xs[4], n = 0;
+        for (int m = 0; m < 4; ++m) {
+          xs[m] = find_x(ei[m], ej[m], ed[m], k);
+          if (xs[m] >= 0) ++n;
+        }
+        if (P > 0) {
+          if (n == 2) {
+            int a = -1, b = -1;
+            for (int m = 0; m < 4; ++m) if (xs[m] >= 0) { if (a < 0) a = xs[m]; else b = xs[m]; }
+            S.push_back({a, b, k});
+          } else if (n == 4) {
+            double F0 = c[0]->f[k];
+            double F1 = align(*c[0], *c[1], k) * c[1]->f[k];
+            double F2 = align(*c[0], *c[1], k) * align(*c[1], *c[2], k) * c[2]->f[k];
+            double F3 = align(*c[0], *c[3], k) * c[3]->f[k];
+            double D = F0 + F2 - F1 - F3;
+            bool cpos = D == 0.0 ? true : !neg((F0 * F2 - F1 * F3) / D);
+            if (cpos == !neg(F0)) { S.push_back({xs[0], xs[1], k}); S.push_back({xs[2], xs[3], k}); }
+            else { S.push_back({xs[0], xs[3], k}); S.push_back({xs[1], xs[2], k}); }
+          } else if (n != 0) {
+            ++unpaired;
+          }
+        } else {
+          // an odd number of lines of the family ends at the umbilic (one at a hyperbolic,
+          // one or three at an elliptic umbilic)
+          if (n == 1 || n == 3) {
+            for (int m = 0; m < 4; ++m)
+              if (xs[m] >= 0) S.push_back({xs[m], -uidx - 1, k});
+          } else {
+            U[uidx].stat |= 4;
+            if (n != 0) ++unpaired;
+          }
+        }
+      }
+    }
+  parallel_for((int)U.size(), nthreads, [&](int lo, int hi) {
+    for (int n = lo; n < hi; ++n) {
+      double x, y, kap;
+      int st = umbilic_newton(G, U[n].i, U[n].j, &x, &y, &kap);
+      U[n].stat |= st; U[n].x = x; U[n].y = y; U[n].kap = kap;
+    }
+  });
+  // 3. swallowtails: g_k changes sign between the two crossings of a segment
+  struct Sw { double x, y, e; int k, seg, stat; };
+  std::vector<Sw> W;
+  for (int n = 0; n < (int)S.size(); ++n) {
+    const Seg& s = S[n];
+    if (s.a < 0 || s.b < 0) continue;
+    const Crossing &A = X[s.a], &B = X[s.b];
+    if ((A.flags | B.flags) & 5) continue;        // umbilic-flagged evaluation or a jump
+    if (neg(A.g) == neg(B.g)) continue;
+    double u = A.g / (A.g - B.g);
+    W.push_back({A.x + u * (B.x - A.x), A.y + u * (B.y - A.y), 0.0, s.k, n, 0});
+  }
+  parallel_for((int)W.size(), nthreads, [&](int lo, int hi) {
+    for (int n = lo; n < hi; ++n) {
+      if (refine) W[n].stat = swallowtail_newton(G, W[n].k, &W[n].x, &W[n].y);
+      W[n].e = sing_at(tab, H, W[n].x, W[n].y).e[W[n].k];
+    }
+  });
+  counts[0] = (int)X.size(); counts[1] = (int)S.size(); counts[2] = (int)U.size(); counts[3] = (int)W.size();
+  counts[4] = skipped; counts[5] = unpaired;
+  for (int n = 0; n < (int)X.size() && n < cap; ++n) {
+    cx[2 * n] = X[n].x; cx[2 * n + 1] = X[n].y; ck[n] = X[n].k + 1; ce[n] = X[n].e; cg[n] = X[n].g; cfl[n] = X[n].flags;
+  }
+  for (int n = 0; n < (int)S.size() && n < cap; ++n) { sa[n] = S[n].a; sb[n] = S[n].b; sk[n] = S[n].k + 1; }
+  for (int n = 0; n < (int)U.size() && n < cap; ++n) {
+    ux[2 * n] = U[n].x; ux[2 * n + 1] = U[n].y; ukap[n] = U[n].kap; ustat[n] = U[n].stat;
+  }
+  for (int n = 0; n < (int)W.size() && n < cap; ++n) {
+    wx[2 * n] = W[n].x; wx[2 * n + 1] = W[n].y; wk[n] = W[n].k + 1; we[n] = W[n].e; wseg[n] = W[n].seg;
+    wstat[n] = W[n].stat;
+  }
+  return 0;
+}
 }  // extern "C"

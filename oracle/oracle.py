@@ -322,3 +322,31 @@ def orient(a, b, c):
 def tri_contains(B, s):
     B = _f64(B).ravel()
     return bool(lib().orc_tri_contains(_p(B), C.c_double(s[0]), C.c_double(s[1])))
+
+
+# --------------------------------------------------------------------------- singularity maps
+def sing_map(tab, grid, refine=True, tol=1e-10, cap=200000, nthreads=None):
+    """A3 crossings, segments, umbilics (D4) and swallowtails (A4) of a single-plane lens on
+    the vertex grid x0 + (i + 1/2) h (Sec. 6)."""
+    tab = _f64(tab)
+    cx, ck, ce, cg, cfl = np.zeros(2 * cap), np.zeros(cap, np.int32), np.zeros(cap), np.zeros(cap), \
+        np.zeros(cap, np.int32)
+    sa, sb, sk = np.zeros(cap, np.int32), np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+    ux, ukap, ust = np.zeros(2 * cap), np.zeros(cap), np.zeros(cap, np.int32)
+    wx, wk, we, wseg = np.zeros(2 * cap), np.zeros(cap, np.int32), np.zeros(cap), np.zeros(cap, np.int32)
+    wst = np.zeros(cap, np.int32)
+    cnt = np.zeros(6, np.int32)
+    I = C.c_int
+    lib().orc_sing_map(_p(tab), I(tab.shape[0]), C.c_double(grid["x0"]), C.c_double(grid["y0"]),
+                       C.c_double(grid["h"]), I(grid["nx"]), I(grid["ny"]), I(1 if refine else 0), C.c_double(tol),
+                       I(cap), _p(cx), _p(ck, I), _p(ce), _p(cg), _p(cfl, I), _p(sa, I), _p(sb, I), _p(sk, I),
+                       _p(ux), _p(ukap), _p(ust, I), _p(wx), _p(wk, I), _p(we), _p(wseg, I), _p(wst, I), _p(cnt, I),
+                       I(nthreads or nthreads_default()))
+    nx_, ns, nu, nw = (min(int(c), cap) for c in cnt[:4])
+    return {"cross": {"pos": cx[:2 * nx_].reshape(-1, 2), "k": ck[:nx_], "e": ce[:nx_], "g": cg[:nx_],
+                      "flags": cfl[:nx_]},
+            "seg": {"a": sa[:ns], "b": sb[:ns], "k": sk[:ns]},
+            "umb": {"pos": ux[:2 * nu].reshape(-1, 2), "kappa": ukap[:nu], "status": ust[:nu]},
+            "swt": {"pos": wx[:2 * nw].reshape(-1, 2), "k": wk[:nw], "e": we[:nw], "seg": wseg[:nw],
+                    "status": wst[:nw]},
+            "counts": cnt.copy()}
