@@ -289,6 +289,52 @@ lf_status lf_find_images_mp(lf_ctx* ctx, const lf_model* const* planes, const do
                             int32_t max_img, lf_prec prec, double* theta_out, double* mu_out,
                             int32_t* count_out, int32_t* flags, void* stream);
 
+/* ---------------------------------------------------------------- singularity-map extraction */
+/* Output lists of lf_singularity_map (all device pointers, each list holding at most cap
+ * entries; counts holds the true counts). */
+typedef struct {
+  int32_t cap;
+  double* cross_pos;     /* [cap*2] A3 crossings on grid edges                              */
+  int32_t* cross_k;      /* [cap] family: 1 (e_1 = kappa + |gamma|) or 2 (e_2)              */
+  double* cross_e;       /* [cap] e_k there: the cusp forms for distance ratio 1 / e_k       */
+  double* cross_g;       /* [cap] g_k = v_k . grad f_k there                                */
+  int32_t* cross_flags;  /* [cap] 1 umbilic-flagged evaluation, 2 no convergence, 4 a jump  */
+  int32_t* seg_a;        /* [cap] segment ends: crossing index, or -(umbilic index) - 1     */
+  int32_t* seg_b;
+  int32_t* seg_k;        /* [cap] family                                                    */
+  double* umb_pos;       /* [cap*2] umbilics (D4)                                           */
+  double* umb_kappa;     /* [cap] kappa there: the umbilic forms for distance ratio 1/kappa */
+  int32_t* umb_status;   /* [cap] 0 ok, 1 no convergence, 2 outside its cell, +4 unjoined   */
+  double* swt_pos;       /* [cap*2] swallowtails (A4)                                       */
+  int32_t* swt_k;        /* [cap] family                                                    */
+  double* swt_e;         /* [cap] e_k there                                                 */
+  int32_t* swt_seg;      /* [cap] segment it lies on                                        */
+  int32_t* swt_status;   /* [cap] 0 ok, 1 no convergence, 2 moved > h, +8 umbilic-flagged  */
+  int32_t* counts;       /* [6] crossings, segments, umbilics, swallowtails, cells skipped  */
+                         /*     next to umbilic-flagged vertices, cells left unpaired       */
+} lf_sing_out;
+
+/* Singularity map of a single-plane lens (Sec. 6): the A3 lines, where the eigenvector v_k
+ * of the deformation tensor is tangent to the critical curve of e_k (f_k = v_k . grad e_k =
+ * 0), umbilics (D4, gamma = 0, where the two families meet) and swallowtails (A4, where v_k is
+ * tangent to the A3 line: g_k = v_k . grad f_k = 0), with the refinement the paper plans.
+ * The fields are evaluated at the grid vertices x0 + (i + 1/2) h (FP64, or MIXED for the
+ * vertex pass only); f_k is compared along each grid edge after aligning the eigenvectors
+ * (line fields); crossings come in the order row j, horizontal edges by i, vertical edges by
+ * i, k = 1, 2.  refine != 0: each crossing is the root of f_k on its edge to a bracket below
+ * tol arcsec (Illinois regula falsi, FP64, <= 100 steps), swallowtails are polished by Newton
+ * on (f_k, g_k) = 0 (<= 20 steps to 1e-10"); refine = 0: linear interpolation.  Segments
+ * join the crossings of a cell (marching squares, the asymptotic decider in saddle cells);
+ * cells whose eigenvector loop has orientation product -1 hold an umbilic, found by Newton
+ * on (gamma_1, gamma_2) = 0 from the cell centre (<= 30 steps to 1e-10"), and an odd number
+ * of lines of each family ends there.  Next to singular centres and where the eigenvectors
+ * turn fast within a cell, spurious entries are flagged by their status.  When counts[0] >
+ * cap no segment, umbilic or swallowtail is produced.  params: device row [n_free] or NULL.
+ * Errors: LF_E_INVALID_ARG (grid smaller than 2 x 2 or above 2^31 vertices, cap < 1, tol <=
+ * 0, a NULL output), LF_E_UNSUPPORTED (elliptical NFW: no third derivatives). */
+lf_status lf_singularity_map(lf_ctx* ctx, const lf_model* m, const double* params, const lf_grid* grid,
+                             lf_prec prec, int32_t refine, double tol, const lf_sing_out* out, void* stream);
+
 /* ---------------------------------------------------------------- uneven batched chi^2 */
 /* One chi^2 problem of an uneven batch: a model, its constraints and S parameter samples. */
 typedef struct {

@@ -429,6 +429,37 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
   add<D3>(acc, t);
 }
 
+// Unit eigenvectors of the deformation tensor (Sec. 6): v of e_1 = kappa + |gamma| is the
+// larger of (g1 + |g|, g2) and (g2, |g| - g1), normalised; w (of e_2) is v turned by +90
+// degrees; each with a non-negative x component (then y).
+__device__ __forceinline__ void a3_vectors(double g1, double g2, double gm, double& vx, double& vy, double& wx,
+                                           double& wy) {
+  double vax = g1 + gm, vay = g2, vbx = g2, vby = gm - g1;
+  double na = vax * vax + vay * vay, nb = vbx * vbx + vby * vby;
+  if (na >= nb) { double n = 1.0 / sqrt(na); vx = vax * n; vy = vay * n; }
+  else { double n = 1.0 / sqrt(nb); vx = vbx * n; vy = vby * n; }
+  if (vx < 0 || (vx == 0 && vy < 0)) { vx = -vx; vy = -vy; }
+  wx = -vy; wy = vx;
+  if (wx < 0 || (wx == 0 && wy < 0)) { wx = -wx; wy = -wy; }
+}
+// A3-line fields f_k = v_k . grad e_k (Sec. 6) from kappa, gamma and the third derivatives;
+// false (umbilic: |gamma| <= 1e-12 |kappa|, f undefined) leaves f1, f2 untouched.
+__device__ __forceinline__ bool a3_fields(double kap, double g1, double g2, double t111, double t112, double t122,
+                                          double t222, double& f1, double& f2, double& vx, double& vy, double& wx,
+                                          double& wy) {
+  double gm = sqrt(g1 * g1 + g2 * g2);
+  if (!(gm > 1e-12 * fabs(kap)) || gm == 0.0) return false;
+  double gkx = 0.5 * (t111 + t122), gky = 0.5 * (t112 + t222);
+  double g1x = 0.5 * (t111 - t122), g1y = 0.5 * (t112 - t222);
+  double g2x = t112, g2y = t122;
+  double igm = 1.0 / gm;
+  double ggx = (g1 * g1x + g2 * g2x) * igm, ggy = (g1 * g1y + g2 * g2y) * igm;
+  a3_vectors(g1, g2, gm, vx, vy, wx, wy);
+  f1 = vx * (gkx + ggx) + vy * (gky + ggy);
+  f2 = wx * (gkx - ggx) + wy * (gky - ggy);
+  return true;
+}
+
 // FP64 epilogue of a single-plane point (Sec. 2.1): kappa, gamma, det A, mu, beta,
 // eigenvalues and the A3-line fields f_k = v_k . grad e_k (Sec. 6).
 struct Epi {
@@ -451,26 +482,9 @@ __device__ __forceinline__ void epilogue(double x, double y, double a, const Acc
   o.flags = h.flags;
   o.f1 = o.f2 = 0.0;
   if (D3) {
-    if (!(gm > 1e-12 * fabs(o.kappa)) || gm == 0.0) {
+    double vx, vy, wx, wy;
+    if (!a3_fields(o.kappa, o.g1, o.g2, h.t111, h.t112, h.t122, h.t222, o.f1, o.f2, vx, vy, wx, wy))
       o.flags |= FL_UMBILIC;
-    } else {
-      double gkx = 0.5 * (h.t111 + h.t122), gky = 0.5 * (h.t112 + h.t222);
-      double g1x = 0.5 * (h.t111 - h.t122), g1y = 0.5 * (h.t112 - h.t222);
-      double g2x = h.t112, g2y = h.t122;
-      double igm = 1.0 / gm;
-      double ggx = (o.g1 * g1x + o.g2 * g2x) * igm, ggy = (o.g1 * g1y + o.g2 * g2y) * igm;
-      // eigenvector of e1: the larger of (g1 + |g|, g2) and (g2, |g| - g1), x-component >= 0
-      double vax = o.g1 + gm, vay = o.g2, vbx = o.g2, vby = gm - o.g1;
-      double na = vax * vax + vay * vay, nb = vbx * vbx + vby * vby;
-      double vx, vy;
-      if (na >= nb) { double n = 1.0 / sqrt(na); vx = vax * n; vy = vay * n; }
-      else { double n = 1.0 / sqrt(nb); vx = vbx * n; vy = vby * n; }
-      if (vx < 0 || (vx == 0 && vy < 0)) { vx = -vx; vy = -vy; }
-      double wx = -vy, wy = vx;
-      if (wx < 0 || (wx == 0 && wy < 0)) { wx = -wx; wy = -wy; }
-      o.f1 = vx * (gkx + ggx) + vy * (gky + ggy);
-      o.f2 = wx * (gkx - ggx) + wy * (gky - ggy);
-    }
   }
 }
 

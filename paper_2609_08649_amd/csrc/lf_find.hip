@@ -14,6 +14,7 @@
 
 #include "lf_find.h"
 #include "lf_segs.h"
+#include "lf_wave.h"
 
 namespace lf {
 
@@ -91,74 +92,11 @@ __device__ bool d_tri_contains(const double* B, double sx, double sy) {
   return true;
 }
 
-// ---------------------------------------------------------------------------------------
-// FP64 lens evaluation for a handful of points (candidate polishing): one wave per point,
-// the halos of a plane split over the 64 lanes, partial sums combined by a butterfly of
-// shuffles (every lane ends with the same bits), Newton logic run redundantly by all lanes.
-// ---------------------------------------------------------------------------------------
-__device__ void member64_term(const Plane64& P, int m, double x, double y, const Quad& qd, Acc& acc) {
-  int sg = 0;
-  while (sg + 1 < NSEG && m >= P.seg.off[sg + 1]) ++sg;
-  const MemRec64 r = P.mem[m];
-  double dx = x - r.x, dy = y - r.y;
-  double r2 = fma(dx, dx, dy * dy);
-  Term<double> t;
-  t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
-  bool sing = (r2 < 1e-24) && (r.s == 0.0 || sg == SEG_POINT || sg == SEG_NFW || sg == SEG_ENFW);
-  if (sing) { acc.flags |= FL_SINGULAR; return; }
-  switch (sg) {
-    case SEG_CPJE: cpje<false>(dx, dy, r.b, r.s, r.a, r.s2, r.a2, r.das, r.da2, t); break;
-    case SEG_EPJE: epje<false>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t); break;
-    case SEG_CSIE: csie<false>(dx, dy, r.b, r.s, r.s2, t); break;
-    case SEG_ESIE: epje<false>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, false, t); break;
-    case SEG_POINT: point_mass<false>(dx, dy, r.b, t); break;
-    case SEG_NFW: nfw_circ<false>(dx, dy, r.b, r.s, t); break;
-    default: {
-      double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
-      Term<double> pr;
-      enfw_prime(xp, yp, r.b, r.s, sqrt(r.q2), qd, pr);
-      rotate_back<false>(r.c, r.sn, pr, t);
-    }
-  }
-  add<false>(acc, t);
-}
-
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ int wor(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ void plane_sum_wave(const Plane64& P, double x, double y, const Quad& qd, Acc& out) {
-  Acc acc;
-  acc.zero();
-  const int lane = threadIdx.x & 63;
-  const int H = P.n_main + P.seg.off[NSEG];
-  for (int h = lane; h < H; h += 64) {
-    if (h < P.n_main) {
-      const MainRec r = P.mains[h];
-      eval_main<false>(r, x, y, qd, acc);
-      acc.flags |= r.flags;
-    } else {
-      member64_term(P, h - P.n_main, x, y, qd, acc);
-    }
-  }
-  out.ax = wsum(acc.ax); out.ay = wsum(acc.ay);
-  out.h11 = wsum(acc.h11); out.h12 = wsum(acc.h12); out.h22 = wsum(acc.h22);
-  out.t111 = out.t112 = out.t122 = out.t222 = 0.0;
-  out.flags = wor(acc.flags);
-}
-
 __device__ void lens_eval64(const LensDev& L, const double* w, double x, double y, double& bx, double& by,
                             double* Aout, int& flags) {
   if (L.n_planes == 1) {
     Acc acc;
-    plane_sum_wave(L.pl[0], x, y, L.qd, acc);
+    plane_sum_wave<false>(L.pl[0], x, y, L.qd, acc);
     double a = w[0];
     bx = x - a * acc.ax;
     by = y - a * acc.ay;
@@ -180,7 +118,7 @@ __device__ void lens_eval64(const LensDev& L, const double* w, double x, double 
       A21 -= wi * (H[1] * Ai[0] + H[2] * Ai[2]); A22 -= wi * (H[1] * Ai[1] + H[2] * Ai[3]);
     }
     Acc acc;
-    plane_sum_wave(L.pl[j], tx, ty, L.qd, acc);
+    plane_sum_wave<false>(L.pl[j], tx, ty, L.qd, acc);
     flags |= acc.flags;
     al[2 * j] = acc.ax; al[2 * j + 1] = acc.ay;
     Hm[3 * j] = acc.h11; Hm[3 * j + 1] = acc.h12; Hm[3 * j + 2] = acc.h22;

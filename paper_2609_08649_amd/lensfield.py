@@ -59,6 +59,14 @@ class lf_points(C.Structure):
     _fields_ = [("grid", lf_grid), ("px", C.c_void_p), ("py", C.c_void_p), ("n", C.c_int64)]
 
 
+SING_FIELDS = ("cross_pos", "cross_k", "cross_e", "cross_g", "cross_flags", "seg_a", "seg_b", "seg_k", "umb_pos",
+               "umb_kappa", "umb_status", "swt_pos", "swt_k", "swt_e", "swt_seg", "swt_status", "counts")
+
+
+class lf_sing_out(C.Structure):
+    _fields_ = [("cap", C.c_int32)] + [(k, C.c_void_p) for k in SING_FIELDS]
+
+
 MAP_FIELDS = ("alpha_x", "alpha_y", "psi11", "psi12", "psi22", "kappa", "gamma1", "gamma2", "detA", "mu",
               "beta_x", "beta_y", "psi111", "psi112", "psi122", "psi222", "e1", "e2", "f1", "f2")
 
@@ -99,6 +107,7 @@ def lib():
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
                                           P, P, P, P]),
+            "lf_singularity_map": (I32, [P, P, P, C.POINTER(lf_grid), I32, I32, D, C.POINTER(lf_sing_out), P]),
             "lf_find_images_mp": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, P, I32, C.POINTER(lf_grid), I32,
                                         I32, P, P, P, P, P]),
             "lf_profile_enable": (I32, [P, I32]),
@@ -444,6 +453,40 @@ def _find_mp(self, planes, z_planes, beta, z_src, grid, max_img=16, prec=LF_PREC
 
 
 Context.find_images = _find
+
+
+def _sing_map(self, model: Model, params, grid, prec=LF_PREC_FP64, refine=True, tol=1e-10, cap=1 << 18,
+              stream=None):
+    """Singularity map of a single-plane lens (A3 crossings and segments, umbilics, swallowtails);
+    device tensors cut to the true counts (or to cap)."""
+    dev = self.device
+    f64 = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=dev)
+    i32 = lambda *sh: torch.zeros(sh, dtype=torch.int32, device=dev)
+    t = {"cross_pos": f64(cap, 2), "cross_k": i32(cap), "cross_e": f64(cap), "cross_g": f64(cap),
+         "cross_flags": i32(cap), "seg_a": i32(cap), "seg_b": i32(cap), "seg_k": i32(cap), "umb_pos": f64(cap, 2),
+         "umb_kappa": f64(cap), "umb_status": i32(cap), "swt_pos": f64(cap, 2), "swt_k": i32(cap), "swt_e": f64(cap),
+         "swt_seg": i32(cap), "swt_status": i32(cap), "counts": i32(6)}
+    o = lf_sing_out()
+    o.cap = int(cap)
+    for k in SING_FIELDS:
+        setattr(o, k, t[k].data_ptr())
+    g = lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_singularity_map(self.handle, model.handle, pp, C.byref(g), int(prec), 1 if refine else 0,
+                                        float(tol), C.byref(o), _stream(stream)))
+    (stream or torch.cuda.current_stream()).synchronize()
+    cnt = t["counts"].cpu()
+    n = [min(int(c), cap) for c in cnt[:4]]
+    return {"cross": {"pos": t["cross_pos"][:n[0]], "k": t["cross_k"][:n[0]], "e": t["cross_e"][:n[0]],
+                      "g": t["cross_g"][:n[0]], "flags": t["cross_flags"][:n[0]]},
+            "seg": {"a": t["seg_a"][:n[1]], "b": t["seg_b"][:n[1]], "k": t["seg_k"][:n[1]]},
+            "umb": {"pos": t["umb_pos"][:n[2]], "kappa": t["umb_kappa"][:n[2]], "status": t["umb_status"][:n[2]]},
+            "swt": {"pos": t["swt_pos"][:n[3]], "k": t["swt_k"][:n[3]], "e": t["swt_e"][:n[3]],
+                    "seg": t["swt_seg"][:n[3]], "status": t["swt_status"][:n[3]]},
+            "counts": cnt.numpy()}
+
+
+Context.singularity_map = _sing_map
 Context.multiplane_trace = _mp_trace
 Context.find_images_mp = _find_mp
 
