@@ -397,10 +397,50 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
     for p in planes:
         p.release()
     torch.cuda.empty_cache()
+    out["singularity_map_4096"] = bench_singularity(ctx, lf, torch, W, stream, timed)
     out["config1_latency"] = bench_config1(ctx, lf, torch, W, stream)
     out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
     out["serving"] = bench_serving(ctx, lf, torch, W)
     return out
+
+
+def bench_singularity(ctx, lf, torch, W, stream, timed, n_rep=3):
+    """Singularity map of the cluster truth model on 4096^2 vertices over 200" (the serving
+    workload's size): vertex fields with third derivatives, crossings refined to 1e-10",
+    segments, umbilics, swallowtails.  Per-stage times from the library's HIP events."""
+    import ctypes as C
+    cfg = W.config2(n_samples=1)
+    m = ctx.upload_model(cfg["model"])
+    p = torch.as_tensor(cfg["truth"][None], device="cuda")
+    grid = {"x0": -100.0, "y0": -100.0, "h": 200.0 / 4096, "nx": 4096, "ny": 4096}
+    buf = lf.sing_buffers(p.device, 1 << 21)
+    L = lf.lib()
+    res = {"vertices": 4096 * 4096, "halos": m.n_halos}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        run = lambda: ctx.singularity_map(m, p, grid, prec, True, 1e-10, stream=stream, out=buf, finish=False)
+        run()
+        torch.cuda.synchronize()
+        L.lf_profile_reset(ctx.handle)
+        L.lf_profile_enable(ctx.handle, 1)
+        t = timed(run, n_rep)
+        L.lf_profile_enable(ctx.handle, 0)
+        stages = {}
+        for k in ("maps_heavy", "maps_lean", "expand", "sing_edges", "sing_refine", "sing_cells", "sing_umb",
+                  "sing_swt"):
+            tot, cnt = C.c_double(), C.c_int64()
+            L.lf_profile_read(ctx.handle, k.encode(), C.byref(tot), C.byref(cnt))
+            if cnt.value:
+                stages[k] = tot.value / n_rep
+        c = buf["counts"].cpu().numpy()
+        res[name] = {"ms": t, "counts": {"crossings": int(c[0]), "segments": int(c[1]), "umbilics": int(c[2]),
+                                         "swallowtails": int(c[3])},
+                     "ok_umbilics": int((buf["umb_status"][:min(int(c[2]), 1 << 21)] == 0).sum().item()),
+                     "stages_ms": stages,
+                     "vertex_evals_per_s": m.n_halos * 4096 * 4096 / (t * 1e-3)}
+    m.release()
+    del buf
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_config1(ctx, lf, torch, W, stream, n_calls=30):

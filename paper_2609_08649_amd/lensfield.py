@@ -455,17 +455,23 @@ def _find_mp(self, planes, z_planes, beta, z_src, grid, max_img=16, prec=LF_PREC
 Context.find_images = _find
 
 
+def sing_buffers(device, cap):
+    """Device output lists for lf_singularity_map (reusable across calls)."""
+    f64 = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=device)
+    i32 = lambda *sh: torch.zeros(sh, dtype=torch.int32, device=device)
+    return {"cross_pos": f64(cap, 2), "cross_k": i32(cap), "cross_e": f64(cap), "cross_g": f64(cap),
+            "cross_flags": i32(cap), "seg_a": i32(cap), "seg_b": i32(cap), "seg_k": i32(cap), "umb_pos": f64(cap, 2),
+            "umb_kappa": f64(cap), "umb_status": i32(cap), "swt_pos": f64(cap, 2), "swt_k": i32(cap),
+            "swt_e": f64(cap), "swt_seg": i32(cap), "swt_status": i32(cap), "counts": i32(6)}
+
+
 def _sing_map(self, model: Model, params, grid, prec=LF_PREC_FP64, refine=True, tol=1e-10, cap=1 << 18,
-              stream=None):
+              stream=None, out=None, finish=True):
     """Singularity map of a single-plane lens (A3 crossings and segments, umbilics, swallowtails);
-    device tensors cut to the true counts (or to cap)."""
-    dev = self.device
-    f64 = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=dev)
-    i32 = lambda *sh: torch.zeros(sh, dtype=torch.int32, device=dev)
-    t = {"cross_pos": f64(cap, 2), "cross_k": i32(cap), "cross_e": f64(cap), "cross_g": f64(cap),
-         "cross_flags": i32(cap), "seg_a": i32(cap), "seg_b": i32(cap), "seg_k": i32(cap), "umb_pos": f64(cap, 2),
-         "umb_kappa": f64(cap), "umb_status": i32(cap), "swt_pos": f64(cap, 2), "swt_k": i32(cap), "swt_e": f64(cap),
-         "swt_seg": i32(cap), "swt_status": i32(cap), "counts": i32(6)}
+    device tensors cut to the true counts (or to cap).  out: buffers from sing_buffers (their
+    capacity is used); finish=False returns the raw buffers without synchronising."""
+    t = out if out is not None else sing_buffers(self.device, cap)
+    cap = t["cross_k"].numel()
     o = lf_sing_out()
     o.cap = int(cap)
     for k in SING_FIELDS:
@@ -474,6 +480,8 @@ def _sing_map(self, model: Model, params, grid, prec=LF_PREC_FP64, refine=True, 
     pp = C.c_void_p(params.data_ptr()) if params is not None else None
     self.check(lib().lf_singularity_map(self.handle, model.handle, pp, C.byref(g), int(prec), 1 if refine else 0,
                                         float(tol), C.byref(o), _stream(stream)))
+    if not finish:
+        return t
     (stream or torch.cuda.current_stream()).synchronize()
     cnt = t["counts"].cpu()
     n = [min(int(c), cap) for c in cnt[:4]]
