@@ -284,6 +284,7 @@ def main():
                     "find_ms": timed(lambda: stage_find(prec), n_rep)}
     fp64_step_ms = st["fp64"]["maps_ms"] + st["fp64"]["chi2_src_ms"] + st["fp64"]["find_ms"]
     obs = bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, n_rep)
+    inference = None if args.no_extras else bench_inference(ctx, lf, torch, W, m, cons, stream)
 
     extras = {}
     if not args.no_extras:
@@ -323,6 +324,7 @@ def main():
                       "chi2_img_per_s": S / (st["fp64"]["chi2_img_ms"] * 1e-3)},
         "stages_ms": st,
         "chi2_flux_td": obs,
+        "inference": inference,
         "kernels": kernels,
         "roofline": {"bound": "alu", "kernel": "maps_lean", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
@@ -402,6 +404,58 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
     out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
     out["serving"] = bench_serving(ctx, lf, torch, W)
     return out
+
+
+def bench_inference(ctx, lf, torch, W, m, cons, stream, n_nm=10000, nm_rounds=2000, n_steps=20000):
+    """End-to-end synthetic reconstruction of the cluster model on the device, the paper's
+    two-step workflow (Sec. 3.5, Sec. 4): n_nm Nelder-Mead runs started uniformly within the
+    prior box (source-plane chi^2, MIXED), nm_rounds evaluations each; then AIES with 32
+    walkers (the paper's ensemble size) jittered around the best fit for n_steps steps, and
+    2048 walkers for 200 steps (throughput).  Wall-clock times include every launch."""
+    lo, hi = W.cluster_prior()
+    D = lo.size
+    rng = np.random.default_rng(2615)
+    start = lo + (hi - lo) * rng.uniform(size=(n_nm, 1, D))
+    S0 = np.clip(start + 0.05 * (hi - lo) * rng.uniform(-1, 1, (n_nm, D + 1, D)), lo, hi)
+    S0[:, 0] = start[:, 0]
+    dev = torch.device("cuda", 0)
+    S = torch.as_tensor(S0, device=dev)
+    lo_t, hi_t = torch.as_tensor(lo, device=dev), torch.as_tensor(hi, device=dev)
+    nev = torch.zeros(n_nm, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = ctx.nelder_mead(m, cons, S, lo_t, hi_t, nm_rounds, prec=lf.LF_PREC_MIXED, n_evals=nev, stream=stream)
+    torch.cuda.synchronize()
+    t_nm = time.perf_counter() - t0
+    fb = f[:, 0].cpu().numpy()
+    best = int(np.argmin(fb))
+    x_best = S[best, 0].cpu().numpy()
+    evals = int(nev.sum().item())
+    res = {"nm": {"runs": n_nm, "rounds": nm_rounds, "evals": evals, "seconds": t_nm, "chi2_per_s": evals / t_nm,
+                  "best_chi2": float(fb[best]), "median_best_chi2": float(np.median(fb)),
+                  "best_params": [float(v) for v in x_best]}}
+    for K, steps in ((32, n_steps), (2048, 200)):
+        X0 = x_best * (1 + 1e-4 * rng.normal(size=(K, D)))
+        X = torch.as_tensor(np.clip(X0, lo, hi), device=dev)
+        lp = torch.zeros(K, dtype=torch.float64, device=dev)
+        acc = torch.zeros(K, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.aies(m, cons, X, lp, lo_t, hi_t, steps, 2616, prec=lf.LF_PREC_MIXED, init_lp=True, n_accept=acc,
+                 stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        lpn = lp.cpu().numpy()
+        res["aies_%d" % K] = {"walkers": K, "steps": steps, "seconds": dt, "ms_per_step": dt * 1e3 / steps,
+                              "chi2_per_s": K * steps / dt, "acceptance": float(acc.sum().item()) / (K * steps),
+                              "best_chi2": float(-2 * lpn.max())}
+    a = res["aies_32"]
+    res["paper_scale_estimate_s"] = {
+        "workflow": "1e4 Nelder-Mead runs + 32 AIES walkers x 1e5 steps (the Ares setup of Sec. 4)",
+        "nm_s": t_nm * 1e4 / n_nm, "aies_s": a["ms_per_step"] * 1e5 / 1e3,
+        "total_s": t_nm * 1e4 / n_nm + a["ms_per_step"] * 1e5 / 1e3,
+        "paper_reported": "about 11 hours on 16 CPU cores"}
+    return res
 
 
 def bench_singularity(ctx, lf, torch, W, stream, timed, n_rep=3):

@@ -335,6 +335,42 @@ typedef struct {
 lf_status lf_singularity_map(lf_ctx* ctx, const lf_model* m, const double* params, const lf_grid* grid,
                              lf_prec prec, int32_t refine, double tol, const lf_sing_out* out, void* stream);
 
+/* ---------------------------------------------------------------- inference on the device */
+/* Affine-invariant ensemble sampler (Sec. 3.5; the stretch move of Goodman & Weare): n_steps
+ * steps of K walkers (K even, >= 4) in the n_free parameters of the model, walkers and
+ * log-probabilities staying on the device.  log p = -chi^2 / 2 (lf_chi2_terms in the given mode
+ * and precision, flux and delay terms included when the constraints carry them) inside the
+ * prior box lo <= x <= hi, -inf outside it or where chi^2 is undefined.  Each step updates
+ * the two halves of the ensemble in turn, each against the other: walker k of the moving
+ * half proposes Y = X_j + z (X_k - X_j) (j drawn from the other half, z = ((a-1) u + 1)^2 / a)
+ * and takes it when log u' < (D-1) log z + log p(Y) - log p(X_k).  u = the top 53 bits of
+ * output n of SplitMix64 seeded with seed, n = ((t * 2 + half) * K + k) * 3 + d for step t
+ * (step0 + s), walker k and draw d (0 partner, 1 stretch, 2 acceptance): a run continued with
+ * step0 = the steps done so far reproduces an uninterrupted one.
+ * Device pointers: X [K * D] and lp [K] in/out (init_lp != 0: lp computed from X first);
+ * lo, hi [D]; chain [n_steps * K * D] and lp_chain [n_steps * K] (state after each step; NULL:
+ * not recorded); n_accept [K] accumulated (NULL: not counted).  Errors: LF_E_INVALID_ARG (no
+ * free parameter, K odd or < 4, a <= 1, bad mode/precision), those of lf_chi2_terms. */
+lf_status lf_aies_run(lf_ctx* ctx, const lf_model* m, const lf_cons* c, int32_t mode, lf_prec prec, int32_t K,
+                      double* X, double* lp, int32_t init_lp, const double* lo, const double* hi, double a,
+                      uint64_t seed, int64_t step0, int32_t n_steps, double* chain, double* lp_chain,
+                      int32_t* n_accept, void* stream);
+
+/* Nelder-Mead downhill simplex (Sec. 3.5) for R independent runs in lockstep: the R initial
+ * simplices [R][D+1][D] (device, in/out) are evaluated, then n_rounds rounds each evaluate
+ * one pending point per run (reflection; expansion or contraction; shrink vertices one per
+ * round).  f = chi^2 (as in lf_aies_run), +inf outside the prior box or where undefined.
+ * Coefficients 1, 2, 1/2, 1/2 and the rules of Lagarias et al. (1998): reflection accepted
+ * when f_0 <= f_r < f_{D-1}; expansion when f_r < f_0 (the better of the two kept); outside
+ * contraction when f_{D-1} <= f_r < f_D (kept if <= f_r), inside when f_r >= f_D (kept if <
+ * f_D); otherwise shrink towards the best vertex.  On return the simplices are sorted by f
+ * (fvals [R][D+1], ties in insertion order) and n_evals [R] (or NULL) counts evaluations.
+ * Errors: LF_E_INVALID_ARG (no free parameter, R < 1, bad mode/precision), those of
+ * lf_chi2_terms. */
+lf_status lf_nelder_mead_run(lf_ctx* ctx, const lf_model* m, const lf_cons* c, int32_t mode, lf_prec prec,
+                             int32_t R, double* simplex, double* fvals, const double* lo, const double* hi,
+                             int32_t n_rounds, int32_t* n_evals, void* stream);
+
 /* ---------------------------------------------------------------- uneven batched chi^2 */
 /* One chi^2 problem of an uneven batch: a model, its constraints and S parameter samples. */
 typedef struct {

@@ -107,6 +107,8 @@ def lib():
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
                                           P, P, P, P]),
+            "lf_aies_run": (I32, [P, P, P, I32, I32, I32, P, P, I32, P, P, D, C.c_uint64, I64, I32, P, P, P, P]),
+            "lf_nelder_mead_run": (I32, [P, P, P, I32, I32, I32, P, P, P, P, I32, P, P]),
             "lf_singularity_map": (I32, [P, P, P, C.POINTER(lf_grid), I32, I32, D, C.POINTER(lf_sing_out), P]),
             "lf_find_images_mp": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, P, I32, C.POINTER(lf_grid), I32,
                                         I32, P, P, P, P, P]),
@@ -495,6 +497,31 @@ def _sing_map(self, model: Model, params, grid, prec=LF_PREC_FP64, refine=True, 
 
 
 Context.singularity_map = _sing_map
+
+
+def _aies(self, model: Model, cons: Constraints, X, lp, lo, hi, n_steps, seed, step0=0, a=2.0, mode=0,
+          prec=LF_PREC_MIXED, init_lp=False, chain=None, lp_chain=None, n_accept=None, stream=None):
+    """AIES steps on device tensors X [K, D] and lp [K] (updated in place)."""
+    K = X.shape[0]
+    self.check(lib().lf_aies_run(self.handle, model.handle, cons.handle, int(mode), int(prec), int(K),
+                                 _ptr(X), _ptr(lp), 1 if init_lp else 0, _ptr(lo), _ptr(hi), float(a),
+                                 C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), int(step0), int(n_steps), _ptr(chain),
+                                 _ptr(lp_chain), _ptr(n_accept), _stream(stream)))
+
+
+def _nelder_mead(self, model: Model, cons: Constraints, simplex, lo, hi, n_rounds, mode=0, prec=LF_PREC_MIXED,
+                 fvals=None, n_evals=None, stream=None):
+    """Nelder-Mead rounds on device simplices [R, D+1, D] (updated in place, sorted); returns f."""
+    R, V, D = simplex.shape
+    f = fvals if fvals is not None else torch.empty((R, V), dtype=torch.float64, device=simplex.device)
+    self.check(lib().lf_nelder_mead_run(self.handle, model.handle, cons.handle, int(mode), int(prec), int(R),
+                                        _ptr(simplex), _ptr(f), _ptr(lo), _ptr(hi), int(n_rounds), _ptr(n_evals),
+                                        _stream(stream)))
+    return f
+
+
+Context.aies = _aies
+Context.nelder_mead = _nelder_mead
 Context.multiplane_trace = _mp_trace
 Context.find_images_mp = _find_mp
 

@@ -131,6 +131,15 @@ def _cluster_model(rng, n_members, field_half=100.0, z_d=0.5, free_offset=0):
     return model, np.array(truth)
 
 
+def cluster_prior():
+    """Uniform prior box of the cluster model's free parameters (layout of _cluster_model):
+    per main halo x, y in [-30, 30]", sigma in [500, 1300] km/s, s in [2, 60] kpc, q in
+    [0.5, 0.99], PA in [0, 180] deg; v* in [150, 300] km/s, theta*_cut in [2, 20]"."""
+    lo = np.array([-30.0, -30.0, 500.0, 2.0, 0.5, 0.0] * 2 + [150.0, 2.0])
+    hi = np.array([30.0, 30.0, 1300.0, 60.0, 0.99, 180.0] * 2 + [300.0, 20.0])
+    return lo, hi
+
+
 def jitter(rng, truth, n_samples):
     """Gaussian ball around the truth (the AIES start of Sec. 3.5): 1% relative on
     velocity dispersions, cores, v* and cut radius; 0.2" on positions; 0.02 on q;
