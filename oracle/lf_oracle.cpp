@@ -193,7 +193,7 @@ static double dist(double z1, double z2, double H0, double Om) {
 //   POINT: b = Einstein radius;  SIS: b;  SIE: b, q, s (core);  PJE: b, q, s, a;
 //   NFW: b = kappa_s, s = r_s;  ENFW: b = kappa_s, s = r_s, q, pa.
 // ----------------------------------------------------------------------------
-enum { POINT = 0, SIS = 1, SIE = 2, PJE = 3, NFW = 4, ENFW = 5 };
+enum { POINT = 0, SIS = 1, SIE = 2, PJE = 3, NFW = 4, ENFW = 5, SHEAR = 6, MPOLE3 = 7 };
 enum { F_SINGULAR = 1, F_GSING = 2, F_NOCONV = 4, F_REJECT = 8, F_MERGED = 16, F_OVERFLOW = 32, F_UMBILIC = 64 };
 
 // Cored isothermal ellipsoid, kappa = (b/2) / sqrt(s^2 + x^2 + y^2/q^2), major axis on x.
@@ -281,9 +281,31 @@ static bool halo_alpha(const double* row, const T& X, const T& Y, T& ax, T& ay) 
   double xc = row[1], yc = row[2], b = row[3], q = row[4], pa = row[5], s = row[6], a = row[7];
   T dx = X - xc, dy = Y - yc;
   double r2v = val(dx) * val(dx) + val(dy) * val(dy);
-  bool singular_type = (type == POINT || type == SIS || type == NFW || type == ENFW ||
+  bool singular_type = (type == POINT || type == SIS || type == NFW || type == ENFW || type == MPOLE3 ||
                         ((type == SIE || type == PJE) && s == 0.0));
   if (singular_type && r2v < 1e-24) { ax = T(0.0); ay = T(0.0); return true; }
+  if (type == SHEAR) {
+    // external shear of amplitude b and angle pa: psi = (b/2) [(x^2 - y^2) cos 2pa + 2 x y sin 2pa]
+    double c2 = std::cos(2 * pa), s2 = std::sin(2 * pa);
+    ax = b * (c2 * dx + s2 * dy);
+    ay = b * (s2 * dx - c2 * dy);
+    return false;
+  }
+  if (type == MPOLE3) {
+    // m = 3 multipole with psi ~ r^2: psi = (b/3) r^2 cos 3(phi - pa) = (b/3) (x'^3 - 3 x' y'^2) / r
+    // in the frame turned by pa; alpha = grad psi
+    double c = std::cos(pa), sn = std::sin(pa);
+    T xp = c * dx + sn * dy, yp = -sn * dx + c * dy;
+    T r = sqrt(xp * xp + yp * yp);
+    T u = xp * xp * xp - 3.0 * xp * yp * yp;
+    T ux = 3.0 * xp * xp - 3.0 * yp * yp, uy = -6.0 * xp * yp;
+    double A = b / 3.0;
+    T r3 = r * r * r;
+    T axp = A * (ux / r - u * xp / r3), ayp = A * (uy / r - u * yp / r3);
+    ax = c * axp - sn * ayp;
+    ay = sn * axp + c * ayp;
+    return false;
+  }
   if (type == POINT) {
     T r2 = dx * dx + dy * dy;
     ax = b * b * dx / r2; ay = b * b * dy / r2; return false;
@@ -399,10 +421,17 @@ static double halo_potential(const double* row, double X, double Y, bool* singul
   double xc = row[1], yc = row[2], b = row[3], q = row[4], pa = row[5], s = row[6], a = row[7];
   double dx = X - xc, dy = Y - yc;
   double r2 = dx * dx + dy * dy;
-  bool singular_type = (type == POINT || type == SIS || type == NFW || type == ENFW ||
+  bool singular_type = (type == POINT || type == SIS || type == NFW || type == ENFW || type == MPOLE3 ||
                         ((type == SIE || type == PJE) && s == 0.0));
   *singular = singular_type && r2 < 1e-24;
   if (*singular) return 0.0;
+  if (type == SHEAR)
+    return 0.5 * b * ((dx * dx - dy * dy) * std::cos(2 * pa) + 2 * dx * dy * std::sin(2 * pa));
+  if (type == MPOLE3) {
+    double c = std::cos(pa), sn = std::sin(pa);
+    double xp = c * dx + sn * dy, yp = -sn * dx + c * dy;
+    return (b / 3.0) * (xp * xp * xp - 3 * xp * yp * yp) / std::sqrt(r2);
+  }
   if (type == POINT) return b * b * 0.5 * std::log(r2);
   if (type == SIS) return b * std::sqrt(r2);
   if (type == NFW) return nfw_potential(r2, b, s);
@@ -542,7 +571,7 @@ int orc_expand(int n_main, const int* main_type, const int* main_bind /*[n_main*
     const double* r = out + 8 * h;
     for (int k = 1; k < 8; ++k) if (!std::isfinite(r[k])) return -3;
     int t = (int)r[0];
-    if (t < 0 || t > 5) return -4;
+    if (t < 0 || t > 7) return -4;
     if (!(r[4] > 0 && r[4] <= 1)) return -5;
     if (r[3] < 0 || r[6] < 0) return -6;
     if (t == PJE && !(r[7] > r[6])) return -7;

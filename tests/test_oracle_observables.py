@@ -7,7 +7,7 @@ from scipy import integrate
 
 from paper_2609_08649_amd import workloads as W
 
-POINT, SIS, SIE, PJE, NFW, ENFW = 0, 1, 2, 3, 4, 5
+POINT, SIS, SIE, PJE, NFW, ENFW, SHEAR, MPOLE3 = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def row(t, x=0.0, y=0.0, b=1.0, q=1.0, pa=0.0, s=0.0, a=0.0):
@@ -25,6 +25,8 @@ PROFILES = [
     ("epje", row(PJE, -1.0, 0.4, b=2.5, q=0.7, pa=2.1, s=0.3, a=6.0)),
     ("nfw", row(NFW, 0.5, 0.5, b=0.25, s=9.0)),
     ("enfw", row(ENFW, 0.5, 0.5, b=0.25, q=0.7, pa=0.4, s=9.0)),
+    ("shear", row(SHEAR, 0.5, -0.5, b=0.07, pa=0.9)),
+    ("mpole3", row(MPOLE3, -0.5, 0.5, b=0.05, pa=2.0)),
 ]
 
 

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 from scipy import integrate
 
-POINT, SIS, SIE, PJE, NFW, ENFW = 0, 1, 2, 3, 4, 5
+POINT, SIS, SIE, PJE, NFW, ENFW, SHEAR, MPOLE3 = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def row(t, x=0.0, y=0.0, b=1.0, q=1.0, pa=0.0, s=0.0, a=0.0):
@@ -55,6 +55,10 @@ def kappa_def(r, x, y):
     if t in (NFW, ENFW):
         qq = q if t == ENFW else 1.0
         return nfw_kappa_X(np.sqrt(xp ** 2 + yp ** 2 / qq ** 2) / s, b)
+    if t == SHEAR:                   # psi quadratic and traceless
+        return np.zeros_like(x)
+    if t == MPOLE3:                  # psi = (b/3) r^2 cos 3phi': nabla^2 (r^2 cos 3phi) = (4 - 9) cos 3phi
+        return -(5.0 / 6.0) * b * np.cos(3 * np.arctan2(yp, xp))
     raise ValueError
 
 
@@ -66,8 +70,10 @@ CASES = [
     row(PJE, 0.0, 0.0, b=1.2, q=1.0, s=0.0, a=5.0),
     row(NFW, -0.5, 0.5, b=0.3, s=15.0),
     row(ENFW, 0.2, 0.1, b=0.25, q=0.65, pa=1.1, s=20.0),
+    row(SHEAR, 0.4, -0.3, b=0.07, pa=0.8),
+    row(MPOLE3, -0.2, 0.6, b=0.05, pa=1.3),
 ]
-IDS = ["sis", "sie_cored", "sie_singular", "pje_ell", "pje_circ_trunc", "nfw", "enfw"]
+IDS = ["sis", "sie_cored", "sie_singular", "pje_ell", "pje_circ_trunc", "nfw", "enfw", "shear", "mpole3"]
 
 
 def pts(seed, n=40, half=8.0):
@@ -221,7 +227,7 @@ def test_enfw_circular_limit_equals_nfw(orc):
         assert np.allclose(a[k], b[k], rtol=1e-8, atol=1e-12)
 
 
-@pytest.mark.parametrize("r", CASES[1:4] + CASES[6:], ids=["sie_cored", "sie_singular", "pje", "enfw"])
+@pytest.mark.parametrize("r", CASES[1:4] + CASES[6:], ids=["sie_cored", "sie_singular", "pje", "enfw", "shear", "mpole3"])
 def test_rotation_covariance(orc, r):
     x, y = pts(10, 10)
     phi = 0.83
@@ -254,3 +260,39 @@ def test_table_order_sum_is_superposition(orc):
     parts = [orc.maps(tab[h:h + 1], x, y, 0.6) for h in range(tab.shape[0])]
     for k in ("ax", "ay", "p11", "p12", "p22", "p111", "p222"):
         assert np.allclose(tot[k], sum(p[k] for p in parts), rtol=1e-12, atol=1e-12)
+
+
+def test_external_shear_is_uniform(orc):
+    """gamma_1 = b cos 2 pa, gamma_2 = b sin 2 pa everywhere, kappa = 0, no third derivatives;
+    alpha vanishes at the reference point."""
+    b, pa = 0.08, 0.7
+    r = row(SHEAR, 1.0, -2.0, b=b, pa=pa)
+    x, y = pts(21)
+    m = orc.maps(r, x, y, 1.0)
+    assert np.allclose(m["gamma1"], b * np.cos(2 * pa), rtol=1e-14)
+    assert np.allclose(m["gamma2"], b * np.sin(2 * pa), rtol=1e-14)
+    assert np.allclose(m["kappa"], 0.0, atol=1e-16)
+    for k in ("p111", "p112", "p122", "p222"):
+        assert np.all(m[k] == 0.0)
+    ax, ay = orc.alpha(r, np.array([1.0]), np.array([-2.0]))
+    assert ax[0] == 0.0 and ay[0] == 0.0
+
+
+def test_multipole_axis_and_threefold_symmetry(orc):
+    """psi = (b/3) r^2 cos 3(phi - pa): on the axis phi = pa, alpha = (2b/3) r along it (from
+    d psi / d r = 2 psi / r and d psi / d phi = 0); turning the point by 120 degrees about the
+    centre turns alpha by 120 degrees."""
+    b, pa, xc, yc = 0.06, 0.4, 0.3, -0.1
+    r = row(MPOLE3, xc, yc, b=b, pa=pa)
+    rad = np.array([0.5, 2.0, 7.0])
+    ax, ay = orc.alpha(r, xc + rad * np.cos(pa), yc + rad * np.sin(pa))
+    assert np.allclose(ax, 2 * b / 3 * rad * np.cos(pa), rtol=1e-13)
+    assert np.allclose(ay, 2 * b / 3 * rad * np.sin(pa), rtol=1e-13)
+    x, y = pts(22)
+    t = 2 * np.pi / 3
+    c, s_ = np.cos(t), np.sin(t)
+    a0x, a0y = orc.alpha(r, x, y)
+    dx, dy = x - xc, y - yc
+    a1x, a1y = orc.alpha(r, xc + c * dx - s_ * dy, yc + s_ * dx + c * dy)
+    assert np.allclose(a1x, c * a0x - s_ * a0y, rtol=1e-11, atol=1e-13)
+    assert np.allclose(a1y, s_ * a0x + c * a0y, rtol=1e-11, atol=1e-13)
