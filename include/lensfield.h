@@ -60,14 +60,20 @@ enum {
 
 typedef enum { LF_PREC_FP64 = 0, LF_PREC_MIXED = 1 } lf_prec;
 
-/* Halo profiles.  Field meaning per profile (all a_dis-free, arcsec):
+/* Halo profiles.  Field meaning per profile (all a_dis-free, arcsec; SHEAR and MPOLE3 only as
+ * main components):
  *   LF_POINT  b = Einstein radius (alpha = b^2 r / |r|^2)
  *   LF_SIS    b = isothermal strength (|alpha| = b)
  *   LF_SIE    cored isothermal ellipsoid, kappa = (b/2) / sqrt(s^2 + x'^2 + y'^2/q^2)
  *   LF_PJE    pseudo-Jaffe / dPIE = SIE(b, q, s) - SIE(b, q, a), 0 <= s < a (Sec. 3.4)
  *   LF_NFW    circular NFW: b = kappa_s, s = r_s
- *   LF_ENFW   elliptical NFW: kappa(xi), xi^2 = x'^2 + y'^2/q^2; b = kappa_s, s = r_s */
-typedef enum { LF_POINT = 0, LF_SIS = 1, LF_SIE = 2, LF_PJE = 3, LF_NFW = 4, LF_ENFW = 5 } lf_profile;
+ *   LF_ENFW   elliptical NFW: kappa(xi), xi^2 = x'^2 + y'^2/q^2; b = kappa_s, s = r_s
+ *   LF_SHEAR  external shear (Sec. 4): psi = (b/2) [(x^2 - y^2) cos 2pa + 2 x y sin 2pa] about
+ *             (x, y); b = amplitude, pa = angle; q, s, a unused
+ *   LF_MPOLE3 m = 3 multipole with psi ~ r^2 (Sec. 4): psi = (b/3) r^2 cos 3(phi - pa) about
+ *             (x, y); b = amplitude, pa = angle; q, s, a unused */
+typedef enum { LF_POINT = 0, LF_SIS = 1, LF_SIE = 2, LF_PJE = 3, LF_NFW = 4, LF_ENFW = 5, LF_SHEAR = 6,
+               LF_MPOLE3 = 7 } lf_profile;
 
 /* How a raw value becomes a lensing-unit field. */
 typedef enum {

@@ -297,7 +297,7 @@ extern "C" lf_status lf_model_upload(lf_ctx* ctx, const lf_component* mainc, int
   int n_mem = mem ? mem->n : 0;
   if (n_mem < 0) return ctx->fail(LF_E_INVALID_ARG, "negative member count");
   for (int m = 0; m < n_main; ++m) {
-    if (mainc[m].type < LF_POINT || mainc[m].type > LF_ENFW) return ctx->fail(LF_E_INVALID_ARG, "main %d: bad profile", m);
+    if (mainc[m].type < LF_POINT || mainc[m].type > LF_MPOLE3) return ctx->fail(LF_E_INVALID_ARG, "main %d: bad profile", m);
     for (int k = 0; k < 7; ++k)
       if (!bind_ok(mainc[m].f[k], n_free)) return ctx->fail(LF_E_INVALID_ARG, "main %d field %d: bad binding", m, k);
     bool m200 = mainc[m].f[2].xform == LF_XF_M200, c200 = mainc[m].f[5].xform == LF_XF_C200;

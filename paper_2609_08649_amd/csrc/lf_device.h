@@ -11,7 +11,7 @@
 
 namespace lf {
 
-enum { T_POINT = 0, T_SIS = 1, T_SIE = 2, T_PJE = 3, T_NFW = 4, T_ENFW = 5 };
+enum { T_POINT = 0, T_SIS = 1, T_SIE = 2, T_PJE = 3, T_NFW = 4, T_ENFW = 5, T_SHEAR = 6, T_MPOLE3 = 7 };
 enum { FL_SINGULAR = 1, FL_GSING = 2, FL_NOCONV = 4, FL_REJECT = 8, FL_MERGED = 16,
        FL_OVERFLOW = 32, FL_UMBILIC = 64, FL_INVALID = 128 };
 
@@ -365,11 +365,62 @@ __device__ __forceinline__ double pot_enfw(double xp, double yp, double ks, doub
   return 0.5 * q * I;
 }
 // Potential of one main component (0 on a singular centre, where its deflection is 0 too).
+// A point exactly on the centre of a profile whose derivatives diverge there gets no term.
+__device__ __forceinline__ bool main_singular(const MainRec& r) {
+  return r.type == T_POINT || r.type == T_SIS || r.type == T_NFW || r.type == T_ENFW || r.type == T_MPOLE3 ||
+         ((r.type == T_SIE || r.type == T_PJE) && r.s == 0.0);
+}
+
+// External shear about the component's centre: gamma_1 = b cos 2pa, gamma_2 = b sin 2pa
+// (from the cosine and sine of pa: cos 2pa = c^2 - s^2, sin 2pa = 2 c s).
+template <bool D3>
+__device__ __forceinline__ void ext_shear(double dx, double dy, double b, double c, double sn, Term<double>& t) {
+  const double g1 = b * (c * c - sn * sn), g2 = b * (2.0 * c * sn);
+  t.ax = g1 * dx + g2 * dy;
+  t.ay = g2 * dx - g1 * dy;
+  t.h11 = g1; t.h12 = g2; t.h22 = -g1;
+  t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
+}
+// m = 3 multipole psi = A r^2 cos 3phi' (A = b/3) in the frame turned by pa, x = x', y = y':
+// alpha = A (2x^4 + 3x^2y^2 - 3y^4, -7x^3y - 3xy^3) / r^3,
+// psi_11 = A (2x^5 + 5x^3y^2 + 15xy^4) / r^5, psi_12 = -A (15x^2y^3 + 3y^5) / r^5,
+// psi_22 = A (5x^3y^2 - 7x^5) / r^5, psi_111 = 15A y^4 (y^2 - 3x^2) / r^7,
+// psi_112 = 15A x y^3 (3x^2 - y^2) / r^7, psi_122 = 15A x^2 y^2 (y^2 - 3x^2) / r^7,
+// psi_222 = 15A x^3 y (3x^2 - y^2) / r^7; then rotated back.
+template <bool D3>
+__device__ __forceinline__ void mpole3(double dx, double dy, double b, double c, double sn, Term<double>& t) {
+  const double x = c * dx + sn * dy, y = c * dy - sn * dx;
+  const double A = b / 3.0, x2 = x * x, y2 = y * y, r2 = x2 + y2;
+  const double ir = frsq(r2), ir2 = ir * ir, ir3 = ir2 * ir, ir5 = ir3 * ir2;
+  Term<double> p;
+  p.ax = A * (2.0 * x2 * x2 + 3.0 * x2 * y2 - 3.0 * y2 * y2) * ir3;
+  p.ay = -A * x * y * (7.0 * x2 + 3.0 * y2) * ir3;
+  p.h11 = A * x * (2.0 * x2 * x2 + 5.0 * x2 * y2 + 15.0 * y2 * y2) * ir5;
+  p.h12 = -A * y * y2 * (15.0 * x2 + 3.0 * y2) * ir5;
+  p.h22 = A * x * x2 * (5.0 * y2 - 7.0 * x2) * ir5;
+  p.t111 = p.t112 = p.t122 = p.t222 = 0.0;
+  if (D3) {
+    const double k = 15.0 * A * ir5 * ir2;
+    p.t111 = k * y2 * y2 * (y2 - 3.0 * x2);
+    p.t112 = k * x * y * y2 * (3.0 * x2 - y2);
+    p.t122 = k * x2 * y2 * (y2 - 3.0 * x2);
+    p.t222 = k * x * x2 * y * (3.0 * x2 - y2);
+  }
+  rotate_back<D3>(c, sn, p, t);
+}
+
 __device__ __forceinline__ double pot_main(const MainRec& r, double px, double py, const Quad& qd) {
   const double dx = px - r.x, dy = py - r.y, r2 = fma(dx, dx, dy * dy);
-  const bool singular = (r.type == T_POINT || r.type == T_SIS || r.type == T_NFW || r.type == T_ENFW || r.s == 0.0);
-  if (singular && r2 < 1e-24) return 0.0;
+  if (main_singular(r) && r2 < 1e-24) return 0.0;
   switch (r.type) {
+    case T_SHEAR: {
+      const double c2 = r.c * r.c - r.sn * r.sn, s2 = 2.0 * r.c * r.sn;
+      return 0.5 * r.b * ((dx * dx - dy * dy) * c2 + 2.0 * dx * dy * s2);
+    }
+    case T_MPOLE3: {
+      const double x = r.c * dx + r.sn * dy, y = r.c * dy - r.sn * dx;
+      return (r.b / 3.0) * x * (x * x - 3.0 * y * y) * frsq(r2);
+    }
     case T_POINT: return r.b * r.b * 0.5 * log(r2);
     case T_SIS: return r.b * sqrt(r2);
     case T_NFW: return pot_nfw(r2, r.b, r.s);
@@ -398,10 +449,10 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
   double r2 = fma(dx, dx, dy * dy);
   Term<double> t;
   t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
-  bool singular = (r.type == T_POINT || r.type == T_SIS || r.type == T_NFW || r.type == T_ENFW ||
-                   r.s == 0.0);
-  if (singular && r2 < 1e-24) { acc.flags |= FL_SINGULAR; return; }
+  if (main_singular(r) && r2 < 1e-24) { acc.flags |= FL_SINGULAR; return; }
   switch (r.type) {
+    case T_SHEAR: ext_shear<D3>(dx, dy, r.b, r.c, r.sn, t); break;
+    case T_MPOLE3: mpole3<D3>(dx, dy, r.b, r.c, r.sn, t); break;
     case T_POINT: point_mass<D3>(dx, dy, r.b, t); break;
     case T_SIS: csie<D3>(dx, dy, r.b, 0.0, 0.0, t); break;
     case T_SIE:

@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 
 # Profile codes (shared vocabulary of the model description).
-POINT, SIS, SIE, PJE, NFW, ENFW = 0, 1, 2, 3, 4, 5
+POINT, SIS, SIE, PJE, NFW, ENFW, SHEAR, MPOLE3 = 0, 1, 2, 3, 4, 5, 6, 7
 PROFILE_NAMES = {POINT: "point", SIS: "sis", SIE: "sie", PJE: "pje", NFW: "nfw", ENFW: "enfw"}
 
 # Transform codes: how a bound raw value becomes a lensing-unit field.
@@ -281,6 +281,10 @@ def tiny_model(seed: int, n_main: int = 2, n_mem: int = 6, elliptical_members: b
         elif t == PJE:
             c = _comp(PJE, x=fixed(cx), y=fixed(cy), b=fixed(rng.uniform(3, 10)), q=fixed(q),
                       pa=fixed(pa), s=fixed(rng.uniform(0.2, 2.0)), a=fixed(rng.uniform(15, 60)))
+        elif t == SHEAR:
+            c = _comp(SHEAR, b=fixed(rng.uniform(0.02, 0.1)), pa=fixed(pa))
+        elif t == MPOLE3:
+            c = _comp(MPOLE3, x=fixed(cx), y=fixed(cy), b=fixed(rng.uniform(0.01, 0.05)), pa=fixed(pa))
         elif t == NFW:
             c = _comp(NFW, x=fixed(cx), y=fixed(cy), b=fixed(rng.uniform(0.1, 0.4)),
                       s=fixed(rng.uniform(10, 40)))

