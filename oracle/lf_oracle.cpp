@@ -750,7 +750,7 @@ static int chi2_one(const double* tab, int H, const double* th, const int* fam, 
                     int img_mode, double newton_tol, double* chi_src, double* chi_img,
                     double* bmod, double* tmod, ImgInfo* info = nullptr) {
   int flags = 0;
-  std::vector<double> bo(2 * n), W(3 * n), detA0(n), csrc_i(n);
+  std::vector<double> bo(2 * n), W(3 * n), M(3 * n), Si(3 * n), detA0(n), csrc_i(n);
   if (info) { info->h.assign(9 * n, 0.0); info->ok.assign(n, 0); }
   for (int i = 0; i < n; ++i) {
     double h[9];
@@ -762,8 +762,9 @@ static int chi2_one(const double* tab, int H, const double* th, const int* fam, 
     double det = A11 * A22 - A12 * A12;
     detA0[i] = det;
     double m11 = A22 / det, m12 = -A12 / det, m22 = A11 / det;      // mu = A^-1 (symmetric)
-    double S[3];
+    double* S = &Si[3 * i];
     sinv(s1[i], s2[i], phi[i], S);
+    M[3 * i] = m11; M[3 * i + 1] = m12; M[3 * i + 2] = m22;
     // W = mu^T S^-1 mu
     double t11 = S[0] * m11 + S[1] * m12, t12 = S[0] * m12 + S[1] * m22;
     double t21 = S[1] * m11 + S[2] * m12, t22 = S[1] * m12 + S[2] * m22;
@@ -804,7 +805,12 @@ static int chi2_one(const double* tab, int H, const double* th, const int* fam, 
     for (int i = 0; i < n; ++i) {
       if (fam[i] != f) continue;
       double dx = bo[2 * i] - bx, dy = bo[2 * i + 1] - by;
-      double c = dx * (W[3 * i] * dx + W[3 * i + 1] * dy) + dy * (W[3 * i + 1] * dx + W[3 * i + 2] * dy);
+      // d^T W d = (mu d)^T S^-1 (mu d): the image-plane offset weighted by the error ellipse,
+      // evaluated in the second form, which rounding cannot make negative when mu is huge
+      const double* m = &M[3 * i];
+      const double* S = &Si[3 * i];
+      double vx = m[0] * dx + m[1] * dy, vy = m[1] * dx + m[2] * dy;
+      double c = S[0] * vx * vx + 2 * S[1] * vx * vy + S[2] * vy * vy;
       csrc_i[i] = c;
       total += c;
     }

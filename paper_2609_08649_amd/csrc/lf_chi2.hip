@@ -443,7 +443,14 @@ __device__ void chi2_src_sample(const Chi2Args& A, int s, bool obs) {
       size_t g = (size_t)s * A.n_img + i;
       double* w = A.wimg + g * 6;
       double dx = w[3] - bmx, dy = w[4] - bmy;
-      double c = dx * (w[0] * dx + w[1] * dy) + dy * (w[1] * dx + w[2] * dy);
+      // d^T W d = (mu d)^T S^-1 (mu d), evaluated in the second form (non-negative under
+      // rounding when mu is huge and W nearly rank one)
+      const double* q = A.part + g * 5;
+      const double A11 = 1.0 - a * q[2], A12 = -a * q[3], A22 = 1.0 - a * q[4], det = w[5];
+      const double m11 = A22 / det, m12 = -A12 / det, m22 = A11 / det;
+      const double vx = m11 * dx + m12 * dy, vy = m12 * dx + m22 * dy;
+      const double* Si = A.sinv + 3 * i;
+      double c = Si[0] * vx * vx + 2.0 * Si[1] * vx * vy + Si[2] * vy * vy;
       A.csrc[g] = c;
       tot += c;
     }
