@@ -284,7 +284,7 @@ def main():
                     "find_ms": timed(lambda: stage_find(prec), n_rep)}
     fp64_step_ms = st["fp64"]["maps_ms"] + st["fp64"]["chi2_src_ms"] + st["fp64"]["find_ms"]
     obs = bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, n_rep)
-    inference = None if args.no_extras else bench_inference(ctx, lf, torch, W, m, cons, stream)
+    inference = None if args.no_extras else bench_inference(ctx, lf, torch, W, m, cons, stream, cfg["truth"])
 
     extras = {}
     if not args.no_extras:
@@ -406,7 +406,7 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
     return out
 
 
-def bench_inference(ctx, lf, torch, W, m, cons, stream, n_nm=10000, nm_rounds=2000, n_steps=20000):
+def bench_inference(ctx, lf, torch, W, m, cons, stream, truth, n_nm=10000, nm_rounds=2000, n_steps=20000):
     """End-to-end synthetic reconstruction of the cluster model on the device, the paper's
     two-step workflow (Sec. 3.5, Sec. 4): n_nm Nelder-Mead runs started uniformly within the
     prior box (source-plane chi^2, MIXED), nm_rounds evaluations each; then AIES with 32
@@ -431,9 +431,12 @@ def bench_inference(ctx, lf, torch, W, m, cons, stream, n_nm=10000, nm_rounds=20
     best = int(np.argmin(fb))
     x_best = S[best, 0].cpu().numpy()
     evals = int(nev.sum().item())
-    res = {"nm": {"runs": n_nm, "rounds": nm_rounds, "evals": evals, "seconds": t_nm, "chi2_per_s": evals / t_nm,
+    tc, _, _ = ctx.chi2_batch(m, torch.as_tensor(truth[None], device=dev), 1, cons, 0, lf.LF_PREC_MIXED)
+    res = {"truth_chi2": float(tc.item()),
+           "nm": {"runs": n_nm, "rounds": nm_rounds, "evals": evals, "seconds": t_nm, "chi2_per_s": evals / t_nm,
                   "best_chi2": float(fb[best]), "median_best_chi2": float(np.median(fb)),
-                  "best_params": [float(v) for v in x_best]}}
+                  "best_params": [float(v) for v in x_best],
+                  "best_minus_truth_over_prior_width": [float(v) for v in (x_best - truth) / (hi - lo)]}}
     for K, steps in ((32, n_steps), (2048, 200)):
         X0 = x_best * (1 + 1e-4 * rng.normal(size=(K, D)))
         X = torch.as_tensor(np.clip(X0, lo, hi), device=dev)
