@@ -1274,6 +1274,131 @@ int orc_find_images_mp(int n_planes, const double* const* tabs, const int* Hs, c
                      count, flags, cand_src, cand_tri, cand_status, max_cand, n_cand, nthreads);
 }
 
+// Image finder of Sec. 2.3: zero contours of f = beta - theta + a alpha (both components)
+// by marching squares on the vertex grid x0 + (i+1/2)h, images at the exact intersections of
+// pairs of contour segments in a cell.  Per cell (corners c0 = (i,j), c1 = (i+1,j),
+// c2 = (i+1,j+1), c3 = (i,j+1); edges in loop order bottom c0-c1, right c1-c2, top c3-c2,
+// left c0-c3), a component with two sign changes on the edges gives one segment joining the
+// two linear-interpolation points, with four the asymptotic decider of its bilinear
+// interpolant pairs them (zero counts as positive).  Intersections are taken for each
+// f_1 segment with each f_2 segment, in that order, cells in row-major order.  polish: each
+// intersection refined by FP64 Newton (<= 30 steps to |d beta| < 1e-10") and kept if it
+// converged within 2h (max-norm) of it; images closer than 1e-6" to an earlier one are merged.
+// Without polish the intersections themselves are the images (accuracy O(h^2)).
+static int ms_segments(const double F[4], double seg[2][4]) {
+  // crossing points on the loop edges in cell coordinates (xi, eta) in [0, 1]^2
+  const double P[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+  const int ea[4] = {0, 1, 3, 0}, eb[4] = {1, 2, 2, 3};
+  double X[4][2];
+  int has[4], n = 0;
+  for (int m = 0; m < 4; ++m) {
+    double fa = F[ea[m]], fb = F[eb[m]];
+    has[m] = (fa < 0) != (fb < 0);
+    if (has[m]) {
+      double t = fa / (fa - fb);
+      X[m][0] = P[ea[m]][0] + t * (P[eb[m]][0] - P[ea[m]][0]);
+      X[m][1] = P[ea[m]][1] + t * (P[eb[m]][1] - P[ea[m]][1]);
+      ++n;
+    }
+  }
+  auto put = [&](int k, int a, int b) { seg[k][0] = X[a][0]; seg[k][1] = X[a][1]; seg[k][2] = X[b][0]; seg[k][3] = X[b][1]; };
+  if (n == 2) {
+    int a = -1, b = -1;
+    for (int m = 0; m < 4; ++m) if (has[m]) { if (a < 0) a = m; else b = m; }
+    put(0, a, b);
+    return 1;
+  }
+  if (n == 4) {
+    double D = F[0] + F[2] - F[1] - F[3];
+    bool cpos = D == 0.0 ? true : !((F[0] * F[2] - F[1] * F[3]) / D < 0);
+    if (cpos == !(F[0] < 0)) { put(0, 0, 1); put(1, 2, 3); }
+    else { put(0, 0, 3); put(1, 1, 2); }
+    return 2;
+  }
+  return 0;
+}
+
+int orc_find_images_ms(const double* tab, int H, double x0, double y0, double h, int nx, int ny, const double* beta,
+                       const double* a_src, int n_src, int max_img, int polish, double* theta_out, double* mu_out,
+                       int* count, int* flags, int nthreads) {
+  std::vector<double> vax((size_t)nx * ny), vay((size_t)nx * ny);
+  parallel_for(ny, nthreads, [&](int lo, int hi) {
+    for (int j = lo; j < hi; ++j)
+      for (int i = 0; i < nx; ++i)
+        halo_sum_alpha(tab, H, x0 + (i + 0.5) * h, y0 + (j + 0.5) * h, &vax[(size_t)j * nx + i], &vay[(size_t)j * nx + i]);
+  });
+  parallel_for(n_src, nthreads, [&](int lo, int hi) {
+    for (int s = lo; s < hi; ++s) {
+      const double a = a_src[s], sx = beta[2 * s], sy = beta[2 * s + 1];
+      int cnt = 0, fl = 0;
+      std::vector<double> got;
+      for (int j = 0; j + 1 < ny; ++j)
+        for (int i = 0; i + 1 < nx; ++i) {
+          const int ci[4] = {i, i + 1, i + 1, i}, cj[4] = {j, j, j + 1, j + 1};
+          double F1[4], F2[4];
+          for (int k = 0; k < 4; ++k) {
+            size_t v = (size_t)cj[k] * nx + ci[k];
+            double tx = x0 + (ci[k] + 0.5) * h, ty = y0 + (cj[k] + 0.5) * h;
+            F1[k] = sx - (tx - a * vax[v]);
+            F2[k] = sy - (ty - a * vay[v]);
+          }
+          double S1[2][4], S2[2][4];
+          int n1 = ms_segments(F1, S1);
+          if (!n1) continue;
+          int n2 = ms_segments(F2, S2);
+          for (int p = 0; p < n1; ++p)
+            for (int q = 0; q < n2; ++q) {
+              double d1x = S1[p][2] - S1[p][0], d1y = S1[p][3] - S1[p][1];
+              double d2x = S2[q][2] - S2[q][0], d2y = S2[q][3] - S2[q][1];
+              double wx = S2[q][0] - S1[p][0], wy = S2[q][1] - S1[p][1];
+              double den = d1x * d2y - d1y * d2x;
+              if (den == 0.0) continue;
+              double tp = (wx * d2y - wy * d2x) / den, tq = (wx * d1y - wy * d1x) / den;
+              if (!(tp >= 0 && tp <= 1 && tq >= 0 && tq <= 1)) continue;
+              double tx = x0 + (i + 0.5) * h + h * (S1[p][0] + tp * d1x);
+              double ty = y0 + (j + 0.5) * h + h * (S1[p][1] + tp * d1y);
+              double d[9];
+              if (polish) {
+                double px = tx, py = ty;
+                bool conv = false;
+                for (int it = 0; it <= 30; ++it) {
+                  halo_sum(tab, H, px, py, d);
+                  double rx = sx - (px - a * d[0]), ry = sy - (py - a * d[1]);
+                  if (std::fabs(rx) < 1e-10 && std::fabs(ry) < 1e-10) { conv = true; break; }
+                  if (it == 30) break;
+                  double A11 = 1 - a * d[2], A12 = -a * d[3], A22 = 1 - a * d[4];
+                  double det = A11 * A22 - A12 * A12;
+                  px += (A22 * rx - A12 * ry) / det;
+                  py += (-A12 * rx + A11 * ry) / det;
+                }
+                if (!conv || std::fabs(px - tx) > 2 * h || std::fabs(py - ty) > 2 * h) continue;
+                tx = px; ty = py;
+              } else {
+                halo_sum(tab, H, tx, ty, d);
+              }
+              bool dup = false;
+              for (size_t k = 0; k < got.size(); k += 2)
+                if (std::sqrt((tx - got[k]) * (tx - got[k]) + (ty - got[k + 1]) * (ty - got[k + 1])) < 1e-6) dup = true;
+              if (dup) { fl |= F_MERGED; continue; }
+              got.push_back(tx); got.push_back(ty);
+              double A11 = 1 - a * d[2], A12 = -a * d[3], A22 = 1 - a * d[4];
+              if (cnt < max_img) {
+                theta_out[((size_t)s * max_img + cnt) * 2] = tx;
+                theta_out[((size_t)s * max_img + cnt) * 2 + 1] = ty;
+                mu_out[(size_t)s * max_img + cnt] = 1.0 / (A11 * A22 - A12 * A12);
+              } else {
+                fl |= F_OVERFLOW;
+              }
+              ++cnt;
+            }
+        }
+      count[s] = cnt;
+      flags[s] = fl;
+    }
+  });
+  return 0;
+}
+
 // vertex beta map of a single-plane lens (test helper for brute-force containment)
 int orc_vertex_beta(const double* tab, int H, double x0, double y0, double h, int nx, int ny,
                     double a, double* bx, double* by) {

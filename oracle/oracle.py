@@ -350,3 +350,19 @@ def sing_map(tab, grid, refine=True, tol=1e-10, cap=200000, nthreads=None):
             "swt": {"pos": wx[:2 * nw].reshape(-1, 2), "k": wk[:nw], "e": we[:nw], "seg": wseg[:nw],
                     "status": wst[:nw]},
             "counts": cnt.copy()}
+
+
+def find_images_ms(tab, grid, beta, a_src, max_img=16, polish=False, nthreads=None):
+    """The contour-intersection finder of Sec. 2.3 (marching squares on both components of
+    beta - theta + a alpha); polish: FP64 Newton from each intersection."""
+    tab = _f64(tab)
+    beta = _f64(beta).reshape(-1, 2)
+    a_src = _f64(np.broadcast_to(a_src, (beta.shape[0],)))
+    ns = beta.shape[0]
+    th, mu = np.zeros((ns, max_img, 2)), np.zeros((ns, max_img))
+    cnt, fl = np.zeros(ns, np.int32), np.zeros(ns, np.int32)
+    lib().orc_find_images_ms(_p(tab), C.c_int(tab.shape[0]), C.c_double(grid["x0"]), C.c_double(grid["y0"]),
+                             C.c_double(grid["h"]), C.c_int(grid["nx"]), C.c_int(grid["ny"]), _p(beta), _p(a_src),
+                             C.c_int(ns), C.c_int(max_img), C.c_int(1 if polish else 0), _p(th), _p(mu),
+                             _p(cnt, C.c_int), _p(fl, C.c_int), C.c_int(nthreads or nthreads_default()))
+    return {"theta": th, "mu": mu, "count": cnt, "flags": fl}
