@@ -400,6 +400,7 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
         p.release()
     torch.cuda.empty_cache()
     out["singularity_map_4096"] = bench_singularity(ctx, lf, torch, W, stream, timed)
+    out["contour_finder_2048"] = bench_contour_finder(ctx, lf, torch, W, stream, timed)
     out["config1_latency"] = bench_config1(ctx, lf, torch, W, stream)
     out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
     out["serving"] = bench_serving(ctx, lf, torch, W)
@@ -458,6 +459,33 @@ def bench_inference(ctx, lf, torch, W, m, cons, stream, truth, n_nm=10000, nm_ro
         "nm_s": t_nm * 1e4 / n_nm, "aies_s": a["ms_per_step"] * 1e5 / 1e3,
         "total_s": t_nm * 1e4 / n_nm + a["ms_per_step"] * 1e5 / 1e3,
         "paper_reported": "about 11 hours on 16 CPU cores"}
+    return res
+
+
+def bench_contour_finder(ctx, lf, torch, W, stream, timed, n_rep=5):
+    """The contour-intersection finder of Sec. 2.3 on the cluster workload (60 sources on the
+    2048^2 grid), raw intersections and polished, beside the triangle-mapping finder."""
+    cfg = W.config2(n_samples=1)
+    m = ctx.upload_model(cfg["model"])
+    p = torch.as_tensor(cfg["truth"][None], device="cuda")
+    rng = np.random.default_rng(2617)
+    beta = torch.as_tensor(cfg["src_cand"][:60], device="cuda")
+    a = torch.as_tensor(np.array([ctx.adis(cfg["model"]["z_d"], z) for z in cfg["zs_cand"][:60]]), device="cuda")
+    grid = cfg["grid"]
+    res = {"sources": 60, "grid": grid["nx"]}
+    for name, prec in (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64)):
+        for polish in (False, True):
+            fn = lambda: ctx.find_images_ms(m, p, beta, a, grid, 16, prec, polish, stream=stream)
+            r = fn()
+            t = timed(fn, n_rep)
+            res["%s_%s_ms" % (name, "polished" if polish else "raw")] = t
+            res["%s_%s_images" % (name, "polished" if polish else "raw")] = int(r["count"].sum().item())
+        fn = lambda: ctx.find_images(m, p, beta, a, grid, 16, prec, stream=stream)
+        r = fn()
+        res["%s_triangle_ms" % name] = timed(fn, n_rep)
+        res["%s_triangle_images" % name] = int(r["count"].sum().item())
+    m.release()
+    del rng
     return res
 
 

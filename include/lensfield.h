@@ -278,6 +278,19 @@ lf_status lf_find_images(lf_ctx* ctx, const lf_model* m, const double* params,
                          const lf_grid* grid, int32_t max_img, lf_prec prec, double* theta_out,
                          double* mu_out, int32_t* count_out, int32_t* flags, void* stream);
 
+/* Image finder of Sec. 2.3, kept as a cross-check on triangle mapping: zero contours of both
+ * components of f = beta - theta + a alpha on the grid vertices (marching squares: linear
+ * interpolation on cell edges, the asymptotic decider in cells crossed four times), images at
+ * the exact intersections of pairs of contour segments (accuracy O(h^2); a singular centre,
+ * where alpha jumps, can give a spurious intersection).  polish != 0: each intersection is
+ * refined by FP64 Newton (<= 30 steps to |d beta| < 1e-10") and kept if it converged within
+ * 2h of it.  Images closer than 1e-6" to an earlier one are merged.  Arguments, outputs and
+ * errors as lf_find_images (single plane); the grid has fewer than 2^30 cells. */
+lf_status lf_find_images_ms(lf_ctx* ctx, const lf_model* m, const double* params, const double* beta,
+                            const double* a_src, int32_t n_src, const lf_grid* grid, int32_t max_img,
+                            lf_prec prec, int32_t polish, double* theta_out, double* mu_out,
+                            int32_t* count_out, int32_t* flags, void* stream);
+
 /* Multi-plane ray trace (Sec. 2.2).  planes sorted by z_planes (increasing),
  * each a model without free fields.  For each point and each source redshift z_src[k]:
  * beta [n_zs][P][2], Jacobian A [n_zs][P][4] (A11 A12 A21 A22; not symmetric), mu [n_zs][P].

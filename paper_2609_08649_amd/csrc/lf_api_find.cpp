@@ -163,6 +163,45 @@ extern "C" lf_status lf_find_images(lf_ctx* ctx, const lf_model* M, const double
   return ctx->hip(lf::launch_find(F, L, st, lf_prof_mark, ctx), "finder kernels");
 }
 
+extern "C" lf_status lf_find_images_ms(lf_ctx* ctx, const lf_model* M, const double* params, const double* beta,
+                                       const double* a_src, int32_t n_src, const lf_grid* grid, int32_t max_img,
+                                       lf_prec prec, int32_t polish, double* theta_out, double* mu_out,
+                                       int32_t* count_out, int32_t* flags, void* stream) {
+  if (!ctx) return LF_E_INVALID_ARG;
+  if (!M || !beta || !a_src || !theta_out || !count_out) return ctx->fail(LF_E_INVALID_ARG, "null argument");
+  if (n_src < 1 || max_img < 1) return ctx->fail(LF_E_INVALID_ARG, "n_src and max_img must be >= 1");
+  if (!grid_ok(grid) || (long long)(grid->nx - 1) * (grid->ny - 1) * 4 >= (1LL << 32))
+    return ctx->fail(LF_E_INVALID_ARG, "bad grid (need nx, ny >= 2, h > 0, fewer than 2^30 cells)");
+  if (M->n_free > 0 && !params) return ctx->fail(LF_E_INVALID_ARG, "model has free fields: params required");
+  if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  lf::PointsSpec ps;
+  lf_points pts;
+  pts.grid = *grid; pts.px = pts.py = nullptr; pts.n = 0;
+  lf_points_spec(&pts, ps);
+  lf_status e = LF_OK;
+  double* va = (double*)ctx->ws("find.va", sizeof(double) * 2 * (size_t)ps.P, st, &e);
+  if (e) return e;
+  lf::LensDev L;
+  std::memset(&L, 0, sizeof L);
+  L.n_planes = 1;
+  e = plane_sum(ctx, M, params, ps, prec == LF_PREC_MIXED, alpha_psi_out(va, ps.P, false), "find", st, &L.pl[0]);
+  if (e) return e;
+  lf::QuadTab q = lf_quad(ctx);
+  L.qd.n = q.n; L.qd.u = q.u; L.qd.w = q.w;
+  lf::FindArgs F;
+  std::memset(&F, 0, sizeof F);
+  F.x0 = grid->x0; F.y0 = grid->y0; F.h = grid->h; F.nx = grid->nx; F.ny = grid->ny;
+  F.n_planes = 1; F.va_pstride = 2; F.va = va;
+  F.n_src = n_src; F.beta = beta; F.w = a_src;
+  F.max_img = max_img; F.theta_out = theta_out; F.mu_out = mu_out; F.count_out = count_out; F.flags_out = flags;
+  e = finder_buffers(ctx, st, F);
+  if (e) return e;
+  ctx->cur_stream = st;
+  return ctx->hip(lf::launch_find_ms(F, L, polish ? 1 : 0, st, lf_prof_mark, ctx), "contour finder kernels");
+}
+
 extern "C" lf_status lf_multiplane_trace(lf_ctx* ctx, const lf_model* const* planes, const double* z_planes,
                                          int32_t n_planes, const lf_cosmo* cosmo, const double* z_src, int32_t n_zs,
                                          const lf_points* pts, lf_prec prec, double* beta_out, double* A_out,

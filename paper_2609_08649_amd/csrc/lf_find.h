@@ -59,6 +59,8 @@ struct MPArgs {
 
 hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st,
                        void (*mark)(void*, const char*, int), void* ctx);
+hipError_t launch_find_ms(const FindArgs& F, const LensDev& L, int polish, hipStream_t st,
+                          void (*mark)(void*, const char*, int), void* ctx);
 hipError_t launch_mp_theta(const MPArgs& M, int j, hipStream_t st);
 hipError_t launch_mp_final(const MPArgs& M, hipStream_t st);
 

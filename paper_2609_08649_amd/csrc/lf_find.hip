@@ -388,6 +388,191 @@ hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void
 }
 
 // ---------------------------------------------------------------------------------------
+// Contour-intersection finder (Sec. 2.3): zero contours of f = beta - theta + a alpha (both
+// components) by marching squares, images at the exact intersections of pairs of segments.
+// Per cell (corners c0 = (i,j), c1 = (i+1,j), c2 = (i+1,j+1), c3 = (i,j+1); loop edges bottom
+// c0-c1, right c1-c2, top c3-c2, left c0-c3; zero counts as positive): two sign changes of a
+// component give one segment between the linear-interpolation points, four are paired by the
+// asymptotic decider of the bilinear interpolant.  Candidates (source, cell, pair = f1 segment
+// * 2 + f2 segment) are sorted like the triangle finder's and take the same final pass.
+// ---------------------------------------------------------------------------------------
+namespace {
+struct MsCell {
+  double F1[4], F2[4];
+};
+__device__ void ms_cell_values(const FindArgs& F, int s, int i, int j, MsCell& c) {
+#pragma clang fp contract(off)
+  const long long P = (long long)F.nx * F.ny;
+  const double a = F.w[s], sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
+  const int ci[4] = {i, i + 1, i + 1, i}, cj[4] = {j, j, j + 1, j + 1};
+  for (int k = 0; k < 4; ++k) {
+    const long long v = (long long)cj[k] * F.nx + ci[k];
+    const double tx = F.x0 + (ci[k] + 0.5) * F.h, ty = F.y0 + (cj[k] + 0.5) * F.h;
+    c.F1[k] = sx - (tx - a * F.va[v]);
+    c.F2[k] = sy - (ty - a * F.va[P + v]);
+  }
+}
+// segments of one component in cell coordinates: seg[k] = (x0, y0, x1, y1); returns 0, 1 or 2
+__device__ int ms_segments(const double* Fv, double seg[2][4]) {
+#pragma clang fp contract(off)
+  const double px[4] = {0.0, 1.0, 1.0, 0.0}, py[4] = {0.0, 0.0, 1.0, 1.0};
+  const int ea[4] = {0, 1, 3, 0}, eb[4] = {1, 2, 2, 3};
+  double X[4][2];
+  bool has[4];
+  int n = 0;
+  for (int m = 0; m < 4; ++m) {
+    const double fa = Fv[ea[m]], fb = Fv[eb[m]];
+    has[m] = (fa < 0) != (fb < 0);
+    X[m][0] = X[m][1] = 0.0;
+    if (has[m]) {
+      const double t = fa / (fa - fb);
+      X[m][0] = px[ea[m]] + t * (px[eb[m]] - px[ea[m]]);
+      X[m][1] = py[ea[m]] + t * (py[eb[m]] - py[ea[m]]);
+      ++n;
+    }
+  }
+  auto put = [&](int k, int a, int b) {
+    seg[k][0] = X[a][0]; seg[k][1] = X[a][1]; seg[k][2] = X[b][0]; seg[k][3] = X[b][1];
+  };
+  if (n == 2) {
+    int a = -1, b = -1;
+    for (int m = 0; m < 4; ++m)
+      if (has[m]) { if (a < 0) a = m; else b = m; }
+    put(0, a, b);
+    return 1;
+  }
+  if (n == 4) {
+    const double D = Fv[0] + Fv[2] - Fv[1] - Fv[3];
+    const bool cpos = D == 0.0 ? true : !((Fv[0] * Fv[2] - Fv[1] * Fv[3]) / D < 0);
+    if (cpos == !(Fv[0] < 0)) { put(0, 0, 1); put(1, 2, 3); }
+    else { put(0, 0, 3); put(1, 1, 2); }
+    return 2;
+  }
+  return 0;
+}
+// intersection of f1 segment p with f2 segment q; false if they do not cross
+__device__ bool ms_cross(const double S1[2][4], int p, const double S2[2][4], int q, double& xi, double& eta) {
+#pragma clang fp contract(off)
+  const double d1x = S1[p][2] - S1[p][0], d1y = S1[p][3] - S1[p][1];
+  const double d2x = S2[q][2] - S2[q][0], d2y = S2[q][3] - S2[q][1];
+  const double wx = S2[q][0] - S1[p][0], wy = S2[q][1] - S1[p][1];
+  const double den = d1x * d2y - d1y * d2x;
+  if (den == 0.0) return false;
+  const double tp = (wx * d2y - wy * d2x) / den, tq = (wx * d1y - wy * d1x) / den;
+  if (!(tp >= 0 && tp <= 1 && tq >= 0 && tq <= 1)) return false;
+  xi = S1[p][0] + tp * d1x;
+  eta = S1[p][1] + tp * d1y;
+  return true;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_ms_cand(const FindArgs F) {
+  const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool valid = c < ncell;
+  const long long cc = valid ? c : 0;
+  const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
+  const int lane = threadIdx.x & 63;
+  for (int s = 0; s < F.n_src; ++s) {
+    MsCell v;
+    ms_cell_values(F, s, i, j, v);
+    int pairs = 0;          // bit p * 2 + q: f1 segment p crosses f2 segment q
+    if (valid) {
+      double S1[2][4], S2[2][4];
+      const int n1 = ms_segments(v.F1, S1);
+      if (n1) {
+        const int n2 = ms_segments(v.F2, S2);
+        for (int p = 0; p < n1; ++p)
+          for (int q = 0; q < n2; ++q) {
+            double xi, eta;
+            if (ms_cross(S1, p, S2, q, xi, eta)) pairs |= 1 << (p * 2 + q);
+          }
+      }
+    }
+    if (!__any(pairs != 0)) continue;
+    for (int k = 0; k < 4; ++k) {
+      const bool hit = (pairs >> k) & 1;
+      const unsigned long long mask = __ballot(hit);
+      if (!mask) continue;
+      const int leader = __ffsll((long long)mask) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
+      base = __shfl(base, leader, 64);
+      if (hit) {
+        const int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+        if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(cc * 4 + k);
+      }
+    }
+  }
+}
+
+// one wave per candidate: the intersection, then (polish) FP64 Newton as the triangle finder
+__global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev L, int polish) {
+  const int n = min(*F.n_cand, F.cap);
+  const int k = blockIdx.x;
+  if (k >= n) return;
+  const unsigned long long key = F.cand[k];
+  const int s = (int)(key >> 32);
+  const long long low = (long long)(key & 0xffffffffull), cell = low >> 2;
+  const int pair = (int)(low & 3), p = pair >> 1, q = pair & 1;
+  const int i = (int)(cell % (F.nx - 1)), j = (int)(cell / (F.nx - 1));
+  MsCell v;
+  ms_cell_values(F, s, i, j, v);
+  double S1[2][4], S2[2][4], xi = 0.0, eta = 0.0;
+  ms_segments(v.F1, S1);
+  ms_segments(v.F2, S2);
+  ms_cross(S1, p, S2, q, xi, eta);
+  double tx, ty;
+  {
+#pragma clang fp contract(off)
+    tx = F.x0 + (i + 0.5) * F.h + F.h * xi;
+    ty = F.y0 + (j + 0.5) * F.h + F.h * eta;
+  }
+  const double* w = F.w + s;
+  const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
+  double A[4], ex, ey;
+  int fl = 0, status = 0;
+  if (polish) {
+    const double tx0 = tx, ty0 = ty;
+    bool conv = false;
+    for (int it = 0; it <= 30; ++it) {
+      lens_eval64(L, w, tx, ty, ex, ey, A, fl);
+      const double rx = sx - ex, ry = sy - ey;
+      if (fabs(rx) < 1e-10 && fabs(ry) < 1e-10) { conv = true; break; }
+      if (it == 30) break;
+      const double det = A[0] * A[3] - A[1] * A[2];
+      tx += (A[3] * rx - A[1] * ry) / det;
+      ty += (-A[2] * rx + A[0] * ry) / det;
+    }
+    if (!conv) status = 1;
+    else if (fabs(tx - tx0) > 2.0 * F.h || fabs(ty - ty0) > 2.0 * F.h) status = 2;
+  } else {
+    lens_eval64(L, w, tx, ty, ex, ey, A, fl);
+  }
+  if (threadIdx.x == 0) {
+    F.c_status[k] = status;
+    F.c_theta[2 * k] = tx;
+    F.c_theta[2 * k + 1] = ty;
+    F.c_mu[k] = 1.0 / (A[0] * A[3] - A[1] * A[2]);
+  }
+}
+
+hipError_t launch_find_ms(const FindArgs& F, const LensDev& L, int polish, hipStream_t st,
+                          void (*mark)(void*, const char*, int), void* ctx) {
+  const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, F.n_cand);
+  mark(ctx, "find_ms_cand", 0);
+  hipLaunchKernelGGL(k_ms_cand, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
+  mark(ctx, "find_ms_cand", 1);
+  hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
+  mark(ctx, "find_ms_point", 0);
+  hipLaunchKernelGGL(k_ms_point, dim3(F.cap), dim3(64), 0, st, F, L, polish);
+  mark(ctx, "find_ms_point", 1);
+  hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Multi-plane passes: theta_j of every point, and the final recursion (Sec. 2.2).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mp_theta(const MPArgs M, int j) {

@@ -105,6 +105,7 @@ def lib():
             "lf_chi2_batch": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
             "lf_chi2_terms": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P, P]),
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
+            "lf_find_images_ms": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
                                           P, P, P, P]),
             "lf_aies_run": (I32, [P, P, P, I32, I32, I32, P, P, I32, P, P, D, C.c_uint64, I64, I32, P, P, P, P]),
@@ -455,6 +456,26 @@ def _find_mp(self, planes, z_planes, beta, z_src, grid, max_img=16, prec=LF_PREC
 
 
 Context.find_images = _find
+
+
+def _find_ms(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, polish=True,
+             stream=None):
+    """Contour-intersection finder (Sec. 2.3) for n_src sources (device tensors beta [n,2], a_src [n])."""
+    n = beta.shape[0]
+    dev = self.device
+    out = {"theta": torch.zeros((n, max_img, 2), dtype=torch.float64, device=dev),
+           "mu": torch.zeros((n, max_img), dtype=torch.float64, device=dev),
+           "count": torch.zeros(n, dtype=torch.int32, device=dev),
+           "flags": torch.zeros(n, dtype=torch.int32, device=dev)}
+    g = lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_find_images_ms(self.handle, model.handle, pp, _ptr(beta), _ptr(a_src), int(n), C.byref(g),
+                                       int(max_img), int(prec), 1 if polish else 0, _ptr(out["theta"]),
+                                       _ptr(out["mu"]), _ptr(out["count"]), _ptr(out["flags"]), _stream(stream)))
+    return out
+
+
+Context.find_images_ms = _find_ms
 
 
 def sing_buffers(device, cap):
