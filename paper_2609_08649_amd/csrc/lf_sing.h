@@ -27,6 +27,7 @@ struct SingArgs {
   int* krow_cnt; int* krow_off;    // cells skipped next to umbilic-flagged vertices
   int* prow_cnt; int* prow_off;    // cells whose crossings could not be paired
   int* wch_cnt; int* wch_off;      // swallowtails per chunk of 256 segments, [cap/256 + 1]
+  unsigned short* ebits;     // [nx*ny] per vertex: edge crossings, alignments, umbilic flag
   long long* ckey;           // [cap] crossing keys ((j * 2 + dir) * nx + i) * 2 + k - 1, ascending
   int* ucell;                // [cap*2] cell (i, j) of each umbilic
   // outputs

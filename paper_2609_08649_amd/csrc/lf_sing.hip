@@ -11,17 +11,18 @@
 //
 // Pipeline (one stream, no host synchronisation; every list is compacted by prefix sums in a
 // fixed order, so results do not depend on the launch shape):
-//   1. k_sing_edges: per vertex row, every grid edge and family: does f_k change sign after
-//      alignment?  Count pass, scan, write pass: crossings in the order (row j; horizontal
-//      edges by i, then vertical edges by i; k = 1, 2), stored as ascending keys;
+//   1. k_sing_bits / k_sing_keys: per vertex row, every grid edge and family: does f_k change
+//      sign after alignment?  One 16-bit word per vertex (crossings, alignments, umbilic
+//      flag), a scan, then the crossings in the order (row j; horizontal edges by i, then
+//      vertical edges by i; k = 1, 2), stored as ascending keys;
 //   2. k_sing_refine: one wave per crossing: Illinois regula falsi on the edge with FP64
 //      evaluations (halos split over the lanes), then e_k and g_k (central differences);
-//   3. k_sing_cells: per cell row, per family: segments (two crossings; four: the
-//      asymptotic decider of the bilinear interpolant), umbilic cells and the segments that
-//      end at them; crossings located by binary search over the keys;
+//   3. k_sing_cells: per cell row, per family, from the four vertex words: segments (two
+//      crossings; four: the asymptotic decider of the bilinear interpolant), umbilic cells and
+//      the segments that end at them; crossings located by binary search over the keys;
 //   4. k_sing_umb: one wave per umbilic cell: Newton on (gamma_1, gamma_2) = 0;
 //   5. k_sing_swt: segments whose ends' g_k differ in sign give swallowtails (interpolated),
-//      refined by Newton on (f_k, g_k) = 0 with difference Jacobians.
+//      refined by Newton on (f_k, g_k) = 0 with difference Jacobians (five waves per point).
 #include <hip/hip_runtime.h>
 
 #include "lf_sing.h"
@@ -153,34 +154,68 @@ __global__ __launch_bounds__(NT) void k_sing_scan(const int* cnt, int n, int* of
 }
 
 // ---------------------------------------------------------------------------------------
-// 1. crossings
+// 1. crossings.  k_sing_bits: one thread per vertex computes a 16-bit word for its right
+//    (horizontal) and upper (vertical) edges: bit 0/1 horizontal crossing k = 1/2, bit 2/3
+//    vertical crossing, bit 4/5 horizontal / vertical alignment of family 1 (dot >= 0), bit
+//    6/7 the same for family 2, bit 8 the vertex is umbilic-flagged; and the row's crossing
+//    count.  k_sing_keys writes the crossing keys in the canonical order.
 // ---------------------------------------------------------------------------------------
-template <bool WRITE>
-__global__ __launch_bounds__(NT) void k_sing_edges(const SingArgs A) {
+namespace {
+constexpr unsigned B_UMB = 0x100;
+__device__ __forceinline__ double bsign(unsigned b, int bit) { return (b >> bit) & 1 ? 1.0 : -1.0; }
+}  // namespace
+
+__global__ __launch_bounds__(NT) void k_sing_bits(const SingArgs A) {
   __shared__ int lds[4];
   const int j = blockIdx.x;
-  const int Th = 2 * (A.nx - 1), Tv = (j + 1 < A.ny) ? 2 * A.nx : 0, T = Th + Tv;
-  int run = WRITE ? A.xrow_off[j] : 0;
-  for (int base = 0; base < T; base += NT) {
-    const int t = base + threadIdx.x;
-    int flag = 0;
-    long long key = 0;
-    if (t < T) {
-      const int dir = t < Th ? 0 : 1, u = t < Th ? t : t - Th, i = u >> 1, k = u & 1;
+  int run = 0;
+  for (int base = 0; base < A.nx; base += NT) {
+    const int i = base + threadIdx.x;
+    int c = 0;
+    if (i < A.nx) {
       const VA3 a = vertex_a3(A, i, j);
-      const VA3 b = dir == 0 ? vertex_a3(A, i + 1, j) : vertex_a3(A, i, j + 1);
-      flag = edge_cross(a, b, k) ? 1 : 0;
-      key = edge_key(A.nx, i, j, dir, k);
+      unsigned bits = a.umb ? B_UMB : 0u;
+      if (i + 1 < A.nx) {
+        const VA3 b = vertex_a3(A, i + 1, j);
+        for (int k = 0; k < 2; ++k) {
+          if (edge_cross(a, b, k)) bits |= 1u << k;
+          if (align(a, b, k) > 0.0) bits |= 0x10u << (2 * k);
+        }
+      }
+      if (j + 1 < A.ny) {
+        const VA3 b = vertex_a3(A, i, j + 1);
+        for (int k = 0; k < 2; ++k) {
+          if (edge_cross(a, b, k)) bits |= 4u << k;
+          if (align(a, b, k) > 0.0) bits |= 0x20u << (2 * k);
+        }
+      }
+      A.ebits[(size_t)j * A.nx + i] = (unsigned short)bits;
+      c = __popc(bits & 0xFu);
     }
     int tot;
-    const int pre = block_scan(flag, lds, tot);
-    if (WRITE && flag) {
-      const int idx = run + pre;
-      if (idx < A.cap) A.ckey[idx] = key;
-    }
+    block_scan(c, lds, tot);
     run += tot;
   }
-  if (!WRITE && threadIdx.x == 0) A.xrow_cnt[j] = run;
+  if (threadIdx.x == 0) A.xrow_cnt[j] = run;
+}
+
+__global__ __launch_bounds__(NT) void k_sing_keys(const SingArgs A) {
+  __shared__ int lds[4];
+  const int j = blockIdx.x;
+  int run = A.xrow_off[j];
+  for (int dir = 0; dir < 2; ++dir)
+    for (int base = 0; base < A.nx; base += NT) {
+      const int i = base + threadIdx.x;
+      const unsigned m = i < A.nx ? (A.ebits[(size_t)j * A.nx + i] >> (2 * dir)) & 3u : 0u;
+      int tot;
+      int idx = run + block_scan(__popc(m), lds, tot);
+      for (int k = 0; k < 2; ++k)
+        if ((m >> k) & 1u) {
+          if (idx < A.cap) A.ckey[idx] = edge_key(A.nx, i, j, dir, k);
+          ++idx;
+        }
+      run += tot;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -270,22 +305,24 @@ __device__ int find_key(const SingArgs& A, int nX, long long key) {
 struct CellRes {
   int nseg, umb, stat4, skipped, unpaired;
 };
-// Marching squares of one cell for both families; emit(a, b, k) for each segment in order.
+// Marching squares of one cell for both families from the vertex words; emit(a, b, k) for
+// each segment in order.
 template <class Emit>
 __device__ CellRes cell_logic(const SingArgs& A, int i, int j, int nX, int uidx, Emit&& emit) {
   CellRes r{0, 0, 0, 0, 0};
-  const VA3 c0 = vertex_a3(A, i, j), c1 = vertex_a3(A, i + 1, j);
-  const VA3 c2 = vertex_a3(A, i + 1, j + 1), c3 = vertex_a3(A, i, j + 1);
-  if (c0.umb || c1.umb || c2.umb || c3.umb) { r.skipped = 1; return r; }
-  const double P = align(c0, c1, 0) * align(c1, c2, 0) * align(c2, c3, 0) * align(c3, c0, 0);
+  const size_t p0 = (size_t)j * A.nx + i;
+  const unsigned b0 = A.ebits[p0], b1 = A.ebits[p0 + 1], b3 = A.ebits[p0 + A.nx], b2 = A.ebits[p0 + A.nx + 1];
+  if ((b0 | b1 | b2 | b3) & B_UMB) { r.skipped = 1; return r; }
+  // loop c0-c1 (bottom: b0 horizontal), c1-c2 (right: b1 vertical), c2-c3 (top: b3
+  // horizontal), c3-c0 (left: b0 vertical)
+  const double P = bsign(b0, 4) * bsign(b1, 5) * bsign(b3, 4) * bsign(b0, 5);
   r.umb = P < 0.0 ? 1 : 0;
   for (int k = 0; k < 2; ++k) {
-    // loop edges: bottom, right, top, left (each as stored: from its lower or left vertex)
     int xs[4];
-    xs[0] = edge_cross(c0, c1, k) ? find_key(A, nX, edge_key(A.nx, i, j, 0, k)) : -1;
-    xs[1] = edge_cross(c1, c2, k) ? find_key(A, nX, edge_key(A.nx, i + 1, j, 1, k)) : -1;
-    xs[2] = edge_cross(c3, c2, k) ? find_key(A, nX, edge_key(A.nx, i, j + 1, 0, k)) : -1;
-    xs[3] = edge_cross(c0, c3, k) ? find_key(A, nX, edge_key(A.nx, i, j, 1, k)) : -1;
+    xs[0] = (b0 >> k) & 1u ? find_key(A, nX, edge_key(A.nx, i, j, 0, k)) : -1;
+    xs[1] = (b1 >> (2 + k)) & 1u ? find_key(A, nX, edge_key(A.nx, i + 1, j, 1, k)) : -1;
+    xs[2] = (b3 >> k) & 1u ? find_key(A, nX, edge_key(A.nx, i, j + 1, 0, k)) : -1;
+    xs[3] = (b0 >> (2 + k)) & 1u ? find_key(A, nX, edge_key(A.nx, i, j, 1, k)) : -1;
     int n = 0;
     for (int m = 0; m < 4; ++m) n += xs[m] >= 0 ? 1 : 0;
     if (P > 0.0) {
@@ -296,10 +333,12 @@ __device__ CellRes cell_logic(const SingArgs& A, int i, int j, int nX, int uidx,
         emit(a, b, k);
         r.nseg += 1;
       } else if (n == 4) {
-        const double F0 = c0.f(k);
-        const double F1 = align(c0, c1, k) * c1.f(k);
-        const double F2 = align(c0, c1, k) * align(c1, c2, k) * c2.f(k);
-        const double F3 = align(c0, c3, k) * c3.f(k);
+        const double* f = k ? A.f2 : A.f1;
+        const double a01 = bsign(b0, 4 + 2 * k), a12 = bsign(b1, 5 + 2 * k), a03 = bsign(b0, 5 + 2 * k);
+        const double F0 = f[p0];
+        const double F1 = a01 * f[p0 + 1];
+        const double F2 = a01 * a12 * f[p0 + A.nx + 1];
+        const double F3 = a03 * f[p0 + A.nx];
         const double D = F0 + F2 - F1 - F3;
         const bool cpos = D == 0.0 ? true : !neg((F0 * F2 - F1 * F3) / D);
         if (cpos == !neg(F0)) { emit(xs[0], xs[1], k); emit(xs[2], xs[3], k); }
@@ -454,58 +493,63 @@ __global__ __launch_bounds__(NT) void k_sing_swt(const SingArgs A) {
 // central differences (step 1e-3 h) and grad g_k by central differences of g (step 1e-2 h):
 // status 0 converged (step < 1e-10") within h of the start, 1 no convergence in 20 steps, 2
 // moved farther than h (the interpolated point is kept), | 8 an umbilic-flagged evaluation;
-// then e_k at the point.
-__device__ void swallowtail_one(const SingArgs& A, int n) {
-  const int k = A.wk[n] - 1;
-  const double x0 = A.wpos[2 * (size_t)n], y0 = A.wpos[2 * (size_t)n + 1];
-  double x = x0, y = y0;
-  int st = 0;
-  if (A.refine) {
-    const double d = 1e-3 * A.h, dg = 1e-2 * A.h;
-    bool conv = false, umb = false;
-#pragma unroll 1
-    for (int it = 0; it < 20; ++it) {
-      double f = 0.0, fx = 0.0, fy = 0.0, g = 0.0, sgx = 0.0, sgy = 0.0;
-#pragma unroll 1
-      for (int m = 0; m < 5; ++m) {        // g at the point, then at (x +- dg, y), (x, y +- dg)
+// then e_k at the point.  One workgroup of five waves per swallowtail: wave m evaluates g at
+// the point (m = 0) or at (x +- dg, y), (x, y +- dg) (m = 1..4); the step is formed from LDS.
+constexpr int SWT_WAVES = 5;
+__global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingArgs A) {
+  __shared__ double gl[SWT_WAVES], fl3[3];
+  __shared__ int ul[SWT_WAVES];
+  const int nW = min(A.counts[3], A.cap);
+  const int m = threadIdx.x >> 6;
+  for (int n = blockIdx.x; n < nW; n += gridDim.x) {
+    const int k = A.wk[n] - 1;
+    const double x0 = A.wpos[2 * (size_t)n], y0 = A.wpos[2 * (size_t)n + 1];
+    double x = x0, y = y0;
+    int st = 0;
+    if (A.refine) {
+      const double d = 1e-3 * A.h, dg = 1e-2 * A.h;
+      bool conv = false, umb = false;
+      for (int it = 0; it < 20; ++it) {
         const double qx = m == 1 ? x + dg : m == 2 ? x - dg : x;
         const double qy = m == 3 ? y + dg : m == 4 ? y - dg : y;
+        bool u = false;
         const VA3 P = point_a3(A, qx, qy);
-        if (P.umb) umb = true;
+        if (P.umb) u = true;
         double gx_, gy_;
-        fd_grad(A, P, qx, qy, k, d, umb, gx_, gy_);
-        const double gm = P.vx(k) * gx_ + P.vy(k) * gy_;
-        if (m == 0) { f = P.f(k); fx = gx_; fy = gy_; g = gm; }
-        else if (m == 1) sgx = gm;
-        else if (m == 2) sgx = sgx - gm;
-        else if (m == 3) sgy = gm;
-        else sgy = sgy - gm;
+        fd_grad(A, P, qx, qy, k, d, u, gx_, gy_);
+        if ((threadIdx.x & 63) == 0) {
+          gl[m] = P.vx(k) * gx_ + P.vy(k) * gy_;
+          ul[m] = u ? 1 : 0;
+          if (m == 0) { fl3[0] = P.f(k); fl3[1] = gx_; fl3[2] = gy_; }
+        }
+        __syncthreads();
+        const double f = fl3[0], fx = fl3[1], fy = fl3[2], g = gl[0];
+        for (int q = 0; q < SWT_WAVES; ++q) umb = umb || ul[q] != 0;
+        const double gx = (gl[1] - gl[2]) / (2 * dg), gy = (gl[3] - gl[4]) / (2 * dg);
+        __syncthreads();
+        const double det = fx * gy - fy * gx;
+        const double sx = -(gy * f - fy * g) / det, sy = -(-gx * f + fx * g) / det;
+        x += sx;
+        y += sy;
+        if (!isfinite(x) || !isfinite(y)) break;
+        if (sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
       }
-      const double gx = sgx / (2 * dg), gy = sgy / (2 * dg);
-      const double det = fx * gy - fy * gx;
-      const double sx = -(gy * f - fy * g) / det, sy = -(-gx * f + fx * g) / det;
-      x += sx;
-      y += sy;
-      if (!isfinite(x) || !isfinite(y)) break;
-      if (sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
+      st = conv ? 0 : 1;
+      if (conv && sqrt((x - x0) * (x - x0) + (y - y0) * (y - y0)) > A.h) st = 2;
+      if (umb) st |= 8;
+      if (st != 0) { x = x0; y = y0; }
     }
-    st = conv ? 0 : 1;
-    if (conv && sqrt((x - x0) * (x - x0) + (y - y0) * (y - y0)) > A.h) st = 2;
-    if (umb) st |= 8;
-    if (st != 0) { x = x0; y = y0; }
+    if (m == 0) {
+      const VA3 P = point_a3(A, x, y);
+      if (threadIdx.x == 0) {
+        A.wpos[2 * (size_t)n] = x;
+        A.wpos[2 * (size_t)n + 1] = y;
+        A.we[n] = P.e(k);
+        A.wstat[n] = st;
+      }
+    }
+    __syncthreads();
   }
-  const VA3 P = point_a3(A, x, y);
-  if ((threadIdx.x & 63) == 0) {
-    A.wpos[2 * (size_t)n] = x;
-    A.wpos[2 * (size_t)n + 1] = y;
-    A.we[n] = P.e(k);
-    A.wstat[n] = st;
-  }
-}
-__global__ __launch_bounds__(NT) void k_sing_swt_refine(const SingArgs A) {
-  const int nW = min(A.counts[3], A.cap);
-  const int nw = gridDim.x * (NT / 64);
-  for (int n = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); n < nW; n += nw) swallowtail_one(A, n);
 }
 
 hipError_t launch_sing(const SingArgs& A, int n_cu, hipStream_t st, void (*mark)(void*, const char*, int),
@@ -513,9 +557,9 @@ hipError_t launch_sing(const SingArgs& A, int n_cu, hipStream_t st, void (*mark)
   const int waves_grid = n_cu * 8;
   const unsigned chunks = (unsigned)((A.cap + NT - 1) / NT);
   mark(ctx, "sing_edges", 0);
-  hipLaunchKernelGGL(k_sing_edges<false>, dim3(A.ny), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(k_sing_bits, dim3(A.ny), dim3(NT), 0, st, A);
   hipLaunchKernelGGL(k_sing_scan, dim3(1), dim3(NT), 0, st, A.xrow_cnt, A.ny, A.xrow_off, A.counts + 0);
-  hipLaunchKernelGGL(k_sing_edges<true>, dim3(A.ny), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(k_sing_keys, dim3(A.ny), dim3(NT), 0, st, A);
   mark(ctx, "sing_edges", 1);
   mark(ctx, "sing_refine", 0);
   hipLaunchKernelGGL(k_sing_refine, dim3(waves_grid), dim3(NT), 0, st, A);
@@ -535,7 +579,7 @@ hipError_t launch_sing(const SingArgs& A, int n_cu, hipStream_t st, void (*mark)
   hipLaunchKernelGGL(k_sing_swt<false>, dim3(chunks), dim3(NT), 0, st, A);
   hipLaunchKernelGGL(k_sing_scan, dim3(1), dim3(NT), 0, st, A.wch_cnt, (int)chunks, A.wch_off, A.counts + 3);
   hipLaunchKernelGGL(k_sing_swt<true>, dim3(chunks), dim3(NT), 0, st, A);
-  hipLaunchKernelGGL(k_sing_swt_refine, dim3(waves_grid), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(k_sing_swt_refine, dim3(n_cu * 4), dim3(64 * SWT_WAVES), 0, st, A);
   mark(ctx, "sing_swt", 1);
   return hipGetLastError();
 }
