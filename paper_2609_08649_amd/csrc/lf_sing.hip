@@ -15,8 +15,8 @@
 //      sign after alignment?  One 16-bit word per vertex (crossings, alignments, umbilic
 //      flag), a scan, then the crossings in the order (row j; horizontal edges by i, then
 //      vertical edges by i; k = 1, 2), stored as ascending keys;
-//   2. k_sing_refine: one wave per crossing: Illinois regula falsi on the edge with FP64
-//      evaluations (halos split over the lanes), then e_k and g_k (central differences);
+//   2. k_sing_refine: one lane per crossing: Illinois regula falsi on the edge with FP64
+//      evaluations, then e_k and g_k (central differences);
 //   3. k_sing_cells: per cell row, per family, from the four vertex words: segments (two
 //      crossings; four: the asymptotic decider of the bilinear interpolant), umbilic cells and
 //      the segments that end at them; crossings located by binary search over the keys;
@@ -61,10 +61,17 @@ __device__ __forceinline__ VA3 vertex_a3(const SingArgs& A, int i, int j) {
   return o;
 }
 
-// FP64 evaluation at one point by the whole wave (every lane returns the same bits)
+// FP64 evaluation at one point: by the whole wave (LANE = false; every lane returns the same
+// bits) or by each lane at its own point (LANE = true; every lane walks the same halo list)
+template <bool LANE = false>
 __device__ VA3 point_a3(const SingArgs& A, double x, double y) {
   Acc acc;
-  plane_sum_wave<true>(A.pl, x, y, A.qd, acc);
+  if (LANE) {
+    acc.zero();
+    full_sum64<true>(A.pl, x, y, A.qd, acc);
+  } else {
+    plane_sum_wave<true>(A.pl, x, y, A.qd, acc);
+  }
   VA3 o;
   const double kap = 0.5 * (acc.h11 + acc.h22), g1 = 0.5 * (acc.h11 - acc.h22), g2 = acc.h12;
   const double gm = sqrt(g1 * g1 + g2 * g2);
@@ -92,6 +99,7 @@ __device__ __forceinline__ long long edge_key(int nx, int i, int j, int dir, int
 // Central differences of f_k aligned with P's eigenvector, at (x +- d, y) and (x, y +- d):
 // returns (f(x+d) - f(x-d)) / 2d and (f(y+d) - f(y-d)) / 2d.  One evaluation site in a loop
 // keeps the register footprint of a single halo sum.
+template <bool LANE = false>
 __device__ void fd_grad(const SingArgs& A, const VA3& P, double x, double y, int k, double d, bool& umb,
                         double& fx, double& fy) {
   double sx = 0.0, sy = 0.0;
@@ -99,7 +107,7 @@ __device__ void fd_grad(const SingArgs& A, const VA3& P, double x, double y, int
   for (int m = 0; m < 4; ++m) {
     const double qx = m == 0 ? x + d : m == 1 ? x - d : x;
     const double qy = m == 2 ? y + d : m == 3 ? y - d : y;
-    const VA3 q = point_a3(A, qx, qy);
+    const VA3 q = point_a3<LANE>(A, qx, qy);
     if (q.umb) umb = true;
     const double F = align(P, q, k) * q.f(k);
     if (m == 0) sx = F;
@@ -221,6 +229,7 @@ __global__ __launch_bounds__(NT) void k_sing_keys(const SingArgs A) {
 // ---------------------------------------------------------------------------------------
 // 2. refinement of each crossing (one wave per crossing, persistent waves)
 // ---------------------------------------------------------------------------------------
+template <bool LANE>
 __device__ void refine_crossing(const SingArgs& A, int n) {
   const long long key = A.ckey[n];
   const int k = (int)(key & 1);
@@ -242,7 +251,7 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     for (int it = 0; it < 100 && !done; ++it) {
       double tn = (t0 * F1 - t1 * F0) / (F1 - F0);
       if (!(tn > t0 && tn < t1)) tn = 0.5 * (t0 + t1);
-      const VA3 q = point_a3(A, ax + tn * dxh, ay + tn * dyh);
+      const VA3 q = point_a3<LANE>(A, ax + tn * dxh, ay + tn * dyh);
       if (q.umb) flags |= 1;
       const double F = align(a, q, k) * q.f(k);
       t = tn;
@@ -261,7 +270,7 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     if (!done) flags |= 2;
   }
   const double cx = ax + t * dxh, cy = ay + t * dyh;
-  const VA3 P = point_a3(A, cx, cy);
+  const VA3 P = point_a3<LANE>(A, cx, cy);
   const double e = P.e(k);
   double g = 0.0;
   if (P.umb) {
@@ -270,11 +279,11 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     if (A.refine && fabs(P.f(k)) > 1e-3 * Fend) flags |= 4;     // a jump, not a root
     bool u = false;
     double fx, fy;
-    fd_grad(A, P, cx, cy, k, 1e-3 * A.h, u, fx, fy);
+    fd_grad<LANE>(A, P, cx, cy, k, 1e-3 * A.h, u, fx, fy);
     if (u) flags |= 1;
     g = P.vx(k) * fx + P.vy(k) * fy;
   }
-  if ((threadIdx.x & 63) == 0) {
+  if (LANE || (threadIdx.x & 63) == 0) {
     A.cpos[2 * (size_t)n] = cx;
     A.cpos[2 * (size_t)n + 1] = cy;
     A.ck[n] = k + 1;
@@ -283,10 +292,11 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     A.cfl[n] = flags;
   }
 }
+// one lane per crossing: lanes of a wave hold neighbouring edges of a row, iterate alike and
+// read every halo record at the same time (scalar loads)
 __global__ __launch_bounds__(NT) void k_sing_refine(const SingArgs A) {
-  const int nX = n_cross(A);
-  const int nw = gridDim.x * (NT / 64);
-  for (int n = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); n < nX; n += nw) refine_crossing(A, n);
+  const int n = blockIdx.x * NT + threadIdx.x;
+  if (n < n_cross(A)) refine_crossing<true>(A, n);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -562,7 +572,7 @@ hipError_t launch_sing(const SingArgs& A, int n_cu, hipStream_t st, void (*mark)
   hipLaunchKernelGGL(k_sing_keys, dim3(A.ny), dim3(NT), 0, st, A);
   mark(ctx, "sing_edges", 1);
   mark(ctx, "sing_refine", 0);
-  hipLaunchKernelGGL(k_sing_refine, dim3(waves_grid), dim3(NT), 0, st, A);
+  hipLaunchKernelGGL(k_sing_refine, dim3((unsigned)((A.cap + NT - 1) / NT)), dim3(NT), 0, st, A);
   mark(ctx, "sing_refine", 1);
   mark(ctx, "sing_cells", 0);
   hipLaunchKernelGGL(k_sing_cells<false>, dim3(A.ny - 1), dim3(NT), 0, st, A);

@@ -1,8 +1,9 @@
 """GPU parity of lf_singularity_map (Sec. 6: A3 lines, umbilics, swallowtails) against the
 oracle's extraction on the same seeded lenses.
 
-FP64: counts, crossing order, families and flags, segments, umbilic and swallowtail statuses
-are identical (integer decisions taken on FP64 values on both sides); refined crossing
+FP64: counts, crossing order, families and flags, segments and umbilic statuses are identical
+(integer decisions taken on FP64 values on both sides; a swallowtail's "converged within 20
+Newton steps" may flip for a slowly converging point, at most 2% of them); refined crossing
 positions agree to 1e-9" (both are roots of f_k bracketed to 1e-10"), umbilics to 1e-8",
 swallowtails to 1e-7" (Newton on finite-difference g), e_k and kappa to 1e-9 relative.
 MIXED: only the vertex pass is FP32-based, so a crossing whose edge has a near-zero vertex
@@ -51,7 +52,11 @@ def _compare_exact(g, o):
     assert np.array_equal(gc["k"], oc["k"]) and np.array_equal(gc["flags"], oc["flags"])
     assert np.max(np.abs(gc["pos"] - oc["pos"]), initial=0) < 1e-9
     ok = gc["flags"] == 0
-    assert np.allclose(gc["e"][ok], oc["e"][ok], rtol=1e-9, atol=1e-12)
+    # e_k at the crossing: the two positions agree to ~1e-10", and near a member centre
+    # |grad e| ~ e^2 / b, so e may differ by ~e^2 |d theta| beyond rounding
+    dpos = np.abs(gc["pos"] - oc["pos"]).max(1)
+    tol_e = 1e-9 * (1 + np.abs(oc["e"])) + 10 * oc["e"] ** 2 * dpos
+    assert np.all(np.abs(gc["e"] - oc["e"])[ok] <= tol_e[ok])
     assert np.allclose(gc["g"][ok], oc["g"][ok], rtol=1e-6, atol=1e-9 * (1 + np.abs(oc["g"][ok]).max(initial=0)))
     for k in ("a", "b", "k"):
         assert np.array_equal(g["seg"][k], o["seg"][k])
@@ -61,10 +66,16 @@ def _compare_exact(g, o):
     assert np.max(np.abs(gu["pos"][good] - ou["pos"][good]), initial=0) < 1e-8
     assert np.allclose(gu["kappa"][good], ou["kappa"][good], rtol=1e-9, atol=1e-12)
     gw, ow = g["swt"], o["swt"]
-    for k in ("k", "seg", "status"):
+    for k in ("k", "seg"):
         assert np.array_equal(gw[k], ow[k])
-    assert np.max(np.abs(gw["pos"] - ow["pos"]), initial=0) < 1e-7
-    assert np.allclose(gw["e"], ow["e"], rtol=1e-7, atol=1e-10)
+    # "converged within 20 steps" is a threshold on an iteration count: for a slowly
+    # converging point, rounding-level differences in its start can flip it
+    diff = gw["status"] != ow["status"]
+    assert np.all(np.isin(gw["status"][diff], (0, 1)) & np.isin(ow["status"][diff], (0, 1)))
+    assert diff.sum() <= max(1, 0.02 * diff.size)
+    both = (gw["status"] == 0) & (ow["status"] == 0)
+    assert np.max(np.abs(gw["pos"][both] - ow["pos"][both]), initial=0) < 1e-7
+    assert np.allclose(gw["e"][both], ow["e"][both], rtol=1e-7, atol=1e-10)
 
 
 @pytest.mark.parametrize("seed", [3, 4, 5])
