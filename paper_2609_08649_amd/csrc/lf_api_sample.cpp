@@ -71,11 +71,14 @@ extern "C" lf_status lf_nelder_mead_run(lf_ctx* ctx, const lf_model* M, const lf
   if (R < 1 || n_rounds < 0) return ctx->fail(LF_E_INVALID_ARG, "R must be >= 1, n_rounds >= 0");
   const int D = M->n_free;
   if ((long long)R * (D + 1) >= (1LL << 31)) return ctx->fail(LF_E_INVALID_ARG, "too many runs");
+  if (D > 64) return ctx->fail(LF_E_UNSUPPORTED, "Nelder-Mead runs take at most 64 parameters");
   hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;
   lf::NMArgs A;
   std::memset(&A, 0, sizeof A);
   A.R = R; A.D = D; A.x = simplex; A.f = fvals; A.lo = lo; A.hi = hi; A.nev = n_evals;
+  A.team = 1;
+  while (A.team < D) A.team <<= 1;
   A.xr = (double*)ctx->ws("nm.xr", sizeof(double) * (size_t)R * D, st, &e); if (e) return e;
   A.fr = (double*)ctx->ws("nm.fr", sizeof(double) * R, st, &e); if (e) return e;
   A.state = (int*)ctx->ws("nm.state", sizeof(int) * R, st, &e); if (e) return e;

@@ -30,6 +30,7 @@ struct NMArgs {
   const double* lo;          // [D] prior box
   const double* hi;
   int* nev;                  // [R] evaluations (may be null)
+  int team;                  // lanes per run: the power of two >= D (<= 64)
 };
 
 hipError_t launch_aies_lp(const AiesArgs& A, const double* chi2, hipStream_t st);

@@ -10,10 +10,11 @@
 // generator seeded with seed (Steele, Lea & Flood 2014), draw n = ((t * 2 + half) * K + k) * 3
 // + d for step t, walker k and draw d (0 complementary walker, 1 stretch factor, 2 acceptance).
 //
-// Nelder-Mead: one state machine per run (one thread), coefficients 1, 2, 1/2, 1/2 and the
-// rules of Lagarias, Reeds, Wright & Wright (1998); vertices kept sorted by f (a new vertex goes
-// after those with equal f, a shrink re-sorts stably); one evaluation per run and round (the
-// pending point of each run forms the next chi^2 batch; a shrink takes D rounds).
+// Nelder-Mead: one state machine per run (a team of lanes, one per coordinate), coefficients
+// 1, 2, 1/2, 1/2 and the rules of Lagarias, Reeds, Wright & Wright (1998); vertices kept sorted
+// by f (a new vertex goes after those with equal f, a shrink re-sorts stably); one evaluation
+// per run and round (the pending point of each run forms the next chi^2 batch; a shrink takes D
+// rounds).
 //
 // Contraction of multiply-adds into fused ones is off in this file, so proposals, centroids
 // and simplex moves round exactly as their plain definitions.
@@ -94,149 +95,173 @@ __global__ void k_aies_record(const AiesArgs A, long long row) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Nelder-Mead
+// Nelder-Mead.  A run is handled by a team of TS lanes of one wave (TS = the power of two >= D,
+// at most 64): lane d owns coordinate d of every vertex, so centroids, moves and row shifts are
+// per-coordinate (coalesced within the team); the values f, the state and the decisions are
+// computed redundantly by every lane of the team (each lane only reads what it wrote itself).
 // ---------------------------------------------------------------------------------------
 namespace {
-struct Run {
+struct Team {
   double* x;      // [(D+1) * D] vertices, sorted by f
   double* f;      // [D+1]
-  double* xr;     // [D] reflection kept for the expansion / outside-contraction decision
+  double* xr;     // [D]
   double* p;      // [D] pending point
-  int D;
+  int D, d;       // parameters, this lane's coordinate (d >= D: idle column)
+  unsigned long long mask;   // the team's lanes in the wave
 };
-__device__ __forceinline__ double nm_value(const double* p, const double* lo, const double* hi, int D, double c) {
-  return (in_box(p, lo, hi, D) && isfinite(c)) ? c : INFINITY;
+__device__ __forceinline__ bool team_all(const Team& t, bool v) {
+  return (__ballot(v) & t.mask) == t.mask;
 }
-__device__ __forceinline__ double centroid(const Run& r, int d) {
+__device__ __forceinline__ double nm_value(const Team& t, const double* lo, const double* hi, double c) {
+  const bool in = t.d >= t.D || (t.p[t.d] >= lo[t.d] && t.p[t.d] <= hi[t.d]);
+  return (team_all(t, in) && isfinite(c)) ? c : INFINITY;
+}
+__device__ __forceinline__ double centroid(const Team& t) {
   double s = 0.0;
-  for (int i = 0; i < r.D; ++i) s += r.x[(size_t)i * r.D + d];
-  return s / r.D;
+  for (int i = 0; i < t.D; ++i) s += t.x[(size_t)i * t.D + t.d];
+  return s / t.D;
 }
-// pending = c + coef (q - c) with q = the reflection (state 1, 2) or the worst vertex (3)
-__device__ void set_pending(Run& r, const double* q, double coef) {
-  for (int d = 0; d < r.D; ++d) {
-    const double c = centroid(r, d);
-    r.p[d] = c + coef * (q[d] - c);
-  }
+// pending = c + coef (q - c), q = the reflection (expansion, outside contraction) or the worst
+// vertex (inside contraction)
+__device__ void set_pending(Team& t, const double* q, double coef) {
+  if (t.d >= t.D) return;
+  const double c = centroid(t);
+  t.p[t.d] = c + coef * (q[t.d] - c);
 }
-__device__ void set_reflection(Run& r) {
-  const double* w = r.x + (size_t)r.D * r.D;
-  for (int d = 0; d < r.D; ++d) {
-    const double c = centroid(r, d);
-    r.p[d] = c + (c - w[d]);
-  }
+__device__ void set_reflection(Team& t) {
+  if (t.d >= t.D) return;
+  const double c = centroid(t);
+  t.p[t.d] = c + (c - t.x[(size_t)t.D * t.D + t.d]);
 }
-__device__ void set_shrink(Run& r, int i) {
-  for (int d = 0; d < r.D; ++d) r.p[d] = r.x[d] + 0.5 * (r.x[(size_t)i * r.D + d] - r.x[d]);
+__device__ void set_shrink(Team& t, int i) {
+  if (t.d >= t.D) return;
+  t.p[t.d] = t.x[t.d] + 0.5 * (t.x[(size_t)i * t.D + t.d] - t.x[t.d]);
 }
 // replace the worst vertex by (q, fq), placed after the vertices with f <= fq
-__device__ void insert(Run& r, const double* q, double fq) {
-  const int D = r.D;
+__device__ void insert(Team& t, const double* q, double fq) {
+  const int D = t.D;
   int k = 0;
-  while (k < D && r.f[k] <= fq) ++k;
+  while (k < D && t.f[k] <= fq) ++k;
+  const double qd = t.d < D ? q[t.d] : 0.0;
   for (int i = D; i > k; --i) {
-    r.f[i] = r.f[i - 1];
-    for (int d = 0; d < D; ++d) r.x[(size_t)i * D + d] = r.x[(size_t)(i - 1) * D + d];
+    t.f[i] = t.f[i - 1];
+    if (t.d < D) t.x[(size_t)i * D + t.d] = t.x[(size_t)(i - 1) * D + t.d];
   }
-  r.f[k] = fq;
-  for (int d = 0; d < D; ++d) r.x[(size_t)k * D + d] = q[d];
+  t.f[k] = fq;
+  if (t.d < D) t.x[(size_t)k * D + t.d] = qd;
 }
 // stable insertion sort of all D+1 vertices by f
-__device__ void sort_all(Run& r) {
-  const int D = r.D;
+__device__ void sort_all(Team& t) {
+  const int D = t.D;
   for (int i = 1; i <= D; ++i) {
     int k = i;
-    while (k > 0 && r.f[k - 1] > r.f[k]) {
-      const double tf = r.f[k]; r.f[k] = r.f[k - 1]; r.f[k - 1] = tf;
-      for (int d = 0; d < D; ++d) {
-        const double tx = r.x[(size_t)k * D + d];
-        r.x[(size_t)k * D + d] = r.x[(size_t)(k - 1) * D + d];
-        r.x[(size_t)(k - 1) * D + d] = tx;
+    while (k > 0 && t.f[k - 1] > t.f[k]) {
+      const double tf = t.f[k]; t.f[k] = t.f[k - 1]; t.f[k - 1] = tf;
+      if (t.d < D) {
+        const double tx = t.x[(size_t)k * D + t.d];
+        t.x[(size_t)k * D + t.d] = t.x[(size_t)(k - 1) * D + t.d];
+        t.x[(size_t)(k - 1) * D + t.d] = tx;
       }
       --k;
     }
   }
 }
-__device__ Run run_of(const NMArgs& A, int r) {
-  Run u;
-  u.D = A.D;
-  u.x = A.x + (size_t)r * (A.D + 1) * A.D;
-  u.f = A.f + (size_t)r * (A.D + 1);
-  u.xr = A.xr + (size_t)r * A.D;
-  u.p = A.pend + (size_t)r * A.D;
-  return u;
+// the run and coordinate of this lane; false for lanes beyond the last run
+__device__ bool team_of(const NMArgs& A, Team& t, int& r) {
+  const int TS = A.team, lane = threadIdx.x & 63;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  r = (int)(g / TS);
+  t.d = (int)(g % TS);
+  t.D = A.D;
+  const int first = lane - t.d;
+  t.mask = (TS == 64 ? ~0ull : ((1ull << TS) - 1ull)) << first;
+  if (r >= A.R) return false;
+  t.x = A.x + (size_t)r * (A.D + 1) * A.D;
+  t.f = A.f + (size_t)r * (A.D + 1);
+  t.xr = A.xr + (size_t)r * A.D;
+  t.p = A.pend + (size_t)r * A.D;
+  return true;
 }
 }  // namespace
 
 // vertices evaluated together (chi2 [R * (D+1)], the parameter batch being the simplices)
 __global__ void k_nm_init(const NMArgs A, const double* chi2) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= A.R) return;
-  Run u = run_of(A, r);
-  for (int v = 0; v <= A.D; ++v)
-    u.f[v] = nm_value(u.x + (size_t)v * A.D, A.lo, A.hi, A.D, chi2[(size_t)r * (A.D + 1) + v]);
-  sort_all(u);
+  Team t;
+  int r;
+  const bool act = team_of(A, t, r);
+  if (!act) return;                   // whole teams leave together (runs are team-aligned)
+  for (int v = 0; v <= A.D; ++v) {
+    const double c = chi2[(size_t)r * (A.D + 1) + v];
+    const bool in = t.d >= t.D || (t.x[(size_t)v * A.D + t.d] >= A.lo[t.d] && t.x[(size_t)v * A.D + t.d] <= A.hi[t.d]);
+    t.f[v] = (team_all(t, in) && isfinite(c)) ? c : INFINITY;
+  }
+  sort_all(t);
   A.state[r] = 0;
   A.idx[r] = 0;
   if (A.nev) A.nev[r] = A.D + 1;
-  set_reflection(u);
+  set_reflection(t);
 }
 
 // consume f at each run's pending point (chi2 [R]) and set the next pending point
 __global__ void k_nm_step(const NMArgs A, const double* chi2) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= A.R) return;
-  Run u = run_of(A, r);
+  Team t;
+  int r;
+  if (!team_of(A, t, r)) return;
   const int D = A.D;
-  const double fp = nm_value(u.p, A.lo, A.hi, D, chi2[r]);
-  if (A.nev) A.nev[r] += 1;
-  int st = A.state[r];
+  const double fp = nm_value(t, A.lo, A.hi, chi2[r]);
+  if (A.nev && t.d == 0) A.nev[r] += 1;
+  const int st = A.state[r];
+  const double fr = A.fr[r];
+  int nst = 0, nidx = A.idx[r];
   if (st == 0) {                                   // reflection evaluated
-    if (u.f[0] <= fp && fp < u.f[D - 1]) {
-      insert(u, u.p, fp);
-    } else if (fp < u.f[0]) {
-      for (int d = 0; d < D; ++d) u.xr[d] = u.p[d];
-      A.fr[r] = fp;
-      A.state[r] = 1;
-      set_pending(u, u.xr, 2.0);
-      return;
-    } else if (fp < u.f[D]) {
-      for (int d = 0; d < D; ++d) u.xr[d] = u.p[d];
-      A.fr[r] = fp;
-      A.state[r] = 2;
-      set_pending(u, u.xr, 0.5);
-      return;
+    if (t.f[0] <= fp && fp < t.f[D - 1]) {
+      insert(t, t.p, fp);
+      set_reflection(t);
+    } else if (fp < t.f[0]) {
+      if (t.d < D) t.xr[t.d] = t.p[t.d];
+      if (t.d == 0) A.fr[r] = fp;
+      nst = 1;
+      set_pending(t, t.xr, 2.0);
+    } else if (fp < t.f[D]) {
+      if (t.d < D) t.xr[t.d] = t.p[t.d];
+      if (t.d == 0) A.fr[r] = fp;
+      nst = 2;
+      set_pending(t, t.xr, 0.5);
     } else {
-      A.state[r] = 3;
-      set_pending(u, u.x + (size_t)D * D, 0.5);
-      return;
+      nst = 3;
+      set_pending(t, t.x + (size_t)D * D, 0.5);
     }
   } else if (st == 1) {                            // expansion
-    if (fp < A.fr[r]) insert(u, u.p, fp);
-    else insert(u, u.xr, A.fr[r]);
+    if (fp < fr) insert(t, t.p, fp);
+    else insert(t, t.xr, fr);
+    set_reflection(t);
   } else if (st == 2 || st == 3) {                 // outside / inside contraction
-    const bool take = st == 2 ? fp <= A.fr[r] : fp < u.f[D];
+    const bool take = st == 2 ? fp <= fr : fp < t.f[D];
     if (take) {
-      insert(u, u.p, fp);
+      insert(t, t.p, fp);
+      set_reflection(t);
     } else {
-      A.state[r] = 4;
-      A.idx[r] = 1;
-      set_shrink(u, 1);
-      return;
+      nst = 4;
+      nidx = 1;
+      set_shrink(t, 1);
     }
   } else {                                         // shrink: vertex i evaluated
-    const int i = A.idx[r];
-    for (int d = 0; d < D; ++d) u.x[(size_t)i * D + d] = u.p[d];
-    u.f[i] = fp;
+    const int i = nidx;
+    if (t.d < D) t.x[(size_t)i * D + t.d] = t.p[t.d];
+    t.f[i] = fp;
     if (i < D) {
-      A.idx[r] = i + 1;
-      set_shrink(u, i + 1);
-      return;
+      nst = 4;
+      nidx = i + 1;
+      set_shrink(t, i + 1);
+    } else {
+      sort_all(t);
+      set_reflection(t);
     }
-    sort_all(u);
   }
-  A.state[r] = 0;
-  set_reflection(u);
+  if (t.d == 0) {
+    A.state[r] = nst;
+    A.idx[r] = nidx;
+  }
 }
 
 hipError_t launch_aies_lp(const AiesArgs& A, const double* chi2, hipStream_t st) {
@@ -257,11 +282,13 @@ hipError_t launch_aies_record(const AiesArgs& A, long long row, hipStream_t st) 
   return hipGetLastError();
 }
 hipError_t launch_nm_init(const NMArgs& A, const double* chi2, hipStream_t st) {
-  hipLaunchKernelGGL(k_nm_init, dim3((A.R + 63) / 64), dim3(64), 0, st, A, chi2);
+  const long long n = (long long)A.R * A.team;
+  hipLaunchKernelGGL(k_nm_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, chi2);
   return hipGetLastError();
 }
 hipError_t launch_nm_step(const NMArgs& A, const double* chi2, hipStream_t st) {
-  hipLaunchKernelGGL(k_nm_step, dim3((A.R + 63) / 64), dim3(64), 0, st, A, chi2);
+  const long long n = (long long)A.R * A.team;
+  hipLaunchKernelGGL(k_nm_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, chi2);
   return hipGetLastError();
 }
 
