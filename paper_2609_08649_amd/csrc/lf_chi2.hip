@@ -42,7 +42,7 @@ __device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, 
     T r2 = fma(dx, dx, dy * dy);
     if (s == (T)0 && r2 < (T)1e-24) return false;
     T m, w, p = 0;
-    if constexpr (SEG == SEG_CPJE) pje_mw<D3>(b, s, a, s * s, a * a, a - s, (a - s) * (a + s), r2, m, w, p);
+    if constexpr (SEG == SEG_CPJE) pje_mw<D3>(b, s, a, s * s, a * a, b * (a - s), a + s, r2, m, w, p);
     else cored_mw<D3>(b, s, s * s, r2, m, w, p);
     radial<D3>(dx, dy, m, w, p, t);
   } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
@@ -106,7 +106,8 @@ __device__ __forceinline__ void seg_ls(const MemCat* __restrict__ cat, int lo, i
 // The bulk circular segments in FP32 (MemCat32): offsets from FP32 pairs, terms summed in
 // FP32 over runs of 16 members and each run added to the FP64 accumulators (the same scheme
 // as the maps kernels).  A member closer than its near-field radius (NEAR_K b / q) is
-// evaluated from the FP64 catalog instead; its FP32 term is taken at r^2 = 1e30 (below 1e-14).
+// evaluated from the FP64 catalog instead; its FP32 term is taken at r^2 = 1e24 (dPIE) or 1e30
+// (cored isothermal), where it is below 1e-14.
 template <int SEG>
 __device__ __forceinline__ void seg_ls32(const MemCat32* __restrict__ cat, const MemCat* __restrict__ cat64,
                                          int lo, int hi, double px, double py, const MulRec& u, Acc& acc,
@@ -126,12 +127,11 @@ __device__ __forceinline__ void seg_ls32(const MemCat32* __restrict__ cat, const
       float b = bm * c.fb, s = sm_ * c.fs;
       float r2 = fmaf(dx, dx, dy * dy);
       const bool nr = r2 < fmaxf(bm2 * c.fbk2, 1e-12f);   // also catches r = 0 for b = 0
-      if (nr) r2 = 1e30f;
+      if (nr) r2 = SEG == SEG_CPJE ? 1e24f : 1e30f;   // far enough for a term below 1e-14
       float m, w, p = 0.f;
       if constexpr (SEG == SEG_CPJE) {
         float a = am * c.fa;
-        float das = a - s;
-        pje_mw<false>(b, s, a, s * s, a * a, das, das * (a + s), r2, m, w, p);
+        pje_mw<false>(b, s, a, s * s, a * a, b * (a - s), a + s, r2, m, w, p);
       } else {
         cored_mw<false>(b, s, s * s, r2, m, w, p);
       }

@@ -103,27 +103,30 @@ __device__ __forceinline__ void cored_mw(T b, T s, T s2, T r2, T& m, T& w, T& wp
 }
 
 // Circular pseudo-Jaffe (dPIE, Sec. 3.4): the cored term with core s minus the same with
-// core a > s, written without cancellation.  With R_c = sqrt(c^2 + r^2), D_c = R_c + c:
-//   dR = R_a - R_s = (a^2 - s^2) / (R_a + R_s),   dD = D_a - D_s = (a - s) + dR,
-//   m  = b/D_s - b/D_a = b dD / (D_s D_a),
-//   w  = -b/(D_s^2 R_s) + b/(D_a^2 R_a) = -b (D_a^2 dR + R_s dD (D_a + D_s)) / ((D_s D_a)^2 R_s R_a),
-// every term positive.  Subtracting two cored terms instead loses about log2(r/a) bits far
-// from the member, where both terms are ~ b/r and their difference ~ b (a - s)/r^2.
-// das = a - s and da2 = a^2 - s^2 are supplied by the caller.  w' (third derivatives only)
-// is the difference of the per-core derivatives b u^2 is^2 (u + is/2), u = 1/D, is = 1/R.
+// core a > s, written without cancellation.  With R_c = sqrt(c^2 + r^2), D_c = R_c + c,
+// Sg = R_s + R_a and G = D_s + D_a = Sg + a + s:
+//   R_a - R_s = (a^2 - s^2) / Sg,   D_a - D_s = (a - s) G / Sg,
+//   m = b/D_s - b/D_a = b (a - s) G / (Sg D_s D_a),
+//   w = -b/(D_s^2 R_s) + b/(D_a^2 R_a) = -b (a - s) (D_a^2 (a + s) + R_s G^2) / (Sg (D_s D_a)^2 R_s R_a),
+// every term positive, and one reciprocal, 1/(Sg D_s D_a), serves m, w and 1/(D_s D_a).
+// Subtracting two cored terms instead loses about log2(r/a) bits far from the member, where
+// both terms are ~ b/r and their difference ~ b (a - s)/r^2.  bd = b (a - s) and apls = a + s
+// are supplied by the caller.  Sg D_s D_a ~ 2 r^3 must stay finite: FP32 callers keep
+// r^2 < 1e25.  w' (third derivatives only) is the difference of the per-core derivatives
+// b u^2 is^2 (u + is/2), u = 1/D, is = 1/R.
 template <bool D3, class T>
-__device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T das, T da2, T r2, T& m, T& w, T& wp) {
+__device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T bd, T apls, T r2, T& m, T& w, T& wp) {
   T Ss = s2 + r2, Sa = a2 + r2;
   T is = frsq(Ss), ia = frsq(Sa);
   T Rs = Ss * is, Ra = Sa * ia;
   T Ds = Rs + s, Da = Ra + a;
-  T dR = da2 * frcp(Ra + Rs);
-  T dD = das + dR;
-  T iP = frcp(Ds * Da);
-  T bi = b * iP;
-  m = bi * dD;
-  T nw = fma(Da * Da, dR, Rs * dD * (Da + Ds));
-  w = -(bi * iP) * nw * (is * ia);
+  T Sg = Rs + Ra, G = Sg + apls;
+  T Z = frcp(Sg * (Ds * Da));
+  T eZ = bd * Z;
+  m = eZ * G;
+  T iP = Sg * Z;
+  T num = fma(Da * apls, Da, Rs * G * G);
+  w = -(eZ * iP) * (is * ia) * num;
   if (D3) {
     T us = Da * iP, ua = Ds * iP;
     T ps = us * us * is * is * fma((T)0.5, is, us);
@@ -132,10 +135,10 @@ __device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T das, T da2, 
   }
 }
 template <bool D3, class T>
-__device__ __forceinline__ void cpje(T dx, T dy, T b, T s, T a, T s2, T a2, T das, T da2, Term<T>& t) {
+__device__ __forceinline__ void cpje(T dx, T dy, T b, T s, T a, T s2, T a2, T bd, T apls, Term<T>& t) {
   T r2 = fma(dx, dx, dy * dy);
   T m, w, p = 0;
-  pje_mw<D3>(b, s, a, s2, a2, das, da2, r2, m, w, p);
+  pje_mw<D3>(b, s, a, s2, a2, bd, apls, r2, m, w, p);
   radial<D3>(dx, dy, m, w, p, t);
 }
 template <bool D3, class T>
@@ -460,7 +463,7 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
       else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, false, t);
       break;
     case T_PJE:
-      if (r.q >= 1.0) cpje<D3>(dx, dy, r.b, r.s, r.a, r.s * r.s, r.a * r.a, r.a - r.s, (r.a - r.s) * (r.a + r.s), t);
+      if (r.q >= 1.0) cpje<D3>(dx, dy, r.b, r.s, r.a, r.s * r.s, r.a * r.a, r.b * (r.a - r.s), r.a + r.s, t);
       else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t);
       break;
     case T_NFW: nfw_circ<D3>(dx, dy, r.b, r.s, t); break;

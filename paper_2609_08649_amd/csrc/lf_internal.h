@@ -57,15 +57,15 @@ struct MulRec {
 static constexpr double NEAR_K = 3.0;
 
 // Pre-scaled member record for one sample.  The FP32 flavour keeps the centre as an FP32
-// pair (as in MemCat32).  das = a - s and da2 = a^2 - s^2 are formed in FP64 before rounding
+// pair (as in MemCat32).  bd = b (a - s) and apls = a + s are formed in FP64 before rounding
 // (they feed the cancellation-free dPIE form); rn2 is the squared near-field radius.
 struct MemRec32 {
   float xh, xl, yh, yl;
-  float b, s, a, s2, a2, das, da2, rn2;   // the circular segments read these 12 words only
+  float b, s, a, s2, a2, bd, apls, rn2;   // the circular segments read these 12 words only
   float c, sn, q2, e, bqe, pad0, pad1, pad2;
 };
 struct MemRec64 {
-  double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, das, da2;
+  double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, bd, apls;
 };
 
 struct SegOff {          // member index range of each segment: [off[k], off[k+1])

@@ -99,11 +99,11 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
       double b = bm * c.fb, sc = sm * c.fs, a = am * c.fa;
       double q2 = c.q * c.q, e = sqrt(fmax(0.0, 1.0 - q2));
       double bqe = e > 0 ? b * c.q / e : 0.0;
-      const double das = a - sc, da2 = das * (a + sc);
+      const double bd = b * (a - sc), apls = a + sc;
       if (m64) {
         MemRec64 r;
         r.x = c.x; r.y = c.y; r.b = b; r.s = sc; r.a = a; r.s2 = sc * sc; r.a2 = a * a;
-        r.c = c.c; r.sn = c.sn; r.q2 = q2; r.e = e; r.bqe = bqe; r.das = das; r.da2 = da2;
+        r.c = c.c; r.sn = c.sn; r.q2 = q2; r.e = e; r.bqe = bqe; r.bd = bd; r.apls = apls;
         m64[(size_t)s * m.n_mem + i] = r;
       }
       if (m32) {
@@ -113,7 +113,7 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
         r.b = (float)b; r.s = (float)sc; r.a = (float)a;
         r.s2 = (float)(sc * sc); r.a2 = (float)(a * a);
         r.c = (float)c.c; r.sn = (float)c.sn; r.q2 = (float)q2; r.e = (float)e; r.bqe = (float)bqe;
-        r.das = (float)das; r.da2 = (float)da2;
+        r.bd = (float)bd; r.apls = (float)apls;
         const double rn = NEAR_K * b / c.q;
         r.rn2 = (float)fmax(rn * rn, 1e-12);
         r.pad0 = r.pad1 = r.pad2 = 0.f;

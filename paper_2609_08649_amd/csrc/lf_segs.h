@@ -40,7 +40,7 @@ __device__ __forceinline__ bool seg_term(const R& r, T dx, T dy, const Quad& qd,
       if (r.s == 0.0 && r2 < 1e-24) return false;
     }
     T m, w, p = 0;
-    if constexpr (SEG == SEG_CPJE) pje_mw<D3>(r.b, r.s, r.a, r.s2, r.a2, r.das, r.da2, r2, m, w, p);
+    if constexpr (SEG == SEG_CPJE) pje_mw<D3>(r.b, r.s, r.a, r.s2, r.a2, r.bd, r.apls, r2, m, w, p);
     else cored_mw<D3>(r.b, r.s, r.s2, r2, m, w, p);
     radial<D3>(dx, dy, m, w, p, t);
   } else if constexpr (SEG == SEG_EPJE || SEG == SEG_ESIE) {
@@ -64,24 +64,27 @@ __device__ __forceinline__ bool seg_term(const R& r, T dx, T dy, const Quad& qd,
 
 // FP32 run sums of the circular segments.  The Hessian is kept as its isotropic part
 // sum(m) and the anisotropic part sum(w x_i x_j), so every term enters through one FMA:
-// psi_ij = sum(m) delta_ij + sum(w x_i x_j); alpha_i = sum(m x_i).
+// psi_ij = sum(m) delta_ij + sum(w x_i x_j); alpha_i = sum(m x_i).  sum(w y^2) is taken as
+// sum(w r^2) - sum(w x^2) when a run is flushed (in FP64).  m is the mean convergence inside r
+// and w r^2 = 2 (kappa - m), so 0 <= kappa <= m (decreasing profiles) gives |w| r^2 <= 2 m: the
+// rounding of sum(w r^2) stays of the order of that of sum(m).
 struct Run32 {
-  float ax, ay, m, h11, h12, h22, t111, t112, t122, t222;
+  float ax, ay, m, h11, h12, wr2, t111, t112, t122, t222;
 };
 template <bool D3>
 __device__ __forceinline__ void run_zero(Run32& s) {
-  s.ax = s.ay = s.m = s.h11 = s.h12 = s.h22 = 0.f;
+  s.ax = s.ay = s.m = s.h11 = s.h12 = s.wr2 = 0.f;
   if (D3) s.t111 = s.t112 = s.t122 = s.t222 = 0.f;
 }
 template <bool D3>
-__device__ __forceinline__ void run_add(float dx, float dy, float m, float w, float wp, Run32& s) {
+__device__ __forceinline__ void run_add(float dx, float dy, float r2, float m, float w, float wp, Run32& s) {
   s.ax = fmaf(m, dx, s.ax);
   s.ay = fmaf(m, dy, s.ay);
   s.m += m;
-  float wx = w * dx, wy = w * dy;
+  float wx = w * dx;
   s.h11 = fmaf(wx, dx, s.h11);
   s.h12 = fmaf(wx, dy, s.h12);
-  s.h22 = fmaf(wy, dy, s.h22);
+  s.wr2 = fmaf(w, r2, s.wr2);
   if (D3) {
     float q = 2.f * wp;
     float qx2 = q * dx * dx, qy2 = q * dy * dy;
@@ -95,7 +98,8 @@ template <bool D3>
 __device__ __forceinline__ void run_flush(const Run32& s, Acc& a) {
   const double m = (double)s.m;
   a.ax += (double)s.ax; a.ay += (double)s.ay;
-  a.h11 += m + (double)s.h11; a.h12 += (double)s.h12; a.h22 += m + (double)s.h22;
+  const double h11 = (double)s.h11;
+  a.h11 += m + h11; a.h12 += (double)s.h12; a.h22 += m + ((double)s.wr2 - h11);
   if (D3) { a.t111 += (double)s.t111; a.t112 += (double)s.t112; a.t122 += (double)s.t122; a.t222 += (double)s.t222; }
 }
 
@@ -103,14 +107,16 @@ __device__ __forceinline__ void run_flush(const Run32& s, Acc& a) {
 template <int SEG, bool D3, class R>
 __device__ __forceinline__ void circ_mw(const R& r, float r2, float& m, float& w, float& wp) {
   wp = 0.f;
-  if constexpr (SEG == SEG_CPJE) pje_mw<D3>(r.b, r.s, r.a, r.s2, r.a2, r.das, r.da2, r2, m, w, wp);
+  if constexpr (SEG == SEG_CPJE) pje_mw<D3>(r.b, r.s, r.a, r.s2, r.a2, r.bd, r.apls, r2, m, w, wp);
   else cored_mw<D3>(r.b, r.s, r.s2, r2, m, w, wp);
 }
 
 // Squared radius at which the FP32 term of a near-field lane is evaluated instead of its own:
 // every circular term there is below 1e-14 (and finite), so the lane's FP32 run sum is
-// unaffected while its exact term is added from the FP64 record.
-static constexpr float FAR_R2 = 1e30f;
+// unaffected while its exact term is added from the FP64 record.  A dPIE term falls off as
+// 1/r^2 and its closed form needs r^2 < 1e25; a cored isothermal term falls off as 1/r.
+template <int SEG>
+static constexpr float FAR_R2 = SEG == SEG_CPJE ? 1e24f : 1e30f;
 
 // near64: the FP64 records of the same members (FP32 path: near-field terms); unused for
 // FP64 records.
@@ -139,8 +145,8 @@ __device__ __forceinline__ void seg_loop(const R* __restrict__ rec, const MemRec
         float r2 = fmaf(dx, dx, dy * dy);
         const bool nr = r2 < r.rn2;
         float m, w, wp;
-        circ_mw<SEG, D3>(r, nr ? FAR_R2 : r2, m, w, wp);
-        run_add<D3>(dx, dy, m, w, wp, ps);
+        circ_mw<SEG, D3>(r, nr ? FAR_R2<SEG> : r2, m, w, wp);
+        run_add<D3>(dx, dy, r2, m, w, wp, ps);
         return nr;
       };
       for (int h0 = lo; h0 < hi; h0 += LF_CHUNK) {

@@ -22,7 +22,7 @@ __device__ void member64_term(const Plane64& P, int m, double x, double y, const
   bool sing = (r2 < 1e-24) && (r.s == 0.0 || sg == SEG_POINT || sg == SEG_NFW || sg == SEG_ENFW);
   if (sing) { acc.flags |= FL_SINGULAR; return; }
   switch (sg) {
-    case SEG_CPJE: cpje<D3>(dx, dy, r.b, r.s, r.a, r.s2, r.a2, r.das, r.da2, t); break;
+    case SEG_CPJE: cpje<D3>(dx, dy, r.b, r.s, r.a, r.s2, r.a2, r.bd, r.apls, t); break;
     case SEG_EPJE: epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t); break;
     case SEG_CSIE: csie<D3>(dx, dy, r.b, r.s, r.s2, t); break;
     case SEG_ESIE: epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, false, t); break;
