@@ -70,7 +70,8 @@ def recorded_traffic():
 def summarize_profiles(kind, dirs):
     """Text summaries of rocprofv3 output (no GPU needed).  kind 'stats': the kernel statistics
     CSV of --kernel-trace --stats; kind 'pmc': two --pmc runs (FETCH_SIZE dir, WRITE_SIZE dir)
-    of 'bench.py --copy-probe', calibrated on the copy of COPY_PROBE_BYTES."""
+    of 'bench.py --copy-probe', calibrated on the copy of COPY_PROBE_BYTES; kind 'insts': --pmc
+    runs of SQ instruction counters (each with SQ_WAVES)."""
     import csv
     import glob
     if kind == "stats":
@@ -80,6 +81,27 @@ def summarize_profiles(kind, dirs):
         for r in rows:
             print("%-60s %7s %12.2f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["AverageNs"]) / 1e3,
                                                    float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+        return
+    if kind == "insts":
+        # SQ instruction counters of the lean maps kernel, per dispatch and per wave x member
+        sums = {}
+        for d in dirs:
+            path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+            per = {}
+            for r in csv.DictReader(open(path)):
+                if "lf::k_maps<true, false, 1>" in r["Kernel_Name"]:
+                    key = (r["Counter_Name"], r["Dispatch_Id"])
+                    per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+            for (ctr, _), v in per.items():
+                sums.setdefault(ctr, []).append(v)
+        from paper_2609_08649_amd import workloads as W
+        n_mem = len(W.config2()["model"]["members"]["x"])
+        waves = sum(sums["SQ_WAVES"]) / len(sums["SQ_WAVES"])
+        print("lean maps kernel, %d dispatches, %.0f waves each, %d members per point" %
+              (len(sums["SQ_WAVES"]), waves, n_mem))
+        for ctr, v in sorted(sums.items()):
+            avg = sum(v) / len(v)
+            print("%-26s %16.0f per dispatch %10.2f per wave x member" % (ctr, avg, avg / waves / n_mem))
         return
     vals = {}
     for d, ctr in zip(dirs, ("FETCH_SIZE", "WRITE_SIZE")):
@@ -121,7 +143,8 @@ def parse():
                     help="after the run, copy %d MiB device to device three times (counter calibration)"
                     % (COPY_PROBE_BYTES >> 20))
     ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
-                    help="print a summary of rocprofv3 output: 'stats DIR' or 'pmc FETCH_DIR WRITE_DIR'")
+                    help="print a summary of rocprofv3 output: 'stats DIR', 'pmc FETCH_DIR WRITE_DIR' or "
+                         "'insts DIR...' (SQ instruction counters)")
     return ap.parse_args()
 
 
