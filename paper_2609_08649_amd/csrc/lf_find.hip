@@ -192,51 +192,100 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
     }
   }
   const float rel = 4.f * (float)(np + 3) * 5.9604645e-8f;   // 4 (np + 3) 2^-24
+  // Coarse test first: every mapped corner lies within r_p = h/2 + sum_p |w_p| da_p (in each
+  // coordinate) of the mapped centre c - sum_p w_p abar_p, where abar_p is the corners' mean
+  // deflection and da_p their largest deviation from it.  The source is kept for the bounding
+  // box test below unless it is farther than that plus four times the box's margin from the
+  // mapped centre: one margin is the box's own, and the rounding of the centre, the means, the
+  // deviations, the radius and the corners adds at most (2 + 7 np) 2^-23 R, within the other
+  // three.  So the coarse test keeps a superset of what the box keeps.
+  const float cxf = 0.25f * ((txf[0] + txf[1]) + (txf[2] + txf[3]));
+  const float cyf = 0.25f * ((tyf[0] + tyf[1]) + (tyf[2] + tyf[3]));
+  const float r0 = 0.5f * fmaxf(fabsf(txf[1] - txf[0]), fabsf(tyf[2] - tyf[0]));
+  float abx[MP], aby[MP], da[MP];
+  for (int p = 0; p < np; ++p) {
+    abx[p] = 0.25f * ((axf[p][0] + axf[p][1]) + (axf[p][2] + axf[p][3]));
+    aby[p] = 0.25f * ((ayf[p][0] + ayf[p][1]) + (ayf[p][2] + ayf[p][3]));
+    da[p] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) da[p] = fmaxf(da[p], fmaxf(fabsf(axf[p][k] - abx[p]), fabsf(ayf[p][k] - aby[p])));
+  }
   const int lane = threadIdx.x & 63;
-  for (int s = 0; s < F.n_src; ++s) {
-    const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
-    {
-      const float sxf = (float)sx, syf = (float)sy;
-      float bxf[4], byf[4];
-      float R = tmax + fmaxf(fabsf(sxf), fabsf(syf));
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { bxf[k] = txf[k]; byf[k] = tyf[k]; }
-      for (int p = 0; p < np; ++p) {
-        const float wf = (float)F.w[s * np + p];
-        R = fmaf(fabsf(wf), amax[p], R);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { bxf[k] = fmaf(-wf, axf[p][k], bxf[k]); byf[k] = fmaf(-wf, ayf[p][k], byf[k]); }
+  // The sources are staged in LDS, SCH at a time: read from global memory in the loop, every
+  // source would cost each wave a round trip to L2 (the candidate stores keep the compiler
+  // from using the scalar cache).
+  constexpr int SCH = 256;
+  __shared__ double sh_b[2 * SCH], sh_w[SCH * MP];
+  for (int s0 = 0; s0 < F.n_src; s0 += SCH) {
+    const int ns = min(SCH, F.n_src - s0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      sh_b[2 * q] = F.beta[2 * (s0 + q)];
+      sh_b[2 * q + 1] = F.beta[2 * (s0 + q) + 1];
+      for (int p = 0; p < np; ++p) sh_w[q * np + p] = F.w[(s0 + q) * np + p];
+    }
+    __syncthreads();
+    for (int sl = 0; sl < ns; ++sl) {
+      const int s = s0 + sl;
+      const double* ws = sh_w + sl * np;
+      const double sx = sh_b[2 * sl], sy = sh_b[2 * sl + 1];
+      {
+        const float sxf = (float)sx, syf = (float)sy;
+        float R = tmax + fmaxf(fabsf(sxf), fabsf(syf));
+        float bcx = cxf, bcy = cyf, rad = r0;
+        for (int p = 0; p < np; ++p) {
+          const float wf = (float)ws[p];
+          R = fmaf(fabsf(wf), amax[p], R);
+          bcx = fmaf(-wf, abx[p], bcx);
+          bcy = fmaf(-wf, aby[p], bcy);
+          rad = fmaf(fabsf(wf), da[p], rad);
+        }
+        const float lim = rad + 4.f * ((float)F.eps + rel * R);
+        if (!__any(valid && fabsf(sxf - bcx) <= lim && fabsf(syf - bcy) <= lim)) continue;
       }
-      const float m = (float)F.eps + rel * R;
-      const bool in = valid && sxf >= fminf(fminf(bxf[0], bxf[1]), fminf(bxf[2], bxf[3])) - m &&
-                      sxf <= fmaxf(fmaxf(bxf[0], bxf[1]), fmaxf(bxf[2], bxf[3])) + m &&
-                      syf >= fminf(fminf(byf[0], byf[1]), fminf(byf[2], byf[3])) - m &&
-                      syf <= fmaxf(fmaxf(byf[0], byf[1]), fmaxf(byf[2], byf[3])) + m;
-      if (!__any(in)) continue;
-    }
-    double bx[4], by[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { bx[k] = tx[k]; by[k] = ty[k]; }
-    for (int p = 0; p < np; ++p) {
-      double w = F.w[s * np + p];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) { bx[k] = fma(-w, ax[p][k], bx[k]); by[k] = fma(-w, ay[p][k], by[k]); }
-    }
-    // corners: 0 = v(i,j), 1 = v(i+1,j), 2 = v(i,j+1), 3 = v(i+1,j+1)
-    double T0[6] = {bx[0], by[0], bx[1], by[1], bx[3], by[3]};
-    double T1[6] = {bx[0], by[0], bx[3], by[3], bx[2], by[2]};
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
-      unsigned long long mask = __ballot(hit);
-      if (mask) {
-        int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (hit) {
-          int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-          if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(2 * cc + t);
+      {
+        const float sxf = (float)sx, syf = (float)sy;
+        float bxf[4], byf[4];
+        float R = tmax + fmaxf(fabsf(sxf), fabsf(syf));
+  #pragma unroll
+        for (int k = 0; k < 4; ++k) { bxf[k] = txf[k]; byf[k] = tyf[k]; }
+        for (int p = 0; p < np; ++p) {
+          const float wf = (float)ws[p];
+          R = fmaf(fabsf(wf), amax[p], R);
+  #pragma unroll
+          for (int k = 0; k < 4; ++k) { bxf[k] = fmaf(-wf, axf[p][k], bxf[k]); byf[k] = fmaf(-wf, ayf[p][k], byf[k]); }
+        }
+        const float m = (float)F.eps + rel * R;
+        const bool in = valid && sxf >= fminf(fminf(bxf[0], bxf[1]), fminf(bxf[2], bxf[3])) - m &&
+                        sxf <= fmaxf(fmaxf(bxf[0], bxf[1]), fmaxf(bxf[2], bxf[3])) + m &&
+                        syf >= fminf(fminf(byf[0], byf[1]), fminf(byf[2], byf[3])) - m &&
+                        syf <= fmaxf(fmaxf(byf[0], byf[1]), fmaxf(byf[2], byf[3])) + m;
+        if (!__any(in)) continue;
+      }
+      double bx[4], by[4];
+  #pragma unroll
+      for (int k = 0; k < 4; ++k) { bx[k] = tx[k]; by[k] = ty[k]; }
+      for (int p = 0; p < np; ++p) {
+        double w = ws[p];
+  #pragma unroll
+        for (int k = 0; k < 4; ++k) { bx[k] = fma(-w, ax[p][k], bx[k]); by[k] = fma(-w, ay[p][k], by[k]); }
+      }
+      // corners: 0 = v(i,j), 1 = v(i+1,j), 2 = v(i,j+1), 3 = v(i+1,j+1)
+      double T0[6] = {bx[0], by[0], bx[1], by[1], bx[3], by[3]};
+      double T1[6] = {bx[0], by[0], bx[3], by[3], bx[2], by[2]};
+  #pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
+        unsigned long long mask = __ballot(hit);
+        if (mask) {
+          int leader = __ffsll((long long)mask) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
+          base = __shfl(base, leader, 64);
+          if (hit) {
+            int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+            if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(2 * cc + t);
+          }
         }
       }
     }
