@@ -150,10 +150,12 @@ __device__ __forceinline__ bool near_tri(const double* B, double sx, double sy, 
   return o0 >= -eps * e0 && o1 >= -eps * e1 && o2 >= -eps * e2;
 }
 
-template <int NP>   // NP = 1: single plane (corners in registers); 0: up to LF_MAX_PLANES planes
+// NP = 1..4: that many planes, corners in registers; 0: any count up to LF_MAX_PLANES (the
+// corner arrays are then indexed at run time and live in scratch memory)
+template <int NP>
 __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
-  constexpr int MP = NP == 1 ? 1 : LF_MAX_PLANES;
-  const int np = NP == 1 ? 1 : F.n_planes;
+  constexpr int MP = NP > 0 ? NP : LF_MAX_PLANES;
+  const int np = NP > 0 ? NP : F.n_planes;
   const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
   const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
   const bool valid = c < ncell;
@@ -165,14 +167,8 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
   double tx[4], ty[4];
   tx[0] = tx[2] = F.x0 + (i + 0.5) * F.h; tx[1] = tx[3] = F.x0 + (i + 1.5) * F.h;
   ty[0] = ty[1] = F.y0 + (j + 0.5) * F.h; ty[2] = ty[3] = F.y0 + (j + 1.5) * F.h;
-  double ax[MP][4], ay[MP][4];
-  for (int p = 0; p < np; ++p)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      ax[p][k] = F.va[(size_t)(F.va_pstride * p) * P + v[k]];
-      ay[p][k] = F.va[(size_t)(F.va_pstride * p + 1) * P + v[k]];
-    }
-  // FP32 copies for the prefilter: a cell is tested in FP64 only when the source lies in the
+  // FP32 copies of the corner deflections for the prefilters (the FP64 values are read again
+  // in the rare case that a source passes them): a cell is tested in FP64 only when the source lies in the
   // FP32 bounding box of its four mapped corners widened by eps plus a bound on the FP32
   // rounding (inputs and FMAs, each <= 2^-24 of a magnitude <= R = |theta| + sum w |alpha| +
   // |beta_s|, at most np + 3 of them per coordinate, taken with a factor 4).
@@ -187,7 +183,8 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
     amax[p] = 0.f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      axf[p][k] = (float)ax[p][k]; ayf[p][k] = (float)ay[p][k];
+      axf[p][k] = (float)F.va[(size_t)(F.va_pstride * p) * P + v[k]];
+      ayf[p][k] = (float)F.va[(size_t)(F.va_pstride * p + 1) * P + v[k]];
       amax[p] = fmaxf(amax[p], fmaxf(fabsf(axf[p][k]), fabsf(ayf[p][k])));
     }
   }
@@ -247,12 +244,12 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
         const float sxf = (float)sx, syf = (float)sy;
         float bxf[4], byf[4];
         float R = tmax + fmaxf(fabsf(sxf), fabsf(syf));
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < 4; ++k) { bxf[k] = txf[k]; byf[k] = tyf[k]; }
         for (int p = 0; p < np; ++p) {
           const float wf = (float)ws[p];
           R = fmaf(fabsf(wf), amax[p], R);
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < 4; ++k) { bxf[k] = fmaf(-wf, axf[p][k], bxf[k]); byf[k] = fmaf(-wf, ayf[p][k], byf[k]); }
         }
         const float m = (float)F.eps + rel * R;
@@ -263,17 +260,19 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
         if (!__any(in)) continue;
       }
       double bx[4], by[4];
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < 4; ++k) { bx[k] = tx[k]; by[k] = ty[k]; }
       for (int p = 0; p < np; ++p) {
-        double w = ws[p];
-  #pragma unroll
-        for (int k = 0; k < 4; ++k) { bx[k] = fma(-w, ax[p][k], bx[k]); by[k] = fma(-w, ay[p][k], by[k]); }
+        const double w = ws[p];
+        const double* vx = F.va + (size_t)(F.va_pstride * p) * P;
+        const double* vy = F.va + (size_t)(F.va_pstride * p + 1) * P;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { bx[k] = fma(-w, vx[v[k]], bx[k]); by[k] = fma(-w, vy[v[k]], by[k]); }
       }
       // corners: 0 = v(i,j), 1 = v(i+1,j), 2 = v(i,j+1), 3 = v(i+1,j+1)
       double T0[6] = {bx[0], by[0], bx[1], by[1], bx[3], by[3]};
       double T1[6] = {bx[0], by[0], bx[3], by[3], bx[2], by[2]};
-  #pragma unroll
+#pragma unroll
       for (int t = 0; t < 2; ++t) {
         bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
         unsigned long long mask = __ballot(hit);
@@ -425,8 +424,14 @@ hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void
   long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, F.n_cand);
   mark(ctx, "find_cand", 0);
-  if (F.n_planes == 1) hipLaunchKernelGGL(k_find_cand<1>, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
-  else hipLaunchKernelGGL(k_find_cand<0>, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
+  const dim3 cgrid((unsigned)((ncell + 255) / 256));
+  switch (F.n_planes) {
+    case 1: hipLaunchKernelGGL(k_find_cand<1>, cgrid, dim3(256), 0, st, F); break;
+    case 2: hipLaunchKernelGGL(k_find_cand<2>, cgrid, dim3(256), 0, st, F); break;
+    case 3: hipLaunchKernelGGL(k_find_cand<3>, cgrid, dim3(256), 0, st, F); break;
+    case 4: hipLaunchKernelGGL(k_find_cand<4>, cgrid, dim3(256), 0, st, F); break;
+    default: hipLaunchKernelGGL(k_find_cand<0>, cgrid, dim3(256), 0, st, F); break;
+  }
   mark(ctx, "find_cand", 1);
   hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
   mark(ctx, "find_polish", 0);
