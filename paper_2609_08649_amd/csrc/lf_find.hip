@@ -92,9 +92,13 @@ __device__ bool d_tri_contains(const double* B, double sx, double sy) {
   return true;
 }
 
+// MULTI = false compiles the single-plane case alone: the multi-plane recursion's per-plane
+// arrays are indexed at run time and would otherwise hold scratch memory and registers in
+// every kernel that calls this.
+template <bool MULTI>
 __device__ void lens_eval64(const LensDev& L, const double* w, double x, double y, double& bx, double& by,
                             double* Aout, int& flags) {
-  if (L.n_planes == 1) {
+  if (!MULTI || L.n_planes == 1) {
     Acc acc;
     plane_sum_wave<false>(L.pl[0], x, y, L.qd, acc);
     double a = w[0];
@@ -320,6 +324,7 @@ __global__ __launch_bounds__(1024) void k_find_sort(const FindArgs F) {
 // ---------------------------------------------------------------------------------------
 // 4. FP64 containment + Newton polish per candidate
 // ---------------------------------------------------------------------------------------
+template <bool MULTI>
 __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const LensDev L) {
   int n = min(*F.n_cand, F.cap);
   int k = blockIdx.x;            // one wave per candidate
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const Lens
   for (int q = 0; q < 3; ++q) {
     T[2 * q] = F.x0 + (vi[q] + 0.5) * F.h;
     T[2 * q + 1] = F.y0 + (vj[q] + 0.5) * F.h;
-    lens_eval64(L, w, T[2 * q], T[2 * q + 1], B[2 * q], B[2 * q + 1], A, fl);
+    lens_eval64<MULTI>(L, w, T[2 * q], T[2 * q + 1], B[2 * q], B[2 * q + 1], A, fl);
   }
   const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
   int status = 4;
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const Lens
     bool conv = false;
     for (int it = 0; it <= 30; ++it) {
       double ex, ey;
-      lens_eval64(L, w, tx, ty, ex, ey, A, fl);
+      lens_eval64<MULTI>(L, w, tx, ty, ex, ey, A, fl);
       double rx = sx - ex, ry = sy - ey;
       if (fabs(rx) < 1e-10 && fabs(ry) < 1e-10) { conv = true; break; }
       if (it == 30) break;
@@ -435,7 +440,8 @@ hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void
   mark(ctx, "find_cand", 1);
   hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
   mark(ctx, "find_polish", 0);
-  hipLaunchKernelGGL(k_find_polish, dim3(F.cap), dim3(64), 0, st, F, L);
+  if (F.n_planes == 1) hipLaunchKernelGGL(k_find_polish<false>, dim3(F.cap), dim3(64), 0, st, F, L);
+  else hipLaunchKernelGGL(k_find_polish<true>, dim3(F.cap), dim3(64), 0, st, F, L);
   mark(ctx, "find_polish", 1);
   hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
   return hipGetLastError();
@@ -561,6 +567,7 @@ __global__ __launch_bounds__(256) void k_ms_cand(const FindArgs F) {
 }
 
 // one wave per candidate: the intersection, then (polish) FP64 Newton as the triangle finder
+template <bool MULTI>
 __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev L, int polish) {
   const int n = min(*F.n_cand, F.cap);
   const int k = blockIdx.x;
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev
     const double tx0 = tx, ty0 = ty;
     bool conv = false;
     for (int it = 0; it <= 30; ++it) {
-      lens_eval64(L, w, tx, ty, ex, ey, A, fl);
+      lens_eval64<MULTI>(L, w, tx, ty, ex, ey, A, fl);
       const double rx = sx - ex, ry = sy - ey;
       if (fabs(rx) < 1e-10 && fabs(ry) < 1e-10) { conv = true; break; }
       if (it == 30) break;
@@ -601,7 +608,7 @@ __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev
     if (!conv) status = 1;
     else if (fabs(tx - tx0) > 2.0 * F.h || fabs(ty - ty0) > 2.0 * F.h) status = 2;
   } else {
-    lens_eval64(L, w, tx, ty, ex, ey, A, fl);
+    lens_eval64<MULTI>(L, w, tx, ty, ex, ey, A, fl);
   }
   if (threadIdx.x == 0) {
     F.c_status[k] = status;
@@ -620,7 +627,8 @@ hipError_t launch_find_ms(const FindArgs& F, const LensDev& L, int polish, hipSt
   mark(ctx, "find_ms_cand", 1);
   hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
   mark(ctx, "find_ms_point", 0);
-  hipLaunchKernelGGL(k_ms_point, dim3(F.cap), dim3(64), 0, st, F, L, polish);
+  if (F.n_planes == 1) hipLaunchKernelGGL(k_ms_point<false>, dim3(F.cap), dim3(64), 0, st, F, L, polish);
+  else hipLaunchKernelGGL(k_ms_point<true>, dim3(F.cap), dim3(64), 0, st, F, L, polish);
   mark(ctx, "find_ms_point", 1);
   hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
   return hipGetLastError();
