@@ -247,15 +247,18 @@ __device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& G
     Gp = gp;
     F = fma(G, z, 1.0);
   } else {
+    // one reciprocal square root y = 1/sqrt(|z|) gives w = sqrt(|z|) = |z| y, 1/w = y and
+    // 1/z = +-y^2
     const double iX2 = frcp(X2);
+    const double az = fabs(z), y = frsq(az);
+    const double w = fma(0.5 * y, fma(-az * y, az * y, az), az * y);   // |z| y, one Newton step
     if (z > 0) {
-      const double w = fsqrt(z), w1 = 1.0 + w;
-      F = 0.5 * log(w1 * w1 * iX2) * frcp(w);
+      const double w1 = 1.0 + w;
+      F = 0.5 * log(w1 * w1 * iX2) * y;
     } else {
-      const double w = fsqrt(-z);
-      F = atan(w) * frcp(w);
+      F = atan(w) * y;
     }
-    const double iz = frcp(z);
+    const double iz = z > 0 ? y * y : -(y * y);
     G = (F - 1.0) * iz;
     const double Fp = 0.5 * (iX2 - F) * iz;
     Gp = (Fp - G) * iz;
@@ -298,13 +301,13 @@ __device__ __forceinline__ void enfw_prime(double xp, double yp, double ks, doub
   for (int i = 0; i < qd.n; ++i) {
     double u = qd.u[i], wq = qd.w[i];
     double W = fma(-e2, u, 1.0);
-    double iW = frcp(W);
+    const double rW = frsq(W), iW = rW * rW;
     double X2 = u * fma(yy, iW, xx) * irs2;
     double F, G, Gp;
     nfw_G(X2, F, G, Gp);
     double kap = 2.0 * ks * G;
     double ukp = -2.0 * ks * Gp * irs2 * u;
-    double f0 = wq * frsq(W);
+    double f0 = wq * rW;
     double f1 = f0 * iW, f2 = f1 * iW;
     J0 = fma(f0, kap, J0); J1 = fma(f1, kap, J1);
     K0 = fma(f0, ukp, K0); K1 = fma(f1, ukp, K1); K2 = fma(f2, ukp, K2);
