@@ -194,8 +194,7 @@ def main():
         summarize_profiles(args.summarize[0], args.summarize[1:])
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (the design notes "
-              "describe how the work would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2609_08649_amd import lensfield as lf
