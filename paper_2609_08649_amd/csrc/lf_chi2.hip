@@ -478,7 +478,7 @@ __global__ __launch_bounds__(64) void k_chi2_src(const Chi2Args A, int obs) { ch
 // images no longer hold whole waves for 20 steps, and many slow ones still fill the waves
 // (64 / NEWTON_G images per wave).  Which round finishes an image, and the group's summation
 // order, depend only on that image, so results do not depend on wave mates, tiles or batches.
-static constexpr int NEWTON_MAX = 20, NEWTON_R1 = 8, NEWTON_G = 8;
+static constexpr int NEWTON_MAX = 20, NEWTON_R1 = 5, NEWTON_G = 16;
 
 struct NewtonImg {
   int s, i;
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(64) void k_batch_src(const BatchArgs B) {
   chi2_src_sample(B.items[B.samp_item[gs]], B.samp_local[gs], false);
 }
 
-__global__ __launch_bounds__(256) void k_batch_newton(const BatchArgs B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_newton(const BatchArgs B) {
   for (;;) {
     int t = next_tile(&B.counter[1]);
     if (t >= B.n_tiles) break;
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(256) void k_batch_newton(const BatchArgs B) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_batch_newton2(const BatchArgs B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_newton2(const BatchArgs B) {
   for (int i = 0; i < B.n_items; ++i) newton_round2(B.items[i]);
 }
 
