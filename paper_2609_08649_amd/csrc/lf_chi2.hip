@@ -555,7 +555,7 @@ __device__ void chi2_newton_lane(const Chi2Args& A, long long g, bool active) {
   }
   if (active && conv) newton_finish(A, g, N, true, tx, ty, det_last);
 }
-__global__ __launch_bounds__(256) void k_chi2_newton(const Chi2Args A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_chi2_newton(const Chi2Args A) {
   long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   const bool active = t < (long long)A.S * A.n_img;
   chi2_newton_lane(A, active ? lane_slot(A, t) : 0, active);
