@@ -294,7 +294,7 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
 }
 // one lane per crossing: lanes of a wave hold neighbouring edges of a row, iterate alike and
 // read every halo record at the same time (scalar loads)
-__global__ __launch_bounds__(NT) void k_sing_refine(const SingArgs A) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sing_refine(const SingArgs A) {
   const int n = blockIdx.x * NT + threadIdx.x;
   if (n < n_cross(A)) refine_crossing<true>(A, n);
 }
