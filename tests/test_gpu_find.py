@@ -59,6 +59,20 @@ def test_find_config1(ctx, lf, orc, prec):
     compare(g, o, 1e-9 if prec == "fp64" else 1e-4)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_find_many_sources(ctx, lf, orc, prec):
+    """More sources than the candidate pass stages in LDS at a time (256): 60 copies of the five
+    config-1 sources each give the oracle's images of the five."""
+    cfg = W.config1()
+    beta, a = lensdata.config1_sources()
+    o = orc.find_images(orc.expand(cfg["model"]), cfg["grid"], beta, np.full(5, a))
+    reps = 60
+    g = _run(ctx, lf, cfg["model"], None, np.tile(beta, (reps, 1)), a, cfg["grid"], prec)
+    assert g["count"].shape[0] == 5 * reps
+    for r in range(reps):
+        compare({k: v[5 * r:5 * r + 5] for k, v in g.items()}, o, 1e-9 if prec == "fp64" else 1e-4)
+
+
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_find_cluster_full_grid(ctx, lf, orc, prec):
     """60 sources at their own redshifts on the 2048^2 grid over 200" (the benchmark's launch)."""

@@ -96,3 +96,38 @@ def test_find_images_multiplane(ctx, lf, orc, prec):
         assert np.max(np.abs(g["theta"][s, :n] - o["theta"][s, :n]), initial=0) <= (1e-9 if prec == "fp64" else 1e-4)
     for p in pl:
         p.release()
+
+
+@pytest.mark.parametrize("n_planes", [1, 2, 5])
+def test_find_images_multiplane_plane_counts(ctx, lf, orc, n_planes):
+    """The candidate pass is compiled per plane count up to 4 and in a generic form beyond:
+    1, 2 and 5 planes (the last adds copies of two planes at z = 0.9 and 1.4, in front of every
+    source) against the oracle, FP64.  Both polishes stop once |d beta| < 1e-10", which fixes an
+    image only to |A^-1| 1e-10" <= 2 |mu| 1e-10" (|A| <= 2 here): positions are compared within
+    twice that plus 1e-9"."""
+    import torch
+    cfg = W.config4(seed=9, grid_n=64, members=(30, 10, 8))
+    P, Z = list(cfg["planes"]), [float(z) for z in cfg["z_planes"]]
+    if n_planes == 5:
+        P = [P[0], P[1], dict(P[1], z_d=0.9), P[2], dict(P[2], z_d=1.4)]
+        Z = [Z[0], Z[1], 0.9, Z[2], 1.4]
+    else:
+        P, Z = P[:n_planes], Z[:n_planes]
+    tabs = [orc.expand(p) for p in P]
+    grid = {"x0": -50.0, "y0": -50.0, "h": 0.390625, "nx": 256, "ny": 256}
+    beta = cfg["src_cand"][:24] * 0.15
+    zs = cfg["zs_cand"][:24]
+    assert zs.min() > max(Z)
+    o = orc.find_images_mp(tabs, Z, grid, beta, zs)
+    pl = [ctx.upload_model(p) for p in P]
+    g = ctx.find_images_mp(pl, Z, torch.as_tensor(beta, device="cuda"), zs, grid, 16, lf.LF_PREC_FP64)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    assert np.array_equal(g["count"], o["count"]), (g["count"], o["count"])
+    assert o["count"].max() >= 2
+    for s in range(len(zs)):
+        n = o["count"][s]
+        tol = 1e-9 + 4e-10 * np.abs(o["mu"][s, :n])
+        assert np.all(np.abs(g["theta"][s, :n] - o["theta"][s, :n]).max(axis=1) <= tol), s
+    for p in pl:
+        p.release()
