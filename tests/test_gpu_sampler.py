@@ -177,6 +177,26 @@ def test_nelder_mead_fp64_identical_to_oracle(ctx, lf, seed):
     assert np.all(of[:, 0] <= smp.lens_chi2(model, cons, lo, hi)(S0.reshape(-1, truth.size)).reshape(12, -1).min(1))
 
 
+@pytest.mark.parametrize("n_main", [0, 1, 7])
+def test_nelder_mead_team_sizes(ctx, lf, n_main):
+    """A run is handled by a team of lanes, one per parameter (the power of two >= D, idle lanes
+    beyond D): D = 2, 7 and 37 (teams of 2, 8 and 64 lanes) against the oracle, FP64; the
+    constraints of the small case serve any model (chi^2 is defined for any positions)."""
+    _, _, cons = lensdata.small_constraints(41)
+    model, truth = W.tiny_model(43, n_main=n_main, n_mem=25, types=[2, 3], free_params=True)
+    assert truth.size == 5 * n_main + 2
+    lo, hi = _box(truth)
+    S0 = _simplices(truth, 6, 7 + n_main)
+    n = 40
+    ox, of = smp.nelder_mead(smp.lens_chi2(model, cons, lo, hi), S0, n)
+    gx, gf, nev = _run_nm(ctx, lf, model, cons, S0, lo, hi, n, lf.LF_PREC_FP64)
+    assert np.array_equal(gx, ox)
+    fin = np.isfinite(of)
+    assert np.array_equal(np.isfinite(gf), fin)
+    assert np.allclose(gf[fin], of[fin], rtol=1e-9, atol=1e-9)
+    assert np.all(nev == truth.size + 1 + n)
+
+
 def test_cluster_full_size_fp64(ctx, lf):
     """The cluster model (14 parameters, 150 images, 302 halos): 1024 walkers for 2 steps and
     128 Nelder-Mead runs for 12 rounds, FP64, against the oracle."""
