@@ -384,7 +384,8 @@ lf_status lf_aies_run(lf_ctx* ctx, const lf_model* m, const lf_cons* c, int32_t 
  * contraction when f_{D-1} <= f_r < f_D (kept if <= f_r), inside when f_r >= f_D (kept if <
  * f_D); otherwise shrink towards the best vertex.  On return the simplices are sorted by f
  * (fvals [R][D+1], ties in insertion order) and n_evals [R] (or NULL) counts evaluations.
- * Errors: LF_E_INVALID_ARG (no free parameter, R < 1, bad mode/precision), those of
+ * Errors: LF_E_INVALID_ARG (no free parameter, R < 1, bad mode/precision), LF_E_UNSUPPORTED
+ * (more than 64 free parameters: a run is handled by one wave, a lane per parameter), those of
  * lf_chi2_terms. */
 lf_status lf_nelder_mead_run(lf_ctx* ctx, const lf_model* m, const lf_cons* c, int32_t mode, lf_prec prec,
                              int32_t R, double* simplex, double* fvals, const double* lo, const double* hi,

@@ -250,5 +250,15 @@ def test_errors(ctx, lf):
         ctx.nelder_mead(mf, c, torch.zeros((2, 2, 1), dtype=torch.float64, device="cuda"), lo[:1], hi[:1], 1)
     assert e.value.status == lf.LF_E_INVALID_ARG
     mf.release()
+    wide, wt = W.tiny_model(3, n_main=13, n_mem=3, types=[2], free_params=True)   # 67 parameters
+    mw = ctx.upload_model(wide)
+    D = wt.size
+    assert D > 64
+    with pytest.raises(lf.LfError) as e:
+        ctx.nelder_mead(mw, c, torch.zeros((1, D + 1, D), dtype=torch.float64, device="cuda"),
+                        torch.full((D,), -1e9, dtype=torch.float64, device="cuda"),
+                        torch.full((D,), 1e9, dtype=torch.float64, device="cuda"), 1)
+    assert e.value.status == lf.LF_E_UNSUPPORTED
+    mw.release()
     c.release()
     m.release()
