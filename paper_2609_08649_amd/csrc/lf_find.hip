@@ -460,16 +460,28 @@ namespace {
 struct MsCell {
   double F1[4], F2[4];
 };
-__device__ void ms_cell_values(const FindArgs& F, int s, int i, int j, MsCell& c) {
+// The corners of cell (i, j) in the order of the cell values: positions and deflections.
+struct MsCorners {
+  double tx[4], ty[4], ax[4], ay[4];
+};
+__device__ void ms_corners(const FindArgs& F, int i, int j, MsCorners& q) {
 #pragma clang fp contract(off)
   const long long P = (long long)F.nx * F.ny;
-  const double a = F.w[s], sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
   const int ci[4] = {i, i + 1, i + 1, i}, cj[4] = {j, j, j + 1, j + 1};
   for (int k = 0; k < 4; ++k) {
     const long long v = (long long)cj[k] * F.nx + ci[k];
-    const double tx = F.x0 + (ci[k] + 0.5) * F.h, ty = F.y0 + (cj[k] + 0.5) * F.h;
-    c.F1[k] = sx - (tx - a * F.va[v]);
-    c.F2[k] = sy - (ty - a * F.va[P + v]);
+    q.tx[k] = F.x0 + (ci[k] + 0.5) * F.h;
+    q.ty[k] = F.y0 + (cj[k] + 0.5) * F.h;
+    q.ax[k] = F.va[v];
+    q.ay[k] = F.va[P + v];
+  }
+}
+// F = beta_s - (theta - a alpha) at the corners, for source (sx, sy) at distance ratio a
+__device__ void ms_cell_values(const MsCorners& q, double sx, double sy, double a, MsCell& c) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 4; ++k) {
+    c.F1[k] = sx - (q.tx[k] - a * q.ax[k]);
+    c.F2[k] = sy - (q.ty[k] - a * q.ay[k]);
   }
 }
 // segments of one component in cell coordinates: seg[k] = (x0, y0, x1, y1); returns 0, 1 or 2
@@ -533,34 +545,50 @@ __global__ __launch_bounds__(256) void k_ms_cand(const FindArgs F) {
   const long long cc = valid ? c : 0;
   const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
   const int lane = threadIdx.x & 63;
-  for (int s = 0; s < F.n_src; ++s) {
-    MsCell v;
-    ms_cell_values(F, s, i, j, v);
-    int pairs = 0;          // bit p * 2 + q: f1 segment p crosses f2 segment q
-    if (valid) {
-      double S1[2][4], S2[2][4];
-      const int n1 = ms_segments(v.F1, S1);
-      if (n1) {
-        const int n2 = ms_segments(v.F2, S2);
-        for (int p = 0; p < n1; ++p)
-          for (int q = 0; q < n2; ++q) {
-            double xi, eta;
-            if (ms_cross(S1, p, S2, q, xi, eta)) pairs |= 1 << (p * 2 + q);
-          }
-      }
+  MsCorners cq;
+  ms_corners(F, i, j, cq);
+  // sources staged in LDS, SCH at a time (see k_find_cand)
+  constexpr int SCH = 256;
+  __shared__ double sh_s[3 * SCH];
+  for (int s0 = 0; s0 < F.n_src; s0 += SCH) {
+    const int ns = min(SCH, F.n_src - s0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      sh_s[3 * q] = F.beta[2 * (s0 + q)];
+      sh_s[3 * q + 1] = F.beta[2 * (s0 + q) + 1];
+      sh_s[3 * q + 2] = F.w[s0 + q];
     }
-    if (!__any(pairs != 0)) continue;
-    for (int k = 0; k < 4; ++k) {
-      const bool hit = (pairs >> k) & 1;
-      const unsigned long long mask = __ballot(hit);
-      if (!mask) continue;
-      const int leader = __ffsll((long long)mask) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
-      base = __shfl(base, leader, 64);
-      if (hit) {
-        const int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-        if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(cc * 4 + k);
+    __syncthreads();
+    for (int sl = 0; sl < ns; ++sl) {
+      const int s = s0 + sl;
+      MsCell v;
+      ms_cell_values(cq, sh_s[3 * sl], sh_s[3 * sl + 1], sh_s[3 * sl + 2], v);
+      int pairs = 0;          // bit p * 2 + q: f1 segment p crosses f2 segment q
+      if (valid) {
+        double S1[2][4], S2[2][4];
+        const int n1 = ms_segments(v.F1, S1);
+        if (n1) {
+          const int n2 = ms_segments(v.F2, S2);
+          for (int p = 0; p < n1; ++p)
+            for (int q = 0; q < n2; ++q) {
+              double xi, eta;
+              if (ms_cross(S1, p, S2, q, xi, eta)) pairs |= 1 << (p * 2 + q);
+            }
+        }
+      }
+      if (!__any(pairs != 0)) continue;
+      for (int k = 0; k < 4; ++k) {
+        const bool hit = (pairs >> k) & 1;
+        const unsigned long long mask = __ballot(hit);
+        if (!mask) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
+        base = __shfl(base, leader, 64);
+        if (hit) {
+          const int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+          if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(cc * 4 + k);
+        }
       }
     }
   }
@@ -577,8 +605,10 @@ __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev
   const long long low = (long long)(key & 0xffffffffull), cell = low >> 2;
   const int pair = (int)(low & 3), p = pair >> 1, q = pair & 1;
   const int i = (int)(cell % (F.nx - 1)), j = (int)(cell / (F.nx - 1));
+  MsCorners cq;
+  ms_corners(F, i, j, cq);
   MsCell v;
-  ms_cell_values(F, s, i, j, v);
+  ms_cell_values(cq, F.beta[2 * s], F.beta[2 * s + 1], F.w[s], v);
   double S1[2][4], S2[2][4], xi = 0.0, eta = 0.0;
   ms_segments(v.F1, S1);
   ms_segments(v.F2, S2);
