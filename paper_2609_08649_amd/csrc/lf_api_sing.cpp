@@ -78,6 +78,7 @@ extern "C" lf_status lf_singularity_map(lf_ctx* ctx, const lf_model* M, const do
   A.ucell = wsi("sing.ucell", 2 * (size_t)cap); if (e) return e;
   A.ebits = (unsigned short*)ctx->ws("sing.bits", sizeof(unsigned short) * (size_t)P, st, &e);
   if (e) return e;
+  A.xpre = wsi("sing.xpre", 2 * (size_t)P); if (e) return e;
   A.ckey = (long long*)ctx->ws("sing.ckey", sizeof(long long) * cap, st, &e);
   if (e) return e;
   A.cpos = out->cross_pos; A.ck = out->cross_k; A.ce = out->cross_e; A.cg = out->cross_g; A.cfl = out->cross_flags;

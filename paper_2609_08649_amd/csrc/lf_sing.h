@@ -29,6 +29,7 @@ struct SingArgs {
   int* wch_cnt; int* wch_off;      // swallowtails per chunk of 256 segments, [cap/256 + 1]
   unsigned short* ebits;     // [nx*ny] per vertex: edge crossings, alignments, umbilic flag
   long long* ckey;           // [cap] crossing keys ((j * 2 + dir) * nx + i) * 2 + k - 1, ascending
+  int* xpre;                 // [2 * nx * ny] per direction and vertex: index of its edge's first crossing
   int* ucell;                // [cap*2] cell (i, j) of each umbilic
   // outputs
   double* cpos; int* ck; double* ce; double* cg; int* cfl;

@@ -217,6 +217,7 @@ __global__ __launch_bounds__(NT) void k_sing_keys(const SingArgs A) {
       const unsigned m = i < A.nx ? (A.ebits[(size_t)j * A.nx + i] >> (2 * dir)) & 3u : 0u;
       int tot;
       int idx = run + block_scan(__popc(m), lds, tot);
+      if (i < A.nx) A.xpre[(size_t)dir * A.nx * A.ny + (size_t)j * A.nx + i] = idx;
       for (int k = 0; k < 2; ++k)
         if ((m >> k) & 1u) {
           if (idx < A.cap) A.ckey[idx] = edge_key(A.nx, i, j, dir, k);
@@ -303,14 +304,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // 3. cells: segments and umbilic cells
 // ---------------------------------------------------------------------------------------
 namespace {
-__device__ int find_key(const SingArgs& A, int nX, long long key) {
-  int lo = 0, hi = nX;
-  while (lo < hi) {
-    const int m = (lo + hi) >> 1;
-    if (A.ckey[m] < key) lo = m + 1;
-    else hi = m;
-  }
-  return (lo < nX && A.ckey[lo] == key) ? lo : -1;
+// index in the crossing list of crossing k of the edge of vertex (i, j) in direction dir (w:
+// that vertex's word): the keys are in canonical order, so it is the vertex's prefix count
+// from the key pass, plus one for k = 1 when the edge also holds crossing k = 0
+__device__ __forceinline__ int cross_index(const SingArgs& A, int i, int j, int dir, int k, unsigned w) {
+  const int base = A.xpre[(size_t)dir * A.nx * A.ny + (size_t)j * A.nx + i];
+  return base + (k == 1 ? (int)((w >> (2 * dir)) & 1u) : 0);
 }
 struct CellRes {
   int nseg, umb, stat4, skipped, unpaired;
@@ -318,7 +317,7 @@ struct CellRes {
 // Marching squares of one cell for both families from the vertex words; emit(a, b, k) for
 // each segment in order.
 template <class Emit>
-__device__ CellRes cell_logic(const SingArgs& A, int i, int j, int nX, int uidx, Emit&& emit) {
+__device__ CellRes cell_logic(const SingArgs& A, int i, int j, int uidx, Emit&& emit) {
   CellRes r{0, 0, 0, 0, 0};
   const size_t p0 = (size_t)j * A.nx + i;
   const unsigned b0 = A.ebits[p0], b1 = A.ebits[p0 + 1], b3 = A.ebits[p0 + A.nx], b2 = A.ebits[p0 + A.nx + 1];
@@ -329,10 +328,10 @@ __device__ CellRes cell_logic(const SingArgs& A, int i, int j, int nX, int uidx,
   r.umb = P < 0.0 ? 1 : 0;
   for (int k = 0; k < 2; ++k) {
     int xs[4];
-    xs[0] = (b0 >> k) & 1u ? find_key(A, nX, edge_key(A.nx, i, j, 0, k)) : -1;
-    xs[1] = (b1 >> (2 + k)) & 1u ? find_key(A, nX, edge_key(A.nx, i + 1, j, 1, k)) : -1;
-    xs[2] = (b3 >> k) & 1u ? find_key(A, nX, edge_key(A.nx, i, j + 1, 0, k)) : -1;
-    xs[3] = (b0 >> (2 + k)) & 1u ? find_key(A, nX, edge_key(A.nx, i, j, 1, k)) : -1;
+    xs[0] = (b0 >> k) & 1u ? cross_index(A, i, j, 0, k, b0) : -1;
+    xs[1] = (b1 >> (2 + k)) & 1u ? cross_index(A, i + 1, j, 1, k, b1) : -1;
+    xs[2] = (b3 >> k) & 1u ? cross_index(A, i, j + 1, 0, k, b3) : -1;
+    xs[3] = (b0 >> (2 + k)) & 1u ? cross_index(A, i, j, 1, k, b0) : -1;
     int n = 0;
     for (int m = 0; m < 4; ++m) n += xs[m] >= 0 ? 1 : 0;
     if (P > 0.0) {
@@ -376,7 +375,6 @@ __global__ __launch_bounds__(NT) void k_sing_cells(const SingArgs A) {
   __shared__ int lds[4];
   const int j = blockIdx.x;            // cell row
   const bool over = A.counts[0] > A.cap;
-  const int nX = n_cross(A);
   if (over) {                          // crossing list incomplete: no cell output
     if (!WRITE && threadIdx.x == 0) {
       A.srow_cnt[j] = 0; A.urow_cnt[j] = 0; A.krow_cnt[j] = 0; A.prow_cnt[j] = 0;
@@ -388,7 +386,7 @@ __global__ __launch_bounds__(NT) void k_sing_cells(const SingArgs A) {
   for (int base = 0; base < T; base += NT) {
     const int i = base + threadIdx.x;
     CellRes c{0, 0, 0, 0, 0};
-    if (i < T) c = cell_logic(A, i, j, nX, 0, [](int, int, int) {});
+    if (i < T) c = cell_logic(A, i, j, 0, [](int, int, int) {});
     int ts, tu, tk, tp;
     const int ps = block_scan(c.nseg, lds, ts);
     const int pu = block_scan(c.umb, lds, tu);
@@ -396,7 +394,7 @@ __global__ __launch_bounds__(NT) void k_sing_cells(const SingArgs A) {
       if (i < T && (c.nseg || c.umb)) {
         const int uidx = urun + pu;
         int s = srun + ps;
-        cell_logic(A, i, j, nX, uidx, [&](int a, int b, int k) {
+        cell_logic(A, i, j, uidx, [&](int a, int b, int k) {
           if (s < A.cap) { A.sa[s] = a; A.sb[s] = b; A.sk[s] = k + 1; }
           ++s;
         });
