@@ -501,14 +501,16 @@ __global__ __launch_bounds__(NT) void k_sing_swt(const SingArgs A) {
 // central differences (step 1e-3 h) and grad g_k by central differences of g (step 1e-2 h):
 // status 0 converged (step < 1e-10") within h of the start, 1 no convergence in 20 steps, 2
 // moved farther than h (the interpolated point is kept), | 8 an umbilic-flagged evaluation;
-// then e_k at the point.  One workgroup of five waves per swallowtail: wave m evaluates g at
-// the point (m = 0) or at (x +- dg, y), (x, y +- dg) (m = 1..4); the step is formed from LDS.
-constexpr int SWT_WAVES = 5;
+// then e_k at the point.  One workgroup per swallowtail: a step needs 25 evaluations (g at the
+// point and at (x +- dg, y), (x, y +- dg), each from its point and four difference points),
+// spread over SWT_WAVES waves (four rounds); each wave keeps f_k, v_k and the umbilic flag of
+// its evaluations in LDS, and every thread then forms the differences in the same order.
+constexpr int SWT_WAVES = 8;
 __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingArgs A) {
-  __shared__ double gl[SWT_WAVES], fl3[3];
-  __shared__ int ul[SWT_WAVES];
+  __shared__ double ev[25][3];
+  __shared__ int eu[25];
   const int nW = min(A.counts[3], A.cap);
-  const int m = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
   for (int n = blockIdx.x; n < nW; n += gridDim.x) {
     const int k = A.wk[n] - 1;
     const double x0 = A.wpos[2 * (size_t)n], y0 = A.wpos[2 * (size_t)n + 1];
@@ -518,25 +520,40 @@ __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingAr
       const double d = 1e-3 * A.h, dg = 1e-2 * A.h;
       bool conv = false, umb = false;
       for (int it = 0; it < 20; ++it) {
-        const double qx = m == 1 ? x + dg : m == 2 ? x - dg : x;
-        const double qy = m == 3 ? y + dg : m == 4 ? y - dg : y;
-        bool u = false;
-        const VA3 P = point_a3(A, qx, qy);
-        if (P.umb) u = true;
-        double gx_, gy_;
-        fd_grad(A, P, qx, qy, k, d, u, gx_, gy_);
-        if ((threadIdx.x & 63) == 0) {
-          gl[m] = P.vx(k) * gx_ + P.vy(k) * gy_;
-          ul[m] = u ? 1 : 0;
-          if (m == 0) { fl3[0] = P.f(k); fl3[1] = gx_; fl3[2] = gy_; }
+        // evaluation e = 5 m + c: stencil point m of g (0 the point, 1/2 x +- dg, 3/4 y +- dg),
+        // c = 0 that point, 1..4 its f stencil (x + d, x - d, y + d, y - d)
+        for (int e = wv; e < 25; e += SWT_WAVES) {
+          const int m = e / 5, c = e - 5 * (e / 5);
+          const double qx = m == 1 ? x + dg : m == 2 ? x - dg : x;
+          const double qy = m == 3 ? y + dg : m == 4 ? y - dg : y;
+          const double px = c == 1 ? qx + d : c == 2 ? qx - d : qx;
+          const double py = c == 3 ? qy + d : c == 4 ? qy - d : qy;
+          const VA3 P = point_a3(A, px, py);
+          if ((threadIdx.x & 63) == 0) {
+            ev[e][0] = P.f(k); ev[e][1] = P.vx(k); ev[e][2] = P.vy(k);
+            eu[e] = P.umb ? 1 : 0;
+          }
         }
         __syncthreads();
-        const double f = fl3[0], fx = fl3[1], fy = fl3[2], g = gl[0];
-        for (int q = 0; q < SWT_WAVES; ++q) umb = umb || ul[q] != 0;
-        const double gx = (gl[1] - gl[2]) / (2 * dg), gy = (gl[3] - gl[4]) / (2 * dg);
+        double g[5], f = 0.0, fx = 0.0, fy = 0.0;
+        for (int m = 0; m < 5; ++m) {
+          const int e0 = 5 * m;
+          double F[4];
+          for (int c = 0; c < 4; ++c) {
+            const int e = e0 + 1 + c;
+            const double al = ev[e0][1] * ev[e][1] + ev[e0][2] * ev[e][2] >= 0.0 ? 1.0 : -1.0;
+            F[c] = al * ev[e][0];
+            umb = umb || eu[e] != 0;
+          }
+          umb = umb || eu[e0] != 0;
+          const double gx_ = (F[0] - F[1]) / (2 * d), gy_ = (F[2] - F[3]) / (2 * d);
+          g[m] = ev[e0][1] * gx_ + ev[e0][2] * gy_;
+          if (m == 0) { f = ev[0][0]; fx = gx_; fy = gy_; }
+        }
         __syncthreads();
+        const double gx = (g[1] - g[2]) / (2 * dg), gy = (g[3] - g[4]) / (2 * dg);
         const double det = fx * gy - fy * gx;
-        const double sx = -(gy * f - fy * g) / det, sy = -(-gx * f + fx * g) / det;
+        const double sx = -(gy * f - fy * g[0]) / det, sy = -(-gx * f + fx * g[0]) / det;
         x += sx;
         y += sy;
         if (!isfinite(x) || !isfinite(y)) break;
@@ -547,7 +564,7 @@ __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingAr
       if (umb) st |= 8;
       if (st != 0) { x = x0; y = y0; }
     }
-    if (m == 0) {
+    if (wv == 0) {
       const VA3 P = point_a3(A, x, y);
       if (threadIdx.x == 0) {
         A.wpos[2 * (size_t)n] = x;
