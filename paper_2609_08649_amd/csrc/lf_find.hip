@@ -2,10 +2,12 @@
 //
 // Finder pipeline (all on the device, no host synchronisation):
 //   1. vertex deflections on the grid (maps kernels, FP32 members in MIXED);
-//   2. k_find_cand: one lane per grid cell keeps its four corners in registers and loops
-//      over the sources; mapped corners beta_v = theta_v - sum_j w_j alpha_j(v); a triangle
-//      is a candidate when the source lies within eps of it (eps covers the vertex error of
-//      the precision in use), appended with one atomic per wave;
+//   2. k_find_cand: one lane per grid cell keeps FP32 copies of its four corners in
+//      registers and loops over the sources (staged in LDS); mapped corners
+//      beta_v = theta_v - sum_j w_j alpha_j(v); two FP32 prefilters (the mapped cell centre
+//      with a radius, then the bounding box), then the FP64 test: a triangle is a candidate
+//      when the source lies within eps of it (eps covers the vertex error of the precision in
+//      use), appended with one atomic per wave;
 //   3. k_find_sort: candidates sorted by (source, triangle) in LDS (bitonic, one workgroup);
 //   4. k_find_polish: per candidate, FP64 vertex deflections, exact orientation signs with
 //      the watertight tie rule, barycentric start, FP64 Newton polish and acceptance;

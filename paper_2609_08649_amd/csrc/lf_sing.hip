@@ -14,15 +14,17 @@
 //   1. k_sing_bits / k_sing_keys: per vertex row, every grid edge and family: does f_k change
 //      sign after alignment?  One 16-bit word per vertex (crossings, alignments, umbilic
 //      flag), a scan, then the crossings in the order (row j; horizontal edges by i, then
-//      vertical edges by i; k = 1, 2), stored as ascending keys;
+//      vertical edges by i; k = 1, 2), stored as ascending keys, with each vertex's index of
+//      its edges' first crossings (a prefix count);
 //   2. k_sing_refine: one lane per crossing: Illinois regula falsi on the edge with FP64
 //      evaluations, then e_k and g_k (central differences);
 //   3. k_sing_cells: per cell row, per family, from the four vertex words: segments (two
 //      crossings; four: the asymptotic decider of the bilinear interpolant), umbilic cells and
-//      the segments that end at them; crossings located by binary search over the keys;
+//      the segments that end at them; crossing indices read from the prefix counts;
 //   4. k_sing_umb: one wave per umbilic cell: Newton on (gamma_1, gamma_2) = 0;
 //   5. k_sing_swt: segments whose ends' g_k differ in sign give swallowtails (interpolated),
-//      refined by Newton on (f_k, g_k) = 0 with difference Jacobians (five waves per point).
+//      refined by Newton on (f_k, g_k) = 0 with difference Jacobians (a workgroup of eight
+//      waves per point).
 #include <hip/hip_runtime.h>
 
 #include "lf_sing.h"
