@@ -82,23 +82,29 @@ def summarize_profiles(kind, dirs):
             print("%-60s %7s %12.2f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["AverageNs"]) / 1e3,
                                                    float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
         return
-    if kind == "insts":
-        # SQ instruction counters of the lean maps kernel, per dispatch and per wave x member
-        sums = {}
+    if kind in ("insts", "insts_d3"):
+        # SQ instruction counters of the lean maps kernel (insts_d3: its third-derivative form,
+        # the dispatches of the largest wave count, i.e. the 4096^2 singularity maps), per
+        # dispatch and per wave x member
+        kern = "lf::k_maps<true, true, 1>" if kind == "insts_d3" else "lf::k_maps<true, false, 1>"
+        per = {}
         for d in dirs:
             path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
-            per = {}
             for r in csv.DictReader(open(path)):
-                if "lf::k_maps<true, false, 1>" in r["Kernel_Name"]:
-                    key = (r["Counter_Name"], r["Dispatch_Id"])
+                if kern in r["Kernel_Name"]:
+                    key = (d, r["Counter_Name"], r["Dispatch_Id"])
                     per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
-            for (ctr, _), v in per.items():
-                sums.setdefault(ctr, []).append(v)
+        waves_of = {(d, i): v for (d, c, i), v in per.items() if c == "SQ_WAVES"}
+        top = max(waves_of.values())
+        sums = {}
+        for (d, c, i), v in per.items():
+            if kind == "insts" or waves_of.get((d, i)) == top:
+                sums.setdefault(c, []).append(v)
         from paper_2609_08649_amd import workloads as W
         n_mem = len(W.config2()["model"]["members"]["x"])
         waves = sum(sums["SQ_WAVES"]) / len(sums["SQ_WAVES"])
-        print("lean maps kernel, %d dispatches, %.0f waves each, %d members per point" %
-              (len(sums["SQ_WAVES"]), waves, n_mem))
+        print("%s, %d dispatches, %.0f waves each, %d members per point" %
+              (kern, len(sums["SQ_WAVES"]), waves, n_mem))
         for ctr, v in sorted(sums.items()):
             avg = sum(v) / len(v)
             print("%-26s %16.0f per dispatch %10.2f per wave x member" % (ctr, avg, avg / waves / n_mem))
@@ -144,7 +150,7 @@ def parse():
                     % (COPY_PROBE_BYTES >> 20))
     ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
                     help="print a summary of rocprofv3 output: 'stats DIR', 'pmc FETCH_DIR WRITE_DIR' or "
-                         "'insts DIR...' (SQ instruction counters)")
+                         "'insts DIR...' / 'insts_d3 DIR...' (SQ instruction counters)")
     return ap.parse_args()
 
 
