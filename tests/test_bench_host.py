@@ -1,0 +1,111 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal, the gate that reports HBM traffic only
+while the kernel sources match the counter record, and the rocprofv3 summaries (kernel
+statistics; FETCH_SIZE / WRITE_SIZE calibrated on a plain copy of known size)."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _write_csv(path, fields, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def _pmc_rows(counter, lean_parts, copies):
+    """Counter rows as rocprofv3 writes them: one row per (dispatch, instance); the summary adds
+    the instances of a dispatch."""
+    lean = "void lf::k_maps<true, false, 1>(lf::MapsArgs)"
+    rows, d = [], 0
+    for parts in lean_parts:
+        d += 1
+        for v in parts:
+            rows.append({"Dispatch_Id": d, "Kernel_Name": lean, "Counter_Name": counter, "Counter_Value": v})
+    for v in copies:
+        d += 1
+        rows.append({"Dispatch_Id": d, "Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Name": counter,
+                     "Counter_Value": v})
+    # another kernel's dispatches are ignored
+    rows.append({"Dispatch_Id": d + 1, "Kernel_Name": "lf::k_expand(...)", "Counter_Name": counter,
+                 "Counter_Value": 1e9})
+    return rows
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_pmc_summary_calibrates_on_the_copy(tmp_path, capsys):
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    kib = bench.COPY_PROBE_BYTES / 1024
+    # FETCH_SIZE reads half of the copy's bytes (factor 2); the three largest copies are the probe
+    _write_csv(str(tmp_path / "f" / "run" / "run_counter_collection.csv"), fields,
+               _pmc_rows("FETCH_SIZE", [[60.0, 40.0], [120.0]], [kib / 2] * 3 + [5.0]))
+    # WRITE_SIZE counts all of them (factor 1)
+    _write_csv(str(tmp_path / "w" / "run" / "run_counter_collection.csv"), fields,
+               _pmc_rows("WRITE_SIZE", [[50.0], [30.0, 40.0]], [kib] * 3 + [7.0]))
+    bench.summarize_profiles("pmc", [str(tmp_path / "f"), str(tmp_path / "w")])
+    out = capsys.readouterr().out.strip().splitlines()
+    rec = json.loads(out[-1])
+    assert rec["copy_factor_fetch"] == pytest.approx(2.0)
+    assert rec["copy_factor_write"] == pytest.approx(1.0)
+    assert rec["dispatches"] == 2
+    assert rec["fetch_bytes_per_launch"] == pytest.approx(110.0 * 1024 * 2.0)
+    assert rec["write_bytes_per_launch"] == pytest.approx(60.0 * 1024)
+    assert rec["source_sha256"] == bench.kernel_source_hash()
+
+
+def test_stats_summary_lists_every_kernel(tmp_path, capsys):
+    fields = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]
+    rows = [{"Name": "void lf::k_maps<true, false, 1>(lf::MapsArgs)", "Calls": 4, "TotalDurationNs": 4.4e6,
+             "AverageNs": 1.1e6, "Percentage": 80.0},
+            {"Name": "lf::k_expand(...)", "Calls": 2, "TotalDurationNs": 1.1e6, "AverageNs": 5.5e5,
+             "Percentage": 20.0}]
+    _write_csv(str(tmp_path / "s" / "x" / "step_kernel_stats.csv"), fields, rows)
+    bench.summarize_profiles("stats", [str(tmp_path / "s")])
+    lines = capsys.readouterr().out.strip().splitlines()
+    assert lines[0].split() == ["kernel", "calls", "avg_us", "total_ms", "pct"]
+    first = lines[1].split()
+    assert first[-4:] == ["4", "1100.00", "4.400", "80.00"]
+    assert len(lines) == 3
+
+
+def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
+    good = {"kernel": "lf::k_maps<true, false, 1>", "source_sha256": bench.kernel_source_hash(),
+            "fetch_bytes_per_launch": 3.0e8, "write_bytes_per_launch": 1.5e8}
+    f = tmp_path / "traffic.txt"
+    f.write_text("# header\n" + json.dumps(good) + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.recorded_traffic() == pytest.approx(4.5e8)
+    stale = dict(good, source_sha256="0" * 64)
+    f.write_text("# header\n" + json.dumps(stale) + "\n")
+    assert bench.recorded_traffic() is None
+    f.write_text("# no record\n")
+    assert bench.recorded_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.recorded_traffic() is None
+
+
+def test_committed_traffic_record_is_well_formed():
+    with open(bench.TRAFFIC_FILE) as fh:
+        rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    assert rec["kernel"] == "lf::k_maps<true, false, 1>"
+    assert rec["fetch_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
+    for k in ("copy_factor_fetch", "copy_factor_write"):
+        assert 0.5 <= rec[k] <= 4.0
+    assert len(rec["source_sha256"]) == 64
