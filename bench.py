@@ -267,6 +267,7 @@ def main():
         torch.cuda.synchronize()
         return ev[0].elapsed_time(ev[1]) / n
 
+    note("warmup")
     for _ in range(args.warmup):
         step(lf.LF_PREC_MIXED)
     torch.cuda.synchronize()
@@ -302,6 +303,7 @@ def main():
         if c:
             kernels[k] = {"avg_ms": t / c, "launches_per_step": c / args.steps}
 
+    note("timed steps done: %.3f ms per step" % ms)
     # per-stage times (MIXED and FP64) with events on the working stream
     n_rep = max(2, args.steps // 2)
     st = {}
@@ -311,7 +313,10 @@ def main():
                     "chi2_img_ms": timed(lambda: stage_chi2(prec, 1), max(1, n_rep // 2)),
                     "find_ms": timed(lambda: stage_find(prec), n_rep)}
     fp64_step_ms = st["fp64"]["maps_ms"] + st["fp64"]["chi2_src_ms"] + st["fp64"]["find_ms"]
+    note("flux and time-delay terms")
     obs = bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, n_rep)
+    if not args.no_extras:
+        note("inference")
     inference = None if args.no_extras else bench_inference(ctx, lf, torch, W, m, cons, stream, cfg["truth"])
 
     extras = {}
@@ -320,6 +325,7 @@ def main():
 
     cpu, prec_rep = None, None
     if not args.no_cpu_baseline:
+        note("cpu baseline (oracle)")
         cpu, ref = cpu_baseline(model, cfg, n_img, cons_np["family"], a_maps, args.cpu_seconds)
         prec_rep = precision_report(ctx, lf, torch, m, params, grid, a_maps, ref)
 
@@ -401,8 +407,14 @@ def bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, 
     return res
 
 
+def note(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def bench_extras(ctx, lf, torch, W, stream, timed):
     out = {}
+    note("extras: multi-plane")
     # multi-plane: 3 planes (300/60/40 halos incl. eNFW), 4096^2 rays, 4 source redshifts
     c4 = W.config4()
     planes = [ctx.upload_model(p) for p in c4["planes"]]
@@ -427,10 +439,15 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
     for p in planes:
         p.release()
     torch.cuda.empty_cache()
+    note("extras: singularity map")
     out["singularity_map_4096"] = bench_singularity(ctx, lf, torch, W, stream, timed)
+    note("extras: contour finder")
     out["contour_finder_2048"] = bench_contour_finder(ctx, lf, torch, W, stream, timed)
+    note("extras: small single plane")
     out["config1_latency"] = bench_config1(ctx, lf, torch, W, stream)
+    note("extras: batched chi^2")
     out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
+    note("extras: serving")
     out["serving"] = bench_serving(ctx, lf, torch, W)
     return out
 
@@ -701,11 +718,13 @@ def bench_serving(ctx, lf, torch, W, duration=4.0):
                 "latency": st}
 
     burst = W.config5_requests(seed=2614, rate=1e6, duration=400 / 1e6)[:150]
+    note("serving: closed loop")
     closed = run(64 << 30, burst)
     C = closed["req_per_s"]
     out = {"closed_loop": closed, "capacity_req_per_s": C}
     for frac in (0.5, 0.8, 0.95):
         reqs = W.config5_requests(seed=2615, rate=frac * C, duration=duration)
+        note("serving: open loop at %g C" % frac)
         out["open_loop_%gC_budget64G" % frac] = dict(run(64 << 30, reqs, rate_scale=1.0), offered_rate=frac * C)
         if frac == 0.8:
             out["open_loop_0.8C_budget8G"] = dict(run(8 << 30, reqs, rate_scale=1.0), offered_rate=frac * C)
