@@ -67,14 +67,17 @@ __device__ __forceinline__ bool seg_term(const R& r, T dx, T dy, const Quad& qd,
 // psi_ij = sum(m) delta_ij + sum(w x_i x_j); alpha_i = sum(m x_i).  sum(w y^2) is taken as
 // sum(w r^2) - sum(w x^2) when a run is flushed (in FP64).  m is the mean convergence inside r
 // and w r^2 = 2 (kappa - m), so 0 <= kappa <= m (decreasing profiles) gives |w| r^2 <= 2 m: the
-// rounding of sum(w r^2) stays of the order of that of sum(m).
+// rounding of sum(w r^2) stays of the order of that of sum(m).  The third derivatives of a
+// circular term are psi_ijk = w (delta_ij x_k + delta_ik x_j + delta_jk x_i) + 2 w' x_i x_j x_k:
+// kept as sum(w x_i) (w x reuses the Hessian's product) and sum(w' x_i x_j x_k), combined at the
+// flush.
 struct Run32 {
-  float ax, ay, m, h11, h12, wr2, t111, t112, t122, t222;
+  float ax, ay, m, h11, h12, wr2, wx, wy, qxxx, qxxy, qxyy, qyyy;
 };
 template <bool D3>
 __device__ __forceinline__ void run_zero(Run32& s) {
   s.ax = s.ay = s.m = s.h11 = s.h12 = s.wr2 = 0.f;
-  if (D3) s.t111 = s.t112 = s.t122 = s.t222 = 0.f;
+  if (D3) s.wx = s.wy = s.qxxx = s.qxxy = s.qxyy = s.qyyy = 0.f;
 }
 template <bool D3>
 __device__ __forceinline__ void run_add(float dx, float dy, float r2, float m, float w, float wp, Run32& s) {
@@ -86,12 +89,13 @@ __device__ __forceinline__ void run_add(float dx, float dy, float r2, float m, f
   s.h12 = fmaf(wx, dy, s.h12);
   s.wr2 = fmaf(w, r2, s.wr2);
   if (D3) {
-    float q = 2.f * wp;
-    float qx2 = q * dx * dx, qy2 = q * dy * dy;
-    s.t111 = fmaf(dx, fmaf(3.f, w, qx2), s.t111);
-    s.t112 = fmaf(dy, w + qx2, s.t112);
-    s.t122 = fmaf(dx, w + qy2, s.t122);
-    s.t222 = fmaf(dy, fmaf(3.f, w, qy2), s.t222);
+    s.wx += wx;
+    s.wy = fmaf(w, dy, s.wy);
+    float pxx = wp * dx * dx, pyy = wp * dy * dy;
+    s.qxxx = fmaf(pxx, dx, s.qxxx);
+    s.qxxy = fmaf(pxx, dy, s.qxxy);
+    s.qxyy = fmaf(pyy, dx, s.qxyy);
+    s.qyyy = fmaf(pyy, dy, s.qyyy);
   }
 }
 template <bool D3>
@@ -100,7 +104,13 @@ __device__ __forceinline__ void run_flush(const Run32& s, Acc& a) {
   a.ax += (double)s.ax; a.ay += (double)s.ay;
   const double h11 = (double)s.h11;
   a.h11 += m + h11; a.h12 += (double)s.h12; a.h22 += m + ((double)s.wr2 - h11);
-  if (D3) { a.t111 += (double)s.t111; a.t112 += (double)s.t112; a.t122 += (double)s.t122; a.t222 += (double)s.t222; }
+  if (D3) {
+    const double wx = (double)s.wx, wy = (double)s.wy;
+    a.t111 += 3.0 * wx + 2.0 * (double)s.qxxx;
+    a.t112 += wy + 2.0 * (double)s.qxxy;
+    a.t122 += wx + 2.0 * (double)s.qxyy;
+    a.t222 += 3.0 * wy + 2.0 * (double)s.qyyy;
+  }
 }
 
 // m, w (and w') of a circular member at squared radius r2 > 0 (FP32 records).
