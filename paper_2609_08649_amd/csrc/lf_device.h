@@ -128,10 +128,9 @@ __device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T bd, T apls, 
   T num = fma(Da * apls, Da, Rs * G * G);
   w = -(eZ * iP) * (is * ia) * num;
   if (D3) {
-    T us = Da * iP, ua = Ds * iP;
-    T ps = us * us * is * is * fma((T)0.5, is, us);
-    T pa = ua * ua * ia * ia * fma((T)0.5, ia, ua);
-    wp = b * (ps - pa);
+    T us = Da * iP, ua = Ds * iP;                 // u of each core
+    T xs = us * is, xa = ua * ia;
+    wp = b * fma(xs * xs, fma((T)0.5, is, us), -(xa * xa * fma((T)0.5, ia, ua)));
   }
 }
 template <bool D3, class T>
