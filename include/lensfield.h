@@ -264,6 +264,23 @@ lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* m, const double* params, in
                         const lf_cons* c, int32_t mode, lf_prec prec, double* chi2,
                         int32_t* flags, double* beta_model, double* terms, void* stream);
 
+/* Allocation-free lf_chi2_batch, for the callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bit-identical) as lf_chi2_batch, but the call allocates
+ * nothing: its workspace is a static device array of LF_CHI2_NOALLOC_SCRATCH_BYTES that every
+ * GPU the library runs on holds until the process ends (lf_init takes its address once per
+ * device).  Workspace (bytes): S * (112 n_main + 32 + 16 n_fam) + 112 S n_img, plus
+ * 112 S n_img with flux or delay data, plus up to 256 per slice for alignment (the
+ * 1024-sample, 150-image, 60-family cluster case needs 18.5 MB).  Every call on a GPU shares
+ * that GPU's array and leaves its contents behind: calls that overlap on one GPU (from any
+ * context or stream) race, so the caller serialises them.  Kernel timing (lf_profile_enable)
+ * does not cover this call.  Errors: those of lf_chi2_batch; LF_E_OUT_OF_BUDGET when the
+ * workspace exceeds the array (nothing is launched). */
+#define LF_CHI2_NOALLOC_SCRATCH_BYTES (32u << 20)
+lf_status lf_chi2_batch_noalloc(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
+                                const lf_cons* c, int32_t mode, lf_prec prec, double* chi2,
+                                int32_t* flags, double* beta_model, void* stream);
+
 /* Image finder by triangle mapping (replacing the marching-squares contours of
  * Sec. 2.3).  Grid vertices are pixel centres; cell (i, j) splits along its
  * (i,j)-(i+1,j+1) diagonal.  A source is inside a mapped triangle by exact orientation

@@ -34,6 +34,17 @@ lf_status lf_ctx::hip(hipError_t e, const char* what) {
 
 // ------------------------------------------------------------------------------ workspace
 void* lf_ctx::ws(const char* name, size_t bytes, hipStream_t st, lf_status* err) {
+  if (arena) {
+    // allocation-free call: consecutive 256-byte aligned slices of the caller-held scratch
+    const size_t at = (arena->used + 255) & ~(size_t)255;
+    if (at + bytes > arena->cap) {
+      *err = fail(LF_E_OUT_OF_BUDGET, "%s: workspace %s does not fit the static scratch (needs %zu bytes from "
+                  "offset %zu; the scratch holds %zu)", arena->who, name, bytes, at, arena->cap);
+      return nullptr;
+    }
+    arena->used = at + bytes;
+    return arena->base + at;
+  }
   Buf& b = bufs[name];
   if (b.bytes >= bytes && b.ptr) return b.ptr;
   size_t want = std::max(bytes, b.bytes + b.bytes / 2);
@@ -214,6 +225,11 @@ extern "C" lf_status lf_init(lf_ctx** out, int32_t device, size_t hbm_budget_byt
   }
   hipMemcpy(c->quad_u, hu.data(), sizeof(double) * LF_ENFW_NODES, hipMemcpyHostToDevice);
   hipMemcpy(c->quad_w, hw.data(), sizeof(double) * LF_ENFW_NODES, hipMemcpyHostToDevice);
+  // address of this device's static scratch (allocation-free entry point), with the device current
+  if (lf_noalloc_setup(c) != LF_OK) {
+    lf_shutdown(c);
+    return LF_E_DEVICE;
+  }
   *out = c;
   return LF_OK;
 }
@@ -449,10 +465,10 @@ bool lf_points_spec(const lf_points* p, lf::PointsSpec& s) {
   return true;
 }
 
-// Expand S samples of a model into workspace tables; returns device pointers.
-lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params, int S, bool need_mem,
-                           hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
-                           lf::MemRec64** m64, const char* tag) {
+// Workspace tables for S expanded samples of a model (nothing is launched).
+lf_status lf_expand_alloc(lf_ctx* ctx, const lf_model* M, int S, bool need_mem, hipStream_t st,
+                          lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32, lf::MemRec64** m64,
+                          const char* tag) {
   lf_status err = LF_OK;
   std::string t(tag);
   int nm = (int)M->main.size(), nb = (int)M->mem.size();
@@ -467,10 +483,25 @@ lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params,
     *m64 = (lf::MemRec64*)ctx->ws((t + ".m64").c_str(), sizeof(lf::MemRec64) * std::max<size_t>(1, (size_t)S * nb), st, &err);
     if (err) return err;
   }
+  return LF_OK;
+}
+
+// Expand S samples of a model into tables placed by lf_expand_alloc.
+lf_status lf_expand_launch(lf_ctx* ctx, const lf_model* M, const double* params, int S, hipStream_t st,
+                           lf::MainRec* mains, lf::MulRec* muls, lf::MemRec32* m32, lf::MemRec64* m64) {
   ctx->prof_begin("expand", st);
-  hipError_t he = lf::launch_expand(lf_dev_model(M), params, S, *mains, *muls, *m32, *m64, st);
+  hipError_t he = lf::launch_expand(lf_dev_model(M), params, S, mains, muls, m32, m64, st);
   ctx->prof_end(st);
   return ctx->hip(he, "expand");
+}
+
+// Expand S samples of a model into workspace tables; returns device pointers.
+lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params, int S, bool need_mem,
+                           hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
+                           lf::MemRec64** m64, const char* tag) {
+  lf_status err = lf_expand_alloc(ctx, M, S, need_mem, st, mains, muls, m32, m64, tag);
+  if (err) return err;
+  return lf_expand_launch(ctx, M, params, S, st, *mains, *muls, *m32, *m64);
 }
 
 // Points per lane of the lean maps kernel: one by default (measured fastest on gfx950 once the

@@ -124,8 +124,10 @@ extern "C" lf_status lf_constraints_release(lf_ctx* ctx, lf_cons* c) {
 
 lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, int S, const lf_cons* c,
                           hipStream_t st, lf::Chi2Args& A, const char* tag) {
+  // every workspace buffer is placed before the first launch, so a call that does not fit
+  // its workspace fails before anything runs
   lf::MainRec* mains; lf::MulRec* muls; lf::MemRec32* m32; lf::MemRec64* m64;
-  lf_status e = lf_expand_tables(ctx, M, params, S, false, st, &mains, &muls, &m32, &m64, tag);
+  lf_status e = lf_expand_alloc(ctx, M, S, false, st, &mains, &muls, &m32, &m64, tag);
   if (e) return e;
   std::string t(tag);
   size_t n = (size_t)S * c->n_img;
@@ -157,7 +159,7 @@ lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, 
   A.qd.n = q.n; A.qd.u = q.u; A.qd.w = q.w;
   A.tmod = nullptr;
   if (c->has_obs()) { A.tmod = wsd(".tmod", n * 2); if (e) return e; }
-  return LF_OK;
+  return lf_expand_launch(ctx, M, params, S, st, mains, muls, m32, m64);
 }
 
 extern "C" lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
@@ -166,9 +168,9 @@ extern "C" lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* M, const double*
   return lf_chi2_terms(ctx, M, params, S, c, mode, prec, chi2, flags, beta_model, nullptr, stream);
 }
 
-extern "C" lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
-                                   const lf_cons* c, int32_t mode, lf_prec prec, double* chi2, int32_t* flags,
-                                   double* beta_model, double* terms, void* stream) {
+// Argument checks shared by the chi^2 entry points (nothing is launched when they fail).
+lf_status lf_chi2_check(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S, const lf_cons* c,
+                        int32_t mode, lf_prec prec, const double* chi2) {
   if (!ctx) return LF_E_INVALID_ARG;
   if (!M || !c || !chi2) return ctx->fail(LF_E_INVALID_ARG, "null model/constraints/output");
   if (S < 1) return ctx->fail(LF_E_INVALID_ARG, "S must be >= 1");
@@ -179,6 +181,14 @@ extern "C" lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* M, const double*
   if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
   if (c->d_mag && lf_model_has_enfw(M))
     return ctx->fail(LF_E_UNSUPPORTED, "flux terms need third derivatives, not available for elliptical NFW");
+  return LF_OK;
+}
+
+extern "C" lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
+                                   const lf_cons* c, int32_t mode, lf_prec prec, double* chi2, int32_t* flags,
+                                   double* beta_model, double* terms, void* stream) {
+  lf_status ce = lf_chi2_check(ctx, M, params, S, c, mode, prec, chi2);
+  if (ce) return ce;
   hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;
   lf::Chi2Args A;

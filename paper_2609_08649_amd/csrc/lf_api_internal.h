@@ -43,6 +43,15 @@ struct lf_ctx {
   void dfree(void* p, size_t bytes);
   int ppl_override = 0;        // LF_MAPS_PPL (1, 2 or 4): points per lane of the lean maps kernel
   int maps_ppl(bool mixed, bool d3);
+  // Allocation-free calls: while `arena` is set, ws() hands out slices of it and never
+  // allocates.  noalloc_scratch is this device's static scratch array (lf_api_noalloc.cpp).
+  struct Arena {
+    char* base;
+    size_t cap, used;
+    const char* who;
+  };
+  Arena* arena = nullptr;
+  char* noalloc_scratch = nullptr;
 };
 
 struct lf_model {
@@ -85,6 +94,12 @@ lf::DevModel lf_dev_model(const lf_model* M);
 lf::QuadTab lf_quad(const lf_ctx* ctx);
 bool lf_model_has_enfw(const lf_model* M);
 bool lf_points_spec(const lf_points* p, lf::PointsSpec& s);
+lf_status lf_expand_alloc(lf_ctx* ctx, const lf_model* M, int S, bool need_mem, hipStream_t st,
+                          lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32, lf::MemRec64** m64,
+                          const char* tag);
+lf_status lf_expand_launch(lf_ctx* ctx, const lf_model* M, const double* params, int S, hipStream_t st,
+                           lf::MainRec* mains, lf::MulRec* muls, lf::MemRec32* m32, lf::MemRec64* m64);
+lf_status lf_noalloc_setup(lf_ctx* ctx);
 lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params, int S, bool need_mem,
                            hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
                            lf::MemRec64** m64, const char* tag);

@@ -104,6 +104,7 @@ def lib():
             "lf_lens_maps": (I32, [P, P, P, I32, C.POINTER(lf_points), D, I32, C.POINTER(lf_maps), P]),
             "lf_chi2_batch": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
             "lf_chi2_terms": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P, P]),
+            "lf_chi2_batch_noalloc": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
             "lf_find_images_ms": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
@@ -361,6 +362,25 @@ def _chi2(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC
 
 
 Context.chi2_batch = _chi2
+
+
+def _chi2_noalloc(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC_FP64, want_beta=False,
+                  stream=None, out=None):
+    """chi^2 per sample through the allocation-free entry point (workspace in the library's static
+    device scratch); same outputs as chi2_batch."""
+    dev = self.device
+    chi2 = out["chi2"] if out else torch.empty(S, dtype=torch.float64, device=dev)
+    flags = out["flags"] if out else torch.empty(S, dtype=torch.int32, device=dev)
+    bm = torch.empty((S, cons.n_fam, 2), dtype=torch.float64, device=dev) if want_beta else None
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_chi2_batch_noalloc(self.handle, model.handle, pp, int(S), cons.handle, int(mode),
+                                           int(prec), C.c_void_p(chi2.data_ptr()), C.c_void_p(flags.data_ptr()),
+                                           C.c_void_p(bm.data_ptr()) if bm is not None else None,
+                                           _stream(stream)))
+    return chi2, flags, bm
+
+
+Context.chi2_batch_noalloc = _chi2_noalloc
 
 
 def _chi2_terms(self, model: Model, params, S, cons: Constraints, mode=0, prec=LF_PREC_FP64, want_beta=False,
