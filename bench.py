@@ -37,6 +37,12 @@ PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak [FLOP/s]
 F_CPJE = 39
 
 
+# The lean maps kernel on a grid in the mixed precision (the roofline kernel), its
+# third-derivative form, and the points each of their lanes holds.
+LEAN_KERNEL = "lf::k_maps_tile<false>"
+LEAN_D3_KERNEL = "lf::k_maps_tile<true>"
+LANE_POINTS = {LEAN_KERNEL: 2, LEAN_D3_KERNEL: 1}
+
 # Sources that define the lean maps kernel: a traffic measurement is reported only while
 # their hash matches the one recorded with the counters.
 MAPS_KERNEL_SOURCES = ("lf_maps.hip", "lf_segs.h", "lf_device.h", "lf_internal.h", "lf_launch.h")
@@ -67,6 +73,25 @@ def recorded_traffic():
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+STATS_FILE = os.path.join(ROOT, "profiles", "step_cluster2048_kernel_stats.txt")
+
+
+def recorded_profile_ms():
+    """Average duration [ms] of the lean maps kernel in the committed rocprofv3 kernel statistics of
+    the bench step, or None when the summary is missing or the kernel sources changed since."""
+    try:
+        lines = open(STATS_FILE).read().splitlines()
+    except OSError:
+        return None
+    sha = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("# source_sha256:")]
+    if not sha or sha[0] != kernel_source_hash():
+        return None
+    for ln in lines:
+        if ln.startswith("void " + LEAN_KERNEL + "(") or ln.startswith(LEAN_KERNEL + "("):
+            return float(ln.split()[-3]) / 1e3
+    return None
+
+
 def summarize_profiles(kind, dirs):
     """Text summaries of rocprofv3 output (no GPU needed).  kind 'stats': the kernel statistics
     CSV of --kernel-trace --stats; kind 'pmc': two --pmc runs (FETCH_SIZE dir, WRITE_SIZE dir)
@@ -77,6 +102,7 @@ def summarize_profiles(kind, dirs):
     if kind == "stats":
         path = glob.glob(os.path.join(dirs[0], "**", "*kernel_stats.csv"), recursive=True)[0]
         rows = list(csv.DictReader(open(path)))
+        print("# source_sha256: %s" % kernel_source_hash())
         print("%-60s %7s %12s %12s %7s" % ("kernel", "calls", "avg_us", "total_ms", "pct"))
         for r in rows:
             print("%-60s %7s %12.2f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["AverageNs"]) / 1e3,
@@ -85,8 +111,10 @@ def summarize_profiles(kind, dirs):
     if kind in ("insts", "insts_d3"):
         # SQ instruction counters of the lean maps kernel (insts_d3: its third-derivative form,
         # the dispatches of the largest wave count, i.e. the 4096^2 singularity maps), per
-        # dispatch and per wave x member
-        kern = "lf::k_maps<true, true, 1>" if kind == "insts_d3" else "lf::k_maps<true, false, 1>"
+        # dispatch and per 64 points x member (one wave's worth of points: the kernel holds
+        # LANE_POINTS[kern] points per lane), and the FLOPs the counters imply (FMA 2, add, mul and
+        # transcendental 1 each, 64 lanes per wave-instruction)
+        kern = LEAN_D3_KERNEL if kind == "insts_d3" else LEAN_KERNEL
         per = {}
         for d in dirs:
             path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
@@ -103,11 +131,18 @@ def summarize_profiles(kind, dirs):
         from paper_2609_08649_amd import workloads as W
         n_mem = len(W.config2()["model"]["members"]["x"])
         waves = sum(sums["SQ_WAVES"]) / len(sums["SQ_WAVES"])
-        print("%s, %d dispatches, %.0f waves each, %d members per point" %
-              (kern, len(sums["SQ_WAVES"]), waves, n_mem))
-        for ctr, v in sorted(sums.items()):
-            avg = sum(v) / len(v)
-            print("%-26s %16.0f per dispatch %10.2f per wave x member" % (ctr, avg, avg / waves / n_mem))
+        groups = waves * LANE_POINTS[kern]
+        print("%s, %d dispatches, %.0f waves each (%d points per lane), %d members per point" %
+              (kern, len(sums["SQ_WAVES"]), waves, LANE_POINTS[kern], n_mem))
+        avg = {ctr: sum(v) / len(v) for ctr, v in sums.items()}
+        for ctr in sorted(avg):
+            print("%-26s %16.0f per dispatch %10.2f per 64 points x member" % (ctr, avg[ctr], avg[ctr] / groups / n_mem))
+        fl = {"FMA": 2, "ADD": 1, "MUL": 1, "TRANS": 1}
+        f32 = sum(64 * w * avg.get("SQ_INSTS_VALU_%s_F32" % k, 0.0) for k, w in fl.items())
+        f64 = sum(64 * w * avg.get("SQ_INSTS_VALU_%s_F64" % k, 0.0) for k, w in fl.items())
+        if f32 or f64:
+            print("counter FLOPs per dispatch: FP32 %.4g, FP64 %.4g; algorithmic %.4g (%d points x %d members x %d)" %
+                  (f32, f64, groups * 64 * n_mem * F_CPJE, groups * 64, n_mem, F_CPJE))
         return
     vals = {}
     for d, ctr in zip(dirs, ("FETCH_SIZE", "WRITE_SIZE")):
@@ -119,7 +154,7 @@ def summarize_profiles(kind, dirs):
             key = (r["Kernel_Name"], r["Dispatch_Id"])
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
         vals[ctr] = per
-    lean = "lf::k_maps<true, false, 1>"
+    lean = LEAN_KERNEL
     out = {}
     for ctr, per in vals.items():
         lk = [v for (n, _), v in per.items() if lean in n]
@@ -144,10 +179,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated extras to run (issue_rates, multiplane, singularity, contour, config1, "
+                         "batched, serving, inference) or 'all'")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the run, copy %d MiB device to device three times (counter calibration)"
                     % (COPY_PROBE_BYTES >> 20))
+    ap.add_argument("--rates", action="store_true", help="print only the issue-rate probe's results (JSON)")
     ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
                     help="print a summary of rocprofv3 output: 'stats DIR', 'pmc FETCH_DIR WRITE_DIR' or "
                          "'insts DIR...' / 'insts_d3 DIR...' (SQ instruction counters)")
@@ -203,6 +242,9 @@ def main():
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.rates:
+        print(json.dumps(issue_rates(torch.cuda.get_device_properties(0).multi_processor_count)), flush=True)
+        return
     from paper_2609_08649_amd import lensfield as lf
     from paper_2609_08649_amd import workloads as W
 
@@ -315,14 +357,16 @@ def main():
     fp64_step_ms = st["fp64"]["maps_ms"] + st["fp64"]["chi2_src_ms"] + st["fp64"]["find_ms"]
     note("flux and time-delay terms")
     obs = bench_flux_td(ctx, lf, torch, cfg, m, params, cons_np, srcs, stream, timed, n_rep)
-    if not args.no_extras:
+    want = (lambda k: not args.no_extras and (args.extras == "all" or k in args.extras.split(",")))
+    if want("inference"):
         note("inference")
-    inference = None if args.no_extras else bench_inference(ctx, lf, torch, W, m, cons, stream, cfg["truth"])
+    inference = bench_inference(ctx, lf, torch, W, m, cons, stream, cfg["truth"]) if want("inference") else None
 
     extras = {}
     if not args.no_extras:
-        extras = bench_extras(ctx, lf, torch, W, stream, timed)
+        extras = bench_extras(ctx, lf, torch, W, stream, timed, want)
 
+    prof_ms = recorded_profile_ms()
     cpu, prec_rep = None, None
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
@@ -364,7 +408,10 @@ def main():
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": recorded_traffic(),
                      "avg_launch_ms": lean_ms, "flops_per_launch": flops_lean,
-                     "flops_per_eval": F_CPJE, "evals_per_launch": n_mem * P},
+                     "flops_per_eval": F_CPJE, "evals_per_launch": n_mem * P,
+                     "timing": "HIP events recorded on the launching stream around each launch, this run",
+                     "profile_avg_launch_ms": prof_ms,
+                     "profile_frac": (flops_lean / (prof_ms * 1e-3) / PEAK_FP32_VECTOR) if prof_ms else None},
         "extras": extras,
         "precision_vs_oracle": prec_rep,
         "cpu_baseline": cpu,
@@ -412,10 +459,78 @@ def note(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def bench_extras(ctx, lf, torch, W, stream, timed):
+# Issue-rate probe kinds: (id, name, waves per SIMD, FP32 non-transcendental and transcendental
+# wave-instructions per lane per iteration, FP64 wave-instructions per lane per iteration)
+RATE_KINDS = ((0, "fma_f32", 8, 32, 0, 0), (7, "mul_f32", 8, 32, 0, 0), (1, "rsq_f32", 8, 0, 8, 0),
+              (2, "rcp_f32", 8, 0, 8, 0), (4, "fma_f64", 8, 0, 0, 32), (3, "fma_f32+rsq 16:1", 8, 32, 2, 0),
+              (8, "fma_f32+rsq 8:1", 8, 32, 4, 0), (9, "fma_f32+rsq 4:1", 8, 32, 8, 0),
+              (5, "fma_f32 dependent, 1 wave/SIMD", 1, 32, 0, 0), (6, "rsq_f32 dependent, 1 wave/SIMD", 1, 0, 8, 0),
+              (10, "fma_f32 vgpr operands", 8, 32, 0, 0), (11, "add_f32 vgpr operands", 8, 32, 0, 0),
+              (13, "mul_f32 vgpr operands", 8, 32, 0, 0), (12, "fma_f32 vgpr operands, 16 chains", 8, 32, 0, 0),
+              (14, "fma_f32 vgpr operands+rsq 8:1", 8, 32, 4, 0))
+
+
+def issue_rates(n_cu, iters=4096):
+    """Wave-instruction issue cost of the VALU operations the halo sums are made of, measured by the
+    probe library (paper_2609_08649_amd/probe/lf_rates.hip) at the shader clock the part ran: for
+    each kind, shader cycles per wave-instruction per SIMD (the mixed kinds give the cost of one
+    transcendental on top of the FMAs), and the FP32 FMA rate as lanes per clock per CU."""
+    from paper_2609_08649_amd import build as hb
+    L = C.CDLL(hb.PROBE_LIB)
+    L.lfr_run.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_double)]
+    L.lfr_run.restype = C.c_int
+    simds = 4 * n_cu
+    out = {"iters": iters, "simds": simds}
+    for kid, name, wps, n32, ntr, n64 in RATE_KINDS:
+        blocks = n_cu * wps                 # 256-thread workgroups: one wave per SIMD each
+        ms, mhz = C.c_float(), C.c_double()
+        L.lfr_run(kid, 64, blocks, C.byref(ms), C.byref(mhz))          # warm-up
+        rc = L.lfr_run(kid, iters, blocks, C.byref(ms), C.byref(mhz))
+        if rc:
+            out[name] = {"error": rc}
+            continue
+        waves = blocks * 4
+        instr = (n32 + ntr + n64) * iters * waves / simds            # wave-instructions per SIMD
+        cycles = ms.value * 1e-3 * mhz.value * 1e6
+        rec = {"ms": ms.value, "clock_mhz": mhz.value, "cycles_per_wave_instr": cycles / instr}
+        if ntr and n32:
+            base = out["fma_f32 vgpr operands" if "vgpr" in name else "fma_f32"]["cycles_per_wave_instr"]
+            rec["cycles_per_transcendental"] = (cycles - base * n32 * iters * waves / simds) / (ntr * iters * waves / simds)
+        if name == "fma_f32":
+            rec["lanes_per_clk_per_cu"] = 64 * 4 / rec["cycles_per_wave_instr"]
+        out[name] = rec
+    return out
+
+
+def bench_extras(ctx, lf, torch, W, stream, timed, want):
     out = {}
-    note("extras: multi-plane")
-    # multi-plane: 3 planes (300/60/40 halos incl. eNFW), 4096^2 rays, 4 source redshifts
+    if want("issue_rates"):
+        note("extras: issue rates")
+        out["issue_rates"] = issue_rates(torch.cuda.get_device_properties(0).multi_processor_count)
+    if want("multiplane"):
+        note("extras: multi-plane")
+        out["multiplane_4096"] = bench_multiplane(ctx, lf, torch, W, stream, timed)
+    if want("singularity"):
+        note("extras: singularity map")
+        out["singularity_map_4096"] = bench_singularity(ctx, lf, torch, W, stream, timed)
+    if want("contour"):
+        note("extras: contour finder")
+        out["contour_finder_2048"] = bench_contour_finder(ctx, lf, torch, W, stream, timed)
+    if want("config1"):
+        note("extras: small single plane")
+        out["config1_latency"] = bench_config1(ctx, lf, torch, W, stream)
+    if want("batched"):
+        note("extras: batched chi^2")
+        out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
+    if want("serving"):
+        note("extras: serving")
+        out["serving"] = bench_serving(ctx, lf, torch, W)
+    return out
+
+
+def bench_multiplane(ctx, lf, torch, W, stream, timed):
+    """Multi-plane: 3 planes (300/60/40 halos incl. eNFW), 4096^2 rays, 4 source redshifts, and
+    the images of 60 sources at their own redshifts on that grid."""
     c4 = W.config4()
     planes = [ctx.upload_model(p) for p in c4["planes"]]
     H4 = sum(p.n_halos for p in planes)
@@ -435,21 +550,10 @@ def bench_extras(ctx, lf, torch, W, stream, timed):
         t = timed(lambda: ctx.find_images_mp(planes, c4["z_planes"], b4, z4, c4["grid"], 16, prec, stream=stream), 2)
         res[name]["find_ms"] = t
         res[name]["find_images"] = int(r["count"].sum().item())
-    out["multiplane_4096"] = {"halos": H4, "rays": P4, "z_src": len(c4["zs_maps"]), "find_sources": n4, **res}
     for p in planes:
         p.release()
     torch.cuda.empty_cache()
-    note("extras: singularity map")
-    out["singularity_map_4096"] = bench_singularity(ctx, lf, torch, W, stream, timed)
-    note("extras: contour finder")
-    out["contour_finder_2048"] = bench_contour_finder(ctx, lf, torch, W, stream, timed)
-    note("extras: small single plane")
-    out["config1_latency"] = bench_config1(ctx, lf, torch, W, stream)
-    note("extras: batched chi^2")
-    out["batched_chi2"] = bench_batched(ctx, lf, torch, W, stream, timed)
-    note("extras: serving")
-    out["serving"] = bench_serving(ctx, lf, torch, W)
-    return out
+    return {"halos": H4, "rays": P4, "z_src": len(c4["zs_maps"]), "find_sources": n4, **res}
 
 
 def bench_inference(ctx, lf, torch, W, m, cons, stream, truth, n_nm=10000, nm_rounds=2000, n_steps=20000):
@@ -735,6 +839,22 @@ def bench_serving(ctx, lf, torch, W, duration=4.0):
     return out
 
 
+def host_info():
+    """The host the oracle ran on: CPU model, logical CPUs (nproc), the CPUs this process may use,
+    and the thread count of the oracle (the process's CPU share)."""
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    from oracle import oracle as orc
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "oracle_threads": orc.nthreads_default()}
+
+
 def cpu_baseline(model, cfg, n_img, family, a_maps, seconds):
     """The FP64 oracle (as it stands, all host threads) timed on one whole step of the same
     workload: maps at every point of the 2048^2 grid (fewer if that alone exceeds the time
@@ -787,8 +907,20 @@ def cpu_baseline(model, cfg, n_img, family, a_maps, seconds):
     P = x.size
     evals = n * H + S * n_img * H + P * H
     t = t_maps + t_chi + t_find
+    # the same maps and chi^2 on one thread (a smaller sample of each)
+    n1 = max(200, n // 64)
+    t0 = time.perf_counter()
+    orc.maps(tab, x[idx[:n1]], y[idx[:n1]], a_maps, nthreads=1)
+    t1_maps = time.perf_counter() - t0
+    S1 = max(8, S // 64)
+    t0 = time.perf_counter()
+    orc.chi2_batch(tabs[:S1], cons, nthreads=1)
+    t1_chi = time.perf_counter() - t0
     res = {"value": evals / t, "unit": "evals/s", "cores": nth, "kind": "oracle",
            "chi2_per_s": S / t_chi, "seconds": {"maps": t_maps, "chi2": t_chi, "find": t_find},
+           "host": host_info(),
+           "single_thread": {"maps_evals_per_s": n1 * H / t1_maps, "chi2_per_s": S1 / t1_chi,
+                             "sample": "maps at %d points, chi^2 of %d samples" % (n1, S1)},
            "sample": "one step: maps at %d of the %d grid points (alpha, Hessian, third derivatives by AD), "
                      "source-plane chi^2 of %d samples x %d images, images of %d sources on the 2048^2 grid; "
                      "%d halos; %.1f s" % (n, P, S, n_img, n_src, H, t)}

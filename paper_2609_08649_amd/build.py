@@ -35,7 +35,25 @@ def _compile(src):
     return obj
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "lf_rates.hip")
+PROBE_LIB = os.path.join(HERE, "liblfrates.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The issue-rate probe used by the benchmark (a separate library: nothing of lensfield uses it)."""
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", "-shared", PROBE_SRC, "-o", tmp] + COMMON + DEVICE
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (PROBE_SRC, r.stderr[-4000:]))
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print("built", PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
+    build_probe(verbose)
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:

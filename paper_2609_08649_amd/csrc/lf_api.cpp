@@ -196,10 +196,6 @@ extern "C" lf_status lf_init(lf_ctx** out, int32_t device, size_t hbm_budget_byt
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LF_E_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return LF_E_DEVICE;
   lf_ctx* c = new lf_ctx();
-  if (const char* e = getenv("LF_MAPS_PPL")) {
-    int v = atoi(e);
-    if (v == 1 || v == 2 || v == 4) c->ppl_override = v;
-  }
   c->device = device;
   size_t fr = 0, tot = 0;
   hipMemGetInfo(&fr, &tot);
@@ -504,14 +500,9 @@ lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params,
   return lf_expand_launch(ctx, M, params, S, st, *mains, *muls, *m32, *m64);
 }
 
-// Points per lane of the lean maps kernel: one by default (measured fastest on gfx950 once the
-// FP64 near-field branch is in the member loop: it costs registers, and occupancy wins over
-// sharing a member record between points).  LF_MAPS_PPL = 2 or 4 selects the multi-point
-// variants of the FP32 path without third derivatives.
-int lf_ctx::maps_ppl(bool mixed, bool d3) {
-  if (mixed && !d3) return ppl_override ? ppl_override : 1;
-  return 1;
-}
+// Points per lane of the lean maps kernel: one (two and four points per lane, sharing a member
+// record between points, measured 7-17% slower on gfx950: occupancy wins).
+int lf_ctx::maps_ppl(bool, bool) { return 1; }
 
 // ------------------------------------------------------------------------------ lens maps
 extern "C" lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,

@@ -41,8 +41,7 @@ struct lf_ctx {
   void* ws(const char* name, size_t bytes, hipStream_t st, lf_status* err);
   lf_status dmalloc(void** p, size_t bytes);
   void dfree(void* p, size_t bytes);
-  int ppl_override = 0;        // LF_MAPS_PPL (1, 2 or 4): points per lane of the lean maps kernel
-  int maps_ppl(bool mixed, bool d3);
+  int maps_ppl(bool mixed, bool d3);   // points per lane of the lean maps kernel
   // Allocation-free calls: while `arena` is set, ws() hands out slices of it and never
   // allocates.  noalloc_scratch is this device's static scratch array (lf_api_noalloc.cpp).
   struct Arena {

@@ -108,12 +108,13 @@ __device__ __forceinline__ void cored_mw(T b, T s, T s2, T r2, T& m, T& w, T& wp
 //   R_a - R_s = (a^2 - s^2) / Sg,   D_a - D_s = (a - s) G / Sg,
 //   m = b/D_s - b/D_a = b (a - s) G / (Sg D_s D_a),
 //   w = -b/(D_s^2 R_s) + b/(D_a^2 R_a) = -b (a - s) (D_a^2 (a + s) + R_s G^2) / (Sg (D_s D_a)^2 R_s R_a),
-// every term positive, and one reciprocal, 1/(Sg D_s D_a), serves m, w and 1/(D_s D_a).
-// Subtracting two cored terms instead loses about log2(r/a) bits far from the member, where
-// both terms are ~ b/r and their difference ~ b (a - s)/r^2.  bd = b (a - s) and apls = a + s
-// are supplied by the caller.  Sg D_s D_a ~ 2 r^3 must stay finite: FP32 callers keep
-// r^2 < 1e25.  w' (third derivatives only) is the difference of the per-core derivatives
-// b u^2 is^2 (u + is/2), u = 1/D, is = 1/R.
+// every term positive, and one reciprocal, 1/(Sg D_s D_a), serves m, w and 1/(D_s D_a).  With
+// R_s (1/R_s) = 1 the last form is w = -b (a - s) (D_a^2 (a + s)/R_s + G^2) / (Sg (D_s D_a)^2 R_a),
+// one product fewer.  Subtracting two cored terms instead loses about log2(r/a) bits far from
+// the member, where both terms are ~ b/r and their difference ~ b (a - s)/r^2.  bd = b (a - s)
+// and apls = a + s are supplied by the caller.  Sg D_s D_a ~ 2 r^3 must stay finite: FP32
+// callers keep r^2 < 1e25.  w' (third derivatives only) is the difference of the per-core
+// derivatives b u^2 is^2 (u + is/2), u = 1/D, is = 1/R.
 template <bool D3, class T>
 __device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T bd, T apls, T r2, T& m, T& w, T& wp) {
   T Ss = s2 + r2, Sa = a2 + r2;
@@ -125,8 +126,8 @@ __device__ __forceinline__ void pje_mw(T b, T s, T a, T s2, T a2, T bd, T apls, 
   T eZ = bd * Z;
   m = eZ * G;
   T iP = Sg * Z;
-  T num = fma(Da * apls, Da, Rs * G * G);
-  w = -(eZ * iP) * (is * ia) * num;
+  T num = fma((Da * apls) * is, Da, G * G);
+  w = -(eZ * iP) * ia * num;
   if (D3) {
     T us = Da * iP, ua = Ds * iP;                 // u of each core
     T xs = us * is, xa = ua * ia;

@@ -117,6 +117,24 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
         const double rn = NEAR_K * b / c.q;
         r.rn2 = (float)fmax(rn * rn, 1e-12);
         r.pad0 = r.pad1 = r.pad2 = 0.f;
+        // far-field expansion of the circular dPIE b (1/(R_s + s) - 1/(R_a + a)): with t = 1/r,
+        // 1/(R_c + c) = t (sqrt(1 + c^2 t^2) - c t) = t (1 - c t + sum_k beta_k (c t)^(2k)),
+        // beta_k = binom(1/2, k), so m = b (a - s) t^2 + sum_k b beta_k (s^2k - a^2k) t^(2k+1) and
+        // w = 2 dm/d(r^2) = -t^3 dm/dt
+        const double beta[6] = {0.0, 0.5, -0.125, 0.0625, -0.0390625, 0.02734375};
+        const bool far_ok = a <= FAR_AMAX;
+        double sp = 1.0, ap = 1.0;
+        for (int k = 0; k < 6; ++k) {
+          double mk = 0.0;
+          if (k == 0) mk = b * (a - sc);
+          else {
+            sp *= sc * sc;
+            ap *= a * a;
+            mk = b * beta[k] * (sp - ap);
+          }
+          r.fm[k] = far_ok ? (float)mk : 0.f;
+          r.fw[k] = far_ok ? (float)(-(2 * k + 1 + (k == 0)) * mk) : 0.f;
+        }
         m32[(size_t)s * m.n_mem + i] = r;
       }
     }
@@ -155,6 +173,38 @@ __device__ __forceinline__ void point_of(const PointsSpec& ps, long long p, doub
     x = ps.px[p];
     y = ps.py[p];
   }
+}
+
+// Fused epilogue (Sec. 2.1; Sec. 6 fields with third derivatives) and the requested planes of
+// one point.
+template <bool D3>
+__device__ __forceinline__ void store_point(const MapsArgs& A, size_t idx, double x, double y, const Acc& acc) {
+  const MapsOut& o = A.out;
+  Epi e;
+  epilogue<D3>(x, y, A.a, acc, e);
+  if (o.ax) o.ax[idx] = acc.ax;
+  if (o.ay) o.ay[idx] = acc.ay;
+  if (o.p11) o.p11[idx] = acc.h11;
+  if (o.p12) o.p12[idx] = acc.h12;
+  if (o.p22) o.p22[idx] = acc.h22;
+  if (o.kappa) o.kappa[idx] = e.kappa;
+  if (o.g1) o.g1[idx] = e.g1;
+  if (o.g2) o.g2[idx] = e.g2;
+  if (o.detA) o.detA[idx] = e.detA;
+  if (o.mu) o.mu[idx] = e.mu;
+  if (o.bx) o.bx[idx] = e.bx;
+  if (o.by) o.by[idx] = e.by;
+  if (o.e1) o.e1[idx] = e.e1;
+  if (o.e2) o.e2[idx] = e.e2;
+  if (D3) {
+    if (o.t111) o.t111[idx] = acc.t111;
+    if (o.t112) o.t112[idx] = acc.t112;
+    if (o.t122) o.t122[idx] = acc.t122;
+    if (o.t222) o.t222[idx] = acc.t222;
+    if (o.f1) o.f1[idx] = e.f1;
+    if (o.f2) o.f2[idx] = e.f2;
+  }
+  if (o.flags) o.flags[idx] = e.flags;
 }
 
 // Heavy pass: main components (FP64) and the rare member segments (elliptical, point,
@@ -231,38 +281,77 @@ __global__ __launch_bounds__(256) void k_maps(const MapsArgs A) {
     seg_loop<SEG_CPJE, D3, PPL>(A.m64 + mo, nullptr, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], px, py, acc, A.qd);
     seg_loop<SEG_CSIE, D3, PPL>(A.m64 + mo, nullptr, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], px, py, acc, A.qd);
   }
-  const MapsOut& o = A.out;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     long long p = base + (long long)k * 256;
     if (p >= P) break;
-    size_t idx = (size_t)s * P + p;
-    Epi e;
-    epilogue<D3>(px[k], py[k], A.a, acc[k], e);
-    if (o.ax) o.ax[idx] = acc[k].ax;
-    if (o.ay) o.ay[idx] = acc[k].ay;
-    if (o.p11) o.p11[idx] = acc[k].h11;
-    if (o.p12) o.p12[idx] = acc[k].h12;
-    if (o.p22) o.p22[idx] = acc[k].h22;
-    if (o.kappa) o.kappa[idx] = e.kappa;
-    if (o.g1) o.g1[idx] = e.g1;
-    if (o.g2) o.g2[idx] = e.g2;
-    if (o.detA) o.detA[idx] = e.detA;
-    if (o.mu) o.mu[idx] = e.mu;
-    if (o.bx) o.bx[idx] = e.bx;
-    if (o.by) o.by[idx] = e.by;
-    if (o.e1) o.e1[idx] = e.e1;
-    if (o.e2) o.e2[idx] = e.e2;
-    if (D3) {
-      if (o.t111) o.t111[idx] = acc[k].t111;
-      if (o.t112) o.t112[idx] = acc[k].t112;
-      if (o.t122) o.t122[idx] = acc[k].t122;
-      if (o.t222) o.t222[idx] = acc[k].t222;
-      if (o.f1) o.f1[idx] = e.f1;
-      if (o.f2) o.f2[idx] = e.f2;
-    }
-    if (o.flags) o.flags[idx] = e.flags;
+    store_point<D3>(A, (size_t)s * P + p, px[k], py[k], acc[k]);
   }
+}
+
+// Lean pass over a grid in MIXED precision: one wave per TILE_W x (TILE_H TP) block of the
+// global grid (seg_loop_tile; a lane holds TP points of one column, TILE_H rows apart), the
+// blocks covering the grid rows of the points [p0, p0 + P).  Lanes' points outside those points
+// (or past the last column) take part in the member loops but store nothing.
+// Without third derivatives: two points per lane (each LDS record read serves both; the LDS
+// data path, which returns a broadcast record to every lane, is the other limit of this loop)
+// at 4 waves per SIMD (102 VGPRs), measured faster than one point per lane at 8 waves and four
+// points at 3 or 4; with third derivatives one point per lane at 7 waves.
+template <bool D3>
+static constexpr int MAPS_TP = D3 ? 1 : 2;
+
+template <bool D3>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D3 ? 7 : 4, 8))) void k_maps_tile(const MapsArgs A) {
+  constexpr int TP = MAPS_TP<D3>, TH = TILE_H * TP;
+  __shared__ float dsh[4][64 * TILE_LSTRIDE<SEG_CPJE, D3>];
+  const int s = blockIdx.y;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const PointsSpec& ps = A.pts;
+  const long long nx = ps.nx, P = ps.P;
+  const long long tiles_x = (nx + TILE_W - 1) / TILE_W;
+  const long long t = (long long)blockIdx.x * 4 + wave;
+  const long long tr = (ps.p0 / nx) / TH + t / tiles_x, tc = t % tiles_x;
+  const long long i = tc * TILE_W + lane % TILE_W;
+  bool active[TP], any = false;
+  long long p[TP];
+  TileLane<TP> L;
+  L.X = ps.x0 + (double)(tc * TILE_W + TILE_W / 2) * ps.h;
+  L.Y = ps.y0 + (double)(tr * TH + TH / 2) * ps.h;
+  L.u = (float)(((double)(lane % TILE_W) - 0.5 * (TILE_W - 1)) * ps.h);
+  L.hwx = 0.5 * (TILE_W - 1) * ps.h * (1.0 + 1e-6);
+  L.hwy = 0.5 * (TH - 1) * ps.h * (1.0 + 1e-6);
+  L.px = ps.x0 + ((double)i + 0.5) * ps.h;
+  L.dsh = dsh[wave];
+#pragma unroll
+  for (int k = 0; k < TP; ++k) {
+    const long long jr = lane / TILE_W + k * TILE_H, j = tr * TH + jr;
+    const long long q = j * nx + i;
+    active[k] = i < nx && q >= ps.p0 && q < ps.p0 + P;
+    any = any || active[k];
+    p[k] = active[k] ? q - ps.p0 : 0;
+    L.v[k] = (float)(((double)jr - 0.5 * (TH - 1)) * ps.h);
+    L.py[k] = ps.y0 + ((double)j + 0.5) * ps.h;
+  }
+  if (__ballot(any) == 0) return;           // a whole block outside the call's points
+  Acc acc[TP];
+#pragma unroll
+  for (int k = 0; k < TP; ++k) {
+    acc[k].zero();
+    if (A.part) {
+      const double* pq = A.part + (size_t)s * NPART * P + p[k];
+      acc[k].ax = pq[0]; acc[k].ay = pq[P]; acc[k].h11 = pq[2 * P]; acc[k].h12 = pq[3 * P]; acc[k].h22 = pq[4 * P];
+      if (D3) { acc[k].t111 = pq[5 * P]; acc[k].t112 = pq[6 * P]; acc[k].t122 = pq[7 * P]; acc[k].t222 = pq[8 * P]; }
+      acc[k].flags = ((const int*)(A.part + (size_t)A.S * NPART * P))[(size_t)s * P + p[k]];
+    }
+  }
+  const SegOff& so = A.m.seg;
+  const size_t mo = (size_t)s * A.m.n_mem;
+  seg_loop_tile<SEG_CPJE, D3, TP>(A.m32 + mo, A.m64 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], L, acc, A.qd);
+  seg_loop_tile<SEG_CSIE, D3, TP>(A.m32 + mo, A.m64 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], L, acc, A.qd);
+#pragma unroll
+  for (int k = 0; k < TP; ++k)
+    if (active[k]) store_point<D3>(A, (size_t)s * P + p[k], L.px, L.py[k], acc[k]);
 }
 
 template <bool MIXED, bool D3, int PPL>
@@ -272,6 +361,15 @@ static void launch_maps_t(const MapsArgs& a, int which, hipStream_t st) {
     if (a.m.has_enfw) hipLaunchKernelGGL((k_heavy<MIXED, D3, 0>), g1, dim3(256), 0, st, a);
     else if (a.m.has_rare) hipLaunchKernelGGL((k_heavy<MIXED, D3, 1>), g1, dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_heavy<MIXED, D3, 2>), g1, dim3(256), 0, st, a);
+    return;
+  }
+  if (MIXED && a.pts.grid) {
+    const long long TH = TILE_H * MAPS_TP<D3>;
+    const long long nx = a.pts.nx, tiles_x = (nx + TILE_W - 1) / TILE_W;
+    const long long tr0 = (a.pts.p0 / nx) / TH, tr1 = ((a.pts.p0 + a.pts.P - 1) / nx) / TH;
+    const long long tiles = tiles_x * (tr1 - tr0 + 1);
+    dim3 grid((unsigned)((tiles + 3) / 4), a.S);
+    hipLaunchKernelGGL((k_maps_tile<D3>), grid, dim3(256), 0, st, a);
     return;
   }
   long long per_block = 256LL * PPL;
@@ -292,10 +390,7 @@ hipError_t launch_maps(const DevModel& m, const MainRec* mains, const MemRec32* 
     launch_maps_t<MX, D, P>(a, which, st);    \
     return hipGetLastError();                 \
   }
-  LF_DISPATCH(true, false, 1) LF_DISPATCH(true, false, 2) LF_DISPATCH(true, false, 4)
-  LF_DISPATCH(false, false, 1) LF_DISPATCH(false, false, 2)
-  LF_DISPATCH(true, true, 1) LF_DISPATCH(true, true, 2)
-  LF_DISPATCH(false, true, 1)
+  LF_DISPATCH(true, false, 1) LF_DISPATCH(false, false, 1) LF_DISPATCH(true, true, 1) LF_DISPATCH(false, true, 1)
 #undef LF_DISPATCH
   return hipErrorInvalidValue;
 }

@@ -225,6 +225,210 @@ __device__ __forceinline__ void seg_loop(const R* __restrict__ rec, const MemRec
 }
 
 
+// ---------------------------------------------------------------------------------------
+// Grid tiles of the FP32 member path.  A wave owns a TILE_W x TILE_H block of grid points
+// aligned to the global grid; its lanes evaluate the member terms at X + (u, v), X the block
+// centre (FP64) and (u, v) the lane's offset from it rounded to FP32 (|u|, |v| <= 7.5 h, so
+// the rounding moves a lane by at most 2^-24 7.5 h, the same for every member).  The offset of
+// a member from X, D = c - X, is formed once per wave in FP64 and rounded to FP32, so a lane's
+// offset is dx = u - D_x: one FP32 subtraction per coordinate, with an error of a few ulp of
+// |dx| + |u| (the block is small next to the near-field radius of the members it holds).
+// ---------------------------------------------------------------------------------------
+static constexpr int TILE_W = 16, TILE_H = 4;
+
+// A lane of a tile: TP points of one column, TILE_H rows apart.
+template <int TP>
+struct TileLane {
+  float u, v[TP];      // offsets from the block centre (FP32)
+  double X, Y;         // block centre (FP64)
+  double hwx, hwy;     // half extent of the block's lane points about the centre
+  double px, py[TP];   // the lane's grid points (FP64)
+  float* dsh;          // this wave's 64 member records in LDS
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS record of one member for one wave: its offset from the block centre and the constants of
+// the evaluation the wave uses for it.  The member loop reads them into VGPRs: on gfx950 a VALU
+// instruction with an SGPR operand issues at about half the rate of one whose operands are all
+// VGPRs, so constants held in SGPRs (scalar loads) would halve the rate of every instruction
+// that reads one.  Floats: Dx, Dy, then either the closed form's s^2, a^2, s, a, b (a - s),
+// a + s, b, or (circular dPIE members at least FAR_K cut radii from the whole block, without
+// third derivatives) the twelve far-field coefficients fm, fw.
+struct MemL {
+  float b, s, a, s2, a2, bd, apls;
+};
+template <int SEG, bool D3>
+static constexpr bool TILE_FAR = SEG == SEG_CPJE && !D3;
+template <int SEG, bool D3>
+static constexpr int TILE_LSTRIDE = TILE_FAR<SEG, D3> ? 16 : 12;
+
+// closed form (three transcendentals per point)
+template <int SEG, bool D3, int TP>
+__device__ __forceinline__ void tile_term_l(const float* l, const TileLane<TP>& L, Run32 (&ps)[TP]) {
+  const float4 q0 = *(const float4*)l, q1 = *(const float4*)(l + 4);
+  MemL r;
+  r.s2 = q0.z; r.a2 = q0.w; r.s = q1.x; r.a = q1.y; r.bd = q1.z; r.apls = q1.w;
+  r.b = (SEG == SEG_CPJE && !D3) ? 0.f : l[8];
+  const float dx = L.u - q0.x;
+#pragma unroll
+  for (int k = 0; k < TP; ++k) {
+    const float dy = L.v[k] - q0.y;
+    const float r2 = fmaf(dx, dx, dy * dy);
+    float m, w, wp;
+    circ_mw<SEG, D3>(r, r2, m, w, wp);
+    run_add<D3>(dx, dy, r2, m, w, wp, ps[k]);
+  }
+}
+
+// far-field expansion of a circular dPIE (one transcendental per point): with t = 1/r and
+// u = t^2, m = u (fm0 + t (fm1 + u (fm2 + u (fm3 + u (fm4 + u fm5))))), w = u^2 (fw0 + t (fw1 + ...))
+template <int TP>
+__device__ __forceinline__ void tile_term_far(const float* l, const TileLane<TP>& L, Run32 (&ps)[TP]) {
+  const float4 q0 = *(const float4*)l, q1 = *(const float4*)(l + 4), q2 = *(const float4*)(l + 8),
+               q3 = *(const float4*)(l + 12);
+  const float dx = L.u - q0.x;
+#pragma unroll
+  for (int k = 0; k < TP; ++k) {
+    const float dy = L.v[k] - q0.y;
+    const float r2 = fmaf(dx, dx, dy * dy);
+    const float t = frsq(r2), uu = t * t;
+    float pm = fmaf(uu, q1.w, q1.z);
+    pm = fmaf(uu, pm, q1.y);
+    pm = fmaf(uu, pm, q1.x);
+    pm = fmaf(uu, pm, q0.w);
+    pm = fmaf(t, pm, q0.z);
+    float pw = fmaf(uu, q3.y, q3.x);
+    pw = fmaf(uu, pw, q2.w);
+    pw = fmaf(uu, pw, q2.z);
+    pw = fmaf(uu, pw, q2.y);
+    pw = fmaf(t, pw, q2.x);
+    run_add<false>(dx, dy, r2, uu * pm, (uu * uu) * pw, 0.f, ps[k]);
+  }
+}
+
+// Members are taken in blocks of 64.  Lane j of the wave takes member j of the block: its
+// offset D from the block centre (FP64, rounded to FP32), whether its near-field disc (radius^2
+// rn2, with a relative margin of 1e-5 for the FP32 rounding of a lane's r^2) meets the wave's
+// block, and whether the whole block lies at least FAR_K cut radii away (far field).  Ballots
+// give the wave's near, far and closed-form sets, and the records are written to LDS in that
+// order: far members first (in member order), then closed-form ones, so that every run of
+// LF_CHUNK members has one evaluation (full runs unrolled).  Runs are counted from the start of
+// each set; near-field members are evaluated after the block lane by lane, exactly as in
+// seg_loop: in FP64 from the FP64 record where the lane's r^2 < rn2, otherwise in FP32 from the
+// pair offsets, each term added to the FP64 accumulators.  Every set depends only on the global
+// block and the member, so results do not depend on the launch shape.
+template <int SEG, bool D3, int TP>
+__device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, const MemRec64* __restrict__ near64,
+                                              int lo, int hi, const TileLane<TP>& L, Acc (&acc)[TP],
+                                              const Quad& qd) {
+  static_assert(SEG == SEG_CPJE || SEG == SEG_CSIE, "tiles hold the circular segments");
+  constexpr int LS = TILE_LSTRIDE<SEG, D3>;
+  constexpr bool FAR = TILE_FAR<SEG, D3>;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int b0 = lo; b0 < hi; b0 += 64) {
+    const int nb = min(64, hi - b0);
+    bool flag = false, far = false;
+    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
+    if (lane < nb) {
+      const double cx = near64[b0 + lane].x, cy = near64[b0 + lane].y;
+      const double ddx = cx - L.X, ddy = cy - L.Y;
+      const double ex = fmax(fabs(ddx) - L.hwx, 0.0), ey = fmax(fabs(ddy) - L.hwy, 0.0);
+      const double e2 = fma(ex, ex, ey * ey);
+      const MemRec32& r = rec[b0 + lane];
+      flag = e2 < (double)r.rn2 * (1.0 + 1e-5);
+      const double ar = near64[b0 + lane].a;
+      far = FAR && !flag && ar <= FAR_AMAX && e2 >= FAR_K * FAR_K * ar * ar;
+      if (far) {
+        w0 = make_float4((float)ddx, (float)ddy, r.fm[0], r.fm[1]);
+        w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fm[5]);
+        w2 = make_float4(r.fw[0], r.fw[1], r.fw[2], r.fw[3]);
+        w3 = make_float4(r.fw[4], r.fw[5], 0.f, 0.f);
+      } else {
+        w0 = make_float4((float)ddx, (float)ddy, r.s2, r.a2);
+        w1 = make_float4(r.s, r.a, r.bd, r.apls);
+        w2 = make_float4(r.b, 0.f, 0.f, 0.f);
+      }
+    }
+    const bool closed = lane < nb && !flag && !far;
+    const unsigned long long nmask = __ballot(flag), fmask = __ballot(far), cmask = __ballot(closed);
+    const int nfar = __popcll(fmask), ncl = __popcll(cmask);
+    const int slot = far ? __popcll(fmask & below) : nfar + __popcll(cmask & below);
+    wave_sync();                        // the previous block's reads precede these writes
+    if (far || closed) {
+      float* lw = L.dsh + LS * slot;
+      *(float4*)lw = w0;
+      *(float4*)(lw + 4) = w1;
+      *(float4*)(lw + 8) = w2;
+      if (LS > 12) *(float4*)(lw + 12) = w3;
+    }
+    wave_sync();
+    if constexpr (FAR) {
+      for (int c0 = 0; c0 < nfar; c0 += LF_CHUNK) {
+        const int n = min(LF_CHUNK, nfar - c0);
+        const float* lr = L.dsh + LS * c0;
+        Run32 ps[TP];
+#pragma unroll
+        for (int k = 0; k < TP; ++k) run_zero<false>(ps[k]);
+        if (n == LF_CHUNK) {
+#pragma unroll
+          for (int k = 0; k < LF_CHUNK; ++k) tile_term_far<TP>(lr + LS * k, L, ps);
+        } else {
+          for (int k = 0; k < n; ++k) tile_term_far<TP>(lr + LS * k, L, ps);
+        }
+#pragma unroll
+        for (int k = 0; k < TP; ++k) run_flush<false>(ps[k], acc[k]);
+      }
+    }
+    for (int c0 = nfar; c0 < nfar + ncl; c0 += LF_CHUNK) {
+      const int n = min(LF_CHUNK, nfar + ncl - c0);
+      const float* lr = L.dsh + LS * c0;
+      Run32 ps[TP];
+#pragma unroll
+      for (int k = 0; k < TP; ++k) run_zero<D3>(ps[k]);
+      if (!D3 && TP == 1 && n == LF_CHUNK) {
+#pragma unroll
+        for (int k = 0; k < LF_CHUNK; ++k) tile_term_l<SEG, D3, TP>(lr + LS * k, L, ps);
+      } else {
+        for (int k = 0; k < n; ++k) tile_term_l<SEG, D3, TP>(lr + LS * k, L, ps);
+      }
+#pragma unroll
+      for (int k = 0; k < TP; ++k) run_flush<D3>(ps[k], acc[k]);
+    }
+    // near-field members of the block, lane by lane
+    unsigned long long fm = nmask;
+    while (fm) {
+      const int h = b0 + __builtin_ctzll(fm);
+      fm &= fm - 1;
+      const MemRec32 r = rec[h];
+      float xh, xl;
+      split32(L.px, xh, xl);
+      const float dx = off32(xh, xl, r.xh, r.xl);
+#pragma unroll
+      for (int k = 0; k < TP; ++k) {
+        float yh, yl;
+        split32(L.py[k], yh, yl);
+        const float dy = off32(yh, yl, r.yh, r.yl);
+        if (fmaf(dx, dx, dy * dy) < r.rn2) {
+          const MemRec64 q = near64[h];
+          Term<double> t;
+          if (seg_term<SEG, D3>(q, L.px - q.x, L.py[k] - q.y, qd, t)) add<D3>(acc[k], t);
+          else acc[k].flags |= FL_SINGULAR;
+        } else {
+          Term<float> t;
+          seg_term<SEG, D3>(r, dx, dy, qd, t);
+          add<D3>(acc[k], t);
+        }
+      }
+    }
+  }
+}
+
 // All components of one sample in FP64 at one point (main halos + every member segment).
 struct Plane64 {
   const MainRec* mains;

@@ -26,7 +26,7 @@ def _write_csv(path, fields, rows):
 def _pmc_rows(counter, lean_parts, copies):
     """Counter rows as rocprofv3 writes them: one row per (dispatch, instance); the summary adds
     the instances of a dispatch."""
-    lean = "void lf::k_maps<true, false, 1>(lf::MapsArgs)"
+    lean = "void lf::k_maps_tile<false>(lf::MapsArgs)"
     rows, d = [], 0
     for parts in lean_parts:
         d += 1
@@ -72,21 +72,33 @@ def test_pmc_summary_calibrates_on_the_copy(tmp_path, capsys):
 
 def test_stats_summary_lists_every_kernel(tmp_path, capsys):
     fields = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]
-    rows = [{"Name": "void lf::k_maps<true, false, 1>(lf::MapsArgs)", "Calls": 4, "TotalDurationNs": 4.4e6,
+    rows = [{"Name": "void lf::k_maps_tile<false>(lf::MapsArgs)", "Calls": 4, "TotalDurationNs": 4.4e6,
              "AverageNs": 1.1e6, "Percentage": 80.0},
             {"Name": "lf::k_expand(...)", "Calls": 2, "TotalDurationNs": 1.1e6, "AverageNs": 5.5e5,
              "Percentage": 20.0}]
     _write_csv(str(tmp_path / "s" / "x" / "step_kernel_stats.csv"), fields, rows)
     bench.summarize_profiles("stats", [str(tmp_path / "s")])
     lines = capsys.readouterr().out.strip().splitlines()
-    assert lines[0].split() == ["kernel", "calls", "avg_us", "total_ms", "pct"]
-    first = lines[1].split()
+    assert lines[0] == "# source_sha256: " + bench.kernel_source_hash()
+    assert lines[1].split() == ["kernel", "calls", "avg_us", "total_ms", "pct"]
+    first = lines[2].split()
     assert first[-4:] == ["4", "1100.00", "4.400", "80.00"]
-    assert len(lines) == 3
+    assert len(lines) == 4
+
+
+def test_profile_timing_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
+    f = tmp_path / "stats.txt"
+    row = "void %s(lf::MapsArgs)" % bench.LEAN_KERNEL
+    f.write_text("# header\n# source_sha256: %s\nkernel calls avg_us total_ms pct\n%-60s %7d %12.2f %12.3f %7.2f\n"
+                 % (bench.kernel_source_hash(), row, 70, 726.39, 50.847, 25.84))
+    monkeypatch.setattr(bench, "STATS_FILE", str(f))
+    assert bench.recorded_profile_ms() == pytest.approx(0.72639)
+    f.write_text(f.read_text().replace(bench.kernel_source_hash(), "0" * 64))
+    assert bench.recorded_profile_ms() is None
 
 
 def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
-    good = {"kernel": "lf::k_maps<true, false, 1>", "source_sha256": bench.kernel_source_hash(),
+    good = {"kernel": "lf::k_maps_tile<false>", "source_sha256": bench.kernel_source_hash(),
             "fetch_bytes_per_launch": 3.0e8, "write_bytes_per_launch": 1.5e8}
     f = tmp_path / "traffic.txt"
     f.write_text("# header\n" + json.dumps(good) + "\n")
@@ -104,7 +116,7 @@ def test_traffic_is_reported_only_for_the_recorded_sources(tmp_path, monkeypatch
 def test_committed_traffic_record_is_well_formed():
     with open(bench.TRAFFIC_FILE) as fh:
         rec = json.loads([ln for ln in fh if ln.startswith("{")][-1])
-    assert rec["kernel"] == "lf::k_maps<true, false, 1>"
+    assert rec["kernel"] == "lf::k_maps_tile<false>"
     assert rec["fetch_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0
     for k in ("copy_factor_fetch", "copy_factor_write"):
         assert 0.5 <= rec[k] <= 4.0
