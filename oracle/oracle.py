@@ -13,7 +13,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lf_oracle.cpp")
-_SO = os.path.join(_HERE, "liblf_oracle.so")
+# LF_ORACLE_SANITIZE=1: a separate build with AddressSanitizer and UndefinedBehaviorSanitizer
+# (run the Python process with the sanitizer runtimes preloaded, see sanitize.sh)
+_SAN = os.environ.get("LF_ORACLE_SANITIZE") == "1"
+_SO = os.path.join(_HERE, "liblf_oracle_san.so" if _SAN else "liblf_oracle.so")
 _lib = None
 
 FIELDS = ("x", "y", "b", "q", "pa", "s", "a")
@@ -26,8 +29,10 @@ def build(force: bool = False) -> str:
     """Compile the oracle with g++ (IEEE double, no fast-math)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp%d" % os.getpid()
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+               "-g"] if _SAN else []
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", "-o", tmp, _SRC, "-lpthread"])
+                               "-ffp-contract=off"] + san + ["-o", tmp, _SRC, "-lpthread"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -67,7 +72,10 @@ def _i32(a):
 
 
 def nthreads_default():
-    return max(1, min(16, os.cpu_count() or 1))
+    """Worker threads: the CPUs this process may use, at most its CPU share (OMP_NUM_THREADS, or 16
+    where that is unset: one GPU's share of a GPU host)."""
+    share = int(os.environ.get("OMP_NUM_THREADS") or 16)
+    return max(1, min(share, len(os.sched_getaffinity(0))))
 
 
 # --------------------------------------------------------------------------- cosmology
