@@ -748,7 +748,7 @@ struct ImgInfo {
 static int chi2_one(const double* tab, int H, const double* th, const int* fam, const double* s1,
                     const double* s2, const double* phi, int n, const double* afam, int n_fam,
                     int img_mode, double newton_tol, double* chi_src, double* chi_img,
-                    double* bmod, double* tmod, ImgInfo* info = nullptr) {
+                    double* bmod, double* tmod, ImgInfo* info = nullptr, int* img_flags = nullptr) {
   int flags = 0;
   std::vector<double> bo(2 * n), W(3 * n), M(3 * n), Si(3 * n), detA0(n), csrc_i(n);
   if (info) { info->h.assign(9 * n, 0.0); info->ok.assign(n, 0); }
@@ -842,6 +842,7 @@ static int chi2_one(const double* tab, int H, const double* th, const int* fam, 
     tmod[2 * i] = tx; tmod[2 * i + 1] = ty;
     if (!conv) flags |= F_NOCONV;
     if (reject) flags |= F_REJECT;
+    if (img_flags) img_flags[i] = (conv ? 0 : F_NOCONV) | (reject ? F_REJECT : 0);
     if (!conv || reject) {
       tot_img += csrc_i[i];
     } else {
@@ -976,13 +977,13 @@ int orc_chi2_batch(const double* tabs, int S, int H, const double* th, const int
                    const double* s1, const double* s2, const double* phi, int n,
                    const double* afam, int n_fam, int img_mode, double newton_tol,
                    double* chi_src, double* chi_img, int* flags, double* bmod, double* tmod,
-                   int nthreads) {
+                   int* img_flags, int nthreads) {
   parallel_for(S, nthreads, [&](int lo, int hi) {
     for (int s = lo; s < hi; ++s) {
       double ci = 0;
       flags[s] = chi2_one(tabs + (size_t)s * H * 8, H, th, fam, s1, s2, phi, n, afam, n_fam, img_mode,
                           newton_tol, chi_src + s, &ci, bmod + (size_t)s * n_fam * 2,
-                          tmod + (size_t)s * n * 2);
+                          tmod + (size_t)s * n * 2, nullptr, img_flags + (size_t)s * n);
       if (img_mode) chi_img[s] = ci;
     }
   });
@@ -1156,92 +1157,102 @@ static int find_images(const Lens& L, const double* W /*[n_src * nw]*/, int nw,
   parallel_for((int)NV, nthreads, [&](int lo, int hi) {
     for (int v = lo; v < hi; ++v) vertex_alphas(L, vx[v], vy[v], &val_al[(size_t)v * 2 * nw]);
   });
-  int ncand_total = 0;
-  for (int s = 0; s < n_src; ++s) {
-    const double* w = W + (size_t)s * nw;
+  // sources are independent items: each thread takes a range of them; candidates are listed
+  // afterwards in source order
+  std::vector<std::vector<int>> src_tris(n_src), src_status(n_src);
+  parallel_for(n_src, nthreads, [&](int s_lo, int s_hi) {
     std::vector<double> bx(NV), by(NV);
-    for (size_t v = 0; v < NV; ++v) {
-      double ex = vx[v], ey = vy[v];
-      for (int j = 0; j < nw; ++j) { ex -= w[j] * val_al[v * 2 * nw + 2 * j]; ey -= w[j] * val_al[v * 2 * nw + 2 * j + 1]; }
-      bx[v] = ex; by[v] = ey;
-    }
-    double sx = beta[2 * s], sy = beta[2 * s + 1];
-    // candidates in triangle order
-    std::vector<int> tris;
-    for (int j = 0; j + 1 < ny; ++j)
-      for (int i = 0; i + 1 < nx; ++i) {
-        size_t v00 = (size_t)j * nx + i, v10 = v00 + 1, v01 = v00 + nx, v11 = v01 + 1;
-        size_t vs[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
-        for (int k = 0; k < 2; ++k) {
-          double B[6];
-          double mnx = 1e300, mxx = -1e300, mny = 1e300, mxy = -1e300;
-          for (int t = 0; t < 3; ++t) {
-            B[2 * t] = bx[vs[k][t]]; B[2 * t + 1] = by[vs[k][t]];
-            mnx = std::min(mnx, B[2 * t]); mxx = std::max(mxx, B[2 * t]);
-            mny = std::min(mny, B[2 * t + 1]); mxy = std::max(mxy, B[2 * t + 1]);
+    for (int s = s_lo; s < s_hi; ++s) {
+      const double* w = W + (size_t)s * nw;
+      for (size_t v = 0; v < NV; ++v) {
+        double ex = vx[v], ey = vy[v];
+        for (int j = 0; j < nw; ++j) { ex -= w[j] * val_al[v * 2 * nw + 2 * j]; ey -= w[j] * val_al[v * 2 * nw + 2 * j + 1]; }
+        bx[v] = ex; by[v] = ey;
+      }
+      double sx = beta[2 * s], sy = beta[2 * s + 1];
+      // candidates in triangle order
+      std::vector<int> tris;
+      for (int j = 0; j + 1 < ny; ++j)
+        for (int i = 0; i + 1 < nx; ++i) {
+          size_t v00 = (size_t)j * nx + i, v10 = v00 + 1, v01 = v00 + nx, v11 = v01 + 1;
+          size_t vs[2][3] = {{v00, v10, v11}, {v00, v11, v01}};
+          for (int k = 0; k < 2; ++k) {
+            double B[6];
+            double mnx = 1e300, mxx = -1e300, mny = 1e300, mxy = -1e300;
+            for (int t = 0; t < 3; ++t) {
+              B[2 * t] = bx[vs[k][t]]; B[2 * t + 1] = by[vs[k][t]];
+              mnx = std::min(mnx, B[2 * t]); mxx = std::max(mxx, B[2 * t]);
+              mny = std::min(mny, B[2 * t + 1]); mxy = std::max(mxy, B[2 * t + 1]);
+            }
+            if (sx < mnx || sx > mxx || sy < mny || sy > mxy) continue;   // exact prefilter
+            if (tri_contains(B, sx, sy)) tris.push_back(2 * (j * (nx - 1) + i) + k);
           }
-          if (sx < mnx || sx > mxx || sy < mny || sy > mxy) continue;   // exact prefilter
-          if (tri_contains(B, sx, sy)) tris.push_back(2 * (j * (nx - 1) + i) + k);
         }
-      }
-    // polish each candidate (FP64 Newton, Sec. 3.5), accept, merge
-    int cnt = 0, fl = 0;
-    std::vector<double> acc_t;
-    for (size_t c = 0; c < tris.size(); ++c) {
-      int tri = tris[c], cell = tri / 2, k = tri % 2;
-      int i = cell % (nx - 1), j = cell / (nx - 1);
-      size_t v00 = (size_t)j * nx + i, v10 = v00 + 1, v01 = v00 + nx, v11 = v01 + 1;
-      size_t vv[3];
-      if (k == 0) { vv[0] = v00; vv[1] = v10; vv[2] = v11; } else { vv[0] = v00; vv[1] = v11; vv[2] = v01; }
-      double B[6], T[6];
-      for (int t = 0; t < 3; ++t) { B[2 * t] = bx[vv[t]]; B[2 * t + 1] = by[vv[t]]; T[2 * t] = vx[vv[t]]; T[2 * t + 1] = vy[vv[t]]; }
-      // barycentric initial guess
-      double area = (B[2] - B[0]) * (B[5] - B[1]) - (B[3] - B[1]) * (B[4] - B[0]);
-      double l1 = ((B[4] - B[2]) * (sy - B[3]) - (B[5] - B[3]) * (sx - B[2])) / area;
-      double l2 = ((B[0] - B[4]) * (sy - B[5]) - (B[1] - B[5]) * (sx - B[4])) / area;
-      double l3 = 1 - l1 - l2;
-      double tx0 = l1 * T[0] + l2 * T[2] + l3 * T[4], ty0 = l1 * T[1] + l2 * T[3] + l3 * T[5];
-      double tx = tx0, ty = ty0, A[4] = {1, 0, 0, 1};
-      bool conv = false;
-      for (int it = 0; it <= 30; ++it) {
-        double ex, ey;
-        lens_eval(L, w, tx, ty, &ex, &ey, A);
-        double rx = sx - ex, ry = sy - ey;
-        if (std::fabs(rx) < 1e-10 && std::fabs(ry) < 1e-10) { conv = true; break; }
-        if (it == 30) break;
-        double det = A[0] * A[3] - A[1] * A[2];
-        tx += (A[3] * rx - A[1] * ry) / det;
-        ty += (-A[2] * rx + A[0] * ry) / det;
-      }
-      int status;
-      if (!conv) status = 1;
-      else if (std::fabs(tx - tx0) > 2 * h || std::fabs(ty - ty0) > 2 * h) status = 2;
-      else {
-        bool dup = false;
-        for (size_t m = 0; m < acc_t.size(); m += 2) {
-          double dx = tx - acc_t[m], dy = ty - acc_t[m + 1];
-          if (std::sqrt(dx * dx + dy * dy) < 1e-6) { dup = true; break; }
+      // polish each candidate (FP64 Newton, Sec. 3.5), accept, merge
+      int cnt = 0, fl = 0;
+      std::vector<double> acc_t;
+      for (size_t c = 0; c < tris.size(); ++c) {
+        int tri = tris[c], cell = tri / 2, k = tri % 2;
+        int i = cell % (nx - 1), j = cell / (nx - 1);
+        size_t v00 = (size_t)j * nx + i, v10 = v00 + 1, v01 = v00 + nx, v11 = v01 + 1;
+        size_t vv[3];
+        if (k == 0) { vv[0] = v00; vv[1] = v10; vv[2] = v11; } else { vv[0] = v00; vv[1] = v11; vv[2] = v01; }
+        double B[6], T[6];
+        for (int t = 0; t < 3; ++t) { B[2 * t] = bx[vv[t]]; B[2 * t + 1] = by[vv[t]]; T[2 * t] = vx[vv[t]]; T[2 * t + 1] = vy[vv[t]]; }
+        // barycentric initial guess
+        double area = (B[2] - B[0]) * (B[5] - B[1]) - (B[3] - B[1]) * (B[4] - B[0]);
+        double l1 = ((B[4] - B[2]) * (sy - B[3]) - (B[5] - B[3]) * (sx - B[2])) / area;
+        double l2 = ((B[0] - B[4]) * (sy - B[5]) - (B[1] - B[5]) * (sx - B[4])) / area;
+        double l3 = 1 - l1 - l2;
+        double tx0 = l1 * T[0] + l2 * T[2] + l3 * T[4], ty0 = l1 * T[1] + l2 * T[3] + l3 * T[5];
+        double tx = tx0, ty = ty0, A[4] = {1, 0, 0, 1};
+        bool conv = false;
+        for (int it = 0; it <= 30; ++it) {
+          double ex, ey;
+          lens_eval(L, w, tx, ty, &ex, &ey, A);
+          double rx = sx - ex, ry = sy - ey;
+          if (std::fabs(rx) < 1e-10 && std::fabs(ry) < 1e-10) { conv = true; break; }
+          if (it == 30) break;
+          double det = A[0] * A[3] - A[1] * A[2];
+          tx += (A[3] * rx - A[1] * ry) / det;
+          ty += (-A[2] * rx + A[0] * ry) / det;
         }
-        if (dup) { status = 3; fl |= F_MERGED; }
+        int status;
+        if (!conv) status = 1;
+        else if (std::fabs(tx - tx0) > 2 * h || std::fabs(ty - ty0) > 2 * h) status = 2;
         else {
-          status = 0;
-          acc_t.push_back(tx); acc_t.push_back(ty);
-          if (cnt < max_img) {
-            theta_out[((size_t)s * max_img + cnt) * 2] = tx;
-            theta_out[((size_t)s * max_img + cnt) * 2 + 1] = ty;
-            mu_out[(size_t)s * max_img + cnt] = 1.0 / (A[0] * A[3] - A[1] * A[2]);
-          } else fl |= F_OVERFLOW;
-          ++cnt;
+          bool dup = false;
+          for (size_t m = 0; m < acc_t.size(); m += 2) {
+            double dx = tx - acc_t[m], dy = ty - acc_t[m + 1];
+            if (std::sqrt(dx * dx + dy * dy) < 1e-6) { dup = true; break; }
+          }
+          if (dup) { status = 3; fl |= F_MERGED; }
+          else {
+            status = 0;
+            acc_t.push_back(tx); acc_t.push_back(ty);
+            if (cnt < max_img) {
+              theta_out[((size_t)s * max_img + cnt) * 2] = tx;
+              theta_out[((size_t)s * max_img + cnt) * 2 + 1] = ty;
+              mu_out[(size_t)s * max_img + cnt] = 1.0 / (A[0] * A[3] - A[1] * A[2]);
+            } else fl |= F_OVERFLOW;
+            ++cnt;
+          }
         }
+        src_tris[s].push_back(tri);
+        src_status[s].push_back(status);
       }
+      count[s] = cnt;
+      flags[s] = fl;
+    }
+  });
+  int ncand_total = 0;
+  for (int s = 0; s < n_src; ++s)
+    for (size_t c = 0; c < src_tris[s].size(); ++c) {
       if (ncand_total < max_cand) {
-        cand_src[ncand_total] = s; cand_tri[ncand_total] = tri; cand_status[ncand_total] = status;
+        cand_src[ncand_total] = s; cand_tri[ncand_total] = src_tris[s][c]; cand_status[ncand_total] = src_status[s][c];
       }
       ++ncand_total;
     }
-    count[s] = cnt;
-    flags[s] = fl;
-  }
   *n_cand = ncand_total;
   return 0;
 }
@@ -1564,11 +1575,16 @@ static double g_at(const double* tab, int H, double x, double y, int k, double d
 
 // Swallowtail refinement: Newton on (f_k, g_k) = 0 from the interpolated point; grad f from
 // the differences inside g (step 1e-3 h), grad g from central differences of g (step
-// 1e-2 h).  Status 0 converged (step < 1e-10") within h of the start, 1 no convergence in
-// 20 steps, 2 moved farther than h.
+// 1e-2 h).  The iteration stops after a step below 1e-10", after 20 steps, or as soon as it
+// leaves the disc of radius h about the start.  Status 0 converged (the last step is below
+// 1e-8") within h of the start, 1 no convergence, 2 left the disc.  The acceptance test sits
+// two decades above the stopping step: the finite-difference g leaves a rounding noise of up
+// to ~1e-9" under the steps, so a test at 1e-10" would decide by that noise; and an iteration
+// that wanders off is stopped while its path is still set by the lens rather than by rounding.
 static int swallowtail_newton(const SingGrid& G, int k, double* px, double* py) {
   double x = *px, y = *py, d = 1e-3 * G.h, dg = 1e-2 * G.h;
-  bool conv = false, umb = false;
+  bool umb = false;
+  double last = HUGE_VAL;
   for (int it = 0; it < 20; ++it) {
     double f, fx, fy, t0, t1, t2;
     double g = g_at(G.tab, G.H, x, y, k, d, &umb, &f, &fx, &fy);
@@ -1580,11 +1596,13 @@ static int swallowtail_newton(const SingGrid& G, int k, double* px, double* py) 
     double det = fx * gy - fy * gx;
     double sx = -(gy * f - fy * g) / det, sy = -(-gx * f + fx * g) / det;
     x += sx; y += sy;
-    if (!std::isfinite(x) || !std::isfinite(y)) break;
-    if (std::sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
+    if (!std::isfinite(x) || !std::isfinite(y)) { last = HUGE_VAL; break; }
+    last = std::sqrt(sx * sx + sy * sy);
+    if (last < 1e-10) break;
+    if (std::hypot(x - *px, y - *py) > G.h) break;
   }
-  int st = conv ? 0 : 1;
-  if (conv && std::hypot(x - *px, y - *py) > G.h) st = 2;
+  int st = last < 1e-8 ? 0 : 1;
+  if (std::hypot(x - *px, y - *py) > G.h) st = 2;
   if (umb) st |= 8;
   if (st == 0) { *px = x; *py = y; }
   return st;

@@ -223,12 +223,13 @@ def chi2_batch(tabs, cons, img_mode=False, newton_tol=1e-9, nthreads=None):
     fl = np.zeros(S, np.int32)
     bm = np.zeros((S, nf, 2))
     tm = np.zeros((S, n, 2))
+    ifl = np.zeros((S, n), np.int32)
     lib().orc_chi2_batch(_p(tabs), C.c_int(S), C.c_int(H), _p(th), _p(fam, C.c_int), _p(s1), _p(s2),
                          _p(phi), C.c_int(n), _p(afam), C.c_int(nf), C.c_int(1 if img_mode else 0),
                          C.c_double(newton_tol), _p(cs), _p(ci), _p(fl, C.c_int), _p(bm), _p(tm),
-                         C.c_int(nthreads or nthreads_default()))
+                         _p(ifl, C.c_int), C.c_int(nthreads or nthreads_default()))
     return {"chi2_src": cs, "chi2_img": ci if img_mode else None, "flags": fl,
-            "beta_model": bm, "theta_model": tm}
+            "beta_model": bm, "theta_model": tm, "img_flags": ifl if img_mode else None}
 
 
 def potential(tab, px, py, nthreads=None):

@@ -131,3 +131,57 @@ def test_find_images_multiplane_plane_counts(ctx, lf, orc, n_planes):
         assert np.all(np.abs(g["theta"][s, :n] - o["theta"][s, :n]).max(axis=1) <= tol), s
     for p in pl:
         p.release()
+
+
+def _golden_4096():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "mp_finder_4096.json")) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_find_images_multiplane_config4_full_size(ctx, lf, prec):
+    """The multi-plane workload at full size: 4096^2 grid over 200", three planes, sources at
+    their own redshifts.  Expected images come from the oracle (tests/golden/make_mp4096.py).
+    For the 60 caustic-margin-clear sources (image count unchanged under +-1e-4" shifts) counts
+    are bit-exact and positions agree within 1e-4" (MIXED) or 1e-9" + 4e-10" |mu| (FP64, the two
+    polishes stop at |d beta| < 1e-10").  The 60 sources the benchmark times are checked the
+    same way where they are margin-clear."""
+    import torch
+    gold = _golden_4096()
+    cfg = W.config4()
+    grid = cfg["grid"]
+    assert {k: grid[k] for k in gold["grid"]} == gold["grid"]
+    assert np.allclose(cfg["z_planes"], gold["z_planes"])
+    pl = _planes(ctx, cfg)
+    p = lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED
+    for key in ("clear", "bench_set"):
+        recs = gold[key]
+        idx = np.array([r["index"] for r in recs])
+        beta = np.asarray(cfg["src_cand"], np.float64)[idx]
+        zs = np.asarray(cfg["zs_cand"], np.float64)[idx]
+        assert np.array_equal(beta, np.array([r["beta"] for r in recs]))
+        assert np.array_equal(zs, np.array([r["z_s"] for r in recs]))
+        print("config-4 finder %s %s: %d sources" % (prec, key, len(recs)), flush=True)
+        g = ctx.find_images_mp(pl, cfg["z_planes"], torch.as_tensor(beta, device="cuda"), zs, grid,
+                               gold["max_img"], p)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in g.items()}
+        checked = 0
+        for s, r in enumerate(recs):
+            if key == "bench_set" and not r["margin_clear"]:
+                continue
+            n = r["count"]
+            assert g["count"][s] == n, (key, s, g["count"][s], n)
+            if n == 0:
+                continue
+            th, mu = np.array(r["theta"]), np.array(r["mu"])
+            tol = 1e-9 + 4e-10 * np.abs(mu) if prec == "fp64" else np.full(n, 1e-4)
+            d = np.abs(g["theta"][s, :n] - th).max(axis=1)
+            assert np.all(d <= tol), (key, s, d.max())
+            checked += 1
+        assert checked >= (50 if key == "clear" else 30)
+    assert sum(r["count"] for r in gold["clear"]) >= 80
+    for q in pl:
+        q.release()
