@@ -169,7 +169,9 @@ typedef struct lf_cons lf_cons;
 
 /* ---------------------------------------------------------------- context */
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the library's own
- * device allocations (0 = 90% of free memory).  Errors: LF_E_INVALID_ARG, LF_E_DEVICE. */
+ * device allocations (0 = 90% of free memory).  The environment variable LF_FIND_CAND_CAP,
+ * when set, fixes the image finders' candidate capacity per call (otherwise
+ * max(65536, 64 n_src)).  Errors: LF_E_INVALID_ARG, LF_E_DEVICE. */
 lf_status lf_init(lf_ctx** out, int32_t device, size_t hbm_budget_bytes);
 lf_status lf_shutdown(lf_ctx* ctx);
 const char* lf_last_error(const lf_ctx* ctx);
@@ -230,8 +232,7 @@ lf_status lf_constraints_observables(lf_ctx* ctx, lf_cons* c, const double* mag,
  * NULL with S = 1 when the model has no free field) and each point, the halo sum of
  * alpha and psi_ij (Sec. 2.1) and, when any of psi111..f2 is requested, the third
  * derivatives psi_ijk and the A3-line fields of Sec. 6.  a_dis > 0 sets beta, det A, mu.
- * Errors: LF_E_INVALID_ARG (no output requested, S < 1, bad points), LF_E_UNSUPPORTED
- * (third derivatives of an elliptical NFW). */
+ * Errors: LF_E_INVALID_ARG (no output requested, S < 1, bad points). */
 lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
                        const lf_points* pts, double a_dis, lf_prec prec, const lf_maps* out,
                        void* stream);
@@ -258,11 +259,21 @@ lf_status lf_chi2_batch(lf_ctx* ctx, const lf_model* m, const double* params, in
  * grad mu from the third derivatives; Eq. td_approx); mode 1: mu and the Fermat potential at
  * the accepted model image (Eq. time_delay), the expansions for images the Newton solve did
  * not accept.  These terms are evaluated in FP64 in both precisions.  Without such data the
- * call equals lf_chi2_batch.  Errors: those of lf_chi2_batch; LF_E_UNSUPPORTED for flux data
- * with an elliptical NFW component (its third derivatives are not provided). */
+ * call equals lf_chi2_batch.  Errors: those of lf_chi2_batch. */
 lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
                         const lf_cons* c, int32_t mode, lf_prec prec, double* chi2,
                         int32_t* flags, double* beta_model, double* terms, void* stream);
+
+/* Image-plane chi^2 (Sec. 3.1 Eq. chi2_img, solved as in Sec. 3.5) with its per-image results:
+ * the same launch and chi2 / flags / beta_model as lf_chi2_batch in mode 1, and per observed
+ * image theta_model [S * n_img * 2], the model image that image's Newton solve reached (its
+ * last iterate when the solve did not converge), and img_flags [S * n_img], that image's
+ * LF_F_NOCONV / LF_F_REJECT bits.  Both are device arrays in the constraint order given to
+ * lf_constraints_upload (sample-major), and either may be NULL.  Errors: those of
+ * lf_chi2_batch. */
+lf_status lf_chi2_images(lf_ctx* ctx, const lf_model* m, const double* params, int32_t S,
+                         const lf_cons* c, lf_prec prec, double* chi2, int32_t* flags,
+                         double* beta_model, double* theta_model, int32_t* img_flags, void* stream);
 
 /* Allocation-free lf_chi2_batch, for the callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
@@ -289,7 +300,10 @@ lf_status lf_chi2_batch_noalloc(lf_ctx* ctx, const lf_model* m, const double* pa
  * 2h of its start, and merged with an earlier image closer than 1e-6".
  * params: device row [n_free] or NULL; beta: device [n_src*2]; a_src: device [n_src].
  * Outputs (device): theta_out [n_src*max_img*2], mu_out [n_src*max_img], count_out [n_src]
- * (true count even when it exceeds max_img), flags [n_src] or NULL. */
+ * (true count even when it exceeds max_img), flags [n_src] or NULL.  Candidate triangles are
+ * kept per source in source order up to the call's candidate capacity; a source whose
+ * candidates do not all fit, and every source after it, gets count 0 and LF_F_OVERFLOW
+ * (the same sources on every run). */
 lf_status lf_find_images(lf_ctx* ctx, const lf_model* m, const double* params,
                          const double* beta, const double* a_src, int32_t n_src,
                          const lf_grid* grid, int32_t max_img, lf_prec prec, double* theta_out,
@@ -359,7 +373,8 @@ typedef struct {
  * (line fields); crossings come in the order row j, horizontal edges by i, vertical edges by
  * i, k = 1, 2.  refine != 0: each crossing is the root of f_k on its edge to a bracket below
  * tol arcsec (Illinois regula falsi, FP64, <= 100 steps), swallowtails are polished by Newton
- * on (f_k, g_k) = 0 (<= 20 steps to 1e-10"); refine = 0: linear interpolation.  Segments
+ * on (f_k, g_k) = 0 (<= 20 steps, stopping below 1e-10"; accepted when the last step is below
+ * 1e-8"); refine = 0: linear interpolation.  Segments
  * join the crossings of a cell (marching squares, the asymptotic decider in saddle cells);
  * cells whose eigenvector loop has orientation product -1 hold an umbilic, found by Newton
  * on (gamma_1, gamma_2) = 0 from the cell centre (<= 30 steps to 1e-10"), and an odd number
@@ -367,7 +382,7 @@ typedef struct {
  * turn fast within a cell, spurious entries are flagged by their status.  When counts[0] >
  * cap no segment, umbilic or swallowtail is produced.  params: device row [n_free] or NULL.
  * Errors: LF_E_INVALID_ARG (grid smaller than 2 x 2 or above 2^31 vertices, cap < 1, tol <=
- * 0, a NULL output), LF_E_UNSUPPORTED (elliptical NFW: no third derivatives). */
+ * 0, a NULL output). */
 lf_status lf_singularity_map(lf_ctx* ctx, const lf_model* m, const double* params, const lf_grid* grid,
                              lf_prec prec, int32_t refine, double tol, const lf_sing_out* out, void* stream);
 

@@ -205,6 +205,7 @@ extern "C" lf_status lf_init(lf_ctx** out, int32_t device, size_t hbm_budget_byt
     c->n_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
   }
+  if (const char* fc = std::getenv("LF_FIND_CAND_CAP")) c->find_cap = std::max(1LL, std::atoll(fc));
   // eNFW quadrature: Gauss-Legendre in t on [0, 1] with u = t^6 (weights carry du/dt)
   std::vector<double> x, w;
   gauss_legendre(LF_ENFW_NODES, x, w);
@@ -521,7 +522,6 @@ extern "C" lf_status lf_lens_maps(lf_ctx* ctx, const lf_model* M, const double* 
              out->gamma1 || out->gamma2 || out->detA || out->mu || out->beta_x || out->beta_y || out->e1 ||
              out->e2 || out->flags;
   if (!any) return ctx->fail(LF_E_INVALID_ARG, "no output requested");
-  if (d3 && lf_model_has_enfw(M)) return ctx->fail(LF_E_UNSUPPORTED, "third derivatives of elliptical NFW");
   if ((long long)S * ps.P > (1LL << 40)) return ctx->fail(LF_E_INVALID_ARG, "S * P too large");
   hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;

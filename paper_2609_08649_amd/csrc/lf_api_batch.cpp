@@ -15,9 +15,6 @@
 #include "lf_api_internal.h"
 #include "lf_chi2.h"
 
-lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, int S, const lf_cons* c,
-                          hipStream_t st, lf::Chi2Args& A, const char* tag);
-
 struct lf_batch {
   lf_ctx* ctx = nullptr;
   int mode = 0;

@@ -56,7 +56,7 @@ extern "C" lf_status lf_constraints_upload(lf_ctx* ctx, const double* theta, con
     si[3 * k + 2] = sn * sn * i1 + cs * cs * i2;
     sm[k] = std::max(sig1[i], sig2[i]);
   }
-  size_t bytes = sizeof(double) * (2 * n_img + 3 * n_img + n_img + n_fam) + sizeof(int) * (n_img + n_fam + 1);
+  size_t bytes = sizeof(double) * (2 * n_img + 3 * n_img + n_img + n_fam) + sizeof(int) * (2 * n_img + n_fam + 1);
   char* base = nullptr;
   lf_status st = ctx->dmalloc((void**)&base, bytes);
   if (st) { delete c; return st; }
@@ -67,12 +67,14 @@ extern "C" lf_status lf_constraints_upload(lf_ctx* ctx, const double* theta, con
   c->d_afam = c->d_sigmax + n_img;
   c->d_fam = (int*)(c->d_afam + n_fam);
   c->d_fam_start = c->d_fam + n_img;
+  c->d_order = c->d_fam_start + n_fam + 1;
   hipMemcpy(c->d_theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice);
   hipMemcpy(c->d_sinv, si.data(), sizeof(double) * si.size(), hipMemcpyHostToDevice);
   hipMemcpy(c->d_sigmax, sm.data(), sizeof(double) * sm.size(), hipMemcpyHostToDevice);
   hipMemcpy(c->d_afam, a_fam, sizeof(double) * n_fam, hipMemcpyHostToDevice);
   hipMemcpy(c->d_fam, fm.data(), sizeof(int) * n_img, hipMemcpyHostToDevice);
   hipMemcpy(c->d_fam_start, c->fam_start.data(), sizeof(int) * (n_fam + 1), hipMemcpyHostToDevice);
+  hipMemcpy(c->d_order, c->order.data(), sizeof(int) * n_img, hipMemcpyHostToDevice);
   *out = c;
   return LF_OK;
 }
@@ -123,7 +125,7 @@ extern "C" lf_status lf_constraints_release(lf_ctx* ctx, lf_cons* c) {
 }
 
 lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, int S, const lf_cons* c,
-                          hipStream_t st, lf::Chi2Args& A, const char* tag) {
+                          hipStream_t st, lf::Chi2Args& A, const char* tag, bool want_tmod) {
   // every workspace buffer is placed before the first launch, so a call that does not fit
   // its workspace fails before anything runs
   lf::MainRec* mains; lf::MulRec* muls; lf::MemRec32* m32; lf::MemRec64* m64;
@@ -158,7 +160,7 @@ lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, 
   lf::QuadTab q = lf_quad(ctx);
   A.qd.n = q.n; A.qd.u = q.u; A.qd.w = q.w;
   A.tmod = nullptr;
-  if (c->has_obs()) { A.tmod = wsd(".tmod", n * 2); if (e) return e; }
+  if (c->has_obs() || want_tmod) { A.tmod = wsd(".tmod", n * 2); if (e) return e; }
   return lf_expand_launch(ctx, M, params, S, st, mains, muls, m32, m64);
 }
 
@@ -179,8 +181,6 @@ lf_status lf_chi2_check(lf_ctx* ctx, const lf_model* M, const double* params, in
   if (mode == 1 && (long long)S * c->n_img >= (1LL << 31))
     return ctx->fail(LF_E_INVALID_ARG, "image plane needs S * n_img < 2^31");
   if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
-  if (c->d_mag && lf_model_has_enfw(M))
-    return ctx->fail(LF_E_UNSUPPORTED, "flux terms need third derivatives, not available for elliptical NFW");
   return LF_OK;
 }
 
@@ -199,4 +199,22 @@ extern "C" lf_status lf_chi2_terms(lf_ctx* ctx, const lf_model* M, const double*
   A.newton_tol = 1e-9;
   ctx->cur_stream = st;
   return ctx->hip(lf::launch_chi2(A, mixed, mode, st, lf_prof_mark, ctx), "chi2 kernels");
+}
+
+extern "C" lf_status lf_chi2_images(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S,
+                                    const lf_cons* c, lf_prec prec, double* chi2, int32_t* flags,
+                                    double* beta_model, double* theta_model, int32_t* img_flags, void* stream) {
+  lf_status ce = lf_chi2_check(ctx, M, params, S, c, 1, prec, chi2);
+  if (ce) return ce;
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  lf::Chi2Args A;
+  lf_status e = lf_chi2_prepare(ctx, M, params, S, c, st, A, "chi2", true);
+  if (e) return e;
+  A.chi2 = chi2; A.flags = flags; A.bmod = beta_model; A.terms = nullptr;
+  A.newton_tol = 1e-9;
+  ctx->cur_stream = st;
+  e = ctx->hip(lf::launch_chi2(A, prec == LF_PREC_MIXED, 1, st, lf_prof_mark, ctx), "chi2 kernels");
+  if (e) return e;
+  return ctx->hip(lf::launch_chi2_images_out(A, c->d_order, theta_model, img_flags, st), "chi2 image outputs");
 }

@@ -51,11 +51,20 @@ lf_status plane_sum(lf_ctx* ctx, const lf_model* M, const double* params, const 
   return ctx->hip(he, "plane lean pass");
 }
 
+// Candidate capacity: max(LF_FIND_CAP_MIN, LF_FIND_CAP_PER_SRC n_src), or the context's
+// (LF_FIND_CAND_CAP at lf_init), at most 2^28.  F.n_src must be set.
 lf_status finder_buffers(lf_ctx* ctx, hipStream_t st, lf::FindArgs& F) {
   lf_status e = LF_OK;
-  F.cap = LF_SORT_CAP;
+  long long cap = ctx->find_cap > 0 ? ctx->find_cap
+                                    : std::max<long long>(LF_FIND_CAP_MIN, (long long)LF_FIND_CAP_PER_SRC * F.n_src);
+  F.cap = (int)std::min<long long>(cap, 1LL << 28);
+  F.n_cu = ctx->n_cu > 0 ? ctx->n_cu : 256;
+  F.cand_raw = (unsigned long long*)ctx->ws("find.craw", sizeof(unsigned long long) * F.cap, st, &e); if (e) return e;
   F.cand = (unsigned long long*)ctx->ws("find.cand", sizeof(unsigned long long) * F.cap, st, &e); if (e) return e;
   F.n_cand = (int*)ctx->ws("find.ncand", 64, st, &e); if (e) return e;
+  F.src_cnt = (int*)ctx->ws("find.scnt", sizeof(int) * F.n_src, st, &e); if (e) return e;
+  F.src_off = (int*)ctx->ws("find.soff", sizeof(int) * (F.n_src + 1), st, &e); if (e) return e;
+  F.src_cur = (int*)ctx->ws("find.scur", sizeof(int) * F.n_src, st, &e); if (e) return e;
   F.c_status = (int*)ctx->ws("find.status", sizeof(int) * F.cap, st, &e); if (e) return e;
   F.c_theta = (double*)ctx->ws("find.theta", sizeof(double) * 2 * F.cap, st, &e); if (e) return e;
   F.c_mu = (double*)ctx->ws("find.mu", sizeof(double) * F.cap, st, &e); if (e) return e;

@@ -16,6 +16,7 @@ struct lf_ctx {
   int device = 0;
   size_t budget = 0, dev_bytes = 0;
   int n_cu = 256;
+  long long find_cap = 0;       // finder candidate capacity (0: sized from the source count)
   std::string arch;
   std::string last_error;
   struct Buf {
@@ -77,6 +78,7 @@ struct lf_cons {
   double* d_sigmax = nullptr;    // [n_img] max(sig1, sig2)
   int* d_fam = nullptr;          // [n_img] family of each sorted image
   int* d_fam_start = nullptr;    // [n_fam + 1]
+  int* d_order = nullptr;        // [n_img] constraint index of each sorted image (as order)
   double* d_afam = nullptr;      // [n_fam]
   size_t bytes = 0;
   // flux and time-delay data (Sec. 3.2, 3.3), sorted like the images; null when absent
@@ -103,3 +105,11 @@ lf_status lf_expand_tables(lf_ctx* ctx, const lf_model* M, const double* params,
                            hipStream_t st, lf::MainRec** mains, lf::MulRec** muls, lf::MemRec32** m32,
                            lf::MemRec64** m64, const char* tag);
 void lf_prof_mark(void* ctx, const char* name, int end_flag);
+namespace lf { struct Chi2Args; }
+// Set-up shared by the chi^2 entry points: argument checks (nothing is launched when they fail);
+// workspace placement and the parameter expansion (want_tmod keeps the model image positions
+// of an image-plane launch).
+lf_status lf_chi2_check(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S, const lf_cons* c,
+                        int32_t mode, lf_prec prec, const double* chi2);
+lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, int S, const lf_cons* c,
+                          hipStream_t st, lf::Chi2Args& A, const char* tag, bool want_tmod = false);

@@ -17,11 +17,6 @@
 #include "lf_api_internal.h"
 #include "lf_chi2.h"
 
-lf_status lf_chi2_check(lf_ctx* ctx, const lf_model* M, const double* params, int32_t S, const lf_cons* c,
-                        int32_t mode, lf_prec prec, const double* chi2);
-lf_status lf_chi2_prepare(lf_ctx* ctx, const lf_model* M, const double* params, int S, const lf_cons* c,
-                          hipStream_t st, lf::Chi2Args& A, const char* tag);
-
 namespace {
 
 __device__ __align__(256) char scratch[LF_CHI2_NOALLOC_SCRATCH_BYTES];

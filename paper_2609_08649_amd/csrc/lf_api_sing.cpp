@@ -25,7 +25,6 @@ extern "C" lf_status lf_singularity_map(lf_ctx* ctx, const lf_model* M, const do
       !out->swt_k || !out->swt_e || !out->swt_seg || !out->swt_status || !out->counts)
     return ctx->fail(LF_E_INVALID_ARG, "every output list is required");
   if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
-  if (lf_model_has_enfw(M)) return ctx->fail(LF_E_UNSUPPORTED, "third derivatives of elliptical NFW");
   hipSetDevice(ctx->device);
   hipStream_t st = (hipStream_t)stream;
   const long long P = (long long)grid->nx * grid->ny;
@@ -56,6 +55,7 @@ extern "C" lf_status lf_singularity_map(lf_ctx* ctx, const lf_model* M, const do
   A.x0 = grid->x0; A.y0 = grid->y0; A.h = grid->h; A.nx = nx; A.ny = ny;
   A.g1 = mo.gamma1; A.g2 = mo.gamma2; A.f1 = mo.f1; A.f2 = mo.f2; A.vflags = mo.flags;
   A.pl.mains = mains; A.pl.n_main = dm.n_main; A.pl.mem = m64; A.pl.seg = dm.seg;
+  A.enfw = dm.has_enfw;
   lf::QuadTab q = lf_quad(ctx);
   A.qd.n = q.n; A.qd.u = q.u; A.qd.w = q.w;
   A.refine = refine ? 1 : 0;

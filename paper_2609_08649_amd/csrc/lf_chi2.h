@@ -66,5 +66,10 @@ hipError_t launch_batch_lean_only(const BatchArgs& B, bool mixed, int block, int
 
 hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st,
                        void (*mark)(void*, const char*, int), void* ctx);
+// Per-image outputs of an image-plane launch (tmod set): model image positions and image flags
+// scattered from the family-sorted order to the caller's constraint order (either may be null).
+hipError_t launch_chi2_images_out(const Chi2Args& A, const int* order, double* theta_model, int* img_flags,
+                                  hipStream_t st);
 
 }  // namespace lf
+

@@ -31,7 +31,7 @@ __device__ __forceinline__ long long lane_slot(const Chi2Args& A, long long t) {
 }
 
 // One catalog member scaled by the lane's multipliers, FP64; false on a singular centre.
-// D3: third derivatives too (not for elliptical NFW members, which the callers exclude).
+// D3: third derivatives too.
 template <int SEG, bool D3 = false>
 __device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, double bm, double sm, double am,
                                          const Quad& qd, Term<double>& t) {
@@ -60,8 +60,8 @@ __device__ __forceinline__ bool cat_term(const MemCat& c, double dx, double dy, 
     if (dx == (T)0 && dy == (T)0) return false;
     double xp = c.c * dx + c.sn * dy, yp = c.c * dy - c.sn * dx;
     Term<double> pr;
-    enfw_prime(xp, yp, b, s, c.q, qd, pr);
-    rotate_back<false>(c.c, c.sn, pr, t);
+    enfw_prime<D3>(xp, yp, b, s, c.q, qd, pr);
+    rotate_back<D3>(c.c, c.sn, pr, t);
   }
   return true;
 }
@@ -280,16 +280,17 @@ __device__ __forceinline__ int wave_or(int v) {
 // Flux and time-delay terms (Sec. 3.2 Eq. chi2_flux, msrc; Sec. 3.3 Eq. chi2_td, dt0,
 // td_approx), FP64 in both precisions.  The observables pass evaluates, per (image, sample),
 // the potential, psi_ij and the third derivatives at theta_obs (WHICH = 0) or the potential
-// and psi_ij at the accepted image-plane model image (WHICH = 1).
+// and psi_ij at the accepted image-plane model image (WHICH = 1).  ENFW = false compiles the
+// elliptical NFW quadrature out (models without such halos; far fewer registers).
 // ---------------------------------------------------------------------------------------
-template <bool D3>
+template <bool D3, bool ENFW>
 __device__ void obs_sums(const Chi2Args& A, int s, double x, double y, bool want_pot, Acc& acc, double& pot) {
   acc.zero();
   pot = 0.0;
   const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
   for (int c = 0; c < A.m.n_main; ++c) {
     const MainRec r = mr[c];
-    eval_main<D3>(r, x, y, A.qd, acc);
+    eval_main<D3, ENFW>(r, x, y, A.qd, acc);
     if (want_pot) pot += pot_main(r, x, y, A.qd);
   }
   const MulRec u = A.muls[s];
@@ -300,7 +301,7 @@ __device__ void obs_sums(const Chi2Args& A, int s, double x, double y, bool want
       const MemCat c = A.m.mem[h];
       const double dx = x - c.x, dy = y - c.y;
       Term<double> t;
-      if (cat_term<SEG, D3 && SEG != SEG_ENFW>(c, dx, dy, u.b, u.s, u.a, A.qd, t)) add<D3>(acc, t);
+      if (cat_term<SEG, D3>(c, dx, dy, u.b, u.s, u.a, A.qd, t)) add<D3>(acc, t);
       if (want_pot) pot += cat_pot<SEG>(c, dx, dy, u.b, u.s, u.a, A.qd);
     }
   };
@@ -310,9 +311,9 @@ __device__ void obs_sums(const Chi2Args& A, int s, double x, double y, bool want
   seg(std::integral_constant<int, SEG_ESIE>());
   seg(std::integral_constant<int, SEG_POINT>());
   seg(std::integral_constant<int, SEG_NFW>());
-  seg(std::integral_constant<int, SEG_ENFW>());
+  if constexpr (ENFW) seg(std::integral_constant<int, SEG_ENFW>());
 }
-template <int WHICH>
+template <int WHICH, bool ENFW>
 __global__ __launch_bounds__(256) void k_chi2_obs(const Chi2Args A) {
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   if (t >= (long long)A.S * A.n_img) return;
@@ -324,13 +325,13 @@ __global__ __launch_bounds__(256) void k_chi2_obs(const Chi2Args A) {
   Acc acc;
   double pot;
   if (WHICH == 0) {
-    obs_sums<true>(A, s, x, y, want_pot, acc, pot);
+    obs_sums<true, ENFW>(A, s, x, y, want_pot, acc, pot);
     double* e = A.ext + (size_t)g * 8;
     e[0] = pot; e[1] = acc.t111; e[2] = acc.t112; e[3] = acc.t122; e[4] = acc.t222;
     e[5] = acc.h11; e[6] = acc.h12; e[7] = acc.h22;
   } else {
     if (A.iflags[g] != 0) return;              // not accepted: the source-plane expansion is used
-    obs_sums<false>(A, s, A.tmod[2 * g], A.tmod[2 * g + 1], want_pot, acc, pot);
+    obs_sums<false, ENFW>(A, s, A.tmod[2 * g], A.tmod[2 * g + 1], want_pot, acc, pot);
     double* e = A.extm + (size_t)g * 4;
     e[0] = pot; e[1] = acc.h11; e[2] = acc.h12; e[3] = acc.h22;
   }
@@ -653,6 +654,29 @@ __device__ void chi2_img_sample(const Chi2Args& A, int s) {
 }
 __global__ __launch_bounds__(64) void k_chi2_img_sum(const Chi2Args A) { chi2_img_sample(A, blockIdx.x); }
 
+// Model image positions and image flags of every (sample, image) slot, written in the caller's
+// constraint order: sorted slot k of sample s goes to constraint order[k].
+__global__ __launch_bounds__(256) void k_chi2_images_out(const Chi2Args A, const int* order, double* theta_model,
+                                                         int* img_flags) {
+  const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)A.S * A.n_img) return;
+  const long long s = g / A.n_img, k = g - s * A.n_img;
+  const long long o = s * A.n_img + order[k];
+  if (theta_model) {
+    theta_model[2 * o] = A.tmod[2 * g];
+    theta_model[2 * o + 1] = A.tmod[2 * g + 1];
+  }
+  if (img_flags) img_flags[o] = A.iflags[g];
+}
+
+hipError_t launch_chi2_images_out(const Chi2Args& A, const int* order, double* theta_model, int* img_flags,
+                                  hipStream_t st) {
+  const long long n = (long long)A.S * A.n_img;
+  hipLaunchKernelGGL(k_chi2_images_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, order, theta_model,
+                     img_flags);
+  return hipGetLastError();
+}
+
 hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, void (*mark)(void*, const char*, int),
                        void* ctx) {
   long long n = (long long)A.S * A.n_img;
@@ -668,7 +692,8 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
   const bool obs = A.mag || A.dt;
   if (obs) {
     mark(ctx, "chi2_obs", 0);
-    hipLaunchKernelGGL(k_chi2_obs<0>, dim3(blocks), dim3(256), 0, st, A);
+    if (A.m.has_enfw) hipLaunchKernelGGL((k_chi2_obs<0, true>), dim3(blocks), dim3(256), 0, st, A);
+    else hipLaunchKernelGGL((k_chi2_obs<0, false>), dim3(blocks), dim3(256), 0, st, A);
     mark(ctx, "chi2_obs", 1);
   }
   mark(ctx, "chi2_src", 0);
@@ -680,7 +705,8 @@ hipError_t launch_chi2(const Chi2Args& A, bool mixed, int mode, hipStream_t st, 
     hipLaunchKernelGGL(k_chi2_newton, dim3(blocks), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_chi2_newton2, dim3(A.n_cu * 4), dim3(256), 0, st, A);
     mark(ctx, "chi2_newton", 1);
-    if (obs) hipLaunchKernelGGL(k_chi2_obs<1>, dim3(blocks), dim3(256), 0, st, A);
+    if (obs && A.m.has_enfw) hipLaunchKernelGGL((k_chi2_obs<1, true>), dim3(blocks), dim3(256), 0, st, A);
+    else if (obs) hipLaunchKernelGGL((k_chi2_obs<1, false>), dim3(blocks), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_chi2_img_sum, dim3(A.S), dim3(64), 0, st, A);
   }
   return hipGetLastError();

@@ -233,19 +233,29 @@ __device__ __forceinline__ void epje(T dx, T dy, T c, T sn, T bqe, T e, T q2, T 
 // ---------------------------------------------------------------------------------------
 // NFW.  With X^2 = xi^2 / r_s^2 and z = 1 - X^2:  F = arccosh(1/X)/sqrt(1-X^2) (X < 1),
 // arccos(1/X)/sqrt(X^2-1) (X > 1); kappa = 2 k_s G(z), G = (F - 1)/z (series near z = 0).
-// Returns G and dG/dz.  For X < 1, arccosh(1/X) = log((1 + w)/X) = log((1 + w)^2 / X^2) / 2
-// with w = sqrt(z) >= 0.3 outside the series range: one logarithm, no cancellation.
+// Returns G and dG/dz (D2: d^2G/dz^2 too).  For X < 1, arccosh(1/X) = log((1 + w)/X) =
+// log((1 + w)^2 / X^2) / 2 with w = sqrt(z) >= 0.3 outside the series range: one logarithm,
+// no cancellation.  Outside the series range the derivatives follow from F' = (1/(1-z) - F) / 2z,
+// F'' = (1/(1-z)^2 - 3 F') / 2z, G' = (F' - G) / z and G'' = (F'' - 2 G') / z.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& Gp) {
+template <bool D2>
+__device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& Gp, double& Gpp) {
   double z = 1.0 - X2;
   if (fabs(z) < 0.1) {
-    // F = sum z^k/(2k+1); G = sum_{k>=1} z^(k-1)/(2k+1); G' = sum_{k>=2} (k-1) z^(k-2)/(2k+1)
+    // F = sum z^k/(2k+1); G = sum_{k>=1} z^(k-1)/(2k+1); G' = sum_{k>=2} (k-1) z^(k-2)/(2k+1);
+    // G'' = sum_{k>=3} (k-1)(k-2) z^(k-3)/(2k+1)
     double g = 0.0, gp = 0.0;
 #pragma unroll
     for (int k = 18; k >= 2; --k) { g = fma(g, z, 1.0 / (2 * k + 1)); gp = fma(gp, z, (double)(k - 1) / (2 * k + 1)); }
     G = fma(g, z, 1.0 / 3.0);
     Gp = gp;
     F = fma(G, z, 1.0);
+    if (D2) {
+      double gpp = 0.0;
+#pragma unroll
+      for (int k = 21; k >= 3; --k) gpp = fma(gpp, z, (double)((k - 1) * (k - 2)) / (2 * k + 1));
+      Gpp = gpp;
+    }
   } else {
     // one reciprocal square root y = 1/sqrt(|z|) gives w = sqrt(|z|) = |z| y, 1/w = y and
     // 1/z = +-y^2
@@ -262,7 +272,15 @@ __device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& G
     G = (F - 1.0) * iz;
     const double Fp = 0.5 * (iX2 - F) * iz;
     Gp = (Fp - G) * iz;
+    if (D2) {
+      const double Fpp = 0.5 * fma(iX2, iX2, -3.0 * Fp) * iz;
+      Gpp = (Fpp - 2.0 * Gp) * iz;
+    }
   }
+}
+__device__ __forceinline__ void nfw_G(double X2, double& F, double& G, double& Gp) {
+  double unused;
+  nfw_G<false>(X2, F, G, Gp, unused);
 }
 
 template <bool D3>
@@ -283,40 +301,59 @@ __device__ __forceinline__ void nfw_circ(double dx, double dy, double ks, double
 }
 
 // Elliptical NFW in its own frame from the integrals
-//   J_n = int_0^1 kappa(xi^2(u)) (1 - e^2 u)^-(n+1/2) du,  K_n = int_0^1 u kappa'(xi^2(u)) (...)^-(n+1/2) du
+//   J_n = int_0^1 kappa(xi^2(u)) (1 - e^2 u)^-(n+1/2) du,  K_n = int_0^1 u kappa'(xi^2(u)) (...)^-(n+1/2) du,
+//   L_n = int_0^1 u^2 kappa''(xi^2(u)) (...)^-(n+1/2) du  (derivatives in xi^2)
 // with xi^2(u) = u (x^2 + y^2/(1 - e^2 u)):  alpha = q (x J0, y J1),
-// psi_xx = 2 q x^2 K0 + q J0, psi_yy = 2 q y^2 K2 + q J1, psi_xy = 2 q x y K1.
+// psi_xx = 2 q x^2 K0 + q J0, psi_yy = 2 q y^2 K2 + q J1, psi_xy = 2 q x y K1.  Since
+// d(xi^2)/dx = 2 u x and d(xi^2)/dy = 2 u y / (1 - e^2 u), d/dx of an integral of order n
+// brings 2 x times the next kind at the same order and d/dy 2 y times it at order n + 1:
+// psi_xxx = q x (6 K0 + 4 x^2 L0), psi_xxy = q y (2 K1 + 4 x^2 L1), psi_xyy = q x (2 K1 + 4 y^2 L2),
+// psi_yyy = q y (6 K2 + 4 y^2 L3).
 // Fixed Gauss-Legendre nodes in t with u = t^6 (u_node, w_node carry the Jacobian).
 struct Quad {
   int n;
   const double* u;
   const double* w;
 };
+template <bool D3 = false>
 __device__ __forceinline__ void enfw_prime(double xp, double yp, double ks, double rs, double q,
                                            const Quad& qd, Term<double>& t) {
   double e2 = 1.0 - q * q;
   double xx = xp * xp, yy = yp * yp;
   double irs2 = 1.0 / (rs * rs);
   double J0 = 0, J1 = 0, K0 = 0, K1 = 0, K2 = 0;
+  double L0 = 0, L1 = 0, L2 = 0, L3 = 0;
   for (int i = 0; i < qd.n; ++i) {
     double u = qd.u[i], wq = qd.w[i];
     double W = fma(-e2, u, 1.0);
     const double rW = frsq(W), iW = rW * rW;
     double X2 = u * fma(yy, iW, xx) * irs2;
-    double F, G, Gp;
-    nfw_G(X2, F, G, Gp);
+    double F, G, Gp, Gpp;
+    nfw_G<D3>(X2, F, G, Gp, Gpp);
     double kap = 2.0 * ks * G;
     double ukp = -2.0 * ks * Gp * irs2 * u;
     double f0 = wq * rW;
     double f1 = f0 * iW, f2 = f1 * iW;
     J0 = fma(f0, kap, J0); J1 = fma(f1, kap, J1);
     K0 = fma(f0, ukp, K0); K1 = fma(f1, ukp, K1); K2 = fma(f2, ukp, K2);
+    if (D3) {
+      const double uukpp = 2.0 * ks * Gpp * (irs2 * u) * (irs2 * u);
+      const double f3 = f2 * iW;
+      L0 = fma(f0, uukpp, L0); L1 = fma(f1, uukpp, L1); L2 = fma(f2, uukpp, L2); L3 = fma(f3, uukpp, L3);
+    }
   }
   t.ax = q * xp * J0; t.ay = q * yp * J1;
   t.h11 = 2.0 * q * xx * K0 + q * J0;
   t.h22 = 2.0 * q * yy * K2 + q * J1;
   t.h12 = 2.0 * q * xp * yp * K1;
-  t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
+  if (D3) {
+    t.t111 = q * xp * fma(4.0 * xx, L0, 6.0 * K0);
+    t.t112 = q * yp * fma(4.0 * xx, L1, 2.0 * K1);
+    t.t122 = q * xp * fma(4.0 * yy, L2, 2.0 * K1);
+    t.t222 = q * yp * fma(4.0 * yy, L3, 6.0 * K2);
+  } else {
+    t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -475,8 +512,8 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
       else if constexpr (ENFW) {
         double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
         Term<double> p;
-        enfw_prime(xp, yp, r.b, r.s, r.q, qd, p);
-        rotate_back<false>(r.c, r.sn, p, t);
+        enfw_prime<D3>(xp, yp, r.b, r.s, r.q, qd, p);
+        rotate_back<D3>(r.c, r.sn, p, t);
       } else {
         acc.flags |= FL_INVALID;
         return;

@@ -5,7 +5,11 @@
 #include "lf_segs.h"
 
 #define LF_MAX_PLANES 8
-#define LF_SORT_CAP 8192
+// Candidate lists: capacity max(LF_FIND_CAP_MIN, LF_FIND_CAP_PER_SRC n_src) unless the context
+// sets another; a source's list is sorted in LDS up to LF_SEG_LDS keys, in global memory beyond.
+#define LF_FIND_CAP_MIN (1 << 16)
+#define LF_FIND_CAP_PER_SRC 64
+#define LF_SEG_LDS 4096
 
 namespace lf {
 
@@ -25,9 +29,20 @@ struct FindArgs {
   const double* beta;        // [n_src*2]
   const double* w;           // [n_src*n_planes] plane weights (single plane: a_dis)
   double eps;                // candidate margin [arcsec]
-  unsigned long long* cand;  // [cap]
-  int* n_cand;
+  // Candidates, key (source << 32) | triangle or cell code.  The candidate pass appends them
+  // in any order to cand_raw and counts them per source; they are then placed in per-source
+  // segments of cand (src_off, the exclusive prefix sum of src_cnt) and each segment sorted,
+  // so cand is ordered by key whatever the order of the atomics.  When the total exceeds cap,
+  // a second candidate pass writes only the sources whose segment fits (a prefix of the
+  // sources; the others are flagged), so which results survive does not depend on timing.
+  unsigned long long* cand_raw;  // [cap]
+  unsigned long long* cand;      // [cap]
+  int* n_cand;                   // [0] all candidates found, [1] candidates kept (n_fit), [2] overflow
+  int* src_cnt;                  // [n_src]
+  int* src_off;                  // [n_src + 1]
+  int* src_cur;                  // [n_src]
   int cap;
+  int n_cu;                      // compute units (grids of the strided passes)
   int* c_status;             // [cap] 0 accepted, 1 no convergence, 2 moved > 2h, 3 merged, 4 outside
   double* c_theta;           // [cap*2]
   double* c_mu;              // [cap]

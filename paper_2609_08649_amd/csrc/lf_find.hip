@@ -7,8 +7,11 @@
 //      beta_v = theta_v - sum_j w_j alpha_j(v); two FP32 prefilters (the mapped cell centre
 //      with a radius, then the bounding box), then the FP64 test: a triangle is a candidate
 //      when the source lies within eps of it (eps covers the vertex error of the precision in
-//      use), appended with one atomic per wave;
-//   3. k_find_sort: candidates sorted by (source, triangle) in LDS (bitonic, one workgroup);
+//      use), appended with one atomic per wave and counted per source;
+//   3. k_find_scan / k_find_scatter / k_find_segsort: per-source segments of the candidate
+//      list (prefix sum of the counts), each sorted by triangle, so the list is ordered by
+//      (source, triangle) whatever the order of the atomics; past the capacity a second
+//      candidate pass fills the segments of the sources that fit and the rest are flagged;
 //   4. k_find_polish: per candidate, FP64 vertex deflections, exact orientation signs with
 //      the watertight tie rule, barycentric start, FP64 Newton polish and acceptance;
 //   5. k_find_final: per source, merge duplicates in candidate order, write images.
@@ -156,14 +159,49 @@ __device__ __forceinline__ bool near_tri(const double* B, double sx, double sy, 
   return o0 >= -eps * e0 && o1 >= -eps * e1 && o2 >= -eps * e2;
 }
 
+// A wave's hits for its source s (low: each lane's triangle or cell code).  FILL = false (the
+// candidate pass): appended to the unordered list, counted per source.  FILL = true (the
+// second pass after an overflow): written straight into the source's segment, for the sources
+// whose segment fits the capacity.
+template <bool FILL>
+__device__ __forceinline__ void emit_cand(const FindArgs& F, int s, bool hit, unsigned long long low, int lane) {
+  const unsigned long long mask = __ballot(hit);
+  if (!mask) return;
+  if (FILL && F.src_off[s + 1] > F.cap) return;
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) {
+    const int c = __popcll(mask);
+    if (FILL) {
+      base = F.src_off[s] + atomicAdd(F.src_cur + s, c);
+    } else {
+      base = atomicAdd(F.n_cand, c);
+      atomicAdd(F.src_cnt + s, c);
+    }
+  }
+  base = __shfl(base, leader, 64);
+  if (hit) {
+    const int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
+    const unsigned long long key = ((unsigned long long)s << 32) | low;
+    if (FILL) {
+      if (idx < F.src_off[s + 1]) F.cand[idx] = key;   // (the pass finds what the first found)
+    } else if (idx < F.cap) {
+      F.cand_raw[idx] = key;
+    }
+  }
+}
+
 // NP = 1..4: that many planes, corners in registers; 0: any count up to LF_MAX_PLANES (the
-// corner arrays are then indexed at run time and live in scratch memory)
-template <int NP>
+// corner arrays are then indexed at run time and live in scratch memory).  FILL: the second
+// pass after an overflow (returns at once otherwise); its grid strides over blocks of cells.
+template <int NP, bool FILL>
 __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
   constexpr int MP = NP > 0 ? NP : LF_MAX_PLANES;
   const int np = NP > 0 ? NP : F.n_planes;
+  if (FILL && F.n_cand[2] == 0) return;
   const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  for (long long cb = (long long)blockIdx.x * 256; cb < ncell; cb += (long long)gridDim.x * 256) {
+  const long long c = cb + threadIdx.x;
   const bool valid = c < ncell;
   const long long cc = valid ? c : 0;
   const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
@@ -280,47 +318,112 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
       double T1[6] = {bx[0], by[0], bx[3], by[3], bx[2], by[2]};
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
-        unsigned long long mask = __ballot(hit);
-        if (mask) {
-          int leader = __ffsll((long long)mask) - 1;
-          int base = 0;
-          if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
-          base = __shfl(base, leader, 64);
-          if (hit) {
-            int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-            if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(2 * cc + t);
-          }
-        }
+        const bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
+        emit_cand<FILL>(F, s, hit, (unsigned long long)(2 * cc + t), lane);
       }
     }
+  }
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// 3. sort by (source, triangle): bitonic in LDS, one workgroup
+// 3. candidates by (source, triangle): per-source segments, each sorted
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_find_sort(const FindArgs F) {
-  __shared__ unsigned long long key[LF_SORT_CAP];
-  int n = min(*F.n_cand, F.cap);
+__global__ __launch_bounds__(256) void k_find_reset(const FindArgs F) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t < 3) F.n_cand[t] = 0;
+  for (int s = t; s < F.n_src; s += gridDim.x * 256) F.src_cnt[s] = 0;
+}
+
+// Exclusive prefix sum of the per-source counts (one workgroup; saturating at INT_MAX, where
+// nothing fits anyway), the number of candidates kept (all, or those of the sources before
+// the first whose segment passes the capacity) and the overflow flag; zeroes the cursors.
+__global__ __launch_bounds__(1024) void k_find_scan(const FindArgs F) {
+  __shared__ int sh[1024];
+  __shared__ long long carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int b = 0; b < F.n_src; b += 1024) {
+    const int s = b + tid;
+    const int v = s < F.n_src ? F.src_cnt[s] : 0;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int u = tid >= o ? sh[tid - o] : 0;
+      __syncthreads();
+      sh[tid] += u;
+      __syncthreads();
+    }
+    const long long excl = carry + sh[tid] - v, incl = excl + v;
+    if (s < F.n_src) {
+      F.src_off[s] = (int)min(excl, (long long)INT_MAX);
+      F.src_cur[s] = 0;
+      if (excl <= F.cap && incl > F.cap) F.n_cand[1] = (int)excl;
+    }
+    __syncthreads();
+    if (tid == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    F.src_off[F.n_src] = (int)min(carry, (long long)INT_MAX);
+    if (carry <= F.cap) F.n_cand[1] = (int)carry;
+    F.n_cand[2] = carry > F.cap ? 1 : 0;
+  }
+}
+
+// Unordered list -> per-source segments (no overflow; otherwise the second candidate pass
+// fills them).
+__global__ __launch_bounds__(256) void k_find_scatter(const FindArgs F) {
+  if (F.n_cand[2]) return;
+  const int n = F.n_cand[0];
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+    const unsigned long long key = F.cand_raw[k];
+    const int s = (int)(key >> 32);
+    F.cand[F.src_off[s] + atomicAdd(F.src_cur + s, 1)] = key;
+  }
+}
+
+// One workgroup per kept source: its segment sorted ascending by a bitonic network in the form
+// where every compare-exchange puts the smaller key first (per block of `size`, a mirror step
+// then half-cleaners), so a partner past the end is skipped as if it held +infinity and any
+// length sorts.  In LDS up to LF_SEG_LDS keys, in place in global memory beyond.
+__global__ __launch_bounds__(256) void k_find_segsort(const FindArgs F) {
+  __shared__ unsigned long long sk[LF_SEG_LDS];
+  const int s = blockIdx.x;
+  const int lo = F.src_off[s], hi = F.src_off[s + 1];
+  if (hi > F.n_cand[1] || hi - lo < 2) return;
+  const int n = hi - lo, tid = threadIdx.x;
+  unsigned long long* g = F.cand + lo;
+  const bool in_lds = n <= LF_SEG_LDS;
+  unsigned long long* a = in_lds ? sk : g;
+  if (in_lds)
+    for (int k = tid; k < n; k += 256) sk[k] = g[k];
+  __syncthreads();
   int m = 1;
   while (m < n) m <<= 1;
-  for (int k = threadIdx.x; k < m; k += 1024) key[k] = k < n ? F.cand[k] : ~0ull;
-  __syncthreads();
   for (int size = 2; size <= m; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int k = threadIdx.x; k < m; k += 1024) {
-        int l = k ^ stride;
-        if (l > k) {
-          bool up = (k & size) == 0;
-          unsigned long long a = key[k], b = key[l];
-          if ((a > b) == up) { key[k] = b; key[l] = a; }
+    for (int k = tid; k < m; k += 256) {
+      const int l = k ^ (size - 1);
+      if (l > k && l < n) {
+        const unsigned long long x = a[k], y = a[l];
+        if (y < x) { a[k] = y; a[l] = x; }
+      }
+    }
+    __syncthreads();
+    for (int stride = size >> 2; stride > 0; stride >>= 1) {
+      for (int k = tid; k < m; k += 256) {
+        const int l = k ^ stride;
+        if (l > k && l < n) {
+          const unsigned long long x = a[k], y = a[l];
+          if (y < x) { a[k] = y; a[l] = x; }
         }
       }
       __syncthreads();
     }
   }
-  for (int k = threadIdx.x; k < n; k += 1024) F.cand[k] = key[k];
+  if (in_lds)
+    for (int k = tid; k < n; k += 256) g[k] = sk[k];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -328,9 +431,8 @@ __global__ __launch_bounds__(1024) void k_find_sort(const FindArgs F) {
 // ---------------------------------------------------------------------------------------
 template <bool MULTI>
 __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const LensDev L) {
-  int n = min(*F.n_cand, F.cap);
-  int k = blockIdx.x;            // one wave per candidate
-  if (k >= n) return;
+  const int n = F.n_cand[1];
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {   // one wave per candidate
   unsigned long long key = F.cand[k];
   int s = (int)(key >> 32);
   long long tri = (long long)(key & 0xffffffffull);
@@ -380,27 +482,23 @@ __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const Lens
     F.c_theta[2 * k + 1] = ty;
     F.c_mu[k] = mu;
   }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
 // 5. per source: merge duplicates in candidate order, write outputs
 // ---------------------------------------------------------------------------------------
-__device__ int lower_bound_key(const unsigned long long* a, int n, unsigned long long x) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    int m = (lo + hi) >> 1;
-    if (a[m] < x) lo = m + 1; else hi = m;
-  }
-  return lo;
-}
+// A source whose candidates were not kept (past the capacity) gets count 0 and FL_OVERFLOW.
 __global__ __launch_bounds__(64) void k_find_final(const FindArgs F) {
   int s = blockIdx.x * 64 + threadIdx.x;
   if (s >= F.n_src) return;
-  int total = *F.n_cand;
-  int n = min(total, F.cap);
-  int lo = lower_bound_key(F.cand, n, (unsigned long long)s << 32);
-  int hi = lower_bound_key(F.cand, n, (unsigned long long)(s + 1) << 32);
-  int cnt = 0, fl = total > F.cap ? FL_OVERFLOW : 0;
+  const int lo = F.src_off[s], hi = F.src_off[s + 1];
+  if (hi > F.n_cand[1]) {
+    F.count_out[s] = 0;
+    if (F.flags_out) F.flags_out[s] = FL_OVERFLOW;
+    return;
+  }
+  int cnt = 0, fl = 0;
   for (int k = lo; k < hi; ++k) {
     if (F.c_status[k] != 0) continue;
     double tx = F.c_theta[2 * k], ty = F.c_theta[2 * k + 1];
@@ -424,26 +522,40 @@ __global__ __launch_bounds__(64) void k_find_final(const FindArgs F) {
   if (F.flags_out) F.flags_out[s] = fl;
 }
 
-__global__ void k_zero_int(int* p) { *p = 0; }
+// prefix sum and, without overflow, the scatter into segments
+static void launch_segments(const FindArgs& F, hipStream_t st) {
+  hipLaunchKernelGGL(k_find_scan, dim3(1), dim3(1024), 0, st, F);
+  hipLaunchKernelGGL(k_find_scatter, dim3((unsigned)max(1, min(4 * F.n_cu, (F.cap + 255) / 256))), dim3(256), 0,
+                     st, F);
+}
 
 hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void (*mark)(void*, const char*, int),
                        void* ctx) {
   long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, F.n_cand);
+  hipLaunchKernelGGL(k_find_reset, dim3((unsigned)min(1024, (F.n_src + 255) / 256 + 1)), dim3(256), 0, st, F);
   mark(ctx, "find_cand", 0);
-  const dim3 cgrid((unsigned)((ncell + 255) / 256));
+  const dim3 cgrid((unsigned)((ncell + 255) / 256)), fgrid((unsigned)(4 * F.n_cu));
   switch (F.n_planes) {
-    case 1: hipLaunchKernelGGL(k_find_cand<1>, cgrid, dim3(256), 0, st, F); break;
-    case 2: hipLaunchKernelGGL(k_find_cand<2>, cgrid, dim3(256), 0, st, F); break;
-    case 3: hipLaunchKernelGGL(k_find_cand<3>, cgrid, dim3(256), 0, st, F); break;
-    case 4: hipLaunchKernelGGL(k_find_cand<4>, cgrid, dim3(256), 0, st, F); break;
-    default: hipLaunchKernelGGL(k_find_cand<0>, cgrid, dim3(256), 0, st, F); break;
+    case 1: hipLaunchKernelGGL((k_find_cand<1, false>), cgrid, dim3(256), 0, st, F); break;
+    case 2: hipLaunchKernelGGL((k_find_cand<2, false>), cgrid, dim3(256), 0, st, F); break;
+    case 3: hipLaunchKernelGGL((k_find_cand<3, false>), cgrid, dim3(256), 0, st, F); break;
+    case 4: hipLaunchKernelGGL((k_find_cand<4, false>), cgrid, dim3(256), 0, st, F); break;
+    default: hipLaunchKernelGGL((k_find_cand<0, false>), cgrid, dim3(256), 0, st, F); break;
   }
   mark(ctx, "find_cand", 1);
-  hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
+  launch_segments(F, st);
+  switch (F.n_planes) {
+    case 1: hipLaunchKernelGGL((k_find_cand<1, true>), fgrid, dim3(256), 0, st, F); break;
+    case 2: hipLaunchKernelGGL((k_find_cand<2, true>), fgrid, dim3(256), 0, st, F); break;
+    case 3: hipLaunchKernelGGL((k_find_cand<3, true>), fgrid, dim3(256), 0, st, F); break;
+    case 4: hipLaunchKernelGGL((k_find_cand<4, true>), fgrid, dim3(256), 0, st, F); break;
+    default: hipLaunchKernelGGL((k_find_cand<0, true>), fgrid, dim3(256), 0, st, F); break;
+  }
+  hipLaunchKernelGGL(k_find_segsort, dim3((unsigned)F.n_src), dim3(256), 0, st, F);
+  const dim3 pgrid((unsigned)min(F.cap, 64 * F.n_cu));
   mark(ctx, "find_polish", 0);
-  if (F.n_planes == 1) hipLaunchKernelGGL(k_find_polish<false>, dim3(F.cap), dim3(64), 0, st, F, L);
-  else hipLaunchKernelGGL(k_find_polish<true>, dim3(F.cap), dim3(64), 0, st, F, L);
+  if (F.n_planes == 1) hipLaunchKernelGGL(k_find_polish<false>, pgrid, dim3(64), 0, st, F, L);
+  else hipLaunchKernelGGL(k_find_polish<true>, pgrid, dim3(64), 0, st, F, L);
   mark(ctx, "find_polish", 1);
   hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
   return hipGetLastError();
@@ -540,9 +652,12 @@ __device__ bool ms_cross(const double S1[2][4], int p, const double S2[2][4], in
 }
 }  // namespace
 
+template <bool FILL>
 __global__ __launch_bounds__(256) void k_ms_cand(const FindArgs F) {
+  if (FILL && F.n_cand[2] == 0) return;
   const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  for (long long cb = (long long)blockIdx.x * 256; cb < ncell; cb += (long long)gridDim.x * 256) {
+  const long long c = cb + threadIdx.x;
   const bool valid = c < ncell;
   const long long cc = valid ? c : 0;
   const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
@@ -579,29 +694,17 @@ __global__ __launch_bounds__(256) void k_ms_cand(const FindArgs F) {
         }
       }
       if (!__any(pairs != 0)) continue;
-      for (int k = 0; k < 4; ++k) {
-        const bool hit = (pairs >> k) & 1;
-        const unsigned long long mask = __ballot(hit);
-        if (!mask) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(F.n_cand, __popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (hit) {
-          const int idx = base + __popcll(mask & ((1ull << lane) - 1ull));
-          if (idx < F.cap) F.cand[idx] = ((unsigned long long)s << 32) | (unsigned long long)(cc * 4 + k);
-        }
-      }
+      for (int k = 0; k < 4; ++k) emit_cand<FILL>(F, s, (pairs >> k) & 1, (unsigned long long)(cc * 4 + k), lane);
     }
+  }
   }
 }
 
 // one wave per candidate: the intersection, then (polish) FP64 Newton as the triangle finder
 template <bool MULTI>
 __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev L, int polish) {
-  const int n = min(*F.n_cand, F.cap);
-  const int k = blockIdx.x;
-  if (k >= n) return;
+  const int n = F.n_cand[1];
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
   const unsigned long long key = F.cand[k];
   const int s = (int)(key >> 32);
   const long long low = (long long)(key & 0xffffffffull), cell = low >> 2;
@@ -648,19 +751,23 @@ __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev
     F.c_theta[2 * k + 1] = ty;
     F.c_mu[k] = 1.0 / (A[0] * A[3] - A[1] * A[2]);
   }
+  }
 }
 
 hipError_t launch_find_ms(const FindArgs& F, const LensDev& L, int polish, hipStream_t st,
                           void (*mark)(void*, const char*, int), void* ctx) {
   const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, F.n_cand);
+  hipLaunchKernelGGL(k_find_reset, dim3((unsigned)min(1024, (F.n_src + 255) / 256 + 1)), dim3(256), 0, st, F);
   mark(ctx, "find_ms_cand", 0);
-  hipLaunchKernelGGL(k_ms_cand, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
+  hipLaunchKernelGGL(k_ms_cand<false>, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, F);
   mark(ctx, "find_ms_cand", 1);
-  hipLaunchKernelGGL(k_find_sort, dim3(1), dim3(1024), 0, st, F);
+  launch_segments(F, st);
+  hipLaunchKernelGGL(k_ms_cand<true>, dim3((unsigned)(4 * F.n_cu)), dim3(256), 0, st, F);
+  hipLaunchKernelGGL(k_find_segsort, dim3((unsigned)F.n_src), dim3(256), 0, st, F);
+  const dim3 pgrid((unsigned)min(F.cap, 64 * F.n_cu));
   mark(ctx, "find_ms_point", 0);
-  if (F.n_planes == 1) hipLaunchKernelGGL(k_ms_point<false>, dim3(F.cap), dim3(64), 0, st, F, L, polish);
-  else hipLaunchKernelGGL(k_ms_point<true>, dim3(F.cap), dim3(64), 0, st, F, L, polish);
+  if (F.n_planes == 1) hipLaunchKernelGGL(k_ms_point<false>, pgrid, dim3(64), 0, st, F, L, polish);
+  else hipLaunchKernelGGL(k_ms_point<true>, pgrid, dim3(64), 0, st, F, L, polish);
   mark(ctx, "find_ms_point", 1);
   hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
   return hipGetLastError();

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
   if constexpr (RARE)
     seg_loop<SEG_NFW, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, acc, A.qd);
   if constexpr (ENFW)
-    seg_loop<SEG_ENFW, false, 1>(A.m64 + mo, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
+    seg_loop<SEG_ENFW, D3, 1>(A.m64 + mo, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, acc, A.qd);
   double* q = A.part + (size_t)s * NPART * P + p;
   q[0] = acc[0].ax; q[P] = acc[0].ay; q[2 * P] = acc[0].h11; q[3 * P] = acc[0].h12; q[4 * P] = acc[0].h22;
   if (D3) { q[5 * P] = acc[0].t111; q[6 * P] = acc[0].t112; q[7 * P] = acc[0].t122; q[8 * P] = acc[0].t222; }

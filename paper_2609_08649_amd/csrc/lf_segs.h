@@ -56,8 +56,8 @@ __device__ __forceinline__ bool seg_term(const R& r, T dx, T dy, const Quad& qd,
     if (dx == (T)0 && dy == (T)0) return false;
     double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
     Term<double> pr;
-    enfw_prime(xp, yp, r.b, r.s, sqrt((double)r.q2), qd, pr);
-    rotate_back<false>((double)r.c, (double)r.sn, pr, *(Term<double>*)&t);
+    enfw_prime<D3>(xp, yp, r.b, r.s, sqrt((double)r.q2), qd, pr);
+    rotate_back<D3>((double)r.c, (double)r.sn, pr, *(Term<double>*)&t);
   }
   return true;
 }
@@ -436,11 +436,12 @@ struct Plane64 {
   const MemRec64* mem;
   SegOff seg;
 };
-template <bool D3>
+// ENFW = false: no elliptical NFW halos in the lens (their quadrature is compiled out).
+template <bool D3, bool ENFW = true>
 __device__ __forceinline__ void full_sum64(const Plane64& P, double x, double y, const Quad& qd, Acc& acc) {
   for (int c = 0; c < P.n_main; ++c) {
     const MainRec r = P.mains[c];
-    eval_main<D3>(r, x, y, qd, acc);
+    eval_main<D3, ENFW>(r, x, y, qd, acc);
     acc.flags |= r.flags;
   }
   double px[1] = {x}, py[1] = {y};
@@ -453,7 +454,7 @@ __device__ __forceinline__ void full_sum64(const Plane64& P, double x, double y,
   seg_loop<SEG_ESIE, D3, 1>(P.mem, nullptr, so.off[SEG_ESIE], so.off[SEG_ESIE + 1], px, py, a1, qd);
   seg_loop<SEG_POINT, D3, 1>(P.mem, nullptr, so.off[SEG_POINT], so.off[SEG_POINT + 1], px, py, a1, qd);
   seg_loop<SEG_NFW, D3, 1>(P.mem, nullptr, so.off[SEG_NFW], so.off[SEG_NFW + 1], px, py, a1, qd);
-  seg_loop<SEG_ENFW, false, 1>(P.mem, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, a1, qd);
+  if constexpr (ENFW) seg_loop<SEG_ENFW, D3, 1>(P.mem, nullptr, so.off[SEG_ENFW], so.off[SEG_ENFW + 1], px, py, a1, qd);
   acc = a1[0];
 }
 

@@ -23,6 +23,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "lf_api_internal.h"
@@ -318,7 +319,7 @@ void launch_chi2_batch(lf_server* s) {
   hipEventRecord(u.ev, st);
   u.reqs = batch;
   s->busy[0] = true;
-  s->inflight.push_back(u);
+  s->inflight.push_back(std::move(u));   // moved: the host buffers the copies read stay alive
 }
 
 void launch_map_chunk(lf_server* s, int si, const std::shared_ptr<Req>& qp) {
@@ -367,7 +368,7 @@ void launch_map_chunk(lf_server* s, int si, const std::shared_ptr<Req>& qp) {
   u.ev = s->ev();
   hipEventRecord(u.ev, st);
   s->busy[si] = true;
-  s->inflight.push_back(u);
+  s->inflight.push_back(std::move(u));   // moved: the host buffers the copies read stay alive
 }
 
 }  // namespace
@@ -495,7 +496,6 @@ extern "C" lf_status lf_serve_submit(lf_server* s, const lf_request* req, int64_
   } else if (r.kind == LF_REQ_MU_MAP || r.kind == LF_REQ_SING_MAP) {
     if (r.grid.nx < 1 || r.grid.ny < 1 || !(r.grid.h > 0) || !(r.a_dis > 0) || (r.model->n_free > 0 && !r.params))
       return LF_E_INVALID_ARG;
-    if (r.kind == LF_REQ_SING_MAP && lf_model_has_enfw(r.model)) return LF_E_UNSUPPORTED;
     if (r.model->n_free > 0) q->params.assign(r.params, r.params + r.model->n_free);
     q->footprint = map_footprint(s, r);
   } else {

@@ -16,6 +16,7 @@ struct SingArgs {
   const double* f2;
   const int* vflags;
   Plane64 pl;                // FP64 lens for the refinement evaluations
+  int enfw;                  // the lens has elliptical NFW halos (selects the kernel variants)
   Quad qd;
   int refine;
   double tol;                // crossing bracket [arcsec]

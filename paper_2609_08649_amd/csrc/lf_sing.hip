@@ -64,15 +64,16 @@ __device__ __forceinline__ VA3 vertex_a3(const SingArgs& A, int i, int j) {
 }
 
 // FP64 evaluation at one point: by the whole wave (LANE = false; every lane returns the same
-// bits) or by each lane at its own point (LANE = true; every lane walks the same halo list)
-template <bool LANE = false>
+// bits) or by each lane at its own point (LANE = true; every lane walks the same halo list).
+// E = false: the lens has no elliptical NFW halo (their quadrature is compiled out).
+template <bool LANE, bool E>
 __device__ VA3 point_a3(const SingArgs& A, double x, double y) {
   Acc acc;
   if (LANE) {
     acc.zero();
-    full_sum64<true>(A.pl, x, y, A.qd, acc);
+    full_sum64<true, E>(A.pl, x, y, A.qd, acc);
   } else {
-    plane_sum_wave<true>(A.pl, x, y, A.qd, acc);
+    plane_sum_wave<true, E>(A.pl, x, y, A.qd, acc);
   }
   VA3 o;
   const double kap = 0.5 * (acc.h11 + acc.h22), g1 = 0.5 * (acc.h11 - acc.h22), g2 = acc.h12;
@@ -101,7 +102,7 @@ __device__ __forceinline__ long long edge_key(int nx, int i, int j, int dir, int
 // Central differences of f_k aligned with P's eigenvector, at (x +- d, y) and (x, y +- d):
 // returns (f(x+d) - f(x-d)) / 2d and (f(y+d) - f(y-d)) / 2d.  One evaluation site in a loop
 // keeps the register footprint of a single halo sum.
-template <bool LANE = false>
+template <bool LANE, bool E>
 __device__ void fd_grad(const SingArgs& A, const VA3& P, double x, double y, int k, double d, bool& umb,
                         double& fx, double& fy) {
   double sx = 0.0, sy = 0.0;
@@ -109,7 +110,7 @@ __device__ void fd_grad(const SingArgs& A, const VA3& P, double x, double y, int
   for (int m = 0; m < 4; ++m) {
     const double qx = m == 0 ? x + d : m == 1 ? x - d : x;
     const double qy = m == 2 ? y + d : m == 3 ? y - d : y;
-    const VA3 q = point_a3<LANE>(A, qx, qy);
+    const VA3 q = point_a3<LANE, E>(A, qx, qy);
     if (q.umb) umb = true;
     const double F = align(P, q, k) * q.f(k);
     if (m == 0) sx = F;
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_sing_keys(const SingArgs A) {
 // ---------------------------------------------------------------------------------------
 // 2. refinement of each crossing (one wave per crossing, persistent waves)
 // ---------------------------------------------------------------------------------------
-template <bool LANE>
+template <bool LANE, bool E>
 __device__ void refine_crossing(const SingArgs& A, int n) {
   const long long key = A.ckey[n];
   const int k = (int)(key & 1);
@@ -254,7 +255,7 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     for (int it = 0; it < 100 && !done; ++it) {
       double tn = (t0 * F1 - t1 * F0) / (F1 - F0);
       if (!(tn > t0 && tn < t1)) tn = 0.5 * (t0 + t1);
-      const VA3 q = point_a3<LANE>(A, ax + tn * dxh, ay + tn * dyh);
+      const VA3 q = point_a3<LANE, E>(A, ax + tn * dxh, ay + tn * dyh);
       if (q.umb) flags |= 1;
       const double F = align(a, q, k) * q.f(k);
       t = tn;
@@ -273,7 +274,7 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     if (!done) flags |= 2;
   }
   const double cx = ax + t * dxh, cy = ay + t * dyh;
-  const VA3 P = point_a3<LANE>(A, cx, cy);
+  const VA3 P = point_a3<LANE, E>(A, cx, cy);
   const double e = P.e(k);
   double g = 0.0;
   if (P.umb) {
@@ -282,7 +283,7 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
     if (A.refine && fabs(P.f(k)) > 1e-3 * Fend) flags |= 4;     // a jump, not a root
     bool u = false;
     double fx, fy;
-    fd_grad<LANE>(A, P, cx, cy, k, 1e-3 * A.h, u, fx, fy);
+    fd_grad<LANE, E>(A, P, cx, cy, k, 1e-3 * A.h, u, fx, fy);
     if (u) flags |= 1;
     g = P.vx(k) * fx + P.vy(k) * fy;
   }
@@ -297,9 +298,10 @@ __device__ void refine_crossing(const SingArgs& A, int n) {
 }
 // one lane per crossing: lanes of a wave hold neighbouring edges of a row, iterate alike and
 // read every halo record at the same time (scalar loads)
+template <bool E>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_sing_refine(const SingArgs A) {
   const int n = blockIdx.x * NT + threadIdx.x;
-  if (n < n_cross(A)) refine_crossing<true>(A, n);
+  if (n < n_cross(A)) refine_crossing<true, E>(A, n);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -425,6 +427,7 @@ __global__ __launch_bounds__(NT) void k_sing_cells(const SingArgs A) {
 //    (converged inside the closed cell), 1 no convergence in 30 steps, 2 outside (| 4 from
 //    the cell pass: a family's crossings could not be joined to it)
 // ---------------------------------------------------------------------------------------
+template <bool E>
 __device__ void umbilic_one(const SingArgs& A, int n) {
   const int i = A.ucell[2 * (size_t)n], j = A.ucell[2 * (size_t)n + 1];
   const double xl = A.x0 + (i + 0.5) * A.h, xr = A.x0 + (i + 1.5) * A.h;
@@ -433,7 +436,7 @@ __device__ void umbilic_one(const SingArgs& A, int n) {
   bool conv = false;
   Acc acc;
   for (int it = 0; it < 30; ++it) {
-    plane_sum_wave<true>(A.pl, x, y, A.qd, acc);
+    plane_sum_wave<true, E>(A.pl, x, y, A.qd, acc);
     const double g1 = 0.5 * (acc.h11 - acc.h22), g2 = acc.h12;
     const double J11 = 0.5 * (acc.t111 - acc.t122), J12 = 0.5 * (acc.t112 - acc.t222);
     const double J21 = acc.t112, J22 = acc.t122;
@@ -444,7 +447,7 @@ __device__ void umbilic_one(const SingArgs& A, int n) {
     if (sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
     if (!isfinite(x) || !isfinite(y)) break;
   }
-  plane_sum_wave<true>(A.pl, x, y, A.qd, acc);
+  plane_sum_wave<true, E>(A.pl, x, y, A.qd, acc);
   int st = 1;
   if (conv) st = (x >= xl && x <= xr && y >= yl && y <= yr) ? 0 : 2;
   if ((threadIdx.x & 63) == 0) {
@@ -454,10 +457,11 @@ __device__ void umbilic_one(const SingArgs& A, int n) {
     A.ustat[n] |= st;
   }
 }
+template <bool E>
 __global__ __launch_bounds__(NT) void k_sing_umb(const SingArgs A) {
   const int nU = min(A.counts[2], A.cap);
   const int nw = gridDim.x * (NT / 64);
-  for (int n = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); n < nU; n += nw) umbilic_one(A, n);
+  for (int n = blockIdx.x * (NT / 64) + (threadIdx.x >> 6); n < nU; n += nw) umbilic_one<E>(A, n);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -500,14 +504,17 @@ __global__ __launch_bounds__(NT) void k_sing_swt(const SingArgs A) {
 }
 
 // Newton on (f_k, g_k) = 0 from the interpolated point, g_k = v_k . grad f_k with grad f_k by
-// central differences (step 1e-3 h) and grad g_k by central differences of g (step 1e-2 h):
-// status 0 converged (step < 1e-10") within h of the start, 1 no convergence in 20 steps, 2
-// moved farther than h (the interpolated point is kept), | 8 an umbilic-flagged evaluation;
-// then e_k at the point.  One workgroup per swallowtail: a step needs 25 evaluations (g at the
+// central differences (step 1e-3 h) and grad g_k by central differences of g (step 1e-2 h),
+// stopped after a step below 1e-10", after 20 steps or on leaving the disc of radius h about
+// the start: status 0 converged (last step below 1e-8", two decades above the stopping step and
+// the ~1e-9" rounding noise that the finite-difference g leaves under the steps) within h of
+// the start, 1 no convergence, 2 left the disc (the interpolated point is kept), | 8 an
+// umbilic-flagged evaluation; then e_k at the point.  One workgroup per swallowtail: a step needs 25 evaluations (g at the
 // point and at (x +- dg, y), (x, y +- dg), each from its point and four difference points),
 // spread over SWT_WAVES waves (four rounds); each wave keeps f_k, v_k and the umbilic flag of
 // its evaluations in LDS, and every thread then forms the differences in the same order.
 constexpr int SWT_WAVES = 8;
+template <bool E>
 __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingArgs A) {
   __shared__ double ev[25][3];
   __shared__ int eu[25];
@@ -520,7 +527,8 @@ __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingAr
     int st = 0;
     if (A.refine) {
       const double d = 1e-3 * A.h, dg = 1e-2 * A.h;
-      bool conv = false, umb = false;
+      bool umb = false;
+      double last = HUGE_VAL;
       for (int it = 0; it < 20; ++it) {
         // evaluation e = 5 m + c: stencil point m of g (0 the point, 1/2 x +- dg, 3/4 y +- dg),
         // c = 0 that point, 1..4 its f stencil (x + d, x - d, y + d, y - d)
@@ -530,7 +538,7 @@ __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingAr
           const double qy = m == 3 ? y + dg : m == 4 ? y - dg : y;
           const double px = c == 1 ? qx + d : c == 2 ? qx - d : qx;
           const double py = c == 3 ? qy + d : c == 4 ? qy - d : qy;
-          const VA3 P = point_a3(A, px, py);
+          const VA3 P = point_a3<false, E>(A, px, py);
           if ((threadIdx.x & 63) == 0) {
             ev[e][0] = P.f(k); ev[e][1] = P.vx(k); ev[e][2] = P.vy(k);
             eu[e] = P.umb ? 1 : 0;
@@ -558,16 +566,18 @@ __global__ __launch_bounds__(64 * SWT_WAVES) void k_sing_swt_refine(const SingAr
         const double sx = -(gy * f - fy * g[0]) / det, sy = -(-gx * f + fx * g[0]) / det;
         x += sx;
         y += sy;
-        if (!isfinite(x) || !isfinite(y)) break;
-        if (sqrt(sx * sx + sy * sy) < 1e-10) { conv = true; break; }
+        if (!isfinite(x) || !isfinite(y)) { last = HUGE_VAL; break; }
+        last = sqrt(sx * sx + sy * sy);
+        if (last < 1e-10) break;
+        if (hypot(x - x0, y - y0) > A.h) break;
       }
-      st = conv ? 0 : 1;
-      if (conv && sqrt((x - x0) * (x - x0) + (y - y0) * (y - y0)) > A.h) st = 2;
+      st = last < 1e-8 ? 0 : 1;
+      if (hypot(x - x0, y - y0) > A.h) st = 2;
       if (umb) st |= 8;
       if (st != 0) { x = x0; y = y0; }
     }
     if (wv == 0) {
-      const VA3 P = point_a3(A, x, y);
+      const VA3 P = point_a3<false, E>(A, x, y);
       if (threadIdx.x == 0) {
         A.wpos[2 * (size_t)n] = x;
         A.wpos[2 * (size_t)n + 1] = y;
@@ -589,7 +599,9 @@ hipError_t launch_sing(const SingArgs& A, int n_cu, hipStream_t st, void (*mark)
   hipLaunchKernelGGL(k_sing_keys, dim3(A.ny), dim3(NT), 0, st, A);
   mark(ctx, "sing_edges", 1);
   mark(ctx, "sing_refine", 0);
-  hipLaunchKernelGGL(k_sing_refine, dim3((unsigned)((A.cap + NT - 1) / NT)), dim3(NT), 0, st, A);
+  const dim3 g_ref((unsigned)((A.cap + NT - 1) / NT));
+  if (A.enfw) hipLaunchKernelGGL(k_sing_refine<true>, g_ref, dim3(NT), 0, st, A);
+  else hipLaunchKernelGGL(k_sing_refine<false>, g_ref, dim3(NT), 0, st, A);
   mark(ctx, "sing_refine", 1);
   mark(ctx, "sing_cells", 0);
   hipLaunchKernelGGL(k_sing_cells<false>, dim3(A.ny - 1), dim3(NT), 0, st, A);
@@ -600,13 +612,15 @@ hipError_t launch_sing(const SingArgs& A, int n_cu, hipStream_t st, void (*mark)
   hipLaunchKernelGGL(k_sing_cells<true>, dim3(A.ny - 1), dim3(NT), 0, st, A);
   mark(ctx, "sing_cells", 1);
   mark(ctx, "sing_umb", 0);
-  hipLaunchKernelGGL(k_sing_umb, dim3(waves_grid), dim3(NT), 0, st, A);
+  if (A.enfw) hipLaunchKernelGGL(k_sing_umb<true>, dim3(waves_grid), dim3(NT), 0, st, A);
+  else hipLaunchKernelGGL(k_sing_umb<false>, dim3(waves_grid), dim3(NT), 0, st, A);
   mark(ctx, "sing_umb", 1);
   mark(ctx, "sing_swt", 0);
   hipLaunchKernelGGL(k_sing_swt<false>, dim3(chunks), dim3(NT), 0, st, A);
   hipLaunchKernelGGL(k_sing_scan, dim3(1), dim3(NT), 0, st, A.wch_cnt, (int)chunks, A.wch_off, A.counts + 3);
   hipLaunchKernelGGL(k_sing_swt<true>, dim3(chunks), dim3(NT), 0, st, A);
-  hipLaunchKernelGGL(k_sing_swt_refine, dim3(n_cu * 4), dim3(64 * SWT_WAVES), 0, st, A);
+  if (A.enfw) hipLaunchKernelGGL(k_sing_swt_refine<true>, dim3(n_cu * 4), dim3(64 * SWT_WAVES), 0, st, A);
+  else hipLaunchKernelGGL(k_sing_swt_refine<false>, dim3(n_cu * 4), dim3(64 * SWT_WAVES), 0, st, A);
   mark(ctx, "sing_swt", 1);
   return hipGetLastError();
 }

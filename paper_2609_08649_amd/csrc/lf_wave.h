@@ -1,8 +1,8 @@
 // FP64 lens evaluation for a handful of points (polishing and refinement passes): one wave per
 // point, the halos of a plane split over the 64 lanes, partial sums combined by a butterfly
 // of shuffles (every lane ends with the same bits), the iteration logic run redundantly by
-// all lanes.  D3: third derivatives too (not for elliptical NFW, which callers exclude; its
-// terms are then flagged invalid).
+// all lanes.  D3: third derivatives too.  ENFW = false compiles the elliptical NFW quadrature
+// out (for lenses without such halos; their kernels then need fewer registers).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -10,7 +10,7 @@
 
 namespace lf {
 
-template <bool D3>
+template <bool D3, bool ENFW = true>
 __device__ void member64_term(const Plane64& P, int m, double x, double y, const Quad& qd, Acc& acc) {
   int sg = 0;
   while (sg + 1 < NSEG && m >= P.seg.off[sg + 1]) ++sg;
@@ -29,11 +29,15 @@ __device__ void member64_term(const Plane64& P, int m, double x, double y, const
     case SEG_POINT: point_mass<D3>(dx, dy, r.b, t); break;
     case SEG_NFW: nfw_circ<D3>(dx, dy, r.b, r.s, t); break;
     default: {
-      if (D3) { acc.flags |= FL_INVALID; return; }
-      double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
-      Term<double> pr;
-      enfw_prime(xp, yp, r.b, r.s, sqrt(r.q2), qd, pr);
-      rotate_back<false>(r.c, r.sn, pr, t);
+      if constexpr (ENFW) {
+        double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
+        Term<double> pr;
+        enfw_prime<D3>(xp, yp, r.b, r.s, sqrt(r.q2), qd, pr);
+        rotate_back<D3>(r.c, r.sn, pr, t);
+      } else {
+        acc.flags |= FL_INVALID;
+        return;
+      }
     }
   }
   add<D3>(acc, t);
@@ -50,7 +54,7 @@ __device__ __forceinline__ int wor(int v) {
   return v;
 }
 
-template <bool D3>
+template <bool D3, bool ENFW = true>
 __device__ void plane_sum_wave(const Plane64& P, double x, double y, const Quad& qd, Acc& out) {
   Acc acc;
   acc.zero();
@@ -59,10 +63,10 @@ __device__ void plane_sum_wave(const Plane64& P, double x, double y, const Quad&
   for (int h = lane; h < H; h += 64) {
     if (h < P.n_main) {
       const MainRec r = P.mains[h];
-      eval_main<D3, !D3>(r, x, y, qd, acc);
+      eval_main<D3, ENFW>(r, x, y, qd, acc);
       acc.flags |= r.flags;
     } else {
-      member64_term<D3>(P, h - P.n_main, x, y, qd, acc);
+      member64_term<D3, ENFW>(P, h - P.n_main, x, y, qd, acc);
     }
   }
   out.ax = wsum(acc.ax); out.ay = wsum(acc.ay);

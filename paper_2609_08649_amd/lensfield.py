@@ -105,6 +105,7 @@ def lib():
             "lf_chi2_batch": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
             "lf_chi2_terms": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P, P]),
             "lf_chi2_batch_noalloc": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
+            "lf_chi2_images": (I32, [P, P, P, I32, P, I32, P, P, P, P, P, P]),
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
             "lf_find_images_ms": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
@@ -400,6 +401,28 @@ def _chi2_terms(self, model: Model, params, S, cons: Constraints, mode=0, prec=L
 
 
 Context.chi2_terms = _chi2_terms
+
+
+def _chi2_images(self, model: Model, params, S, cons: Constraints, prec=LF_PREC_FP64, stream=None):
+    """Image-plane chi^2 with per-image results (device tensors): chi2 [S], flags [S],
+    beta_model [S, n_fam, 2], theta_model [S, n_img, 2] and img_flags [S, n_img] in the constraint
+    order."""
+    dev = self.device
+    n = cons.n_img
+    r = {"chi2": torch.empty(S, dtype=torch.float64, device=dev),
+         "flags": torch.empty(S, dtype=torch.int32, device=dev),
+         "beta_model": torch.empty((S, cons.n_fam, 2), dtype=torch.float64, device=dev),
+         "theta_model": torch.empty((S, n, 2), dtype=torch.float64, device=dev),
+         "img_flags": torch.empty((S, n), dtype=torch.int32, device=dev)}
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_chi2_images(self.handle, model.handle, pp, int(S), cons.handle, int(prec),
+                                    *[C.c_void_p(r[k].data_ptr()) for k in
+                                      ("chi2", "flags", "beta_model", "theta_model", "img_flags")],
+                                    _stream(stream)))
+    return r
+
+
+Context.chi2_images = _chi2_images
 
 
 def _find(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, stream=None, out=None):

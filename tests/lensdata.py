@@ -165,3 +165,67 @@ def cluster_sources(seed=2611):
     grid = {"x0": -60.0, "y0": -60.0, "h": 0.25, "nx": 480, "ny": 480}
     srcs = select_sources(orc, tab, grid, cfg["src_cand"], cfg["zs_cand"], cfg["model"]["z_d"], cfg["n_src"])
     return np.array([s[0] for s in srcs]), np.array([s[1] for s in srcs]), np.array([s[2] for s in srcs])
+
+
+def mu_max(orc, tabs, cons):
+    """Largest |mu| over the observed images of each sample (conditioning of W = mu^T S^-1 mu)."""
+    a = cons["a_fam"][cons["family"]]
+    out = np.zeros(len(tabs))
+    for s, t in enumerate(tabs):
+        m = orc.maps(t, cons["theta"][:, 0], cons["theta"][:, 1], 1.0)
+        det = (1 - a * m["p11"]) * (1 - a * m["p22"]) - a * a * m["p12"] ** 2
+        out[s] = np.max(np.abs(1 / det))
+    return out
+
+
+def stable_image_plane(orc, tabs, cons, ref, eps=1e-5):
+    """Samples whose image-plane chi^2 is well posed: in the oracle every image's Newton solve
+    converges and is accepted, and the result moves by less than 1e-4 (relative) when every
+    observed position is shifted by eps in three directions.  Newton basins have fractal
+    boundaries; where an image does not converge within the step budget, or a 1e-5" shift
+    changes which root it reaches, two correct implementations may legitimately disagree."""
+    base = orc.chi2_batch(tabs, cons, img_mode=True)
+    ok = (base["flags"] & 12) == 0            # every image converged and was accepted
+    for d in ((eps, 0.0), (0.0, eps), (-eps, eps)):
+        r = orc.chi2_batch(tabs, dict(cons, theta=cons["theta"] + np.array(d)), img_mode=True)
+        ok &= np.abs(r["chi2_img"] - ref) <= 1e-4 * np.abs(ref) + 1e-4
+    return ok
+
+
+def mu_images(orc, tabs, cons):
+    """mu at every observed image of every sample, [S, n_img]."""
+    a = cons["a_fam"][cons["family"]]
+    out = np.zeros((len(tabs), a.size))
+    for s, t in enumerate(tabs):
+        m = orc.maps(t, cons["theta"][:, 0], cons["theta"][:, 1], 1.0)
+        out[s] = 1 / ((1 - a * m["p11"]) * (1 - a * m["p22"]) - a * a * m["p12"] ** 2)
+    return out
+
+
+def key_map(r, grid):
+    """Crossings of a singularity map keyed by (row, column, edge direction, family) of their
+    grid edge, so that maps of different windows of the same vertices can be matched."""
+    out = {}
+    for n, (p, k) in enumerate(zip(r["cross"]["pos"], r["cross"]["k"])):
+        fi = (p[0] - grid["x0"]) / grid["h"] - 0.5
+        fj = (p[1] - grid["y0"]) / grid["h"] - 0.5
+        if abs(fj - round(fj)) < 1e-7:
+            key = (int(round(fj)), int(np.floor(fi + 1e-9)), 0, int(k))
+        else:
+            key = (int(np.floor(fj + 1e-9)), int(round(fi)), 1, int(k))
+        out[key] = n
+    return out
+
+
+def ainv_norm(orc, tabs, cons, theta):
+    """Spectral norm of A^-1 = (I - a psi)^-1 at positions theta [S, n_img, 2] (each image at its
+    family's distance ratio): how far an error in beta moves a root of the lens equation."""
+    a = cons["a_fam"][cons["family"]]
+    out = np.zeros(theta.shape[:2])
+    for s, t in enumerate(tabs):
+        m = orc.maps(t, theta[s, :, 0], theta[s, :, 1], 1.0)
+        A11, A12, A22 = 1 - a * m["p11"], -a * m["p12"], 1 - a * m["p22"]
+        # eigenvalues of the symmetric A: the smallest |lambda| sets the norm of A^-1
+        h, d = 0.5 * (A11 + A22), np.hypot(0.5 * (A11 - A22), A12)
+        out[s] = 1 / np.minimum(np.abs(h - d), np.abs(h + d))
+    return out

@@ -8,6 +8,7 @@ import pytest
 
 from paper_2609_08649_amd import workloads as W
 from tests import lensdata
+from tests.lensdata import ainv_norm, mu_images, mu_max, stable_image_plane
 
 pytestmark = pytest.mark.gpu
 
@@ -45,31 +46,6 @@ def _gpu(ctx, lf, model, params, cons, mode, prec):
     c.release()
     m.release()
     return out
-
-
-def mu_max(orc, tabs, cons):
-    """Largest |mu| over the observed images of each sample (conditioning of W = mu^T S^-1 mu)."""
-    a = cons["a_fam"][cons["family"]]
-    out = np.zeros(len(tabs))
-    for s, t in enumerate(tabs):
-        m = orc.maps(t, cons["theta"][:, 0], cons["theta"][:, 1], 1.0)
-        det = (1 - a * m["p11"]) * (1 - a * m["p22"]) - a * a * m["p12"] ** 2
-        out[s] = np.max(np.abs(1 / det))
-    return out
-
-
-def stable_image_plane(orc, tabs, cons, ref, eps=1e-5):
-    """Samples whose image-plane chi^2 is well posed: in the oracle every image's Newton solve
-    converges and is accepted, and the result moves by less than 1e-4 (relative) when every
-    observed position is shifted by eps in three directions.  Newton basins have fractal
-    boundaries; where an image does not converge within the step budget, or a 1e-5" shift
-    changes which root it reaches, two correct implementations may legitimately disagree."""
-    base = orc.chi2_batch(tabs, cons, img_mode=True)
-    ok = (base["flags"] & 12) == 0            # every image converged and was accepted
-    for d in ((eps, 0.0), (0.0, eps), (-eps, eps)):
-        r = orc.chi2_batch(tabs, dict(cons, theta=cons["theta"] + np.array(d)), img_mode=True)
-        ok &= np.abs(r["chi2_img"] - ref) <= 1e-4 * np.abs(ref) + 1e-4
-    return ok
 
 
 def _close(g, o, prec, mu=None):
@@ -128,6 +104,80 @@ def test_chi2_cluster_image_plane_subset(ctx, lf, orc, shrink, min_frac):
         g, fl, _ = _gpu(ctx, lf, cfg["model"], params, cons, 1, P)
         _close(g[st], o["chi2_img"][st], prec, mu[st])
         assert np.array_equal(fl[st] & 4, o["flags"][st] & 4)
+
+
+def test_chi2_cluster_image_plane_every_image(ctx, lf, orc):
+    """Image-plane chi^2 on all 1024 cluster samples, image by image (lf_chi2_images).  Where both
+    sides accept an image and reach the same root (|d theta| < 1e-4"), the model positions agree
+    within 1e-9" + 2 |A^-1| |d beta_model| of the image's family: the Newton solve chases a
+    beta_model that the two source-plane fits set to within d beta_model (rounding in FP64 -- up
+    to ~1e-7" for a family whose matrix G is nearly singular -- and the member-term error in
+    MIXED), and an error in beta moves a root by A^-1 of it.  Samples on which every image's
+    decision and root agree are compared as in the subset test.  The fraction of images whose
+    Newton decision (converged, accepted, root) differs is printed; Newton basins have fractal
+    boundaries, so it is bounded by 2% rather than zero."""
+    import torch
+    cfg = W.config2(n_samples=1024)
+    cons = lensdata.cluster_constraints()
+    tabs = orc.expand_batch(cfg["model"], cfg["params"])
+    o = orc.chi2_batch(tabs, cons, img_mode=True)
+    mu = np.abs(mu_images(orc, tabs, cons))
+    ainv = ainv_norm(orc, tabs, cons, o["theta_model"])
+    m = ctx.upload_model(cfg["model"])
+    c = ctx.upload_constraints(cons)
+    pp = torch.as_tensor(cfg["params"], device="cuda")
+    fam = cons["family"]
+    for prec, P in (("fp64", lf.LF_PREC_FP64), ("mixed", lf.LF_PREC_MIXED)):
+        g = ctx.chi2_images(m, pp, 1024, c, P)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in g.items()}
+        both_ok = (g["img_flags"] == 0) & (o["img_flags"] == 0)
+        d = np.abs(g["theta_model"] - o["theta_model"]).max(axis=2)
+        same = both_ok & (d < 1e-4)
+        agree = (g["img_flags"] == o["img_flags"]) & (same | ~both_ok)
+        dbm = np.hypot(*(g["beta_model"] - o["beta_model"]).transpose(2, 0, 1))[:, fam]
+        tol = 1e-9 + 2 * ainv * dbm
+        assert np.all(d[same] <= tol[same]), (prec, np.max(d[same] / tol[same]))
+        frac = 1 - agree.mean()
+        print("chi2_img %s: %d of %d images accepted on both sides at the same root; differing Newton "
+              "decisions %.4f%%" % (prec, same.sum(), same.size, 100 * frac), flush=True)
+        assert frac <= 0.02
+        assert same.mean() >= 0.5
+        whole = agree.all(axis=1)
+        assert whole.mean() >= 0.3
+        _close(g["chi2"][whole], o["chi2_img"][whole], prec, mu.max(axis=1)[whole])
+        assert np.array_equal(g["flags"][whole] & 12, o["flags"][whole] & 12)
+    c.release()
+    m.release()
+
+
+def test_chi2_images_order_and_totals(ctx, lf, orc):
+    """lf_chi2_images returns lf_chi2_batch's mode-1 results bit for bit, and its per-image
+    outputs in the caller's constraint order (families given interleaved here, so the library's
+    family sort is not the identity)."""
+    import torch
+    model, truth, cons = lensdata.small_constraints(42)
+    perm = np.random.default_rng(5).permutation(cons["family"].size)
+    cons = dict(cons, theta=cons["theta"][perm], family=cons["family"][perm], sig1=cons["sig1"][perm],
+                sig2=cons["sig2"][perm], phi=cons["phi"][perm])
+    params = _jitter(truth, 37, 42)
+    tabs = orc.expand_batch(model, params)
+    o = orc.chi2_batch(tabs, cons, img_mode=True)
+    m = ctx.upload_model(model)
+    c = ctx.upload_constraints(cons)
+    pp = torch.as_tensor(params, device="cuda")
+    g = ctx.chi2_images(m, pp, 37, c, lf.LF_PREC_FP64)
+    chi, fl, bm = ctx.chi2_batch(m, pp, 37, c, 1, lf.LF_PREC_FP64, want_beta=True)
+    torch.cuda.synchronize()
+    assert torch.equal(g["chi2"], chi) and torch.equal(g["flags"], fl) and torch.equal(g["beta_model"], bm)
+    th, ifl = g["theta_model"].cpu().numpy(), g["img_flags"].cpu().numpy()
+    ok = (ifl == 0) & (o["img_flags"] == 0)
+    assert ok.mean() > 0.5
+    assert np.abs(th - o["theta_model"]).max(axis=2)[ok].max() < 1e-6
+    # an image's flags are those the per-sample flags collect
+    assert np.array_equal(np.bitwise_or.reduce(ifl, axis=1) & 12, fl.cpu().numpy() & 12)
+    c.release()
+    m.release()
 
 
 def test_chi2_same_alone_and_in_batch(ctx, lf):

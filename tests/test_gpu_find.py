@@ -118,3 +118,44 @@ def test_find_overflow_reports_true_count(ctx, lf, orc):
     assert np.array_equal(g["count"], o["count"])
     assert np.all(g["flags"][o["count"] > 2] & lf.FLAG_OVERFLOW)
     assert np.allclose(g["theta"][:, :2], o["theta"][:, :2], atol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_find_more_candidates_than_one_workgroup_sorts(ctx, lf, orc, prec):
+    """2000 copies of the five config-1 sources (10^4 sources, about 3 x 10^4 candidate triangles:
+    more than one workgroup's LDS could sort, and more than 1024 sources per prefix-sum chunk):
+    every copy gives the oracle's images of the five."""
+    cfg = W.config1()
+    beta, a = lensdata.config1_sources()
+    o = orc.find_images(orc.expand(cfg["model"]), cfg["grid"], beta, np.full(5, a))
+    reps = 2000
+    assert o["n_cand"] * reps > 3 * 8192
+    g = _run(ctx, lf, cfg["model"], None, np.tile(beta, (reps, 1)), a, cfg["grid"], prec)
+    assert not np.any(g["flags"] & lf.FLAG_OVERFLOW)
+    for r in range(0, reps, 7):
+        compare({k: v[5 * r:5 * r + 5] for k, v in g.items()}, o, 1e-9 if prec == "fp64" else 1e-4)
+    assert np.array_equal(g["count"], np.tile(o["count"], reps))
+
+
+def test_find_candidate_overflow_is_deterministic(lf, orc, monkeypatch):
+    """A candidate capacity of 64 (LF_FIND_CAND_CAP) for 300 sources: the sources whose
+    candidates fit, in source order, are found exactly as with room to spare; every later source
+    gets count 0 and the overflow flag; two runs agree bit for bit."""
+    monkeypatch.setenv("LF_FIND_CAND_CAP", "64")
+    small = lf.Context(0)
+    cfg = W.config1()
+    beta, a = lensdata.config1_sources()
+    o = orc.find_images(orc.expand(cfg["model"]), cfg["grid"], beta, np.full(5, a))
+    bb = np.tile(beta, (60, 1))
+    g1 = _run(small, lf, cfg["model"], None, bb, a, cfg["grid"], "fp64")
+    g2 = _run(small, lf, cfg["model"], None, bb, a, cfg["grid"], "fp64")
+    small.close()
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k]), k
+    over = (g1["flags"] & lf.FLAG_OVERFLOW) != 0
+    first = int(np.argmax(over))
+    assert over.any() and first >= 5 and over[first:].all() and not over[:first].any()
+    assert np.all(g1["count"][first:] == 0)
+    for s in range(first):
+        compare({k: v[s:s + 1] for k, v in g1.items()}, {k: v[s % 5:s % 5 + 1] for k, v in o.items()
+                                                          if k in ("count", "theta", "mu")}, 1e-9)

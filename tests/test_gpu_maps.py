@@ -39,10 +39,11 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
 
 
-def check(gpu, orc_out, prec, d3=False, sl=slice(None), a_dis=None):
+def check(gpu, orc_out, prec, d3=False, sl=slice(None), a_dis=None, a=None):
     """Compare GPU planes (numpy) with oracle columns at tolerances of the precision.  With
     a_dis given, relative mu errors are divided by the condition number of det A,
-    (|A11 A22| + A12^2) / |det A| (near a singular centre det A ~ 1e9 from terms ~ 1e18)."""
+    (|A11 A22| + A12^2) / |det A| (near a singular centre det A ~ 1e9 from terms ~ 1e18).  The
+    MIXED det A check needs the distance ratio of the maps (a, or a_dis)."""
     ax, ay = gpu["alpha_x"][sl], gpu["alpha_y"][sl]
     dal = np.hypot(ax - orc_out["ax"], ay - orc_out["ay"])
     amag = np.hypot(orc_out["ax"], orc_out["ay"])
@@ -78,10 +79,50 @@ def check(gpu, orc_out, prec, d3=False, sl=slice(None), a_dis=None):
         for k in ("p11", "p12", "p22", "kappa", "gamma1", "gamma2"):
             g, o = gpu[OR2GPU[k]][sl], orc_out[k]
             assert np.max(np.abs(g - o) / (1 + np.abs(o))) < 1e-5, k
+        # beta = theta - a alpha: |d beta| = a |d alpha|
+        if "beta_x" in gpu:
+            db = np.hypot(gpu["beta_x"][sl] - orc_out["beta_x"], gpu["beta_y"][sl] - orc_out["beta_y"])
+            assert np.max(db) <= 1e-5, np.max(db)
+        # det A = A11 A22 - A12^2 with A = I - a psi: first-order propagation of the psi bound
+        # d psi <= 1e-5 (1 + |psi|)
+        a = a if a is not None else a_dis
+        if a is not None:
+            A11, A22, A12 = 1 - a * orc_out["p11"], 1 - a * orc_out["p22"], -a * orc_out["p12"]
+            dpsi = 1e-5 * (1 + np.maximum(np.maximum(np.abs(orc_out["p11"]), np.abs(orc_out["p22"])),
+                                          np.abs(orc_out["p12"])))
+            bound = a * (np.abs(A11) + np.abs(A22) + 2 * np.abs(A12)) * dpsi + 1e-12
+            assert np.max(np.abs(gpu["detA"][sl] - orc_out["detA"]) / bound) <= 1.0
+        # e1,2 = kappa +- |gamma|
+        if "e1" in gpu:
+            gm = np.hypot(orc_out["gamma1"], orc_out["gamma2"])
+            scale = 1 + np.abs(orc_out["kappa"]) + gm
+            for k in ("e1", "e2"):
+                assert np.max(np.abs(gpu[k][sl] - orc_out[k]) / scale) < 2e-5, k
         if d3:
             for k in ("p111", "p112", "p122", "p222"):
                 g, o = gpu[OR2GPU[k]][sl], orc_out[k]
                 assert np.max(np.abs(g - o) / (1 + np.abs(o))) < 1e-4, k
+            check_fields(gpu, orc_out, sl, 1e-4)
+
+
+def check_fields(gpu, o, sl, tol):
+    """Signed A3-line fields f1, f2 where they are well conditioned: |gamma| > 0.05 (the
+    eigenvectors turn as d gamma / |gamma|) and the eigenvector sign rule (positive x component)
+    is not ambiguous (|x component| > 1e-3).  Error scale: the third derivatives the field is
+    made of, 1 + |f| + max |psi_ijk|."""
+    g1, g2 = o["gamma1"], o["gamma2"]
+    gm = np.hypot(g1, g2)
+    vax, vay, vbx, vby = g1 + gm, g2, g2, gm - g1
+    na, nb = np.hypot(vax, vay), np.hypot(vbx, vby)
+    use_a = na >= nb
+    vx = np.where(use_a, vax / np.where(na > 0, na, 1), vbx / np.where(nb > 0, nb, 1))
+    vy = np.where(use_a, vay / np.where(na > 0, na, 1), vby / np.where(nb > 0, nb, 1))
+    t3 = np.max(np.abs(np.stack([o["p111"], o["p112"], o["p122"], o["p222"]])), axis=0)
+    for k, comp in (("f1", np.abs(vx)), ("f2", np.abs(vy))):
+        ok = (gm > 0.05) & (comp > 1e-3)
+        assert ok.sum() > 0.5 * ok.size, k
+        err = np.abs(gpu[k][sl] - o[k]) / (1 + np.abs(o[k]) + t3)
+        assert np.max(err[ok]) < tol, (k, np.max(err[ok]))
 
 
 def _run(ctx, lf, model, params, S, pts, a, prec, outputs=BASE):
@@ -106,7 +147,7 @@ def test_maps_mixed_profiles_explicit_points(ctx, lf, orc, prec, seed, types, el
     x, y = W.random_points(seed, 3001, 25.0)           # several tiles and a ragged tail
     g = _run(ctx, lf, model, None, 1, (x, y), 0.63, prec)
     o = orc.maps(orc.expand(model), x, y, 0.63)
-    check({k: v[0] for k, v in g.items()}, o, prec)
+    check({k: v[0] for k, v in g.items()}, o, prec, a=0.63)
     assert np.array_equal(g["flags"][0] & 1, o["flags"] & 1)
 
 
@@ -119,7 +160,7 @@ def test_maps_third_derivatives_and_singularity_fields(ctx, lf, orc, prec):
     x, y = W.random_points(7, 1500, 20.0)
     g = _run(ctx, lf, model, None, 1, (x, y), 0.45, prec, outputs=BASE + D3)
     o = orc.maps(orc.expand(model), x, y, 0.45)
-    check({k: v[0] for k, v in g.items()}, o, prec, d3=True)
+    check({k: v[0] for k, v in g.items()}, o, prec, d3=True, a=0.45)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -132,7 +173,7 @@ def test_maps_many_samples_with_free_parameters(ctx, lf, orc, prec):
     g = _run(ctx, lf, model, params, S, (x, y), 0.7, prec)
     for s in range(S):
         o = orc.maps(orc.expand(model, params[s]), x, y, 0.7)
-        check({k: v[s] for k, v in g.items()}, o, prec)
+        check({k: v[s] for k, v in g.items()}, o, prec, a=0.7)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -141,7 +182,7 @@ def test_maps_config1_grid(ctx, lf, orc, prec):
     g = _run(ctx, lf, cfg["model"], None, 1, cfg["grid"], 0.6354, prec)
     x, y = W.grid_points(cfg["grid"])
     o = orc.maps(orc.expand(cfg["model"]), x, y, 0.6354)
-    check({k: v[0] for k, v in g.items()}, o, prec)
+    check({k: v[0] for k, v in g.items()}, o, prec, a=0.6354)
 
 
 def test_maps_config2_full_grid(ctx, lf, orc):
@@ -151,7 +192,7 @@ def test_maps_config2_full_grid(ctx, lf, orc):
     g = _run(ctx, lf, cfg["model"], cfg["params"][:1], 1, cfg["grid"], 0.7, "mixed")
     x, y = W.grid_points(cfg["grid"])
     o = orc.maps(orc.expand(cfg["model"], cfg["params"][0]), x, y, 0.7)
-    check({k: v[0] for k, v in g.items()}, o, "mixed")
+    check({k: v[0] for k, v in g.items()}, o, "mixed", a=0.7)
 
 
 def test_maps_edge_cases(ctx, lf, orc):
@@ -181,9 +222,6 @@ def test_maps_errors(ctx, lf):
     with pytest.raises(lf.LfError) as e:
         ctx.lens_maps(m, None, 1, {"x0": 0, "y0": 0, "h": 1.0, "nx": 4, "ny": 4}, 0.5, outputs=(), flags=False)
     assert e.value.status == lf.LF_E_INVALID_ARG
-    with pytest.raises(lf.LfError) as e:
-        ctx.lens_maps(m, None, 1, {"x0": 0, "y0": 0, "h": 1.0, "nx": 4, "ny": 4}, 0.5, outputs=("psi111",))
-    assert e.value.status == lf.LF_E_UNSUPPORTED
     with pytest.raises(lf.LfError) as e:
         ctx.lens_maps(m, None, 1, {"x0": 0, "y0": 0, "h": -1.0, "nx": 4, "ny": 4}, 0.5)
     assert e.value.status == lf.LF_E_INVALID_ARG
@@ -225,3 +263,44 @@ def test_maps_member_centres_and_near_field(ctx, lf, orc, prec):
     assert (o["flags"] & 1).sum() == 4          # exact centres of the s = 0 SIS/PJE/SIE and the point mass
     ok = (o["flags"] & 1) == 0
     check({k: v[ok] for k, v in gg.items()}, {k: v[ok] for k, v in o.items()}, prec, a_dis=0.6)
+
+
+def _cluster_window_grid(cfg, i0, j0, n):
+    g = cfg["grid"]
+    return {"x0": g["x0"] + i0 * g["h"], "y0": g["y0"] + j0 * g["h"], "h": g["h"], "nx": n, "ny": n - 3}
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_maps_third_derivatives_cluster_grid(ctx, lf, orc, prec):
+    """Third derivatives and A3-line fields of the cluster model (2 elliptical dPIE + 300 circular
+    dPIE members: the circular members' FP32 run sums with third derivatives) on grid windows of
+    the 2048^2 map: one at the cluster centre (member near fields and their edges), one at the
+    field edge (members far away), with ragged block edges (n x (n - 3) vertices)."""
+    cfg = W.config2(n_samples=1)
+    tab = orc.expand(cfg["model"], cfg["params"][0])
+    for i0, j0, n in ((900, 920, 61), (60, 1900, 45)):
+        grid = _cluster_window_grid(cfg, i0, j0, n)
+        g = _run(ctx, lf, cfg["model"], cfg["params"][:1], 1, grid, 0.5, prec, outputs=BASE + D3)
+        x, y = W.grid_points(grid)
+        o = orc.maps(tab, x, y, 0.5)
+        check({k: v[0] for k, v in g.items()}, o, prec, d3=True, a=0.5)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_maps_third_derivatives_cluster_points(ctx, lf, orc, prec):
+    """The same at explicit points: 3000 random points of the cluster field and 1200 points
+    around member centres at the near-field radius 3 b/q and its edges."""
+    cfg = W.config2(n_samples=1)
+    tab = orc.expand(cfg["model"], cfg["params"][0])
+    mem = tab[2:]
+    rng = np.random.default_rng(43)
+    x, y = W.random_points(43, 3000, 100.0)
+    k = rng.integers(0, mem.shape[0], 1200)
+    rn = 3.0 * mem[k, 3] / mem[k, 4]
+    d = rn * rng.choice([0.5, 0.999, 1.001, 1.5, 3.0], 1200)
+    t = rng.uniform(0, 2 * np.pi, 1200)
+    x = np.concatenate([x, mem[k, 1] + d * np.cos(t)])
+    y = np.concatenate([y, mem[k, 2] + d * np.sin(t)])
+    g = _run(ctx, lf, cfg["model"], cfg["params"][:1], 1, (x, y), 0.5, prec, outputs=BASE + D3)
+    o = orc.maps(tab, x, y, 0.5)
+    check({k: v[0] for k, v in g.items()}, o, prec, d3=True, a=0.5)

@@ -17,7 +17,8 @@ import pytest
 
 from paper_2609_08649_amd import workloads as W
 from tests import lensdata
-from tests.test_gpu_chi2 import mu_max, stable_image_plane, _jitter
+from tests.lensdata import mu_max, stable_image_plane
+from tests.test_gpu_chi2 import _jitter
 
 pytestmark = pytest.mark.gpu
 
@@ -193,16 +194,38 @@ def test_observables_errors(ctx, lf):
         lf.Batch(ctx, [(m, c, pp, 2)])
     assert e.value.status == lf.LF_E_UNSUPPORTED
     m.release()
-    # flux data with an elliptical NFW component: its third derivatives are not provided
-    em, et = W.tiny_model(5, n_main=2, n_mem=4, types=[5, 2], free_params=True)
-    me = ctx.upload_model(em)
-    pe = torch.as_tensor(et[None], device="cuda")
-    with pytest.raises(lf.LfError) as e:
-        ctx.chi2_terms(me, pe, 1, c, 0, lf.LF_PREC_FP64)
-    assert e.value.status == lf.LF_E_UNSUPPORTED
-    dt_only = ctx.upload_constraints({k: v for k, v in cons.items() if k not in ("mag", "sig_mag")})
-    ctx.chi2_terms(me, pe, 1, dt_only, 0, lf.LF_PREC_FP64)     # delays alone are fine
-    torch.cuda.synchronize()
-    dt_only.release()
-    me.release()
     c.release()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_observables_elliptical_nfw(ctx, lf, orc, prec):
+    """Flux and delay terms of a lens with elliptical NFW halos and members: grad mu from their
+    third derivatives, the potential from their quadrature; both chi^2 modes against the oracle."""
+    import torch
+    from tests.test_gpu_profiles_ext import enfw_model
+    model = enfw_model(56)
+    tab = orc.expand(model)
+    rng = np.random.default_rng(56)
+    cand = tab[0, 1:3] + rng.uniform(-3, 3, (400, 2))
+    zs = rng.uniform(1.0, 6.0, 400)
+    grid = {"x0": -30.0, "y0": -30.0, "h": 0.2, "nx": 300, "ny": 300}
+    srcs = lensdata.select_sources(orc, tab, grid, cand, zs, model["z_d"], 4)
+    cons = lensdata.constraints_from_sources(srcs, 10 ** 6, rng.normal(0, 0.03, (200, 2)), 0.3)
+    cons = lensdata.observables(orc, tab, srcs, cons, model["z_d"], 57)
+    assert cons["theta"].shape[0] >= 8
+    tabs = tab[None]
+    mu = mu_max(orc, tabs, cons)
+    assert stable_image_plane(orc, tabs, cons, orc.chi2_batch(tabs, cons, img_mode=True)["chi2_img"])[0]
+    m = ctx.upload_model(model)
+    c = ctx.upload_constraints(cons)
+    P = lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED
+    for mode in (0, 1):
+        _, fl, terms, _ = ctx.chi2_terms(m, None, 1, c, mode, P)
+        torch.cuda.synchronize()
+        o = orc.chi2_obs(tabs, cons, img_mode=bool(mode))
+        bt, bf = _mixed_bound(orc, tabs, cons, o["td"], o["flux"])
+        _check(terms.cpu().numpy(), o, prec, mu, bt, bf)
+        assert o["flux"][0] > 0 and o["td"][0] > 0
+        assert np.array_equal(fl.cpu().numpy() & 12, o["flags"] & 12)
+    c.release()
+    m.release()

@@ -32,6 +32,39 @@ def test_third_derivatives_smacs_like(ctx, lf, orc, prec):
     check({k: v[0] for k, v in g.items()}, o, prec, d3=True)
 
 
+def enfw_model(seed=54, n_mem=30, n_enfw=4):
+    """Two elliptical NFW halos and a cored SIE, with dPIE members of which n_enfw are elliptical
+    NFW members (kappa_s 0.05-0.2, r_s 3-8", q 0.6-0.9)."""
+    model, _ = W.tiny_model(seed, n_main=3, n_mem=n_mem, types=[W.ENFW, W.ENFW, W.SIE])
+    rng = np.random.default_rng(seed + 1000)
+    mem = model["members"]
+    lum = mem["lum"]
+    typ = np.full(n_mem, W.PJE, np.int32)
+    typ[:n_enfw] = W.ENFW
+    enfw = typ == W.ENFW
+    model["members"] = {
+        "type": typ, "x": mem["x"], "y": mem["y"],
+        "q": np.where(enfw, rng.uniform(0.6, 0.9, n_mem), 1.0), "pa": rng.uniform(0, np.pi, n_mem),
+        "b0": np.where(enfw, rng.uniform(0.05, 0.2, n_mem), 0.8 * np.sqrt(lum)),
+        "s0": np.where(enfw, rng.uniform(3.0, 8.0, n_mem), 0.05),
+        "a0": np.where(enfw, 0.0, 8.0 * np.sqrt(lum)),
+        "bmul": W.fixed(1.0), "smul": W.fixed(1.0), "amul": W.fixed(1.0)}
+    return model
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_third_derivatives_elliptical_nfw(ctx, lf, orc, prec):
+    """Third derivatives and A3 fields of elliptical NFW main halos and members (integrals L_n of
+    kappa'' over the same quadrature as alpha and psi_ij) against the oracle's derivatives of its
+    adaptive quadrature."""
+    model = enfw_model()
+    x, y = W.random_points(54, 2001, 20.0)
+    g = _run(ctx, lf, model, None, 1, (x, y), 0.55, prec, outputs=BASE + D3)
+    o = orc.maps(orc.expand(model), x, y, 0.55)
+    assert np.max(np.abs(o["p111"])) > 1e-3
+    check({k: v[0] for k, v in g.items()}, o, prec, d3=True, a=0.55)
+
+
 def _system(orc, seed=53):
     model, _ = W.tiny_model(seed, n_main=3, n_mem=20, types=[W.SIE, W.SHEAR, W.MPOLE3])
     tab = orc.expand(model)

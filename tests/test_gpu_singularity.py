@@ -1,9 +1,10 @@
 """GPU parity of lf_singularity_map (Sec. 6: A3 lines, umbilics, swallowtails) against the
 oracle's extraction on the same seeded lenses.
 
-FP64: counts, crossing order, families and flags, segments and umbilic statuses are identical
-(integer decisions taken on FP64 values on both sides; a swallowtail's "converged within 20
-Newton steps" may flip for a slowly converging point, at most 2% of them); refined crossing
+FP64: counts, crossing order, families and flags, segments, umbilic and swallowtail statuses
+are identical (integer decisions taken on FP64 values on both sides; a swallowtail is accepted
+when its last Newton step is below 1e-8", well above the rounding noise of its finite-difference
+polish, so the decision does not rest on that noise); refined crossing
 positions agree to 1e-9" (both are roots of f_k bracketed to 1e-10"), umbilics to 1e-8",
 swallowtails to 1e-7" (Newton on finite-difference g), e_k and kappa to 1e-9 relative.
 MIXED: only the vertex pass is FP32-based, so a crossing whose edge has a near-zero vertex
@@ -14,6 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2609_08649_amd import workloads as W
+from tests.lensdata import key_map
 
 pytestmark = pytest.mark.gpu
 
@@ -46,11 +48,14 @@ def _gpu(ctx, lf, model, truth, grid, prec, refine=True, cap=1 << 18):
     return r
 
 
-def _compare_exact(g, o):
+def _compare_exact(g, o, quad=1.0):
+    """quad: widening of the position bars for lenses whose derivatives come from quadrature
+    on both sides (elliptical NFW: 24 fixed nodes on the GPU, adaptive to 1e-14 in the oracle),
+    where f_k differs by the quadrature error rather than by rounding."""
     assert np.array_equal(g["counts"], o["counts"]), (g["counts"], o["counts"])
     gc, oc = g["cross"], o["cross"]
     assert np.array_equal(gc["k"], oc["k"]) and np.array_equal(gc["flags"], oc["flags"])
-    assert np.max(np.abs(gc["pos"] - oc["pos"]), initial=0) < 1e-9
+    assert np.max(np.abs(gc["pos"] - oc["pos"]), initial=0) < 1e-9 * quad
     ok = gc["flags"] == 0
     # e_k at the crossing: the two positions agree to ~1e-10", and near a member centre
     # |grad e| ~ e^2 / b, so e may differ by ~e^2 |d theta| beyond rounding
@@ -63,18 +68,14 @@ def _compare_exact(g, o):
     gu, ou = g["umb"], o["umb"]
     assert np.array_equal(gu["status"], ou["status"])
     good = (ou["status"] & 3) != 1
-    assert np.max(np.abs(gu["pos"][good] - ou["pos"][good]), initial=0) < 1e-8
+    assert np.max(np.abs(gu["pos"][good] - ou["pos"][good]), initial=0) < 1e-8 * quad
     assert np.allclose(gu["kappa"][good], ou["kappa"][good], rtol=1e-9, atol=1e-12)
     gw, ow = g["swt"], o["swt"]
     for k in ("k", "seg"):
         assert np.array_equal(gw[k], ow[k])
-    # "converged within 20 steps" is a threshold on an iteration count: for a slowly
-    # converging point, rounding-level differences in its start can flip it
-    diff = gw["status"] != ow["status"]
-    assert np.all(np.isin(gw["status"][diff], (0, 1)) & np.isin(ow["status"][diff], (0, 1)))
-    assert diff.sum() <= max(1, 0.02 * diff.size)
+    assert np.array_equal(gw["status"], ow["status"])
     both = (gw["status"] == 0) & (ow["status"] == 0)
-    assert np.max(np.abs(gw["pos"][both] - ow["pos"][both]), initial=0) < 1e-7
+    assert np.max(np.abs(gw["pos"][both] - ow["pos"][both]), initial=0) < 1e-7 * quad
     assert np.allclose(gw["e"][both], ow["e"][both], rtol=1e-7, atol=1e-10)
 
 
@@ -131,26 +132,13 @@ def _no_members():
             "b0": None, "s0": None, "a0": None, "bmul": W.fixed(1.0), "smul": W.fixed(0.0), "amul": W.fixed(1.0)}
 
 
-def _key_map(r, grid):
-    out = {}
-    for n, (p, k) in enumerate(zip(r["cross"]["pos"], r["cross"]["k"])):
-        fi = (p[0] - grid["x0"]) / grid["h"] - 0.5
-        fj = (p[1] - grid["y0"]) / grid["h"] - 0.5
-        if abs(fj - round(fj)) < 1e-7:
-            key = (int(round(fj)), int(np.floor(fi + 1e-9)), 0, int(k))
-        else:
-            key = (int(np.floor(fj + 1e-9)), int(round(fi)), 1, int(k))
-        out[key] = n
-    return out
-
-
 def test_small_model_mixed(ctx, lf, orc):
     model, truth = W.tiny_model(4, n_main=2, n_mem=25, types=[2, 3], free_params=True)
     tab = orc.expand(model, truth)
     grid = {"x0": -20.0, "y0": -20.0, "h": 0.4, "nx": 100, "ny": 100}
     o = orc.sing_map(tab, grid)
     g = _gpu(ctx, lf, model, truth, grid, lf.LF_PREC_MIXED)
-    ko, kg = _key_map(o, grid), _key_map(g, grid)
+    ko, kg = key_map(o, grid), key_map(g, grid)
     common = set(ko) & set(kg)
     assert len(set(ko) ^ set(kg)) <= 0.005 * len(ko) + 2, (len(ko), len(kg), len(common))
     roots = [q for q in common if o["cross"]["flags"][ko[q]] == 0 and g["cross"]["flags"][kg[q]] == 0]
@@ -176,12 +164,12 @@ def test_cluster_4096_windows(ctx, lf, orc, prec):
     g = _gpu(ctx, lf, cfg["model"], cfg["truth"], full, P, cap=1 << 21)
     assert g["counts"][0] < (1 << 21)
     tab = orc.expand(cfg["model"], cfg["truth"])
-    gk = _key_map(g, full)
+    gk = key_map(g, full)
     for (i0, j0) in ((1968, 1968), (1700, 2300), (2500, 1500)):
         n = 160
         win = {"x0": full["x0"] + i0 * full["h"], "y0": full["y0"] + j0 * full["h"], "h": full["h"], "nx": n, "ny": n}
         o = orc.sing_map(tab, win)
-        ok = _key_map(o, win)
+        ok = key_map(o, win)
         inside = {(j + j0, i + i0, d, k): v for (j, i, d, k), v in ok.items()}
         got = {q: v for q, v in gk.items() if j0 <= q[0] < j0 + n and i0 <= q[1] < i0 + n
                and not (q[2] == 0 and q[1] == i0 + n - 1) and not (q[2] == 1 and q[0] == j0 + n - 1)}
@@ -202,15 +190,23 @@ def test_cluster_4096_windows(ctx, lf, orc, prec):
     torch.cuda.empty_cache()
 
 
+def test_elliptical_nfw_fp64_identical(ctx, lf, orc):
+    """A lens of elliptical NFW halos and members (their third derivatives from the integrals of
+    kappa''): every decision as the oracle's; positions within ten times the FP64 bars, since
+    both sides take those derivatives from quadratures, not from closed forms."""
+    from tests.test_gpu_profiles_ext import enfw_model
+    model = enfw_model(55)
+    tab = orc.expand(model)
+    grid = {"x0": -20.0, "y0": -20.0, "h": 0.4, "nx": 100, "ny": 100}
+    o = orc.sing_map(tab, grid)
+    g = _gpu(ctx, lf, model, None, grid, lf.LF_PREC_FP64)
+    assert o["counts"][0] > 500 and o["counts"][2] > 0
+    print("eNFW crossings: max |d pos| %.3g\"" % np.max(np.abs(g["cross"]["pos"] - o["cross"]["pos"]), initial=0))
+    _compare_exact(g, o, quad=10.0)
+
+
 def test_errors(ctx, lf):
     import torch
-    model, truth = W.tiny_model(5, n_main=2, n_mem=4, types=[5, 2], free_params=True)
-    m = ctx.upload_model(model)
-    p = torch.as_tensor(truth[None], device="cuda")
-    with pytest.raises(lf.LfError) as e:
-        ctx.singularity_map(m, p, {"x0": 0.0, "y0": 0.0, "h": 0.1, "nx": 10, "ny": 10})
-    assert e.value.status == lf.LF_E_UNSUPPORTED
-    m.release()
     model, truth = W.tiny_model(6, n_main=2, n_mem=4, types=[2, 3], free_params=True)
     m = ctx.upload_model(model)
     p = torch.as_tensor(truth[None], device="cuda")
