@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12    # MI355X published FP32 vector peak [FLOP/s]
+PEAK_FP64_VECTOR = 78.6e12     # MI355X published FP64 vector peak [FLOP/s]
 # Algorithmic FLOPs of one circular dPIE member at one point (alpha + Hessian), counted on the
 # closed form (add/mul 1, FMA 2, each rsqrt/reciprocal 1): offset 2, r^2 3, two cored terms
 # 2 x 9, differences 2, alpha and Hessian assembly 9, accumulation 5.
@@ -107,6 +108,47 @@ def summarize_profiles(kind, dirs):
         for r in rows:
             print("%-60s %7s %12.2f %12.3f %7.2f" % (r["Name"][:60], r["Calls"], float(r["AverageNs"]) / 1e3,
                                                    float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+        return
+    if kind == "flops":
+        # every kernel of a run: counter FLOPs (per-op VALU counters, FMA 2, add, mul and
+        # transcendental 1 each, 64 lanes per wave-instruction: lanes masked off count too) from a
+        # --pmc run, and its time from a --kernel-trace --stats run of the same command; rates are
+        # total FLOPs over total time, against the FP32 and FP64 vector peaks
+        spath = glob.glob(os.path.join(dirs[0], "**", "*kernel_stats.csv"), recursive=True)[0]
+        stats = {r["Name"]: (int(r["Calls"]), float(r["TotalDurationNs"]) * 1e-9) for r in csv.DictReader(open(spath))}
+        per = {}
+        for d in dirs[1:]:
+            path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+            for r in csv.DictReader(open(path)):
+                key = (r["Kernel_Name"], d, r["Dispatch_Id"])
+                per.setdefault(key, {})
+                per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        tot = {}
+        for (name, d, _), ctrs in per.items():
+            t = tot.setdefault(name, {"dispatches": 0})
+            t["dispatches"] += 1
+            for c, v in ctrs.items():
+                t[c] = t.get(c, 0.0) + v
+        fl = {"FMA": 2, "ADD": 1, "MUL": 1, "TRANS": 1}
+        print("# source_sha256: %s" % kernel_source_hash())
+        print("%-52s %6s %6s %10s %10s %10s %8s %8s %7s %7s %9s" % (
+            "kernel", "calls", "pmc", "time_ms", "GFLOP32", "GFLOP64", "TF/s32", "TF/s64", "frac32", "frac64",
+            "Gtrans/s"))
+        rows = []
+        for name, t in tot.items():
+            if name not in stats:
+                continue
+            calls, sec = stats[name]
+            f32 = sum(64 * w * t.get("SQ_INSTS_VALU_%s_F32" % k, 0.0) for k, w in fl.items())
+            f64 = sum(64 * w * t.get("SQ_INSTS_VALU_%s_F64" % k, 0.0) for k, w in fl.items())
+            tr = 64 * (t.get("SQ_INSTS_VALU_TRANS_F32", 0.0) + t.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
+            if sec <= 0 or (f32 + f64) < 1e6:
+                continue
+            rows.append((sec, name, calls, t["dispatches"], f32, f64, tr))
+        for sec, name, calls, nd, f32, f64, tr in sorted(rows, reverse=True):
+            print("%-52s %6d %6d %10.3f %10.3f %10.3f %8.2f %8.2f %7.3f %7.3f %9.1f" % (
+                name[:52], calls, nd, sec * 1e3, f32 / 1e9, f64 / 1e9, f32 / sec / 1e12, f64 / sec / 1e12,
+                f32 / sec / PEAK_FP32_VECTOR, f64 / sec / PEAK_FP64_VECTOR, tr / sec / 1e9))
         return
     if kind in ("insts", "insts_d3"):
         # SQ instruction counters of the lean maps kernel (insts_d3: its third-derivative form,
@@ -187,9 +229,12 @@ def parse():
                     help="after the run, copy %d MiB device to device three times (counter calibration)"
                     % (COPY_PROBE_BYTES >> 20))
     ap.add_argument("--rates", action="store_true", help="print only the issue-rate probe's results (JSON)")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="print only the per-result precision report against the oracle (JSON)")
     ap.add_argument("--summarize", nargs="+", metavar=("KIND", "DIR"),
-                    help="print a summary of rocprofv3 output: 'stats DIR', 'pmc FETCH_DIR WRITE_DIR' or "
-                         "'insts DIR...' / 'insts_d3 DIR...' (SQ instruction counters)")
+                    help="print a summary of rocprofv3 output: 'stats DIR', 'pmc FETCH_DIR WRITE_DIR', "
+                         "'insts DIR...' / 'insts_d3 DIR...' (SQ instruction counters) or 'flops STATS_DIR "
+                         "PMC_DIR...' (counter FLOP/s of every kernel)")
     return ap.parse_args()
 
 
@@ -248,6 +293,11 @@ def main():
     from paper_2609_08649_amd import lensfield as lf
     from paper_2609_08649_amd import workloads as W
 
+    if args.precision_only:
+        ctx = lf.Context(0)
+        print(json.dumps(precision_report_more(ctx, lf, torch, W)), flush=True)
+        ctx.close()
+        return
     dev = torch.device("cuda", 0)
     L = lf.lib()
     cfg = W.config2()
@@ -372,6 +422,8 @@ def main():
         note("cpu baseline (oracle)")
         cpu, ref = cpu_baseline(model, cfg, n_img, cons_np["family"], a_maps, args.cpu_seconds)
         prec_rep = precision_report(ctx, lf, torch, m, params, grid, a_maps, ref)
+        note("precision report (oracle)")
+        prec_rep.update(precision_report_more(ctx, lf, torch, W))
 
     res = {
         "metric": "halo x point lens evals/s (alpha+Jacobian)",
@@ -980,6 +1032,142 @@ def precision_report(ctx, lf, torch, m, params, grid, a_maps, ref):
     out["find"] = {"sources": n, "images": int(of["count"].sum()),
                    "count_mismatches": int(np.sum(cnt != of["count"])), "max_dtheta": dth,
                    "limits": {"dtheta": 1e-4}}
+    return out
+
+
+def _q(v):
+    v = np.asarray(v, np.float64).ravel()
+    if v.size == 0:
+        return {"n": 0, "max": None, "p999": None}
+    return {"n": int(v.size), "max": float(v.max()), "p999": float(np.quantile(v, 0.999))}
+
+
+def precision_report_more(ctx, lf, torch, W):
+    """Per-result errors of both precisions against the oracle, on inputs built by the workload
+    generator and the oracle only: image-plane chi^2 of 64 cluster samples (relative, well-posed
+    samples; model image positions where both sides accept an image at the same root; the
+    fraction of differing Newton decisions), multi-plane beta and mu at 2000 sampled points of
+    the 4096^2 three-plane trace, the position, flux and delay terms of 64 cluster samples in
+    both chi^2 modes, the items of an uneven batch, and refined A3 crossings of the 4096^2
+    singularity map on a 160^2 window."""
+    from oracle import oracle as orc
+    from tests import lensdata
+    dev = torch.device("cuda", 0)
+    precs = (("mixed", lf.LF_PREC_MIXED), ("fp64", lf.LF_PREC_FP64))
+    out = {}
+    # image-plane chi^2 (Sec. 3.1 Eq. chi2_img, Sec. 3.5)
+    cfg = W.config2(n_samples=1024)
+    cons = lensdata.cluster_constraints()
+    params = cfg["params"][:64]
+    tabs = orc.expand_batch(cfg["model"], params)
+    o = orc.chi2_batch(tabs, cons, img_mode=True)
+    well = lensdata.stable_image_plane(orc, tabs, cons, o["chi2_img"])
+    m = ctx.upload_model(cfg["model"])
+    c = ctx.upload_constraints(cons)
+    pp = torch.as_tensor(params, device=dev)
+    rep = {"samples": int(params.shape[0]), "images": int(cons["theta"].shape[0]), "well_posed": int(well.sum())}
+    for name, P in precs:
+        g = {k: v.cpu().numpy() for k, v in ctx.chi2_images(m, pp, params.shape[0], c, P).items()}
+        rel = np.abs(g["chi2"] - o["chi2_img"]) / np.abs(o["chi2_img"])
+        both = (g["img_flags"] == 0) & (o["img_flags"] == 0)
+        d = np.abs(g["theta_model"] - o["theta_model"]).max(axis=2)
+        same = both & (d < 1e-4)
+        agree = (g["img_flags"] == o["img_flags"]) & (same | ~both)
+        rep[name] = {"rel_chi2_well_posed": _q(rel[well]), "dtheta_model_same_root": _q(d[same]),
+                     "differing_newton_decisions": float(1 - agree.mean())}
+    c.release()
+    out["chi2_img"] = rep
+    # position, flux and delay terms (Sec. 3.1-3.3)
+    ocons = lensdata.cluster_observables()
+    c = ctx.upload_constraints(ocons)
+    rep = {"samples": int(params.shape[0])}
+    for mode in (0, 1):
+        oo = orc.chi2_obs(tabs, ocons, img_mode=bool(mode))
+        for name, P in precs:
+            _, _, t, _ = ctx.chi2_terms(m, pp, params.shape[0], c, mode, P)
+            t = t.cpu().numpy()
+            r = {}
+            for j, k in enumerate(("pos", "flux", "td")):
+                ok = well if mode == 1 else np.ones(t.shape[0], bool)
+                r[k] = _q((np.abs(t[:, j] - oo[k]) / np.maximum(np.abs(oo[k]), 1e-300))[ok])
+            rep["mode%d_%s" % (mode, name)] = r
+    rep["note"] = "relative error per term; image-plane mode (1) on the well-posed samples"
+    c.release()
+    m.release()
+    out["chi2_terms"] = rep
+    # uneven batch items (source plane)
+    cfg3 = W.config3(walkers_per_model=64)
+    items, refs, mus = [], [], []
+    for it in cfg3["models"]:
+        n = it["n_img"]
+        a = np.array([orc.adis(it["model"]["z_d"], z) for z in it["z_fam"]])
+        cn = {"theta": it["theta"], "family": it["family"], "sig1": np.full(n, 0.5), "sig2": np.full(n, 0.5),
+              "phi": np.zeros(n), "a_fam": a}
+        items.append((ctx.upload_model(it["model"]), ctx.upload_constraints(cn),
+                      torch.as_tensor(it["params"], device=dev), it["params"].shape[0]))
+        tb = orc.expand_batch(it["model"], it["params"])
+        refs.append(orc.chi2_batch(tb, cn)["chi2_src"])
+        mus.append(lensdata.mu_max(orc, tb, cn))
+    mus = np.concatenate(mus)
+    rep = {"items": len(items), "samples": int(sum(i[3] for i in items)),
+           "note": "constraint positions are random points, so some sit next to critical curves: the "
+                   "relative error is given where every |mu| < 100 and, for all samples, divided by "
+                   "1 + mu_max^2 (W = mu^T S^-1 mu grows as mu^2)"}
+    for name, P in precs:
+        b = lf.Batch(ctx, items, 0, P, autotune=False)
+        res = b.run()
+        torch.cuda.synchronize()
+        rel = np.concatenate([np.abs(r[0].cpu().numpy() - ref) / np.abs(ref) for r, ref in zip(res, refs)])
+        ok = np.isfinite(rel)
+        rep[name] = {"rel_chi2_src_mu_lt_100": _q(rel[ok & (mus < 100)]),
+                     "rel_over_1_plus_mu_max2": _q((rel / (1 + mus ** 2))[ok])}
+        b.release()
+    for mm, cc, _, _ in items:
+        cc.release()
+        mm.release()
+    out["batched_chi2"] = rep
+    # multi-plane beta and mu (Sec. 2.2)
+    c4 = W.config4()
+    tabs4 = [orc.expand(p) for p in c4["planes"]]
+    x, y = W.grid_points(c4["grid"])
+    idx = np.random.default_rng(3).choice(x.size, 2000, replace=False)
+    o4 = orc.multiplane(tabs4, c4["z_planes"], c4["zs_maps"], x[idx], y[idx])
+    pl = [ctx.upload_model(p) for p in c4["planes"]]
+    ti = torch.as_tensor(idx, device=dev)
+    rep = {"points": int(idx.size), "z_src": [float(z) for z in c4["zs_maps"]]}
+    for name, P in precs:
+        g = ctx.multiplane_trace(pl, c4["z_planes"], c4["zs_maps"], c4["grid"], P, outputs=("beta", "mu"))
+        gb, gm = g["beta"][:, ti].cpu().numpy(), g["mu"][:, ti].cpu().numpy()
+        del g
+        torch.cuda.empty_cache()
+        db = np.hypot(*(gb - o4["beta"]).transpose(2, 0, 1))
+        sel = np.abs(o4["mu"]) < 100
+        rep[name] = {"dbeta": _q(db), "rel_mu_abs_mu_lt_100": _q(np.abs(gm - o4["mu"])[sel] / np.abs(o4["mu"][sel]))}
+    for p in pl:
+        p.release()
+    out["multiplane"] = rep
+    # refined A3 crossings (Sec. 6)
+    cfg1 = W.config2(n_samples=1)
+    full = {"x0": -100.0, "y0": -100.0, "h": 200.0 / 4096, "nx": 4096, "ny": 4096}
+    i0 = j0 = 1968
+    n = 160
+    win = {"x0": full["x0"] + i0 * full["h"], "y0": full["y0"] + j0 * full["h"], "h": full["h"], "nx": n, "ny": n}
+    ow = orc.sing_map(orc.expand(cfg1["model"], cfg1["truth"]), win)
+    okm = {(j + j0, i + i0, dd, k): v for (j, i, dd, k), v in lensdata.key_map(ow, win).items()}
+    m = ctx.upload_model(cfg1["model"])
+    pt = torch.as_tensor(cfg1["truth"][None], device=dev)
+    rep = {"window": "160^2 vertices at (1968, 1968) of the 4096^2 grid over 200\"", "crossings": len(okm)}
+    for name, P in precs:
+        g = ctx.singularity_map(m, pt, full, P, True, 1e-10, 1 << 21)
+        g = {k: ({kk: vv.cpu().numpy() for kk, vv in v.items()} if isinstance(v, dict) else v) for k, v in g.items()}
+        gk = {q: v for q, v in lensdata.key_map(g, full).items() if j0 <= q[0] < j0 + n and i0 <= q[1] < i0 + n
+              and not (q[2] == 0 and q[1] == i0 + n - 1) and not (q[2] == 1 and q[0] == j0 + n - 1)}
+        common = set(gk) & set(okm)
+        roots = [q for q in common if g["cross"]["flags"][gk[q]] == 0 and ow["cross"]["flags"][okm[q]] == 0]
+        d = [np.abs(g["cross"]["pos"][gk[q]] - ow["cross"]["pos"][okm[q]]).max() for q in roots]
+        rep[name] = {"dpos_roots": _q(np.array(d)), "only_one_side": len(set(gk) ^ set(okm))}
+    m.release()
+    out["singularity_crossings"] = rep
     return out
 
 
