@@ -309,6 +309,18 @@ lf_status lf_find_images(lf_ctx* ctx, const lf_model* m, const double* params,
                          const lf_grid* grid, int32_t max_img, lf_prec prec, double* theta_out,
                          double* mu_out, int32_t* count_out, int32_t* flags, void* stream);
 
+/* lf_find_images on a deflection map the caller already has: alpha_x, alpha_y (device, [ny][nx],
+ * a_dis-free, at the grid's vertices) replace the finder's own vertex halo sum, so a pipeline
+ * that computes maps and then images of the same sample (Sec. 2.1, 2.3) sums the halos on the
+ * grid once.  With the maps of lf_lens_maps for the same model, sample, grid and precision the
+ * results are those of lf_find_images bit for bit; the FP64 containment tests and the Newton
+ * polish use the model as there.  Other arguments, outputs and errors as lf_find_images. */
+lf_status lf_find_images_alpha(lf_ctx* ctx, const lf_model* m, const double* params,
+                               const double* alpha_x, const double* alpha_y, const double* beta,
+                               const double* a_src, int32_t n_src, const lf_grid* grid, int32_t max_img,
+                               lf_prec prec, double* theta_out, double* mu_out, int32_t* count_out,
+                               int32_t* flags, void* stream);
+
 /* Image finder of Sec. 2.3, kept as a cross-check on triangle mapping: zero contours of both
  * components of f = beta - theta + a alpha on the grid vertices (marching squares: linear
  * interpolation on cell edges, the asymptotic decider in cells crossed four times), images at
@@ -471,7 +483,11 @@ enum { LF_REQ_CHI2 = 0, LF_REQ_MU_MAP = 1, LF_REQ_SING_MAP = 2 };
  * output out_host [S] (and flags_host [S] or NULL).  LF_REQ_MU_MAP: model (+ host params row or
  * NULL), grid, a_dis, prec; out_host [P] = mu.  LF_REQ_SING_MAP: out_host [6][P] = kappa,
  * det A, e1, e2, f1, f2 (Sec. 6).  Outputs are written by asynchronous copies: pass pinned host
- * memory (pageable memory works but stalls the scheduler while it copies). */
+ * memory (pageable memory works but stalls the scheduler while it copies).  Maps may instead
+ * keep their result on the device: out_device (caller-owned device memory of the same layout,
+ * and flags_device [P] or NULL) replaces out_host, which is then NULL; nothing is copied to the
+ * host, the output planes are not counted in the request's footprint, and the result is
+ * complete once the ticket is done. */
 typedef struct {
   int32_t kind;
   int32_t S;
@@ -484,6 +500,8 @@ typedef struct {
   double a_dis;
   double* out_host;
   int32_t* flags_host;
+  double* out_device;
+  int32_t* flags_device;
 } lf_request;
 
 /* Start a server on a context: a scheduler thread admits requests in arrival order whenever

@@ -162,9 +162,47 @@ extern "C" lf_status lf_find_images(lf_ctx* ctx, const lf_model* M, const double
   L.qd.n = q.n; L.qd.u = q.u; L.qd.w = q.w;
   lf::FindArgs F;
   F.x0 = grid->x0; F.y0 = grid->y0; F.h = grid->h; F.nx = grid->nx; F.ny = grid->ny;
-  F.n_planes = 1; F.va_pstride = 2; F.va = va;
+  F.n_planes = 1; F.va_pstride = 0; F.vax = va; F.vay = va + ps.P;
   F.n_src = n_src; F.beta = beta; F.w = a_src;
   F.eps = mixed ? 5e-5 : 1e-9;
+  F.max_img = max_img; F.theta_out = theta_out; F.mu_out = mu_out; F.count_out = count_out; F.flags_out = flags;
+  e = finder_buffers(ctx, st, F);
+  if (e) return e;
+  ctx->cur_stream = st;
+  return ctx->hip(lf::launch_find(F, L, st, lf_prof_mark, ctx), "finder kernels");
+}
+
+extern "C" lf_status lf_find_images_alpha(lf_ctx* ctx, const lf_model* M, const double* params,
+                                          const double* alpha_x, const double* alpha_y, const double* beta,
+                                          const double* a_src, int32_t n_src, const lf_grid* grid, int32_t max_img,
+                                          lf_prec prec, double* theta_out, double* mu_out, int32_t* count_out,
+                                          int32_t* flags, void* stream) {
+  if (!ctx) return LF_E_INVALID_ARG;
+  if (!M || !alpha_x || !alpha_y || !beta || !a_src || !theta_out || !count_out)
+    return ctx->fail(LF_E_INVALID_ARG, "null argument");
+  if (n_src < 1 || max_img < 1) return ctx->fail(LF_E_INVALID_ARG, "n_src and max_img must be >= 1");
+  if (!grid_ok(grid)) return ctx->fail(LF_E_INVALID_ARG, "bad grid (need nx, ny >= 2, h > 0)");
+  if (M->n_free > 0 && !params) return ctx->fail(LF_E_INVALID_ARG, "model has free fields: params required");
+  if (prec != LF_PREC_FP64 && prec != LF_PREC_MIXED) return ctx->fail(LF_E_INVALID_ARG, "bad precision");
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  // the FP64 tables of the sample for containment and polishing; the vertex deflections are the
+  // caller's map
+  lf::MainRec* mains; lf::MulRec* muls; lf::MemRec32* m32; lf::MemRec64* m64;
+  lf_status e = lf_expand_tables(ctx, M, params, 1, true, st, &mains, &muls, &m32, &m64, "find");
+  if (e) return e;
+  lf::DevModel dm = lf_dev_model(M);
+  lf::LensDev L;
+  std::memset(&L, 0, sizeof L);
+  L.n_planes = 1;
+  L.pl[0].mains = mains; L.pl[0].n_main = dm.n_main; L.pl[0].mem = m64; L.pl[0].seg = dm.seg;
+  lf::QuadTab q = lf_quad(ctx);
+  L.qd.n = q.n; L.qd.u = q.u; L.qd.w = q.w;
+  lf::FindArgs F;
+  F.x0 = grid->x0; F.y0 = grid->y0; F.h = grid->h; F.nx = grid->nx; F.ny = grid->ny;
+  F.n_planes = 1; F.va_pstride = 0; F.vax = alpha_x; F.vay = alpha_y;
+  F.n_src = n_src; F.beta = beta; F.w = a_src;
+  F.eps = prec == LF_PREC_MIXED ? 5e-5 : 1e-9;
   F.max_img = max_img; F.theta_out = theta_out; F.mu_out = mu_out; F.count_out = count_out; F.flags_out = flags;
   e = finder_buffers(ctx, st, F);
   if (e) return e;
@@ -202,7 +240,7 @@ extern "C" lf_status lf_find_images_ms(lf_ctx* ctx, const lf_model* M, const dou
   lf::FindArgs F;
   std::memset(&F, 0, sizeof F);
   F.x0 = grid->x0; F.y0 = grid->y0; F.h = grid->h; F.nx = grid->nx; F.ny = grid->ny;
-  F.n_planes = 1; F.va_pstride = 2; F.va = va;
+  F.n_planes = 1; F.va_pstride = 0; F.vax = va; F.vay = va + ps.P;
   F.n_src = n_src; F.beta = beta; F.w = a_src;
   F.max_img = max_img; F.theta_out = theta_out; F.mu_out = mu_out; F.count_out = count_out; F.flags_out = flags;
   e = finder_buffers(ctx, st, F);
@@ -290,7 +328,7 @@ extern "C" lf_status lf_find_images_mp(lf_ctx* ctx, const lf_model* const* plane
   hipMemcpyAsync(d_w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, st);
   lf::FindArgs F;
   F.x0 = grid->x0; F.y0 = grid->y0; F.h = grid->h; F.nx = grid->nx; F.ny = grid->ny;
-  F.n_planes = n_planes; F.va_pstride = 5; F.va = M.al;
+  F.n_planes = n_planes; F.va_pstride = 5 * M.P; F.vax = M.al; F.vay = M.al + M.P;
   F.n_src = n_src; F.beta = beta; F.w = d_w;
   F.eps = mixed ? 5e-5 : 1e-9;
   F.max_img = max_img; F.theta_out = theta_out; F.mu_out = mu_out; F.count_out = count_out; F.flags_out = flags;

@@ -23,8 +23,10 @@ struct LensDev {           // FP64 lens for polishing: 1 plane, or planes with D
 struct FindArgs {
   double x0, y0, h;
   int nx, ny;
-  int n_planes, va_pstride;  // vertex deflection of plane p: va + (pstride p) P (x), +1 (y)
-  const double* va;
+  int n_planes;
+  long long va_pstride;      // vertex deflection of plane p: vax + pstride p (x), vay + pstride p (y)
+  const double* vax;
+  const double* vay;
   int n_src;
   const double* beta;        // [n_src*2]
   const double* w;           // [n_src*n_planes] plane weights (single plane: a_dis)

@@ -205,7 +205,6 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
   const bool valid = c < ncell;
   const long long cc = valid ? c : 0;
   const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
-  const long long P = (long long)F.nx * F.ny;
   const long long v[4] = {(long long)j * F.nx + i, (long long)j * F.nx + i + 1, (long long)(j + 1) * F.nx + i,
                           (long long)(j + 1) * F.nx + i + 1};
   double tx[4], ty[4];
@@ -227,8 +226,8 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
     amax[p] = 0.f;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      axf[p][k] = (float)F.va[(size_t)(F.va_pstride * p) * P + v[k]];
-      ayf[p][k] = (float)F.va[(size_t)(F.va_pstride * p + 1) * P + v[k]];
+      axf[p][k] = (float)F.vax[(size_t)F.va_pstride * p + v[k]];
+      ayf[p][k] = (float)F.vay[(size_t)F.va_pstride * p + v[k]];
       amax[p] = fmaxf(amax[p], fmaxf(fabsf(axf[p][k]), fabsf(ayf[p][k])));
     }
   }
@@ -308,8 +307,8 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
       for (int k = 0; k < 4; ++k) { bx[k] = tx[k]; by[k] = ty[k]; }
       for (int p = 0; p < np; ++p) {
         const double w = ws[p];
-        const double* vx = F.va + (size_t)(F.va_pstride * p) * P;
-        const double* vy = F.va + (size_t)(F.va_pstride * p + 1) * P;
+        const double* vx = F.vax + (size_t)F.va_pstride * p;
+        const double* vy = F.vay + (size_t)F.va_pstride * p;
 #pragma unroll
         for (int k = 0; k < 4; ++k) { bx[k] = fma(-w, vx[v[k]], bx[k]); by[k] = fma(-w, vy[v[k]], by[k]); }
       }
@@ -580,14 +579,13 @@ struct MsCorners {
 };
 __device__ void ms_corners(const FindArgs& F, int i, int j, MsCorners& q) {
 #pragma clang fp contract(off)
-  const long long P = (long long)F.nx * F.ny;
   const int ci[4] = {i, i + 1, i + 1, i}, cj[4] = {j, j, j + 1, j + 1};
   for (int k = 0; k < 4; ++k) {
     const long long v = (long long)cj[k] * F.nx + ci[k];
     q.tx[k] = F.x0 + (ci[k] + 0.5) * F.h;
     q.ty[k] = F.y0 + (cj[k] + 0.5) * F.h;
-    q.ax[k] = F.va[v];
-    q.ay[k] = F.va[P + v];
+    q.ax[k] = F.vax[v];
+    q.ay[k] = F.vay[v];
   }
 }
 // F = beta_s - (theta - a alpha) at the corners, for source (sx, sy) at distance ratio a

@@ -71,8 +71,12 @@ struct MemRec32 {
 
 // Far field of a circular dPIE member: at r >= FAR_K a the truncated expansion of its closed
 // form in 1/r (terms through 1/r^11) is exact to 4e-9 (m) and 3e-8 (w) relative, below FP32
-// rounding; FAR_AMAX bounds a so that the FP32 coefficients (~ b a^10) stay finite.
+// rounding; farther out fewer terms reach the same bound: five (through 1/r^9) at r >= FAR_K5 a
+// (6e-9, 4e-8) and four (through 1/r^7) at r >= FAR_K4 a (5e-9, 2e-8), for cores s <= 0.95 a.
+// FAR_AMAX bounds a so that the FP32 coefficients (~ b a^10) stay finite.
 static constexpr double FAR_K = 5.0;
+static constexpr double FAR_K5 = 7.0;
+static constexpr double FAR_K4 = 13.0;
 static constexpr double FAR_AMAX = 1e3;
 struct MemRec64 {
   double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, bd, apls;

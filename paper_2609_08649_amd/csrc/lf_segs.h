@@ -275,52 +275,89 @@ __device__ __forceinline__ void tile_term_l(const float* l, const TileLane<TP>& 
   r.s2 = q0.z; r.a2 = q0.w; r.s = q1.x; r.a = q1.y; r.bd = q1.z; r.apls = q1.w;
   r.b = (SEG == SEG_CPJE && !D3) ? 0.f : l[8];
   const float dx = L.u - q0.x;
+  const float dx2 = dx * dx;
 #pragma unroll
   for (int k = 0; k < TP; ++k) {
     const float dy = L.v[k] - q0.y;
-    const float r2 = fmaf(dx, dx, dy * dy);
+    const float r2 = fmaf(dy, dy, dx2);
     float m, w, wp;
     circ_mw<SEG, D3>(r, r2, m, w, wp);
     run_add<D3>(dx, dy, r2, m, w, wp, ps[k]);
   }
 }
 
-// far-field expansion of a circular dPIE (one transcendental per point): with t = 1/r and
-// u = t^2, m = u (fm0 + t (fm1 + u (fm2 + u (fm3 + u (fm4 + u fm5))))), w = u^2 (fw0 + t (fw1 + ...))
-template <int TP>
+// far-field expansion of a circular dPIE (one transcendental per point), NT = 4, 5 or 6 terms:
+// with t = 1/r and u = t^2, m = u (fm0 + t (fm1 + u (fm2 + ...))), w = u^2 (fw0 + t (fw1 + ...)).
+// The record holds Dx, Dy, fm0..fm(NT-1), fw0..fw(NT-1) contiguously.
+template <int TP, int NT>
 __device__ __forceinline__ void tile_term_far(const float* l, const TileLane<TP>& L, Run32 (&ps)[TP]) {
-  const float4 q0 = *(const float4*)l, q1 = *(const float4*)(l + 4), q2 = *(const float4*)(l + 8),
-               q3 = *(const float4*)(l + 12);
-  const float dx = L.u - q0.x;
+  static_assert(NT >= 4 && NT <= 6, "four to six terms");
+  // 16-byte reads, and an 8-byte one for a 2-float tail (a broadcast read moves its size times
+  // 64 lanes through the LDS return path, the resource the far-field loop is closest to)
+  constexpr int NF = 2 + 2 * NT;
+  float f[16];
+#pragma unroll
+  for (int q = 0; q < NF / 4; ++q) {
+    const float4 v = *(const float4*)(l + 4 * q);
+    f[4 * q] = v.x; f[4 * q + 1] = v.y; f[4 * q + 2] = v.z; f[4 * q + 3] = v.w;
+  }
+  if constexpr (NF % 4 == 2) {
+    const float2 v = *(const float2*)(l + NF - 2);
+    f[NF - 2] = v.x; f[NF - 1] = v.y;
+  }
+  const float* fm = f + 2;
+  const float* fw = f + 2 + NT;
+  const float dx = L.u - f[0];
+  const float dx2 = dx * dx;
 #pragma unroll
   for (int k = 0; k < TP; ++k) {
-    const float dy = L.v[k] - q0.y;
-    const float r2 = fmaf(dx, dx, dy * dy);
+    const float dy = L.v[k] - f[1];
+    const float r2 = fmaf(dy, dy, dx2);
     const float t = frsq(r2), uu = t * t;
-    float pm = fmaf(uu, q1.w, q1.z);
-    pm = fmaf(uu, pm, q1.y);
-    pm = fmaf(uu, pm, q1.x);
-    pm = fmaf(uu, pm, q0.w);
-    pm = fmaf(t, pm, q0.z);
-    float pw = fmaf(uu, q3.y, q3.x);
-    pw = fmaf(uu, pw, q2.w);
-    pw = fmaf(uu, pw, q2.z);
-    pw = fmaf(uu, pw, q2.y);
-    pw = fmaf(t, pw, q2.x);
+    float pm = fmaf(uu, fm[NT - 1], fm[NT - 2]);
+    float pw = fmaf(uu, fw[NT - 1], fw[NT - 2]);
+#pragma unroll
+    for (int j = NT - 3; j >= 1; --j) {
+      pm = fmaf(uu, pm, fm[j]);
+      pw = fmaf(uu, pw, fw[j]);
+    }
+    pm = fmaf(t, pm, fm[0]);
+    pw = fmaf(t, pw, fw[0]);
     run_add<false>(dx, dy, r2, uu * pm, (uu * uu) * pw, 0.f, ps[k]);
+  }
+}
+
+// The runs of one far-field tier: records [c_begin, c_end) of the wave's LDS list.
+template <int TP, int NT, int LS>
+__device__ __forceinline__ void far_runs(int c_begin, int c_end, const TileLane<TP>& L, Acc (&acc)[TP]) {
+  for (int c0 = c_begin; c0 < c_end; c0 += LF_CHUNK) {
+    const int n = min(LF_CHUNK, c_end - c0);
+    const float* lr = L.dsh + LS * c0;
+    Run32 ps[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) run_zero<false>(ps[k]);
+    if (n == LF_CHUNK) {
+#pragma unroll
+      for (int k = 0; k < LF_CHUNK; ++k) tile_term_far<TP, NT>(lr + LS * k, L, ps);
+    } else {
+      for (int k = 0; k < n; ++k) tile_term_far<TP, NT>(lr + LS * k, L, ps);
+    }
+#pragma unroll
+    for (int k = 0; k < TP; ++k) run_flush<false>(ps[k], acc[k]);
   }
 }
 
 // Members are taken in blocks of 64.  Lane j of the wave takes member j of the block: its
 // offset D from the block centre (FP64, rounded to FP32), whether its near-field disc (radius^2
 // rn2, with a relative margin of 1e-5 for the FP32 rounding of a lane's r^2) meets the wave's
-// block, and whether the whole block lies at least FAR_K cut radii away (far field).  Ballots
-// give the wave's near, far and closed-form sets, and the records are written to LDS in that
-// order: far members first (in member order), then closed-form ones, so that every run of
-// LF_CHUNK members has one evaluation (full runs unrolled).  Runs are counted from the start of
-// each set; near-field members are evaluated after the block lane by lane, exactly as in
-// seg_loop: in FP64 from the FP64 record where the lane's r^2 < rn2, otherwise in FP32 from the
-// pair offsets, each term added to the FP64 accumulators.  Every set depends only on the global
+// block, and how many cut radii away the whole block lies (far field with four terms at
+// FAR_K4, five at FAR_K5, six at FAR_K).  Ballots give the wave's near, far and closed-form
+// sets, and the records are written to LDS in the order four-term, five-term, six-term far
+// members, then closed-form ones (each set in member order), so that every run of LF_CHUNK
+// members has one evaluation (full runs unrolled).  Runs are counted from the start of each
+// set; near-field members are evaluated after the block lane by lane, exactly as in seg_loop:
+// in FP64 from the FP64 record where the lane's r^2 < rn2, otherwise in FP32 from the pair
+// offsets, each term added to the FP64 accumulators.  Every set depends only on the global
 // block and the member, so results do not depend on the launch shape.
 template <int SEG, bool D3, int TP>
 __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, const MemRec64* __restrict__ near64,
@@ -333,7 +370,8 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int b0 = lo; b0 < hi; b0 += 64) {
     const int nb = min(64, hi - b0);
-    bool flag = false, far = false;
+    bool flag = false;
+    int tier = 0;                       // far-field terms (4, 5 or 6), 0: closed form
     float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
     if (lane < nb) {
       const double cx = near64[b0 + lane].x, cy = near64[b0 + lane].y;
@@ -342,48 +380,51 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
       const double e2 = fma(ex, ex, ey * ey);
       const MemRec32& r = rec[b0 + lane];
       flag = e2 < (double)r.rn2 * (1.0 + 1e-5);
-      const double ar = near64[b0 + lane].a;
-      far = FAR && !flag && ar <= FAR_AMAX && e2 >= FAR_K * FAR_K * ar * ar;
-      if (far) {
-        w0 = make_float4((float)ddx, (float)ddy, r.fm[0], r.fm[1]);
+      const double ar = near64[b0 + lane].a, a2r = ar * ar;
+      if (FAR && !flag && ar <= FAR_AMAX)
+        tier = e2 >= FAR_K4 * FAR_K4 * a2r ? 4 : e2 >= FAR_K5 * FAR_K5 * a2r ? 5 : e2 >= FAR_K * FAR_K * a2r ? 6 : 0;
+      const float dxf = (float)ddx, dyf = (float)ddy;
+      if (tier == 4) {
+        w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
+        w1 = make_float4(r.fm[2], r.fm[3], r.fw[0], r.fw[1]);
+        w2 = make_float4(r.fw[2], r.fw[3], 0.f, 0.f);
+      } else if (tier == 5) {
+        w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
+        w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fw[0]);
+        w2 = make_float4(r.fw[1], r.fw[2], r.fw[3], r.fw[4]);
+      } else if (tier == 6) {
+        w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
         w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fm[5]);
         w2 = make_float4(r.fw[0], r.fw[1], r.fw[2], r.fw[3]);
         w3 = make_float4(r.fw[4], r.fw[5], 0.f, 0.f);
       } else {
-        w0 = make_float4((float)ddx, (float)ddy, r.s2, r.a2);
+        w0 = make_float4(dxf, dyf, r.s2, r.a2);
         w1 = make_float4(r.s, r.a, r.bd, r.apls);
         w2 = make_float4(r.b, 0.f, 0.f, 0.f);
       }
     }
-    const bool closed = lane < nb && !flag && !far;
-    const unsigned long long nmask = __ballot(flag), fmask = __ballot(far), cmask = __ballot(closed);
-    const int nfar = __popcll(fmask), ncl = __popcll(cmask);
-    const int slot = far ? __popcll(fmask & below) : nfar + __popcll(cmask & below);
+    const bool closed = lane < nb && !flag && tier == 0;
+    const unsigned long long nmask = __ballot(flag), m4 = __ballot(tier == 4), m5 = __ballot(tier == 5),
+                             m6 = __ballot(tier == 6), cmask = __ballot(closed);
+    const int n4 = __popcll(m4), n5 = __popcll(m5), n6 = __popcll(m6), ncl = __popcll(cmask);
+    const int nfar = n4 + n5 + n6;
+    const int slot = tier == 4 ? __popcll(m4 & below)
+                   : tier == 5 ? n4 + __popcll(m5 & below)
+                   : tier == 6 ? n4 + n5 + __popcll(m6 & below)
+                               : nfar + __popcll(cmask & below);
     wave_sync();                        // the previous block's reads precede these writes
-    if (far || closed) {
+    if (tier != 0 || closed) {
       float* lw = L.dsh + LS * slot;
       *(float4*)lw = w0;
       *(float4*)(lw + 4) = w1;
       *(float4*)(lw + 8) = w2;
-      if (LS > 12) *(float4*)(lw + 12) = w3;
+      if (LS > 12 && tier == 6) *(float4*)(lw + 12) = w3;
     }
     wave_sync();
     if constexpr (FAR) {
-      for (int c0 = 0; c0 < nfar; c0 += LF_CHUNK) {
-        const int n = min(LF_CHUNK, nfar - c0);
-        const float* lr = L.dsh + LS * c0;
-        Run32 ps[TP];
-#pragma unroll
-        for (int k = 0; k < TP; ++k) run_zero<false>(ps[k]);
-        if (n == LF_CHUNK) {
-#pragma unroll
-          for (int k = 0; k < LF_CHUNK; ++k) tile_term_far<TP>(lr + LS * k, L, ps);
-        } else {
-          for (int k = 0; k < n; ++k) tile_term_far<TP>(lr + LS * k, L, ps);
-        }
-#pragma unroll
-        for (int k = 0; k < TP; ++k) run_flush<false>(ps[k], acc[k]);
-      }
+      far_runs<TP, 4, LS>(0, n4, L, acc);
+      far_runs<TP, 5, LS>(n4, n4 + n5, L, acc);
+      far_runs<TP, 6, LS>(n4 + n5, nfar, L, acc);
     }
     for (int c0 = nfar; c0 < nfar + ncl; c0 += LF_CHUNK) {
       const int n = min(LF_CHUNK, nfar + ncl - c0);

@@ -153,7 +153,9 @@ size_t map_footprint(const lf_server* s, const lf_request& r) {
   long long P = (long long)r.grid.nx * r.grid.ny;
   long long chunkP = (long long)s->cfg.map_chunk_rows * r.grid.nx;
   size_t nb = r.model->mem.size();
-  return 256 * 10 + sizeof(double) * r.model->n_free + sizeof(double) * map_planes(r.kind) * P + sizeof(int) * P +
+  const bool dev = r.out_device != nullptr;     // the caller's device memory holds the result
+  return 256 * 10 + sizeof(double) * r.model->n_free + (dev ? 0 : sizeof(double) * map_planes(r.kind) * P) +
+         (dev && !r.flags_device ? sizeof(int) * chunkP : dev ? 0 : sizeof(int) * P) +
          chunkP * (sizeof(double) * 9 + sizeof(int)) + sizeof(lf::MainRec) * std::max<size_t>(1, r.model->main.size()) +
          sizeof(lf::MulRec) + (sizeof(lf::MemRec32) + sizeof(lf::MemRec64)) * std::max<size_t>(1, nb);
 }
@@ -212,8 +214,15 @@ bool admit_map(lf_server* s, Req& q) {
   bool ok = true;
   auto get = [&](size_t b) { void* p = ok ? take(s, q, b) : nullptr; if (!p) ok = false; return p; };
   q.d_params = (double*)get(sizeof(double) * std::max<size_t>(1, r.model->n_free));
-  q.d_out = (double*)get(sizeof(double) * q.n_planes * q.P);
-  q.d_flags = (int*)get(sizeof(int) * q.P);
+  if (r.out_device) {
+    // result in the caller's device memory; without flags_device, chunk-sized scratch for the
+    // flags every chunk writes
+    q.d_out = r.out_device;
+    q.d_flags = r.flags_device ? r.flags_device : (int*)get(sizeof(int) * chunkP);
+  } else {
+    q.d_out = (double*)get(sizeof(double) * q.n_planes * q.P);
+    q.d_flags = (int*)get(sizeof(int) * q.P);
+  }
   q.part = (double*)get(chunkP * (sizeof(double) * 9 + sizeof(int)));
   q.mains = (lf::MainRec*)get(sizeof(lf::MainRec) * std::max<size_t>(1, r.model->main.size()));
   q.muls = (lf::MulRec*)get(sizeof(lf::MulRec));
@@ -347,7 +356,7 @@ void launch_map_chunk(lf_server* s, int si, const std::shared_ptr<Req>& qp) {
   } else {
     o.mu = q.d_out + off;
   }
-  o.flags = q.d_flags + off;
+  o.flags = (r.out_device && !r.flags_device) ? q.d_flags : q.d_flags + off;   // (outputs are chunk-relative)
   lf::DevModel dm = lf_dev_model(r.model);
   bool mixed = r.prec == LF_PREC_MIXED;
   double* part = lf::has_heavy(dm) ? q.part : nullptr;
@@ -356,11 +365,13 @@ void launch_map_chunk(lf_server* s, int si, const std::shared_ptr<Req>& qp) {
   lf::launch_maps(dm, q.mains, q.m32, q.m64, 1, ps, r.a_dis, mixed, d3, o, lf_quad(s->ctx), ppl, part, 2, st);
   q.next_row += rows;
   const size_t n = (size_t)rows * r.grid.nx;
-  for (int p = 0; p < q.n_planes; ++p)
-    hipMemcpyAsync((double*)r.out_host + p * q.P + off, q.d_out + p * q.P + off, sizeof(double) * n,
-                   hipMemcpyDeviceToHost, st);
-  if (r.flags_host)
-    hipMemcpyAsync((int*)r.flags_host + off, q.d_flags + off, sizeof(int) * n, hipMemcpyDeviceToHost, st);
+  if (r.out_host) {
+    for (int p = 0; p < q.n_planes; ++p)
+      hipMemcpyAsync((double*)r.out_host + p * q.P + off, q.d_out + p * q.P + off, sizeof(double) * n,
+                     hipMemcpyDeviceToHost, st);
+    if (r.flags_host)
+      hipMemcpyAsync((int*)r.flags_host + off, q.d_flags + off, sizeof(int) * n, hipMemcpyDeviceToHost, st);
+  }
   Unit u;
   u.stream = si;
   u.last_chunk = q.next_row >= r.grid.ny;
@@ -480,8 +491,9 @@ extern "C" lf_status lf_serve_start(lf_ctx* ctx, const lf_serve_config* cfg, lf_
 extern "C" lf_status lf_serve_submit(lf_server* s, const lf_request* req, int64_t* ticket) {
   if (!s || !req || !ticket) return LF_E_INVALID_ARG;
   const lf_request& r = *req;
-  if (!r.model || !r.out_host || (r.prec != LF_PREC_FP64 && r.prec != LF_PREC_MIXED))
-    return LF_E_INVALID_ARG;
+  if (!r.model || (r.prec != LF_PREC_FP64 && r.prec != LF_PREC_MIXED)) return LF_E_INVALID_ARG;
+  const bool map = r.kind == LF_REQ_MU_MAP || r.kind == LF_REQ_SING_MAP;
+  if (map ? (!r.out_host == !r.out_device) : (!r.out_host || r.out_device)) return LF_E_INVALID_ARG;
   auto q = std::make_shared<Req>();
   q->r = r;
   if (r.kind == LF_REQ_CHI2) {

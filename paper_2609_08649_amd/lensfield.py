@@ -107,6 +107,7 @@ def lib():
             "lf_chi2_batch_noalloc": (I32, [P, P, P, I32, P, I32, I32, P, P, P, P]),
             "lf_chi2_images": (I32, [P, P, P, I32, P, I32, P, P, P, P, P, P]),
             "lf_find_images": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
+            "lf_find_images_alpha": (I32, [P, P, P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, P, P, P, P, P]),
             "lf_find_images_ms": (I32, [P, P, P, P, P, I32, C.POINTER(lf_grid), I32, I32, I32, P, P, P, P, P]),
             "lf_multiplane_trace": (I32, [P, P, P, I32, C.POINTER(lf_cosmo), P, I32, C.POINTER(lf_points), I32,
                                           P, P, P, P]),
@@ -444,6 +445,29 @@ def _find(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PRE
     return {"theta": th, "mu": mu, "count": cnt, "flags": fl}
 
 
+def _find_alpha(self, model: Model, params, alpha_x, alpha_y, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64,
+                stream=None, out=None):
+    """Images of n_src sources on a grid whose vertex deflections alpha_x, alpha_y (device f64,
+    nx * ny each, e.g. lens_maps outputs on that grid) are already computed."""
+    n = beta.shape[0]
+    dev = self.device
+    if out is None:
+        out = {"theta": torch.zeros((n, max_img, 2), dtype=torch.float64, device=dev),
+               "mu": torch.zeros((n, max_img), dtype=torch.float64, device=dev),
+               "count": torch.zeros(n, dtype=torch.int32, device=dev),
+               "flags": torch.zeros(n, dtype=torch.int32, device=dev)}
+    th, mu, cnt, fl = out["theta"], out["mu"], out["count"], out["flags"]
+    assert alpha_x.numel() == grid["nx"] * grid["ny"] and alpha_y.numel() == alpha_x.numel()
+    g = lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"])
+    pp = C.c_void_p(params.data_ptr()) if params is not None else None
+    self.check(lib().lf_find_images_alpha(self.handle, model.handle, pp, C.c_void_p(alpha_x.data_ptr()),
+                                          C.c_void_p(alpha_y.data_ptr()), C.c_void_p(beta.data_ptr()),
+                                          C.c_void_p(a_src.data_ptr()), int(n), C.byref(g), int(max_img), int(prec),
+                                          C.c_void_p(th.data_ptr()), C.c_void_p(mu.data_ptr()),
+                                          C.c_void_p(cnt.data_ptr()), C.c_void_p(fl.data_ptr()), _stream(stream)))
+    return {"theta": th, "mu": mu, "count": cnt, "flags": fl}
+
+
 def _planes_arg(planes, z_planes, H0, Om):
     arr = (C.c_void_p * len(planes))(*[p.handle.value for p in planes])
     zp = np.ascontiguousarray(z_planes, np.float64)
@@ -499,6 +523,7 @@ def _find_mp(self, planes, z_planes, beta, z_src, grid, max_img=16, prec=LF_PREC
 
 
 Context.find_images = _find
+Context.find_images_alpha = _find_alpha
 
 
 def _find_ms(self, model: Model, params, beta, a_src, grid, max_img=16, prec=LF_PREC_FP64, polish=True,
@@ -644,7 +669,8 @@ class lf_serve_config(C.Structure):
 class lf_request(C.Structure):
     _fields_ = [("kind", C.c_int32), ("S", C.c_int32), ("model", C.c_void_p), ("cons", C.c_void_p),
                 ("params", C.c_void_p), ("mode", C.c_int32), ("prec", C.c_int32), ("grid", lf_grid),
-                ("a_dis", C.c_double), ("out_host", C.c_void_p), ("flags_host", C.c_void_p)]
+                ("a_dis", C.c_double), ("out_host", C.c_void_p), ("flags_host", C.c_void_p),
+                ("out_device", C.c_void_p), ("flags_device", C.c_void_p)]
 
 
 class Server:
@@ -674,17 +700,21 @@ class Server:
         out = out if out is not None else torch.empty(S, dtype=torch.float64, pin_memory=True)
         flags = flags if flags is not None else torch.empty(S, dtype=torch.int32, pin_memory=True)
         req = lf_request(LF_REQ_CHI2, S, model.handle.value, cons.handle.value, p.ctypes.data if p.size else None,
-                         int(mode), int(prec), lf_grid(0, 0, 1, 1, 1), 1.0, out.data_ptr(), flags.data_ptr())
+                         int(mode), int(prec), lf_grid(0, 0, 1, 1, 1), 1.0, out.data_ptr(), flags.data_ptr(), None,
+                         None)
         return self._submit(req, (p, out, flags)), out, flags
 
     def submit_map(self, model, params, grid, a_dis, kind=LF_REQ_MU_MAP, prec=LF_PREC_MIXED, out=None):
+        """out: pinned host [planes, P] (allocated when None), or a device tensor of that shape to
+        keep the result on the device (no copy to the host)."""
         planes = 6 if kind == LF_REQ_SING_MAP else 1
         P = grid["nx"] * grid["ny"]
         out = out if out is not None else torch.empty((planes, P), dtype=torch.float64, pin_memory=True)
+        on_dev = out.is_cuda
         p = np.ascontiguousarray(params, np.float64) if params is not None else None
         req = lf_request(int(kind), 1, model.handle.value, None, p.ctypes.data if p is not None else None, 0, int(prec),
                          lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"]), float(a_dis),
-                         out.data_ptr(), None)
+                         None if on_dev else out.data_ptr(), None, out.data_ptr() if on_dev else None, None)
         return self._submit(req, (p, out)), out
 
     def poll(self, ticket):

@@ -159,3 +159,25 @@ def test_find_candidate_overflow_is_deterministic(lf, orc, monkeypatch):
     for s in range(first):
         compare({k: v[s:s + 1] for k, v in g1.items()}, {k: v[s % 5:s % 5 + 1] for k, v in o.items()
                                                           if k in ("count", "theta", "mu")}, 1e-9)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_find_on_the_maps_deflections(ctx, lf, prec):
+    """lf_find_images_alpha on the deflection planes lf_lens_maps wrote for the same sample and
+    grid (the 2048^2 cluster launch) gives lf_find_images' results bit for bit."""
+    import torch
+    cfg = W.config2(n_samples=1)
+    beta, zs, a = lensdata.cluster_sources()
+    P_ = lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED
+    m = ctx.upload_model(cfg["model"])
+    pp = torch.as_tensor(cfg["truth"][None], device="cuda")
+    b = torch.as_tensor(beta, device="cuda")
+    aa = torch.as_tensor(a, device="cuda")
+    maps = ctx.lens_maps(m, pp, 1, cfg["grid"], 0.7, P_, outputs=("alpha_x", "alpha_y", "mu"))
+    r1 = ctx.find_images_alpha(m, pp, maps["alpha_x"][0], maps["alpha_y"][0], b, aa, cfg["grid"], 16, P_)
+    r2 = ctx.find_images(m, pp, b, aa, cfg["grid"], 16, P_)
+    torch.cuda.synchronize()
+    for k in ("count", "theta", "mu", "flags"):
+        assert torch.equal(r1[k], r2[k]), k
+    assert int(r1["count"].sum()) >= 150
+    m.release()

@@ -102,6 +102,38 @@ def test_served_maps_equal_direct_maps(lf, env):
         assert np.array_equal(out2.numpy()[k], d2[name].cpu().numpy()[0]), name
 
 
+def test_device_resident_map_results(lf, env):
+    """Maps served into caller-owned device memory (no copy to the host; their output planes are
+    not charged to the budget) equal the host-copied results bit for bit, beside chi^2 requests;
+    a request with both or neither output is refused."""
+    import torch
+    ctx, cfg, m, cons = env[0], env[1], env[2], env[3]
+    grid = {"x0": -50.0, "y0": -50.0, "h": 100.0 / 384, "nx": 384, "ny": 300}
+    P = grid["nx"] * grid["ny"]
+    # 1 MB of planes per singularity map, beyond a budget that holds the rest of the request
+    srv = lf.Server(ctx, 6 << 20, n_streams=3, map_chunk_rows=41)
+    dev = torch.full((6, P), np.nan, dtype=torch.float64, device="cuda")
+    dmu = torch.full((1, P), np.nan, dtype=torch.float64, device="cuda")
+    c = srv.submit_chi2(m, cons, cfg["params"][:64], 0)
+    t1, _ = srv.submit_map(m, cfg["params"][0], grid, 0.4, lf.LF_REQ_SING_MAP, lf.LF_PREC_MIXED, out=dev)
+    t2, _ = srv.submit_map(m, cfg["params"][0], grid, 0.6, lf.LF_REQ_MU_MAP, lf.LF_PREC_FP64, out=dmu)
+    assert srv.wait(t1)[0] == 1 and srv.wait(t2)[0] == 1 and srv.wait(c[0])[0] == 1
+    srv.stop()
+    srv = lf.Server(ctx, 1 << 30, n_streams=2, map_chunk_rows=41)
+    h1 = srv.submit_map(m, cfg["params"][0], grid, 0.4, lf.LF_REQ_SING_MAP, lf.LF_PREC_MIXED)
+    h2 = srv.submit_map(m, cfg["params"][0], grid, 0.6, lf.LF_REQ_MU_MAP, lf.LF_PREC_FP64)
+    assert srv.wait(h1[0])[0] == 1 and srv.wait(h2[0])[0] == 1
+    req = lf.lf_request(lf.LF_REQ_MU_MAP, 1, m.handle.value, None, None, 0, lf.LF_PREC_MIXED,
+                        lf.lf_grid(grid["x0"], grid["y0"], grid["h"], grid["nx"], grid["ny"]), 0.6,
+                        h2[1].data_ptr(), None, dmu.data_ptr(), None)
+    with pytest.raises(lf.LfError):
+        srv._submit(req, None)
+    srv.stop()
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy(), h1[1].numpy())
+    assert np.array_equal(dmu.cpu().numpy(), h2[1].numpy())
+
+
 def test_budget_admission_and_errors(lf, env):
     ctx, cfg, m, cons = env[0], env[1], env[2], env[3]
     # ~4.3 MB per 256-sample request against a 12 MB budget: requests queue and all finish
