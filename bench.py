@@ -1194,8 +1194,40 @@ def precision_report_more(ctx, lf, torch, W):
     for p in pl:
         p.release()
     out["multiplane"] = rep
-    # refined A3 crossings (Sec. 6)
+    # third derivatives and A3 fields of the cluster model (Sec. 6): 3000 random points of the
+    # field and 1200 at the members' near-field radius 3 b/q and its edges
     cfg1 = W.config2(n_samples=1)
+    tabc = orc.expand(cfg1["model"], cfg1["params"][0])
+    mem = tabc[2:]
+    rng = np.random.default_rng(43)
+    x, y = W.random_points(43, 3000, 100.0)
+    k = rng.integers(0, mem.shape[0], 1200)
+    d = 3.0 * mem[k, 3] / mem[k, 4] * rng.choice([0.5, 0.999, 1.001, 1.5, 3.0], 1200)
+    t = rng.uniform(0, 2 * np.pi, 1200)
+    x = np.concatenate([x, mem[k, 1] + d * np.cos(t)])
+    y = np.concatenate([y, mem[k, 2] + d * np.sin(t)])
+    od = orc.maps(tabc, x, y, 0.5)
+    m = ctx.upload_model(cfg1["model"])
+    pc = torch.as_tensor(cfg1["params"][:1], device=dev)
+    tx, ty = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+    names = {"p111": "psi111", "p112": "psi112", "p122": "psi122", "p222": "psi222", "f1": "f1", "f2": "f2"}
+    rep = {"points": int(x.size), "note": "|d| / (1 + |oracle|); |f_k| where |gamma| > 0.05 (eigenvectors "
+                                          "turn as d gamma / |gamma|), relative to 1 + |f| + max |psi_ijk|"}
+    t3 = np.max(np.abs(np.stack([od[q] for q in ("p111", "p112", "p122", "p222")])), axis=0)
+    well = np.hypot(od["gamma1"], od["gamma2"]) > 0.05
+    for name, P in precs:
+        g = ctx.lens_maps(m, pc, 1, (tx, ty), 0.5, P, outputs=tuple(names.values()) + ("gamma1", "gamma2"))
+        g = {q: v[0].cpu().numpy() for q, v in g.items()}
+        r = {}
+        for q, gq in names.items():
+            if q in ("f1", "f2"):
+                r[q] = _q((np.abs(np.abs(g[gq]) - np.abs(od[q])) / (1 + np.abs(od[q]) + t3))[well])
+            else:
+                r[q] = _q(np.abs(g[gq] - od[q]) / (1 + np.abs(od[q])))
+        rep[name] = r
+    m.release()
+    out["third_derivatives"] = rep
+    # refined A3 crossings (Sec. 6)
     full = {"x0": -100.0, "y0": -100.0, "h": 200.0 / 4096, "nx": 4096, "ny": 4096}
     i0 = j0 = 1968
     n = 160

@@ -1,6 +1,8 @@
-"""Uneven batched chi^2 (persistent launch in a hipGraph, autotuned tiles): every item's
-result is bit-identical to lf_chi2_batch on that item alone (both GPU), graph replays track
-new parameter contents, and two items are compared with the oracle at the chi^2 tolerances."""
+"""Uneven batched chi^2 (persistent launch in a hipGraph, autotuned tiles) at the full uneven-batch
+size (8 models of 50-800 halos and 40-400 images, 512 walkers each): every item's result is
+bit-identical to lf_chi2_batch on that item alone (both GPU), graph replays track new parameter
+contents, and every item is compared with the oracle at the chi^2 tolerances in both
+precisions."""
 import os
 
 import numpy as np
@@ -37,7 +39,7 @@ def _cons(m, adis):
 @pytest.fixture(scope="module")
 def cfg3(ctx, lf):
     import torch
-    cfg = W.config3(walkers_per_model=96)
+    cfg = W.config3(walkers_per_model=512)
     items = []
     for m in cfg["models"]:
         mod = ctx.upload_model(m["model"])
@@ -84,27 +86,42 @@ def test_batch_graph_replays_track_new_parameters(ctx, lf, cfg3):
     b.release()
 
 
-def test_batch_items_against_oracle(ctx, lf, orc, cfg3):
-    import torch
+@pytest.fixture(scope="module")
+def oracle_items(orc, cfg3):
+    """The oracle's source-plane chi^2 of every item and the largest |mu| at each sample's
+    constraint positions (random points: some sit next to critical curves)."""
+    from tests.lensdata import mu_max
     cfg, items = cfg3
-    b = lf.Batch(ctx, items, 0, lf.LF_PREC_FP64, autotune=False)
-    outs = b.run()
-    torch.cuda.synchronize()
-    for k in (0, 5):
-        m = cfg["models"][k]
+    out = []
+    for k, m in enumerate(cfg["models"]):
         p = items[k][2].cpu().numpy()
         tabs = orc.expand_batch(m["model"], p)
         cons = _cons(m, orc.adis)
-        o = orc.chi2_batch(tabs, cons)
+        out.append((orc.chi2_batch(tabs, cons)["chi2_src"], mu_max(orc, tabs, cons)))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_items_against_oracle(ctx, lf, cfg3, oracle_items, prec):
+    """FP64: relative 1e-9 + 1e-15 mu_max^2 on every sample.  MIXED: relative 1e-3 + 4e-5 mu_max.
+    The constraint positions are random points, so most samples have an image next to a critical
+    curve (median mu_max ~ 10^3); there det A carries the member terms' error, |d det A| <=
+    2e-5 (the maps bar), so mu moves by 2e-5 |mu| relative and W = mu^T S^-1 mu by twice that:
+    at most 4e-5 mu_max of chi^2 if that image's term is all of it."""
+    import torch
+    cfg, items = cfg3
+    b = lf.Batch(ctx, items, 0, lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED, autotune=False)
+    outs = b.run()
+    torch.cuda.synchronize()
+    for k in range(len(items)):
+        o, mu = oracle_items[k]
         g = outs[k][0].cpu().numpy()
-        a = cons["a_fam"][cons["family"]]
-        mu = np.zeros(len(tabs))
-        for s, t in enumerate(tabs):
-            mm = orc.maps(t, cons["theta"][:, 0], cons["theta"][:, 1], 1.0)
-            det = (1 - a * mm["p11"]) * (1 - a * mm["p22"]) - a * a * mm["p12"] ** 2
-            mu[s] = np.max(np.abs(1 / det))
-        tol = 1e-9 + 1e-15 * mu ** 2
-        assert np.all(np.abs(g - o["chi2_src"]) <= tol * np.abs(o["chi2_src"]) + tol)
+        if prec == "fp64":
+            tol = 1e-9 + 1e-15 * mu ** 2
+            assert np.all(np.abs(g - o) <= tol * np.abs(o) + tol), k
+        else:
+            tol = 1e-3 + 4e-5 * mu
+            assert np.all(np.abs(g - o) <= tol * np.abs(o) + 1e-3), k
     b.release()
 
 
