@@ -43,7 +43,7 @@ F_CPJE = 39
 # third-derivative form, and the points each of their lanes holds.
 LEAN_KERNEL = "lf::k_maps_tile<false>"
 LEAN_D3_KERNEL = "lf::k_maps_tile<true>"
-LANE_POINTS = {LEAN_KERNEL: 2, LEAN_D3_KERNEL: 1}
+LANE_POINTS = {LEAN_KERNEL: 2, LEAN_D3_KERNEL: 2}
 
 # Sources that define the lean maps kernel: a traffic measurement is reported only while
 # their hash matches the one recorded with the counters.

@@ -59,24 +59,30 @@ static constexpr double NEAR_K = 3.0;
 // Pre-scaled member record for one sample.  The FP32 flavour keeps the centre as an FP32
 // pair (as in MemCat32).  bd = b (a - s) and apls = a + s are formed in FP64 before rounding
 // (they feed the cancellation-free dPIE form); rn2 is the squared near-field radius.
-// fm, fw: coefficients of the far-field expansion of a circular dPIE in t = 1/r (valid for
-// r >= FAR_K a): m = u (fm0 + t (fm1 + u (fm2 + u (fm3 + u (fm4 + u fm5))))) and
-// w = u^2 (fw0 + t (fw1 + u (...))), u = t^2 (see lf_segs.h).
+// fm, fw, fwp: coefficients of the far-field expansion of a circular dPIE in t = 1/r (valid for
+// r >= FAR_K a): m = u (fm0 + t (fm1 + u (fm2 + u (fm3 + u (fm4 + u fm5))))),
+// w = u^2 (fw0 + t (fw1 + u (...))) and w' = dw/d(r^2) = u^3 (fwp0 + t (fwp1 + u (...))),
+// u = t^2 (see lf_segs.h).
 struct MemRec32 {
   float xh, xl, yh, yl;
   float b, s, a, s2, a2, bd, apls, rn2;   // the circular segments read these 12 words only
   float c, sn, q2, e, bqe, pad0, pad1, pad2;
-  float fm[6], fw[6];
+  float fm[6], fw[6], fwp[6];
 };
 
 // Far field of a circular dPIE member: at r >= FAR_K a the truncated expansion of its closed
 // form in 1/r (terms through 1/r^11) is exact to 4e-9 (m) and 3e-8 (w) relative, below FP32
 // rounding; farther out fewer terms reach the same bound: five (through 1/r^9) at r >= FAR_K5 a
 // (6e-9, 4e-8) and four (through 1/r^7) at r >= FAR_K4 a (5e-9, 2e-8), for cores s <= 0.95 a.
+// With third derivatives w' (its series converging more slowly) sets the bounds: six terms at
+// r >= FAR_D3_K a, five at FAR_D3_K5 a, four at FAR_D3_K4 a (w' within 2e-8, 4e-8, 2e-8).
 // FAR_AMAX bounds a so that the FP32 coefficients (~ b a^10) stay finite.
 static constexpr double FAR_K = 5.0;
 static constexpr double FAR_K5 = 7.0;
 static constexpr double FAR_K4 = 13.0;
+static constexpr double FAR_D3_K = 6.0;
+static constexpr double FAR_D3_K5 = 8.0;
+static constexpr double FAR_D3_K4 = 15.0;
 static constexpr double FAR_AMAX = 1e3;
 struct MemRec64 {
   double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, bd, apls;

@@ -132,8 +132,12 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
             ap *= a * a;
             mk = b * beta[k] * (sp - ap);
           }
+          // m's term in t^p (p = 2, 3, 5, ...) gives w's in t^(p+2) (factor -p) and w''s in
+          // t^(p+4) (factor -(p+2)/2: w' = dw/d(r^2) = -(t^3/2) dw/dt)
+          const double p = 2 * k + 1 + (k == 0);
           r.fm[k] = far_ok ? (float)mk : 0.f;
-          r.fw[k] = far_ok ? (float)(-(2 * k + 1 + (k == 0)) * mk) : 0.f;
+          r.fw[k] = far_ok ? (float)(-p * mk) : 0.f;
+          r.fwp[k] = far_ok ? (float)(0.5 * (p + 2.0) * p * mk) : 0.f;
         }
         m32[(size_t)s * m.n_mem + i] = r;
       }
@@ -293,15 +297,15 @@ __global__ __launch_bounds__(256) void k_maps(const MapsArgs A) {
 // global grid (seg_loop_tile; a lane holds TP points of one column, TILE_H rows apart), the
 // blocks covering the grid rows of the points [p0, p0 + P).  Lanes' points outside those points
 // (or past the last column) take part in the member loops but store nothing.
-// Without third derivatives: two points per lane (each LDS record read serves both; the LDS
-// data path, which returns a broadcast record to every lane, is the other limit of this loop)
-// at 4 waves per SIMD (102 VGPRs), measured faster than one point per lane at 8 waves and four
-// points at 3 or 4; with third derivatives one point per lane at 7 waves.
+// Two points per lane (each LDS record read serves both; the LDS data path, which returns a
+// broadcast record to every lane, is the other limit of this loop): without third derivatives
+// at 4 waves per SIMD (104 VGPRs), measured faster than one point per lane at 8 waves and four
+// points at 3 or 4; with third derivatives at 3 waves (faster than one point per lane at 4-7).
 template <bool D3>
-static constexpr int MAPS_TP = D3 ? 1 : 2;
+static constexpr int MAPS_TP = 2;
 
 template <bool D3>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D3 ? 7 : 4, 8))) void k_maps_tile(const MapsArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D3 ? 3 : 4, 8))) void k_maps_tile(const MapsArgs A) {
   constexpr int TP = MAPS_TP<D3>, TH = TILE_H * TP;
   __shared__ float dsh[4][64 * TILE_LSTRIDE<SEG_CPJE, D3>];
   const int s = blockIdx.y;

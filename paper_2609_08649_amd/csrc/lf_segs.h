@@ -263,9 +263,9 @@ struct MemL {
   float b, s, a, s2, a2, bd, apls;
 };
 template <int SEG, bool D3>
-static constexpr bool TILE_FAR = SEG == SEG_CPJE && !D3;
+static constexpr bool TILE_FAR = SEG == SEG_CPJE;
 template <int SEG, bool D3>
-static constexpr int TILE_LSTRIDE = TILE_FAR<SEG, D3> ? 16 : 12;
+static constexpr int TILE_LSTRIDE = TILE_FAR<SEG, D3> ? (D3 ? 20 : 16) : 12;
 
 // closed form (three transcendentals per point)
 template <int SEG, bool D3, int TP>
@@ -287,15 +287,23 @@ __device__ __forceinline__ void tile_term_l(const float* l, const TileLane<TP>& 
 }
 
 // far-field expansion of a circular dPIE (one transcendental per point), NT = 4, 5 or 6 terms:
-// with t = 1/r and u = t^2, m = u (fm0 + t (fm1 + u (fm2 + ...))), w = u^2 (fw0 + t (fw1 + ...)).
-// The record holds Dx, Dy, fm0..fm(NT-1), fw0..fw(NT-1) contiguously.
-template <int TP, int NT>
+// with t = 1/r and u = t^2, m = u (fm0 + t (fm1 + u (fm2 + ...))), w = u^2 (fw0 + t (fw1 + ...))
+// and, with third derivatives, w' = u^3 (fwp0 + t (fwp1 + ...)).  The record holds Dx, Dy,
+// fm0..fm(NT-1), fw0..fw(NT-1) (and fwp0..fwp(NT-1)) contiguously.
+template <int NT>
+__device__ __forceinline__ float far_poly(const float* c, float t, float uu) {
+  float p = fmaf(uu, c[NT - 1], c[NT - 2]);
+#pragma unroll
+  for (int j = NT - 3; j >= 1; --j) p = fmaf(uu, p, c[j]);
+  return fmaf(t, p, c[0]);
+}
+template <int TP, int NT, bool D3>
 __device__ __forceinline__ void tile_term_far(const float* l, const TileLane<TP>& L, Run32 (&ps)[TP]) {
   static_assert(NT >= 4 && NT <= 6, "four to six terms");
-  // 16-byte reads, and an 8-byte one for a 2-float tail (a broadcast read moves its size times
-  // 64 lanes through the LDS return path, the resource the far-field loop is closest to)
-  constexpr int NF = 2 + 2 * NT;
-  float f[16];
+  // 16-byte reads, and an 8- or 4-byte one for a short tail (a broadcast read moves its size
+  // times 64 lanes through the LDS return path)
+  constexpr int NF = 2 + (D3 ? 3 : 2) * NT;
+  float f[20];
 #pragma unroll
   for (int q = 0; q < NF / 4; ++q) {
     const float4 v = *(const float4*)(l + 4 * q);
@@ -304,47 +312,68 @@ __device__ __forceinline__ void tile_term_far(const float* l, const TileLane<TP>
   if constexpr (NF % 4 == 2) {
     const float2 v = *(const float2*)(l + NF - 2);
     f[NF - 2] = v.x; f[NF - 1] = v.y;
+  } else if constexpr (NF % 4 == 1) {
+    f[NF - 1] = l[NF - 1];
+  } else if constexpr (NF % 4 == 3) {
+    const float2 v = *(const float2*)(l + NF - 3);
+    f[NF - 3] = v.x; f[NF - 2] = v.y; f[NF - 1] = l[NF - 1];
   }
-  const float* fm = f + 2;
-  const float* fw = f + 2 + NT;
   const float dx = L.u - f[0];
   const float dx2 = dx * dx;
 #pragma unroll
   for (int k = 0; k < TP; ++k) {
     const float dy = L.v[k] - f[1];
     const float r2 = fmaf(dy, dy, dx2);
-    const float t = frsq(r2), uu = t * t;
-    float pm = fmaf(uu, fm[NT - 1], fm[NT - 2]);
-    float pw = fmaf(uu, fw[NT - 1], fw[NT - 2]);
-#pragma unroll
-    for (int j = NT - 3; j >= 1; --j) {
-      pm = fmaf(uu, pm, fm[j]);
-      pw = fmaf(uu, pw, fw[j]);
-    }
-    pm = fmaf(t, pm, fm[0]);
-    pw = fmaf(t, pw, fw[0]);
-    run_add<false>(dx, dy, r2, uu * pm, (uu * uu) * pw, 0.f, ps[k]);
+    const float t = frsq(r2), uu = t * t, uu2 = uu * uu;
+    const float pm = far_poly<NT>(f + 2, t, uu), pw = far_poly<NT>(f + 2 + NT, t, uu);
+    const float wp = D3 ? (uu2 * uu) * far_poly<NT>(f + 2 + 2 * NT, t, uu) : 0.f;
+    run_add<D3>(dx, dy, r2, uu * pm, uu2 * pw, wp, ps[k]);
   }
 }
 
 // The runs of one far-field tier: records [c_begin, c_end) of the wave's LDS list.
-template <int TP, int NT, int LS>
+template <int TP, int NT, int LS, bool D3>
 __device__ __forceinline__ void far_runs(int c_begin, int c_end, const TileLane<TP>& L, Acc (&acc)[TP]) {
   for (int c0 = c_begin; c0 < c_end; c0 += LF_CHUNK) {
     const int n = min(LF_CHUNK, c_end - c0);
     const float* lr = L.dsh + LS * c0;
     Run32 ps[TP];
 #pragma unroll
-    for (int k = 0; k < TP; ++k) run_zero<false>(ps[k]);
+    for (int k = 0; k < TP; ++k) run_zero<D3>(ps[k]);
     if (n == LF_CHUNK) {
 #pragma unroll
-      for (int k = 0; k < LF_CHUNK; ++k) tile_term_far<TP, NT>(lr + LS * k, L, ps);
+      for (int k = 0; k < LF_CHUNK; ++k) tile_term_far<TP, NT, D3>(lr + LS * k, L, ps);
     } else {
-      for (int k = 0; k < n; ++k) tile_term_far<TP, NT>(lr + LS * k, L, ps);
+      for (int k = 0; k < n; ++k) tile_term_far<TP, NT, D3>(lr + LS * k, L, ps);
     }
 #pragma unroll
-    for (int k = 0; k < TP; ++k) run_flush<false>(ps[k], acc[k]);
+    for (int k = 0; k < TP; ++k) run_flush<D3>(ps[k], acc[k]);
   }
+}
+
+// One far record (Dx, Dy and the first NT coefficients of m, w and, with third derivatives,
+// w') written to LDS at lw, in 16-byte stores.
+template <bool D3, int NT>
+__device__ __forceinline__ void put_far_n(float* lw, float dx, float dy, const MemRec32& r) {
+  constexpr int NF = 2 + (D3 ? 3 : 2) * NT;
+  float f[(NF + 3) / 4 * 4];
+  f[0] = dx; f[1] = dy;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    f[2 + k] = r.fm[k];
+    f[2 + NT + k] = r.fw[k];
+    if constexpr (D3) f[2 + 2 * NT + k] = r.fwp[k];
+  }
+#pragma unroll
+  for (int k = NF; k < (NF + 3) / 4 * 4; ++k) f[k] = 0.f;
+#pragma unroll
+  for (int q = 0; q < (NF + 3) / 4; ++q) *(float4*)(lw + 4 * q) = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
+}
+template <bool D3>
+__device__ __forceinline__ void put_far(float* lw, int nt, float dx, float dy, const MemRec32& r) {
+  if (nt == 4) put_far_n<D3, 4>(lw, dx, dy, r);
+  else if (nt == 5) put_far_n<D3, 5>(lw, dx, dy, r);
+  else put_far_n<D3, 6>(lw, dx, dy, r);
 }
 
 // Members are taken in blocks of 64.  Lane j of the wave takes member j of the block: its
@@ -372,7 +401,8 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
     const int nb = min(64, hi - b0);
     bool flag = false;
     int tier = 0;                       // far-field terms (4, 5 or 6), 0: closed form
-    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
+    float dxf = 0.f, dyf = 0.f;
+    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0;
     if (lane < nb) {
       const double cx = near64[b0 + lane].x, cy = near64[b0 + lane].y;
       const double ddx = cx - L.X, ddy = cy - L.Y;
@@ -381,27 +411,13 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
       const MemRec32& r = rec[b0 + lane];
       flag = e2 < (double)r.rn2 * (1.0 + 1e-5);
       const double ar = near64[b0 + lane].a, a2r = ar * ar;
+      constexpr double K4 = D3 ? FAR_D3_K4 : FAR_K4, K5 = D3 ? FAR_D3_K5 : FAR_K5, K6 = D3 ? FAR_D3_K : FAR_K;
       if (FAR && !flag && ar <= FAR_AMAX)
-        tier = e2 >= FAR_K4 * FAR_K4 * a2r ? 4 : e2 >= FAR_K5 * FAR_K5 * a2r ? 5 : e2 >= FAR_K * FAR_K * a2r ? 6 : 0;
-      const float dxf = (float)ddx, dyf = (float)ddy;
-      if (tier == 4) {
-        w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
-        w1 = make_float4(r.fm[2], r.fm[3], r.fw[0], r.fw[1]);
-        w2 = make_float4(r.fw[2], r.fw[3], 0.f, 0.f);
-      } else if (tier == 5) {
-        w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
-        w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fw[0]);
-        w2 = make_float4(r.fw[1], r.fw[2], r.fw[3], r.fw[4]);
-      } else if (tier == 6) {
-        w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
-        w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fm[5]);
-        w2 = make_float4(r.fw[0], r.fw[1], r.fw[2], r.fw[3]);
-        w3 = make_float4(r.fw[4], r.fw[5], 0.f, 0.f);
-      } else {
-        w0 = make_float4(dxf, dyf, r.s2, r.a2);
-        w1 = make_float4(r.s, r.a, r.bd, r.apls);
-        w2 = make_float4(r.b, 0.f, 0.f, 0.f);
-      }
+        tier = e2 >= K4 * K4 * a2r ? 4 : e2 >= K5 * K5 * a2r ? 5 : e2 >= K6 * K6 * a2r ? 6 : 0;
+      dxf = (float)ddx; dyf = (float)ddy;
+      w0 = make_float4(dxf, dyf, r.s2, r.a2);
+      w1 = make_float4(r.s, r.a, r.bd, r.apls);
+      w2 = make_float4(r.b, 0.f, 0.f, 0.f);
     }
     const bool closed = lane < nb && !flag && tier == 0;
     const unsigned long long nmask = __ballot(flag), m4 = __ballot(tier == 4), m5 = __ballot(tier == 5),
@@ -413,18 +429,19 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
                    : tier == 6 ? n4 + n5 + __popcll(m6 & below)
                                : nfar + __popcll(cmask & below);
     wave_sync();                        // the previous block's reads precede these writes
-    if (tier != 0 || closed) {
+    if (tier != 0) {
+      put_far<D3>(L.dsh + LS * slot, tier, dxf, dyf, rec[b0 + lane]);
+    } else if (closed) {
       float* lw = L.dsh + LS * slot;
       *(float4*)lw = w0;
       *(float4*)(lw + 4) = w1;
       *(float4*)(lw + 8) = w2;
-      if (LS > 12 && tier == 6) *(float4*)(lw + 12) = w3;
     }
     wave_sync();
     if constexpr (FAR) {
-      far_runs<TP, 4, LS>(0, n4, L, acc);
-      far_runs<TP, 5, LS>(n4, n4 + n5, L, acc);
-      far_runs<TP, 6, LS>(n4 + n5, nfar, L, acc);
+      far_runs<TP, 4, LS, D3>(0, n4, L, acc);
+      far_runs<TP, 5, LS, D3>(n4, n4 + n5, L, acc);
+      far_runs<TP, 6, LS, D3>(n4 + n5, nfar, L, acc);
     }
     for (int c0 = nfar; c0 < nfar + ncl; c0 += LF_CHUNK) {
       const int n = min(LF_CHUNK, nfar + ncl - c0);

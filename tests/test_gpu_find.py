@@ -28,7 +28,7 @@ def _run(ctx, lf, model, params, beta, a, grid, prec, max_img=16):
     import torch
     m = ctx.upload_model(model)
     b = torch.as_tensor(np.ascontiguousarray(beta, np.float64), device="cuda")
-    aa = torch.as_tensor(np.ascontiguousarray(np.broadcast_to(a, (beta.shape[0],)), np.float64), device="cuda")
+    aa = torch.as_tensor(np.array(np.broadcast_to(a, (beta.shape[0],)), np.float64), device="cuda")
     pp = torch.as_tensor(params, device="cuda") if params is not None else None
     r = ctx.find_images(m, pp, b, aa, grid, max_img, lf.LF_PREC_FP64 if prec == "fp64" else lf.LF_PREC_MIXED)
     torch.cuda.synchronize()
