@@ -59,15 +59,16 @@ static constexpr double NEAR_K = 3.0;
 // Pre-scaled member record for one sample.  The FP32 flavour keeps the centre as an FP32
 // pair (as in MemCat32).  bd = b (a - s) and apls = a + s are formed in FP64 before rounding
 // (they feed the cancellation-free dPIE form); rn2 is the squared near-field radius.
-// fm, fw, fwp: coefficients of the far-field expansion of a circular dPIE in t = 1/r (valid for
-// r >= FAR_K a): m = u (fm0 + t (fm1 + u (fm2 + u (fm3 + u (fm4 + u fm5))))),
-// w = u^2 (fw0 + t (fw1 + u (...))) and w' = dw/d(r^2) = u^3 (fwp0 + t (fwp1 + u (...))),
-// u = t^2 (see lf_segs.h).
+// fm, fw: coefficients of the far-field expansion of a circular dPIE in t = 1/r (valid for
+// r >= FAR_K a): m = u (fm0 + t (fm1 + u (fm2 + u (fm3 + u (fm4 + u fm5))))) and
+// w = u^2 (fw0 + t (fw1 + u (...))), u = t^2 (see lf_segs.h).  The coefficients of
+// w' = dw/d(r^2) = u^3 (fwp0 + t (fwp1 + u (...))) are fixed multiples of fm (FAR_WP) and are
+// formed when a record is staged for third derivatives.
 struct MemRec32 {
   float xh, xl, yh, yl;
   float b, s, a, s2, a2, bd, apls, rn2;   // the circular segments read these 12 words only
   float c, sn, q2, e, bqe, pad0, pad1, pad2;
-  float fm[6], fw[6], fwp[6];
+  float fm[6], fw[6];
 };
 
 // Far field of a circular dPIE member: at r >= FAR_K a the truncated expansion of its closed
@@ -84,6 +85,9 @@ static constexpr double FAR_D3_K = 6.0;
 static constexpr double FAR_D3_K5 = 8.0;
 static constexpr double FAR_D3_K4 = 15.0;
 static constexpr double FAR_AMAX = 1e3;
+// m's term in t^p (p = 2, 3, 5, 7, 9, 11) gives w's in t^(p+2) (factor -p) and w''s in t^(p+4)
+// (w' = dw/d(r^2) = -(t^3/2) dw/dt: factor (p + 2) p / 2)
+static constexpr float FAR_WP[6] = {4.0f, 7.5f, 17.5f, 31.5f, 49.5f, 71.5f};
 struct MemRec64 {
   double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, bd, apls;
 };

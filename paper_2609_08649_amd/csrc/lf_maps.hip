@@ -132,12 +132,8 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
             ap *= a * a;
             mk = b * beta[k] * (sp - ap);
           }
-          // m's term in t^p (p = 2, 3, 5, ...) gives w's in t^(p+2) (factor -p) and w''s in
-          // t^(p+4) (factor -(p+2)/2: w' = dw/d(r^2) = -(t^3/2) dw/dt)
-          const double p = 2 * k + 1 + (k == 0);
           r.fm[k] = far_ok ? (float)mk : 0.f;
-          r.fw[k] = far_ok ? (float)(-p * mk) : 0.f;
-          r.fwp[k] = far_ok ? (float)(0.5 * (p + 2.0) * p * mk) : 0.f;
+          r.fw[k] = far_ok ? (float)(-(2 * k + 1 + (k == 0)) * mk) : 0.f;
         }
         m32[(size_t)s * m.n_mem + i] = r;
       }

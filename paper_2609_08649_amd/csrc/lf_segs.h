@@ -351,29 +351,28 @@ __device__ __forceinline__ void far_runs(int c_begin, int c_end, const TileLane<
   }
 }
 
-// One far record (Dx, Dy and the first NT coefficients of m, w and, with third derivatives,
-// w') written to LDS at lw, in 16-byte stores.
-template <bool D3, int NT>
-__device__ __forceinline__ void put_far_n(float* lw, float dx, float dy, const MemRec32& r) {
-  constexpr int NF = 2 + (D3 ? 3 : 2) * NT;
+// One far record with third derivatives (Dx, Dy and the first NT coefficients of m, w and w')
+// written to LDS at lw, in 16-byte stores.
+template <int NT>
+__device__ __forceinline__ void put_far_d3_n(float* lw, float dx, float dy, const MemRec32& r) {
+  constexpr int NF = 2 + 3 * NT;
   float f[(NF + 3) / 4 * 4];
   f[0] = dx; f[1] = dy;
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
     f[2 + k] = r.fm[k];
     f[2 + NT + k] = r.fw[k];
-    if constexpr (D3) f[2 + 2 * NT + k] = r.fwp[k];
+    f[2 + 2 * NT + k] = FAR_WP[k] * r.fm[k];
   }
 #pragma unroll
   for (int k = NF; k < (NF + 3) / 4 * 4; ++k) f[k] = 0.f;
 #pragma unroll
   for (int q = 0; q < (NF + 3) / 4; ++q) *(float4*)(lw + 4 * q) = make_float4(f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]);
 }
-template <bool D3>
-__device__ __forceinline__ void put_far(float* lw, int nt, float dx, float dy, const MemRec32& r) {
-  if (nt == 4) put_far_n<D3, 4>(lw, dx, dy, r);
-  else if (nt == 5) put_far_n<D3, 5>(lw, dx, dy, r);
-  else put_far_n<D3, 6>(lw, dx, dy, r);
+__device__ __forceinline__ void put_far_d3(float* lw, int nt, float dx, float dy, const MemRec32& r) {
+  if (nt == 4) put_far_d3_n<4>(lw, dx, dy, r);
+  else if (nt == 5) put_far_d3_n<5>(lw, dx, dy, r);
+  else put_far_d3_n<6>(lw, dx, dy, r);
 }
 
 // Members are taken in blocks of 64.  Lane j of the wave takes member j of the block: its
@@ -402,7 +401,7 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
     bool flag = false;
     int tier = 0;                       // far-field terms (4, 5 or 6), 0: closed form
     float dxf = 0.f, dyf = 0.f;
-    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0;
+    float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
     if (lane < nb) {
       const double cx = near64[b0 + lane].x, cy = near64[b0 + lane].y;
       const double ddx = cx - L.X, ddy = cy - L.Y;
@@ -418,6 +417,24 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
       w0 = make_float4(dxf, dyf, r.s2, r.a2);
       w1 = make_float4(r.s, r.a, r.bd, r.apls);
       w2 = make_float4(r.b, 0.f, 0.f, 0.f);
+      if constexpr (!D3) {
+        // without third derivatives a far record fits the closed form's three 16-byte words
+        // (four with six terms), selected here and written by one store sequence below
+        if (tier == 4) {
+          w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
+          w1 = make_float4(r.fm[2], r.fm[3], r.fw[0], r.fw[1]);
+          w2 = make_float4(r.fw[2], r.fw[3], 0.f, 0.f);
+        } else if (tier == 5) {
+          w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
+          w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fw[0]);
+          w2 = make_float4(r.fw[1], r.fw[2], r.fw[3], r.fw[4]);
+        } else if (tier == 6) {
+          w0 = make_float4(dxf, dyf, r.fm[0], r.fm[1]);
+          w1 = make_float4(r.fm[2], r.fm[3], r.fm[4], r.fm[5]);
+          w2 = make_float4(r.fw[0], r.fw[1], r.fw[2], r.fw[3]);
+          w3 = make_float4(r.fw[4], r.fw[5], 0.f, 0.f);
+        }
+      }
     }
     const bool closed = lane < nb && !flag && tier == 0;
     const unsigned long long nmask = __ballot(flag), m4 = __ballot(tier == 4), m5 = __ballot(tier == 5),
@@ -429,13 +446,14 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
                    : tier == 6 ? n4 + n5 + __popcll(m6 & below)
                                : nfar + __popcll(cmask & below);
     wave_sync();                        // the previous block's reads precede these writes
-    if (tier != 0) {
-      put_far<D3>(L.dsh + LS * slot, tier, dxf, dyf, rec[b0 + lane]);
-    } else if (closed) {
+    if (D3 && tier != 0) {
+      put_far_d3(L.dsh + LS * slot, tier, dxf, dyf, rec[b0 + lane]);
+    } else if (tier != 0 || closed) {
       float* lw = L.dsh + LS * slot;
       *(float4*)lw = w0;
       *(float4*)(lw + 4) = w1;
       *(float4*)(lw + 8) = w2;
+      if (!D3 && LS > 12 && tier == 6) *(float4*)(lw + 12) = w3;
     }
     wave_sync();
     if constexpr (FAR) {
