@@ -156,6 +156,7 @@ extern "C" lf_status lf_find_images(lf_ctx* ctx, const lf_model* M, const double
   lf::LensDev L;
   std::memset(&L, 0, sizeof L);
   L.n_planes = 1;
+  L.enfw = lf_model_has_enfw(M) ? 1 : 0;
   e = plane_sum(ctx, M, params, ps, mixed, alpha_psi_out(va, ps.P, false), "find", st, &L.pl[0]);
   if (e) return e;
   lf::QuadTab q = lf_quad(ctx);
@@ -195,6 +196,7 @@ extern "C" lf_status lf_find_images_alpha(lf_ctx* ctx, const lf_model* M, const 
   lf::LensDev L;
   std::memset(&L, 0, sizeof L);
   L.n_planes = 1;
+  L.enfw = lf_model_has_enfw(M) ? 1 : 0;
   L.pl[0].mains = mains; L.pl[0].n_main = dm.n_main; L.pl[0].mem = m64; L.pl[0].seg = dm.seg;
   lf::QuadTab q = lf_quad(ctx);
   L.qd.n = q.n; L.qd.u = q.u; L.qd.w = q.w;
@@ -233,6 +235,7 @@ extern "C" lf_status lf_find_images_ms(lf_ctx* ctx, const lf_model* M, const dou
   lf::LensDev L;
   std::memset(&L, 0, sizeof L);
   L.n_planes = 1;
+  L.enfw = lf_model_has_enfw(M) ? 1 : 0;
   e = plane_sum(ctx, M, params, ps, prec == LF_PREC_MIXED, alpha_psi_out(va, ps.P, false), "find", st, &L.pl[0]);
   if (e) return e;
   lf::QuadTab q = lf_quad(ctx);
@@ -312,6 +315,7 @@ extern "C" lf_status lf_find_images_mp(lf_ctx* ctx, const lf_model* const* plane
   lf::LensDev L;
   std::memset(&L, 0, sizeof L);
   L.n_planes = n_planes;
+  for (int j = 0; j < n_planes; ++j) L.enfw |= lf_model_has_enfw(planes[j]) ? 1 : 0;
   std::memcpy(L.wij, M.wij, sizeof L.wij);
   lf::QuadTab q = lf_quad(ctx);
   L.qd.n = q.n; L.qd.u = q.u; L.qd.w = q.w;

@@ -15,6 +15,7 @@ namespace lf {
 
 struct LensDev {           // FP64 lens for polishing: 1 plane, or planes with D_ij/D_j
   int n_planes;
+  int enfw;                  // some plane holds an elliptical NFW halo (selects kernel variants)
   Plane64 pl[LF_MAX_PLANES];
   double wij[LF_MAX_PLANES * LF_MAX_PLANES];
   Quad qd;

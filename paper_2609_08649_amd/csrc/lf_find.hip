@@ -2,18 +2,21 @@
 //
 // Finder pipeline (all on the device, no host synchronisation):
 //   1. vertex deflections on the grid (maps kernels, FP32 members in MIXED);
-//   2. k_find_cand: one lane per grid cell keeps FP32 copies of its four corners in
-//      registers and loops over the sources (staged in LDS); mapped corners
-//      beta_v = theta_v - sum_j w_j alpha_j(v); two FP32 prefilters (the mapped cell centre
-//      with a radius, then the bounding box), then the FP64 test: a triangle is a candidate
-//      when the source lies within eps of it (eps covers the vertex error of the precision in
-//      use), appended with one atomic per wave and counted per source;
+//   2. k_find_cand: one lane per grid cell (a wave per 8 x 8 tile) keeps FP32 copies of its
+//      four corners in registers; mapped corners beta_v = theta_v - sum_j w_j alpha_j(v);
+//      the wave's lanes first test 64 sources (staged in LDS) at a time against a box that
+//      holds every mapped corner of the tile, then the sources that pass go through two
+//      per-cell FP32 prefilters (the mapped cell centre with a radius, then the bounding box)
+//      and the FP64 test: a triangle is a candidate when the source lies within eps of it (eps
+//      covers the vertex error of the precision in use), appended with one atomic per wave
+//      and counted per source;
 //   3. k_find_scan / k_find_scatter / k_find_segsort: per-source segments of the candidate
 //      list (prefix sum of the counts), each sorted by triangle, so the list is ordered by
 //      (source, triangle) whatever the order of the atomics; past the capacity a second
 //      candidate pass fills the segments of the sources that fit and the rest are flagged;
-//   4. k_find_polish: per candidate, FP64 vertex deflections, exact orientation signs with
-//      the watertight tie rule, barycentric start, FP64 Newton polish and acceptance;
+//   4. k_find_polish: per candidate (one workgroup each), FP64 vertex deflections, exact
+//      orientation signs with the watertight tie rule, barycentric start, FP64 Newton polish
+//      and acceptance;
 //   5. k_find_final: per source, merge duplicates in candidate order, write images.
 #include <hip/hip_runtime.h>
 
@@ -97,15 +100,105 @@ __device__ bool d_tri_contains(const double* B, double sx, double sy) {
   return true;
 }
 
+// FP64 lens evaluation by a whole workgroup (the polishing passes take one candidate per
+// workgroup: a few hundred candidates would leave most of the chip idle at one wave each, and
+// the evaluation is a chain of dependent sums).  The halos of a plane are split over the
+// threads, each wave's partial sums combined by a butterfly of shuffles and the waves' sums
+// added in LDS in wave order, so every thread ends with the same bits and runs the iteration
+// logic alike (measured: 256 threads per workgroup beat 512 on the cluster lens, whose 304
+// work items then leave most threads one item).  ENFW = false compiles the elliptical NFW
+// quadrature out.
+constexpr int POL_T = 256;
+constexpr int POL_W = POL_T / 64;
+// Single-plane lenses with at most this many main halos and members have their FP64 records
+// copied to LDS once per workgroup (every evaluation of every candidate reads them; 5% off
+// the cluster finder's time).
+constexpr int POL_LDS_MAIN = 16, POL_LDS_MEM = 320;
+struct PolRed {
+  double v[POL_W][5];
+  int f[POL_W];
+};
+
+template <bool ENFW>
+__device__ __forceinline__ void eval_main_part(const MainRec& r, int part, double px, double py, const Quad& qd,
+                                               Acc& acc) {
+  if (r.type != T_PJE || r.q >= 1.0) {
+    if (part == 0) {
+      eval_main<false, ENFW>(r, px, py, qd, acc);
+      acc.flags |= r.flags;
+    }
+    return;
+  }
+  const double dx = px - r.x, dy = py - r.y;
+  if (part == 0) {
+    acc.flags |= r.flags;
+    if (main_singular(r) && fma(dx, dx, dy * dy) < 1e-24) { acc.flags |= FL_SINGULAR; return; }
+  } else if (main_singular(r) && fma(dx, dx, dy * dy) < 1e-24) {
+    return;
+  }
+  const double xp = r.c * dx + r.sn * dy, yp = r.c * dy - r.sn * dx;
+  Term<double> p, t;
+  esie_prime<false>(xp, yp, r.bqe, r.e, r.q2, part == 0 ? r.s : r.a, p);
+  if (part) { p.ax = -p.ax; p.ay = -p.ay; p.h11 = -p.h11; p.h12 = -p.h12; p.h22 = -p.h22; }
+  rotate_back<false>(r.c, r.sn, p, t);
+  t.t111 = t.t112 = t.t122 = t.t222 = 0.0;
+  add<false>(acc, t);
+}
+
+// Work items: the main halos' parts (two each), then the members.  With at most a quarter of
+// the threads needed for the main parts, those go to the last 2 n_main threads, one each, and
+// the members are strided over the other threads; otherwise all items are strided over all
+// threads.  (One call site per halo kind keeps the kernel's code, and its registers, small.)
+template <bool ENFW>
+__device__ void plane_sum_block(const Plane64& P, double x, double y, const Quad& qd, Acc& out, PolRed& R) {
+  Acc acc;
+  acc.zero();
+  constexpr int nt = POL_T;
+  const int nmem = P.seg.off[NSEG], msl = 2 * P.n_main;
+  const int mt = msl <= nt / 2 ? nt - msl : 0;
+  const int tid = threadIdx.x;
+  int first, stride, end;
+  if (mt == 0) { first = tid; stride = nt; end = msl + nmem; }
+  else if (tid >= mt) { first = tid - mt; stride = nt; end = first + 1; }
+  else { first = msl + tid; stride = mt; end = msl + nmem; }
+  for (int it = first; it < end; it += stride) {
+    if (it < msl) eval_main_part<ENFW>(P.mains[it >> 1], it & 1, x, y, qd, acc);
+    else member64_term<false, ENFW>(P, it - msl, x, y, qd, acc);
+  }
+  const double s0 = wsum(acc.ax), s1 = wsum(acc.ay), s2 = wsum(acc.h11), s3 = wsum(acc.h12), s4 = wsum(acc.h22);
+  const int fl = wor(acc.flags);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    R.v[wv][0] = s0; R.v[wv][1] = s1; R.v[wv][2] = s2; R.v[wv][3] = s3; R.v[wv][4] = s4;
+    R.f[wv] = fl;
+  }
+  __syncthreads();
+  double t[5];
+  int f = R.f[0];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) t[k] = R.v[0][k];
+#pragma unroll
+  for (int q = 1; q < POL_W; ++q) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) t[k] += R.v[q][k];
+    f |= R.f[q];
+  }
+  __syncthreads();                      // R is written again by the next evaluation
+  out.ax = t[0]; out.ay = t[1]; out.h11 = t[2]; out.h12 = t[3]; out.h22 = t[4];
+  out.t111 = out.t112 = out.t122 = out.t222 = 0.0;
+  out.flags = f;
+}
+
 // MULTI = false compiles the single-plane case alone: the multi-plane recursion's per-plane
 // arrays are indexed at run time and would otherwise hold scratch memory and registers in
 // every kernel that calls this.
-template <bool MULTI>
-__device__ void lens_eval64(const LensDev& L, const double* w, double x, double y, double& bx, double& by,
-                            double* Aout, int& flags) {
+// P0: the lens's first plane (its records possibly in LDS).
+template <bool MULTI, bool ENFW>
+__device__ void lens_eval64(const LensDev& L, const Plane64& P0, const double* w, double x, double y, double& bx,
+                            double& by, double* Aout, int& flags, PolRed& R) {
   if (!MULTI || L.n_planes == 1) {
     Acc acc;
-    plane_sum_wave<false>(L.pl[0], x, y, L.qd, acc);
+    plane_sum_block<ENFW>(P0, x, y, L.qd, acc, R);
     double a = w[0];
     bx = x - a * acc.ax;
     by = y - a * acc.ay;
@@ -127,7 +220,7 @@ __device__ void lens_eval64(const LensDev& L, const double* w, double x, double 
       A21 -= wi * (H[1] * Ai[0] + H[2] * Ai[2]); A22 -= wi * (H[1] * Ai[1] + H[2] * Ai[3]);
     }
     Acc acc;
-    plane_sum_wave<false>(L.pl[j], tx, ty, L.qd, acc);
+    plane_sum_block<ENFW>(L.pl[j], tx, ty, L.qd, acc, R);
     flags |= acc.flags;
     al[2 * j] = acc.ax; al[2 * j + 1] = acc.ay;
     Hm[3 * j] = acc.h11; Hm[3 * j + 1] = acc.h12; Hm[3 * j + 2] = acc.h22;
@@ -191,30 +284,60 @@ __device__ __forceinline__ void emit_cand(const FindArgs& F, int s, bool hit, un
   }
 }
 
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// A wave takes a tile of FIND_TW x FIND_TH cells (lane l: cell (l % FIND_TW, l / FIND_TW) of
+// the tile), a workgroup FIND_WG of them side by side.
+constexpr int FIND_TW = 8, FIND_TH = 8, FIND_WG = 4;
+
 // NP = 1..4: that many planes, corners in registers; 0: any count up to LF_MAX_PLANES (the
 // corner arrays are then indexed at run time and live in scratch memory).  FILL: the second
-// pass after an overflow (returns at once otherwise); its grid strides over blocks of cells.
+// pass after an overflow (returns at once otherwise).
+//
+// Three FP32 filters narrow the (cell, source) pairs before the FP64 test, each keeping a
+// superset of what the next keeps:
+//   * per wave, lanes over sources: the source against the box that holds every mapped corner
+//     of the wave's tile, theta in [min, max] - sum_p w_p alpha_p in [w_p min, w_p max]
+//     (bounds reduced over the tile), widened by twice the bounding-box margin below, which
+//     covers the box's own margin and the at most 3 np + 2 further roundings of these bounds;
+//   * per lane, the mapped cell centre with a radius (the coarse test);
+//   * per lane, the bounding box of the cell's four mapped corners.
+// Only the sources that pass the first filter for some lane's tile are taken one by one.
 template <int NP, bool FILL>
 __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
   constexpr int MP = NP > 0 ? NP : LF_MAX_PLANES;
   const int np = NP > 0 ? NP : F.n_planes;
   if (FILL && F.n_cand[2] == 0) return;
-  const long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
-  for (long long cb = (long long)blockIdx.x * 256; cb < ncell; cb += (long long)gridDim.x * 256) {
-  const long long c = cb + threadIdx.x;
-  const bool valid = c < ncell;
-  const long long cc = valid ? c : 0;
-  const int i = (int)(cc % (F.nx - 1)), j = (int)(cc / (F.nx - 1));
+  const int ncx = F.nx - 1, ncy = F.ny - 1;
+  const int tiles_x = (ncx + FIND_TW - 1) / FIND_TW, tiles_y = (ncy + FIND_TH - 1) / FIND_TH;
+  const long long n_tiles = (long long)tiles_x * tiles_y;
+  const long long n_groups = (n_tiles + FIND_WG - 1) / FIND_WG;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (long long g = blockIdx.x; g < n_groups; g += gridDim.x) {
+  const long long tile = g * FIND_WG + wv;
+  const int ti = (int)(tile % tiles_x), tj = (int)(tile / tiles_x);
+  const int ci = ti * FIND_TW + (lane % FIND_TW), cj = tj * FIND_TH + (lane / FIND_TW);
+  const bool valid = tile < n_tiles && ci < ncx && cj < ncy;
+  const int i = valid ? ci : 0, j = valid ? cj : 0;
+  const long long cc = (long long)j * ncx + i;
   const long long v[4] = {(long long)j * F.nx + i, (long long)j * F.nx + i + 1, (long long)(j + 1) * F.nx + i,
                           (long long)(j + 1) * F.nx + i + 1};
   double tx[4], ty[4];
   tx[0] = tx[2] = F.x0 + (i + 0.5) * F.h; tx[1] = tx[3] = F.x0 + (i + 1.5) * F.h;
   ty[0] = ty[1] = F.y0 + (j + 0.5) * F.h; ty[2] = ty[3] = F.y0 + (j + 1.5) * F.h;
-  // FP32 copies of the corner deflections for the prefilters (the FP64 values are read again
-  // in the rare case that a source passes them): a cell is tested in FP64 only when the source lies in the
-  // FP32 bounding box of its four mapped corners widened by eps plus a bound on the FP32
-  // rounding (inputs and FMAs, each <= 2^-24 of a magnitude <= R = |theta| + sum w |alpha| +
-  // |beta_s|, at most np + 3 of them per coordinate, taken with a factor 4).
+  // FP32 copies of the corner deflections for the filters (the FP64 values are read again in
+  // the rare case that a source passes them): the bounding-box margin is eps plus a bound on
+  // the FP32 rounding (inputs and FMAs, each <= 2^-24 of a magnitude <= R = |theta| +
+  // sum w |alpha| + |beta_s|, at most np + 3 of them per coordinate, taken with a factor 4).
   float txf[4], tyf[4], axf[MP][4], ayf[MP][4], amax[MP];
   float tmax = 0.f;
 #pragma unroll
@@ -232,7 +355,7 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
     }
   }
   const float rel = 4.f * (float)(np + 3) * 5.9604645e-8f;   // 4 (np + 3) 2^-24
-  // Coarse test first: every mapped corner lies within r_p = h/2 + sum_p |w_p| da_p (in each
+  // Coarse test: every mapped corner lies within r_p = h/2 + sum_p |w_p| da_p (in each
   // coordinate) of the mapped centre c - sum_p w_p abar_p, where abar_p is the corners' mean
   // deflection and da_p their largest deviation from it.  The source is kept for the bounding
   // box test below unless it is farther than that plus four times the box's margin from the
@@ -250,7 +373,22 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) da[p] = fmaxf(da[p], fmaxf(fabsf(axf[p][k] - abx[p]), fabsf(ayf[p][k] - aby[p])));
   }
-  const int lane = threadIdx.x & 63;
+  // The tile's bounds (invalid lanes take no part); a wave without valid lanes skips the sources.
+  const bool any_valid = __any(valid);
+  const float INF = __builtin_inff();
+  const float Txlo = wave_min(valid ? txf[0] : INF), Txhi = wave_max(valid ? txf[1] : -INF);
+  const float Tylo = wave_min(valid ? tyf[0] : INF), Tyhi = wave_max(valid ? tyf[2] : -INF);
+  const float Tmax = wave_max(valid ? tmax : 0.f);
+  float Axlo[MP], Axhi[MP], Aylo[MP], Ayhi[MP], Amax[MP];
+  for (int p = 0; p < np; ++p) {
+    const float xl = fminf(fminf(axf[p][0], axf[p][1]), fminf(axf[p][2], axf[p][3]));
+    const float xh = fmaxf(fmaxf(axf[p][0], axf[p][1]), fmaxf(axf[p][2], axf[p][3]));
+    const float yl = fminf(fminf(ayf[p][0], ayf[p][1]), fminf(ayf[p][2], ayf[p][3]));
+    const float yh = fmaxf(fmaxf(ayf[p][0], ayf[p][1]), fmaxf(ayf[p][2], ayf[p][3]));
+    Axlo[p] = wave_min(valid ? xl : INF); Axhi[p] = wave_max(valid ? xh : -INF);
+    Aylo[p] = wave_min(valid ? yl : INF); Ayhi[p] = wave_max(valid ? yh : -INF);
+    Amax[p] = wave_max(valid ? amax[p] : 0.f);
+  }
   // The sources are staged in LDS, SCH at a time: read from global memory in the loop, every
   // source would cost each wave a round trip to L2 (the candidate stores keep the compiler
   // from using the scalar cache).
@@ -265,7 +403,28 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
       for (int p = 0; p < np; ++p) sh_w[q * np + p] = F.w[(s0 + q) * np + p];
     }
     __syncthreads();
-    for (int sl = 0; sl < ns; ++sl) {
+    if (!any_valid) continue;
+    for (int sb = 0; sb < ns; sb += 64) {
+      bool pass = false;
+      if (sb + lane < ns) {
+        const int q = sb + lane;
+        const float sxf = (float)sh_b[2 * q], syf = (float)sh_b[2 * q + 1];
+        float lx = Txlo, hx = Txhi, ly = Tylo, hy = Tyhi;
+        float R = Tmax + fmaxf(fabsf(sxf), fabsf(syf));
+        for (int p = 0; p < np; ++p) {
+          const float wf = (float)sh_w[q * np + p];
+          const float x1 = wf * Axlo[p], x2 = wf * Axhi[p], y1 = wf * Aylo[p], y2 = wf * Ayhi[p];
+          lx -= fmaxf(x1, x2); hx -= fminf(x1, x2);
+          ly -= fmaxf(y1, y2); hy -= fminf(y1, y2);
+          R = fmaf(fabsf(wf), Amax[p], R);
+        }
+        const float M = 2.f * ((float)F.eps + rel * R);
+        pass = sxf >= lx - M && sxf <= hx + M && syf >= ly - M && syf <= hy + M;
+      }
+      unsigned long long todo = __ballot(pass);
+      while (todo) {
+      const int sl = sb + __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
       const int s = s0 + sl;
       const double* ws = sh_w + sl * np;
       const double sx = sh_b[2 * sl], sy = sh_b[2 * sl + 1];
@@ -319,6 +478,7 @@ __global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
       for (int t = 0; t < 2; ++t) {
         const bool hit = valid && near_tri(t == 0 ? T0 : T1, sx, sy, F.eps);
         emit_cand<FILL>(F, s, hit, (unsigned long long)(2 * cc + t), lane);
+      }
       }
     }
   }
@@ -428,10 +588,29 @@ __global__ __launch_bounds__(256) void k_find_segsort(const FindArgs F) {
 // ---------------------------------------------------------------------------------------
 // 4. FP64 containment + Newton polish per candidate
 // ---------------------------------------------------------------------------------------
-template <bool MULTI>
-__global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const LensDev L) {
+// The first plane of the lens; with CACHE its halo records copied to LDS and read from there.
+template <bool CACHE>
+__device__ __forceinline__ Plane64 polish_plane(const LensDev& L) {
+  Plane64 P = L.pl[0];
+  if constexpr (CACHE) {
+    __shared__ MainRec sm_main[POL_LDS_MAIN];
+    __shared__ MemRec64 sm_mem[POL_LDS_MEM];
+    const int nmem = P.seg.off[NSEG];
+    for (int i = threadIdx.x; i < P.n_main; i += blockDim.x) sm_main[i] = P.mains[i];
+    for (int i = threadIdx.x; i < nmem; i += blockDim.x) sm_mem[i] = P.mem[i];
+    __syncthreads();
+    P.mains = sm_main;
+    P.mem = sm_mem;
+  }
+  return P;
+}
+
+template <bool MULTI, bool ENFW, bool CACHE>
+__global__ __launch_bounds__(POL_T) __attribute__((amdgpu_waves_per_eu(2))) void k_find_polish(const FindArgs F, const LensDev L) {
+  __shared__ PolRed R;
+  const Plane64 P0 = polish_plane<CACHE>(L);
   const int n = F.n_cand[1];
-  for (int k = blockIdx.x; k < n; k += gridDim.x) {   // one wave per candidate
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {   // one workgroup per candidate
   unsigned long long key = F.cand[k];
   int s = (int)(key >> 32);
   long long tri = (long long)(key & 0xffffffffull);
@@ -447,7 +626,7 @@ __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const Lens
   for (int q = 0; q < 3; ++q) {
     T[2 * q] = F.x0 + (vi[q] + 0.5) * F.h;
     T[2 * q + 1] = F.y0 + (vj[q] + 0.5) * F.h;
-    lens_eval64<MULTI>(L, w, T[2 * q], T[2 * q + 1], B[2 * q], B[2 * q + 1], A, fl);
+    lens_eval64<MULTI, ENFW>(L, P0, w, T[2 * q], T[2 * q + 1], B[2 * q], B[2 * q + 1], A, fl, R);
   }
   const double sx = F.beta[2 * s], sy = F.beta[2 * s + 1];
   int status = 4;
@@ -462,7 +641,7 @@ __global__ __launch_bounds__(64) void k_find_polish(const FindArgs F, const Lens
     bool conv = false;
     for (int it = 0; it <= 30; ++it) {
       double ex, ey;
-      lens_eval64<MULTI>(L, w, tx, ty, ex, ey, A, fl);
+      lens_eval64<MULTI, ENFW>(L, P0, w, tx, ty, ex, ey, A, fl, R);
       double rx = sx - ex, ry = sy - ey;
       if (fabs(rx) < 1e-10 && fabs(ry) < 1e-10) { conv = true; break; }
       if (it == 30) break;
@@ -521,6 +700,29 @@ __global__ __launch_bounds__(64) void k_find_final(const FindArgs F) {
   if (F.flags_out) F.flags_out[s] = fl;
 }
 
+// The polishing passes' variant for a lens: the LDS copy of the halo records for a small
+// single-plane lens.
+static bool polish_cache(const LensDev& L) {
+  return L.n_planes == 1 && L.pl[0].n_main <= POL_LDS_MAIN && L.pl[0].seg.off[NSEG] <= POL_LDS_MEM;
+}
+#define LF_POLISH_LAUNCH(KERNEL, ...)                                                                         \
+  do {                                                                                                        \
+    const bool cache = polish_cache(L);                                                                       \
+    const dim3 pgrid((unsigned)min(F.cap, 16 * F.n_cu)), pblock((unsigned)POL_T);                            \
+    if (F.n_planes == 1) {                                                                                    \
+      if (L.enfw) {                                                                                           \
+        if (cache) hipLaunchKernelGGL((KERNEL<false, true, true>), pgrid, pblock, 0, st, __VA_ARGS__);     \
+        else hipLaunchKernelGGL((KERNEL<false, true, false>), pgrid, pblock, 0, st, __VA_ARGS__);             \
+      } else {                                                                                                \
+        if (cache) hipLaunchKernelGGL((KERNEL<false, false, true>), pgrid, pblock, 0, st, __VA_ARGS__);    \
+        else hipLaunchKernelGGL((KERNEL<false, false, false>), pgrid, pblock, 0, st, __VA_ARGS__);            \
+      }                                                                                                       \
+    } else {                                                                                                  \
+      if (L.enfw) hipLaunchKernelGGL((KERNEL<true, true, false>), pgrid, pblock, 0, st, __VA_ARGS__);         \
+      else hipLaunchKernelGGL((KERNEL<true, false, false>), pgrid, pblock, 0, st, __VA_ARGS__);               \
+    }                                                                                                         \
+  } while (0)
+
 // prefix sum and, without overflow, the scatter into segments
 static void launch_segments(const FindArgs& F, hipStream_t st) {
   hipLaunchKernelGGL(k_find_scan, dim3(1), dim3(1024), 0, st, F);
@@ -530,10 +732,11 @@ static void launch_segments(const FindArgs& F, hipStream_t st) {
 
 hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void (*mark)(void*, const char*, int),
                        void* ctx) {
-  long long ncell = (long long)(F.nx - 1) * (F.ny - 1);
   hipLaunchKernelGGL(k_find_reset, dim3((unsigned)min(1024, (F.n_src + 255) / 256 + 1)), dim3(256), 0, st, F);
   mark(ctx, "find_cand", 0);
-  const dim3 cgrid((unsigned)((ncell + 255) / 256)), fgrid((unsigned)(4 * F.n_cu));
+  const long long n_tiles = (long long)((F.nx - 1 + FIND_TW - 1) / FIND_TW) * ((F.ny - 1 + FIND_TH - 1) / FIND_TH);
+  const long long n_groups = (n_tiles + FIND_WG - 1) / FIND_WG;
+  const dim3 cgrid((unsigned)(n_groups < (1LL << 30) ? n_groups : (1LL << 30))), fgrid((unsigned)(4 * F.n_cu));
   switch (F.n_planes) {
     case 1: hipLaunchKernelGGL((k_find_cand<1, false>), cgrid, dim3(256), 0, st, F); break;
     case 2: hipLaunchKernelGGL((k_find_cand<2, false>), cgrid, dim3(256), 0, st, F); break;
@@ -551,10 +754,8 @@ hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void
     default: hipLaunchKernelGGL((k_find_cand<0, true>), fgrid, dim3(256), 0, st, F); break;
   }
   hipLaunchKernelGGL(k_find_segsort, dim3((unsigned)F.n_src), dim3(256), 0, st, F);
-  const dim3 pgrid((unsigned)min(F.cap, 64 * F.n_cu));
   mark(ctx, "find_polish", 0);
-  if (F.n_planes == 1) hipLaunchKernelGGL(k_find_polish<false>, pgrid, dim3(64), 0, st, F, L);
-  else hipLaunchKernelGGL(k_find_polish<true>, pgrid, dim3(64), 0, st, F, L);
+  LF_POLISH_LAUNCH(k_find_polish, F, L);
   mark(ctx, "find_polish", 1);
   hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
   return hipGetLastError();
@@ -698,9 +899,11 @@ __global__ __launch_bounds__(256) void k_ms_cand(const FindArgs F) {
   }
 }
 
-// one wave per candidate: the intersection, then (polish) FP64 Newton as the triangle finder
-template <bool MULTI>
-__global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev L, int polish) {
+// one workgroup per candidate: the intersection, then (polish) FP64 Newton as the triangle finder
+template <bool MULTI, bool ENFW, bool CACHE>
+__global__ __launch_bounds__(POL_T) __attribute__((amdgpu_waves_per_eu(2))) void k_ms_point(const FindArgs F, const LensDev L, int polish) {
+  __shared__ PolRed R;
+  const Plane64 P0 = polish_plane<CACHE>(L);
   const int n = F.n_cand[1];
   for (int k = blockIdx.x; k < n; k += gridDim.x) {
   const unsigned long long key = F.cand[k];
@@ -730,7 +933,7 @@ __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev
     const double tx0 = tx, ty0 = ty;
     bool conv = false;
     for (int it = 0; it <= 30; ++it) {
-      lens_eval64<MULTI>(L, w, tx, ty, ex, ey, A, fl);
+      lens_eval64<MULTI, ENFW>(L, P0, w, tx, ty, ex, ey, A, fl, R);
       const double rx = sx - ex, ry = sy - ey;
       if (fabs(rx) < 1e-10 && fabs(ry) < 1e-10) { conv = true; break; }
       if (it == 30) break;
@@ -741,7 +944,7 @@ __global__ __launch_bounds__(64) void k_ms_point(const FindArgs F, const LensDev
     if (!conv) status = 1;
     else if (fabs(tx - tx0) > 2.0 * F.h || fabs(ty - ty0) > 2.0 * F.h) status = 2;
   } else {
-    lens_eval64<MULTI>(L, w, tx, ty, ex, ey, A, fl);
+    lens_eval64<MULTI, ENFW>(L, P0, w, tx, ty, ex, ey, A, fl, R);
   }
   if (threadIdx.x == 0) {
     F.c_status[k] = status;
@@ -762,10 +965,8 @@ hipError_t launch_find_ms(const FindArgs& F, const LensDev& L, int polish, hipSt
   launch_segments(F, st);
   hipLaunchKernelGGL(k_ms_cand<true>, dim3((unsigned)(4 * F.n_cu)), dim3(256), 0, st, F);
   hipLaunchKernelGGL(k_find_segsort, dim3((unsigned)F.n_src), dim3(256), 0, st, F);
-  const dim3 pgrid((unsigned)min(F.cap, 64 * F.n_cu));
   mark(ctx, "find_ms_point", 0);
-  if (F.n_planes == 1) hipLaunchKernelGGL(k_ms_point<false>, pgrid, dim3(64), 0, st, F, L, polish);
-  else hipLaunchKernelGGL(k_ms_point<true>, pgrid, dim3(64), 0, st, F, L, polish);
+  LF_POLISH_LAUNCH(k_ms_point, F, L, polish);
   mark(ctx, "find_ms_point", 1);
   hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
   return hipGetLastError();
