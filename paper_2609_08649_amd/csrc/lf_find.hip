@@ -103,8 +103,8 @@ __device__ bool d_tri_contains(const double* B, double sx, double sy) {
 // FP64 lens evaluation by a whole workgroup (the polishing passes take one candidate per
 // workgroup: a few hundred candidates would leave most of the chip idle at one wave each, and
 // the evaluation is a chain of dependent sums).  The halos of a plane are split over the
-// threads, each wave's partial sums combined by a butterfly of shuffles and the waves' sums
-// added in LDS in wave order, so every thread ends with the same bits and runs the iteration
+// threads, each wave's partial sums combined by DPP lane moves and the waves' sums added in LDS
+// in wave order, so every thread ends with the same bits and runs the iteration
 // logic alike (measured: 256 threads per workgroup beat 512 on the cluster lens, whose 304
 // work items then leave most threads one item).  ENFW = false compiles the elliptical NFW
 // quadrature out.
@@ -119,6 +119,43 @@ struct PolRed {
   int f[POL_W];
 };
 
+// Wave sums by DPP lane moves (no LDS round trips, which the butterfly of shuffles takes six of
+// in a row): two quad permutations and two row rotations give every lane its row's total, two
+// row broadcasts carry the row totals into the last row, and lane 63's value is read out, so
+// every lane gets the same bits.  Lanes of rows a move leaves out add zero.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i32<CTRL, ROWS>((int)b), hi = dpp_i32<CTRL, ROWS>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xb1, 0xf>(v);     // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4e, 0xf>(v);     // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x124, 0xf>(v);    // row_ror 4
+  v += dpp_f64<0x128, 0xf>(v);    // row_ror 8
+  v += dpp_f64<0x142, 0xa>(v);    // row_bcast 15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);    // row_bcast 31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ int wave_or_dpp(int v) {
+  v |= dpp_i32<0xb1, 0xf>(v);
+  v |= dpp_i32<0x4e, 0xf>(v);
+  v |= dpp_i32<0x124, 0xf>(v);
+  v |= dpp_i32<0x128, 0xf>(v);
+  v |= dpp_i32<0x142, 0xa>(v);
+  v |= dpp_i32<0x143, 0xc>(v);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Half of a main halo: an elliptical dPIE is the difference of two cored isothermal terms
+// (cores s and a), taken as part 0 and part 1 by two threads; any other halo is part 0 whole.
 template <bool ENFW>
 __device__ __forceinline__ void eval_main_part(const MainRec& r, int part, double px, double py, const Quad& qd,
                                                Acc& acc) {
@@ -145,28 +182,30 @@ __device__ __forceinline__ void eval_main_part(const MainRec& r, int part, doubl
   add<false>(acc, t);
 }
 
-// Work items: the main halos' parts (two each), then the members.  With at most a quarter of
-// the threads needed for the main parts, those go to the last 2 n_main threads, one each, and
-// the members are strided over the other threads; otherwise all items are strided over all
-// threads.  (One call site per halo kind keeps the kernel's code, and its registers, small.)
+// Work items: the main halos' parts (two each), then the members.  With at most 64 main parts
+// they take the last wave, one part per lane, and the members are strided over the other
+// waves: a wave that held both would run the two code paths one after the other (measured on
+// the cluster lens: 2.15 us per evaluation with the parts on the last lanes of a mixed wave).
+// Otherwise all items are strided over all threads.  (One call site per halo kind keeps the
+// kernel's code, and its registers, small.)
 template <bool ENFW>
 __device__ void plane_sum_block(const Plane64& P, double x, double y, const Quad& qd, Acc& out, PolRed& R) {
   Acc acc;
   acc.zero();
-  constexpr int nt = POL_T;
+  constexpr int nt = POL_T, mt = POL_T - 64;
   const int nmem = P.seg.off[NSEG], msl = 2 * P.n_main;
-  const int mt = msl <= nt / 2 ? nt - msl : 0;
   const int tid = threadIdx.x;
   int first, stride, end;
-  if (mt == 0) { first = tid; stride = nt; end = msl + nmem; }
-  else if (tid >= mt) { first = tid - mt; stride = nt; end = first + 1; }
+  if (msl > 64) { first = tid; stride = nt; end = msl + nmem; }
+  else if (tid >= mt) { first = tid - mt; stride = nt; end = min(first + 1, msl); }
   else { first = msl + tid; stride = mt; end = msl + nmem; }
   for (int it = first; it < end; it += stride) {
     if (it < msl) eval_main_part<ENFW>(P.mains[it >> 1], it & 1, x, y, qd, acc);
     else member64_term<false, ENFW>(P, it - msl, x, y, qd, acc);
   }
-  const double s0 = wsum(acc.ax), s1 = wsum(acc.ay), s2 = wsum(acc.h11), s3 = wsum(acc.h12), s4 = wsum(acc.h22);
-  const int fl = wor(acc.flags);
+  const double s0 = wave_sum_dpp(acc.ax), s1 = wave_sum_dpp(acc.ay), s2 = wave_sum_dpp(acc.h11),
+               s3 = wave_sum_dpp(acc.h12), s4 = wave_sum_dpp(acc.h22);
+  const int fl = wave_or_dpp(acc.flags);
   const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     R.v[wv][0] = s0; R.v[wv][1] = s1; R.v[wv][2] = s2; R.v[wv][3] = s3; R.v[wv][4] = s4;
