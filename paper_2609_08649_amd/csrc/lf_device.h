@@ -167,13 +167,11 @@ __device__ __forceinline__ void point_mass(T dx, T dy, T b, Term<T>& t) {
 //   N_xx = q^2 s^2 + y^2 + s psi~, N_yy = s^2 + x^2 + s psi~, N_xy = -x y;
 //   d_k psi_ij = b q / (psi~ D) (d_k N_ij - N_ij L_k), L_k = d_k psi~/psi~ + d_k D / D.
 // ---------------------------------------------------------------------------------------
+// Second and third derivatives of one core, psi~ given.
 template <bool D3, class T>
-__device__ __forceinline__ void esie_prime(T xp, T yp, T bqe, T e, T q2, T s, Term<T>& t) {
-  T xx = xp * xp, yy = yp * yp, ss = s * s;
-  T psi = fsqrt(fma(q2, ss + xx, yy));
+__device__ __forceinline__ void esie_hess(T xp, T yp, T xx, T yy, T bqe, T e, T q2, T s, T psi, Term<T>& t) {
+  T ss = s * s;
   T ip = frcp(psi);
-  t.ax = bqe * fatan(e * xp * frcp(psi + s));
-  t.ay = bqe * fatanh(e * yp * frcp(fma(q2, s, psi)));
   T D = fma((T)1 + q2, ss, fma((T)2 * psi, s, xx + yy));
   T iD = frcp(D);
   T Tn = bqe * e * ip * iD;
@@ -188,6 +186,35 @@ __device__ __forceinline__ void esie_prime(T xp, T yp, T bqe, T e, T q2, T s, Te
     t.t112 = Tn * ((T)2 * yp + s * dpy - Nxx * Ly);
     t.t122 = Tn * ((T)2 * xp + s * dpx - Nyy * Lx);
     t.t222 = Tn * (s * dpy - Nyy * Ly);
+  }
+}
+template <bool D3, class T>
+__device__ __forceinline__ void esie_prime(T xp, T yp, T bqe, T e, T q2, T s, Term<T>& t) {
+  T xx = xp * xp, yy = yp * yp;
+  T psi = fsqrt(fma(q2, fma(s, s, xx), yy));
+  t.ax = bqe * fatan(e * xp * frcp(psi + s));
+  t.ay = bqe * fatanh(e * yp * frcp(fma(q2, s, psi)));
+  esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, s, psi, t);
+}
+// The dPIE pair (core s minus core a) in its own frame.  The deflection takes one arctangent
+// and one inverse hyperbolic tangent for both cores: atan u1 - atan u2 = atan((u1 - u2) /
+// (1 + u1 u2)) with u1 u2 >= 0 (both have the sign of x'), and atanh v1 - atanh v2 =
+// atanh((v1 - v2) / (1 - v1 v2)) with v1 v2 >= 0 and |v| <= e < 1; the difference u1 - u2 is
+// as exact as the difference of the two arctangents it replaces.
+template <bool D3, class T>
+__device__ __forceinline__ void epje_prime(T xp, T yp, T bqe, T e, T q2, T s, T a, Term<T>& t) {
+  T xx = xp * xp, yy = yp * yp;
+  T psi_s = fsqrt(fma(q2, fma(s, s, xx), yy)), psi_a = fsqrt(fma(q2, fma(a, a, xx), yy));
+  T u1 = e * xp * frcp(psi_s + s), u2 = e * xp * frcp(psi_a + a);
+  T v1 = e * yp * frcp(fma(q2, s, psi_s)), v2 = e * yp * frcp(fma(q2, a, psi_a));
+  t.ax = bqe * fatan((u1 - u2) * frcp(fma(u1, u2, (T)1)));
+  t.ay = bqe * fatanh((v1 - v2) * frcp(fma(-v1, v2, (T)1)));
+  Term<T> hs, ha;
+  esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, s, psi_s, hs);
+  esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, a, psi_a, ha);
+  t.h11 = hs.h11 - ha.h11; t.h12 = hs.h12 - ha.h12; t.h22 = hs.h22 - ha.h22;
+  if (D3) {
+    t.t111 = hs.t111 - ha.t111; t.t112 = hs.t112 - ha.t112; t.t122 = hs.t122 - ha.t122; t.t222 = hs.t222 - ha.t222;
   }
 }
 
@@ -224,9 +251,9 @@ __device__ __forceinline__ void sub_term(Term<T>& a, const Term<T>& b) {
 template <bool D3, class T>
 __device__ __forceinline__ void epje(T dx, T dy, T c, T sn, T bqe, T e, T q2, T s, T a, bool pje, Term<T>& t) {
   T xp = c * dx + sn * dy, yp = c * dy - sn * dx;
-  Term<T> p, p2;
-  esie_prime<D3>(xp, yp, bqe, e, q2, s, p);
-  if (pje) { esie_prime<D3>(xp, yp, bqe, e, q2, a, p2); sub_term<D3>(p, p2); }
+  Term<T> p;
+  if (pje) epje_prime<D3>(xp, yp, bqe, e, q2, s, a, p);
+  else esie_prime<D3>(xp, yp, bqe, e, q2, s, p);
   rotate_back<D3>(c, sn, p, t);
 }
 
