@@ -201,14 +201,28 @@ __device__ __forceinline__ void esie_prime(T xp, T yp, T bqe, T e, T q2, T s, Te
 // (1 + u1 u2)) with u1 u2 >= 0 (both have the sign of x'), and atanh v1 - atanh v2 =
 // atanh((v1 - v2) / (1 - v1 v2)) with v1 v2 >= 0 and |v| <= e < 1; the difference u1 - u2 is
 // as exact as the difference of the two arctangents it replaces.
+// In FP64 the two arguments are formed with one reciprocal each: with A_c = psi~_c + c and
+// B_c = psi~_c + q^2 c, psi~_a - psi~_s = q^2 (a^2 - s^2) / (psi~_a + psi~_s) (no cancellation),
+//   (u1 - u2) / (1 + u1 u2) = e x' [q^2 (a^2 - s^2) + (a - s) P] / (P (A_s A_a + e^2 x'^2)),
+//   (v1 - v2) / (1 - v1 v2) = e y' q^2 (a - s) (P + a + s) / (P (B_s B_a - e^2 y'^2)),
+// P = psi~_s + psi~_a; B_s B_a - e^2 y'^2 >= q^2 y'^2 (psi~ >= |y'|).
 template <bool D3, class T>
 __device__ __forceinline__ void epje_prime(T xp, T yp, T bqe, T e, T q2, T s, T a, Term<T>& t) {
   T xx = xp * xp, yy = yp * yp;
   T psi_s = fsqrt(fma(q2, fma(s, s, xx), yy)), psi_a = fsqrt(fma(q2, fma(a, a, xx), yy));
-  T u1 = e * xp * frcp(psi_s + s), u2 = e * xp * frcp(psi_a + a);
-  T v1 = e * yp * frcp(fma(q2, s, psi_s)), v2 = e * yp * frcp(fma(q2, a, psi_a));
-  t.ax = bqe * fatan((u1 - u2) * frcp(fma(u1, u2, (T)1)));
-  t.ay = bqe * fatanh((v1 - v2) * frcp(fma(-v1, v2, (T)1)));
+  if constexpr (sizeof(T) == 8) {
+    const T P = psi_s + psi_a, as = a - s, ee = e * e;
+    const T As = psi_s + s, Aa = psi_a + a, Bs = fma(q2, s, psi_s), Ba = fma(q2, a, psi_a);
+    const T zx = e * xp * fma(q2 * as, a + s, as * P) * frcp(P * fma(ee, xx, As * Aa));
+    const T zy = e * yp * q2 * as * (P + (a + s)) * frcp(P * fma(-ee, yy, Bs * Ba));
+    t.ax = bqe * fatan(zx);
+    t.ay = bqe * fatanh(zy);
+  } else {
+    T u1 = e * xp * frcp(psi_s + s), u2 = e * xp * frcp(psi_a + a);
+    T v1 = e * yp * frcp(fma(q2, s, psi_s)), v2 = e * yp * frcp(fma(q2, a, psi_a));
+    t.ax = bqe * fatan((u1 - u2) * frcp(fma(u1, u2, (T)1)));
+    t.ay = bqe * fatanh((v1 - v2) * frcp(fma(-v1, v2, (T)1)));
+  }
   Term<T> hs, ha;
   esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, s, psi_s, hs);
   esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, a, psi_a, ha);
