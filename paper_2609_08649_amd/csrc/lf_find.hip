@@ -323,16 +323,26 @@ __device__ __forceinline__ void emit_cand(const FindArgs& F, int s, bool hit, un
   }
 }
 
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
+// Wave minimum and maximum by the lane moves of wave_sum_dpp; lanes of rows a move leaves out
+// take the identity (+inf, -inf).
+template <int CTRL, int ROWS, int OLD>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(OLD, __float_as_int(v), CTRL, ROWS, 0xf, false));
 }
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+template <bool MAX>
+__device__ __forceinline__ float wave_ext(float v) {
+  constexpr int ID = MAX ? (int)0xff800000 : 0x7f800000;
+  auto op = [](float a, float b) { return MAX ? fmaxf(a, b) : fminf(a, b); };
+  v = op(v, dpp_f32<0xb1, 0xf, ID>(v));
+  v = op(v, dpp_f32<0x4e, 0xf, ID>(v));
+  v = op(v, dpp_f32<0x124, 0xf, ID>(v));
+  v = op(v, dpp_f32<0x128, 0xf, ID>(v));
+  v = op(v, dpp_f32<0x142, 0xa, ID>(v));
+  v = op(v, dpp_f32<0x143, 0xc, ID>(v));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
+__device__ __forceinline__ float wave_min(float v) { return wave_ext<false>(v); }
+__device__ __forceinline__ float wave_max(float v) { return wave_ext<true>(v); }
 
 // A wave takes a tile of FIND_TW x FIND_TH cells (lane l: cell (l % FIND_TW, l / FIND_TW) of
 // the tile), a workgroup FIND_WG of them side by side.
@@ -352,7 +362,7 @@ constexpr int FIND_TW = 8, FIND_TH = 8, FIND_WG = 4;
 //   * per lane, the bounding box of the cell's four mapped corners.
 // Only the sources that pass the first filter for some lane's tile are taken one by one.
 template <int NP, bool FILL>
-__global__ __launch_bounds__(256) void k_find_cand(const FindArgs F) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NP == 1 ? 4 : 1))) void k_find_cand(const FindArgs F) {
   constexpr int MP = NP > 0 ? NP : LF_MAX_PLANES;
   const int np = NP > 0 ? NP : F.n_planes;
   if (FILL && F.n_cand[2] == 0) return;
@@ -706,15 +716,55 @@ __global__ __launch_bounds__(POL_T) __attribute__((amdgpu_waves_per_eu(2))) void
 // 5. per source: merge duplicates in candidate order, write outputs
 // ---------------------------------------------------------------------------------------
 // A source whose candidates were not kept (past the capacity) gets count 0 and FL_OVERFLOW.
+// One wave per source.  Up to 64 candidates, lane j holds the source's candidate j: candidate
+// k is a duplicate when an earlier candidate that was kept lies within 1e-6"; the candidates
+// are settled in order (each by then knows whether the earlier ones were kept, read from their
+// lanes), and the kept ones are written in candidate order.  More candidates take the same
+// rule in one lane.
+__device__ __forceinline__ double lane_f64(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, q), hi = __builtin_amdgcn_readlane((int)(b >> 32), q);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __global__ __launch_bounds__(64) void k_find_final(const FindArgs F) {
-  int s = blockIdx.x * 64 + threadIdx.x;
-  if (s >= F.n_src) return;
+  const int s = blockIdx.x, lane = threadIdx.x;
   const int lo = F.src_off[s], hi = F.src_off[s + 1];
   if (hi > F.n_cand[1]) {
-    F.count_out[s] = 0;
-    if (F.flags_out) F.flags_out[s] = FL_OVERFLOW;
+    if (lane == 0) {
+      F.count_out[s] = 0;
+      if (F.flags_out) F.flags_out[s] = FL_OVERFLOW;
+    }
     return;
   }
+  const int n = hi - lo;
+  if (n <= 64) {
+    const bool in = lane < n;
+    const int k = lo + (in ? lane : 0);
+    bool keep = in && F.c_status[k] == 0;
+    const double tx = in ? F.c_theta[2 * k] : 0.0, ty = in ? F.c_theta[2 * k + 1] : 0.0;
+    bool merged = false;
+    for (int q = 0; q < n - 1; ++q) {
+      if (!(__ballot(keep) >> q & 1ull)) continue;
+      const double qx = lane_f64(tx, q), qy = lane_f64(ty, q);
+      const double dx = tx - qx, dy = ty - qy;
+      if (keep && lane > q && sqrt(dx * dx + dy * dy) < 1e-6) { keep = false; merged = true; }
+    }
+    if (merged) F.c_status[k] = 3;
+    const unsigned long long km = __ballot(keep);
+    const int rank = __popcll(km & ((1ull << lane) - 1ull)), cnt = __popcll(km);
+    if (keep && rank < F.max_img) {
+      F.theta_out[((size_t)s * F.max_img + rank) * 2] = tx;
+      F.theta_out[((size_t)s * F.max_img + rank) * 2 + 1] = ty;
+      if (F.mu_out) F.mu_out[(size_t)s * F.max_img + rank] = F.c_mu[k];
+    }
+    const int fl = (__ballot(merged) ? FL_MERGED : 0) | (cnt > F.max_img ? FL_OVERFLOW : 0);
+    if (lane == 0) {
+      F.count_out[s] = cnt;
+      if (F.flags_out) F.flags_out[s] = fl;
+    }
+    return;
+  }
+  if (lane != 0) return;
   int cnt = 0, fl = 0;
   for (int k = lo; k < hi; ++k) {
     if (F.c_status[k] != 0) continue;
@@ -796,7 +846,7 @@ hipError_t launch_find(const FindArgs& F, const LensDev& L, hipStream_t st, void
   mark(ctx, "find_polish", 0);
   LF_POLISH_LAUNCH(k_find_polish, F, L);
   mark(ctx, "find_polish", 1);
-  hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
+  hipLaunchKernelGGL(k_find_final, dim3((unsigned)F.n_src), dim3(64), 0, st, F);
   return hipGetLastError();
 }
 
@@ -1007,7 +1057,7 @@ hipError_t launch_find_ms(const FindArgs& F, const LensDev& L, int polish, hipSt
   mark(ctx, "find_ms_point", 0);
   LF_POLISH_LAUNCH(k_ms_point, F, L, polish);
   mark(ctx, "find_ms_point", 1);
-  hipLaunchKernelGGL(k_find_final, dim3((F.n_src + 63) / 64), dim3(64), 0, st, F);
+  hipLaunchKernelGGL(k_find_final, dim3((unsigned)F.n_src), dim3(64), 0, st, F);
   return hipGetLastError();
 }
 
