@@ -210,19 +210,19 @@ template <bool D3, class T>
 __device__ __forceinline__ void epje_prime(T xp, T yp, T bqe, T e, T q2, T s, T a, Term<T>& t) {
   T xx = xp * xp, yy = yp * yp;
   T psi_s = fsqrt(fma(q2, fma(s, s, xx), yy)), psi_a = fsqrt(fma(q2, fma(a, a, xx), yy));
+  T zx, zy;
   if constexpr (sizeof(T) == 8) {
     const T P = psi_s + psi_a, as = a - s, ee = e * e;
     const T As = psi_s + s, Aa = psi_a + a, Bs = fma(q2, s, psi_s), Ba = fma(q2, a, psi_a);
-    const T zx = e * xp * fma(q2 * as, a + s, as * P) * frcp(P * fma(ee, xx, As * Aa));
-    const T zy = e * yp * q2 * as * (P + (a + s)) * frcp(P * fma(-ee, yy, Bs * Ba));
-    t.ax = bqe * fatan(zx);
-    t.ay = bqe * fatanh(zy);
+    zx = e * xp * fma(q2 * as, a + s, as * P) * frcp(P * fma(ee, xx, As * Aa));
+    zy = e * yp * q2 * as * (P + (a + s)) * frcp(P * fma(-ee, yy, Bs * Ba));
   } else {
     T u1 = e * xp * frcp(psi_s + s), u2 = e * xp * frcp(psi_a + a);
     T v1 = e * yp * frcp(fma(q2, s, psi_s)), v2 = e * yp * frcp(fma(q2, a, psi_a));
-    t.ax = bqe * fatan((u1 - u2) * frcp(fma(u1, u2, (T)1)));
-    t.ay = bqe * fatanh((v1 - v2) * frcp(fma(-v1, v2, (T)1)));
+    zx = (u1 - u2) * frcp(fma(u1, u2, (T)1));
+    zy = (v1 - v2) * frcp(fma(-v1, v2, (T)1));
   }
+  // the derivatives first, so that few values stay live across the two library calls
   Term<T> hs, ha;
   esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, s, psi_s, hs);
   esie_hess<D3>(xp, yp, xx, yy, bqe, e, q2, a, psi_a, ha);
@@ -230,6 +230,8 @@ __device__ __forceinline__ void epje_prime(T xp, T yp, T bqe, T e, T q2, T s, T 
   if (D3) {
     t.t111 = hs.t111 - ha.t111; t.t112 = hs.t112 - ha.t112; t.t122 = hs.t122 - ha.t122; t.t222 = hs.t222 - ha.t222;
   }
+  t.ax = bqe * fatan(zx);
+  t.ay = bqe * fatanh(zy);
 }
 
 template <class T>
@@ -262,12 +264,25 @@ __device__ __forceinline__ void sub_term(Term<T>& a, const Term<T>& b) {
   if (D3) { a.t111 -= b.t111; a.t112 -= b.t112; a.t122 -= b.t122; a.t222 -= b.t222; }
 }
 
-template <bool D3, class T>
+// PAIR: the dPIE by epje_prime (one arctangent and one inverse hyperbolic tangent); otherwise
+// as the difference of two cored isothermal terms.  The main-halo pass of the maps takes the
+// pair form (19% faster there); in the image-plane Newton kernel the pair form measured 2.2x
+// slower (its code around the per-lane member loop compiles differently), so the other
+// callers keep the two-term form.
+template <bool D3, class T, bool PAIR = false>
 __device__ __forceinline__ void epje(T dx, T dy, T c, T sn, T bqe, T e, T q2, T s, T a, bool pje, Term<T>& t) {
   T xp = c * dx + sn * dy, yp = c * dy - sn * dx;
   Term<T> p;
-  if (pje) epje_prime<D3>(xp, yp, bqe, e, q2, s, a, p);
-  else esie_prime<D3>(xp, yp, bqe, e, q2, s, p);
+  if (PAIR && pje) {
+    epje_prime<D3>(xp, yp, bqe, e, q2, s, a, p);
+  } else {
+    esie_prime<D3>(xp, yp, bqe, e, q2, s, p);
+    if (pje) {
+      Term<T> p2;
+      esie_prime<D3>(xp, yp, bqe, e, q2, a, p2);
+      sub_term<D3>(p, p2);
+    }
+  }
   rotate_back<D3>(c, sn, p, t);
 }
 
@@ -527,7 +542,7 @@ __device__ __forceinline__ double pot_main(const MainRec& r, double px, double p
 // ENFW = false compiles the elliptical NFW quadrature out (a kernel variant for models without
 // elliptical NFW halos, which then needs far fewer registers); such a halo reaching it is
 // flagged invalid.
-template <bool D3, bool ENFW = true>
+template <bool D3, bool ENFW = true, bool PAIR = false>
 __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py, const Quad& qd, Acc& acc) {
   double dx = px - r.x, dy = py - r.y;
   double r2 = fma(dx, dx, dy * dy);
@@ -545,7 +560,7 @@ __device__ __forceinline__ void eval_main(const MainRec& r, double px, double py
       break;
     case T_PJE:
       if (r.q >= 1.0) cpje<D3>(dx, dy, r.b, r.s, r.a, r.s * r.s, r.a * r.a, r.b * (r.a - r.s), r.a + r.s, t);
-      else epje<D3>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t);
+      else epje<D3, double, PAIR>(dx, dy, r.c, r.sn, r.bqe, r.e, r.q2, r.s, r.a, true, t);
       break;
     case T_NFW: nfw_circ<D3>(dx, dy, r.b, r.s, t); break;
     default:

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_heavy(const MapsArgs A) {
   const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
   for (int c = 0; c < A.m.n_main; ++c) {
     const MainRec r = mr[c];
-    eval_main<D3, ENFW>(r, px[0], py[0], A.qd, acc[0]);
+    eval_main<D3, ENFW, true>(r, px[0], py[0], A.qd, acc[0]);
     acc[0].flags |= r.flags;
   }
   const SegOff& so = A.m.seg;
