@@ -113,9 +113,11 @@ def summarize_profiles(kind, dirs):
         return
     if kind == "flops":
         # every kernel of a run: counter FLOPs (per-op VALU counters, FMA 2, add, mul and
-        # transcendental 1 each, 64 lanes per wave-instruction: lanes masked off count too) from a
-        # --pmc run, and its time from a --kernel-trace --stats run of the same command; rates are
-        # total FLOPs over total time, against the FP32 and FP64 vector peaks
+        # transcendental 1 each, 64 lanes per wave-instruction: lanes masked off count too) from
+        # --pmc runs, and its time from a --kernel-trace --stats run of the same command; rates are
+        # FLOPs per dispatch (each counter averaged over the dispatches of its own run) times the
+        # calls of the stats run, over their total time, against the FP32 and FP64 vector peaks
+        # (runs of one command can differ in dispatch counts: the bench's clock settle is timed)
         spath = glob.glob(os.path.join(dirs[0], "**", "*kernel_stats.csv"), recursive=True)[0]
         stats = {r["Name"]: (int(r["Calls"]), float(r["TotalDurationNs"]) * 1e-9) for r in csv.DictReader(open(spath))}
         per = {}
@@ -125,14 +127,18 @@ def summarize_profiles(kind, dirs):
                 key = (r["Kernel_Name"], d, r["Dispatch_Id"])
                 per.setdefault(key, {})
                 per[key][r["Counter_Name"]] = per[key].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-        tot, nd = {}, {}
+        sums, nd = {}, {}
         for (name, d, _), ctrs in per.items():
-            t = tot.setdefault(name, {})
+            t = sums.setdefault((name, d), {})
             nd[(name, d)] = nd.get((name, d), 0) + 1
             for c, v in ctrs.items():
                 t[c] = t.get(c, 0.0) + v
-        for name, t in tot.items():        # dispatches of one run (every run repeats the command)
-            t["dispatches"] = max(v for (n, _), v in nd.items() if n == name)
+        tot = {}                           # per-dispatch averages, each counter from its own run
+        for (name, d), t in sums.items():
+            a = tot.setdefault(name, {"dispatches": 0})
+            a["dispatches"] = max(a["dispatches"], nd[(name, d)])
+            for c, v in t.items():
+                a[c] = v / nd[(name, d)]
         fl = {"FMA": 2, "ADD": 1, "MUL": 1, "TRANS": 1}
         print("# source_sha256: %s" % kernel_source_hash())
         print("%-52s %6s %6s %10s %10s %10s %8s %8s %7s %7s %9s" % (
@@ -143,9 +149,9 @@ def summarize_profiles(kind, dirs):
             if name not in stats:
                 continue
             calls, sec = stats[name]
-            f32 = sum(64 * w * t.get("SQ_INSTS_VALU_%s_F32" % k, 0.0) for k, w in fl.items())
-            f64 = sum(64 * w * t.get("SQ_INSTS_VALU_%s_F64" % k, 0.0) for k, w in fl.items())
-            tr = 64 * (t.get("SQ_INSTS_VALU_TRANS_F32", 0.0) + t.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
+            f32 = calls * sum(64 * w * t.get("SQ_INSTS_VALU_%s_F32" % k, 0.0) for k, w in fl.items())
+            f64 = calls * sum(64 * w * t.get("SQ_INSTS_VALU_%s_F64" % k, 0.0) for k, w in fl.items())
+            tr = calls * 64 * (t.get("SQ_INSTS_VALU_TRANS_F32", 0.0) + t.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
             if sec <= 0 or (f32 + f64) < 1e6:
                 continue
             rows.append((sec, name, calls, t["dispatches"], f32, f64, tr))

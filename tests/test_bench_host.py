@@ -127,7 +127,8 @@ def test_flops_summary_joins_counters_and_times(tmp_path, capsys):
     sfields = ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]
     _write_csv(str(tmp_path / "s" / "x" / "x_kernel_stats.csv"), sfields,
                [{"Name": "kA", "Calls": 2, "TotalDurationNs": 2e6, "AverageNs": 1e6, "Percentage": 90},
-                {"Name": "kB", "Calls": 1, "TotalDurationNs": 1e5, "AverageNs": 1e5, "Percentage": 10}])
+                {"Name": "kB", "Calls": 1, "TotalDurationNs": 1e5, "AverageNs": 1e5, "Percentage": 10},
+                {"Name": "kC", "Calls": 4, "TotalDurationNs": 4e6, "AverageNs": 1e6, "Percentage": 5}])
     pf = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
     rows = []
     for d in (1, 2):       # kA: two dispatches, each 1e6 FP64 FMA + 5e5 FP32 adds, split over two instances
@@ -138,15 +139,22 @@ def test_flops_summary_joins_counters_and_times(tmp_path, capsys):
                          "Counter_Value": 2.5e5})
     rows.append({"Dispatch_Id": 3, "Kernel_Name": "kB", "Counter_Name": "SQ_INSTS_VALU_TRANS_F32",
                  "Counter_Value": 1e6})
+    # kC: 4 calls in the timed run but one dispatch in the counter run (a run of the same command
+    # can launch a kernel a different number of times): FLOPs per dispatch x calls
+    rows.append({"Dispatch_Id": 4, "Kernel_Name": "kC", "Counter_Name": "SQ_INSTS_VALU_FMA_F32",
+                 "Counter_Value": 1e6})
     _write_csv(str(tmp_path / "p" / "r" / "r_counter_collection.csv"), pf, rows)
     bench.summarize_profiles("flops", [str(tmp_path / "s"), str(tmp_path / "p")])
     lines = capsys.readouterr().out.strip().splitlines()
     assert lines[0] == "# source_sha256: " + bench.kernel_source_hash()
-    a = lines[2].split()
-    assert a[0] == "kA" and a[1:3] == ["2", "2"]
+    a = [l.split() for l in lines[2:] if l.startswith("kA")][0]
+    assert a[1:3] == ["2", "2"]
     # FP64: 2 dispatches x 1e6 FMA x 64 lanes x 2 = 2.56e8 FLOP in 2 ms -> 0.128 TFLOP/s
     assert float(a[5]) == pytest.approx(0.256) and float(a[7]) == pytest.approx(0.128, abs=0.01)
     assert float(a[4]) == pytest.approx(0.064)
     assert float(a[9]) == pytest.approx(0.128e12 / bench.PEAK_FP64_VECTOR, abs=1e-3)
-    b = lines[3].split()
-    assert b[0] == "kB" and float(b[-1]) == pytest.approx(64e6 / 1e-4 / 1e9)
+    c = [l.split() for l in lines[2:] if l.startswith("kC")][0]
+    # 4 x 1e6 FMA x 64 lanes x 2 = 5.12e8 FLOP in 4 ms -> 0.128 TFLOP/s
+    assert c[1:3] == ["4", "1"] and float(c[4]) == pytest.approx(0.512) and float(c[6]) == pytest.approx(0.128, abs=0.01)
+    b = [l.split() for l in lines[2:] if l.startswith("kB")][0]
+    assert float(b[-1]) == pytest.approx(64e6 / 1e-4 / 1e9)
