@@ -110,6 +110,24 @@ def test_find_sis_analytic_and_vertex_sources(ctx, lf):
         assert np.allclose(g2["theta"][:, 0], pts, atol=1e-12)
 
 
+def test_find_merge_more_than_64_candidates(ctx, lf):
+    """A source with more than 64 candidate triangles takes the merge's one-lane path (up to 64
+    the candidates sit one per lane): with no lens and the MIXED candidate margin of 5e-5" over a
+    grid of 1e-5" cells, about 240 triangles lie within the margin of the source.  One image, at
+    the source, unflagged; in FP64 (margin 1e-9") the same image through the lane path."""
+    model = {"z_d": 0.5, "H0": 70.0, "Om": 0.3, "n_free": 0, "main": [],
+             "members": {"type": np.zeros(0, np.int32), "x": np.zeros(0), "y": np.zeros(0), "q": None,
+                         "pa": None, "lum": None, "b0": np.zeros(0), "s0": np.zeros(0), "a0": np.zeros(0),
+                         "bmul": W.fixed(1.0), "smul": W.fixed(1.0), "amul": W.fixed(1.0)}}
+    grid = {"x0": -2e-4, "y0": -2e-4, "h": 1e-5, "nx": 40, "ny": 40}
+    beta = np.array([[1.234e-6, -2.345e-6], [7.7e-5, 3.1e-5]])
+    for prec in ("mixed", "fp64"):
+        g = _run(ctx, lf, model, None, beta, 1.0, grid, prec)
+        assert g["count"].tolist() == [1, 1], prec
+        assert np.allclose(g["theta"][:, 0], beta, rtol=0, atol=1e-12), prec
+        assert not np.any(g["flags"]), prec
+
+
 def test_find_overflow_reports_true_count(ctx, lf, orc):
     cfg = W.config1()
     beta, a = lensdata.config1_sources()
