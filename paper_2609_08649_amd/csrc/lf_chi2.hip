@@ -193,7 +193,7 @@ __device__ void chi2_heavy_lane(const Chi2Args& A, long long g) {
   const MainRec* mr = A.mains + (size_t)s * A.m.n_main;
   for (int c = 0; c < A.m.n_main; ++c) {
     const MainRec r = mr[c];
-    eval_main<false>(r, x, y, A.qd, acc);
+    eval_main<false, true, true>(r, x, y, A.qd, acc);
     acc.flags |= r.flags;
   }
   const MulRec u = A.muls[s];

@@ -265,10 +265,10 @@ __device__ __forceinline__ void sub_term(Term<T>& a, const Term<T>& b) {
 }
 
 // PAIR: the dPIE by epje_prime (one arctangent and one inverse hyperbolic tangent); otherwise
-// as the difference of two cored isothermal terms.  The main-halo pass of the maps takes the
-// pair form (19% faster there); in the image-plane Newton kernel the pair form measured 2.2x
-// slower (its code around the per-lane member loop compiles differently), so the other
-// callers keep the two-term form.
+// as the difference of two cored isothermal terms.  The main-halo passes of the maps and of the
+// chi^2 take the pair form (19% and ~4% faster there); in the image-plane Newton kernel the
+// pair form measured 2.2x slower (its code around the per-lane member loop compiles
+// differently), so the other callers keep the two-term form.
 template <bool D3, class T, bool PAIR = false>
 __device__ __forceinline__ void epje(T dx, T dy, T c, T sn, T bqe, T e, T q2, T s, T a, bool pje, Term<T>& t) {
   T xp = c * dx + sn * dy, yp = c * dy - sn * dx;
