@@ -110,6 +110,36 @@ def test_find_sis_analytic_and_vertex_sources(ctx, lf):
         assert np.allclose(g2["theta"][:, 0], pts, atol=1e-12)
 
 
+@pytest.mark.parametrize("kind", ["many_members", "many_mains", "enfw"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_find_polish_layouts(ctx, lf, orc, kind, prec):
+    """The polish's other work layouts against the oracle: 400 members (more than the LDS copy of
+    the records holds: read from global memory, three or more members per thread), 40 main
+    halos (80 main parts: all halos strided over all threads) and an elliptical NFW main halo
+    (the variant with the quadrature)."""
+    if kind == "many_members":
+        model, _ = W.tiny_model(31, n_main=2, n_mem=400, types=[W.SIE, W.PJE])
+    elif kind == "many_mains":
+        model, _ = W.tiny_model(32, n_main=40, n_mem=6, types=[W.SIS, W.SIE, W.PJE, W.POINT])
+        for c in model["main"]:       # 40 halos of the usual strength would make a far too massive lens
+            c["b"] = W.fixed(c["b"][1] * 0.15)
+    else:
+        model, _ = W.tiny_model(33, n_main=2, n_mem=6, types=[W.ENFW, W.PJE])
+    tab = orc.expand(model)
+    grid = {"x0": -16.0, "y0": -16.0, "h": 32.0 / 256, "nx": 256, "ny": 256}
+    a = 0.6
+    # sources: the oracle's source positions of points within 2" of the two first main halos
+    rng = np.random.default_rng(34)
+    th = np.array([[model["main"][i % 2]["x"][1], model["main"][i % 2]["y"][1]] for i in range(12)])
+    th = th + rng.uniform(-2.0, 2.0, th.shape)
+    mp = orc.maps(tab, th[:, 0], th[:, 1], a)
+    beta = np.stack([mp["beta_x"], mp["beta_y"]], 1)
+    o = orc.find_images(tab, grid, beta, np.full(len(beta), a))
+    assert o["count"].sum() > len(beta)          # some multiple images
+    g = _run(ctx, lf, model, None, beta, a, grid, prec)
+    compare(g, o, 1e-9 if prec == "fp64" else 1e-4)
+
+
 def test_find_merge_more_than_64_candidates(ctx, lf):
     """A source with more than 64 candidate triangles takes the merge's one-lane path (up to 64
     the candidates sit one per lane): with no lens and the MIXED candidate margin of 5e-5" over a
