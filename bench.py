@@ -359,10 +359,11 @@ def main():
     # step's deflections.  Consecutive steps are pipelined over two streams with a context each
     # (calls on one context share its workspace): the maps and then the chi^2 batch on the first
     # stream, the finder on the second once its step's maps are written, so that the finder's
-    # polish -- chains of dependent FP64 sums on a few hundred workgroups -- runs beside the next
-    # step's maps instead of leaving the chip idle.  The maps outputs are double buffered: step
-    # n + 2 writes step n's buffers once step n's finder is done.  The per-stage times below run
-    # each stage alone on one stream.
+    # polish -- chains of dependent FP64 sums on a few hundred workgroups -- runs beside the chi^2
+    # batch and the next step's maps instead of leaving the chip idle (started after the chi^2
+    # batch instead, beside the next main-halo pass, the step took 1.04 instead of 0.98 ms).  The
+    # maps outputs are double buffered: step n + 2 writes step n's buffers once step n's finder
+    # is done.  The per-stage times below run each stage alone on one stream.
     streamF = torch.cuda.Stream(device=dev)
     ctxF = lf.Context(0)
     mF = ctxF.upload_model(model)
@@ -413,9 +414,12 @@ def main():
     for _ in range(args.warmup):
         step(lf.LF_PREC_MIXED)
     torch.cuda.synchronize()
-    for c in (ctx, ctxF):
-        L.lf_profile_reset(c.handle)
-        L.lf_profile_enable(c.handle, 1)
+    # In the timed steps only the roofline kernel is bracketed by the library's HIP events
+    # (events around every launch cost the step ~3%); the other kernels are timed in a pass of
+    # their own after the clock stops.
+    L.lf_profile_reset(ctx.handle)
+    L.lf_profile_only(ctx.handle, b"maps_lean")
+    L.lf_profile_enable(ctx.handle, 1)
     # Steps are issued back to back; per-step times come from events recorded on the first
     # stream at the step boundaries (the finder's stream is drained before the clock stops).
     step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -428,8 +432,6 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     step_ms = [step_ev[k].elapsed_time(step_ev[k + 1]) for k in range(args.steps)]
-    for c in (ctx, ctxF):
-        L.lf_profile_enable(c.handle, 0)
     ms = (t1 - t0) * 1e3 / args.steps
 
     def prof(name):
@@ -439,16 +441,28 @@ def main():
         return tot.value, cnt.value
 
     lean_tot, lean_cnt = prof("maps_lean")
+    L.lf_profile_enable(ctx.handle, 0)
+    L.lf_profile_only(ctx.handle, None)
     lean_ms = lean_tot / max(1, lean_cnt)
     n_mem = len(model["members"]["x"])
     flops_lean = n_mem * P * F_CPJE
     achieved = flops_lean / (lean_ms * 1e-3)
+    # per-kernel breakdown: the same pipelined steps again with every launch timed
+    n_brk = max(2, args.steps // 2)
+    for c in (ctx, ctxF):
+        L.lf_profile_reset(c.handle)
+        L.lf_profile_enable(c.handle, 1)
+    for _ in range(n_brk):
+        step(lf.LF_PREC_MIXED)
+    torch.cuda.synchronize()
     kernels = {}
     for k in ("expand", "maps_heavy", "maps_lean", "chi2_heavy", "chi2_lean", "chi2_src", "find_cand",
               "find_polish"):
         t, c = prof(k)
         if c:
-            kernels[k] = {"avg_ms": t / c, "launches_per_step": c / args.steps}
+            kernels[k] = {"avg_ms": t / c, "launches_per_step": c / n_brk}
+    for c in (ctx, ctxF):
+        L.lf_profile_enable(c.handle, 0)
 
     note("timed steps done: %.3f ms per step" % ms)
     # per-stage times (MIXED and FP64) with events on the working stream
@@ -512,9 +526,10 @@ def main():
         "inference": inference,
         "clock_settle_ms": CLOCK_SETTLE_MS,
         "step_schedule": "steps pipelined over two streams: maps then source-plane chi^2 on the first, the "
-                         "finder on the second beside the next step's maps (double-buffered maps outputs); "
-                         "kernel averages include that overlap",
+                         "finder on the second beside the chi^2 and the next step's maps (double-buffered "
+                         "maps outputs); kernel averages include that overlap",
         "kernels": kernels,
+        "kernels_timing": "library HIP events around every launch, in %d pipelined steps after the timed ones" % n_brk,
         "roofline": {"bound": "alu", "kernel": "maps_lean", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR, "traffic": recorded_traffic(),

@@ -185,6 +185,10 @@ size_t lf_device_bytes(const lf_ctx* ctx);
 lf_status lf_profile_enable(lf_ctx* ctx, int32_t on);
 lf_status lf_profile_read(lf_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
 lf_status lf_profile_reset(lf_ctx* ctx);
+/* Restrict kernel timing to one kernel name (host string, copied), so that the events of the
+ * other launches stay off the streams; NULL or "" times every kernel again.  Returns
+ * LF_E_INVALID_ARG for a null context. */
+lf_status lf_profile_only(lf_ctx* ctx, const char* kernel);
 
 /* ---------------------------------------------------------------- cosmology helpers (host) */
 /* Angular-diameter distance D(z1, z2) [Mpc] in flat LCDM (Sec. 2.1, 2.2). */

@@ -94,12 +94,15 @@ hipEvent_t lf_ctx::prof_ev() {
 }
 void lf_ctx::prof_begin(const char* name, hipStream_t st) {
   if (!prof) return;
+  prof_skip = !prof_only.empty() && prof_only != name;
+  if (prof_skip) return;
   Rec r;
   r.name = name; r.a = prof_ev(); r.b = nullptr;
   hipEventRecord(r.a, st);
   prof_pending.push_back(r);
 }
 void lf_ctx::prof_end(hipStream_t st) {
+  if (prof_skip) { prof_skip = false; return; }
   if (!prof || prof_pending.empty() || prof_pending.back().b) return;
   prof_pending.back().b = prof_ev();
   hipEventRecord(prof_pending.back().b, st);
@@ -123,6 +126,11 @@ extern "C" lf_status lf_profile_enable(lf_ctx* ctx, int32_t on) {
   if (!ctx) return LF_E_INVALID_ARG;
   ctx->prof_flush();
   ctx->prof = on != 0;
+  return LF_OK;
+}
+extern "C" lf_status lf_profile_only(lf_ctx* ctx, const char* kernel) {
+  if (!ctx) return LF_E_INVALID_ARG;
+  ctx->prof_only = kernel ? kernel : "";
   return LF_OK;
 }
 extern "C" lf_status lf_profile_read(lf_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches) {

@@ -28,6 +28,8 @@ struct lf_ctx {
   double* quad_w = nullptr;
   // kernel timing (HIP events on the launching stream)
   bool prof = false;
+  std::string prof_only;      // time only this kernel name (empty: every kernel)
+  bool prof_skip = false;     // the open bracket was not recorded
   hipStream_t cur_stream = nullptr;
   struct Rec { std::string name; hipEvent_t a, b; };
   std::vector<Rec> prof_pending;

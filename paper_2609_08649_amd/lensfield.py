@@ -129,6 +129,7 @@ def lib():
             "lf_serve_stop": (I32, [P]),
             "lf_profile_read": (I32, [P, C.c_char_p, C.POINTER(D), C.POINTER(I64)]),
             "lf_profile_reset": (I32, [P]),
+            "lf_profile_only": (I32, [P, C.c_char_p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

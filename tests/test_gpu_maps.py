@@ -185,6 +185,40 @@ def test_maps_config1_grid(ctx, lf, orc, prec):
     check({k: v[0] for k, v in g.items()}, o, prec, a=0.6354)
 
 
+def test_profile_only_times_one_kernel(lf):
+    """lf_profile_only: with a kernel name only that kernel's launches are timed; with NULL every
+    launch again."""
+    import ctypes as C
+    c = lf.Context(0)
+    try:
+        cfg = W.config1()
+        L = lf.lib()
+
+        def counts():
+            out = {}
+            for k in ("maps_lean", "maps_heavy", "expand"):
+                t, n = C.c_double(), C.c_int64()
+                assert L.lf_profile_read(c.handle, k.encode(), C.byref(t), C.byref(n)) == 0
+                out[k] = n.value
+            return out
+
+        assert L.lf_profile_only(None, b"maps_lean") != 0
+        L.lf_profile_reset(c.handle)
+        assert L.lf_profile_only(c.handle, b"maps_lean") == 0
+        L.lf_profile_enable(c.handle, 1)
+        _run(c, lf, cfg["model"], None, 1, cfg["grid"], 0.6354, "mixed")
+        one = counts()
+        assert one["maps_lean"] >= 1 and one["maps_heavy"] == 0 and one["expand"] == 0
+        L.lf_profile_reset(c.handle)
+        assert L.lf_profile_only(c.handle, None) == 0
+        _run(c, lf, cfg["model"], None, 1, cfg["grid"], 0.6354, "mixed")
+        every = counts()
+        assert every["maps_lean"] >= 1 and every["expand"] >= 1
+        L.lf_profile_enable(c.handle, 0)
+    finally:
+        c.close()
+
+
 def test_maps_config2_full_grid(ctx, lf, orc):
     """Full 2048^2 cluster map (2 elliptical dPIE + 300 members) in the benchmark's launch
     configuration, compared with the oracle at every one of the 4.2M points."""
