@@ -881,6 +881,20 @@ def bench_batched(ctx, lf, torch, W, stream, timed):
                     ctx.chi2_batch(mod, p, Sm, cons, mode, prec, stream=stream)
             seq()
             res[name + tag]["per_model_calls_ms"] = timed(seq, 5 if mode == 0 else 2)
+    # Where the one-launch form pays: many small items (each model's walkers in slices of 16,
+    # 64 items of 16 samples), whose separate calls are a few short kernels each.
+    small = [(mod, cons, p[16 * j:16 * (j + 1)], 16) for (mod, cons, p, Sm) in items for j in range(8)]
+    b = lf.Batch(ctx, small, 0, lf.LF_PREC_MIXED, autotune=True)
+    b.run(stream)
+    t = timed(lambda: b.run(stream), 10)
+    b.release()
+
+    def seq_small():
+        for (mod, cons, p, Sm) in small:
+            ctx.chi2_batch(mod, p, Sm, cons, 0, lf.LF_PREC_MIXED, stream=stream)
+    seq_small()
+    res["mixed_small_items"] = {"items": len(small), "samples_per_item": 16, "graph_ms": t,
+                                "per_item_calls_ms": timed(seq_small, 5)}
     for mod, cons, p, Sm in items:
         cons.release()
         mod.release()
