@@ -483,7 +483,7 @@ lf_status lf_expand_alloc(lf_ctx* ctx, const lf_model* M, int S, bool need_mem, 
   if (err) return err;
   *m32 = nullptr; *m64 = nullptr;
   if (need_mem) {
-    *m32 = (lf::MemRec32*)ctx->ws((t + ".m32").c_str(), sizeof(lf::MemRec32) * std::max<size_t>(1, (size_t)S * nb), st, &err);
+    *m32 = (lf::MemRec32*)ctx->ws((t + ".m32").c_str(), std::max(sizeof(lf::MemRec32), lf::mem32_bytes(S, nb)), st, &err);
     if (err) return err;
     *m64 = (lf::MemRec64*)ctx->ws((t + ".m64").c_str(), sizeof(lf::MemRec64) * std::max<size_t>(1, (size_t)S * nb), st, &err);
     if (err) return err;

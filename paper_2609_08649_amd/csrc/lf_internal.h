@@ -1,5 +1,7 @@
 // Internal host/device data layouts of the lensfield library (not part of the ABI).
 #pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace lf {
@@ -91,6 +93,35 @@ static constexpr float FAR_WP[6] = {4.0f, 7.5f, 17.5f, 31.5f, 49.5f, 71.5f};
 struct MemRec64 {
   double x, y, b, s, a, s2, a2, c, sn, q2, e, bqe, bd, apls;
 };
+
+// A member table of S samples holds S * n_mem MemRec32 records followed by S blocks, one per
+// sample, of the fields the grid tiles classify and expand members with, as structure of arrays
+// of soa_pad(n_mem) entries: centre x, y and cut radius a (FP64), then the near-field radius^2
+// rn2 and the far-field coefficients fm0..fm5 (FP32).  The 64 lanes of a wave that take 64
+// consecutive members read 64 consecutive entries of a field (a few cache lines) instead of one
+// field of 64 records 128 bytes apart.
+__host__ __device__ inline size_t soa_pad(int n) { return ((size_t)n + 63) / 64 * 64; }
+__host__ __device__ inline size_t soa_block_bytes(int n) { return soa_pad(n) * (3 * sizeof(double) + 7 * sizeof(float)); }
+__host__ __device__ inline size_t mem32_bytes(int S, int n) {
+  return sizeof(MemRec32) * (size_t)S * (size_t)n + (size_t)S * soa_block_bytes(n);
+}
+struct MemSoA {
+  double *x, *y, *a;
+  float *rn2, *fm;     // coefficient k of member i: fm[k * pad + i]
+  size_t pad;
+};
+// The block of sample s of a table of S samples of n members.
+__host__ __device__ inline MemSoA mem_soa(const MemRec32* m32, int S, int n, int s) {
+  MemSoA v;
+  v.pad = soa_pad(n);
+  char* b = (char*)(m32 + (size_t)S * n) + (size_t)s * soa_block_bytes(n);
+  v.x = (double*)b;
+  v.y = v.x + v.pad;
+  v.a = v.y + v.pad;
+  v.rn2 = (float*)(v.a + v.pad);
+  v.fm = v.rn2 + v.pad;
+  return v;
+}
 
 struct SegOff {          // member index range of each segment: [off[k], off[k+1])
   int32_t off[NSEG + 1];

@@ -42,7 +42,8 @@ struct MapsOut {
 };
 
 // a1: per-sample expansion of main components, multipliers and (optionally) pre-scaled
-// member tables.  Writes mains [S*n_main], muls [S], m32/m64 [S*n_mem] (each may be null).
+// member tables.  Writes mains [S*n_main], muls [S], m32/m64 [S*n_mem] (each may be null; m32
+// is followed by the S structure-of-arrays blocks of mem_soa, mem32_bytes(S, n_mem) in all).
 hipError_t launch_expand(const DevModel& m, const double* params, int S, MainRec* mains,
                          MulRec* muls, MemRec32* m32, MemRec64* m64, hipStream_t st);
 

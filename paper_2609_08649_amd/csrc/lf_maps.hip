@@ -136,6 +136,9 @@ __global__ void k_expand(const DevModel m, const double* __restrict__ params, in
           r.fw[k] = far_ok ? (float)(-(2 * k + 1 + (k == 0)) * mk) : 0.f;
         }
         m32[(size_t)s * m.n_mem + i] = r;
+        const MemSoA v = mem_soa(m32, S, m.n_mem, s);
+        v.x[i] = c.x; v.y[i] = c.y; v.a[i] = a; v.rn2[i] = r.rn2;
+        for (int k = 0; k < 6; ++k) v.fm[k * v.pad + i] = r.fm[k];
       }
     }
   }
@@ -347,8 +350,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D3 ? 3 : 4,
   }
   const SegOff& so = A.m.seg;
   const size_t mo = (size_t)s * A.m.n_mem;
-  seg_loop_tile<SEG_CPJE, D3, TP>(A.m32 + mo, A.m64 + mo, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], L, acc, A.qd);
-  seg_loop_tile<SEG_CSIE, D3, TP>(A.m32 + mo, A.m64 + mo, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], L, acc, A.qd);
+  const MemSoA sa = mem_soa(A.m32, A.S, A.m.n_mem, s);
+  seg_loop_tile<SEG_CPJE, D3, TP>(A.m32 + mo, A.m64 + mo, sa, so.off[SEG_CPJE], so.off[SEG_CPJE + 1], L, acc, A.qd);
+  seg_loop_tile<SEG_CSIE, D3, TP>(A.m32 + mo, A.m64 + mo, sa, so.off[SEG_CSIE], so.off[SEG_CSIE + 1], L, acc, A.qd);
 #pragma unroll
   for (int k = 0; k < TP; ++k)
     if (active[k]) store_point<D3>(A, (size_t)s * P + p[k], L.px, L.py[k], acc[k]);

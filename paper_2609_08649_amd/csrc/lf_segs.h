@@ -1,6 +1,7 @@
 // Member-galaxy segment loops shared by the maps, finder and multi-plane kernels.
 #pragma once
 #include "lf_device.h"
+#include "lf_lexp.h"
 
 namespace lf {
 
@@ -375,45 +376,103 @@ __device__ __forceinline__ void put_far_d3(float* lw, int nt, float dx, float dy
   else put_far_d3_n<6>(lw, dx, dy, r);
 }
 
-// Members are taken in blocks of 64.  Lane j of the wave takes member j of the block: its
-// offset D from the block centre (FP64, rounded to FP32), whether its near-field disc (radius^2
-// rn2, with a relative margin of 1e-5 for the FP32 rounding of a lane's r^2) meets the wave's
-// block, and how many cut radii away the whole block lies (far field with four terms at
-// FAR_K4, five at FAR_K5, six at FAR_K).  Ballots give the wave's near, far and closed-form
-// sets, and the records are written to LDS in the order four-term, five-term, six-term far
-// members, then closed-form ones (each set in member order), so that every run of LF_CHUNK
-// members has one evaluation (full runs unrolled).  Runs are counted from the start of each
-// set; near-field members are evaluated after the block lane by lane, exactly as in seg_loop:
-// in FP64 from the FP64 record where the lane's r^2 < rn2, otherwise in FP32 from the pair
-// offsets, each term added to the FP64 accumulators.  Every set depends only on the global
-// block and the member, so results do not depend on the launch shape.
+// Classification of member h for the wave's block: whether its near-field disc (radius^2 rn2,
+// with a relative margin of 1e-5 for the FP32 rounding of a lane's r^2) meets the block, how
+// many cut radii away the whole block lies (far field with four terms at FAR_K4, five at FAR_K5,
+// six at FAR_K; 0: closed form), and (EXP) whether the member joins the block's local expansion
+// (a far member at least LX_DIST block radii from the centre).  Every result depends only on the
+// global block and the member.
+struct TileCls {
+  bool flag, ex;
+  int tier;
+  double ddx, ddy;      // offset of the member from the block centre
+};
+template <bool FAR, bool D3, bool EXP, int TP>
+__device__ __forceinline__ TileCls tile_class(double x, double y, double ar, float rn2, const TileLane<TP>& L) {
+  TileCls c;
+  c.ddx = x - L.X; c.ddy = y - L.Y;
+  const double ex = fmax(fabs(c.ddx) - L.hwx, 0.0), ey = fmax(fabs(c.ddy) - L.hwy, 0.0);
+  const double e2 = fma(ex, ex, ey * ey);
+  c.flag = e2 < (double)rn2 * (1.0 + 1e-5);
+  const double a2r = ar * ar;
+  constexpr double K4 = D3 ? FAR_D3_K4 : FAR_K4, K5 = D3 ? FAR_D3_K5 : FAR_K5, K6 = D3 ? FAR_D3_K : FAR_K;
+  c.tier = 0;
+  if (FAR && !c.flag && ar <= FAR_AMAX)
+    c.tier = e2 >= K4 * K4 * a2r ? 4 : e2 >= K5 * K5 * a2r ? 5 : e2 >= K6 * K6 * a2r ? 6 : 0;
+  c.ex = EXP && c.tier != 0 &&
+         fma(c.ddx, c.ddx, c.ddy * c.ddy) >= LX_DIST * LX_DIST * fma(L.hwx, L.hwx, L.hwy * L.hwy);
+  return c;
+}
+
+// The block's local expansion (lf_lexp.h): every member of [lo, hi) that tile_class puts in it
+// adds its coefficients on the lane that holds it; the wave sums them into its LDS area (the
+// member loop's first wave_sync orders these reads before the records are written there) and
+// adds the expansion's deflection and Hessian at each of the lane's points.
+template <int TP>
+__device__ __forceinline__ void lexp_pass(const MemSoA& so, int lo, int hi, const TileLane<TP>& L, Acc (&acc)[TP]) {
+  const int lane = threadIdx.x & 63;
+  LxAcc g;
+  lx_zero(g);
+  bool any = false;
+  for (int b0 = lo; b0 < hi; b0 += 64) {
+    const int h = b0 + lane;
+    if (h < hi) {
+      const TileCls c = tile_class<true, false, true, TP>(so.x[h], so.y[h], so.a[h], so.rn2[h], L);
+      if (c.ex) {
+        float fm[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fm[k] = so.fm[k * so.pad + h];
+        lx_member((float)c.ddx, (float)c.ddy, fm, g);
+        any = true;
+      }
+    }
+  }
+  if (__ballot(any) == 0) return;
+  lx_reduce_store(g, L.dsh);
+  wave_sync();
+  lx_eval<TP>(L.dsh, L.u, L.v, acc);
+}
+
+// Members are taken in blocks of 64.  Lane j of the wave takes member j of the block and
+// classifies it (tile_class).  Without third derivatives the far dPIE members at least LX_DIST
+// block radii away are summed by the block's local expansion first (lexp_pass) and skipped
+// here.  Ballots give the wave's near, far and closed-form sets, and the records are written to
+// LDS in the order four-term, five-term, six-term far members, then closed-form ones (each set
+// in member order), so that every run of LF_CHUNK members has one evaluation (full runs
+// unrolled).  Runs are counted from the start of each set; near-field members are evaluated
+// after the block lane by lane, exactly as in seg_loop: in FP64 from the FP64 record where the
+// lane's r^2 < rn2, otherwise in FP32 from the pair offsets, each term added to the FP64
+// accumulators.  Every set depends only on the global block and the member, so results do not
+// depend on the launch shape.
 template <int SEG, bool D3, int TP>
 __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, const MemRec64* __restrict__ near64,
-                                              int lo, int hi, const TileLane<TP>& L, Acc (&acc)[TP],
-                                              const Quad& qd) {
+                                              const MemSoA& so, int lo, int hi, const TileLane<TP>& L,
+                                              Acc (&acc)[TP], const Quad& qd) {
   static_assert(SEG == SEG_CPJE || SEG == SEG_CSIE, "tiles hold the circular segments");
   constexpr int LS = TILE_LSTRIDE<SEG, D3>;
   constexpr bool FAR = TILE_FAR<SEG, D3>;
+  constexpr bool EXP = FAR && !D3;
+  if constexpr (EXP) lexp_pass<TP>(so, lo, hi, L, acc);
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int b0 = lo; b0 < hi; b0 += 64) {
     const int nb = min(64, hi - b0);
     bool flag = false;
     int tier = 0;                       // far-field terms (4, 5 or 6), 0: closed form
+    bool ex = false;                    // summed by the local expansion
     float dxf = 0.f, dyf = 0.f;
     float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
     if (lane < nb) {
-      const double cx = near64[b0 + lane].x, cy = near64[b0 + lane].y;
-      const double ddx = cx - L.X, ddy = cy - L.Y;
-      const double ex = fmax(fabs(ddx) - L.hwx, 0.0), ey = fmax(fabs(ddy) - L.hwy, 0.0);
-      const double e2 = fma(ex, ex, ey * ey);
+      const int h = b0 + lane;
+      const TileCls c = tile_class<FAR, D3, EXP, TP>(so.x[h], so.y[h], so.a[h], so.rn2[h], L);
+      flag = c.flag;
+      ex = c.ex;
+      tier = ex ? 0 : c.tier;
+      dxf = (float)c.ddx; dyf = (float)c.ddy;
+    }
+    // the records of the members this wave stages (LDS) are read by those lanes only
+    if (lane < nb && !flag && !ex) {
       const MemRec32& r = rec[b0 + lane];
-      flag = e2 < (double)r.rn2 * (1.0 + 1e-5);
-      const double ar = near64[b0 + lane].a, a2r = ar * ar;
-      constexpr double K4 = D3 ? FAR_D3_K4 : FAR_K4, K5 = D3 ? FAR_D3_K5 : FAR_K5, K6 = D3 ? FAR_D3_K : FAR_K;
-      if (FAR && !flag && ar <= FAR_AMAX)
-        tier = e2 >= K4 * K4 * a2r ? 4 : e2 >= K5 * K5 * a2r ? 5 : e2 >= K6 * K6 * a2r ? 6 : 0;
-      dxf = (float)ddx; dyf = (float)ddy;
       w0 = make_float4(dxf, dyf, r.s2, r.a2);
       w1 = make_float4(r.s, r.a, r.bd, r.apls);
       w2 = make_float4(r.b, 0.f, 0.f, 0.f);
@@ -436,7 +495,7 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
         }
       }
     }
-    const bool closed = lane < nb && !flag && tier == 0;
+    const bool closed = lane < nb && !flag && !ex && tier == 0;
     const unsigned long long nmask = __ballot(flag), m4 = __ballot(tier == 4), m5 = __ballot(tier == 5),
                              m6 = __ballot(tier == 6), cmask = __ballot(closed);
     const int n4 = __popcll(m4), n5 = __popcll(m5), n6 = __popcll(m6), ncl = __popcll(cmask);

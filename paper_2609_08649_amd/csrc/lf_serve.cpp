@@ -157,7 +157,8 @@ size_t map_footprint(const lf_server* s, const lf_request& r) {
   return 256 * 10 + sizeof(double) * r.model->n_free + (dev ? 0 : sizeof(double) * map_planes(r.kind) * P) +
          (dev && !r.flags_device ? sizeof(int) * chunkP : dev ? 0 : sizeof(int) * P) +
          chunkP * (sizeof(double) * 9 + sizeof(int)) + sizeof(lf::MainRec) * std::max<size_t>(1, r.model->main.size()) +
-         sizeof(lf::MulRec) + (sizeof(lf::MemRec32) + sizeof(lf::MemRec64)) * std::max<size_t>(1, nb);
+         sizeof(lf::MulRec) + lf::mem32_bytes(1, (int)std::max<size_t>(1, nb)) +
+         sizeof(lf::MemRec64) * std::max<size_t>(1, nb);
 }
 
 void* take(lf_server* s, Req& q, size_t bytes) {
@@ -226,7 +227,7 @@ bool admit_map(lf_server* s, Req& q) {
   q.part = (double*)get(chunkP * (sizeof(double) * 9 + sizeof(int)));
   q.mains = (lf::MainRec*)get(sizeof(lf::MainRec) * std::max<size_t>(1, r.model->main.size()));
   q.muls = (lf::MulRec*)get(sizeof(lf::MulRec));
-  q.m32 = (lf::MemRec32*)get(sizeof(lf::MemRec32) * nb);
+  q.m32 = (lf::MemRec32*)get(lf::mem32_bytes(1, (int)nb));
   q.m64 = (lf::MemRec64*)get(sizeof(lf::MemRec64) * nb);
   if (!ok) { give_back(s, q); return false; }
   return true;
