@@ -296,15 +296,16 @@ __global__ __launch_bounds__(256) void k_maps(const MapsArgs A) {
 // global grid (seg_loop_tile; a lane holds TP points of one column, TILE_H rows apart), the
 // blocks covering the grid rows of the points [p0, p0 + P).  Lanes' points outside those points
 // (or past the last column) take part in the member loops but store nothing.
-// Two points per lane (each LDS record read serves both; the LDS data path, which returns a
-// broadcast record to every lane, is the other limit of this loop): without third derivatives
-// at 4 waves per SIMD (104 VGPRs), measured faster than one point per lane at 8 waves and four
-// points at 3 or 4; with third derivatives at 3 waves (faster than one point per lane at 4-7).
+// Without third derivatives four points per lane (16 x 16 blocks) at 3 waves per SIMD: most
+// members go through the block's local expansion, whose per-member work is per block, so larger
+// blocks amortise it (measured 11% faster than two points per lane at 4 waves, and than four
+// points at 4 waves, which spills); with third derivatives two points per lane at 3 waves (each
+// LDS record read serves both; faster than one point per lane at 4-7 waves).
 template <bool D3>
-static constexpr int MAPS_TP = 2;
+static constexpr int MAPS_TP = D3 ? 2 : 4;
 
 template <bool D3>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D3 ? 3 : 4, 8))) void k_maps_tile(const MapsArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_maps_tile(const MapsArgs A) {
   constexpr int TP = MAPS_TP<D3>, TH = TILE_H * TP;
   __shared__ float dsh[4][64 * TILE_LSTRIDE<SEG_CPJE, D3>];
   const int s = blockIdx.y;
