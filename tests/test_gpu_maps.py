@@ -372,3 +372,19 @@ def test_maps_local_expansion_members(ctx, lf, orc):
     gg = {k: v[0] for k, v in g.items()}
     check(gg, o, "mixed", a=0.6)
     assert np.max(np.hypot(gg["alpha_x"] - o["ax"], gg["alpha_y"] - o["ay"])) < 2e-6
+
+
+def test_maps_grid_many_samples_mixed(ctx, lf, orc):
+    """MIXED grid maps of several samples in one call (free parameters): each sample's member
+    table, its structure-of-arrays block and its blocks' local expansions, against the oracle
+    at every point of every sample."""
+    model, truth = W.tiny_model(35, n_main=2, n_mem=90, types=[3, 2], free_params=True)
+    rng = np.random.default_rng(3)
+    S = 3
+    params = np.repeat(truth[None], S, 0) * (1 + 0.02 * rng.normal(size=(S, truth.size)))
+    grid = {"x0": -25.0, "y0": -18.0, "h": 0.2, "nx": 250, "ny": 180}
+    g = _run(ctx, lf, model, params, S, grid, 0.7, "mixed")
+    x, y = W.grid_points(grid)
+    for s in range(S):
+        o = orc.maps(orc.expand(model, params[s]), x, y, 0.7)
+        check({k: v[s] for k, v in g.items()}, o, "mixed", a=0.7)
