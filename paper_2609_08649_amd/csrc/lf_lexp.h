@@ -1,4 +1,4 @@
-// Local expansion of the far members of a grid block (lean maps, no third derivatives).
+// Local expansion of the far members of a grid block (the lean maps passes on a grid).
 //
 // A circular dPIE member (Sec. 3.4) that lies far from a block (the far-field series of its
 // closed form holds over the whole block, and the block is small next to its distance) is not
@@ -22,7 +22,8 @@
 // Terms up to total degree LX_K = 7 are kept.  Members are taken at distances of at least
 // LX_DIST block radii (|delta| / |zeta0| <= 1/8): the truncation is then below 1e-9 arcsec in
 // alpha and 1e-9 in the Hessian on cluster members, against 1e-7 for the FP32 rounding of one
-// member term.  Coefficients are formed and summed in FP32 except G_10 (the block centre's
+// member term; third derivatives (third derivatives of the same polynomial, degree 4) stay
+// within 3e-8 of the exact member sums.  Coefficients are formed and summed in FP32 except G_10 (the block centre's
 // deflection, the one term of the size of the total), which the lanes keep in FP64.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -210,10 +211,17 @@ __device__ __forceinline__ void lx_horner(float& zr, float& zi, float u, float v
 
 // Inner polynomials in delta for the power B of conj(delta), from the power A of delta down:
 // alpha: 2 (B+1) G(A, B+1) (the constant G_01 is added in FP64 by lx_eval), Laplacian:
-// 4 (A+1)(B+1) G(A+1, B+1), Gamma: 4 (B+2)(B+1) G(A, B+2).  All NP points of the lane at once,
-// so that each coefficient is read and scaled once.
-template <int A, int B, int NP>
-__device__ __forceinline__ void lx_inner(const float* g, float u, const float (&v)[NP], float (&q)[NP][6]) {
+// 4 (A+1)(B+1) G(A+1, B+1), Gamma: 4 (B+2)(B+1) G(A, B+2) and, with third derivatives (D3),
+// T = 8 d^3 psi / d conj(delta)^3: 8 (B+3)(B+2)(B+1) G(A, B+3) and
+// U = 8 d^3 psi / d delta d conj(delta)^2: 8 (A+1)(B+2)(B+1) G(A+1, B+2).  All NP points of the
+// lane at once, so that each coefficient is read and scaled once.
+template <int NQ>
+__device__ __forceinline__ void lx_step(float (&q)[NQ], int o, bool first, float u, float v, float cr, float ci) {
+  if (first) { q[o] = cr; q[o + 1] = ci; }
+  else lx_horner<false>(q[o], q[o + 1], u, v, cr, ci);
+}
+template <int A, int B, int NP, bool D3, int NQ>
+__device__ __forceinline__ void lx_inner(const float* g, float u, const float (&v)[NP], float (&q)[NP][NQ]) {
   constexpr int K = LX_K;
   float cr = 0.f, ci = 0.f;
   if constexpr (A + B > 0) {
@@ -221,10 +229,7 @@ __device__ __forceinline__ void lx_inner(const float* g, float u, const float (&
     cr *= 2.f * (B + 1); ci *= 2.f * (B + 1);
   }
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    if constexpr (A == K - 1 - B) { q[k][0] = cr; q[k][1] = ci; }
-    else lx_horner<false>(q[k][0], q[k][1], u, v[k], cr, ci);
-  }
+  for (int k = 0; k < NP; ++k) lx_step(q[k], 0, A == K - 1 - B, u, v[k], cr, ci);
   if constexpr (A + B <= K - 2) {
     float c2r, c2i, c3r, c3i;
     lx_get<A + 1, B + 1>(g, c2r, c2i);
@@ -233,44 +238,62 @@ __device__ __forceinline__ void lx_inner(const float* g, float u, const float (&
     c2r *= f2; c2i *= f2; c3r *= f3; c3i *= f3;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      if constexpr (A == K - 2 - B) { q[k][2] = c2r; q[k][3] = c2i; q[k][4] = c3r; q[k][5] = c3i; }
-      else {
-        lx_horner<false>(q[k][2], q[k][3], u, v[k], c2r, c2i);
-        lx_horner<false>(q[k][4], q[k][5], u, v[k], c3r, c3i);
-      }
+      lx_step(q[k], 2, A == K - 2 - B, u, v[k], c2r, c2i);
+      lx_step(q[k], 4, A == K - 2 - B, u, v[k], c3r, c3i);
     }
   }
-  if constexpr (A > 0) lx_inner<A - 1, B, NP>(g, u, v, q);
+  if constexpr (D3 && A + B <= K - 3) {
+    float c4r, c4i, c5r, c5i;
+    lx_get<A, B + 3>(g, c4r, c4i);
+    lx_get<A + 1, B + 2>(g, c5r, c5i);
+    constexpr float f4 = 8.f * (B + 3) * (B + 2) * (B + 1), f5 = 8.f * (A + 1) * (B + 2) * (B + 1);
+    c4r *= f4; c4i *= f4; c5r *= f5; c5i *= f5;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      lx_step(q[k], 6, A == K - 3 - B, u, v[k], c4r, c4i);
+      lx_step(q[k], 8, A == K - 3 - B, u, v[k], c5r, c5i);
+    }
+  }
+  if constexpr (A > 0) lx_inner<A - 1, B, NP, D3, NQ>(g, u, v, q);
 }
 
-// Outer Horner steps in conj(delta), from the power B down; P = {alpha, Laplacian, Gamma}.
-template <int B, int NP>
-__device__ __forceinline__ void lx_outer(const float* g, float u, const float (&v)[NP], float (&P)[NP][6]) {
+// Outer Horner steps in conj(delta), from the power B down; P = {alpha, Laplacian, Gamma, T, U}.
+template <int NQ>
+__device__ __forceinline__ void lx_ostep(float (&P)[NQ], const float (&q)[NQ], int o, bool first, float u, float v) {
+  if (first) { P[o] = q[o]; P[o + 1] = q[o + 1]; }
+  else lx_horner<true>(P[o], P[o + 1], u, v, q[o], q[o + 1]);
+}
+template <int B, int NP, bool D3, int NQ>
+__device__ __forceinline__ void lx_outer(const float* g, float u, const float (&v)[NP], float (&P)[NP][NQ]) {
   constexpr int K = LX_K;
-  float q[NP][6];
-  lx_inner<K - 1 - B, B, NP>(g, u, v, q);
+  float q[NP][NQ];
+  lx_inner<K - 1 - B, B, NP, D3, NQ>(g, u, v, q);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    if constexpr (B == K - 1) { P[k][0] = q[k][0]; P[k][1] = q[k][1]; }
-    else lx_horner<true>(P[k][0], P[k][1], u, v[k], q[k][0], q[k][1]);
-    if constexpr (B == K - 2) { P[k][2] = q[k][2]; P[k][3] = q[k][3]; P[k][4] = q[k][4]; P[k][5] = q[k][5]; }
-    else if constexpr (B < K - 2) {
-      lx_horner<true>(P[k][2], P[k][3], u, v[k], q[k][2], q[k][3]);
-      lx_horner<true>(P[k][4], P[k][5], u, v[k], q[k][4], q[k][5]);
+    lx_ostep(P[k], q[k], 0, B == K - 1, u, v[k]);
+    if constexpr (B <= K - 2) {
+      lx_ostep(P[k], q[k], 2, B == K - 2, u, v[k]);
+      lx_ostep(P[k], q[k], 4, B == K - 2, u, v[k]);
+    }
+    if constexpr (D3 && B <= K - 3) {
+      lx_ostep(P[k], q[k], 6, B == K - 3, u, v[k]);
+      lx_ostep(P[k], q[k], 8, B == K - 3, u, v[k]);
     }
   }
-  if constexpr (B > 0) lx_outer<B - 1, NP>(g, u, v, P);
+  if constexpr (B > 0) lx_outer<B - 1, NP, D3, NQ>(g, u, v, P);
 }
 
-// Adds the summed expansion's (LDS image c) deflection and Hessian at the offsets (u, v[k])
-// from the block centre.  Each of alpha_x + i alpha_y, the Laplacian and
-// psi_xx - psi_yy + 2i psi_xy is a polynomial sum_{a,b} c_ab delta^a conj(delta)^b, evaluated
-// by Horner's rule in delta (inner) and conj(delta) (outer).  The Laplacian is real (its
-// imaginary part cancels).
-template <int NP>
+// Adds the summed expansion's (LDS image c) deflection and Hessian (D3: and third derivatives)
+// at the offsets (u, v[k]) from the block centre.  Each of alpha_x + i alpha_y, the Laplacian,
+// Gamma = psi_xx - psi_yy + 2i psi_xy, T = psi_xxx - 3 psi_xyy + i (3 psi_xxy - psi_yyy) and
+// U = psi_xxx + psi_xyy + i (psi_xxy + psi_yyy) is a polynomial sum_{a,b} c_ab delta^a
+// conj(delta)^b, evaluated by Horner's rule in delta (inner) and conj(delta) (outer).  The
+// Laplacian is real (its imaginary part cancels).
+template <bool D3, int NP>
 __device__ __forceinline__ void lx_eval(const float* c, float u, const float (&v)[NP], Acc (&acc)[NP]) {
-  float P[NP][6];
-  lx_outer<LX_K - 1, NP>(c, u, v, P);
+  constexpr int NQ = D3 ? 10 : 6;
+  float P[NP][NQ];
+  lx_outer<LX_K - 1, NP, D3, NQ>(c, u, v, P);
   // constant term of alpha: 2 G_01 = 2 conj(G_10)
   const double c10r = ((const double*)c)[0], c10i = ((const double*)c)[1];
 #pragma unroll
@@ -280,6 +303,13 @@ __device__ __forceinline__ void lx_eval(const float* c, float u, const float (&v
     acc[k].h11 += 0.5 * ((double)P[k][2] + (double)P[k][4]);
     acc[k].h22 += 0.5 * ((double)P[k][2] - (double)P[k][4]);
     acc[k].h12 += 0.5 * (double)P[k][5];
+    if constexpr (D3) {
+      const double Tr = P[k][6], Ti = P[k][7], Ur = P[k][8], Ui = P[k][9];
+      acc[k].t111 += 0.25 * (3.0 * Ur + Tr);
+      acc[k].t122 += 0.25 * (Ur - Tr);
+      acc[k].t112 += 0.25 * (Ui + Ti);
+      acc[k].t222 += 0.25 * (3.0 * Ui - Ti);
+    }
   }
 }
 

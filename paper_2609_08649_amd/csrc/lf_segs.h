@@ -408,7 +408,7 @@ __device__ __forceinline__ TileCls tile_class(double x, double y, double ar, flo
 // adds its coefficients on the lane that holds it; the wave sums them into its LDS area (the
 // member loop's first wave_sync orders these reads before the records are written there) and
 // adds the expansion's deflection and Hessian at each of the lane's points.
-template <int TP>
+template <bool D3, int TP>
 __device__ __forceinline__ void lexp_pass(const MemSoA& so, int lo, int hi, const TileLane<TP>& L, Acc (&acc)[TP]) {
   const int lane = threadIdx.x & 63;
   LxAcc g;
@@ -417,7 +417,7 @@ __device__ __forceinline__ void lexp_pass(const MemSoA& so, int lo, int hi, cons
   for (int b0 = lo; b0 < hi; b0 += 64) {
     const int h = b0 + lane;
     if (h < hi) {
-      const TileCls c = tile_class<true, false, true, TP>(so.x[h], so.y[h], so.a[h], so.rn2[h], L);
+      const TileCls c = tile_class<true, D3, true, TP>(so.x[h], so.y[h], so.a[h], so.rn2[h], L);
       if (c.ex) {
         float fm[6];
 #pragma unroll
@@ -430,11 +430,11 @@ __device__ __forceinline__ void lexp_pass(const MemSoA& so, int lo, int hi, cons
   if (__ballot(any) == 0) return;
   lx_reduce_store(g, L.dsh);
   wave_sync();
-  lx_eval<TP>(L.dsh, L.u, L.v, acc);
+  lx_eval<D3, TP>(L.dsh, L.u, L.v, acc);
 }
 
 // Members are taken in blocks of 64.  Lane j of the wave takes member j of the block and
-// classifies it (tile_class).  Without third derivatives the far dPIE members at least LX_DIST
+// classifies it (tile_class).  The far dPIE members at least LX_DIST
 // block radii away are summed by the block's local expansion first (lexp_pass) and skipped
 // here.  Ballots give the wave's near, far and closed-form sets, and the records are written to
 // LDS in the order four-term, five-term, six-term far members, then closed-form ones (each set
@@ -451,8 +451,8 @@ __device__ __forceinline__ void seg_loop_tile(const MemRec32* __restrict__ rec, 
   static_assert(SEG == SEG_CPJE || SEG == SEG_CSIE, "tiles hold the circular segments");
   constexpr int LS = TILE_LSTRIDE<SEG, D3>;
   constexpr bool FAR = TILE_FAR<SEG, D3>;
-  constexpr bool EXP = FAR && !D3;
-  if constexpr (EXP) lexp_pass<TP>(so, lo, hi, L, acc);
+  constexpr bool EXP = FAR;
+  if constexpr (EXP) lexp_pass<D3, TP>(so, lo, hi, L, acc);
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int b0 = lo; b0 < hi; b0 += 64) {
