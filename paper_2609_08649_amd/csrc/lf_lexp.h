@@ -22,8 +22,8 @@
 // Terms up to total degree LX_K = 7 are kept.  Members are taken at distances of at least
 // LX_DIST block radii (|delta| / |zeta0| <= 1/8): the truncation is then below 1e-9 arcsec in
 // alpha and 1e-9 in the Hessian on cluster members, against 1e-7 for the FP32 rounding of one
-// member term; third derivatives (third derivatives of the same polynomial, degree 4) stay
-// within 3e-8 of the exact member sums.  Coefficients are formed and summed in FP32 except G_10 (the block centre's
+// member term; the third derivatives (of the same polynomial, to degree 4) stay within 3e-8 of
+// the exact member sums.  Coefficients are formed and summed in FP32 except G_10 (the block centre's
 // deflection, the one term of the size of the total), which the lanes keep in FP64.
 #pragma once
 #include <hip/hip_runtime.h>
