@@ -95,6 +95,27 @@ def recorded_profile_ms():
     return None
 
 
+INSTS_FILE = os.path.join(ROOT, "profiles", "maps_lean_cluster2048_instructions.txt")
+
+
+def recorded_counter_flops():
+    """FLOPs (FP32, FP64) one lean maps launch executes by the committed SQ counter summary
+    (FMA 2, add, mul and transcendental 1, 64 lanes per wave-instruction), or None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    try:
+        lines = open(INSTS_FILE).read().splitlines()
+    except OSError:
+        return None
+    sha = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("# source_sha256:")]
+    if not sha or sha[0] != kernel_source_hash():
+        return None
+    for ln in lines:
+        if ln.startswith("counter FLOPs per dispatch:"):
+            f = ln.split(":", 1)[1].split(";")[0].split(",")
+            return float(f[0].split()[-1]), float(f[1].split()[-1])
+    return None
+
+
 def summarize_profiles(kind, dirs):
     """Text summaries of rocprofv3 output (no GPU needed).  kind 'stats': the kernel statistics
     CSV of --kernel-trace --stats; kind 'pmc': two --pmc runs (FETCH_SIZE dir, WRITE_SIZE dir)
@@ -182,6 +203,7 @@ def summarize_profiles(kind, dirs):
                 sums.setdefault(c, []).append(v)
         from paper_2609_08649_amd import workloads as W
         n_mem = len(W.config2()["model"]["members"]["x"])
+        print("# source_sha256: %s" % kernel_source_hash())
         waves = sum(sums["SQ_WAVES"]) / len(sums["SQ_WAVES"])
         groups = waves * LANE_POINTS[kern]
         print("%s, %d dispatches, %.0f waves each (%d points per lane), %d members per point" %
@@ -494,6 +516,14 @@ def main():
         note("precision report (oracle)")
         prec_rep.update(precision_report_more(ctx, lf, torch, W))
 
+    cf = recorded_counter_flops()
+    executed = None
+    if cf is not None:
+        executed = {"fp32_flops_per_launch": cf[0], "fp64_flops_per_launch": cf[1],
+                    "fp32_tflops": cf[0] / (lean_ms * 1e-3) / 1e12, "fp64_tflops": cf[1] / (lean_ms * 1e-3) / 1e12,
+                    "fp32_frac": cf[0] / (lean_ms * 1e-3) / PEAK_FP32_VECTOR,
+                    "source": "SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS} per dispatch of the committed counter summary "
+                              "over this run's launch average"}
     res = {
         "metric": "halo x point lens evals/s (alpha+Jacobian)",
         "value": evals_step / (ms * 1e-3),
@@ -538,10 +568,11 @@ def main():
                      "timing": "HIP events recorded on the launching stream around each launch, this run",
                      "profile_avg_launch_ms": prof_ms,
                      "profile_frac": (flops_lean / (prof_ms * 1e-3) / PEAK_FP32_VECTOR) if prof_ms else None,
+                     "executed": executed,
                      "note": "achieved counts the FLOPs of the direct member sum (flops_per_eval per member and "
                              "point); the kernel sums the far members of each 16 x 16 block through a local "
-                             "expansion about the block centre and executes fewer (the counter FLOP rate of "
-                             "the kernel is in profiles/kernel_flops_cluster_extras.txt)"},
+                             "expansion about the block centre and executes fewer: 'executed' holds the FLOPs "
+                             "its SQ counters count per launch and their rate"},
         "extras": extras,
         "precision_vs_oracle": prec_rep,
         "cpu_baseline": cpu,

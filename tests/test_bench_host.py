@@ -158,3 +158,13 @@ def test_flops_summary_joins_counters_and_times(tmp_path, capsys):
     assert c[1:3] == ["4", "1"] and float(c[4]) == pytest.approx(0.512) and float(c[6]) == pytest.approx(0.128, abs=0.01)
     b = [l.split() for l in lines[2:] if l.startswith("kB")][0]
     assert float(b[-1]) == pytest.approx(64e6 / 1e-4 / 1e9)
+
+
+def test_counter_flops_are_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
+    f = tmp_path / "insts.txt"
+    body = "lf::k_maps_tile<false>, 3 dispatches\ncounter FLOPs per dispatch: FP32 7.159e+09, FP64 7.144e+08; algorithmic 4.907e+10\n"
+    f.write_text("# header\n# source_sha256: %s\n" % bench.kernel_source_hash() + body)
+    monkeypatch.setattr(bench, "INSTS_FILE", str(f))
+    assert bench.recorded_counter_flops() == (7.159e9, 7.144e8)
+    f.write_text("# source_sha256: 0\n" + body)
+    assert bench.recorded_counter_flops() is None
